@@ -1,0 +1,271 @@
+"""FP64 CPU oracle for HyperNetVec multi-level refinement (arXiv 2103.09660).
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the plain, slow reference the GPU
+library is checked against.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import it; the product package never
+does.  It shares no code with the GPU library: the arithmetic lives in
+``hnv_oracle.c`` (plain C, FP64) and the driver below follows the paper's
+three phases in order:
+
+* Algorithm 1 (Section 3.1), one featureless coarsening step per level;
+* the projection rule at the end of Section 3.3 (a merged node's embedding is
+  given to every fine node of its set);
+* Algorithm 2 (Section 3.3), ``k`` smoothing sweeps per level, from the
+  coarsest level to the finest;
+* the reverse mode of the projection and of each sweep, and the linear
+  cross-entropy head used downstream (Section 4, experimental settings).
+
+The function groups that have no external pin are listed under
+``PARITY_UNPINNED`` below (empty: every function is pinned by a test in
+``tests/test_oracle_*.py``).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+PARITY_UNPINNED: tuple = ()
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hnv_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f32p = ctypes.POINTER(ctypes.c_float)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (strict IEEE FP64, no contraction)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                               "-shared", "-fPIC", "-Wall", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_transpose.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _i64p, _i32p]
+        lib.oracle_coarsen.restype = ctypes.c_int
+        lib.oracle_coarsen.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _f32p, _i32p, _i32p,
+                                       _i64p, _i64p, _i64p, _i64p, _i32p, _f32p]
+        lib.oracle_rowmap.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _i32p, _i32p,
+                                      ctypes.c_int64, _i64p]
+        lib.oracle_project.argtypes = [ctypes.c_int64, _i64p, ctypes.c_int64, _f64p, _f64p]
+        lib.oracle_sweep.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _i64p, _i32p, _f32p,
+                                     ctypes.c_int64, ctypes.c_double, ctypes.c_int, _f64p, _f64p]
+        lib.oracle_sweep_vjp.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _i64p, _i32p, _f32p,
+                                         ctypes.c_int64, ctypes.c_double, _f64p, _f64p, _f64p, _f64p]
+        lib.oracle_project_vjp.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, ctypes.c_int64, _f64p, _f64p]
+        _lib = lib
+    return _lib
+
+
+def threads() -> int:
+    return int(_L().oracle_threads())
+
+
+def _p(a: Optional[np.ndarray], t):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+@dataclasses.dataclass
+class Level:
+    """One hypergraph of the hierarchy, with both star-expansion adjacencies."""
+    n_nodes: int
+    n_edges: int
+    eptr: np.ndarray                 # int64 [n_edges+1]  hyperedge -> members
+    eidx: np.ndarray                 # int32 [nnz]
+    w: Optional[np.ndarray]          # float32 [n_edges] or None (unit)
+    nptr: np.ndarray = None          # int64 [n_nodes+1]  node -> hyperedges
+    nidx: np.ndarray = None          # int32 [nnz]
+
+    def __post_init__(self):
+        self.eptr = np.ascontiguousarray(self.eptr, dtype=np.int64)
+        self.eidx = np.ascontiguousarray(self.eidx, dtype=np.int32)
+        if self.w is not None:
+            self.w = np.ascontiguousarray(self.w, dtype=np.float32)
+        if self.nptr is None:
+            self.nptr, self.nidx = transpose(self.n_nodes, self.n_edges, self.eptr, self.eidx)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.eptr[-1])
+
+    @property
+    def rows(self) -> int:
+        return self.n_nodes + self.n_edges
+
+
+def transpose(n_nodes, n_edges, eptr, eidx):
+    nptr = np.zeros(n_nodes + 1, dtype=np.int64)
+    nidx = np.zeros(max(int(eptr[-1]), 1), dtype=np.int32)
+    _L().oracle_transpose(n_nodes, n_edges, _p(eptr, _i64p), _p(eidx, _i32p), _p(nptr, _i64p), _p(nidx, _i32p))
+    return nptr, nidx[: int(eptr[-1])]
+
+
+@dataclasses.dataclass
+class Coarsening:
+    node_rep: np.ndarray   # int32 [n_nodes_fine]
+    edge_rep: np.ndarray   # int32 [n_edges_fine], -1 = removed
+    coarse: Level
+
+
+def coarsen_level(lv: Level) -> Coarsening:
+    """Algorithm 1's loop body once, featureless (Section 3.1)."""
+    nnz = lv.nnz
+    node_rep = np.zeros(max(lv.n_nodes, 1), dtype=np.int32)
+    edge_rep = np.zeros(max(lv.n_edges, 1), dtype=np.int32)
+    c_eptr = np.zeros(lv.n_edges + 1, dtype=np.int64)
+    c_eidx = np.zeros(max(nnz, 1), dtype=np.int32)
+    c_w = np.zeros(max(lv.n_edges, 1), dtype=np.float32)
+    nv = ctypes.c_int64(); ne = ctypes.c_int64(); nz = ctypes.c_int64()
+    rc = _L().oracle_coarsen(lv.n_nodes, lv.n_edges, _p(lv.eptr, _i64p), _p(lv.eidx, _i32p), _p(lv.w, _f32p),
+                             _p(node_rep, _i32p), _p(edge_rep, _i32p), ctypes.byref(nv), ctypes.byref(ne),
+                             ctypes.byref(nz), _p(c_eptr, _i64p), _p(c_eidx, _i32p), _p(c_w, _f32p))
+    if rc != 0:
+        raise MemoryError("oracle_coarsen")
+    ne_, nz_ = ne.value, nz.value
+    coarse = Level(nv.value, ne_, c_eptr[: ne_ + 1].copy(), c_eidx[:nz_].copy(),
+                   None if lv.w is None else c_w[:ne_].copy())
+    return Coarsening(node_rep[: lv.n_nodes].copy(), edge_rep[: lv.n_edges].copy(), coarse)
+
+
+def build_hierarchy(n_nodes, n_edges, eptr, eidx, w, n_coarsen: int):
+    """Levels 0 (finest) .. n_coarsen (coarsest) and the maps between them."""
+    levels = [Level(n_nodes, n_edges, eptr, eidx, w)]
+    maps: List[Coarsening] = []
+    for _ in range(n_coarsen):
+        c = coarsen_level(levels[-1])
+        maps.append(c)
+        levels.append(c.coarse)
+    return levels, maps
+
+
+def rowmap(fine: Level, cm: Coarsening) -> np.ndarray:
+    out = np.zeros(fine.rows, dtype=np.int64)
+    _L().oracle_rowmap(fine.n_nodes, fine.n_edges, _p(fine.eptr, _i64p), _p(fine.eidx, _i32p),
+                       _p(cm.node_rep, _i32p), _p(cm.edge_rep, _i32p), cm.coarse.n_nodes, _p(out, _i64p))
+    return out
+
+
+def project(rmap: np.ndarray, zc: np.ndarray) -> np.ndarray:
+    zc = np.ascontiguousarray(zc, dtype=np.float64)
+    d = zc.shape[1]
+    zf = np.empty((len(rmap), d), dtype=np.float64)
+    _L().oracle_project(len(rmap), _p(rmap, _i64p), d, _p(zc, _f64p), _p(zf, _f64p))
+    return zf
+
+
+def sweep(lv: Level, z: np.ndarray, omega: float, order: int = 0, w: Optional[np.ndarray] = None) -> np.ndarray:
+    """One iteration of Algorithm 2 over the star expansion of ``lv``.
+    ``w`` overrides the level's hyperedge weights (e.g. learnt weights)."""
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    assert z.shape[0] == lv.rows
+    out = np.empty_like(z)
+    ww = lv.w if w is None else np.ascontiguousarray(w, dtype=np.float32)
+    _L().oracle_sweep(lv.n_nodes, lv.n_edges, _p(lv.eptr, _i64p), _p(lv.eidx, _i32p), _p(lv.nptr, _i64p),
+                      _p(lv.nidx, _i32p), _p(ww, _f32p), z.shape[1], float(omega), int(order),
+                      _p(z, _f64p), _p(out, _f64p))
+    return out
+
+
+def residual(z_new: np.ndarray, z_old: np.ndarray) -> float:
+    """Frobenius norm of the change made by one sweep (the consecutive-
+    iterate difference named as a stopping rule in Section 4)."""
+    diff = np.asarray(z_new, dtype=np.float64) - np.asarray(z_old, dtype=np.float64)
+    return float(np.sqrt(np.sum(diff * diff)))
+
+
+def refine(levels: Sequence[Level], maps: Sequence[Coarsening], z_coarsest: np.ndarray,
+           sweeps: Sequence[int], omega: float, order: int = 0, tol: float = 0.0,
+           return_residuals: bool = False):
+    """Refinement from the coarsest level to the finest (Section 3.3): sweeps
+    at the coarsest level, then for each finer level project and sweep.
+    ``sweeps[l]`` is the count for level l.  ``tol > 0`` stops a level early
+    once a sweep changes Z by at most ``tol`` in Frobenius norm."""
+    L = len(levels) - 1
+    z = np.ascontiguousarray(z_coarsest, dtype=np.float64)
+    res = []
+    for lvl in range(L, -1, -1):
+        if lvl < L:
+            z = project(rowmap(levels[lvl], maps[lvl]), z)
+        for _ in range(int(sweeps[lvl])):
+            zn = sweep(levels[lvl], z, omega, order)
+            r = residual(zn, z)
+            res.append(r)
+            z = zn
+            if tol > 0 and r <= tol:
+                break
+    return (z, res) if return_residuals else z
+
+
+def sweep_vjp(lv: Level, y: np.ndarray, g: np.ndarray, omega: float, w: Optional[np.ndarray] = None):
+    """Reverse mode of one order-0 sweep at inputs ``y``: returns (dL/dy, dL/dw)."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    gy = np.empty_like(y)
+    dw = np.zeros(max(lv.n_edges, 1), dtype=np.float64)
+    ww = lv.w if w is None else np.ascontiguousarray(w, dtype=np.float32)
+    _L().oracle_sweep_vjp(lv.n_nodes, lv.n_edges, _p(lv.eptr, _i64p), _p(lv.eidx, _i32p), _p(lv.nptr, _i64p),
+                          _p(lv.nidx, _i32p), _p(ww, _f32p), y.shape[1], float(omega), _p(y, _f64p),
+                          _p(g, _f64p), _p(gy, _f64p), _p(dw, _f64p))
+    return gy, dw[: lv.n_edges]
+
+
+def project_vjp(rmap: np.ndarray, rows_coarse: int, gf: np.ndarray) -> np.ndarray:
+    gf = np.ascontiguousarray(gf, dtype=np.float64)
+    gc = np.empty((rows_coarse, gf.shape[1]), dtype=np.float64)
+    _L().oracle_project_vjp(len(rmap), rows_coarse, _p(rmap, _i64p), gf.shape[1], _p(gf, _f64p), _p(gc, _f64p))
+    return gc
+
+
+def finest_refine_vjp(fine: Level, cm: Coarsening, z_coarse: np.ndarray, w: Optional[np.ndarray],
+                      k: int, omega: float, g_out: np.ndarray):
+    """Forward and reverse of: project the coarse embedding onto the finest
+    level, then ``k`` sweeps with hyperedge weights ``w``.  Returns
+    (Z_k, dL/dZ_coarse, dL/dw) for the cotangent ``g_out`` = dL/dZ_k."""
+    rm = rowmap(fine, cm)
+    states = [project(rm, z_coarse)]
+    for _ in range(k):
+        states.append(sweep(fine, states[-1], omega, 0, w))
+    g = np.ascontiguousarray(g_out, dtype=np.float64)
+    dw = np.zeros(fine.n_edges, dtype=np.float64)
+    for i in range(k, 0, -1):
+        g, dwi = sweep_vjp(fine, states[i - 1], g, omega, w)
+        dw += dwi
+    gc = project_vjp(rm, cm.coarse.rows, g)
+    return states[-1], gc, dw
+
+
+def ce_head(z_nodes: np.ndarray, labels: np.ndarray, W: np.ndarray, b: np.ndarray):
+    """Mean cross-entropy of a linear head, FP64: returns (loss, dL/dz_nodes).
+    logits = z W^T + b; loss = mean_i (logsumexp(logits_i) - logits_i[y_i])."""
+    z = np.asarray(z_nodes, dtype=np.float64)
+    W64 = np.asarray(W, dtype=np.float64)
+    logits = z @ W64.T + np.asarray(b, dtype=np.float64)
+    m = logits.max(axis=1, keepdims=True)
+    ex = np.exp(logits - m)
+    se = ex.sum(axis=1, keepdims=True)
+    lse = (m + np.log(se))[:, 0]
+    n = len(labels)
+    loss = float(np.mean(lse - logits[np.arange(n), labels]))
+    p = ex / se
+    p[np.arange(n), labels] -= 1.0
+    dz = (p / n) @ W64
+    return loss, dz

@@ -1,0 +1,88 @@
+"""Pins for the oracle's reverse mode: the transpose of the dense sweep matrix,
+the dot-product identity, and central finite differences in FP64 through
+projection + several sweeps (for the coarse embedding and for the
+per-hyperedge log-weights), plus the cross-entropy head."""
+import numpy as np
+import pytest
+
+from synth import random_hypergraph
+from tests.dense_ref import jacobi_matrix, star_adjacency
+
+
+def _level(O, hg):
+    return O.Level(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_vjp_is_dense_transpose_and_dot_identity(oracle_mod, seed):
+    O = oracle_mod
+    hg = random_hypergraph(seed, 33, 21, 1, 6, weighted=True)
+    lv = _level(O, hg)
+    rng = np.random.default_rng(seed)
+    y = rng.standard_normal((lv.rows, 3))
+    g = rng.standard_normal((lv.rows, 3))
+    gy, _ = O.sweep_vjp(lv, y, g, 0.4)
+    M = jacobi_matrix(star_adjacency(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w), 0.4)
+    np.testing.assert_allclose(gy, M.T @ g, atol=1e-13)
+    x = rng.standard_normal((lv.rows, 3))
+    lhs = np.sum(O.sweep(lv, x, 0.4, 0) * g)
+    rhs = np.sum(x * O.sweep_vjp(lv, x, g, 0.4)[0])
+    assert abs(lhs - rhs) <= 1e-13 * max(1.0, abs(lhs))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_finite_differences_theta_and_coarse(oracle_mod, seed):
+    """L(theta, Zc) = <Z_k, G> with Z_k = k sweeps (weights exp(theta)) after
+    projecting Zc.  Central differences, h = 1e-6, FP64."""
+    O = oracle_mod
+    hg = random_hypergraph(20 + seed, 40, 25, 2, 6, weighted=False)
+    fine = _level(O, hg)
+    c = O.coarsen_level(fine)
+    rng = np.random.default_rng(seed)
+    theta = rng.uniform(-0.5, 0.5, size=hg.n_edges)
+    zc = rng.standard_normal((c.coarse.rows, 3))
+    G = rng.standard_normal((fine.rows, 3))
+    k, omega = 4, 0.5
+
+    def loss(th, zcoarse):
+        zk, _, _ = O.finest_refine_vjp(fine, c, zcoarse, np.exp(th).astype(np.float32), k, omega, G)
+        return float(np.sum(zk * G))
+
+    # weights enter as float32, so dL/dw is checked with steps that are exact
+    # in float32 (relative 1e-3); dL/dtheta = w dL/dw is the chain rule.
+    w0 = np.exp(theta).astype(np.float32)
+    _, gc, dw = O.finest_refine_vjp(fine, c, zc, w0, k, omega, G)
+    h = 1e-6
+    for e in range(0, hg.n_edges, 3):
+        wp = w0.astype(np.float64).copy(); wm = wp.copy()
+        step = np.float32(w0[e] * (1 + 1e-3)) - w0[e]          # exact float32 step
+        wp[e] += step; wm[e] -= step
+        lp = float(np.sum(O.finest_refine_vjp(fine, c, zc, wp.astype(np.float32), k, omega, G)[0] * G))
+        lm = float(np.sum(O.finest_refine_vjp(fine, c, zc, wm.astype(np.float32), k, omega, G)[0] * G))
+        fd = (lp - lm) / (2 * float(step))
+        assert abs(fd - dw[e]) <= 1e-5 * max(1.0, abs(dw[e])), (e, fd, dw[e])
+    for r in range(0, c.coarse.rows, 4):
+        for col in range(3):
+            zp = zc.copy(); zm = zc.copy()
+            zp[r, col] += h; zm[r, col] -= h
+            fd = (loss(theta, zp) - loss(theta, zm)) / (2 * h)
+            assert abs(fd - gc[r, col]) <= 1e-6 * max(1.0, abs(gc[r, col]))
+
+
+def test_ce_head_gradient(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(0)
+    z = rng.standard_normal((20, 8))
+    W = rng.standard_normal((5, 8)) / 3
+    b = rng.standard_normal(5)
+    y = rng.integers(0, 5, size=20)
+    loss, dz = O.ce_head(z, y, W, b)
+    # closed form at W = 0: every class equally likely, loss = log C
+    assert abs(O.ce_head(z, y, np.zeros_like(W), np.zeros_like(b))[0] - np.log(5)) < 1e-14
+    h = 1e-6
+    for i in range(0, 20, 3):
+        for j in range(8):
+            zp = z.copy(); zm = z.copy()
+            zp[i, j] += h; zm[i, j] -= h
+            fd = (O.ce_head(zp, y, W, b)[0] - O.ce_head(zm, y, W, b)[0]) / (2 * h)
+            assert abs(fd - dz[i, j]) < 1e-8
