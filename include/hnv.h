@@ -1,0 +1,226 @@
+/*
+ * hnv.h -- C ABI of the MI355X (gfx950) HyperNetVec refinement library.
+ *
+ * HyperNetVec (Maleki, Saless, Wall, Pingali, arXiv 2103.09660) embeds a
+ * hypergraph H = (V, E) (Section 1) by coarsening it (Section 3.1,
+ * Algorithm 1), embedding the coarsest level, and refining the embedding
+ * level by level back to the finest (Section 3.3, Algorithm 2).  This library
+ * runs the refinement on the GPU: per level, the projection of the coarser
+ * embedding and repeated smoothing sweeps over the star expansion H*
+ * (Section 1.1), plus the reverse mode of both.  Coarsening runs on the host.
+ *
+ * Conventions used by every call
+ *   - Star-expansion rows of a level: nodes first, then hyperedges.  Row v is
+ *     node v, row n_nodes + e is hyperedge e.  rows = n_nodes + n_edges.
+ *   - An embedding Z of a level is a row-major [rows x d] matrix of the
+ *     plan's storage type (HNV_F32: float, HNV_BF16: bfloat16 bit patterns,
+ *     round-to-nearest-even), 16-byte aligned, in device memory.
+ *   - A hyperedge is a nonempty set of nodes (Section 1): its member list is
+ *     strictly ascending.  Weights are finite and > 0; a NULL weight array
+ *     means unit weights (Section 3.3: "a value of 1 is used").
+ *   - The star edge between node v and hyperedge e carries the weight w_e in
+ *     both directions.  So a hyperedge row is relaxed towards the plain mean
+ *     of its members and a node row towards the w-weighted mean of its
+ *     hyperedges.
+ *   - One sweep is the Jacobi form of Algorithm 2: every row reads the
+ *     previous iterate; a row without neighbours keeps its value.
+ *   - Every call returns an hnv_status; nothing aborts and no C++ exception
+ *     crosses this boundary.  On failure hnv_last_error() describes it.
+ *   - Device work is enqueued on the caller's HIP stream (hipStream_t passed
+ *     as void*; NULL = the default stream) and is asynchronous unless stated.
+ *     The library allocates no device memory: it carves the caller's
+ *     workspace.  A plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef HNV_H
+#define HNV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HNV_ABI_VERSION 1
+
+typedef enum {
+    HNV_OK = 0,
+    HNV_EINVAL = 1,        /* null pointer, negative size, bad parameter */
+    HNV_ERANGE = 2,        /* an index or map entry out of range */
+    HNV_EUNSORTED = 3,     /* a member list not strictly ascending */
+    HNV_EUNSUPPORTED = 4,  /* a size or width outside what the kernels handle */
+    HNV_EWORKSPACE = 5,    /* workspace too small or not 256-byte aligned */
+    HNV_EDEVICE = 6,       /* a HIP runtime error (message has the HIP text) */
+    HNV_ENOMEM = 7         /* host allocation failed */
+} hnv_status;
+
+typedef enum { HNV_F32 = 0, HNV_BF16 = 1 } hnv_dtype;
+
+/* One hypergraph of the hierarchy, in HOST memory.
+ * edge_ptr[n_edges+1] (edge_ptr[0] = 0, edge_ptr[n_edges] = nnz) and
+ * edge_idx[nnz] list each hyperedge's members (node ids in [0, n_nodes),
+ * strictly ascending).  edge_w[n_edges] or NULL.  Limits: nnz, n_nodes +
+ * n_edges < 2^31. */
+typedef struct {
+    int64_t n_nodes;
+    int64_t n_edges;
+    int64_t nnz;
+    const int64_t *edge_ptr;
+    const int32_t *edge_idx;
+    const float *edge_w;
+} hnv_level;
+
+/* Coarsening maps from level l to level l+1, in HOST memory (Section 3.1:
+ * rep(v) and rep(e)).  node_rep[n_nodes_l] in [0, n_nodes_{l+1});
+ * edge_rep[n_edges_l] in [0, n_edges_{l+1}) or -1 for a hyperedge that was
+ * removed because all of its members were merged into one coarse node. */
+typedef struct {
+    const int32_t *node_rep;
+    const int32_t *edge_rep;
+} hnv_map;
+
+/* Tuning knobs; zero fields take the library's defaults. */
+typedef struct {
+    int32_t panel_cols;  /* columns per pass of a forward sweep (divides d, multiple of 8) */
+    int32_t small_max;   /* rows with at most this many neighbours go to a lane group */
+    int32_t chunk;       /* neighbours per wavefront work item; longer rows are split */
+} hnv_options;
+
+typedef struct hnv_plan hnv_plan;
+
+/* HNV_ABI_VERSION of the built library. */
+int hnv_abi_version(void);
+
+/* Message for the last non-OK status returned on this thread ("" if none).
+ * The pointer stays valid until the next hnv_* call on this thread. */
+const char *hnv_last_error(void);
+
+/* Checks a level: offsets, index range, ascending unique member lists,
+ * weights finite and > 0, size limits.  Host only. */
+hnv_status hnv_validate_level(const hnv_level *level);
+
+/* One step of Algorithm 1 without node features (Section 3.1), on the host.
+ * Each node v with hyperedges is assigned to c(v), the hyperedge of N(v)
+ * with the largest weight, then the fewest members, then the lowest id (the
+ * paper's featureless rule "weights or degrees of a hyperedge", with its
+ * random tie-break replaced by a fixed order so the maps are reproducible).
+ * Nodes with the same c(v) merge into one coarse node; a node without
+ * hyperedges stays a node of its own.  Coarse node ids follow the smallest
+ * fine node of each group.  A hyperedge all of whose members chose it is
+ * removed (edge_rep = -1), every other hyperedge is kept in order with the
+ * coarse member set {rep(v) : v in e} (ascending, repeats collapsed) and the
+ * same weight.
+ * Outputs (HOST, caller-allocated, sized for the fine level):
+ *   node_rep[n_nodes], edge_rep[n_edges], c_edge_ptr[n_edges+1],
+ *   c_edge_idx[nnz], c_edge_w[n_edges] (may be NULL if fine->edge_w is NULL);
+ *   *c_n_nodes, *c_n_edges, *c_nnz receive the coarse sizes.
+ * The input is validated first (errors as hnv_validate_level). */
+hnv_status hnv_coarsen_level(const hnv_level *fine, int32_t *node_rep, int32_t *edge_rep,
+                             int64_t *c_edge_ptr, int32_t *c_edge_idx, float *c_edge_w,
+                             int64_t *c_n_nodes, int64_t *c_n_edges, int64_t *c_nnz);
+
+/* Device workspace a plan over these levels needs, in bytes.  levels[0] is
+ * the finest, levels[n_levels-1] the coarsest; maps[l] maps level l to l+1
+ * (n_levels-1 entries, may be NULL if n_levels == 1).  d: embedding width,
+ * a multiple of 8 up to 512.  opts may be NULL.  Host only. */
+hnv_status hnv_plan_workspace_bytes(const hnv_level *levels, const hnv_map *maps, int n_levels,
+                                    int d, hnv_dtype dtype, const hnv_options *opts, size_t *bytes);
+
+/* Builds a plan: the star-expansion adjacency of every level in both
+ * directions, the degree-tiered work lists, the row maps of the projection,
+ * their inverse, and the FP64-computed reciprocals of the row weight sums.
+ * Everything is copied into `workspace` (device memory of ws_bytes >=
+ * hnv_plan_workspace_bytes, 256-byte aligned, owned by the caller, must
+ * outlive the plan).  The host arrays are not retained.  validate != 0 runs
+ * hnv_validate_level on every level and checks the maps.  Synchronises
+ * `stream` before returning. */
+hnv_status hnv_plan_create(const hnv_level *levels, const hnv_map *maps, int n_levels, int d,
+                           hnv_dtype dtype, const hnv_options *opts, int validate, void *workspace,
+                           size_t ws_bytes, void *stream, hnv_plan **out);
+
+/* Frees the plan's host state; the workspace stays the caller's. */
+hnv_status hnv_plan_destroy(hnv_plan *plan);
+
+/* Sizes of one level of the plan (any pointer may be NULL). */
+hnv_status hnv_plan_level_info(const hnv_plan *plan, int level, int64_t *n_nodes, int64_t *n_edges,
+                               int64_t *nnz);
+
+/* Replaces the hyperedge weights of one level with w_dev[n_edges] (DEVICE,
+ * finite, > 0; not checked on the device) and recomputes the row
+ * reciprocals 1 / sum_{e ∋ v} w_e in FP64. */
+hnv_status hnv_set_edge_weights(hnv_plan *plan, int level, const float *w_dev, void *stream);
+
+/* As hnv_set_edge_weights with w = exp(theta): theta_dev[n_edges] DEVICE
+ * log-weights (the learnable parameterisation); w_out_dev[n_edges] (DEVICE,
+ * may be NULL) receives w. */
+hnv_status hnv_set_edge_logweights(hnv_plan *plan, int level, const float *theta_dev,
+                                   float *w_out_dev, void *stream);
+
+/* Multi-level refinement (Section 3.3): starting from z_coarsest (DEVICE,
+ * [rows of the coarsest level x d]), run sweeps_per_level[L] sweeps at the
+ * coarsest level L, then for l = L-1 .. 0 project onto level l (a merged
+ * node's row goes to every fine node of its set; a kept hyperedge takes
+ * rep(e)'s row, a removed one its members' common coarse node row) and run
+ * sweeps_per_level[l] sweeps.  The projection is fused into the first sweep
+ * of a level.  Writes z_finest (DEVICE, [rows of level 0 x d]; must not
+ * alias z_coarsest).
+ *   sweeps_per_level: HOST [n_levels], index = level, each >= 0.
+ *   omega: relaxation, 0 <= omega <= 1 (Algorithm 2).
+ *   tol: <= 0 runs the fixed counts; > 0 also stops a level after the first
+ *        sweep whose change ||Z^i - Z^{i-1}||_F is <= tol (this synchronises
+ *        the stream after every sweep).
+ *   residuals_dev: DEVICE double [sum of sweeps_per_level] or NULL; entry k
+ *        receives ||Z^i - Z^{i-1}||_F of the k-th sweep run (coarsest level
+ *        first), reduced in FP64 in a fixed order.  Entries past the last
+ *        sweep run (when tol stops levels early) are left untouched.
+ *   sweeps_done: HOST int32 [n_levels] or NULL: sweeps actually run. */
+hnv_status hnv_refine(hnv_plan *plan, const void *z_coarsest, void *z_finest,
+                      const int32_t *sweeps_per_level, float omega, double tol,
+                      double *residuals_dev, int32_t *sweeps_done, void *stream);
+
+/* Projection alone onto level `level` (< L): z_fine[u] = z_coarse[rowmap(u)]. */
+hnv_status hnv_project(hnv_plan *plan, int level, const void *z_coarse, void *z_fine, void *stream);
+
+/* One sweep at `level` (Algorithm 2, one iteration).  If from_coarse != 0,
+ * z_in is the embedding of level+1 and the sweep runs on its projection
+ * (fused; equal to hnv_project then hnv_sweep).  z_out must not alias z_in.
+ * resid_dev: DEVICE double[1] or NULL, receives ||z_out - z_start||_F. */
+hnv_status hnv_sweep(hnv_plan *plan, int level, const void *z_in, void *z_out, float omega,
+                     int from_coarse, double *resid_dev, void *stream);
+
+/* Reverse mode of one sweep at `level` (from_coarse = 0).  With y = z_prev
+ * (the sweep's input), z = z_cur (its output) and g_in = dL/dz, writes
+ * g_out = dL/dy:
+ *   node v:      (1-omega) g_v + omega sum_{e ∋ v} g_e / |e|
+ *   hyperedge e: (1-omega) g_e + omega w_e sum_{v in e} g_v / S_v,
+ *                S_v = sum_{e' ∋ v} w_e'
+ *   rows without neighbours: g_out = g_in,
+ * and if dw_accum != NULL adds dL/dw_e = omega sum_{v in e}
+ * <g_v, y_e - zt_v> / S_v to dw_accum[e] (DEVICE float [n_edges]), where
+ * zt_v = (z_v - (1-omega) y_v) / omega is node v's neighbour mean.  Needs
+ * omega > 0.  All matrices [rows x d] of the plan's storage type; g_out must
+ * not alias g_in. */
+hnv_status hnv_sweep_adjoint(hnv_plan *plan, int level, const void *g_in, void *g_out,
+                             const void *z_prev, const void *z_cur, float *dw_accum, float omega,
+                             void *stream);
+
+/* Reverse mode of the projection onto `level`: g_coarse[r] = sum of g_fine[u]
+ * over the fine rows u with rowmap(u) = r, summed in ascending u.  Coarse
+ * rows with no preimage get 0. */
+hnv_status hnv_project_adjoint(hnv_plan *plan, int level, const void *g_fine, void *g_coarse,
+                               void *stream);
+
+/* Chain rule for log-weights: dtheta[e] = w[e] * dw[e] with the level's
+ * current weights (DEVICE float [n_edges] each; dtheta may alias dw). */
+hnv_status hnv_logweight_grad(hnv_plan *plan, int level, const float *dw, float *dtheta, void *stream);
+
+/* Element-wise conversion between storage types on the device (FP32 ->
+ * BF16 rounds to nearest even; BF16 -> FP32 is exact).  n elements. */
+hnv_status hnv_cast(const void *src, hnv_dtype src_dtype, void *dst, hnv_dtype dst_dtype,
+                    int64_t n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HNV_H */

@@ -1,0 +1,21 @@
+"""MI355X-native HyperNetVec refinement (arXiv 2103.09660).
+
+The refinement hot path -- per-level projection of coarse embeddings and
+smoothing sweeps over the star-expansion incidence, in FP32 or BF16 storage,
+plus its reverse mode -- runs in hand-written HIP kernels for gfx950 behind
+the C ABI of include/hnv.h.  This package is the thin Python binding.
+"""
+from .api import (  # noqa: F401
+    Hierarchy,
+    HostLevel,
+    HostMap,
+    Plan,
+    abi_version,
+    cast,
+    coarsen_level,
+    last_error,
+    plan_workspace_bytes,
+    refine_level,
+    validate_level,
+)
+from ._lib import HnvError  # noqa: F401

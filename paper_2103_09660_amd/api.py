@@ -1,0 +1,376 @@
+"""Python binding of the HyperNetVec refinement library (include/hnv.h).
+
+Every function here marshals arguments into one C-ABI call; the refinement
+itself (projection, sweeps, residuals, reverse sweeps, reciprocals, casts)
+runs in the library's HIP kernels.  PyTorch provides device memory and the
+current HIP stream.  The hierarchy (coarsening, Section 3.1) is built on the
+host by the library's own C++ code.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+
+
+def abi_version() -> int:
+    return int(L.lib().hnv_abi_version())
+
+
+def last_error() -> str:
+    return L.last_error()
+
+
+# ----------------------------------------------------------------------------
+# host hierarchy
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class HostLevel:
+    n_nodes: int
+    n_edges: int
+    edge_ptr: np.ndarray              # int64 [n_edges+1]
+    edge_idx: np.ndarray              # int32 [nnz]
+    edge_w: Optional[np.ndarray]      # float32 [n_edges] or None
+
+    def __post_init__(self):
+        self.edge_ptr = np.ascontiguousarray(self.edge_ptr, dtype=np.int64)
+        self.edge_idx = np.ascontiguousarray(self.edge_idx, dtype=np.int32)
+        if self.edge_w is not None:
+            self.edge_w = np.ascontiguousarray(self.edge_w, dtype=np.float32)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.edge_ptr[-1])
+
+    @property
+    def rows(self) -> int:
+        return self.n_nodes + self.n_edges
+
+    def c(self) -> L.HnvLevel:
+        return L.HnvLevel(self.n_nodes, self.n_edges, self.nnz,
+                          self.edge_ptr.ctypes.data_as(L.i64p), self.edge_idx.ctypes.data_as(L.i32p),
+                          None if self.edge_w is None else self.edge_w.ctypes.data_as(L.f32p))
+
+
+@dataclasses.dataclass
+class HostMap:
+    node_rep: np.ndarray   # int32 [n_nodes of the finer level]
+    edge_rep: np.ndarray   # int32 [n_edges of the finer level], -1 = removed
+
+    def c(self) -> L.HnvMap:
+        return L.HnvMap(self.node_rep.ctypes.data_as(L.i32p), self.edge_rep.ctypes.data_as(L.i32p))
+
+
+def validate_level(level: HostLevel) -> None:
+    lv = level.c()
+    L.call("hnv_validate_level", ctypes.byref(lv))
+
+
+def coarsen_level(level: HostLevel):
+    """One featureless coarsening step (library C++): returns (HostMap, coarse HostLevel)."""
+    nnz = level.nnz
+    node_rep = np.empty(max(level.n_nodes, 1), dtype=np.int32)
+    edge_rep = np.empty(max(level.n_edges, 1), dtype=np.int32)
+    c_ptr = np.empty(level.n_edges + 1, dtype=np.int64)
+    c_idx = np.empty(max(nnz, 1), dtype=np.int32)
+    c_w = None if level.edge_w is None else np.empty(max(level.n_edges, 1), dtype=np.float32)
+    nv, ne, nz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    lv = level.c()
+    L.call("hnv_coarsen_level", ctypes.byref(lv), node_rep.ctypes.data_as(L.i32p), edge_rep.ctypes.data_as(L.i32p),
+           c_ptr.ctypes.data_as(L.i64p), c_idx.ctypes.data_as(L.i32p),
+           None if c_w is None else c_w.ctypes.data_as(L.f32p), ctypes.byref(nv), ctypes.byref(ne), ctypes.byref(nz))
+    coarse = HostLevel(nv.value, ne.value, c_ptr[: ne.value + 1].copy(), c_idx[: nz.value].copy(),
+                       None if c_w is None else c_w[: ne.value].copy())
+    return HostMap(node_rep[: level.n_nodes].copy(), edge_rep[: level.n_edges].copy()), coarse
+
+
+class Hierarchy:
+    """Levels 0 (finest) .. L (coarsest) and the maps between them."""
+
+    def __init__(self, levels: List[HostLevel], maps: List[HostMap]):
+        assert len(maps) == len(levels) - 1
+        self.levels = levels
+        self.maps = maps
+
+    @classmethod
+    def build(cls, n_nodes, n_edges, edge_ptr, edge_idx, edge_w, n_coarsen: int) -> "Hierarchy":
+        levels = [HostLevel(n_nodes, n_edges, edge_ptr, edge_idx, edge_w)]
+        maps = []
+        for _ in range(n_coarsen):
+            m, c = coarsen_level(levels[-1])
+            maps.append(m)
+            levels.append(c)
+        return cls(levels, maps)
+
+    @property
+    def n_levels(self) -> int:
+        return len(self.levels)
+
+    def c_arrays(self):
+        lv = (L.HnvLevel * self.n_levels)(*[x.c() for x in self.levels])
+        mp = (L.HnvMap * max(len(self.maps), 1))(*[m.c() for m in self.maps]) if self.maps else None
+        return lv, mp
+
+
+def _options(options) -> Optional[L.HnvOptions]:
+    if options is None:
+        return None
+    if isinstance(options, L.HnvOptions):
+        return options
+    return L.HnvOptions(int(options.get("panel_cols", 0)), int(options.get("small_max", 0)),
+                        int(options.get("chunk", 0)))
+
+
+def plan_workspace_bytes(hier: Hierarchy, d: int, dtype: str = "f32", options=None) -> int:
+    lv, mp = hier.c_arrays()
+    out = ctypes.c_size_t()
+    o = _options(options)
+    L.call("hnv_plan_workspace_bytes", lv, mp, hier.n_levels, d, _dt(dtype),
+           None if o is None else ctypes.byref(o), ctypes.byref(out))
+    return int(out.value)
+
+
+def _dt(dtype: str) -> int:
+    if dtype in ("f32", "float32"):
+        return L.HNV_F32
+    if dtype in ("bf16", "bfloat16"):
+        return L.HNV_BF16
+    raise ValueError(dtype)
+
+
+# ----------------------------------------------------------------------------
+# device plan
+# ----------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(device=None) -> int:
+    torch = _torch()
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Plan:
+    """A device plan over a hierarchy: the workspace (a torch uint8 tensor)
+    holds every level's adjacency, work lists, maps and reciprocals."""
+
+    def __init__(self, hier: Hierarchy, d: int, dtype: str = "f32", options=None, device=None,
+                 validate: bool = True):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("a GPU is required for a device plan")
+        self.device = torch.device("cuda" if device is None else device)
+        self.hier = hier
+        self.d = int(d)
+        self.dtype = dtype
+        self.torch_dtype = torch.float32 if _dt(dtype) == L.HNV_F32 else torch.bfloat16
+        self.n_levels = hier.n_levels
+        nbytes = plan_workspace_bytes(hier, d, dtype, options)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % 256:
+            raise RuntimeError("workspace is not 256-byte aligned")
+        lv, mp = hier.c_arrays()
+        o = _options(options)
+        handle = ctypes.c_void_p()
+        L.call("hnv_plan_create", lv, mp, self.n_levels, self.d, _dt(dtype), None if o is None else ctypes.byref(o),
+               1 if validate else 0, self.workspace.data_ptr(), nbytes, _stream(self.device), ctypes.byref(handle))
+        self._h = handle
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().hnv_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # sizes -----------------------------------------------------------------
+    def level_info(self, level: int):
+        nv, ne, nz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        L.call("hnv_plan_level_info", self._h, level, ctypes.byref(nv), ctypes.byref(ne), ctypes.byref(nz))
+        return nv.value, ne.value, nz.value
+
+    def rows(self, level: int) -> int:
+        nv, ne, _ = self.level_info(level)
+        return nv + ne
+
+    def empty(self, level: int):
+        return _torch().empty((self.rows(level), self.d), dtype=self.torch_dtype, device=self.device)
+
+    def _check(self, t, level: int, name: str):
+        if t.dtype != self.torch_dtype or not t.is_contiguous() or t.device.type != "cuda" or \
+                tuple(t.shape) != (self.rows(level), self.d):
+            raise ValueError(f"{name}: expected contiguous {self.torch_dtype} [{self.rows(level)} x {self.d}] "
+                             f"on the GPU, got {t.dtype} {tuple(t.shape)} on {t.device}")
+
+    # weights ---------------------------------------------------------------
+    def set_edge_weights(self, level: int, w):
+        L.call("hnv_set_edge_weights", self._h, level, _ptr(w), _stream(self.device))
+
+    def set_edge_logweights(self, level: int, theta, w_out=None):
+        L.call("hnv_set_edge_logweights", self._h, level, _ptr(theta), _ptr(w_out), _stream(self.device))
+
+    def logweight_grad(self, level: int, dw, dtheta=None):
+        out = dw if dtheta is None else dtheta
+        L.call("hnv_logweight_grad", self._h, level, _ptr(dw), _ptr(out), _stream(self.device))
+        return out
+
+    # forward ---------------------------------------------------------------
+    def refine(self, z_coarsest, sweeps: Sequence[int], omega: float = 0.5, tol: float = 0.0,
+               residuals: bool = False, out=None):
+        """Multi-level refinement.  Returns (z_finest, residuals or None, sweeps_done)."""
+        torch = _torch()
+        self._check(z_coarsest, self.n_levels - 1, "z_coarsest")
+        z_out = self.empty(0) if out is None else out
+        self._check(z_out, 0, "out")
+        sw = np.ascontiguousarray(sweeps, dtype=np.int32)
+        assert len(sw) == self.n_levels
+        res = torch.zeros(max(int(sw.sum()), 1), dtype=torch.float64, device=self.device) if residuals else None
+        done = np.zeros(self.n_levels, dtype=np.int32)
+        L.call("hnv_refine", self._h, z_coarsest.data_ptr(), z_out.data_ptr(), sw.ctypes.data_as(L.i32p),
+               float(omega), float(tol), _ptr(res), done.ctypes.data_as(L.i32p), _stream(self.device))
+        return z_out, res, done
+
+    def sweep(self, level: int, z_in, omega: float = 0.5, from_coarse: bool = False, out=None, resid=None):
+        self._check(z_in, level + 1 if from_coarse else level, "z_in")
+        z_out = self.empty(level) if out is None else out
+        self._check(z_out, level, "out")
+        L.call("hnv_sweep", self._h, level, z_in.data_ptr(), z_out.data_ptr(), float(omega), 1 if from_coarse else 0,
+               _ptr(resid), _stream(self.device))
+        return z_out
+
+    def project(self, level: int, z_coarse, out=None):
+        self._check(z_coarse, level + 1, "z_coarse")
+        z_out = self.empty(level) if out is None else out
+        self._check(z_out, level, "out")
+        L.call("hnv_project", self._h, level, z_coarse.data_ptr(), z_out.data_ptr(), _stream(self.device))
+        return z_out
+
+    # reverse ---------------------------------------------------------------
+    def sweep_adjoint(self, level: int, g_in, z_prev, z_cur, omega: float = 0.5, dw=None, out=None):
+        for t, n in ((g_in, "g_in"), (z_prev, "z_prev"), (z_cur, "z_cur")):
+            self._check(t, level, n)
+        g_out = self.empty(level) if out is None else out
+        self._check(g_out, level, "out")
+        L.call("hnv_sweep_adjoint", self._h, level, g_in.data_ptr(), g_out.data_ptr(), z_prev.data_ptr(),
+               z_cur.data_ptr(), _ptr(dw), float(omega), _stream(self.device))
+        return g_out
+
+    def project_adjoint(self, level: int, g_fine, out=None):
+        self._check(g_fine, level, "g_fine")
+        g_out = self.empty(level + 1) if out is None else out
+        self._check(g_out, level + 1, "out")
+        L.call("hnv_project_adjoint", self._h, level, g_fine.data_ptr(), g_out.data_ptr(), _stream(self.device))
+        return g_out
+
+
+def cast(src, dst_dtype: str):
+    """Storage conversion on the device (FP32 -> BF16 rounds to nearest even)."""
+    torch = _torch()
+    sdt = L.HNV_F32 if src.dtype == torch.float32 else L.HNV_BF16 if src.dtype == torch.bfloat16 else None
+    if sdt is None or not src.is_contiguous():
+        raise ValueError("cast: contiguous float32 or bfloat16 tensor expected")
+    ddt = _dt(dst_dtype)
+    out = torch.empty(src.shape, dtype=torch.float32 if ddt == L.HNV_F32 else torch.bfloat16, device=src.device)
+    L.call("hnv_cast", src.data_ptr(), sdt, out.data_ptr(), ddt, src.numel(), _stream(src.device))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# autograd
+# ----------------------------------------------------------------------------
+
+def _refine_function():
+    torch = _torch()
+
+    class RefineFunction(torch.autograd.Function):
+        """K sweeps at one level with learnable log-weights theta (w = exp theta),
+        starting from the coarser level's embedding (from_coarse, the first
+        sweep fused with the projection) or from this level's own.  The
+        forward keeps every ckpt_every-th state; the backward recomputes each
+        segment from its checkpoint and runs the reverse sweeps."""
+
+        @staticmethod
+        def forward(ctx, z_start, theta, plan, level, sweeps, omega, from_coarse, ckpt_every):
+            if theta is not None:
+                plan.set_edge_logweights(level, theta.detach())
+            ck = max(1, int(ckpt_every))
+            K = int(sweeps)
+            saved = {0: z_start.detach()}
+            cur = z_start.detach()
+            for i in range(1, K + 1):
+                nxt = plan.sweep(level, cur, omega, from_coarse=(from_coarse and i == 1))
+                if i % ck == 0 or i == K:
+                    saved[i] = nxt
+                cur = nxt
+            if K == 0:
+                cur = plan.project(level, z_start.detach()) if from_coarse else z_start.detach().clone()
+            ctx.plan, ctx.level, ctx.K, ctx.omega, ctx.from_coarse, ctx.ck = plan, level, K, omega, from_coarse, ck
+            ctx.ckpt_keys = sorted(saved)
+            ctx.save_for_backward(*(saved[k] for k in ctx.ckpt_keys), *(() if theta is None else (theta.detach(),)))
+            ctx.has_theta = theta is not None
+            return cur
+
+        @staticmethod
+        def backward(ctx, g_out):
+            torch = _torch()
+            plan, level, K, omega = ctx.plan, ctx.level, ctx.K, ctx.omega
+            tensors = ctx.saved_tensors
+            n_ck = len(ctx.ckpt_keys)
+            ckpts = dict(zip(ctx.ckpt_keys, tensors[:n_ck]))
+            theta = tensors[n_ck] if ctx.has_theta else None
+            if theta is not None:
+                plan.set_edge_logweights(level, theta)
+            g = g_out.contiguous().to(plan.torch_dtype)
+            n_edges = plan.level_info(level)[1]
+            dw = torch.zeros(max(n_edges, 1), dtype=torch.float32, device=plan.device) if theta is not None else None
+            bounds = ctx.ckpt_keys
+            for si in range(len(bounds) - 1, 0, -1):
+                s0, s1 = bounds[si - 1], bounds[si]
+                states = {}
+                start = ckpts[s0]
+                if ctx.from_coarse and s0 == 0:
+                    states[0] = plan.project(level, start)
+                else:
+                    states[s0] = start
+                for i in range(s0 + 1, s1):
+                    states[i] = plan.sweep(level, states[i - 1], omega)
+                states[s1] = ckpts[s1]
+                for i in range(s1, s0, -1):
+                    g = plan.sweep_adjoint(level, g, states[i - 1], states[i], omega, dw=dw)
+            if K == 0 and not ctx.from_coarse:
+                gz = g
+            elif ctx.from_coarse:
+                gz = plan.project_adjoint(level, g)
+            else:
+                gz = g
+            gtheta = plan.logweight_grad(level, dw)[:n_edges] if theta is not None else None
+            return gz, gtheta, None, None, None, None, None, None
+
+    return RefineFunction
+
+
+_RF = None
+
+
+def refine_level(z_start, theta, plan: Plan, level: int, sweeps: int, omega: float = 0.5,
+                 from_coarse: bool = True, ckpt_every: int = 5):
+    """Differentiable refinement of one level (see RefineFunction)."""
+    global _RF
+    if _RF is None:
+        _RF = _refine_function()
+    return _RF.apply(z_start, theta, plan, level, sweeps, omega, from_coarse, ckpt_every)

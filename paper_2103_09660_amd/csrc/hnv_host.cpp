@@ -1,0 +1,667 @@
+// Host side of the HyperNetVec refinement library: error plumbing, input
+// validation, featureless coarsening (Section 3.1, Algorithm 1), and the
+// plan: star-expansion adjacency in both directions, degree-tiered work
+// lists, projection row maps and their inverse, all carved out of the
+// caller's device workspace.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hnv_internal.h"
+
+namespace hnv {
+
+static thread_local std::string g_error;
+
+hnv_status fail(hnv_status st, const std::string &msg)
+{
+    g_error = msg;
+    return st;
+}
+
+void clear_error() { g_error.clear(); }
+
+int next_pow2(int x)
+{
+    int p = 1;
+    while (p < x)
+        p <<= 1;
+    return p;
+}
+
+int64_t blocks_for(int64_t items, int64_t per_block) { return (items + per_block - 1) / per_block; }
+
+static constexpr int64_t kMaxI32 = std::numeric_limits<int32_t>::max();
+static constexpr int kDefaultSmallMax = 32;
+static constexpr int kDefaultChunk = 512;
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+
+// full = false checks only what memory safety needs (offsets and index
+// ranges); full = true also checks ordering, emptiness and weights.
+static hnv_status validate(const hnv_level *lv, bool full = true)
+{
+    if (!lv)
+        return fail(HNV_EINVAL, "level is NULL");
+    if (lv->n_nodes < 0 || lv->n_edges < 0 || lv->nnz < 0)
+        return fail(HNV_EINVAL, "negative size");
+    if (lv->n_nodes + lv->n_edges >= kMaxI32 || lv->nnz >= kMaxI32)
+        return fail(HNV_EUNSUPPORTED, "rows and nnz must be below 2^31");
+    if (!lv->edge_ptr || (lv->nnz > 0 && !lv->edge_idx))
+        return fail(HNV_EINVAL, "edge_ptr / edge_idx is NULL");
+    if (lv->edge_ptr[0] != 0 || lv->edge_ptr[lv->n_edges] != lv->nnz)
+        return fail(HNV_EINVAL, "edge_ptr must start at 0 and end at nnz");
+    for (int64_t e = 0; e < lv->n_edges; ++e) {
+        const int64_t a = lv->edge_ptr[e], b = lv->edge_ptr[e + 1];
+        if (b < a || b > lv->nnz)
+            return fail(HNV_EINVAL, "edge_ptr decreases at hyperedge " + std::to_string(e));
+        if (full && b == a)
+            return fail(HNV_EINVAL, "hyperedge " + std::to_string(e) + " is empty");
+        for (int64_t j = a; j < b; ++j) {
+            const int32_t v = lv->edge_idx[j];
+            if (v < 0 || v >= lv->n_nodes)
+                return fail(HNV_ERANGE, "member " + std::to_string(v) + " of hyperedge " + std::to_string(e) +
+                                            " outside [0, n_nodes)");
+            if (full && j > a && lv->edge_idx[j - 1] >= v)
+                return fail(HNV_EUNSORTED, "members of hyperedge " + std::to_string(e) +
+                                               " are not strictly ascending");
+        }
+        if (full && lv->edge_w) {
+            const float w = lv->edge_w[e];
+            if (!(w > 0.0f) || !std::isfinite(w))
+                return fail(HNV_EINVAL, "weight of hyperedge " + std::to_string(e) + " is not finite and > 0");
+        }
+    }
+    return HNV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// coarsening
+// ---------------------------------------------------------------------------
+
+// node -> incident hyperedges, ascending hyperedge id, via a counting pass
+static void incidence_by_node(const hnv_level *lv, std::vector<int32_t> &nptr, std::vector<int32_t> &nedge)
+{
+    nptr.assign(lv->n_nodes + 1, 0);
+    for (int64_t j = 0; j < lv->nnz; ++j)
+        ++nptr[lv->edge_idx[j] + 1];
+    for (int64_t v = 0; v < lv->n_nodes; ++v)
+        nptr[v + 1] += nptr[v];
+    nedge.resize(lv->nnz);
+    std::vector<int32_t> cursor(nptr.begin(), nptr.end() - 1);
+    for (int64_t e = 0; e < lv->n_edges; ++e)
+        for (int64_t j = lv->edge_ptr[e]; j < lv->edge_ptr[e + 1]; ++j)
+            nedge[cursor[lv->edge_idx[j]]++] = (int32_t)e;
+}
+
+static hnv_status coarsen(const hnv_level *lv, int32_t *node_rep, int32_t *edge_rep, int64_t *c_ptr,
+                          int32_t *c_idx, float *c_w, int64_t *c_nodes, int64_t *c_edges, int64_t *c_nnz)
+{
+    const int64_t nV = lv->n_nodes, nE = lv->n_edges;
+    std::vector<int32_t> nptr, nedge;
+    incidence_by_node(lv, nptr, nedge);
+
+    // Assignment key of a hyperedge: larger weight wins, then fewer members,
+    // then the lower id.  choice[v] = -1 for a node without hyperedges.
+    auto wt = [&](int32_t e) { return lv->edge_w ? lv->edge_w[e] : 1.0f; };
+    auto size = [&](int32_t e) { return lv->edge_ptr[e + 1] - lv->edge_ptr[e]; };
+    std::vector<int32_t> choice(nV, -1);
+    for (int64_t v = 0; v < nV; ++v) {
+        int32_t best = -1;
+        for (int32_t j = nptr[v]; j < nptr[v + 1]; ++j) {
+            const int32_t e = nedge[j];
+            if (best < 0) {
+                best = e;
+                continue;
+            }
+            const float we = wt(e), wb = wt(best);
+            const int64_t se = size(e), sb = size(best);
+            if (we > wb || (we == wb && (se < sb || (se == sb && e < best))))
+                best = e;
+        }
+        choice[v] = best;
+    }
+
+    // Coarse node numbering: first appearance of a group in ascending v.
+    std::vector<int32_t> group_of_edge(nE, -1);
+    std::vector<int64_t> chosen_count(nE, 0);
+    int32_t n_groups = 0;
+    for (int64_t v = 0; v < nV; ++v) {
+        const int32_t e = choice[v];
+        if (e < 0) {
+            node_rep[v] = n_groups++;
+            continue;
+        }
+        if (group_of_edge[e] < 0)
+            group_of_edge[e] = n_groups++;
+        node_rep[v] = group_of_edge[e];
+        ++chosen_count[e];
+    }
+
+    // A hyperedge is removed when every member chose it (count == size).
+    int32_t kept = 0;
+    for (int64_t e = 0; e < nE; ++e)
+        edge_rep[e] = (chosen_count[e] == size((int32_t)e)) ? -1 : kept++;
+
+    // Coarse member sets through rep(), ascending, repeats collapsed.
+    int64_t pos = 0;
+    c_ptr[0] = 0;
+    std::vector<int32_t> buf;
+    for (int64_t e = 0; e < nE; ++e) {
+        if (edge_rep[e] < 0)
+            continue;
+        buf.assign(lv->edge_idx + lv->edge_ptr[e], lv->edge_idx + lv->edge_ptr[e + 1]);
+        for (auto &v : buf)
+            v = node_rep[v];
+        std::sort(buf.begin(), buf.end());
+        const auto end = std::unique(buf.begin(), buf.end());
+        for (auto it = buf.begin(); it != end; ++it)
+            c_idx[pos++] = *it;
+        c_ptr[edge_rep[e] + 1] = pos;
+        if (c_w)
+            c_w[edge_rep[e]] = wt((int32_t)e);
+    }
+    *c_nodes = n_groups;
+    *c_edges = kept;
+    *c_nnz = pos;
+    return HNV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// plan construction
+// ---------------------------------------------------------------------------
+
+struct HostTier {
+    std::vector<int32_t> small;
+    std::vector<Chunk> chunks;
+    std::vector<Split> splits;
+};
+
+// Rows with at most small_max neighbours: ordered by degree (descending,
+// then row) so that the rows sharing a wavefront have equal trip counts.
+// Longer rows: cut into chunks of at most `chunk` neighbours; a row of more
+// than one chunk gets consecutive partial slots.  Chunks are ordered longest
+// first so the heaviest work starts earliest.
+static void tier_side(const int32_t *ptr, int32_t n_rows, int small_max, int chunk, int32_t *slot_base,
+                      HostTier &t)
+{
+    std::vector<int32_t> count(small_max + 2, 0);
+    int64_t n_small = 0;
+    for (int32_t r = 0; r < n_rows; ++r) {
+        const int32_t deg = ptr[r + 1] - ptr[r];
+        if (deg <= small_max) {
+            ++count[small_max - deg + 1];
+            ++n_small;
+        }
+    }
+    for (int k = 0; k <= small_max; ++k)
+        count[k + 1] += count[k];
+    t.small.assign(n_small, 0);
+    t.chunks.clear();
+    t.splits.clear();
+    for (int32_t r = 0; r < n_rows; ++r) {
+        const int32_t deg = ptr[r + 1] - ptr[r];
+        if (deg <= small_max) {
+            t.small[count[small_max - deg]++] = r;
+            continue;
+        }
+        const int32_t pieces = (deg + chunk - 1) / chunk;
+        if (pieces == 1) {
+            t.chunks.push_back(Chunk{r, ptr[r], deg, -1});
+            continue;
+        }
+        t.splits.push_back(Split{r, *slot_base, pieces, deg});
+        for (int32_t k = 0; k < pieces; ++k) {
+            const int32_t s = ptr[r] + k * chunk;
+            t.chunks.push_back(Chunk{r, s, std::min(chunk, ptr[r + 1] - s), *slot_base + k});
+        }
+        *slot_base += pieces;
+    }
+    std::stable_sort(t.chunks.begin(), t.chunks.end(),
+                     [](const Chunk &a, const Chunk &b) { return a.len > b.len; });
+}
+
+struct HostLevel {
+    int64_t nV = 0, nE = 0, nnz = 0, rows = 0, rows_c = 0;
+    bool has_coarse = false;
+    std::vector<int32_t> ptr[2], idx[2], cidx[2];
+    HostTier tier[2];
+    int32_t n_slots = 0;
+    std::vector<int32_t> rowmap, inv_ptr, inv_idx;
+};
+
+static void resolve_options(const hnv_options *in, int d, hnv_options *out)
+{
+    hnv_options o{};
+    if (in)
+        o = *in;
+    if (o.panel_cols <= 0)
+        o.panel_cols = d;
+    if (o.small_max <= 0)
+        o.small_max = kDefaultSmallMax;
+    if (o.chunk <= 0)
+        o.chunk = kDefaultChunk;
+    *out = o;
+}
+
+static hnv_status check_shape(const hnv_level *levels, const hnv_map *maps, int n_levels, int d,
+                              hnv_dtype dtype, const hnv_options &o)
+{
+    if (!levels || n_levels < 1)
+        return fail(HNV_EINVAL, "need at least one level");
+    if (n_levels > 1 && !maps)
+        return fail(HNV_EINVAL, "maps is NULL with more than one level");
+    if (d < 8 || d > 512 || d % 8 != 0)
+        return fail(HNV_EUNSUPPORTED, "d must be a multiple of 8 in [8, 512]");
+    if (dtype != HNV_F32 && dtype != HNV_BF16)
+        return fail(HNV_EINVAL, "unknown dtype");
+    if (o.panel_cols % 8 != 0 || d % o.panel_cols != 0)
+        return fail(HNV_EUNSUPPORTED, "panel_cols must be a multiple of 8 dividing d");
+    if (o.small_max > 4096 || o.chunk > (1 << 20))
+        return fail(HNV_EUNSUPPORTED, "small_max <= 4096 and chunk <= 2^20");
+    for (int l = 0; l < n_levels; ++l) {
+        const hnv_level &L = levels[l];
+        if (L.n_nodes < 0 || L.n_edges < 0 || L.nnz < 0 || !L.edge_ptr || (L.nnz > 0 && !L.edge_idx))
+            return fail(HNV_EINVAL, "level " + std::to_string(l) + ": bad sizes or NULL arrays");
+        if (L.n_nodes + L.n_edges >= kMaxI32 || L.nnz >= kMaxI32)
+            return fail(HNV_EUNSUPPORTED, "level " + std::to_string(l) + ": rows and nnz must be below 2^31");
+        if (l + 1 < n_levels && (!maps[l].node_rep || (L.n_edges > 0 && !maps[l].edge_rep)))
+            return fail(HNV_EINVAL, "map " + std::to_string(l) + " has a NULL array");
+    }
+    return HNV_OK;
+}
+
+static hnv_status check_map(const hnv_level &f, const hnv_level &c, const hnv_map &m, int l, bool full)
+{
+    for (int64_t v = 0; v < f.n_nodes; ++v)
+        if (m.node_rep[v] < 0 || m.node_rep[v] >= c.n_nodes)
+            return fail(HNV_ERANGE, "map " + std::to_string(l) + ": node_rep[" + std::to_string(v) + "] out of range");
+    for (int64_t e = 0; e < f.n_edges; ++e) {
+        const int32_t r = m.edge_rep[e];
+        if (r < -1 || r >= c.n_edges)
+            return fail(HNV_ERANGE, "map " + std::to_string(l) + ": edge_rep[" + std::to_string(e) + "] out of range");
+        if (r == -1 && f.edge_ptr[e + 1] == f.edge_ptr[e])
+            return fail(HNV_ERANGE, "map " + std::to_string(l) + ": removed hyperedge " + std::to_string(e) +
+                                        " has no members");
+        if (full && r == -1) {
+            const int32_t first = m.node_rep[f.edge_idx[f.edge_ptr[e]]];
+            for (int64_t j = f.edge_ptr[e]; j < f.edge_ptr[e + 1]; ++j)
+                if (m.node_rep[f.edge_idx[j]] != first)
+                    return fail(HNV_ERANGE, "map " + std::to_string(l) + ": removed hyperedge " + std::to_string(e) +
+                                                " has members in different coarse nodes");
+        }
+    }
+    return HNV_OK;
+}
+
+// Builds the host arrays of one level (with_arrays = false: only what the
+// workspace size needs).
+static void build_level(const hnv_level *levels, const hnv_map *maps, int n_levels, int l, const hnv_options &o,
+                        bool with_arrays, HostLevel &h)
+{
+    const hnv_level &L = levels[l];
+    h.nV = L.n_nodes;
+    h.nE = L.n_edges;
+    h.nnz = L.nnz;
+    h.rows = h.nV + h.nE;
+    h.has_coarse = (l + 1 < n_levels);
+    h.rows_c = h.has_coarse ? levels[l + 1].n_nodes + levels[l + 1].n_edges : 0;
+
+    // side 0: hyperedge rows -> member nodes (Z row = node id)
+    h.ptr[0].resize(h.nE + 1);
+    for (int64_t e = 0; e <= h.nE; ++e)
+        h.ptr[0][e] = (int32_t)L.edge_ptr[e];
+    // side 1: node rows -> incident hyperedges (Z row = n_nodes + e)
+    h.ptr[1].assign(h.nV + 1, 0);
+    for (int64_t j = 0; j < h.nnz; ++j)
+        ++h.ptr[1][L.edge_idx[j] + 1];
+    for (int64_t v = 0; v < h.nV; ++v)
+        h.ptr[1][v + 1] += h.ptr[1][v];
+
+    int32_t slots = 0;
+    tier_side(h.ptr[0].data(), (int32_t)h.nE, o.small_max, o.chunk, &slots, h.tier[0]);
+    tier_side(h.ptr[1].data(), (int32_t)h.nV, o.small_max, o.chunk, &slots, h.tier[1]);
+    h.n_slots = slots;
+    if (!with_arrays)
+        return;
+
+    h.idx[0].assign(L.edge_idx, L.edge_idx + h.nnz);
+    h.idx[1].resize(h.nnz);
+    {
+        std::vector<int32_t> cursor(h.ptr[1].begin(), h.ptr[1].end() - 1);
+        for (int64_t e = 0; e < h.nE; ++e)
+            for (int64_t j = L.edge_ptr[e]; j < L.edge_ptr[e + 1]; ++j)
+                h.idx[1][cursor[L.edge_idx[j]]++] = (int32_t)(h.nV + e);
+    }
+    if (!h.has_coarse)
+        return;
+
+    // Projection row map: node v -> rep(v); kept hyperedge -> rep(e);
+    // removed hyperedge -> the coarse node its members were merged into.
+    const hnv_map &m = maps[l];
+    const int64_t nVc = levels[l + 1].n_nodes;
+    h.rowmap.resize(h.rows);
+    for (int64_t v = 0; v < h.nV; ++v)
+        h.rowmap[v] = m.node_rep[v];
+    for (int64_t e = 0; e < h.nE; ++e) {
+        const int32_t r = m.edge_rep[e];
+        h.rowmap[h.nV + e] = (r >= 0) ? (int32_t)(nVc + r) : m.node_rep[L.edge_idx[L.edge_ptr[e]]];
+    }
+    for (int s = 0; s < 2; ++s) {
+        h.cidx[s].resize(h.nnz);
+        for (int64_t j = 0; j < h.nnz; ++j)
+            h.cidx[s][j] = h.rowmap[h.idx[s][j]];
+    }
+    // inverse map: fine rows of each coarse row, ascending
+    h.inv_ptr.assign(h.rows_c + 1, 0);
+    for (int64_t u = 0; u < h.rows; ++u)
+        ++h.inv_ptr[h.rowmap[u] + 1];
+    for (int64_t r = 0; r < h.rows_c; ++r)
+        h.inv_ptr[r + 1] += h.inv_ptr[r];
+    h.inv_idx.resize(h.rows);
+    std::vector<int32_t> cursor(h.inv_ptr.begin(), h.inv_ptr.end() - 1);
+    for (int64_t u = 0; u < h.rows; ++u)
+        h.inv_idx[cursor[h.rowmap[u]]++] = (int32_t)u;
+}
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <class T>
+    T *take(int64_t count)
+    {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += size_t(std::max<int64_t>(count, 1)) * sizeof(T);
+        return p;
+    }
+};
+
+void forward_geometry(const hnv_plan *p, const LevelPlan &L, int64_t *main_blocks, int64_t *fin_blocks)
+{
+    const int64_t rows_per_block = kBlock / p->g_fwd;
+    int64_t per_panel = 0;
+    for (int s = 0; s < 2; ++s)
+        per_panel += blocks_for(L.n_chunks[s], kWavesPerBlock) + blocks_for(L.n_small[s], rows_per_block);
+    int64_t fin = 0;
+    for (int s = 0; s < 2; ++s)
+        fin += blocks_for(L.n_splits[s], kWavesPerBlock);
+    *main_blocks = per_panel * p->panels;
+    *fin_blocks = fin * p->panels;
+}
+
+// Lays out the workspace (base == nullptr: sizing only) and fills the
+// plan's device pointers.
+static void carve(hnv_plan *p, std::vector<HostLevel> &hl, char *base)
+{
+    Carver c{base};
+    const size_t elem = (p->dtype == HNV_BF16) ? 2 : 4;
+    int64_t max_nodes = 1;
+    p->max_slots = 1;
+    p->max_resid_blocks = 1;
+    for (int l = 0; l < p->n_levels; ++l) {
+        HostLevel &h = hl[l];
+        LevelPlan &L = p->lv[l];
+        for (int s = 0; s < 2; ++s) {
+            DevSide &S = L.side[s];
+            S.n_rows = (int32_t)(s == 0 ? h.nE : h.nV);
+            S.row_base = (int32_t)(s == 0 ? h.nV : 0);
+            S.ptr = c.take<int32_t>(S.n_rows + 1);
+            S.idx = c.take<int32_t>(h.nnz);
+            S.cidx = h.has_coarse ? c.take<int32_t>(h.nnz) : nullptr;
+            S.wn = (s == 1) ? c.take<float>(h.nnz) : nullptr;
+            S.sn = c.take<float>(h.nnz);
+            S.n_small = (int32_t)h.tier[s].small.size();
+            S.n_chunks = (int32_t)h.tier[s].chunks.size();
+            S.n_splits = (int32_t)h.tier[s].splits.size();
+            S.small_rows = c.take<int32_t>(S.n_small);
+            S.chunks = c.take<Chunk>(S.n_chunks);
+            S.splits = c.take<Split>(S.n_splits);
+            L.n_small[s] = S.n_small;
+            L.n_chunks[s] = S.n_chunks;
+            L.n_splits[s] = S.n_splits;
+        }
+        L.r = c.take<float>(h.rows);
+        L.w = c.take<float>(h.nE);
+        if (h.has_coarse) {
+            L.rowmap = c.take<int32_t>(h.rows);
+            L.inv_ptr = c.take<int32_t>(h.rows_c + 1);
+            L.inv_idx = c.take<int32_t>(h.rows);
+        }
+        L.n_slots = h.n_slots;
+        max_nodes = std::max(max_nodes, h.nV);
+        p->max_slots = std::max<int64_t>(p->max_slots, h.n_slots);
+        int64_t mb = 0, fb = 0;
+        forward_geometry(p, L, &mb, &fb);
+        p->max_resid_blocks = std::max(p->max_resid_blocks, mb + fb);
+    }
+    p->zbuf = c.take<char>(p->lv[0].rows * p->d * (int64_t)elem);
+    p->partials = c.take<float>(p->max_slots * p->pstride);
+    p->resid_part = c.take<double>(p->max_resid_blocks);
+    p->cscratch = c.take<float>(max_nodes);
+    p->resid_tmp = c.take<double>(1);
+    p->ws_bytes = (c.off + 255) & ~size_t(255);
+}
+
+static void init_plan_shape(hnv_plan *p, const hnv_level *levels, int n_levels, int d, hnv_dtype dtype,
+                            const hnv_options &o)
+{
+    p->n_levels = n_levels;
+    p->d = d;
+    p->dtype = dtype;
+    p->opts = o;
+    p->dp = o.panel_cols;
+    p->panels = d / o.panel_cols;
+    p->g_fwd = next_pow2(p->dp / 8);
+    p->g_full = next_pow2(d / 8);
+    p->pstride = d + 8;
+    p->lv.assign(n_levels, LevelPlan{});
+    for (int l = 0; l < n_levels; ++l) {
+        LevelPlan &L = p->lv[l];
+        L.n_nodes = levels[l].n_nodes;
+        L.n_edges = levels[l].n_edges;
+        L.nnz = levels[l].nnz;
+        L.rows = L.n_nodes + L.n_edges;
+        L.has_coarse = (l + 1 < n_levels);
+        L.rows_coarse = L.has_coarse ? levels[l + 1].n_nodes + levels[l + 1].n_edges : 0;
+        L.unit_w = (levels[l].edge_w == nullptr);
+    }
+}
+
+}  // namespace hnv
+
+using namespace hnv;
+
+// ---------------------------------------------------------------------------
+// C ABI (host-only calls)
+// ---------------------------------------------------------------------------
+
+extern "C" int hnv_abi_version(void) { return HNV_ABI_VERSION; }
+
+extern "C" const char *hnv_last_error(void) { return g_error.c_str(); }
+
+extern "C" hnv_status hnv_validate_level(const hnv_level *level)
+{
+    clear_error();
+    return validate(level);
+}
+
+extern "C" hnv_status hnv_coarsen_level(const hnv_level *fine, int32_t *node_rep, int32_t *edge_rep,
+                                        int64_t *c_edge_ptr, int32_t *c_edge_idx, float *c_edge_w,
+                                        int64_t *c_n_nodes, int64_t *c_n_edges, int64_t *c_nnz)
+{
+    clear_error();
+    hnv_status st = validate(fine);
+    if (st != HNV_OK)
+        return st;
+    if ((fine->n_nodes > 0 && !node_rep) || (fine->n_edges > 0 && !edge_rep) || !c_edge_ptr ||
+        (fine->nnz > 0 && !c_edge_idx) || !c_n_nodes || !c_n_edges || !c_nnz)
+        return fail(HNV_EINVAL, "an output array is NULL");
+    try {
+        return coarsen(fine, node_rep, edge_rep, c_edge_ptr, c_edge_idx, c_edge_w, c_n_nodes, c_n_edges, c_nnz);
+    } catch (const std::bad_alloc &) {
+        return fail(HNV_ENOMEM, "host allocation failed in hnv_coarsen_level");
+    }
+}
+
+extern "C" hnv_status hnv_plan_workspace_bytes(const hnv_level *levels, const hnv_map *maps, int n_levels, int d,
+                                               hnv_dtype dtype, const hnv_options *opts, size_t *bytes)
+{
+    clear_error();
+    if (!bytes)
+        return fail(HNV_EINVAL, "bytes is NULL");
+    hnv_options o;
+    resolve_options(opts, d, &o);
+    hnv_status st = check_shape(levels, maps, n_levels, d, dtype, o);
+    if (st != HNV_OK)
+        return st;
+    try {
+        hnv_plan p;
+        init_plan_shape(&p, levels, n_levels, d, dtype, o);
+        std::vector<HostLevel> hl(n_levels);
+        for (int l = 0; l < n_levels; ++l)
+            build_level(levels, maps, n_levels, l, o, false, hl[l]);
+        carve(&p, hl, nullptr);
+        *bytes = p.ws_bytes;
+        return HNV_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(HNV_ENOMEM, "host allocation failed in hnv_plan_workspace_bytes");
+    }
+}
+
+static hnv_status upload(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0)
+        return HNV_OK;
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess)
+        return fail(HNV_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+    return HNV_OK;
+}
+
+extern "C" hnv_status hnv_plan_create(const hnv_level *levels, const hnv_map *maps, int n_levels, int d,
+                                      hnv_dtype dtype, const hnv_options *opts, int validate_inputs,
+                                      void *workspace, size_t ws_bytes, void *stream, hnv_plan **out)
+{
+    clear_error();
+    if (!out)
+        return fail(HNV_EINVAL, "out is NULL");
+    *out = nullptr;
+    hnv_options o;
+    resolve_options(opts, d, &o);
+    hnv_status st = check_shape(levels, maps, n_levels, d, dtype, o);
+    if (st != HNV_OK)
+        return st;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(HNV_EWORKSPACE, "workspace must be non-NULL and 256-byte aligned");
+    // Offsets, index ranges and map ranges are always checked (the kernels
+    // trust them); validate_inputs adds ordering, emptiness and weights.
+    for (int l = 0; l < n_levels; ++l) {
+        st = validate(&levels[l], validate_inputs != 0);
+        if (st != HNV_OK)
+            return fail(st, "level " + std::to_string(l) + ": " + g_error);
+        if (l + 1 < n_levels) {
+            st = check_map(levels[l], levels[l + 1], maps[l], l, validate_inputs != 0);
+            if (st != HNV_OK)
+                return st;
+        }
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hnv_plan *p = nullptr;
+    try {
+        p = new hnv_plan;
+        init_plan_shape(p, levels, n_levels, d, dtype, o);
+        // sizing pass (work-list counts only), then carve for real
+        {
+            std::vector<HostLevel> hl(n_levels);
+            for (int l = 0; l < n_levels; ++l)
+                build_level(levels, maps, n_levels, l, o, false, hl[l]);
+            carve(p, hl, nullptr);
+            if (p->ws_bytes > ws_bytes) {
+                const size_t need = p->ws_bytes;
+                delete p;
+                return fail(HNV_EWORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " +
+                                                std::to_string(need));
+            }
+            carve(p, hl, reinterpret_cast<char *>(workspace));
+        }
+        // one level at a time: build host arrays, upload, wait, free
+        for (int l = 0; l < n_levels; ++l) {
+            HostLevel h;
+            build_level(levels, maps, n_levels, l, o, true, h);
+            LevelPlan &L = p->lv[l];
+            for (int sd = 0; sd < 2; ++sd) {
+                DevSide &S = L.side[sd];
+                if ((st = upload((void *)S.ptr, h.ptr[sd].data(), h.ptr[sd].size() * 4, s)) != HNV_OK ||
+                    (st = upload((void *)S.idx, h.idx[sd].data(), h.idx[sd].size() * 4, s)) != HNV_OK ||
+                    (S.cidx && (st = upload((void *)S.cidx, h.cidx[sd].data(), h.cidx[sd].size() * 4, s)) != HNV_OK) ||
+                    (st = upload((void *)S.small_rows, h.tier[sd].small.data(), h.tier[sd].small.size() * 4, s)) != HNV_OK ||
+                    (st = upload((void *)S.chunks, h.tier[sd].chunks.data(), h.tier[sd].chunks.size() * sizeof(Chunk), s)) != HNV_OK ||
+                    (st = upload((void *)S.splits, h.tier[sd].splits.data(), h.tier[sd].splits.size() * sizeof(Split), s)) != HNV_OK)
+                    break;
+            }
+            if (st == HNV_OK && L.has_coarse) {
+                if ((st = upload(L.rowmap, h.rowmap.data(), h.rowmap.size() * 4, s)) == HNV_OK &&
+                    (st = upload(L.inv_ptr, h.inv_ptr.data(), h.inv_ptr.size() * 4, s)) == HNV_OK)
+                    st = upload(L.inv_idx, h.inv_idx.data(), h.inv_idx.size() * 4, s);
+            }
+            std::vector<float> w(L.n_edges, 1.0f);
+            if (st == HNV_OK && levels[l].edge_w)
+                std::copy(levels[l].edge_w, levels[l].edge_w + L.n_edges, w.begin());
+            if (st == HNV_OK)
+                st = upload(L.w, w.data(), w.size() * 4, s);
+            if (st == HNV_OK) {
+                hipError_t e = hipStreamSynchronize(s);
+                if (e != hipSuccess)
+                    st = fail(HNV_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+            }
+            if (st == HNV_OK)
+                st = dev_recompute_reciprocals(p, l, stream);
+            if (st != HNV_OK) {
+                delete p;
+                return st;
+            }
+        }
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            delete p;
+            return fail(HNV_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+        }
+    } catch (const std::bad_alloc &) {
+        delete p;
+        return fail(HNV_ENOMEM, "host allocation failed in hnv_plan_create");
+    }
+    *out = p;
+    return HNV_OK;
+}
+
+extern "C" hnv_status hnv_plan_destroy(hnv_plan *plan)
+{
+    clear_error();
+    delete plan;
+    return HNV_OK;
+}
+
+extern "C" hnv_status hnv_plan_level_info(const hnv_plan *plan, int level, int64_t *n_nodes, int64_t *n_edges,
+                                          int64_t *nnz)
+{
+    clear_error();
+    if (!plan || level < 0 || level >= plan->n_levels)
+        return fail(HNV_EINVAL, "bad plan or level");
+    const LevelPlan &L = plan->lv[level];
+    if (n_nodes)
+        *n_nodes = L.n_nodes;
+    if (n_edges)
+        *n_edges = L.n_edges;
+    if (nnz)
+        *nnz = L.nnz;
+    return HNV_OK;
+}

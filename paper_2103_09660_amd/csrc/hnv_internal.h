@@ -1,0 +1,103 @@
+// Internal declarations shared by the host code (hnv_host.cpp) and the HIP
+// kernels (hnv_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hnv.h"
+
+namespace hnv {
+
+constexpr int kBlock = 256;   // threads per workgroup (4 wavefronts of 64)
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+// A work item of the wavefront tier: `len` neighbours of `row` starting at
+// `start` in the side's neighbour array.  slot < 0: the wavefront owns the
+// whole row and writes the result; slot >= 0: it writes a partial sum to
+// partial slot `slot` and a finalize pass combines the row's slots in order.
+struct alignas(16) Chunk {
+    int32_t row, start, len, slot;
+};
+// A row split over n_slots consecutive partial slots starting at first_slot.
+struct alignas(16) Split {
+    int32_t row, first_slot, n_slots, deg;
+};
+
+// One side of the star expansion of a level, as device arrays.
+//   side 0: hyperedge rows, neighbours = member nodes (hyperedge->members)
+//   side 1: node rows, neighbours = incident hyperedges (node->hyperedges)
+struct DevSide {
+    int32_t n_rows = 0;
+    int32_t row_base = 0;            // Z row of local row 0 (n_nodes for side 0, 0 for side 1)
+    const int32_t *ptr = nullptr;    // [n_rows + 1]
+    const int32_t *idx = nullptr;    // [nnz] neighbour Z row at this level
+    const int32_t *cidx = nullptr;   // [nnz] neighbour Z row at the next coarser level, or null
+    float *wn = nullptr;             // [nnz] weight of each star edge (side 1 only)
+    float *sn = nullptr;             // [nnz] reverse-mode scale: reciprocal of the neighbour's row sum
+    const int32_t *small_rows = nullptr;
+    int32_t n_small = 0;
+    const Chunk *chunks = nullptr;
+    int32_t n_chunks = 0;
+    const Split *splits = nullptr;
+    int32_t n_splits = 0;
+};
+
+struct LevelPlan {
+    int64_t n_nodes = 0, n_edges = 0, nnz = 0, rows = 0;
+    int64_t rows_coarse = 0;         // rows of level + 1 (0 at the coarsest level)
+    bool has_coarse = false;
+    bool unit_w = true;
+    DevSide side[2];
+    float *r = nullptr;              // [rows] 1 / (row weight sum), 0 for rows without neighbours
+    float *w = nullptr;              // [n_edges] current hyperedge weights
+    int32_t *rowmap = nullptr;       // [rows] -> row of level + 1
+    int32_t *inv_ptr = nullptr;      // [rows_coarse + 1]
+    int32_t *inv_idx = nullptr;      // [rows] fine rows grouped by coarse row, ascending
+    int32_t n_slots = 0;             // partial slots used by split rows (both sides)
+    // host copies of the work-list sizes (for launch geometry)
+    int32_t n_small[2] = {0, 0}, n_chunks[2] = {0, 0}, n_splits[2] = {0, 0};
+};
+
+}  // namespace hnv
+
+struct hnv_plan {
+    int n_levels = 0;
+    int d = 0;
+    hnv_dtype dtype = HNV_F32;
+    hnv_options opts{};
+    std::vector<hnv::LevelPlan> lv;
+    void *zbuf = nullptr;            // scratch embedding [rows of level 0 x d]
+    float *partials = nullptr;       // [max_slots x pstride]
+    int32_t pstride = 0;             // floats per partial slot (d + 8)
+    int64_t max_slots = 0;
+    double *resid_part = nullptr;    // [max_resid_blocks]
+    int64_t max_resid_blocks = 0;
+    float *cscratch = nullptr;       // [max n_nodes] per-node scalar of the reverse sweep
+    double *resid_tmp = nullptr;     // [1]
+    int panels = 1;                  // column passes of a forward sweep
+    int dp = 0;                      // columns per pass
+    int g_fwd = 1;                   // lanes per row in a forward pass
+    int g_full = 1;                  // lanes per full-width row
+    size_t ws_bytes = 0;
+};
+
+namespace hnv {
+
+// thread-local error text
+hnv_status fail(hnv_status st, const std::string &msg);
+void clear_error();
+
+int next_pow2(int x);
+int64_t blocks_for(int64_t items, int64_t per_block);
+
+// Forward-sweep launch geometry of a level (blocks per panel and finalize blocks).
+void forward_geometry(const hnv_plan *p, const LevelPlan &L, int64_t *main_blocks, int64_t *fin_blocks);
+
+// Device-side pieces implemented in hnv_kernels.hip
+hnv_status dev_recompute_reciprocals(hnv_plan *p, int level, void *stream);
+hnv_status dev_check(const char *what);
+
+}  // namespace hnv

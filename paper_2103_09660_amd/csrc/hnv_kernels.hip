@@ -1,0 +1,1165 @@
+// HIP kernels (gfx950) of the HyperNetVec refinement library and the C ABI
+// calls that launch them.
+//
+// The refinement sweep (Section 3.3, Algorithm 2) is a sparse x dense gather
+// over the star expansion H* (Section 1.1): every row of H* relaxes towards
+// the weighted mean of its neighbours' rows.  It has no dense contraction, so
+// it is bound by HBM bandwidth and the kernels are built around memory
+// traffic, not matrix cores:
+//   - a row of Z is read by a group of G lanes, 8 elements (16 B of BF16,
+//     32 B of FP32) per lane, so every gathered row is one coalesced access;
+//   - rows are tiered by neighbour count on the host.  Rows with few
+//     neighbours are handled by one lane group each (64/G rows per
+//     wavefront, same-degree rows together).  Longer rows get a whole
+//     wavefront per chunk of neighbours.  The 64/G groups of the wavefront
+//     take interleaved neighbours and are combined with cross-lane shuffles.
+//     Rows longer than one chunk are split over several wavefronts whose FP32
+//     partial sums are combined in a fixed order by a finalize pass;
+//   - neighbour indices are loaded once per lane and broadcast with
+//     cross-lane shuffles, and four neighbour rows are in flight per lane;
+//   - the first sweep of a level reads the coarser level's rows through the
+//     projection row map (fused projection + sweep);
+//   - no atomics: every sum has a fixed order, so results are bitwise
+//     reproducible run to run;
+//   - the per-sweep residual is reduced in FP64 (per block, then a single
+//     fixed-order pass), as are the reciprocals of the row weight sums.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "hnv_internal.h"
+
+namespace hnv {
+
+typedef uint16_t bf16_t;
+
+// ---------------------------------------------------------------------------
+// storage conversions
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float bf_lo(uint32_t x) { return __uint_as_float(x << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t x) { return __uint_as_float(x & 0xffff0000u); }
+
+// FP32 -> BF16 bits, round to nearest even; NaN stays NaN.
+__device__ __forceinline__ uint32_t to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u)
+        return (u >> 16) | 0x40u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+template <typename T>
+struct Row8;
+
+template <>
+struct Row8<float> {
+    static __device__ __forceinline__ void load(const float *p, float (&v)[8])
+    {
+        const float4 a = reinterpret_cast<const float4 *>(p)[0];
+        const float4 b = reinterpret_cast<const float4 *>(p)[1];
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    }
+    // stores v and returns in v the values as stored
+    static __device__ __forceinline__ void store(float *p, float (&v)[8])
+    {
+        reinterpret_cast<float4 *>(p)[0] = make_float4(v[0], v[1], v[2], v[3]);
+        reinterpret_cast<float4 *>(p)[1] = make_float4(v[4], v[5], v[6], v[7]);
+    }
+};
+
+template <>
+struct Row8<bf16_t> {
+    static __device__ __forceinline__ void load(const bf16_t *p, float (&v)[8])
+    {
+        const uint4 q = *reinterpret_cast<const uint4 *>(p);
+        v[0] = bf_lo(q.x); v[1] = bf_hi(q.x); v[2] = bf_lo(q.y); v[3] = bf_hi(q.y);
+        v[4] = bf_lo(q.z); v[5] = bf_hi(q.z); v[6] = bf_lo(q.w); v[7] = bf_hi(q.w);
+    }
+    static __device__ __forceinline__ void store(bf16_t *p, float (&v)[8])
+    {
+        uint32_t h[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            h[i] = to_bf16(v[i]);
+            v[i] = __uint_as_float(h[i] << 16);
+        }
+        uint4 q;
+        q.x = h[0] | (h[1] << 16);
+        q.y = h[2] | (h[3] << 16);
+        q.z = h[4] | (h[5] << 16);
+        q.w = h[6] | (h[7] << 16);
+        *reinterpret_cast<uint4 *>(p) = q;
+    }
+};
+
+__device__ __forceinline__ void zero8(float (&a)[8])
+{
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        a[i] = 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// kernel arguments
+// ---------------------------------------------------------------------------
+
+enum Mode : int {
+    kFwd = 0,       // forward sweep
+    kAdjNode = 1,   // reverse sweep, node rows
+    kAdjEdge = 2,   // reverse sweep, hyperedge rows
+};
+
+struct GatherArgs {
+    DevSide side[2];
+    int32_t nb_chunk[2];      // blocks of the wavefront tier per side (per panel)
+    int32_t nb_small[2];      // blocks of the lane-group tier per side (per panel)
+    int32_t nb_split[2];      // finalize blocks per side (per panel)
+    int32_t blocks_per_panel;
+    int32_t dp;               // columns per panel
+    int64_t ld;               // row stride (elements) = d
+    float omega;
+    const float *r;           // [rows] reciprocal row weight sum
+    const float *w;           // [n_edges] hyperedge weights
+    const int32_t *rowmap;    // fused projection: row map to the coarser level
+    const void *src;          // gathered matrix (Z^{i-1}, the coarser Z if fused, or G)
+    void *dst;                // output matrix
+    const void *yprev;        // reverse: sweep input y
+    const void *zcur;         // reverse: sweep output z
+    float *cvec;              // reverse: per-node scalar (written on node rows, read on hyperedge rows)
+    float *dw;                // reverse: dL/dw accumulator or null
+    float *partials;          // split-row partial sums
+    int32_t pstride;
+    double *resid;            // per-block residual partials or null
+    int32_t resid_offset;     // first partial index of this launch
+};
+
+// ---------------------------------------------------------------------------
+// gathers
+// ---------------------------------------------------------------------------
+
+// One lane group (G lanes) gathers one row: acc = sum_j s_j * src[nb_j] over
+// the row's neighbours in order; csum = sum_j c[nb_j] (per lane, partial).
+template <typename T, int G, bool SCALE, bool SCALAR>
+__device__ __forceinline__ void gather_group(const int32_t *__restrict__ nb, const float *__restrict__ sc,
+                                             const float *__restrict__ cvec, int start, int deg,
+                                             const T *__restrict__ src, int64_t ld, int col, bool col_ok, int gl,
+                                             int gbase, float (&acc)[8], float &csum)
+{
+    for (int b = 0; b < deg; b += G) {
+        const int p = b + gl;
+        int my_nb = 0;
+        float my_s = 1.0f;
+        if (p < deg) {
+            my_nb = nb[start + p];
+            if (SCALE)
+                my_s = sc[start + p];
+            if (SCALAR)
+                csum += cvec[my_nb];
+        }
+        const int n = min(G, deg - b);
+        int j = 0;
+        for (; j + 4 <= n; j += 4) {
+            int v[4];
+            float s[4], x[4][8];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                v[k] = __shfl(my_nb, gbase + j + k, kWave);
+                s[k] = SCALE ? __shfl(my_s, gbase + j + k, kWave) : 1.0f;
+            }
+            if (col_ok) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    Row8<T>::load(src + (int64_t)v[k] * ld + col, x[k]);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        acc[i] = SCALE ? fmaf(s[k], x[k][i], acc[i]) : acc[i] + x[k][i];
+            }
+        }
+        for (; j < n; ++j) {
+            const int v = __shfl(my_nb, gbase + j, kWave);
+            const float s = SCALE ? __shfl(my_s, gbase + j, kWave) : 1.0f;
+            if (col_ok) {
+                float x[8];
+                Row8<T>::load(src + (int64_t)v * ld + col, x);
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    acc[i] = SCALE ? fmaf(s, x[i], acc[i]) : acc[i] + x[i];
+            }
+        }
+    }
+}
+
+// A whole wavefront gathers `len` neighbours: group g takes neighbours
+// g, g + Q, g + 2Q, ... (Q = 64 / G), then the Q group sums are added with an
+// xor butterfly (every lane ends with the same, order-fixed total).
+template <typename T, int G, bool SCALE, bool SCALAR>
+__device__ __forceinline__ void gather_wave(const int32_t *__restrict__ nb, const float *__restrict__ sc,
+                                            const float *__restrict__ cvec, int start, int len,
+                                            const T *__restrict__ src, int64_t ld, int col, bool col_ok, int lane,
+                                            int g, float (&acc)[8], float &csum)
+{
+    constexpr int Q = kWave / G;
+    for (int b = 0; b < len; b += kWave) {
+        const int p = b + lane;
+        int my_nb = 0;
+        float my_s = 1.0f;
+        if (p < len) {
+            my_nb = nb[start + p];
+            if (SCALE)
+                my_s = sc[start + p];
+            if (SCALAR)
+                csum += cvec[my_nb];
+        }
+        const int n = min(kWave, len - b);
+        for (int t = 0; t < n; t += 4 * Q) {
+            int v[4];
+            float s[4], x[4][8];
+            bool ok[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int q = t + k * Q + g;
+                ok[k] = q < n;
+                v[k] = __shfl(my_nb, q & (kWave - 1), kWave);
+                s[k] = SCALE ? __shfl(my_s, q & (kWave - 1), kWave) : 1.0f;
+            }
+            if (col_ok) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (ok[k])
+                        Row8<T>::load(src + (int64_t)v[k] * ld + col, x[k]);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (ok[k])
+#pragma unroll
+                        for (int i = 0; i < 8; ++i)
+                            acc[i] = SCALE ? fmaf(s[k], x[k][i], acc[i]) : acc[i] + x[k][i];
+            }
+        }
+    }
+#pragma unroll
+    for (int off = G; off < kWave; off <<= 1)
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            acc[i] += __shfl_xor(acc[i], off, kWave);
+    if (SCALAR) {
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1)
+            csum += __shfl_xor(csum, off, kWave);
+    }
+}
+
+// sum over the G lanes of a group (xor butterfly inside the group)
+template <int G>
+__device__ __forceinline__ float group_sum(float x)
+{
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1)
+        x += __shfl_xor(x, off, kWave);
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// row epilogues
+// ---------------------------------------------------------------------------
+
+// Forward: z'_u = (1 - omega) z_u + omega r_u acc (rows with neighbours),
+// z'_u = z_u otherwise.  Returns the row's contribution to ||z' - z||^2.
+template <typename T, bool FUSED>
+__device__ __forceinline__ double epilogue_fwd(const GatherArgs &a, int zrow, int deg, int col, bool col_ok,
+                                               float (&acc)[8])
+{
+    if (!col_ok)
+        return 0.0;
+    const T *src = static_cast<const T *>(a.src);
+    const int64_t self_row = FUSED ? (int64_t)a.rowmap[zrow] : (int64_t)zrow;
+    float z[8], o[8];
+    Row8<T>::load(src + self_row * a.ld + col, z);
+    if (deg > 0) {
+        const float keep = 1.0f - a.omega;
+        const float mix = a.omega * a.r[zrow];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            o[i] = fmaf(mix, acc[i], keep * z[i]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            o[i] = z[i];
+    }
+    Row8<T>::store(static_cast<T *>(a.dst) + (int64_t)zrow * a.ld + col, o);
+    double r2 = 0.0;
+    if (a.resid) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const double dd = (double)o[i] - (double)z[i];
+            r2 += dd * dd;
+        }
+    }
+    return r2;
+}
+
+// Reverse, node row v (side 1): g'_v = (1-omega) g_v + omega acc where acc =
+// sum_e g_e / |e|; c_v = <g_v, zt_v> / S_v with zt_v = (z_v - (1-omega) y_v) / omega.
+template <typename T, int G>
+__device__ __forceinline__ void epilogue_adj_node(const GatherArgs &a, int row, int deg, int col, bool col_ok,
+                                                  float (&acc)[8], bool writer)
+{
+    const int64_t zrow = row;  // node rows start at Z row 0
+    float g[8], y[8], z[8];
+    float dot = 0.0f;
+    if (col_ok) {
+        Row8<T>::load(static_cast<const T *>(a.src) + zrow * a.ld + col, g);
+        float o[8];
+        if (deg > 0) {
+            Row8<T>::load(static_cast<const T *>(a.yprev) + zrow * a.ld + col, y);
+            Row8<T>::load(static_cast<const T *>(a.zcur) + zrow * a.ld + col, z);
+            const float keep = 1.0f - a.omega;
+            const float inv_om = 1.0f / a.omega;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                o[i] = fmaf(a.omega, acc[i], keep * g[i]);
+                const float zt = (z[i] - keep * y[i]) * inv_om;
+                dot = fmaf(g[i], zt, dot);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                o[i] = g[i];
+        }
+        if (writer)
+            Row8<T>::store(static_cast<T *>(a.dst) + zrow * a.ld + col, o);
+    }
+    dot = group_sum<G>(dot);
+    if (writer && (threadIdx.x % G) == 0)
+        a.cvec[row] = (deg > 0) ? a.r[zrow] * dot : 0.0f;
+}
+
+// Reverse, hyperedge row e (side 0): g'_e = (1-omega) g_e + omega w_e acc with
+// acc = sum_v g_v / S_v; dL/dw_e += omega (<acc, y_e> - sum_v c_v).
+template <typename T, int G>
+__device__ __forceinline__ void epilogue_adj_edge(const GatherArgs &a, int row, int deg, int col, bool col_ok,
+                                                  float (&acc)[8], float csum, bool writer)
+{
+    const int64_t zrow = (int64_t)a.side[0].row_base + row;
+    float dot = 0.0f;
+    if (col_ok) {
+        float g[8], o[8];
+        Row8<T>::load(static_cast<const T *>(a.src) + zrow * a.ld + col, g);
+        if (deg > 0) {
+            float y[8];
+            Row8<T>::load(static_cast<const T *>(a.yprev) + zrow * a.ld + col, y);
+            const float keep = 1.0f - a.omega;
+            const float mix = a.omega * a.w[row];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                o[i] = fmaf(mix, acc[i], keep * g[i]);
+                dot = fmaf(acc[i], y[i], dot);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                o[i] = g[i];
+        }
+        if (writer)
+            Row8<T>::store(static_cast<T *>(a.dst) + zrow * a.ld + col, o);
+    }
+    dot = group_sum<G>(dot);
+    if (writer && a.dw && deg > 0 && (threadIdx.x % G) == 0)
+        a.dw[row] += a.omega * (dot - csum);
+}
+
+// ---------------------------------------------------------------------------
+// block-level residual reduction (FP64, fixed order)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void block_resid(const GatherArgs &a, double r2)
+{
+    if (!a.resid)
+        return;
+    __shared__ double wsum[kWavesPerBlock];
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1)
+        r2 += __shfl_xor(r2, off, kWave);
+    const int wave = threadIdx.x / kWave;
+    if ((threadIdx.x % kWave) == 0)
+        wsum[wave] = r2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < kWavesPerBlock; ++i)
+            s += wsum[i];
+        a.resid[a.resid_offset + blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// main kernel: wavefront tier + lane-group tier of both sides, all panels
+// ---------------------------------------------------------------------------
+
+template <typename T, int G, int MODE, bool FUSED>
+__global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
+{
+    constexpr int Q = kWave / G;
+    int b = blockIdx.x;
+    const int panel = b / a.blocks_per_panel;
+    b -= panel * a.blocks_per_panel;
+    const int lane = threadIdx.x % kWave;
+    const int wave = threadIdx.x / kWave;
+    const int g = lane / G;
+    const int gl = lane % G;
+    const int col = panel * a.dp + gl * 8;
+    const bool col_ok = gl * 8 < a.dp;
+    const T *src = static_cast<const T *>(a.src);
+    float acc[8];
+    zero8(acc);
+    float csum = 0.0f;
+    double r2 = 0.0;
+
+    // which tier / side does this block serve?
+    int side = -1, tier = 0;  // tier 0: wavefront, 1: lane group
+    if (b < a.nb_chunk[0]) {
+        side = 0;
+    } else if ((b -= a.nb_chunk[0]) < a.nb_chunk[1]) {
+        side = 1;
+    } else if ((b -= a.nb_chunk[1]) < a.nb_small[0]) {
+        side = 0;
+        tier = 1;
+    } else {
+        b -= a.nb_small[0];
+        side = 1;
+        tier = 1;
+    }
+    // Every side-dependent choice is uniform over the block.
+    const DevSide &S = a.side[side];
+    constexpr bool kScalar = (MODE == kAdjEdge);
+    const bool use_scale = (MODE != kFwd) || (side == 1 && S.wn != nullptr);
+    const float *sc = (MODE == kFwd) ? S.wn : S.sn;
+    const int32_t *nb = FUSED ? S.cidx : S.idx;
+
+    // In reverse mode only one side is active per launch.
+    if ((MODE == kAdjNode && side != 1) || (MODE == kAdjEdge && side != 0))
+        return;
+
+    if (tier == 0) {
+        const int item = b * kWavesPerBlock + wave;
+        const bool valid = item < S.n_chunks;
+        Chunk c{0, 0, 0, -1};
+        if (valid)
+            c = S.chunks[item];
+        if (valid) {
+            if (use_scale)
+                gather_wave<T, G, true, kScalar>(nb, sc, a.cvec, c.start, c.len, src, a.ld, col, col_ok, lane, g, acc,
+                                                 csum);
+            else
+                gather_wave<T, G, false, kScalar>(nb, sc, a.cvec, c.start, c.len, src, a.ld, col, col_ok, lane, g,
+                                                  acc, csum);
+        }
+        if (valid && c.slot >= 0) {
+            if (g == 0 && col_ok) {
+                float *pp = a.partials + (int64_t)c.slot * a.pstride + col;
+                reinterpret_cast<float4 *>(pp)[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+                reinterpret_cast<float4 *>(pp)[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+                if (kScalar && gl == 0)
+                    a.partials[(int64_t)c.slot * a.pstride + a.ld] = csum;
+            }
+        } else if (valid) {
+            const int deg = S.ptr[c.row + 1] - S.ptr[c.row];
+            if (MODE == kFwd) {
+                if (g == 0)
+                    r2 = epilogue_fwd<T, FUSED>(a, S.row_base + c.row, deg, col, col_ok, acc);
+            } else if (MODE == kAdjNode) {
+                epilogue_adj_node<T, G>(a, c.row, deg, col, col_ok, acc, g == 0);
+            } else {
+                epilogue_adj_edge<T, G>(a, c.row, deg, col, col_ok, acc, csum, g == 0);
+            }
+        }
+    } else {
+        const int item = b * (kBlock / G) + (int)(threadIdx.x / G);
+        const bool valid = item < S.n_small;
+        int row = 0, start = 0, deg = 0;
+        if (valid) {
+            row = S.small_rows[item];
+            start = S.ptr[row];
+            deg = S.ptr[row + 1] - start;
+        }
+        const int gbase = g * G;
+        if (use_scale)
+            gather_group<T, G, true, kScalar>(nb, sc, a.cvec, start, deg, src, a.ld, col, col_ok, gl, gbase, acc,
+                                              csum);
+        else
+            gather_group<T, G, false, kScalar>(nb, sc, a.cvec, start, deg, src, a.ld, col, col_ok, gl, gbase, acc,
+                                               csum);
+        if (MODE == kFwd) {
+            if (valid)
+                r2 = epilogue_fwd<T, FUSED>(a, S.row_base + row, deg, col, col_ok, acc);
+        } else if (MODE == kAdjNode) {
+            epilogue_adj_node<T, G>(a, row, deg, col, col_ok, acc, valid);
+        } else {
+            csum = group_sum<G>(csum);
+            epilogue_adj_edge<T, G>(a, row, deg, col, col_ok, acc, csum, valid);
+        }
+    }
+    (void)Q;
+    if (MODE == kFwd)
+        block_resid(a, r2);
+}
+
+// Finalize rows that were split over several wavefronts: one wavefront per
+// row adds the row's partial slots in slot order (group g takes slots
+// g, g+Q, ...; groups combined by the xor butterfly), then applies the
+// row's epilogue.
+template <typename T, int G, int MODE, bool FUSED>
+__global__ __launch_bounds__(kBlock) void k_finalize(GatherArgs a)
+{
+    constexpr int Q = kWave / G;
+    int b = blockIdx.x;
+    const int per_panel = a.nb_split[0] + a.nb_split[1];
+    const int panel = b / per_panel;
+    b -= panel * per_panel;
+    const int lane = threadIdx.x % kWave;
+    const int wave = threadIdx.x / kWave;
+    const int g = lane / G;
+    const int gl = lane % G;
+    const int col = panel * a.dp + gl * 8;
+    const bool col_ok = gl * 8 < a.dp;
+    int side = 0;
+    if (b >= a.nb_split[0]) {
+        b -= a.nb_split[0];
+        side = 1;
+    }
+    const DevSide &S = a.side[side];
+    const int item = b * kWavesPerBlock + wave;
+    const bool valid = item < S.n_splits;
+    float acc[8];
+    zero8(acc);
+    float csum = 0.0f;
+    double r2 = 0.0;
+    const bool active = valid && !((MODE == kAdjNode && side != 1) || (MODE == kAdjEdge && side != 0));
+    if (active) {
+        const Split sp = S.splits[item];
+        for (int k = g; k < sp.n_slots; k += Q) {
+            const float *pp = a.partials + (int64_t)(sp.first_slot + k) * a.pstride;
+            if (col_ok) {
+                const float4 x0 = reinterpret_cast<const float4 *>(pp + col)[0];
+                const float4 x1 = reinterpret_cast<const float4 *>(pp + col)[1];
+                acc[0] += x0.x; acc[1] += x0.y; acc[2] += x0.z; acc[3] += x0.w;
+                acc[4] += x1.x; acc[5] += x1.y; acc[6] += x1.z; acc[7] += x1.w;
+            }
+            if (MODE == kAdjEdge && gl == 0)
+                csum += pp[a.ld];
+        }
+#pragma unroll
+        for (int off = G; off < kWave; off <<= 1) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                acc[i] += __shfl_xor(acc[i], off, kWave);
+            if (MODE == kAdjEdge)
+                csum += __shfl_xor(csum, off, kWave);
+        }
+        if (MODE == kFwd) {
+            if (g == 0)
+                r2 = epilogue_fwd<T, FUSED>(a, S.row_base + sp.row, sp.deg, col, col_ok, acc);
+        } else if (MODE == kAdjNode) {
+            epilogue_adj_node<T, G>(a, sp.row, sp.deg, col, col_ok, acc, g == 0);
+        } else {
+            epilogue_adj_edge<T, G>(a, sp.row, sp.deg, col, col_ok, acc, csum, g == 0);
+        }
+    }
+    if (MODE == kFwd)
+        block_resid(a, r2);
+}
+
+// Single block: out[0] = sqrt(sum of n partials), summed in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_resid_final(const double *part, int64_t n, double *out)
+{
+    __shared__ double s[kBlock];
+    double x = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock)
+        x += part[i];
+    s[threadIdx.x] = x;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        out[0] = sqrt(s[0]);
+}
+
+// ---------------------------------------------------------------------------
+// projection and its reverse
+// ---------------------------------------------------------------------------
+
+// z_fine[u] = z_coarse[rowmap[u]], 8 elements per thread
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_project(const T *__restrict__ zc, T *__restrict__ zf,
+                                                    const int32_t *__restrict__ rowmap, int64_t rows, int d)
+{
+    const int per_row = d / 8;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= rows * per_row)
+        return;
+    const int64_t u = t / per_row;
+    const int c = (int)(t - u * per_row) * 8;
+    float v[8];
+    Row8<T>::load(zc + (int64_t)rowmap[u] * d + c, v);
+    Row8<T>::store(zf + u * d + c, v);
+}
+
+// g_coarse[r] = sum of g_fine[u] over rowmap(u) = r, ascending u.  One
+// wavefront per coarse row (gather_wave over the inverse map).
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_project_adj(const T *__restrict__ gf, T *__restrict__ gc,
+                                                        const int32_t *__restrict__ inv_ptr,
+                                                        const int32_t *__restrict__ inv_idx, int64_t rows_c, int d)
+{
+    const int64_t r = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int g = lane / G, gl = lane % G;
+    const int col = gl * 8;
+    const bool col_ok = col < d;
+    if (r >= rows_c)
+        return;  // uniform per wavefront
+    float acc[8];
+    zero8(acc);
+    float cs = 0.0f;
+    const int start = inv_ptr[r], len = inv_ptr[r + 1] - start;
+    gather_wave<T, G, false, false>(inv_idx, nullptr, nullptr, start, len, gf, d, col, col_ok, lane, g, acc, cs);
+    if (g == 0 && col_ok)
+        Row8<T>::store(gc + r * d + col, acc);
+}
+
+// ---------------------------------------------------------------------------
+// reciprocals (FP64) and per-star-edge scale arrays
+// ---------------------------------------------------------------------------
+
+// node v: S_v = sum_{e ∋ v} w_e in FP64 (one wavefront per node, lanes
+// strided, fixed butterfly), r_v = 1 / S_v (0 without hyperedges).
+__global__ __launch_bounds__(kBlock) void k_recip_nodes(const int32_t *__restrict__ ptr,
+                                                        const int32_t *__restrict__ idx,
+                                                        const float *__restrict__ w, int64_t n_nodes,
+                                                        int64_t row_base_edges, float *__restrict__ r)
+{
+    const int64_t v = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    if (v >= n_nodes)
+        return;
+    double s = 0.0;
+    for (int j = ptr[v] + lane; j < ptr[v + 1]; j += kWave)
+        s += (double)w[idx[j] - row_base_edges];
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1)
+        s += __shfl_xor(s, off, kWave);
+    if (lane == 0)
+        r[v] = (s > 0.0) ? (float)(1.0 / s) : 0.0f;
+}
+
+// hyperedge e: r_e = 1 / |e| (its weight cancels in its own mean)
+__global__ __launch_bounds__(kBlock) void k_recip_edges(const int32_t *__restrict__ ptr, int64_t n_edges,
+                                                        int64_t n_nodes, float *__restrict__ r)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= n_edges)
+        return;
+    const int deg = ptr[e + 1] - ptr[e];
+    r[n_nodes + e] = (deg > 0) ? (float)(1.0 / (double)deg) : 0.0f;
+}
+
+// per star edge: node side (neighbour = hyperedge e): weight w_e and reverse
+// scale r_e; hyperedge side (neighbour = node v): reverse scale r_v.
+__global__ __launch_bounds__(kBlock) void k_fill_edge_scales(const int32_t *__restrict__ idx_node_side,
+                                                             const int32_t *__restrict__ idx_edge_side,
+                                                             const float *__restrict__ w,
+                                                             const float *__restrict__ r, int64_t nnz,
+                                                             int64_t n_nodes, float *__restrict__ wn,
+                                                             float *__restrict__ sn_node_side,
+                                                             float *__restrict__ sn_edge_side)
+{
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= nnz)
+        return;
+    const int32_t erow = idx_node_side[j];
+    wn[j] = w[erow - n_nodes];
+    sn_node_side[j] = r[erow];
+    sn_edge_side[j] = r[idx_edge_side[j]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_exp(const float *__restrict__ theta, float *__restrict__ w,
+                                                float *__restrict__ w_out, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    const float x = expf(theta[i]);
+    w[i] = x;
+    if (w_out)
+        w_out[i] = x;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mul(const float *__restrict__ a, const float *__restrict__ b,
+                                                float *__restrict__ out, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n)
+        out[i] = a[i] * b[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cast_f32_bf16(const float *__restrict__ src, bf16_t *__restrict__ dst,
+                                                          int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n)
+        dst[i] = (bf16_t)to_bf16(src[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cast_bf16_f32(const bf16_t *__restrict__ src, float *__restrict__ dst,
+                                                          int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n)
+        dst[i] = __uint_as_float((uint32_t)src[i] << 16);
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+
+hnv_status dev_check(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(HNV_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return HNV_OK;
+}
+
+static inline unsigned grid1d(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+hnv_status dev_recompute_reciprocals(hnv_plan *p, int level, void *stream)
+{
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    LevelPlan &L = p->lv[level];
+    if (L.n_nodes > 0)
+        k_recip_nodes<<<grid1d(L.n_nodes, kWavesPerBlock), kBlock, 0, s>>>(L.side[1].ptr, L.side[1].idx, L.w,
+                                                                             L.n_nodes, L.n_nodes, L.r);
+    if (L.n_edges > 0)
+        k_recip_edges<<<grid1d(L.n_edges, kBlock), kBlock, 0, s>>>(L.side[0].ptr, L.n_edges, L.n_nodes, L.r);
+    if (L.nnz > 0)
+        k_fill_edge_scales<<<grid1d(L.nnz, kBlock), kBlock, 0, s>>>(L.side[1].idx, L.side[0].idx, L.w, L.r, L.nnz,
+                                                                    L.n_nodes, L.side[1].wn, L.side[1].sn,
+                                                                    L.side[0].sn);
+    return dev_check("reciprocal kernels");
+}
+
+static GatherArgs base_args(hnv_plan *p, LevelPlan &L, int G, int dp, int panels)
+{
+    GatherArgs a{};
+    a.side[0] = L.side[0];
+    a.side[1] = L.side[1];
+    if (L.unit_w)
+        a.side[1].wn = nullptr;  // unit weights: skip the per-edge multiply
+    const int rows_per_block = kBlock / G;
+    int32_t per_panel = 0;
+    for (int s = 0; s < 2; ++s) {
+        a.nb_chunk[s] = (int32_t)blocks_for(L.n_chunks[s], kWavesPerBlock);
+        a.nb_small[s] = (int32_t)blocks_for(L.n_small[s], rows_per_block);
+        a.nb_split[s] = (int32_t)blocks_for(L.n_splits[s], kWavesPerBlock);
+        per_panel += a.nb_chunk[s] + a.nb_small[s];
+    }
+    a.blocks_per_panel = per_panel;
+    a.dp = dp;
+    a.ld = p->d;
+    a.r = L.r;
+    a.w = L.w;
+    a.rowmap = L.rowmap;
+    a.partials = p->partials;
+    a.pstride = p->pstride;
+    (void)panels;
+    return a;
+}
+
+// Restricts a launch to one side (the reverse sweep runs its two sides as
+// two dependent launches).
+static GatherArgs only_side(GatherArgs a, int side)
+{
+    const int other = 1 - side;
+    a.nb_chunk[other] = a.nb_small[other] = a.nb_split[other] = 0;
+    a.blocks_per_panel = a.nb_chunk[side] + a.nb_small[side];
+    return a;
+}
+
+template <typename T, int G, int MODE, bool FUSED>
+static void launch_pair(const GatherArgs &a, int panels, hipStream_t s)
+{
+    const unsigned main_blocks = (unsigned)a.blocks_per_panel * panels;
+    if (main_blocks)
+        k_gather<T, G, MODE, FUSED><<<main_blocks, kBlock, 0, s>>>(a);
+    const unsigned fin_blocks = (unsigned)(a.nb_split[0] + a.nb_split[1]) * panels;
+    if (fin_blocks) {
+        GatherArgs f = a;
+        f.resid_offset = a.resid_offset + (int32_t)main_blocks;
+        k_finalize<T, G, MODE, FUSED><<<fin_blocks, kBlock, 0, s>>>(f);
+    }
+}
+
+template <typename T, int MODE, bool FUSED>
+static hnv_status dispatch_g(int G, const GatherArgs &a, int panels, hipStream_t s)
+{
+    switch (G) {
+    case 1: launch_pair<T, 1, MODE, FUSED>(a, panels, s); break;
+    case 2: launch_pair<T, 2, MODE, FUSED>(a, panels, s); break;
+    case 4: launch_pair<T, 4, MODE, FUSED>(a, panels, s); break;
+    case 8: launch_pair<T, 8, MODE, FUSED>(a, panels, s); break;
+    case 16: launch_pair<T, 16, MODE, FUSED>(a, panels, s); break;
+    case 32: launch_pair<T, 32, MODE, FUSED>(a, panels, s); break;
+    case 64: launch_pair<T, 64, MODE, FUSED>(a, panels, s); break;
+    default: return fail(HNV_EUNSUPPORTED, "lane group width");
+    }
+    return dev_check("sweep kernels");
+}
+
+// One forward sweep of `level` (src -> dst); fused reads the coarser level.
+static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, float omega, bool fused,
+                            double *resid_out, hipStream_t s)
+{
+    LevelPlan &L = p->lv[level];
+    GatherArgs a = base_args(p, L, p->g_fwd, p->dp, p->panels);
+    a.omega = omega;
+    a.src = src;
+    a.dst = dst;
+    a.resid = resid_out ? p->resid_part : nullptr;
+    a.resid_offset = 0;
+    hnv_status st;
+    if (p->dtype == HNV_F32)
+        st = fused ? dispatch_g<float, kFwd, true>(p->g_fwd, a, p->panels, s)
+                   : dispatch_g<float, kFwd, false>(p->g_fwd, a, p->panels, s);
+    else
+        st = fused ? dispatch_g<bf16_t, kFwd, true>(p->g_fwd, a, p->panels, s)
+                   : dispatch_g<bf16_t, kFwd, false>(p->g_fwd, a, p->panels, s);
+    if (st != HNV_OK)
+        return st;
+    if (resid_out) {
+        int64_t mb = 0, fb = 0;
+        forward_geometry(p, L, &mb, &fb);
+        k_resid_final<<<1, kBlock, 0, s>>>(p->resid_part, mb + fb, resid_out);
+        return dev_check("residual kernel");
+    }
+    return HNV_OK;
+}
+
+static hnv_status run_project(hnv_plan *p, int level, const void *zc, void *zf, hipStream_t s)
+{
+    LevelPlan &L = p->lv[level];
+    const int64_t threads = L.rows * (p->d / 8);
+    if (threads == 0)
+        return HNV_OK;
+    if (p->dtype == HNV_F32)
+        k_project<float><<<grid1d(threads, kBlock), kBlock, 0, s>>>(static_cast<const float *>(zc),
+                                                                    static_cast<float *>(zf), L.rowmap, L.rows, p->d);
+    else
+        k_project<bf16_t><<<grid1d(threads, kBlock), kBlock, 0, s>>>(static_cast<const bf16_t *>(zc),
+                                                                     static_cast<bf16_t *>(zf), L.rowmap, L.rows,
+                                                                     p->d);
+    return dev_check("projection kernel");
+}
+
+static size_t elem_bytes(const hnv_plan *p) { return p->dtype == HNV_BF16 ? 2 : 4; }
+
+static hnv_status check_level(const hnv_plan *p, int level)
+{
+    if (!p)
+        return fail(HNV_EINVAL, "plan is NULL");
+    if (level < 0 || level >= p->n_levels)
+        return fail(HNV_EINVAL, "level " + std::to_string(level) + " out of range");
+    return HNV_OK;
+}
+
+static bool aligned16(const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; }
+
+}  // namespace hnv
+
+using namespace hnv;
+
+// ---------------------------------------------------------------------------
+// C ABI (device calls)
+// ---------------------------------------------------------------------------
+
+extern "C" hnv_status hnv_set_edge_weights(hnv_plan *plan, int level, const float *w_dev, void *stream)
+{
+    clear_error();
+    hnv_status st = check_level(plan, level);
+    if (st != HNV_OK)
+        return st;
+    if (!w_dev && plan->lv[level].n_edges > 0)
+        return fail(HNV_EINVAL, "w_dev is NULL");
+    LevelPlan &L = plan->lv[level];
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (L.n_edges > 0) {
+        hipError_t e = hipMemcpyAsync(L.w, w_dev, L.n_edges * sizeof(float), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess)
+            return fail(HNV_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+    }
+    L.unit_w = false;
+    return dev_recompute_reciprocals(plan, level, stream);
+}
+
+extern "C" hnv_status hnv_set_edge_logweights(hnv_plan *plan, int level, const float *theta_dev, float *w_out_dev,
+                                              void *stream)
+{
+    clear_error();
+    hnv_status st = check_level(plan, level);
+    if (st != HNV_OK)
+        return st;
+    LevelPlan &L = plan->lv[level];
+    if (!theta_dev && L.n_edges > 0)
+        return fail(HNV_EINVAL, "theta_dev is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (L.n_edges > 0)
+        k_exp<<<grid1d(L.n_edges, kBlock), kBlock, 0, s>>>(theta_dev, L.w, w_out_dev, L.n_edges);
+    if ((st = dev_check("exp kernel")) != HNV_OK)
+        return st;
+    L.unit_w = false;
+    return dev_recompute_reciprocals(plan, level, stream);
+}
+
+extern "C" hnv_status hnv_logweight_grad(hnv_plan *plan, int level, const float *dw, float *dtheta, void *stream)
+{
+    clear_error();
+    hnv_status st = check_level(plan, level);
+    if (st != HNV_OK)
+        return st;
+    LevelPlan &L = plan->lv[level];
+    if ((!dw || !dtheta) && L.n_edges > 0)
+        return fail(HNV_EINVAL, "dw / dtheta is NULL");
+    if (L.n_edges > 0)
+        k_mul<<<grid1d(L.n_edges, kBlock), kBlock, 0, reinterpret_cast<hipStream_t>(stream)>>>(L.w, dw, dtheta,
+                                                                                               L.n_edges);
+    return dev_check("log-weight gradient kernel");
+}
+
+extern "C" hnv_status hnv_sweep(hnv_plan *plan, int level, const void *z_in, void *z_out, float omega,
+                                int from_coarse, double *resid_dev, void *stream)
+{
+    clear_error();
+    hnv_status st = check_level(plan, level);
+    if (st != HNV_OK)
+        return st;
+    if (!z_in || !z_out || z_in == z_out)
+        return fail(HNV_EINVAL, "z_in / z_out NULL or aliased");
+    if (!aligned16(z_in) || !aligned16(z_out))
+        return fail(HNV_EINVAL, "z_in / z_out must be 16-byte aligned");
+    if (!(omega >= 0.0f && omega <= 1.0f))
+        return fail(HNV_EINVAL, "omega must be in [0, 1]");
+    if (from_coarse && !plan->lv[level].has_coarse)
+        return fail(HNV_EINVAL, "from_coarse at the coarsest level");
+    return run_sweep(plan, level, z_in, z_out, omega, from_coarse != 0, resid_dev,
+                     reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" hnv_status hnv_project(hnv_plan *plan, int level, const void *z_coarse, void *z_fine, void *stream)
+{
+    clear_error();
+    hnv_status st = check_level(plan, level);
+    if (st != HNV_OK)
+        return st;
+    if (!plan->lv[level].has_coarse)
+        return fail(HNV_EINVAL, "no coarser level to project from");
+    if (!z_coarse || !z_fine || !aligned16(z_coarse) || !aligned16(z_fine))
+        return fail(HNV_EINVAL, "z_coarse / z_fine NULL or not 16-byte aligned");
+    return run_project(plan, level, z_coarse, z_fine, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" hnv_status hnv_refine(hnv_plan *plan, const void *z_coarsest, void *z_finest,
+                                 const int32_t *sweeps_per_level, float omega, double tol, double *residuals_dev,
+                                 int32_t *sweeps_done, void *stream)
+{
+    clear_error();
+    if (!plan)
+        return fail(HNV_EINVAL, "plan is NULL");
+    if (!z_coarsest || !z_finest || z_coarsest == z_finest || !sweeps_per_level)
+        return fail(HNV_EINVAL, "z_coarsest / z_finest / sweeps_per_level NULL or aliased");
+    if (!aligned16(z_coarsest) || !aligned16(z_finest))
+        return fail(HNV_EINVAL, "embeddings must be 16-byte aligned");
+    if (!(omega >= 0.0f && omega <= 1.0f))
+        return fail(HNV_EINVAL, "omega must be in [0, 1]");
+    const int Lc = plan->n_levels - 1;
+    for (int l = 0; l <= Lc; ++l)
+        if (sweeps_per_level[l] < 0)
+            return fail(HNV_EINVAL, "negative sweep count");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const size_t eb = elem_bytes(plan);
+
+    // Operations in order: per level (coarsest first) the sweeps, or a bare
+    // projection when a finer level has no sweeps.  Writes alternate between
+    // z_finest and the scratch buffer.  With fixed counts the alternation is
+    // counted back from the last operation so that it writes z_finest; with
+    // tol the count is not known ahead and a final copy may be needed.
+    int64_t n_ops = 0;
+    for (int l = Lc; l >= 0; --l)
+        n_ops += (sweeps_per_level[l] > 0) ? sweeps_per_level[l] : (l < Lc ? 1 : 0);
+    if (n_ops == 0) {
+        hipError_t e = hipMemcpyAsync(z_finest, z_coarsest, plan->lv[0].rows * plan->d * eb,
+                                      hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess)
+            return fail(HNV_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+        if (sweeps_done)
+            for (int l = 0; l <= Lc; ++l)
+                sweeps_done[l] = 0;
+        return HNV_OK;
+    }
+    void *bufs[2] = {z_finest, plan->zbuf};
+    int64_t op = 0;
+    const void *cur = z_coarsest;
+    auto target = [&](int64_t k) { return tol > 0 ? bufs[k % 2] : bufs[(n_ops - 1 - k) % 2]; };
+    int64_t resid_k = 0;
+    hnv_status st = HNV_OK;
+    for (int l = Lc; l >= 0; --l) {
+        const int K = sweeps_per_level[l];
+        int done = 0;
+        if (K == 0 && l < Lc) {
+            void *out = target(op++);
+            if ((st = run_project(plan, l, cur, out, s)) != HNV_OK)
+                return st;
+            cur = out;
+        }
+        for (int k = 0; k < K; ++k) {
+            void *out = target(op++);
+            const bool fused = (k == 0 && l < Lc);
+            double *rd = residuals_dev ? residuals_dev + resid_k : (tol > 0 ? plan->resid_tmp : nullptr);
+            if ((st = run_sweep(plan, l, cur, out, omega, fused, rd, s)) != HNV_OK)
+                return st;
+            ++resid_k;
+            cur = out;
+            ++done;
+            if (tol > 0) {
+                double host_r = 0.0;
+                hipError_t e = hipMemcpyAsync(&host_r, rd, sizeof(double), hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess)
+                    e = hipStreamSynchronize(s);
+                if (e != hipSuccess)
+                    return fail(HNV_EDEVICE, std::string("residual read-back: ") + hipGetErrorString(e));
+                if (host_r <= tol)
+                    break;
+            }
+        }
+        if (sweeps_done)
+            sweeps_done[l] = done;
+    }
+    if (cur != z_finest) {
+        hipError_t e = hipMemcpyAsync(z_finest, cur, plan->lv[0].rows * plan->d * eb, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess)
+            return fail(HNV_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+    }
+    return HNV_OK;
+}
+
+extern "C" hnv_status hnv_sweep_adjoint(hnv_plan *plan, int level, const void *g_in, void *g_out,
+                                        const void *z_prev, const void *z_cur, float *dw_accum, float omega,
+                                        void *stream)
+{
+    clear_error();
+    hnv_status st = check_level(plan, level);
+    if (st != HNV_OK)
+        return st;
+    if (!g_in || !g_out || !z_prev || !z_cur || g_in == g_out)
+        return fail(HNV_EINVAL, "NULL or aliased matrices");
+    if (!aligned16(g_in) || !aligned16(g_out) || !aligned16(z_prev) || !aligned16(z_cur))
+        return fail(HNV_EINVAL, "matrices must be 16-byte aligned");
+    if (!(omega > 0.0f && omega <= 1.0f))
+        return fail(HNV_EINVAL, "omega must be in (0, 1] for the reverse sweep");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    LevelPlan &L = plan->lv[level];
+    const int G = plan->g_full;
+    GatherArgs a = base_args(plan, L, G, plan->d, 1);
+    a.omega = omega;
+    a.src = g_in;
+    a.dst = g_out;
+    a.yprev = z_prev;
+    a.zcur = z_cur;
+    a.cvec = plan->cscratch;
+    a.dw = dw_accum;
+    a.resid = nullptr;
+    // node rows first (they produce the per-node scalars), then hyperedge rows
+    const GatherArgs an = only_side(a, 1), ae = only_side(a, 0);
+    if (plan->dtype == HNV_F32) {
+        if ((st = dispatch_g<float, kAdjNode, false>(G, an, 1, s)) != HNV_OK)
+            return st;
+        st = dispatch_g<float, kAdjEdge, false>(G, ae, 1, s);
+    } else {
+        if ((st = dispatch_g<bf16_t, kAdjNode, false>(G, an, 1, s)) != HNV_OK)
+            return st;
+        st = dispatch_g<bf16_t, kAdjEdge, false>(G, ae, 1, s);
+    }
+    return st;
+}
+
+extern "C" hnv_status hnv_project_adjoint(hnv_plan *plan, int level, const void *g_fine, void *g_coarse,
+                                          void *stream)
+{
+    clear_error();
+    hnv_status st = check_level(plan, level);
+    if (st != HNV_OK)
+        return st;
+    LevelPlan &L = plan->lv[level];
+    if (!L.has_coarse)
+        return fail(HNV_EINVAL, "no coarser level");
+    if (!g_fine || !g_coarse || !aligned16(g_fine) || !aligned16(g_coarse))
+        return fail(HNV_EINVAL, "g_fine / g_coarse NULL or not 16-byte aligned");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int G = plan->g_full;
+    const unsigned blocks = grid1d(L.rows_coarse, kWavesPerBlock);
+    if (blocks == 0)
+        return HNV_OK;
+#define HNV_PADJ(TT, GG)                                                                                         \
+    k_project_adj<TT, GG><<<blocks, kBlock, 0, s>>>(static_cast<const TT *>(g_fine), static_cast<TT *>(g_coarse), \
+                                                    L.inv_ptr, L.inv_idx, L.rows_coarse, plan->d)
+#define HNV_PADJ_G(TT)                                                                                           \
+    switch (G) {                                                                                                 \
+    case 1: HNV_PADJ(TT, 1); break;                                                                              \
+    case 2: HNV_PADJ(TT, 2); break;                                                                              \
+    case 4: HNV_PADJ(TT, 4); break;                                                                              \
+    case 8: HNV_PADJ(TT, 8); break;                                                                              \
+    case 16: HNV_PADJ(TT, 16); break;                                                                            \
+    case 32: HNV_PADJ(TT, 32); break;                                                                            \
+    default: HNV_PADJ(TT, 64); break;                                                                            \
+    }
+    if (plan->dtype == HNV_F32) {
+        HNV_PADJ_G(float)
+    } else {
+        HNV_PADJ_G(bf16_t)
+    }
+#undef HNV_PADJ_G
+#undef HNV_PADJ
+    return dev_check("projection reverse kernel");
+}
+
+extern "C" hnv_status hnv_cast(const void *src, hnv_dtype src_dtype, void *dst, hnv_dtype dst_dtype, int64_t n,
+                               void *stream)
+{
+    clear_error();
+    if (n < 0 || (n > 0 && (!src || !dst)))
+        return fail(HNV_EINVAL, "bad cast arguments");
+    if (n == 0)
+        return HNV_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (src_dtype == HNV_F32 && dst_dtype == HNV_BF16)
+        k_cast_f32_bf16<<<grid1d(n, kBlock), kBlock, 0, s>>>(static_cast<const float *>(src),
+                                                             static_cast<bf16_t *>(dst), n);
+    else if (src_dtype == HNV_BF16 && dst_dtype == HNV_F32)
+        k_cast_bf16_f32<<<grid1d(n, kBlock), kBlock, 0, s>>>(static_cast<const bf16_t *>(src),
+                                                             static_cast<float *>(dst), n);
+    else if (src_dtype == dst_dtype) {
+        hipError_t e = hipMemcpyAsync(dst, src, n * (src_dtype == HNV_BF16 ? 2 : 4), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess)
+            return fail(HNV_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+        return HNV_OK;
+    } else
+        return fail(HNV_EINVAL, "unknown dtype");
+    return dev_check("cast kernel");
+}

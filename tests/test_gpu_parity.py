@@ -1,0 +1,265 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Tolerances: FP32 storage <= 1e-5 relative (Frobenius,
+over the compared rows and columns, and max-abs relative to the largest
+reference entry); BF16 storage <= 1e-2 relative against the oracle run on the
+BF16-rounded input; reverse mode <= 1e-4 relative."""
+import numpy as np
+import pytest
+
+from tests.cases import (CONFIGS, both_hierarchies, coarsest_embedding, make_hypergraph, max_abs_rel,
+                         random_hypergraph, rel_fro, tier_hypergraph)
+
+pytestmark = pytest.mark.gpu
+
+F32_TOL = 1e-5
+BF16_TOL = 1e-2
+GRAD_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2103_09660_amd as H
+    return H
+
+
+def _dev(x, dtype="f32"):
+    import torch
+    t = torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    return t if dtype == "f32" else t.to(torch.bfloat16)
+
+
+def _host(t):
+    import torch
+    return t.float().cpu().numpy().astype(np.float64) if t.dtype != torch.float64 else t.cpu().numpy()
+
+
+def _bf16_round(x):
+    import torch
+    return torch.as_tensor(np.asarray(x, dtype=np.float32)).to(torch.bfloat16).float().numpy().astype(np.float64)
+
+
+def _assert_close(got, ref, tol, what):
+    r, m = rel_fro(got, ref), max_abs_rel(got, ref)
+    assert r <= tol and m <= 10 * tol, f"{what}: rel_fro={r:.3e} max_abs_rel={m:.3e} tol={tol}"
+
+
+# ---------------------------------------------------------------------------
+# single sweeps over random hypergraphs and every tier
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed,n_nodes,n_edges,d,weighted", [
+    (0, 50, 30, 8, True), (1, 300, 200, 32, False), (2, 1000, 700, 40, True),
+    (3, 2000, 900, 64, True), (4, 513, 129, 128, False), (5, 64, 300, 16, True),
+    (6, 900, 600, 256, True), (7, 100, 80, 512, False)])
+def test_sweep_and_fused_projection(oracle_mod, H, seed, n_nodes, n_edges, d, weighted):
+    import torch
+    O = oracle_mod
+    hg = random_hypergraph(seed, n_nodes, n_edges, 1, 12, weighted=weighted)
+    levels, maps, hier = both_hierarchies(O, H, hg, 1)
+    plan = H.Plan(hier, d, "f32")
+    rng = np.random.default_rng(seed)
+    z0 = rng.standard_normal((levels[0].rows, d)).astype(np.float32)
+    zc = rng.standard_normal((levels[1].rows, d)).astype(np.float32)
+    resid = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for omega in (0.5, 0.3, 1.0):
+        out = _host(plan.sweep(0, _dev(z0), omega, resid=resid))
+        ref = O.sweep(levels[0], z0, omega)
+        _assert_close(out, ref, F32_TOL, f"sweep omega={omega}")
+        assert abs(float(resid.item()) - O.residual(ref, z0)) <= 1e-5 * max(1.0, O.residual(ref, z0))
+        fused = _host(plan.sweep(0, _dev(zc), omega, from_coarse=True))
+        ref_f = O.sweep(levels[0], O.project(O.rowmap(levels[0], maps[0]), zc), omega)
+        _assert_close(fused, ref_f, F32_TOL, f"fused omega={omega}")
+    proj = _host(plan.project(0, _dev(zc)))
+    np.testing.assert_array_equal(proj, O.project(O.rowmap(levels[0], maps[0]), zc))
+
+
+@pytest.mark.parametrize("small_max,chunk", [(4, 64), (8, 64), (32, 128), (1, 64)])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_every_tier(oracle_mod, H, small_max, chunk, dtype):
+    O = oracle_mod
+    hg = tier_hypergraph(11, small_max, chunk)
+    levels, maps, hier = both_hierarchies(O, H, hg, 1)
+    d = 64
+    opts = {"small_max": small_max, "chunk": chunk}
+    plan = H.Plan(hier, d, dtype, options=opts)
+    rng = np.random.default_rng(3)
+    z0 = rng.standard_normal((levels[0].rows, d)).astype(np.float32)
+    zin = z0 if dtype == "f32" else _bf16_round(z0)
+    out = _host(plan.sweep(0, _dev(z0, dtype), 0.5))
+    ref = O.sweep(levels[0], zin, 0.5)
+    _assert_close(out, ref, F32_TOL if dtype == "f32" else BF16_TOL, f"tiers {opts} {dtype}")
+    # columns in two passes: a narrower lane group, so a different (fixed)
+    # summation order; same tolerance, and repeatable bit for bit
+    plan2 = H.Plan(hier, d, dtype, options=dict(opts, panel_cols=32))
+    out2 = _host(plan2.sweep(0, _dev(z0, dtype), 0.5))
+    _assert_close(out2, ref, F32_TOL if dtype == "f32" else BF16_TOL, f"tiers {opts} {dtype} two panels")
+    np.testing.assert_array_equal(_host(plan2.sweep(0, _dev(z0, dtype), 0.5)), out2)
+
+
+# ---------------------------------------------------------------------------
+# multi-level refinement
+# ---------------------------------------------------------------------------
+
+def _refine_case(O, H, cfg_name, dtype, cols=None, n_levels=None, sweeps=None):
+    cfg = CONFIGS[cfg_name]
+    hg = make_hypergraph(cfg)
+    L = cfg.levels if n_levels is None else n_levels
+    levels, maps, hier = both_hierarchies(O, H, hg, L)
+    K = list(cfg.sweeps[: L + 1]) if sweeps is None else sweeps
+    zc = coarsest_embedding(cfg, levels[-1].rows, cfg.d)
+    plan = H.Plan(hier, cfg.d, dtype)
+    zdev = _dev(zc, dtype)
+    out, res, done = plan.refine(zdev, K, 0.5, residuals=True)
+    got = _host(out)
+    zin = zc if dtype == "f32" else _bf16_round(zc)
+    c = slice(None) if cols is None else cols
+    ref, ref_res = O.refine(levels, maps, np.ascontiguousarray(zin[:, c]), K, 0.5, return_residuals=True)
+    return got[:, c], ref, _host(res), np.array(ref_res), done, K
+
+
+def test_refine_c1_f32(oracle_mod, H):
+    got, ref, res, ref_res, done, K = _refine_case(oracle_mod, H, "c1", "f32")
+    _assert_close(got, ref, F32_TOL, "c1 refine f32")
+    assert list(done) == list(K)
+    np.testing.assert_allclose(res[: len(ref_res)], ref_res, rtol=1e-5)
+
+
+def test_refine_c1_bf16(oracle_mod, H):
+    got, ref, _, _, _, _ = _refine_case(oracle_mod, H, "c1", "bf16")
+    _assert_close(got, ref, BF16_TOL, "c1 refine bf16")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_refine_c2(oracle_mod, H, dtype):
+    """Medium hub-heavy config, all columns."""
+    got, ref, res, ref_res, _, _ = _refine_case(oracle_mod, H, "c2", dtype)
+    _assert_close(got, ref, F32_TOL if dtype == "f32" else BF16_TOL, f"c2 refine {dtype}")
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f32"])
+def test_refine_c3_full_size_column_sample(oracle_mod, H, dtype):
+    """The benchmark workload (2M nodes, 1.5M hyperedges, 8 coarsening
+    steps, 20 sweeps per level, d = 128, default launch options) on the GPU;
+    the oracle computes two of the 128 columns over every row (columns are
+    independent under the sweep and the projection)."""
+    cols = [0, 77]
+    got, ref, res, ref_res, done, K = _refine_case(oracle_mod, H, "c3", dtype, cols=cols)
+    _assert_close(got, ref, F32_TOL if dtype == "f32" else BF16_TOL, f"c3 refine {dtype} cols {cols}")
+
+
+def test_refine_zero_and_tol(oracle_mod, H):
+    """K = 0 levels (bare projections), omega = 0 (identity), early stop."""
+    import torch
+    O = oracle_mod
+    hg = random_hypergraph(9, 400, 300, 2, 6, weighted=True)
+    levels, maps, hier = both_hierarchies(O, H, hg, 3)
+    d = 16
+    plan = H.Plan(hier, d, "f32")
+    zc = np.random.default_rng(0).standard_normal((levels[-1].rows, d)).astype(np.float32)
+    for K in ([0, 0, 0, 0], [0, 3, 0, 2], [4, 0, 0, 0], [1, 1, 1, 1]):
+        out, _, _ = plan.refine(_dev(zc), K, 0.5)
+        _assert_close(_host(out), O.refine(levels, maps, zc, K, 0.5), F32_TOL, f"K={K}")
+    out, _, _ = plan.refine(_dev(zc), [2, 2, 2, 2], 0.0)
+    np.testing.assert_array_equal(_host(out), O.refine(levels, maps, zc, [0, 0, 0, 0], 0.5))
+    tol = 0.5
+    out, res, done = plan.refine(_dev(zc), [50, 50, 50, 50], 0.5, tol=tol, residuals=True)
+    ref, ref_res = O.refine(levels, maps, zc, [50, 50, 50, 50], 0.5, tol=tol, return_residuals=True)
+    _assert_close(_host(out), ref, F32_TOL, "tol")
+    assert int(done.sum()) == len(ref_res)
+    torch.cuda.synchronize()
+
+
+def test_determinism_bitwise(oracle_mod, H):
+    O = oracle_mod
+    hg = tier_hypergraph(5, 8, 64)
+    levels, maps, hier = both_hierarchies(O, H, hg, 2)
+    plan = H.Plan(hier, 32, "bf16", options={"small_max": 8, "chunk": 64})
+    zc = _dev(np.random.default_rng(1).standard_normal((levels[-1].rows, 32)), "bf16")
+    a, ra, _ = plan.refine(zc, [3, 3, 3], 0.5, residuals=True)
+    b, rb, _ = plan.refine(zc, [3, 3, 3], 0.5, residuals=True)
+    import torch
+    assert torch.equal(a.view(torch.int16), b.view(torch.int16))
+    assert torch.equal(ra, rb)
+
+
+def test_cast_round_to_nearest_even(H):
+    import torch
+    x = np.random.default_rng(0).standard_normal(10_000).astype(np.float32) * 100
+    x[:4] = [1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -0.0, 3.0e38]   # exact ties and extremes
+    t = H.cast(_dev(x), "bf16")
+    ref = torch.as_tensor(x).to(torch.bfloat16)
+    assert bool((t.cpu().view(torch.int16) == ref.view(torch.int16)).all())
+    back = H.cast(t, "f32")
+    assert bool((back.cpu() == ref.float()).all())
+
+
+# ---------------------------------------------------------------------------
+# reverse mode
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed,small_max,chunk,d", [(0, 32, 512, 32), (1, 4, 64, 64), (2, 1, 64, 16),
+                                                     (3, 8, 128, 128)])
+def test_sweep_adjoint(oracle_mod, H, seed, small_max, chunk, d):
+    import torch
+    O = oracle_mod
+    hg = tier_hypergraph(seed, max(small_max, 2), chunk) if seed % 2 else \
+        random_hypergraph(seed, 800, 500, 1, 10, weighted=True)
+    levels, maps, hier = both_hierarchies(O, H, hg, 1)
+    plan = H.Plan(hier, d, "f32", options={"small_max": small_max, "chunk": chunk})
+    rng = np.random.default_rng(seed)
+    theta = rng.uniform(-0.5, 0.5, size=levels[0].n_edges).astype(np.float32)
+    wt = torch.empty(levels[0].n_edges, dtype=torch.float32, device="cuda")
+    plan.set_edge_logweights(0, _dev(theta), w_out=wt)
+    w_host = wt.cpu().numpy()
+    y = rng.standard_normal((levels[0].rows, d)).astype(np.float32)
+    g = rng.standard_normal((levels[0].rows, d)).astype(np.float32)
+    omega = 0.5
+    z = plan.sweep(0, _dev(y), omega)
+    _assert_close(_host(z), O.sweep(levels[0], y, omega, 0, w_host), F32_TOL, "weighted forward")
+    dw = torch.zeros(levels[0].n_edges, dtype=torch.float32, device="cuda")
+    gy = plan.sweep_adjoint(0, _dev(g), _dev(y), z, omega, dw=dw)
+    ref_gy, ref_dw = O.sweep_vjp(levels[0], y, g, omega, w_host)
+    _assert_close(_host(gy), ref_gy, F32_TOL, "adjoint gy")
+    _assert_close(dw.cpu().numpy(), ref_dw, GRAD_TOL, "adjoint dw")
+    # project adjoint
+    gc = plan.project_adjoint(0, _dev(g))
+    _assert_close(_host(gc), O.project_vjp(O.rowmap(levels[0], maps[0]), levels[1].rows, g), F32_TOL,
+                  "project adjoint")
+    dth = plan.logweight_grad(0, dw.clone())
+    _assert_close(dth.cpu().numpy(), ref_dw * w_host, GRAD_TOL, "dtheta")
+
+
+def test_refine_function_c4_shape_small(oracle_mod, H):
+    """Differentiable refinement (projection + 10 sweeps with learnable
+    log-weights, checkpoint every 5) on a reduced instance of the
+    differentiable-refinement workload; loss = CE of a linear head."""
+    import torch
+    O = oracle_mod
+    hg = random_hypergraph(4, 5000, 3000, 2, 20, weighted=False)
+    levels, maps, hier = both_hierarchies(O, H, hg, 1)
+    d, K = 32, 10
+    plan = H.Plan(hier, d, "f32")
+    rng = np.random.default_rng(4)
+    zc = rng.standard_normal((levels[1].rows, d)).astype(np.float32)
+    theta = rng.uniform(-0.3, 0.3, size=levels[0].n_edges).astype(np.float32)
+    lab_nodes = np.sort(rng.choice(levels[0].n_nodes, size=500, replace=False))
+    labels = rng.integers(0, 16, size=500)
+    W = (rng.standard_normal((16, d)) / np.sqrt(d)).astype(np.float32)
+    zc_t = _dev(zc).requires_grad_(True)
+    th_t = _dev(theta).requires_grad_(True)
+    out = H.refine_level(zc_t, th_t, plan, 0, K, 0.5, from_coarse=True, ckpt_every=5)
+    logits = out[torch.as_tensor(lab_nodes).cuda()] @ _dev(W).t()
+    loss = torch.nn.functional.cross_entropy(logits, torch.as_tensor(labels).cuda())
+    loss.backward()
+    w_dev = torch.as_tensor(theta).cuda().exp().cpu().numpy()
+    zK, _, _ = O.finest_refine_vjp(levels[0], maps[0], zc, w_dev, K, 0.5, np.zeros((levels[0].rows, d)))
+    ref_loss, dz_nodes = O.ce_head(zK[lab_nodes], labels, W, np.zeros(16))
+    gK = np.zeros((levels[0].rows, d))
+    gK[lab_nodes] = dz_nodes
+    _, ref_gc, ref_dw = O.finest_refine_vjp(levels[0], maps[0], zc, w_dev, K, 0.5, gK)
+    assert abs(loss.item() - ref_loss) <= 1e-5 * abs(ref_loss)
+    _assert_close(_host(zc_t.grad), ref_gc, GRAD_TOL, "dL/dZc")
+    _assert_close(th_t.grad.cpu().numpy(), ref_dw * w_dev, GRAD_TOL, "dL/dtheta")
