@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""Benchmark of the HyperNetVec refinement hot path on one MI355X.
+
+One step = one multi-level refinement of the benchmark hypergraph (2,000,000
+nodes, 1,500,000 hyperedges with truncated Zipf(2.1) sizes on [2, 2000],
+d = 128, 8 coarsening steps, 20 sweeps per level, omega = 0.5): sweeps at the
+coarsest level, then per finer level the projection fused into the first
+sweep and the remaining sweeps, with the FP64 per-sweep residual, in BF16
+storage with FP32 accumulation.  The same refinement in FP32 storage is timed
+in the same run for the BF16-vs-FP32 comparison.
+
+Prints one JSON line (rank 0) with the throughput in star-edge x dimension
+updates per second (2 * nnz * d per sweep, summed over levels), the roofline
+of the dominant kernel (the forward sweep kernel, timed live with HIP events
+on its launch stream), and the FP64 CPU oracle timed on a bounded sample.
+Inputs are synthetic and seeded.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "refinement nnz·d updates/s and % HBM roofline, BF16 vs FP32 sweep, 1 MI355X"
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_sweep_c3_bf16.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2103_09660_amd", "csrc", "hnv_kernels.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def sweep_alg_bytes(n_nodes, n_edges, nnz, d, s):
+    """Compulsory HBM bytes of one forward sweep at one level: every row read
+    and written once (2*d*s), its offset (8) and reciprocal (4), both
+    directions of the incidence (2 * 4 B per star edge) and one weight per
+    hyperedge (4)."""
+    rows = n_nodes + n_edges
+    return rows * (2 * d * s + 12) + 8 * nnz + 4 * n_edges
+
+
+def kernel_source_digest():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def read_counters():
+    """HBM traffic per launch of the forward sweep kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    kv = {}
+    for line in open(COUNTERS_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_gpu(H, torch, hier, cfg, dtype, zc_f32, steps, warmup):
+    import numpy as np
+    plan = H.Plan(hier, cfg.d, dtype)
+    z0 = zc_f32 if dtype == "f32" else H.cast(zc_f32, "bf16")
+    sweeps = list(cfg.sweeps)
+    for _ in range(warmup):
+        plan.refine(z0, sweeps, 0.5, residuals=True)
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out, res, _ = plan.refine(z0, sweeps, 0.5, residuals=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / steps
+    s = 2 if dtype == "bf16" else 4
+    launches, alg_bytes, kernel_ms = 0, 0.0, 0.0
+    for lvl in range(plan.n_levels):
+        n, ms = plan.profile_read(0, lvl)        # HNV_PROF_SWEEP
+        nv, ne, nz = plan.level_info(lvl)
+        launches += n
+        kernel_ms += ms
+        alg_bytes += n * sweep_alg_bytes(nv, ne, nz, cfg.d, s)
+    nf, msf = plan.profile_read(1, -1)           # HNV_PROF_FUSED
+    plan.set_profiling(False)
+    updates = sum(sweeps[l] * 2 * hier.levels[l].nnz * cfg.d for l in range(hier.n_levels))
+    result = {
+        "ms_per_step": ms_per_step,
+        "updates_per_step": updates,
+        "value": updates / (ms_per_step / 1000.0),
+        "sweep_kernel_launches": launches,
+        "sweep_kernel_avg_ms": kernel_ms / max(launches, 1),
+        "sweep_alg_bytes_per_launch": alg_bytes / max(launches, 1),
+        "fused_kernel_avg_ms": msf / max(nf, 1),
+        "kernel_ms_per_step": (kernel_ms + msf) / steps,
+        "final_residual": float(res[sum(sweeps) - 1].item()),
+    }
+    return result, out.float(), plan
+
+
+def cpu_baseline(O, hg, cfg, budget_s=12.0, max_sweeps=20):
+    """The oracle as it stands, on a bounded sample of the same workload:
+    Jacobi sweeps of the finest level at full width d (FP64), repeated until
+    about budget_s seconds of work.  The oracle's time does not depend on the
+    values, so the start embedding is a tiled seeded block."""
+    import numpy as np
+    from synth import coarsest_embedding
+    lv = O.Level(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w)
+    z = np.resize(coarsest_embedding(cfg, 4096, cfg.d).astype(np.float64), (lv.rows, cfg.d))
+    n, t = 0, 0.0
+    while n < max_sweeps and t < budget_s:
+        t0 = time.perf_counter()
+        z = O.sweep(lv, z, 0.5)
+        t += time.perf_counter() - t0
+        n += 1
+    upd = n * 2 * lv.nnz * cfg.d
+    return {"value": upd / t, "unit": "updates/s", "cores": O.threads(), "kind": "oracle",
+            "sample": f"{n} Jacobi sweeps of the finest level ({lv.n_nodes} nodes, {lv.n_edges} hyperedges, "
+                      f"{lv.nnz} incidences) at d={cfg.d}, FP64, {t:.1f} s"}
+
+
+def oracle_errors(O, hg, cfg, zc, outs, cols=(0, 77)):
+    """Errors of the GPU results against the FP64 oracle on a column sample
+    (columns are independent under projection and sweeps)."""
+    import numpy as np
+    levels, maps = O.build_hierarchy(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, cfg.levels)
+    ref = O.refine(levels, maps, np.ascontiguousarray(zc[:, list(cols)], dtype=np.float64), list(cfg.sweeps), 0.5)
+    errs = {}
+    for name, out in outs.items():
+        got = out[:, list(cols)].cpu().numpy().astype(np.float64)
+        errs[name] = {"rel_fro": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                      "max_abs": float(np.max(np.abs(got - ref))),
+                      "max_abs_rel": float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))),
+                      "columns": list(cols)}
+    return errs
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--dtypes", default="bf16,f32", help="storage types to time; the first is the headline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the refinement is measured on one MI355X "
+              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2103_09660_amd as H
+    from synth import CONFIGS, coarsest_embedding, make_hypergraph
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    cfg = CONFIGS[args.config]
+    t = time.perf_counter()
+    hg = make_hypergraph(cfg)
+    log(f"generated {cfg.name}: {hg.n_nodes} nodes, {hg.n_edges} hyperedges, {hg.nnz} incidences "
+        f"({time.perf_counter() - t:.1f} s)")
+    t = time.perf_counter()
+    hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, cfg.levels)
+    log(f"coarsened to {hier.n_levels} levels ({time.perf_counter() - t:.1f} s): "
+        + ", ".join(f"({l.n_nodes},{l.n_edges},{l.nnz})" for l in hier.levels))
+    zc = coarsest_embedding(cfg, hier.levels[-1].rows, cfg.d)
+    zc_dev = torch.as_tensor(zc).cuda()
+
+    dtypes = [d for d in args.dtypes.split(",") if d]
+    results, outs = {}, {}
+    for dt in dtypes:
+        r, out, plan = run_gpu(H, torch, hier, cfg, dt, zc_dev, args.steps, args.warmup)
+        results[dt], outs[dt] = r, out
+        log(f"{dt}: {r['ms_per_step']:.2f} ms/step, {r['value'] / 1e12:.3f} T updates/s, sweep kernel "
+            f"{r['sweep_kernel_avg_ms'] * 1e3:.1f} us avg over {r['sweep_kernel_launches']} launches")
+        del plan
+        torch.cuda.empty_cache()
+
+    head = results[dtypes[0]]
+    s = 2 if dtypes[0] == "bf16" else 4
+    achieved = head["sweep_alg_bytes_per_launch"] / (head["sweep_kernel_avg_ms"] / 1000.0) / 1e9
+    traffic = read_counters() if dtypes[0] == "bf16" and args.config == "c3" else None
+    line = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtypes[0],
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: multi-level refinement, {cfg.n_nodes} nodes, {cfg.n_edges} "
+                               f"hyperedges, sizes {cfg.sizes}, members {cfg.members[0]}, d={cfg.d}, "
+                               f"{cfg.levels} coarsening steps, {cfg.sweeps[0]} sweeps per level, omega=0.5, "
+                               f"FP32 accumulation",
+                   "n_nodes": hg.n_nodes, "n_edges": hg.n_edges, "nnz": hg.nnz, "d": cfg.d,
+                   "levels": hier.n_levels, "sweeps_per_level": list(cfg.sweeps),
+                   "level_sizes": [[l.n_nodes, l.n_edges, l.nnz] for l in hier.levels]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": f"forward sweep (k_gather, {dtypes[0]}, non-fused), "
+                               f"{head['sweep_kernel_launches']} launches",
+                     "alg_bytes_per_launch": head["sweep_alg_bytes_per_launch"],
+                     "avg_launch_ms": head["sweep_kernel_avg_ms"]},
+    }
+    for dt in dtypes[1:]:
+        r = results[dt]
+        line[dt] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                    "sweep_kernel_avg_ms": r["sweep_kernel_avg_ms"],
+                    "achieved_GBps": r["sweep_alg_bytes_per_launch"] / (r["sweep_kernel_avg_ms"] / 1000.0) / 1e9}
+        line[f"{dtypes[0]}_over_{dt}"] = head["value"] / r["value"]
+    line["fused_projection_sweep_avg_ms"] = head["fused_kernel_avg_ms"]
+
+    need_oracle = not (args.no_cpu_baseline and args.no_oracle_check)
+    if need_oracle:
+        from oracle import oracle as O
+        if not args.no_oracle_check:
+            t = time.perf_counter()
+            line["error_vs_fp64_oracle"] = oracle_errors(O, hg, cfg, zc, outs)
+            log(f"oracle check ({time.perf_counter() - t:.1f} s): {line['error_vs_fp64_oracle']}")
+        if not args.no_cpu_baseline:
+            line["cpu_baseline"] = cpu_baseline(O, hg, cfg)
+            log(f"cpu baseline: {line['cpu_baseline']}")
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

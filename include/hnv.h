@@ -214,6 +214,26 @@ hnv_status hnv_project_adjoint(hnv_plan *plan, int level, const void *g_fine, vo
  * current weights (DEVICE float [n_edges] each; dtheta may alias dw). */
 hnv_status hnv_logweight_grad(hnv_plan *plan, int level, const float *dw, float *dtheta, void *stream);
 
+/* Kernel timing, for profiling and tracing.  While enabled, every launch of
+ * a sweep's main kernel is bracketed by two hipEvents recorded on the
+ * launch stream (a few microseconds of host time per launch).  Kinds:
+ *   HNV_PROF_SWEEP     forward sweep (reads this level's previous iterate)
+ *   HNV_PROF_FUSED     forward sweep fused with the projection
+ *   HNV_PROF_ADJ_NODE  reverse sweep, node rows
+ *   HNV_PROF_ADJ_EDGE  reverse sweep, hyperedge rows
+ * enable = 0 stops recording and discards what was recorded. */
+#define HNV_PROF_SWEEP 0
+#define HNV_PROF_FUSED 1
+#define HNV_PROF_ADJ_NODE 2
+#define HNV_PROF_ADJ_EDGE 3
+hnv_status hnv_plan_set_profiling(hnv_plan *plan, int enable);
+
+/* Waits for the recorded events and returns, for one kind and one level
+ * (level = -1: all levels), the number of launches and their summed
+ * durations in milliseconds.  Host call; records are kept until
+ * hnv_plan_set_profiling(plan, 0). */
+hnv_status hnv_plan_profile_read(hnv_plan *plan, int kind, int level, int64_t *launches, double *total_ms);
+
 /* Element-wise conversion between storage types on the device (FP32 ->
  * BF16 rounds to nearest even; BF16 -> FP32 is exact).  n elements. */
 hnv_status hnv_cast(const void *src, hnv_dtype src_dtype, void *dst, hnv_dtype dst_dtype,

@@ -16,6 +16,7 @@ HNV_OK, HNV_EINVAL, HNV_ERANGE, HNV_EUNSORTED, HNV_EUNSUPPORTED, HNV_EWORKSPACE,
 STATUS_NAMES = {0: "HNV_OK", 1: "HNV_EINVAL", 2: "HNV_ERANGE", 3: "HNV_EUNSORTED", 4: "HNV_EUNSUPPORTED",
                 5: "HNV_EWORKSPACE", 6: "HNV_EDEVICE", 7: "HNV_ENOMEM"}
 HNV_F32, HNV_BF16 = 0, 1
+HNV_PROF_SWEEP, HNV_PROF_FUSED, HNV_PROF_ADJ_NODE, HNV_PROF_ADJ_EDGE = 0, 1, 2, 3
 
 i64 = ctypes.c_int64
 i32 = ctypes.c_int32
@@ -66,6 +67,8 @@ _SIGS = {
     "hnv_sweep_adjoint": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_float, vp]),
     "hnv_project_adjoint": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
     "hnv_logweight_grad": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
+    "hnv_plan_set_profiling": (ctypes.c_int, [vp, ctypes.c_int]),
+    "hnv_plan_profile_read": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, i64p, f64p]),
     "hnv_cast": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.c_int, i64, vp]),
 }
 

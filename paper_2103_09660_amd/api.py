@@ -217,6 +217,16 @@ class Plan:
             raise ValueError(f"{name}: expected contiguous {self.torch_dtype} [{self.rows(level)} x {self.d}] "
                              f"on the GPU, got {t.dtype} {tuple(t.shape)} on {t.device}")
 
+    # kernel timing ---------------------------------------------------------
+    def set_profiling(self, enable: bool):
+        L.call("hnv_plan_set_profiling", self._h, 1 if enable else 0)
+
+    def profile_read(self, kind: int, level: int = -1):
+        """(launches, total milliseconds) of one kernel kind (see hnv.h)."""
+        n, ms = ctypes.c_int64(), ctypes.c_double()
+        L.call("hnv_plan_profile_read", self._h, int(kind), int(level), ctypes.byref(n), ctypes.byref(ms))
+        return n.value, ms.value
+
     # weights ---------------------------------------------------------------
     def set_edge_weights(self, level: int, w):
         L.call("hnv_set_edge_weights", self._h, level, _ptr(w), _stream(self.device))

@@ -82,6 +82,15 @@ struct hnv_plan {
     int g_fwd = 1;                   // lanes per row in a forward pass
     int g_full = 1;                  // lanes per full-width row
     size_t ws_bytes = 0;
+    // kernel timing (hnv_plan_set_profiling)
+    struct ProfRecord {
+        int kind, level;
+        void *ev_begin, *ev_end;   // hipEvent_t
+    };
+    bool profiling = false;
+    std::vector<ProfRecord> prof;
+    std::vector<void *> ev_pool;
+    ~hnv_plan();
 };
 
 namespace hnv {

@@ -794,12 +794,50 @@ static GatherArgs only_side(GatherArgs a, int side)
     return a;
 }
 
+// Events bracketing one main-kernel launch when the plan is profiling.
+struct ProfScope {
+    hnv_plan *p;
+    hipStream_t s;
+    int kind, level;
+    hipEvent_t b = nullptr, e = nullptr;
+    hipEvent_t take()
+    {
+        if (!p->ev_pool.empty()) {
+            hipEvent_t ev = reinterpret_cast<hipEvent_t>(p->ev_pool.back());
+            p->ev_pool.pop_back();
+            return ev;
+        }
+        hipEvent_t ev = nullptr;
+        return hipEventCreate(&ev) == hipSuccess ? ev : nullptr;
+    }
+    void begin()
+    {
+        if (!p || !p->profiling)
+            return;
+        b = take();
+        e = take();
+        if (b && e)
+            (void)hipEventRecord(b, s);
+    }
+    void end()
+    {
+        if (!b || !e)
+            return;
+        (void)hipEventRecord(e, s);
+        p->prof.push_back(hnv_plan::ProfRecord{kind, level, b, e});
+    }
+};
+
 template <typename T, int G, int MODE, bool FUSED>
-static void launch_pair(const GatherArgs &a, int panels, hipStream_t s)
+static void launch_pair(const GatherArgs &a, int panels, hipStream_t s, ProfScope *ps)
 {
     const unsigned main_blocks = (unsigned)a.blocks_per_panel * panels;
+    if (ps)
+        ps->begin();
     if (main_blocks)
         k_gather<T, G, MODE, FUSED><<<main_blocks, kBlock, 0, s>>>(a);
+    if (ps)
+        ps->end();
     const unsigned fin_blocks = (unsigned)(a.nb_split[0] + a.nb_split[1]) * panels;
     if (fin_blocks) {
         GatherArgs f = a;
@@ -809,16 +847,16 @@ static void launch_pair(const GatherArgs &a, int panels, hipStream_t s)
 }
 
 template <typename T, int MODE, bool FUSED>
-static hnv_status dispatch_g(int G, const GatherArgs &a, int panels, hipStream_t s)
+static hnv_status dispatch_g(int G, const GatherArgs &a, int panels, hipStream_t s, ProfScope *ps)
 {
     switch (G) {
-    case 1: launch_pair<T, 1, MODE, FUSED>(a, panels, s); break;
-    case 2: launch_pair<T, 2, MODE, FUSED>(a, panels, s); break;
-    case 4: launch_pair<T, 4, MODE, FUSED>(a, panels, s); break;
-    case 8: launch_pair<T, 8, MODE, FUSED>(a, panels, s); break;
-    case 16: launch_pair<T, 16, MODE, FUSED>(a, panels, s); break;
-    case 32: launch_pair<T, 32, MODE, FUSED>(a, panels, s); break;
-    case 64: launch_pair<T, 64, MODE, FUSED>(a, panels, s); break;
+    case 1: launch_pair<T, 1, MODE, FUSED>(a, panels, s, ps); break;
+    case 2: launch_pair<T, 2, MODE, FUSED>(a, panels, s, ps); break;
+    case 4: launch_pair<T, 4, MODE, FUSED>(a, panels, s, ps); break;
+    case 8: launch_pair<T, 8, MODE, FUSED>(a, panels, s, ps); break;
+    case 16: launch_pair<T, 16, MODE, FUSED>(a, panels, s, ps); break;
+    case 32: launch_pair<T, 32, MODE, FUSED>(a, panels, s, ps); break;
+    case 64: launch_pair<T, 64, MODE, FUSED>(a, panels, s, ps); break;
     default: return fail(HNV_EUNSUPPORTED, "lane group width");
     }
     return dev_check("sweep kernels");
@@ -835,13 +873,14 @@ static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, 
     a.dst = dst;
     a.resid = resid_out ? p->resid_part : nullptr;
     a.resid_offset = 0;
+    ProfScope ps{p, s, fused ? HNV_PROF_FUSED : HNV_PROF_SWEEP, level};
     hnv_status st;
     if (p->dtype == HNV_F32)
-        st = fused ? dispatch_g<float, kFwd, true>(p->g_fwd, a, p->panels, s)
-                   : dispatch_g<float, kFwd, false>(p->g_fwd, a, p->panels, s);
+        st = fused ? dispatch_g<float, kFwd, true>(p->g_fwd, a, p->panels, s, &ps)
+                   : dispatch_g<float, kFwd, false>(p->g_fwd, a, p->panels, s, &ps);
     else
-        st = fused ? dispatch_g<bf16_t, kFwd, true>(p->g_fwd, a, p->panels, s)
-                   : dispatch_g<bf16_t, kFwd, false>(p->g_fwd, a, p->panels, s);
+        st = fused ? dispatch_g<bf16_t, kFwd, true>(p->g_fwd, a, p->panels, s, &ps)
+                   : dispatch_g<bf16_t, kFwd, false>(p->g_fwd, a, p->panels, s, &ps);
     if (st != HNV_OK)
         return st;
     if (resid_out) {
@@ -1087,14 +1126,15 @@ extern "C" hnv_status hnv_sweep_adjoint(hnv_plan *plan, int level, const void *g
     a.resid = nullptr;
     // node rows first (they produce the per-node scalars), then hyperedge rows
     const GatherArgs an = only_side(a, 1), ae = only_side(a, 0);
+    ProfScope pn{plan, s, HNV_PROF_ADJ_NODE, level}, pe{plan, s, HNV_PROF_ADJ_EDGE, level};
     if (plan->dtype == HNV_F32) {
-        if ((st = dispatch_g<float, kAdjNode, false>(G, an, 1, s)) != HNV_OK)
+        if ((st = dispatch_g<float, kAdjNode, false>(G, an, 1, s, &pn)) != HNV_OK)
             return st;
-        st = dispatch_g<float, kAdjEdge, false>(G, ae, 1, s);
+        st = dispatch_g<float, kAdjEdge, false>(G, ae, 1, s, &pe);
     } else {
-        if ((st = dispatch_g<bf16_t, kAdjNode, false>(G, an, 1, s)) != HNV_OK)
+        if ((st = dispatch_g<bf16_t, kAdjNode, false>(G, an, 1, s, &pn)) != HNV_OK)
             return st;
-        st = dispatch_g<bf16_t, kAdjEdge, false>(G, ae, 1, s);
+        st = dispatch_g<bf16_t, kAdjEdge, false>(G, ae, 1, s, &pe);
     }
     return st;
 }
@@ -1162,4 +1202,56 @@ extern "C" hnv_status hnv_cast(const void *src, hnv_dtype src_dtype, void *dst, 
     } else
         return fail(HNV_EINVAL, "unknown dtype");
     return dev_check("cast kernel");
+}
+
+extern "C" hnv_status hnv_plan_set_profiling(hnv_plan *plan, int enable)
+{
+    clear_error();
+    if (!plan)
+        return fail(HNV_EINVAL, "plan is NULL");
+    if (!enable) {
+        for (auto &r : plan->prof) {
+            plan->ev_pool.push_back(r.ev_begin);
+            plan->ev_pool.push_back(r.ev_end);
+        }
+        plan->prof.clear();
+    }
+    plan->profiling = enable != 0;
+    return HNV_OK;
+}
+
+extern "C" hnv_status hnv_plan_profile_read(hnv_plan *plan, int kind, int level, int64_t *launches,
+                                            double *total_ms)
+{
+    clear_error();
+    if (!plan || !launches || !total_ms)
+        return fail(HNV_EINVAL, "NULL argument");
+    int64_t n = 0;
+    double ms = 0.0;
+    for (auto &r : plan->prof) {
+        if (r.kind != kind || (level >= 0 && r.level != level))
+            continue;
+        hipEvent_t e = reinterpret_cast<hipEvent_t>(r.ev_end);
+        hipError_t err = hipEventSynchronize(e);
+        float t = 0.0f;
+        if (err == hipSuccess)
+            err = hipEventElapsedTime(&t, reinterpret_cast<hipEvent_t>(r.ev_begin), e);
+        if (err != hipSuccess)
+            return fail(HNV_EDEVICE, std::string("event timing: ") + hipGetErrorString(err));
+        ++n;
+        ms += t;
+    }
+    *launches = n;
+    *total_ms = ms;
+    return HNV_OK;
+}
+
+hnv_plan::~hnv_plan()
+{
+    for (auto &r : prof) {
+        (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(r.ev_begin));
+        (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(r.ev_end));
+    }
+    for (void *ev : ev_pool)
+        (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(ev));
 }
