@@ -82,7 +82,8 @@ typedef struct {
 /* Tuning knobs; zero fields take the library's defaults. */
 typedef struct {
     int32_t panel_cols;  /* columns per pass of a forward sweep (divides d, multiple of 8) */
-    int32_t small_max;   /* rows with at most this many neighbours go to a lane group */
+    int32_t small_max;   /* rows with at most this many neighbours go to a lane group (capped
+                            at 4 lanes' worth of indices per lane of the group) */
     int32_t chunk;       /* neighbours per wavefront work item; longer rows are split */
 } hnv_options;
 

@@ -37,8 +37,17 @@ int next_pow2(int x)
 
 int64_t blocks_for(int64_t items, int64_t per_block) { return (items + per_block - 1) / per_block; }
 
+void lane_layout(int cols, int elem, int *lanes, int *elems_per_lane)
+{
+    int epl = 16 / elem;
+    if (cols / epl > kWave)
+        epl = 32 / elem;
+    *elems_per_lane = epl;
+    *lanes = next_pow2((cols + epl - 1) / epl);
+}
+
 static constexpr int64_t kMaxI32 = std::numeric_limits<int32_t>::max();
-static constexpr int kDefaultSmallMax = 32;
+static constexpr int kDefaultSmallMax = 64;
 static constexpr int kDefaultChunk = 512;
 
 // ---------------------------------------------------------------------------
@@ -180,8 +189,8 @@ static hnv_status coarsen(const hnv_level *lv, int32_t *node_rep, int32_t *edge_
 // ---------------------------------------------------------------------------
 
 struct HostTier {
-    std::vector<int32_t> small;
-    std::vector<Chunk> chunks;
+    std::vector<Item> small;
+    std::vector<Item> chunks;
     std::vector<Split> splits;
 };
 
@@ -204,29 +213,28 @@ static void tier_side(const int32_t *ptr, int32_t n_rows, int small_max, int chu
     }
     for (int k = 0; k <= small_max; ++k)
         count[k + 1] += count[k];
-    t.small.assign(n_small, 0);
+    t.small.assign(n_small, Item{0, 0, 0, 0});
     t.chunks.clear();
     t.splits.clear();
     for (int32_t r = 0; r < n_rows; ++r) {
         const int32_t deg = ptr[r + 1] - ptr[r];
         if (deg <= small_max) {
-            t.small[count[small_max - deg]++] = r;
+            t.small[count[small_max - deg]++] = Item{r, ptr[r], deg, 0};
             continue;
         }
         const int32_t pieces = (deg + chunk - 1) / chunk;
         if (pieces == 1) {
-            t.chunks.push_back(Chunk{r, ptr[r], deg, -1});
+            t.chunks.push_back(Item{r, ptr[r], deg, -1});
             continue;
         }
         t.splits.push_back(Split{r, *slot_base, pieces, deg});
         for (int32_t k = 0; k < pieces; ++k) {
             const int32_t s = ptr[r] + k * chunk;
-            t.chunks.push_back(Chunk{r, s, std::min(chunk, ptr[r + 1] - s), *slot_base + k});
+            t.chunks.push_back(Item{r, s, std::min(chunk, ptr[r + 1] - s), *slot_base + k});
         }
         *slot_base += pieces;
     }
-    std::stable_sort(t.chunks.begin(), t.chunks.end(),
-                     [](const Chunk &a, const Chunk &b) { return a.len > b.len; });
+    std::stable_sort(t.chunks.begin(), t.chunks.end(), [](const Item &a, const Item &b) { return a.len > b.len; });
 }
 
 struct HostLevel {
@@ -238,13 +246,16 @@ struct HostLevel {
     std::vector<int32_t> rowmap, inv_ptr, inv_idx;
 };
 
-static void resolve_options(const hnv_options *in, int d, hnv_options *out)
+static void resolve_options(const hnv_options *in, int d, hnv_dtype dtype, hnv_options *out)
 {
     hnv_options o{};
     if (in)
         o = *in;
+    // FP32 rows wider than 64 columns run in 64-column passes: 16 lanes per
+    // row slice keep four rows per wavefront (measured faster than full-width
+    // rows at two per wavefront, despite reading the indices once per pass).
     if (o.panel_cols <= 0)
-        o.panel_cols = d;
+        o.panel_cols = (dtype == HNV_F32 && d > 64 && d % 64 == 0) ? 64 : d;
     if (o.small_max <= 0)
         o.small_max = kDefaultSmallMax;
     if (o.chunk <= 0)
@@ -305,7 +316,7 @@ static hnv_status check_map(const hnv_level &f, const hnv_level &c, const hnv_ma
 // Builds the host arrays of one level (with_arrays = false: only what the
 // workspace size needs).
 static void build_level(const hnv_level *levels, const hnv_map *maps, int n_levels, int l, const hnv_options &o,
-                        bool with_arrays, HostLevel &h)
+                        int small_max, bool with_arrays, HostLevel &h)
 {
     const hnv_level &L = levels[l];
     h.nV = L.n_nodes;
@@ -327,8 +338,8 @@ static void build_level(const hnv_level *levels, const hnv_map *maps, int n_leve
         h.ptr[1][v + 1] += h.ptr[1][v];
 
     int32_t slots = 0;
-    tier_side(h.ptr[0].data(), (int32_t)h.nE, o.small_max, o.chunk, &slots, h.tier[0]);
-    tier_side(h.ptr[1].data(), (int32_t)h.nV, o.small_max, o.chunk, &slots, h.tier[1]);
+    tier_side(h.ptr[0].data(), (int32_t)h.nE, small_max, o.chunk, &slots, h.tier[0]);
+    tier_side(h.ptr[1].data(), (int32_t)h.nV, small_max, o.chunk, &slots, h.tier[1]);
     h.n_slots = slots;
     if (!with_arrays)
         return;
@@ -359,6 +370,10 @@ static void build_level(const hnv_level *levels, const hnv_map *maps, int n_leve
         h.cidx[s].resize(h.nnz);
         for (int64_t j = 0; j < h.nnz; ++j)
             h.cidx[s][j] = h.rowmap[h.idx[s][j]];
+        // lane-group items carry the coarse row their own value comes from
+        const int64_t base = (s == 0) ? h.nV : 0;
+        for (auto &it : h.tier[s].small)
+            it.aux = h.rowmap[base + it.row];
     }
     // inverse map: fine rows of each coarse row, ascending
     h.inv_ptr.assign(h.rows_c + 1, 0);
@@ -422,8 +437,8 @@ static void carve(hnv_plan *p, std::vector<HostLevel> &hl, char *base)
             S.n_small = (int32_t)h.tier[s].small.size();
             S.n_chunks = (int32_t)h.tier[s].chunks.size();
             S.n_splits = (int32_t)h.tier[s].splits.size();
-            S.small_rows = c.take<int32_t>(S.n_small);
-            S.chunks = c.take<Chunk>(S.n_chunks);
+            S.small = c.take<Item>(S.n_small);
+            S.chunks = c.take<Item>(S.n_chunks);
             S.splits = c.take<Split>(S.n_splits);
             L.n_small[s] = S.n_small;
             L.n_chunks[s] = S.n_chunks;
@@ -460,8 +475,10 @@ static void init_plan_shape(hnv_plan *p, const hnv_level *levels, int n_levels, 
     p->opts = o;
     p->dp = o.panel_cols;
     p->panels = d / o.panel_cols;
-    p->g_fwd = next_pow2(p->dp / 8);
-    p->g_full = next_pow2(d / 8);
+    const int elem = (dtype == HNV_BF16) ? 2 : 4;
+    lane_layout(p->dp, elem, &p->g_fwd, &p->epl_fwd);
+    lane_layout(d, elem, &p->g_full, &p->epl_full);
+    p->small_max = std::min(o.small_max, kIdxRegs * p->g_fwd);
     p->pstride = d + 8;
     p->lv.assign(n_levels, LevelPlan{});
     for (int l = 0; l < n_levels; ++l) {
@@ -519,7 +536,7 @@ extern "C" hnv_status hnv_plan_workspace_bytes(const hnv_level *levels, const hn
     if (!bytes)
         return fail(HNV_EINVAL, "bytes is NULL");
     hnv_options o;
-    resolve_options(opts, d, &o);
+    resolve_options(opts, d, dtype, &o);
     hnv_status st = check_shape(levels, maps, n_levels, d, dtype, o);
     if (st != HNV_OK)
         return st;
@@ -528,7 +545,7 @@ extern "C" hnv_status hnv_plan_workspace_bytes(const hnv_level *levels, const hn
         init_plan_shape(&p, levels, n_levels, d, dtype, o);
         std::vector<HostLevel> hl(n_levels);
         for (int l = 0; l < n_levels; ++l)
-            build_level(levels, maps, n_levels, l, o, false, hl[l]);
+            build_level(levels, maps, n_levels, l, o, p.small_max, false, hl[l]);
         carve(&p, hl, nullptr);
         *bytes = p.ws_bytes;
         return HNV_OK;
@@ -556,7 +573,7 @@ extern "C" hnv_status hnv_plan_create(const hnv_level *levels, const hnv_map *ma
         return fail(HNV_EINVAL, "out is NULL");
     *out = nullptr;
     hnv_options o;
-    resolve_options(opts, d, &o);
+    resolve_options(opts, d, dtype, &o);
     hnv_status st = check_shape(levels, maps, n_levels, d, dtype, o);
     if (st != HNV_OK)
         return st;
@@ -583,7 +600,7 @@ extern "C" hnv_status hnv_plan_create(const hnv_level *levels, const hnv_map *ma
         {
             std::vector<HostLevel> hl(n_levels);
             for (int l = 0; l < n_levels; ++l)
-                build_level(levels, maps, n_levels, l, o, false, hl[l]);
+                build_level(levels, maps, n_levels, l, o, p->small_max, false, hl[l]);
             carve(p, hl, nullptr);
             if (p->ws_bytes > ws_bytes) {
                 const size_t need = p->ws_bytes;
@@ -596,15 +613,15 @@ extern "C" hnv_status hnv_plan_create(const hnv_level *levels, const hnv_map *ma
         // one level at a time: build host arrays, upload, wait, free
         for (int l = 0; l < n_levels; ++l) {
             HostLevel h;
-            build_level(levels, maps, n_levels, l, o, true, h);
+            build_level(levels, maps, n_levels, l, o, p->small_max, true, h);
             LevelPlan &L = p->lv[l];
             for (int sd = 0; sd < 2; ++sd) {
                 DevSide &S = L.side[sd];
                 if ((st = upload((void *)S.ptr, h.ptr[sd].data(), h.ptr[sd].size() * 4, s)) != HNV_OK ||
                     (st = upload((void *)S.idx, h.idx[sd].data(), h.idx[sd].size() * 4, s)) != HNV_OK ||
                     (S.cidx && (st = upload((void *)S.cidx, h.cidx[sd].data(), h.cidx[sd].size() * 4, s)) != HNV_OK) ||
-                    (st = upload((void *)S.small_rows, h.tier[sd].small.data(), h.tier[sd].small.size() * 4, s)) != HNV_OK ||
-                    (st = upload((void *)S.chunks, h.tier[sd].chunks.data(), h.tier[sd].chunks.size() * sizeof(Chunk), s)) != HNV_OK ||
+                    (st = upload((void *)S.small, h.tier[sd].small.data(), h.tier[sd].small.size() * sizeof(Item), s)) != HNV_OK ||
+                    (st = upload((void *)S.chunks, h.tier[sd].chunks.data(), h.tier[sd].chunks.size() * sizeof(Item), s)) != HNV_OK ||
                     (st = upload((void *)S.splits, h.tier[sd].splits.data(), h.tier[sd].splits.size() * sizeof(Split), s)) != HNV_OK)
                     break;
             }

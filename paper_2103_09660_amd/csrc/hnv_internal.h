@@ -14,12 +14,15 @@ constexpr int kBlock = 256;   // threads per workgroup (4 wavefronts of 64)
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = kBlock / kWave;
 
-// A work item of the wavefront tier: `len` neighbours of `row` starting at
-// `start` in the side's neighbour array.  slot < 0: the wavefront owns the
-// whole row and writes the result; slot >= 0: it writes a partial sum to
-// partial slot `slot` and a finalize pass combines the row's slots in order.
-struct alignas(16) Chunk {
-    int32_t row, start, len, slot;
+// A work item: `len` neighbours of side-local row `row` starting at `start`
+// in the side's neighbour array.
+//   lane-group tier: len = the row's degree, aux = the row of the next
+//     coarser level its value is projected from (0 at the coarsest level);
+//   wavefront tier: aux = -1 if the wavefront owns the whole row (len = its
+//     degree), else the partial slot it writes; a finalize pass combines a
+//     split row's slots in order.
+struct alignas(16) Item {
+    int32_t row, start, len, aux;
 };
 // A row split over n_slots consecutive partial slots starting at first_slot.
 struct alignas(16) Split {
@@ -37,9 +40,9 @@ struct DevSide {
     const int32_t *cidx = nullptr;   // [nnz] neighbour Z row at the next coarser level, or null
     float *wn = nullptr;             // [nnz] weight of each star edge (side 1 only)
     float *sn = nullptr;             // [nnz] reverse-mode scale: reciprocal of the neighbour's row sum
-    const int32_t *small_rows = nullptr;
+    const Item *small = nullptr;
     int32_t n_small = 0;
-    const Chunk *chunks = nullptr;
+    const Item *chunks = nullptr;
     int32_t n_chunks = 0;
     const Split *splits = nullptr;
     int32_t n_splits = 0;
@@ -80,7 +83,10 @@ struct hnv_plan {
     int panels = 1;                  // column passes of a forward sweep
     int dp = 0;                      // columns per pass
     int g_fwd = 1;                   // lanes per row in a forward pass
+    int epl_fwd = 8;                 // elements per lane in a forward pass
     int g_full = 1;                  // lanes per full-width row
+    int epl_full = 8;                // elements per lane of a full-width row
+    int small_max = 0;               // effective lane-group tier bound
     size_t ws_bytes = 0;
     // kernel timing (hnv_plan_set_profiling)
     struct ProfRecord {
@@ -100,6 +106,10 @@ hnv_status fail(hnv_status st, const std::string &msg);
 void clear_error();
 
 int next_pow2(int x);
+// Lane layout of a row slice of `cols` elements of `elem` bytes: every lane
+// moves 16 B (32 B when a 64-lane wavefront would not cover the slice).
+void lane_layout(int cols, int elem, int *lanes, int *elems_per_lane);
+constexpr int kIdxRegs = 4;          // neighbour indices a lane preloads in the lane-group tier
 int64_t blocks_for(int64_t items, int64_t per_block);
 
 // Forward-sweep launch geometry of a level (blocks per panel and finalize blocks).

@@ -4,19 +4,24 @@
 // The refinement sweep (Section 3.3, Algorithm 2) is a sparse x dense gather
 // over the star expansion H* (Section 1.1): every row of H* relaxes towards
 // the weighted mean of its neighbours' rows.  It has no dense contraction, so
-// it is bound by HBM bandwidth and the kernels are built around memory
-// traffic, not matrix cores:
-//   - a row of Z is read by a group of G lanes, 8 elements (16 B of BF16,
-//     32 B of FP32) per lane, so every gathered row is one coalesced access;
+// it is bound by memory traffic and latency, and the kernels are built around
+// them rather than around matrix cores:
+//   - a row slice of Z is read by a group of G lanes, each moving 16 bytes
+//     (8 BF16 or 4 FP32 elements), so every gathered row is one coalesced
+//     access and a wavefront covers 64/G rows at once;
 //   - rows are tiered by neighbour count on the host.  Rows with few
-//     neighbours are handled by one lane group each (64/G rows per
-//     wavefront, same-degree rows together).  Longer rows get a whole
-//     wavefront per chunk of neighbours.  The 64/G groups of the wavefront
-//     take interleaved neighbours and are combined with cross-lane shuffles.
-//     Rows longer than one chunk are split over several wavefronts whose FP32
-//     partial sums are combined in a fixed order by a finalize pass;
-//   - neighbour indices are loaded once per lane and broadcast with
-//     cross-lane shuffles, and four neighbour rows are in flight per lane;
+//     neighbours get one lane group each (same-degree rows share a
+//     wavefront); longer rows get a whole wavefront per chunk of neighbours,
+//     the 64/G groups taking interleaved neighbours and being combined by a
+//     cross-lane butterfly; rows longer than one chunk are split over several
+//     wavefronts whose FP32 partial sums a finalize pass adds in slot order;
+//   - latency is hidden by keeping the dependent-load chain short: a work
+//     item carries the row, its first neighbour and its degree (and, for the
+//     first sweep of a level, the coarser row it is projected from); a lane
+//     preloads its share of the row's neighbour indices, the row's own value
+//     is fetched before the neighbours, and four neighbour rows are in
+//     flight per lane, masked at the row's end (deeper unrolling costs
+//     registers, and measured slower: occupancy matters more here);
 //   - the first sweep of a level reads the coarser level's rows through the
 //     projection row map (fused projection + sweep);
 //   - no atomics: every sum has a fixed order, so results are bitwise
@@ -31,19 +36,26 @@
 
 #include "hnv_internal.h"
 
+#define HNV_DEV __device__ __forceinline__
+
 namespace hnv {
 
 typedef uint16_t bf16_t;
 
+#ifndef HNV_UNROLL
+#define HNV_UNROLL 4
+#endif
+constexpr int kUnroll = HNV_UNROLL;   // neighbour rows in flight per lane (4 keeps 8 waves per SIMD)
+
 // ---------------------------------------------------------------------------
-// storage conversions
+// storage: one lane's slice of a row, EPL consecutive elements
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ float bf_lo(uint32_t x) { return __uint_as_float(x << 16); }
-__device__ __forceinline__ float bf_hi(uint32_t x) { return __uint_as_float(x & 0xffff0000u); }
+HNV_DEV float bf_lo(uint32_t x) { return __uint_as_float(x << 16); }
+HNV_DEV float bf_hi(uint32_t x) { return __uint_as_float(x & 0xffff0000u); }
 
 // FP32 -> BF16 bits, round to nearest even; NaN stays NaN.
-__device__ __forceinline__ uint32_t to_bf16(float f)
+HNV_DEV uint32_t to_bf16(float f)
 {
     uint32_t u = __float_as_uint(f);
     if ((u & 0x7fffffffu) > 0x7f800000u)
@@ -52,20 +64,41 @@ __device__ __forceinline__ uint32_t to_bf16(float f)
     return u >> 16;
 }
 
-template <typename T>
-struct Row8;
+template <typename T, int EPL>
+struct Slice;
 
 template <>
-struct Row8<float> {
-    static __device__ __forceinline__ void load(const float *p, float (&v)[8])
+struct Slice<float, 4> {
+    struct Raw {
+        float4 a;
+    };
+    static HNV_DEV Raw load(const float *p) { return Raw{*reinterpret_cast<const float4 *>(p)}; }
+    static HNV_DEV void unpack(const Raw &r, float (&v)[4])
     {
-        const float4 a = reinterpret_cast<const float4 *>(p)[0];
-        const float4 b = reinterpret_cast<const float4 *>(p)[1];
-        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+        v[0] = r.a.x; v[1] = r.a.y; v[2] = r.a.z; v[3] = r.a.w;
     }
-    // stores v and returns in v the values as stored
-    static __device__ __forceinline__ void store(float *p, float (&v)[8])
+    // stores v and leaves in v the values as stored
+    static HNV_DEV void store(float *p, float (&v)[4])
+    {
+        *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+};
+
+template <>
+struct Slice<float, 8> {
+    struct Raw {
+        float4 a, b;
+    };
+    static HNV_DEV Raw load(const float *p)
+    {
+        return Raw{reinterpret_cast<const float4 *>(p)[0], reinterpret_cast<const float4 *>(p)[1]};
+    }
+    static HNV_DEV void unpack(const Raw &r, float (&v)[8])
+    {
+        v[0] = r.a.x; v[1] = r.a.y; v[2] = r.a.z; v[3] = r.a.w;
+        v[4] = r.b.x; v[5] = r.b.y; v[6] = r.b.z; v[7] = r.b.w;
+    }
+    static HNV_DEV void store(float *p, float (&v)[8])
     {
         reinterpret_cast<float4 *>(p)[0] = make_float4(v[0], v[1], v[2], v[3]);
         reinterpret_cast<float4 *>(p)[1] = make_float4(v[4], v[5], v[6], v[7]);
@@ -73,14 +106,17 @@ struct Row8<float> {
 };
 
 template <>
-struct Row8<bf16_t> {
-    static __device__ __forceinline__ void load(const bf16_t *p, float (&v)[8])
+struct Slice<bf16_t, 8> {
+    struct Raw {
+        uint4 q;
+    };
+    static HNV_DEV Raw load(const bf16_t *p) { return Raw{*reinterpret_cast<const uint4 *>(p)}; }
+    static HNV_DEV void unpack(const Raw &r, float (&v)[8])
     {
-        const uint4 q = *reinterpret_cast<const uint4 *>(p);
-        v[0] = bf_lo(q.x); v[1] = bf_hi(q.x); v[2] = bf_lo(q.y); v[3] = bf_hi(q.y);
-        v[4] = bf_lo(q.z); v[5] = bf_hi(q.z); v[6] = bf_lo(q.w); v[7] = bf_hi(q.w);
+        v[0] = bf_lo(r.q.x); v[1] = bf_hi(r.q.x); v[2] = bf_lo(r.q.y); v[3] = bf_hi(r.q.y);
+        v[4] = bf_lo(r.q.z); v[5] = bf_hi(r.q.z); v[6] = bf_lo(r.q.w); v[7] = bf_hi(r.q.w);
     }
-    static __device__ __forceinline__ void store(bf16_t *p, float (&v)[8])
+    static HNV_DEV void store(bf16_t *p, float (&v)[8])
     {
         uint32_t h[8];
 #pragma unroll
@@ -97,11 +133,23 @@ struct Row8<bf16_t> {
     }
 };
 
-__device__ __forceinline__ void zero8(float (&a)[8])
+template <int N>
+HNV_DEV void zero(float (&a)[N])
 {
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < N; ++i)
         a[i] = 0.0f;
+}
+
+// acc += s * row (SCALE) or acc += row
+template <bool SCALE, typename T, int EPL>
+HNV_DEV void accumulate(float (&acc)[EPL], float s, const typename Slice<T, EPL>::Raw &raw)
+{
+    float v[EPL];
+    Slice<T, EPL>::unpack(raw, v);
+#pragma unroll
+    for (int i = 0; i < EPL; ++i)
+        acc[i] = SCALE ? fmaf(s, v[i], acc[i]) : acc[i] + v[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -142,111 +190,120 @@ struct GatherArgs {
 // gathers
 // ---------------------------------------------------------------------------
 
-// One lane group (G lanes) gathers one row: acc = sum_j s_j * src[nb_j] over
-// the row's neighbours in order; csum = sum_j c[nb_j] (per lane, partial).
-template <typename T, int G, bool SCALE, bool SCALAR>
-__device__ __forceinline__ void gather_group(const int32_t *__restrict__ nb, const float *__restrict__ sc,
-                                             const float *__restrict__ cvec, int start, int deg,
-                                             const T *__restrict__ src, int64_t ld, int col, bool col_ok, int gl,
-                                             int gbase, float (&acc)[8], float &csum)
+// One lane group (G lanes) gathers one row of degree deg <= kIdxRegs * G:
+// acc = sum_j s_j * src[nb_j] in neighbour order; csum (per lane, partial) =
+// sum of c[nb_j] over the lane's own neighbours.  Lane gl preloads the
+// indices of positions gl, gl + G, gl + 2G, gl + 3G; the neighbour rows are
+// fetched kUnroll at a time, masked at the row's end.
+template <typename T, int EPL, int G, bool SCALE, bool SCALAR>
+HNV_DEV void gather_group(const int32_t *__restrict__ nb, const float *__restrict__ sc,
+                          const float *__restrict__ cvec, int start, int deg, const T *__restrict__ src, int64_t ld,
+                          int col, bool col_ok, int gl, int gbase, float (&acc)[EPL], float &csum)
 {
-    for (int b = 0; b < deg; b += G) {
-        const int p = b + gl;
-        int my_nb = 0;
-        float my_s = 1.0f;
+    using S = Slice<T, EPL>;
+    int ix[kIdxRegs];
+    float sv[kIdxRegs];
+#pragma unroll
+    for (int r = 0; r < kIdxRegs; ++r) {
+        const int p = gl + r * G;
+        ix[r] = 0;
+        sv[r] = 1.0f;
         if (p < deg) {
-            my_nb = nb[start + p];
+            ix[r] = nb[start + p];
             if (SCALE)
-                my_s = sc[start + p];
-            if (SCALAR)
-                csum += cvec[my_nb];
+                sv[r] = sc[start + p];
         }
-        const int n = min(G, deg - b);
-        int j = 0;
-        for (; j + 4 <= n; j += 4) {
-            int v[4];
-            float s[4], x[4][8];
+    }
+    if (SCALAR) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                v[k] = __shfl(my_nb, gbase + j + k, kWave);
-                s[k] = SCALE ? __shfl(my_s, gbase + j + k, kWave) : 1.0f;
-            }
-            if (col_ok) {
+        for (int r = 0; r < kIdxRegs; ++r)
+            if (gl + r * G < deg)
+                csum += cvec[ix[r]];
+    }
+    for (int j = 0; j < deg; j += kUnroll) {
+        typename S::Raw raw[kUnroll];
+        float s[kUnroll];
+        bool ok[kUnroll];
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    Row8<T>::load(src + (int64_t)v[k] * ld + col, x[k]);
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-#pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        acc[i] = SCALE ? fmaf(s[k], x[k][i], acc[i]) : acc[i] + x[k][i];
-            }
+        for (int k = 0; k < kUnroll; ++k) {
+            const int q = j + k;
+            const int r = q / G;
+            const int xr = (r == 0) ? ix[0] : (r == 1) ? ix[1] : (r == 2) ? ix[2] : ix[3];
+            const float sr = (r == 0) ? sv[0] : (r == 1) ? sv[1] : (r == 2) ? sv[2] : sv[3];
+            const int lane_src = gbase + (q & (G - 1));
+            ok[k] = q < deg;
+            const int v = __shfl(xr, lane_src, kWave);
+            s[k] = SCALE ? __shfl(sr, lane_src, kWave) : 1.0f;
+            if (ok[k] && col_ok)
+                raw[k] = S::load(src + (int64_t)v * ld + col);
         }
-        for (; j < n; ++j) {
-            const int v = __shfl(my_nb, gbase + j, kWave);
-            const float s = SCALE ? __shfl(my_s, gbase + j, kWave) : 1.0f;
-            if (col_ok) {
-                float x[8];
-                Row8<T>::load(src + (int64_t)v * ld + col, x);
+        if (col_ok) {
 #pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    acc[i] = SCALE ? fmaf(s, x[i], acc[i]) : acc[i] + x[i];
-            }
+            for (int k = 0; k < kUnroll; ++k)
+                if (ok[k])
+                    accumulate<SCALE, T, EPL>(acc, s[k], raw[k]);
         }
     }
 }
 
 // A whole wavefront gathers `len` neighbours: group g takes neighbours
 // g, g + Q, g + 2Q, ... (Q = 64 / G), then the Q group sums are added with an
-// xor butterfly (every lane ends with the same, order-fixed total).
-template <typename T, int G, bool SCALE, bool SCALAR>
-__device__ __forceinline__ void gather_wave(const int32_t *__restrict__ nb, const float *__restrict__ sc,
-                                            const float *__restrict__ cvec, int start, int len,
-                                            const T *__restrict__ src, int64_t ld, int col, bool col_ok, int lane,
-                                            int g, float (&acc)[8], float &csum)
+// xor butterfly (every lane ends with the same, order-fixed total).  The
+// indices of the next 64 neighbours are fetched while the current ones are
+// gathered.
+template <typename T, int EPL, int G, bool SCALE, bool SCALAR>
+HNV_DEV void gather_wave(const int32_t *__restrict__ nb, const float *__restrict__ sc,
+                         const float *__restrict__ cvec, int start, int len, const T *__restrict__ src, int64_t ld,
+                         int col, bool col_ok, int lane, int g, float (&acc)[EPL], float &csum)
 {
+    using S = Slice<T, EPL>;
     constexpr int Q = kWave / G;
+    int my_nb = 0;
+    float my_s = 1.0f;
+    if (lane < len) {
+        my_nb = nb[start + lane];
+        if (SCALE)
+            my_s = sc[start + lane];
+    }
     for (int b = 0; b < len; b += kWave) {
-        const int p = b + lane;
-        int my_nb = 0;
-        float my_s = 1.0f;
-        if (p < len) {
-            my_nb = nb[start + p];
+        const int pn = b + kWave + lane;
+        int nx_nb = 0;
+        float nx_s = 1.0f;
+        if (pn < len) {
+            nx_nb = nb[start + pn];
             if (SCALE)
-                my_s = sc[start + p];
-            if (SCALAR)
-                csum += cvec[my_nb];
+                nx_s = sc[start + pn];
         }
+        if (SCALAR && b + lane < len)
+            csum += cvec[my_nb];
         const int n = min(kWave, len - b);
-        for (int t = 0; t < n; t += 4 * Q) {
-            int v[4];
-            float s[4], x[4][8];
-            bool ok[4];
+        for (int t = 0; t < n; t += kUnroll * Q) {
+            typename S::Raw raw[kUnroll];
+            float s[kUnroll];
+            bool ok[kUnroll];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < kUnroll; ++k) {
                 const int q = t + k * Q + g;
                 ok[k] = q < n;
-                v[k] = __shfl(my_nb, q & (kWave - 1), kWave);
+                const int v = __shfl(my_nb, q & (kWave - 1), kWave);
                 s[k] = SCALE ? __shfl(my_s, q & (kWave - 1), kWave) : 1.0f;
+                if (ok[k] && col_ok)
+                    raw[k] = S::load(src + (int64_t)v * ld + col);
             }
             if (col_ok) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
+                for (int k = 0; k < kUnroll; ++k)
                     if (ok[k])
-                        Row8<T>::load(src + (int64_t)v[k] * ld + col, x[k]);
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (ok[k])
-#pragma unroll
-                        for (int i = 0; i < 8; ++i)
-                            acc[i] = SCALE ? fmaf(s[k], x[k][i], acc[i]) : acc[i] + x[k][i];
+                        accumulate<SCALE, T, EPL>(acc, s[k], raw[k]);
             }
         }
+        my_nb = nx_nb;
+        my_s = nx_s;
     }
 #pragma unroll
     for (int off = G; off < kWave; off <<= 1)
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < EPL; ++i)
             acc[i] += __shfl_xor(acc[i], off, kWave);
     if (SCALAR) {
 #pragma unroll
@@ -257,7 +314,7 @@ __device__ __forceinline__ void gather_wave(const int32_t *__restrict__ nb, cons
 
 // sum over the G lanes of a group (xor butterfly inside the group)
 template <int G>
-__device__ __forceinline__ float group_sum(float x)
+HNV_DEV float group_sum(float x)
 {
 #pragma unroll
     for (int off = 1; off < G; off <<= 1)
@@ -266,37 +323,35 @@ __device__ __forceinline__ float group_sum(float x)
 }
 
 // ---------------------------------------------------------------------------
-// row epilogues
+// row epilogues (`self` is the row's own slice, already fetched)
 // ---------------------------------------------------------------------------
 
 // Forward: z'_u = (1 - omega) z_u + omega r_u acc (rows with neighbours),
 // z'_u = z_u otherwise.  Returns the row's contribution to ||z' - z||^2.
-template <typename T, bool FUSED>
-__device__ __forceinline__ double epilogue_fwd(const GatherArgs &a, int zrow, int deg, int col, bool col_ok,
-                                               float (&acc)[8])
+template <typename T, int EPL>
+HNV_DEV double epilogue_fwd(const GatherArgs &a, int zrow, int deg, int col, bool col_ok, float (&acc)[EPL],
+                            const typename Slice<T, EPL>::Raw &self)
 {
     if (!col_ok)
         return 0.0;
-    const T *src = static_cast<const T *>(a.src);
-    const int64_t self_row = FUSED ? (int64_t)a.rowmap[zrow] : (int64_t)zrow;
-    float z[8], o[8];
-    Row8<T>::load(src + self_row * a.ld + col, z);
+    float z[EPL], o[EPL];
+    Slice<T, EPL>::unpack(self, z);
     if (deg > 0) {
         const float keep = 1.0f - a.omega;
         const float mix = a.omega * a.r[zrow];
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < EPL; ++i)
             o[i] = fmaf(mix, acc[i], keep * z[i]);
     } else {
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < EPL; ++i)
             o[i] = z[i];
     }
-    Row8<T>::store(static_cast<T *>(a.dst) + (int64_t)zrow * a.ld + col, o);
+    Slice<T, EPL>::store(static_cast<T *>(a.dst) + (int64_t)zrow * a.ld + col, o);
     double r2 = 0.0;
     if (a.resid) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < EPL; ++i) {
             const double dd = (double)o[i] - (double)z[i];
             r2 += dd * dd;
         }
@@ -306,34 +361,35 @@ __device__ __forceinline__ double epilogue_fwd(const GatherArgs &a, int zrow, in
 
 // Reverse, node row v (side 1): g'_v = (1-omega) g_v + omega acc where acc =
 // sum_e g_e / |e|; c_v = <g_v, zt_v> / S_v with zt_v = (z_v - (1-omega) y_v) / omega.
-template <typename T, int G>
-__device__ __forceinline__ void epilogue_adj_node(const GatherArgs &a, int row, int deg, int col, bool col_ok,
-                                                  float (&acc)[8], bool writer)
+template <typename T, int EPL, int G>
+HNV_DEV void epilogue_adj_node(const GatherArgs &a, int row, int deg, int col, bool col_ok, float (&acc)[EPL],
+                               const typename Slice<T, EPL>::Raw &self, bool writer)
 {
+    using S = Slice<T, EPL>;
     const int64_t zrow = row;  // node rows start at Z row 0
-    float g[8], y[8], z[8];
     float dot = 0.0f;
     if (col_ok) {
-        Row8<T>::load(static_cast<const T *>(a.src) + zrow * a.ld + col, g);
-        float o[8];
+        float g[EPL], o[EPL];
+        S::unpack(self, g);
         if (deg > 0) {
-            Row8<T>::load(static_cast<const T *>(a.yprev) + zrow * a.ld + col, y);
-            Row8<T>::load(static_cast<const T *>(a.zcur) + zrow * a.ld + col, z);
+            float y[EPL], z[EPL];
+            S::unpack(S::load(static_cast<const T *>(a.yprev) + zrow * a.ld + col), y);
+            S::unpack(S::load(static_cast<const T *>(a.zcur) + zrow * a.ld + col), z);
             const float keep = 1.0f - a.omega;
             const float inv_om = 1.0f / a.omega;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
+            for (int i = 0; i < EPL; ++i) {
                 o[i] = fmaf(a.omega, acc[i], keep * g[i]);
                 const float zt = (z[i] - keep * y[i]) * inv_om;
                 dot = fmaf(g[i], zt, dot);
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
+            for (int i = 0; i < EPL; ++i)
                 o[i] = g[i];
         }
         if (writer)
-            Row8<T>::store(static_cast<T *>(a.dst) + zrow * a.ld + col, o);
+            S::store(static_cast<T *>(a.dst) + zrow * a.ld + col, o);
     }
     dot = group_sum<G>(dot);
     if (writer && (threadIdx.x % G) == 0)
@@ -342,32 +398,33 @@ __device__ __forceinline__ void epilogue_adj_node(const GatherArgs &a, int row, 
 
 // Reverse, hyperedge row e (side 0): g'_e = (1-omega) g_e + omega w_e acc with
 // acc = sum_v g_v / S_v; dL/dw_e += omega (<acc, y_e> - sum_v c_v).
-template <typename T, int G>
-__device__ __forceinline__ void epilogue_adj_edge(const GatherArgs &a, int row, int deg, int col, bool col_ok,
-                                                  float (&acc)[8], float csum, bool writer)
+template <typename T, int EPL, int G>
+HNV_DEV void epilogue_adj_edge(const GatherArgs &a, int row, int deg, int col, bool col_ok, float (&acc)[EPL],
+                               float csum, const typename Slice<T, EPL>::Raw &self, bool writer)
 {
+    using S = Slice<T, EPL>;
     const int64_t zrow = (int64_t)a.side[0].row_base + row;
     float dot = 0.0f;
     if (col_ok) {
-        float g[8], o[8];
-        Row8<T>::load(static_cast<const T *>(a.src) + zrow * a.ld + col, g);
+        float g[EPL], o[EPL];
+        S::unpack(self, g);
         if (deg > 0) {
-            float y[8];
-            Row8<T>::load(static_cast<const T *>(a.yprev) + zrow * a.ld + col, y);
+            float y[EPL];
+            S::unpack(S::load(static_cast<const T *>(a.yprev) + zrow * a.ld + col), y);
             const float keep = 1.0f - a.omega;
             const float mix = a.omega * a.w[row];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
+            for (int i = 0; i < EPL; ++i) {
                 o[i] = fmaf(mix, acc[i], keep * g[i]);
                 dot = fmaf(acc[i], y[i], dot);
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
+            for (int i = 0; i < EPL; ++i)
                 o[i] = g[i];
         }
         if (writer)
-            Row8<T>::store(static_cast<T *>(a.dst) + zrow * a.ld + col, o);
+            S::store(static_cast<T *>(a.dst) + zrow * a.ld + col, o);
     }
     dot = group_sum<G>(dot);
     if (writer && a.dw && deg > 0 && (threadIdx.x % G) == 0)
@@ -378,7 +435,7 @@ __device__ __forceinline__ void epilogue_adj_edge(const GatherArgs &a, int row, 
 // block-level residual reduction (FP64, fixed order)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void block_resid(const GatherArgs &a, double r2)
+HNV_DEV void block_resid(const GatherArgs &a, double r2)
 {
     if (!a.resid)
         return;
@@ -402,10 +459,10 @@ __device__ __forceinline__ void block_resid(const GatherArgs &a, double r2)
 // main kernel: wavefront tier + lane-group tier of both sides, all panels
 // ---------------------------------------------------------------------------
 
-template <typename T, int G, int MODE, bool FUSED>
+template <typename T, int EPL, int G, int MODE, bool FUSED>
 __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
 {
-    constexpr int Q = kWave / G;
+    using S = Slice<T, EPL>;
     int b = blockIdx.x;
     const int panel = b / a.blocks_per_panel;
     b -= panel * a.blocks_per_panel;
@@ -413,16 +470,16 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
     const int wave = threadIdx.x / kWave;
     const int g = lane / G;
     const int gl = lane % G;
-    const int col = panel * a.dp + gl * 8;
-    const bool col_ok = gl * 8 < a.dp;
+    const int col = panel * a.dp + gl * EPL;
+    const bool col_ok = gl * EPL < a.dp;
     const T *src = static_cast<const T *>(a.src);
-    float acc[8];
-    zero8(acc);
+    float acc[EPL];
+    zero(acc);
     float csum = 0.0f;
     double r2 = 0.0;
 
-    // which tier / side does this block serve?
-    int side = -1, tier = 0;  // tier 0: wavefront, 1: lane group
+    // which tier / side does this block serve?  (uniform over the block)
+    int side, tier = 0;  // tier 0: wavefront, 1: lane group
     if (b < a.nb_chunk[0]) {
         side = 0;
     } else if ((b -= a.nb_chunk[0]) < a.nb_chunk[1]) {
@@ -435,12 +492,11 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
         side = 1;
         tier = 1;
     }
-    // Every side-dependent choice is uniform over the block.
-    const DevSide &S = a.side[side];
+    const DevSide &Sd = a.side[side];
     constexpr bool kScalar = (MODE == kAdjEdge);
-    const bool use_scale = (MODE != kFwd) || (side == 1 && S.wn != nullptr);
-    const float *sc = (MODE == kFwd) ? S.wn : S.sn;
-    const int32_t *nb = FUSED ? S.cidx : S.idx;
+    const bool use_scale = (MODE != kFwd) || (side == 1 && Sd.wn != nullptr);
+    const float *sc = (MODE == kFwd) ? Sd.wn : Sd.sn;
+    const int32_t *nb = FUSED ? Sd.cidx : Sd.idx;
 
     // In reverse mode only one side is active per launch.
     if ((MODE == kAdjNode && side != 1) || (MODE == kAdjEdge && side != 0))
@@ -448,64 +504,67 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
 
     if (tier == 0) {
         const int item = b * kWavesPerBlock + wave;
-        const bool valid = item < S.n_chunks;
-        Chunk c{0, 0, 0, -1};
-        if (valid)
-            c = S.chunks[item];
-        if (valid) {
-            if (use_scale)
-                gather_wave<T, G, true, kScalar>(nb, sc, a.cvec, c.start, c.len, src, a.ld, col, col_ok, lane, g, acc,
-                                                 csum);
-            else
-                gather_wave<T, G, false, kScalar>(nb, sc, a.cvec, c.start, c.len, src, a.ld, col, col_ok, lane, g,
-                                                  acc, csum);
-        }
-        if (valid && c.slot >= 0) {
-            if (g == 0 && col_ok) {
-                float *pp = a.partials + (int64_t)c.slot * a.pstride + col;
-                reinterpret_cast<float4 *>(pp)[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
-                reinterpret_cast<float4 *>(pp)[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
-                if (kScalar && gl == 0)
-                    a.partials[(int64_t)c.slot * a.pstride + a.ld] = csum;
+        if (item < Sd.n_chunks) {   // uniform over the wavefront
+            const Item c = Sd.chunks[item];
+            const int zrow = Sd.row_base + c.row;
+            const bool whole = c.aux < 0;
+            typename S::Raw self{};
+            if (whole && col_ok) {
+                const int64_t srow = (MODE == kFwd && FUSED) ? (int64_t)a.rowmap[zrow] : (int64_t)zrow;
+                self = S::load(src + srow * a.ld + col);
             }
-        } else if (valid) {
-            const int deg = S.ptr[c.row + 1] - S.ptr[c.row];
-            if (MODE == kFwd) {
+            if (use_scale)
+                gather_wave<T, EPL, G, true, kScalar>(nb, sc, a.cvec, c.start, c.len, src, a.ld, col, col_ok, lane, g,
+                                                      acc, csum);
+            else
+                gather_wave<T, EPL, G, false, kScalar>(nb, sc, a.cvec, c.start, c.len, src, a.ld, col, col_ok, lane,
+                                                       g, acc, csum);
+            if (!whole) {
+                if (g == 0 && col_ok) {
+                    float *pp = a.partials + (int64_t)c.aux * a.pstride + col;
+#pragma unroll
+                    for (int i = 0; i < EPL; i += 4)
+                        *reinterpret_cast<float4 *>(pp + i) = make_float4(acc[i], acc[i + 1], acc[i + 2], acc[i + 3]);
+                    if (kScalar && gl == 0)
+                        a.partials[(int64_t)c.aux * a.pstride + a.ld] = csum;
+                }
+            } else if (MODE == kFwd) {
                 if (g == 0)
-                    r2 = epilogue_fwd<T, FUSED>(a, S.row_base + c.row, deg, col, col_ok, acc);
+                    r2 = epilogue_fwd<T, EPL>(a, zrow, c.len, col, col_ok, acc, self);
             } else if (MODE == kAdjNode) {
-                epilogue_adj_node<T, G>(a, c.row, deg, col, col_ok, acc, g == 0);
+                epilogue_adj_node<T, EPL, G>(a, c.row, c.len, col, col_ok, acc, self, g == 0);
             } else {
-                epilogue_adj_edge<T, G>(a, c.row, deg, col, col_ok, acc, csum, g == 0);
+                epilogue_adj_edge<T, EPL, G>(a, c.row, c.len, col, col_ok, acc, csum, self, g == 0);
             }
         }
     } else {
         const int item = b * (kBlock / G) + (int)(threadIdx.x / G);
-        const bool valid = item < S.n_small;
-        int row = 0, start = 0, deg = 0;
-        if (valid) {
-            row = S.small_rows[item];
-            start = S.ptr[row];
-            deg = S.ptr[row + 1] - start;
+        const bool valid = item < Sd.n_small;
+        Item it{0, 0, 0, 0};
+        if (valid)
+            it = Sd.small[item];
+        const int zrow = Sd.row_base + it.row;
+        typename S::Raw self{};
+        if (valid && col_ok) {
+            const int64_t srow = (MODE == kFwd && FUSED) ? (int64_t)it.aux : (int64_t)zrow;
+            self = S::load(src + srow * a.ld + col);
         }
-        const int gbase = g * G;
         if (use_scale)
-            gather_group<T, G, true, kScalar>(nb, sc, a.cvec, start, deg, src, a.ld, col, col_ok, gl, gbase, acc,
-                                              csum);
+            gather_group<T, EPL, G, true, kScalar>(nb, sc, a.cvec, it.start, it.len, src, a.ld, col, col_ok, gl,
+                                                   g * G, acc, csum);
         else
-            gather_group<T, G, false, kScalar>(nb, sc, a.cvec, start, deg, src, a.ld, col, col_ok, gl, gbase, acc,
-                                               csum);
+            gather_group<T, EPL, G, false, kScalar>(nb, sc, a.cvec, it.start, it.len, src, a.ld, col, col_ok, gl,
+                                                    g * G, acc, csum);
         if (MODE == kFwd) {
             if (valid)
-                r2 = epilogue_fwd<T, FUSED>(a, S.row_base + row, deg, col, col_ok, acc);
+                r2 = epilogue_fwd<T, EPL>(a, zrow, it.len, col, col_ok, acc, self);
         } else if (MODE == kAdjNode) {
-            epilogue_adj_node<T, G>(a, row, deg, col, col_ok, acc, valid);
+            epilogue_adj_node<T, EPL, G>(a, it.row, it.len, col, col_ok, acc, self, valid);
         } else {
             csum = group_sum<G>(csum);
-            epilogue_adj_edge<T, G>(a, row, deg, col, col_ok, acc, csum, valid);
+            epilogue_adj_edge<T, EPL, G>(a, it.row, it.len, col, col_ok, acc, csum, self, valid);
         }
     }
-    (void)Q;
     if (MODE == kFwd)
         block_resid(a, r2);
 }
@@ -514,9 +573,10 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
 // row adds the row's partial slots in slot order (group g takes slots
 // g, g+Q, ...; groups combined by the xor butterfly), then applies the
 // row's epilogue.
-template <typename T, int G, int MODE, bool FUSED>
+template <typename T, int EPL, int G, int MODE, bool FUSED>
 __global__ __launch_bounds__(kBlock) void k_finalize(GatherArgs a)
 {
+    using S = Slice<T, EPL>;
     constexpr int Q = kWave / G;
     int b = blockIdx.x;
     const int per_panel = a.nb_split[0] + a.nb_split[1];
@@ -526,30 +586,39 @@ __global__ __launch_bounds__(kBlock) void k_finalize(GatherArgs a)
     const int wave = threadIdx.x / kWave;
     const int g = lane / G;
     const int gl = lane % G;
-    const int col = panel * a.dp + gl * 8;
-    const bool col_ok = gl * 8 < a.dp;
+    const int col = panel * a.dp + gl * EPL;
+    const bool col_ok = gl * EPL < a.dp;
     int side = 0;
     if (b >= a.nb_split[0]) {
         b -= a.nb_split[0];
         side = 1;
     }
-    const DevSide &S = a.side[side];
+    const DevSide &Sd = a.side[side];
     const int item = b * kWavesPerBlock + wave;
-    const bool valid = item < S.n_splits;
-    float acc[8];
-    zero8(acc);
+    float acc[EPL];
+    zero(acc);
     float csum = 0.0f;
     double r2 = 0.0;
-    const bool active = valid && !((MODE == kAdjNode && side != 1) || (MODE == kAdjEdge && side != 0));
-    if (active) {
-        const Split sp = S.splits[item];
+    const bool active = item < Sd.n_splits && !((MODE == kAdjNode && side != 1) || (MODE == kAdjEdge && side != 0));
+    if (active) {   // uniform over the wavefront
+        const Split sp = Sd.splits[item];
+        const int zrow = Sd.row_base + sp.row;
+        typename S::Raw self{};
+        if (col_ok) {
+            const int64_t srow = (MODE == kFwd && FUSED) ? (int64_t)a.rowmap[zrow] : (int64_t)zrow;
+            self = S::load(static_cast<const T *>(a.src) + srow * a.ld + col);
+        }
         for (int k = g; k < sp.n_slots; k += Q) {
             const float *pp = a.partials + (int64_t)(sp.first_slot + k) * a.pstride;
             if (col_ok) {
-                const float4 x0 = reinterpret_cast<const float4 *>(pp + col)[0];
-                const float4 x1 = reinterpret_cast<const float4 *>(pp + col)[1];
-                acc[0] += x0.x; acc[1] += x0.y; acc[2] += x0.z; acc[3] += x0.w;
-                acc[4] += x1.x; acc[5] += x1.y; acc[6] += x1.z; acc[7] += x1.w;
+#pragma unroll
+                for (int i = 0; i < EPL; i += 4) {
+                    const float4 x = *reinterpret_cast<const float4 *>(pp + col + i);
+                    acc[i] += x.x;
+                    acc[i + 1] += x.y;
+                    acc[i + 2] += x.z;
+                    acc[i + 3] += x.w;
+                }
             }
             if (MODE == kAdjEdge && gl == 0)
                 csum += pp[a.ld];
@@ -557,34 +626,44 @@ __global__ __launch_bounds__(kBlock) void k_finalize(GatherArgs a)
 #pragma unroll
         for (int off = G; off < kWave; off <<= 1) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
+            for (int i = 0; i < EPL; ++i)
                 acc[i] += __shfl_xor(acc[i], off, kWave);
             if (MODE == kAdjEdge)
                 csum += __shfl_xor(csum, off, kWave);
         }
         if (MODE == kFwd) {
             if (g == 0)
-                r2 = epilogue_fwd<T, FUSED>(a, S.row_base + sp.row, sp.deg, col, col_ok, acc);
+                r2 = epilogue_fwd<T, EPL>(a, zrow, sp.deg, col, col_ok, acc, self);
         } else if (MODE == kAdjNode) {
-            epilogue_adj_node<T, G>(a, sp.row, sp.deg, col, col_ok, acc, g == 0);
+            epilogue_adj_node<T, EPL, G>(a, sp.row, sp.deg, col, col_ok, acc, self, g == 0);
         } else {
-            epilogue_adj_edge<T, G>(a, sp.row, sp.deg, col, col_ok, acc, csum, g == 0);
+            epilogue_adj_edge<T, EPL, G>(a, sp.row, sp.deg, col, col_ok, acc, csum, self, g == 0);
         }
     }
     if (MODE == kFwd)
         block_resid(a, r2);
 }
 
-// Single block: out[0] = sqrt(sum of n partials), summed in a fixed order.
-__global__ __launch_bounds__(kBlock) void k_resid_final(const double *part, int64_t n, double *out)
+// Single block of 1024 threads: out[0] = sqrt(sum of n partials).  Thread t
+// sums partials t, t + 1024, ... into four interleaved accumulators (so four
+// loads are in flight), then a tree over the block; the order is fixed.
+constexpr int kFinalThreads = 1024;
+__global__ __launch_bounds__(kFinalThreads) void k_resid_final(const double *__restrict__ part, int64_t n,
+                                                               double *__restrict__ out)
 {
-    __shared__ double s[kBlock];
-    double x = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += kBlock)
-        x += part[i];
-    s[threadIdx.x] = x;
+    __shared__ double s[kFinalThreads];
+    double x[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t i = threadIdx.x;
+    for (; i + 3 * kFinalThreads < n; i += 4 * kFinalThreads) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            x[k] += part[i + k * kFinalThreads];
+    }
+    for (int k = 0; i < n; i += kFinalThreads, ++k)
+        x[k] += part[i];
+    s[threadIdx.x] = (x[0] + x[1]) + (x[2] + x[3]);
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
+    for (int w = kFinalThreads / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
             s[threadIdx.x] += s[threadIdx.x + w];
         __syncthreads();
@@ -597,25 +676,26 @@ __global__ __launch_bounds__(kBlock) void k_resid_final(const double *part, int6
 // projection and its reverse
 // ---------------------------------------------------------------------------
 
-// z_fine[u] = z_coarse[rowmap[u]], 8 elements per thread
-template <typename T>
+// z_fine[u] = z_coarse[rowmap[u]], one lane slice per thread
+template <typename T, int EPL>
 __global__ __launch_bounds__(kBlock) void k_project(const T *__restrict__ zc, T *__restrict__ zf,
                                                     const int32_t *__restrict__ rowmap, int64_t rows, int d)
 {
-    const int per_row = d / 8;
+    using S = Slice<T, EPL>;
+    const int per_row = d / EPL;
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= rows * per_row)
         return;
     const int64_t u = t / per_row;
-    const int c = (int)(t - u * per_row) * 8;
-    float v[8];
-    Row8<T>::load(zc + (int64_t)rowmap[u] * d + c, v);
-    Row8<T>::store(zf + u * d + c, v);
+    const int c = (int)(t - u * per_row) * EPL;
+    float v[EPL];
+    S::unpack(S::load(zc + (int64_t)rowmap[u] * d + c), v);
+    S::store(zf + u * d + c, v);
 }
 
 // g_coarse[r] = sum of g_fine[u] over rowmap(u) = r, ascending u.  One
 // wavefront per coarse row (gather_wave over the inverse map).
-template <typename T, int G>
+template <typename T, int EPL, int G>
 __global__ __launch_bounds__(kBlock) void k_project_adj(const T *__restrict__ gf, T *__restrict__ gc,
                                                         const int32_t *__restrict__ inv_ptr,
                                                         const int32_t *__restrict__ inv_idx, int64_t rows_c, int d)
@@ -623,17 +703,17 @@ __global__ __launch_bounds__(kBlock) void k_project_adj(const T *__restrict__ gf
     const int64_t r = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
     const int g = lane / G, gl = lane % G;
-    const int col = gl * 8;
+    const int col = gl * EPL;
     const bool col_ok = col < d;
     if (r >= rows_c)
         return;  // uniform per wavefront
-    float acc[8];
-    zero8(acc);
+    float acc[EPL];
+    zero(acc);
     float cs = 0.0f;
     const int start = inv_ptr[r], len = inv_ptr[r + 1] - start;
-    gather_wave<T, G, false, false>(inv_idx, nullptr, nullptr, start, len, gf, d, col, col_ok, lane, g, acc, cs);
+    gather_wave<T, EPL, G, false, false>(inv_idx, nullptr, nullptr, start, len, gf, d, col, col_ok, lane, g, acc, cs);
     if (g == 0 && col_ok)
-        Row8<T>::store(gc + r * d + col, acc);
+        Slice<T, EPL>::store(gc + r * d + col, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -757,7 +837,7 @@ hnv_status dev_recompute_reciprocals(hnv_plan *p, int level, void *stream)
     return dev_check("reciprocal kernels");
 }
 
-static GatherArgs base_args(hnv_plan *p, LevelPlan &L, int G, int dp, int panels)
+static GatherArgs base_args(hnv_plan *p, LevelPlan &L, int G, int dp)
 {
     GatherArgs a{};
     a.side[0] = L.side[0];
@@ -780,7 +860,6 @@ static GatherArgs base_args(hnv_plan *p, LevelPlan &L, int G, int dp, int panels
     a.rowmap = L.rowmap;
     a.partials = p->partials;
     a.pstride = p->pstride;
-    (void)panels;
     return a;
 }
 
@@ -828,36 +907,45 @@ struct ProfScope {
     }
 };
 
-template <typename T, int G, int MODE, bool FUSED>
+template <typename T, int EPL, int G, int MODE, bool FUSED>
 static void launch_pair(const GatherArgs &a, int panels, hipStream_t s, ProfScope *ps)
 {
     const unsigned main_blocks = (unsigned)a.blocks_per_panel * panels;
     if (ps)
         ps->begin();
     if (main_blocks)
-        k_gather<T, G, MODE, FUSED><<<main_blocks, kBlock, 0, s>>>(a);
+        k_gather<T, EPL, G, MODE, FUSED><<<main_blocks, kBlock, 0, s>>>(a);
     if (ps)
         ps->end();
     const unsigned fin_blocks = (unsigned)(a.nb_split[0] + a.nb_split[1]) * panels;
     if (fin_blocks) {
         GatherArgs f = a;
         f.resid_offset = a.resid_offset + (int32_t)main_blocks;
-        k_finalize<T, G, MODE, FUSED><<<fin_blocks, kBlock, 0, s>>>(f);
+        k_finalize<T, EPL, G, MODE, FUSED><<<fin_blocks, kBlock, 0, s>>>(f);
     }
 }
 
+// Instantiated lane layouts: BF16 always 8 elements per lane; FP32 4 per
+// lane, or 8 when a row slice is wider than 256 elements (then G = 64).
 template <typename T, int MODE, bool FUSED>
-static hnv_status dispatch_g(int G, const GatherArgs &a, int panels, hipStream_t s, ProfScope *ps)
+static hnv_status dispatch_g(int G, int EPL, const GatherArgs &a, int panels, hipStream_t s, ProfScope *ps)
 {
-    switch (G) {
-    case 1: launch_pair<T, 1, MODE, FUSED>(a, panels, s, ps); break;
-    case 2: launch_pair<T, 2, MODE, FUSED>(a, panels, s, ps); break;
-    case 4: launch_pair<T, 4, MODE, FUSED>(a, panels, s, ps); break;
-    case 8: launch_pair<T, 8, MODE, FUSED>(a, panels, s, ps); break;
-    case 16: launch_pair<T, 16, MODE, FUSED>(a, panels, s, ps); break;
-    case 32: launch_pair<T, 32, MODE, FUSED>(a, panels, s, ps); break;
-    case 64: launch_pair<T, 64, MODE, FUSED>(a, panels, s, ps); break;
-    default: return fail(HNV_EUNSUPPORTED, "lane group width");
+    constexpr int E = 16 / (int)sizeof(T);
+    if (EPL == E) {
+        switch (G) {
+        case 1: launch_pair<T, E, 1, MODE, FUSED>(a, panels, s, ps); break;
+        case 2: launch_pair<T, E, 2, MODE, FUSED>(a, panels, s, ps); break;
+        case 4: launch_pair<T, E, 4, MODE, FUSED>(a, panels, s, ps); break;
+        case 8: launch_pair<T, E, 8, MODE, FUSED>(a, panels, s, ps); break;
+        case 16: launch_pair<T, E, 16, MODE, FUSED>(a, panels, s, ps); break;
+        case 32: launch_pair<T, E, 32, MODE, FUSED>(a, panels, s, ps); break;
+        case 64: launch_pair<T, E, 64, MODE, FUSED>(a, panels, s, ps); break;
+        default: return fail(HNV_EUNSUPPORTED, "lane group width");
+        }
+    } else if (E == 4 && EPL == 8 && G == 64) {
+        launch_pair<T, 8, 64, MODE, FUSED>(a, panels, s, ps);
+    } else {
+        return fail(HNV_EUNSUPPORTED, "lane layout");
     }
     return dev_check("sweep kernels");
 }
@@ -867,26 +955,27 @@ static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, 
                             double *resid_out, hipStream_t s)
 {
     LevelPlan &L = p->lv[level];
-    GatherArgs a = base_args(p, L, p->g_fwd, p->dp, p->panels);
+    GatherArgs a = base_args(p, L, p->g_fwd, p->dp);
     a.omega = omega;
     a.src = src;
     a.dst = dst;
     a.resid = resid_out ? p->resid_part : nullptr;
     a.resid_offset = 0;
     ProfScope ps{p, s, fused ? HNV_PROF_FUSED : HNV_PROF_SWEEP, level};
+    const int G = p->g_fwd, E = p->epl_fwd;
     hnv_status st;
     if (p->dtype == HNV_F32)
-        st = fused ? dispatch_g<float, kFwd, true>(p->g_fwd, a, p->panels, s, &ps)
-                   : dispatch_g<float, kFwd, false>(p->g_fwd, a, p->panels, s, &ps);
+        st = fused ? dispatch_g<float, kFwd, true>(G, E, a, p->panels, s, &ps)
+                   : dispatch_g<float, kFwd, false>(G, E, a, p->panels, s, &ps);
     else
-        st = fused ? dispatch_g<bf16_t, kFwd, true>(p->g_fwd, a, p->panels, s, &ps)
-                   : dispatch_g<bf16_t, kFwd, false>(p->g_fwd, a, p->panels, s, &ps);
+        st = fused ? dispatch_g<bf16_t, kFwd, true>(G, E, a, p->panels, s, &ps)
+                   : dispatch_g<bf16_t, kFwd, false>(G, E, a, p->panels, s, &ps);
     if (st != HNV_OK)
         return st;
     if (resid_out) {
         int64_t mb = 0, fb = 0;
         forward_geometry(p, L, &mb, &fb);
-        k_resid_final<<<1, kBlock, 0, s>>>(p->resid_part, mb + fb, resid_out);
+        k_resid_final<<<1, kFinalThreads, 0, s>>>(p->resid_part, mb + fb, resid_out);
         return dev_check("residual kernel");
     }
     return HNV_OK;
@@ -895,16 +984,22 @@ static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, 
 static hnv_status run_project(hnv_plan *p, int level, const void *zc, void *zf, hipStream_t s)
 {
     LevelPlan &L = p->lv[level];
-    const int64_t threads = L.rows * (p->d / 8);
+    const int E = p->epl_full;
+    const int64_t threads = L.rows * (p->d / E);
     if (threads == 0)
         return HNV_OK;
-    if (p->dtype == HNV_F32)
-        k_project<float><<<grid1d(threads, kBlock), kBlock, 0, s>>>(static_cast<const float *>(zc),
-                                                                    static_cast<float *>(zf), L.rowmap, L.rows, p->d);
-    else
-        k_project<bf16_t><<<grid1d(threads, kBlock), kBlock, 0, s>>>(static_cast<const bf16_t *>(zc),
-                                                                     static_cast<bf16_t *>(zf), L.rowmap, L.rows,
-                                                                     p->d);
+    const unsigned grid = grid1d(threads, kBlock);
+    if (p->dtype == HNV_F32) {
+        if (E == 4)
+            k_project<float, 4><<<grid, kBlock, 0, s>>>(static_cast<const float *>(zc), static_cast<float *>(zf),
+                                                        L.rowmap, L.rows, p->d);
+        else
+            k_project<float, 8><<<grid, kBlock, 0, s>>>(static_cast<const float *>(zc), static_cast<float *>(zf),
+                                                        L.rowmap, L.rows, p->d);
+    } else {
+        k_project<bf16_t, 8><<<grid, kBlock, 0, s>>>(static_cast<const bf16_t *>(zc), static_cast<bf16_t *>(zf),
+                                                     L.rowmap, L.rows, p->d);
+    }
     return dev_check("projection kernel");
 }
 
@@ -1114,8 +1209,8 @@ extern "C" hnv_status hnv_sweep_adjoint(hnv_plan *plan, int level, const void *g
         return fail(HNV_EINVAL, "omega must be in (0, 1] for the reverse sweep");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     LevelPlan &L = plan->lv[level];
-    const int G = plan->g_full;
-    GatherArgs a = base_args(plan, L, G, plan->d, 1);
+    const int G = plan->g_full, E = plan->epl_full;
+    GatherArgs a = base_args(plan, L, G, plan->d);
     a.omega = omega;
     a.src = g_in;
     a.dst = g_out;
@@ -1128,13 +1223,13 @@ extern "C" hnv_status hnv_sweep_adjoint(hnv_plan *plan, int level, const void *g
     const GatherArgs an = only_side(a, 1), ae = only_side(a, 0);
     ProfScope pn{plan, s, HNV_PROF_ADJ_NODE, level}, pe{plan, s, HNV_PROF_ADJ_EDGE, level};
     if (plan->dtype == HNV_F32) {
-        if ((st = dispatch_g<float, kAdjNode, false>(G, an, 1, s, &pn)) != HNV_OK)
+        if ((st = dispatch_g<float, kAdjNode, false>(G, E, an, 1, s, &pn)) != HNV_OK)
             return st;
-        st = dispatch_g<float, kAdjEdge, false>(G, ae, 1, s, &pe);
+        st = dispatch_g<float, kAdjEdge, false>(G, E, ae, 1, s, &pe);
     } else {
-        if ((st = dispatch_g<bf16_t, kAdjNode, false>(G, an, 1, s, &pn)) != HNV_OK)
+        if ((st = dispatch_g<bf16_t, kAdjNode, false>(G, E, an, 1, s, &pn)) != HNV_OK)
             return st;
-        st = dispatch_g<bf16_t, kAdjEdge, false>(G, ae, 1, s, &pe);
+        st = dispatch_g<bf16_t, kAdjEdge, false>(G, E, ae, 1, s, &pe);
     }
     return st;
 }
@@ -1152,27 +1247,31 @@ extern "C" hnv_status hnv_project_adjoint(hnv_plan *plan, int level, const void 
     if (!g_fine || !g_coarse || !aligned16(g_fine) || !aligned16(g_coarse))
         return fail(HNV_EINVAL, "g_fine / g_coarse NULL or not 16-byte aligned");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const int G = plan->g_full;
+    const int G = plan->g_full, E = plan->epl_full;
     const unsigned blocks = grid1d(L.rows_coarse, kWavesPerBlock);
     if (blocks == 0)
         return HNV_OK;
-#define HNV_PADJ(TT, GG)                                                                                         \
-    k_project_adj<TT, GG><<<blocks, kBlock, 0, s>>>(static_cast<const TT *>(g_fine), static_cast<TT *>(g_coarse), \
-                                                    L.inv_ptr, L.inv_idx, L.rows_coarse, plan->d)
-#define HNV_PADJ_G(TT)                                                                                           \
+#define HNV_PADJ(TT, EE, GG)                                                                                     \
+    k_project_adj<TT, EE, GG><<<blocks, kBlock, 0, s>>>(static_cast<const TT *>(g_fine), static_cast<TT *>(g_coarse), \
+                                                        L.inv_ptr, L.inv_idx, L.rows_coarse, plan->d)
+#define HNV_PADJ_G(TT, EE)                                                                                       \
     switch (G) {                                                                                                 \
-    case 1: HNV_PADJ(TT, 1); break;                                                                              \
-    case 2: HNV_PADJ(TT, 2); break;                                                                              \
-    case 4: HNV_PADJ(TT, 4); break;                                                                              \
-    case 8: HNV_PADJ(TT, 8); break;                                                                              \
-    case 16: HNV_PADJ(TT, 16); break;                                                                            \
-    case 32: HNV_PADJ(TT, 32); break;                                                                            \
-    default: HNV_PADJ(TT, 64); break;                                                                            \
+    case 1: HNV_PADJ(TT, EE, 1); break;                                                                          \
+    case 2: HNV_PADJ(TT, EE, 2); break;                                                                          \
+    case 4: HNV_PADJ(TT, EE, 4); break;                                                                          \
+    case 8: HNV_PADJ(TT, EE, 8); break;                                                                          \
+    case 16: HNV_PADJ(TT, EE, 16); break;                                                                        \
+    case 32: HNV_PADJ(TT, EE, 32); break;                                                                        \
+    default: HNV_PADJ(TT, EE, 64); break;                                                                        \
     }
     if (plan->dtype == HNV_F32) {
-        HNV_PADJ_G(float)
+        if (E == 4) {
+            HNV_PADJ_G(float, 4)
+        } else {
+            HNV_PADJ(float, 8, 64);
+        }
     } else {
-        HNV_PADJ_G(bf16_t)
+        HNV_PADJ_G(bf16_t, 8)
     }
 #undef HNV_PADJ_G
 #undef HNV_PADJ
