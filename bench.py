@@ -37,11 +37,19 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def sweep_alg_bytes(n_nodes, n_edges, nnz, d, s):
-    """Compulsory HBM bytes of one forward sweep at one level: every row read
-    and written once (2*d*s), its offset (8) and reciprocal (4), both
-    directions of the incidence (2 * 4 B per star edge) and one weight per
-    hyperedge (4)."""
+def sweep_stream_bytes(n_nodes, n_edges, nnz, d, s):
+    """Bytes one forward sweep at one level moves when gathered rows are not
+    reused from cache (the gather algorithm's traffic): per star edge and
+    direction one neighbour row (d*s) and its index (4); per row its own value
+    read and the result written (2*d*s), its offset (8) and reciprocal (4);
+    one weight per hyperedge (4)."""
+    rows = n_nodes + n_edges
+    return 2 * nnz * (d * s + 4) + rows * (2 * d * s + 12) + 4 * n_edges
+
+
+def sweep_min_bytes(n_nodes, n_edges, nnz, d, s):
+    """Compulsory bytes of one forward sweep: every row read and written once,
+    offsets, reciprocals, both index directions and the weights."""
     rows = n_nodes + n_edges
     return rows * (2 * d * s + 12) + 8 * nnz + 4 * n_edges
 
@@ -86,13 +94,14 @@ def run_gpu(H, torch, hier, cfg, dtype, zc_f32, steps, warmup):
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1000.0 / steps
     s = 2 if dtype == "bf16" else 4
-    launches, alg_bytes, kernel_ms = 0, 0.0, 0.0
+    launches, alg_bytes, min_bytes, kernel_ms = 0, 0.0, 0.0, 0.0
     for lvl in range(plan.n_levels):
         n, ms = plan.profile_read(0, lvl)        # HNV_PROF_SWEEP
         nv, ne, nz = plan.level_info(lvl)
         launches += n
         kernel_ms += ms
-        alg_bytes += n * sweep_alg_bytes(nv, ne, nz, cfg.d, s)
+        alg_bytes += n * sweep_stream_bytes(nv, ne, nz, cfg.d, s)
+        min_bytes += n * sweep_min_bytes(nv, ne, nz, cfg.d, s)
     nf, msf = plan.profile_read(1, -1)           # HNV_PROF_FUSED
     plan.set_profiling(False)
     updates = sum(sweeps[l] * 2 * hier.levels[l].nnz * cfg.d for l in range(hier.n_levels))
@@ -103,11 +112,68 @@ def run_gpu(H, torch, hier, cfg, dtype, zc_f32, steps, warmup):
         "sweep_kernel_launches": launches,
         "sweep_kernel_avg_ms": kernel_ms / max(launches, 1),
         "sweep_alg_bytes_per_launch": alg_bytes / max(launches, 1),
+        "sweep_min_bytes_per_launch": min_bytes / max(launches, 1),
         "fused_kernel_avg_ms": msf / max(nf, 1),
         "kernel_ms_per_step": (kernel_ms + msf) / steps,
         "final_residual": float(res[sum(sweeps) - 1].item()),
     }
-    return result, out.float(), plan
+    return result, (out if dtype == "f32" else H.cast(out, "f32")), plan
+
+
+def run_differentiable(H, torch, steps, warmup):
+    """Differentiable refinement workload (500,000 nodes, 300,000 hyperedges,
+    truncated Zipf(2.1) sizes on [2, 1000], d = 128 FP32): projection of a
+    learnable coarse embedding + 10 sweeps with learnable per-hyperedge
+    log-weights, cross-entropy of a linear 16-class head on 10% of the
+    nodes, forward + backward with a checkpoint every 5 sweeps."""
+    import numpy as np
+    from synth import CONFIGS, coarsest_embedding, labelled_nodes, linear_head, make_hypergraph
+    cfg = CONFIGS["c4"]
+    hg = make_hypergraph(cfg)
+    hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, cfg.levels)
+    plan = H.Plan(hier, cfg.d, "f32")
+    K = cfg.sweeps[0]
+    zc = torch.as_tensor(coarsest_embedding(cfg, hier.levels[1].rows, cfg.d)).cuda().requires_grad_(True)
+    theta = torch.zeros(hg.n_edges, device="cuda", requires_grad=True)
+    nodes, labels = labelled_nodes(cfg)
+    W, b = linear_head(cfg)
+    nodes_t, labels_t = torch.as_tensor(nodes).cuda(), torch.as_tensor(labels).cuda()
+    W_t, b_t = torch.as_tensor(W).cuda(), torch.as_tensor(b).cuda()
+
+    def step():
+        zc.grad = None
+        theta.grad = None
+        z0 = H.refine_level(zc, theta, plan, 0, K, 0.5, from_coarse=True, ckpt_every=cfg.checkpoint_every)
+        loss = torch.nn.functional.cross_entropy(z0[nodes_t] @ W_t.t() + b_t, labels_t)
+        loss.backward()
+        return loss
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        loss = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / steps
+    nf, tf = plan.profile_read(0, 0)
+    nfu, tfu = plan.profile_read(1, 0)
+    nn_, tn = plan.profile_read(2, 0)
+    ne_, te = plan.profile_read(3, 0)
+    plan.set_profiling(False)
+    nnz = hg.nnz
+    recompute = K - (K + cfg.checkpoint_every - 1) // cfg.checkpoint_every
+    sweeps_total = K + recompute + K          # forward, recomputed, reverse
+    return {"workload": "c4: 500000 nodes, 300000 hyperedges, sizes ('zipf', 2.1, 1000), d=128 FP32, "
+                        "projection + 10 sweeps, learnable log-weights and coarse embedding, CE head on 10% "
+                        "of nodes, checkpoint every 5",
+            "ms_per_step": ms, "loss": float(loss.item()),
+            "sweeps_per_step": {"forward": K, "recomputed": recompute, "reverse": K},
+            "updates_per_s": sweeps_total * 2 * nnz * cfg.d / (ms / 1000.0),
+            "forward_sweep_avg_ms": (tf + tfu) / max(nf + nfu, 1),
+            "reverse_sweep_avg_ms": (tn + te) / max(steps * K, 1),
+            "reverse_node_rows_avg_ms": tn / max(nn_, 1), "reverse_hyperedge_rows_avg_ms": te / max(ne_, 1)}
 
 
 def cpu_baseline(O, hg, cfg, budget_s=12.0, max_sweeps=20):
@@ -156,6 +222,8 @@ def main():
     ap.add_argument("--dtypes", default="bf16,f32", help="storage types to time; the first is the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--no-differentiable", action="store_true",
+                    help="skip the forward + backward (reverse-mode) leg")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -206,8 +274,8 @@ def main():
         torch.cuda.empty_cache()
 
     head = results[dtypes[0]]
-    s = 2 if dtypes[0] == "bf16" else 4
     achieved = head["sweep_alg_bytes_per_launch"] / (head["sweep_kernel_avg_ms"] / 1000.0) / 1e9
+    compulsory = head["sweep_min_bytes_per_launch"] / (head["sweep_kernel_avg_ms"] / 1000.0) / 1e9
     traffic = read_counters() if dtypes[0] == "bf16" and args.config == "c3" else None
     line = {
         "metric": METRIC,
@@ -233,16 +301,25 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"forward sweep (k_gather, {dtypes[0]}, non-fused), "
                                f"{head['sweep_kernel_launches']} launches",
+                     "alg_bytes": "gather stream: 2*nnz*(d*s+4) + rows*(2*d*s+12) + 4*n_edges per sweep",
                      "alg_bytes_per_launch": head["sweep_alg_bytes_per_launch"],
-                     "avg_launch_ms": head["sweep_kernel_avg_ms"]},
+                     "avg_launch_ms": head["sweep_kernel_avg_ms"],
+                     "compulsory_bytes_per_launch": head["sweep_min_bytes_per_launch"],
+                     "compulsory_GBps": compulsory, "compulsory_frac": compulsory / HBM_PEAK_GBS},
     }
     for dt in dtypes[1:]:
         r = results[dt]
         line[dt] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
                     "sweep_kernel_avg_ms": r["sweep_kernel_avg_ms"],
-                    "achieved_GBps": r["sweep_alg_bytes_per_launch"] / (r["sweep_kernel_avg_ms"] / 1000.0) / 1e9}
+                    "achieved_GBps": r["sweep_alg_bytes_per_launch"] / (r["sweep_kernel_avg_ms"] / 1000.0) / 1e9,
+                    "frac": r["sweep_alg_bytes_per_launch"] / (r["sweep_kernel_avg_ms"] / 1000.0) / 1e9
+                    / HBM_PEAK_GBS}
         line[f"{dtypes[0]}_over_{dt}"] = head["value"] / r["value"]
     line["fused_projection_sweep_avg_ms"] = head["fused_kernel_avg_ms"]
+    if not args.no_differentiable and args.config == "c3":
+        t = time.perf_counter()
+        line["differentiable"] = run_differentiable(H, torch, max(2, args.steps // 2), 1)
+        log(f"differentiable ({time.perf_counter() - t:.1f} s): {line['differentiable']}")
 
     need_oracle = not (args.no_cpu_baseline and args.no_oracle_check)
     if need_oracle:

@@ -402,7 +402,7 @@ struct Carver {
 
 void forward_geometry(const hnv_plan *p, const LevelPlan &L, int64_t *main_blocks, int64_t *fin_blocks)
 {
-    const int64_t rows_per_block = kBlock / p->g_fwd;
+    const int64_t rows_per_block = kRowsPerGroup * kBlock / p->g_fwd;
     int64_t per_panel = 0;
     for (int s = 0; s < 2; ++s)
         per_panel += blocks_for(L.n_chunks[s], kWavesPerBlock) + blocks_for(L.n_small[s], rows_per_block);
@@ -461,6 +461,8 @@ static void carve(hnv_plan *p, std::vector<HostLevel> &hl, char *base)
     p->zbuf = c.take<char>(p->lv[0].rows * p->d * (int64_t)elem);
     p->partials = c.take<float>(p->max_slots * p->pstride);
     p->resid_part = c.take<double>(p->max_resid_blocks);
+    p->resid_stage_len = blocks_for(p->max_resid_blocks, kBlock * 8) + 1;
+    p->resid_stage = c.take<double>(2 * p->resid_stage_len);
     p->cscratch = c.take<float>(max_nodes);
     p->resid_tmp = c.take<double>(1);
     p->ws_bytes = (c.off + 255) & ~size_t(255);

@@ -13,6 +13,10 @@ namespace hnv {
 constexpr int kBlock = 256;   // threads per workgroup (4 wavefronts of 64)
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = kBlock / kWave;
+#ifndef HNV_ROWS_PER_GROUP
+#define HNV_ROWS_PER_GROUP 1
+#endif
+constexpr int kRowsPerGroup = HNV_ROWS_PER_GROUP;   // lane-group tier rows a group handles in turn
 
 // A work item: `len` neighbours of side-local row `row` starting at `start`
 // in the side's neighbour array.
@@ -78,6 +82,8 @@ struct hnv_plan {
     int64_t max_slots = 0;
     double *resid_part = nullptr;    // [max_resid_blocks]
     int64_t max_resid_blocks = 0;
+    double *resid_stage = nullptr;   // [2 x resid_stage_len] partial sums of the residual stages
+    int64_t resid_stage_len = 0;
     float *cscratch = nullptr;       // [max n_nodes] per-node scalar of the reverse sweep
     double *resid_tmp = nullptr;     // [1]
     int panels = 1;                  // column passes of a forward sweep

@@ -538,31 +538,37 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
             }
         }
     } else {
-        const int item = b * (kBlock / G) + (int)(threadIdx.x / G);
-        const bool valid = item < Sd.n_small;
-        Item it{0, 0, 0, 0};
-        if (valid)
-            it = Sd.small[item];
-        const int zrow = Sd.row_base + it.row;
-        typename S::Raw self{};
-        if (valid && col_ok) {
-            const int64_t srow = (MODE == kFwd && FUSED) ? (int64_t)it.aux : (int64_t)zrow;
-            self = S::load(src + srow * a.ld + col);
-        }
-        if (use_scale)
-            gather_group<T, EPL, G, true, kScalar>(nb, sc, a.cvec, it.start, it.len, src, a.ld, col, col_ok, gl,
-                                                   g * G, acc, csum);
-        else
-            gather_group<T, EPL, G, false, kScalar>(nb, sc, a.cvec, it.start, it.len, src, a.ld, col, col_ok, gl,
-                                                    g * G, acc, csum);
-        if (MODE == kFwd) {
+        for (int rr = 0; rr < kRowsPerGroup; ++rr) {
+            const int item = (b * kRowsPerGroup + rr) * (kBlock / G) + (int)(threadIdx.x / G);
+            const bool valid = item < Sd.n_small;
+            Item it{0, 0, 0, 0};
             if (valid)
-                r2 = epilogue_fwd<T, EPL>(a, zrow, it.len, col, col_ok, acc, self);
-        } else if (MODE == kAdjNode) {
-            epilogue_adj_node<T, EPL, G>(a, it.row, it.len, col, col_ok, acc, self, valid);
-        } else {
-            csum = group_sum<G>(csum);
-            epilogue_adj_edge<T, EPL, G>(a, it.row, it.len, col, col_ok, acc, csum, self, valid);
+                it = Sd.small[item];
+            const int zrow = Sd.row_base + it.row;
+            typename S::Raw self{};
+            if (valid && col_ok) {
+                const int64_t srow = (MODE == kFwd && FUSED) ? (int64_t)it.aux : (int64_t)zrow;
+                self = S::load(src + srow * a.ld + col);
+            }
+            if (rr > 0) {
+                zero(acc);
+                csum = 0.0f;
+            }
+            if (use_scale)
+                gather_group<T, EPL, G, true, kScalar>(nb, sc, a.cvec, it.start, it.len, src, a.ld, col, col_ok, gl,
+                                                       g * G, acc, csum);
+            else
+                gather_group<T, EPL, G, false, kScalar>(nb, sc, a.cvec, it.start, it.len, src, a.ld, col, col_ok, gl,
+                                                        g * G, acc, csum);
+            if (MODE == kFwd) {
+                if (valid)
+                    r2 += epilogue_fwd<T, EPL>(a, zrow, it.len, col, col_ok, acc, self);
+            } else if (MODE == kAdjNode) {
+                epilogue_adj_node<T, EPL, G>(a, it.row, it.len, col, col_ok, acc, self, valid);
+            } else {
+                csum = group_sum<G>(csum);
+                epilogue_adj_edge<T, EPL, G>(a, it.row, it.len, col, col_ok, acc, csum, self, valid);
+            }
         }
     }
     if (MODE == kFwd)
@@ -644,32 +650,31 @@ __global__ __launch_bounds__(kBlock) void k_finalize(GatherArgs a)
         block_resid(a, r2);
 }
 
-// Single block of 1024 threads: out[0] = sqrt(sum of n partials).  Thread t
-// sums partials t, t + 1024, ... into four interleaved accumulators (so four
-// loads are in flight), then a tree over the block; the order is fixed.
-constexpr int kFinalThreads = 1024;
-__global__ __launch_bounds__(kFinalThreads) void k_resid_final(const double *__restrict__ part, int64_t n,
-                                                               double *__restrict__ out)
+// Residual reduction, one stage: block b sums partials [b*2048, (b+1)*2048)
+// (each thread eight strided loads, all in flight at once, added in a fixed
+// order, then a tree over the block) and writes one value; the last stage
+// (a single block) writes the square root.
+constexpr int kResidPer = kBlock * 8;
+__global__ __launch_bounds__(kBlock) void k_resid_stage(const double *__restrict__ part, int64_t n,
+                                                        double *__restrict__ out, int final_sqrt)
 {
-    __shared__ double s[kFinalThreads];
-    double x[4] = {0.0, 0.0, 0.0, 0.0};
-    int64_t i = threadIdx.x;
-    for (; i + 3 * kFinalThreads < n; i += 4 * kFinalThreads) {
+    __shared__ double s[kBlock];
+    const int64_t base = (int64_t)blockIdx.x * kResidPer + threadIdx.x;
+    double x[8];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            x[k] += part[i + k * kFinalThreads];
+    for (int k = 0; k < 8; ++k) {
+        const int64_t i = base + (int64_t)k * kBlock;
+        x[k] = (i < n) ? part[i] : 0.0;
     }
-    for (int k = 0; i < n; i += kFinalThreads, ++k)
-        x[k] += part[i];
-    s[threadIdx.x] = (x[0] + x[1]) + (x[2] + x[3]);
+    s[threadIdx.x] = ((x[0] + x[1]) + (x[2] + x[3])) + ((x[4] + x[5]) + (x[6] + x[7]));
     __syncthreads();
-    for (int w = kFinalThreads / 2; w > 0; w >>= 1) {
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
             s[threadIdx.x] += s[threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        out[0] = sqrt(s[0]);
+        out[blockIdx.x] = final_sqrt ? sqrt(s[0]) : s[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -844,7 +849,7 @@ static GatherArgs base_args(hnv_plan *p, LevelPlan &L, int G, int dp)
     a.side[1] = L.side[1];
     if (L.unit_w)
         a.side[1].wn = nullptr;  // unit weights: skip the per-edge multiply
-    const int rows_per_block = kBlock / G;
+    const int rows_per_block = kRowsPerGroup * kBlock / G;
     int32_t per_panel = 0;
     for (int s = 0; s < 2; ++s) {
         a.nb_chunk[s] = (int32_t)blocks_for(L.n_chunks[s], kWavesPerBlock);
@@ -975,8 +980,19 @@ static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, 
     if (resid_out) {
         int64_t mb = 0, fb = 0;
         forward_geometry(p, L, &mb, &fb);
-        k_resid_final<<<1, kFinalThreads, 0, s>>>(p->resid_part, mb + fb, resid_out);
-        return dev_check("residual kernel");
+        const double *in = p->resid_part;
+        int64_t n = mb + fb;
+        int which = 0;
+        while (n > kResidPer) {
+            const int64_t nb = blocks_for(n, kResidPer);
+            double *out = p->resid_stage + which * p->resid_stage_len;
+            k_resid_stage<<<(unsigned)nb, kBlock, 0, s>>>(in, n, out, 0);
+            in = out;
+            n = nb;
+            which ^= 1;
+        }
+        k_resid_stage<<<1, kBlock, 0, s>>>(in, n, resid_out, 1);
+        return dev_check("residual kernels");
     }
     return HNV_OK;
 }
