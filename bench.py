@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "refinement nnz·d updates/s and % HBM roofline, BF16 vs FP32 sweep, 1 MI355X"
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_sweep_c3_bf16.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_sweep_zipf2m_bf16.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2103_09660_amd", "csrc", "hnv_kernels.hip")
 
 
@@ -128,7 +128,7 @@ def run_differentiable(H, torch, steps, warmup):
     nodes, forward + backward with a checkpoint every 5 sweeps."""
     import numpy as np
     from synth import CONFIGS, coarsest_embedding, labelled_nodes, linear_head, make_hypergraph
-    cfg = CONFIGS["c4"]
+    cfg = CONFIGS["grad-500k"]
     hg = make_hypergraph(cfg)
     hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, cfg.levels)
     plan = H.Plan(hier, cfg.d, "f32")
@@ -165,7 +165,7 @@ def run_differentiable(H, torch, steps, warmup):
     nnz = hg.nnz
     recompute = K - (K + cfg.checkpoint_every - 1) // cfg.checkpoint_every
     sweeps_total = K + recompute + K          # forward, recomputed, reverse
-    return {"workload": "c4: 500000 nodes, 300000 hyperedges, sizes ('zipf', 2.1, 1000), d=128 FP32, "
+    return {"workload": "grad-500k: 500000 nodes, 300000 hyperedges, sizes ('zipf', 2.1, 1000), d=128 FP32, "
                         "projection + 10 sweeps, learnable log-weights and coarse embedding, CE head on 10% "
                         "of nodes, checkpoint every 5",
             "ms_per_step": ms, "loss": float(loss.item()),
@@ -218,7 +218,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="zipf-2m", choices=["tiny-2k", "hub-200k", "zipf-2m"])
     ap.add_argument("--dtypes", default="bf16,f32", help="storage types to time; the first is the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
@@ -276,7 +276,7 @@ def main():
     head = results[dtypes[0]]
     achieved = head["sweep_alg_bytes_per_launch"] / (head["sweep_kernel_avg_ms"] / 1000.0) / 1e9
     compulsory = head["sweep_min_bytes_per_launch"] / (head["sweep_kernel_avg_ms"] / 1000.0) / 1e9
-    traffic = read_counters() if dtypes[0] == "bf16" and args.config == "c3" else None
+    traffic = read_counters() if dtypes[0] == "bf16" and args.config == "zipf-2m" else None
     line = {
         "metric": METRIC,
         "value": head["value"],
@@ -316,7 +316,7 @@ def main():
                     / HBM_PEAK_GBS}
         line[f"{dtypes[0]}_over_{dt}"] = head["value"] / r["value"]
     line["fused_projection_sweep_avg_ms"] = head["fused_kernel_avg_ms"]
-    if not args.no_differentiable and args.config == "c3":
+    if not args.no_differentiable and args.config == "zipf-2m":
         t = time.perf_counter()
         line["differentiable"] = run_differentiable(H, torch, max(2, args.steps // 2), 1)
         log(f"differentiable ({time.perf_counter() - t:.1f} s): {line['differentiable']}")

@@ -15,8 +15,8 @@ A hypergraph is returned in canonical form: each hyperedge row lists its
 members in ascending order without duplicates (hyperedges are sets of nodes,
 Section 1), offsets are int64 and member ids int32.
 
-Seeds for a named configuration Ck: structure k, weights 100+k, embeddings
-200+k, labels / head / cotangent 300+k.
+Each named configuration carries a seed k: structure k, weights 100+k,
+embeddings 200+k, labels / head / cotangent 300+k.
 """
 from __future__ import annotations
 
@@ -51,21 +51,21 @@ def _sweeps(levels: int, k: int) -> tuple:
 
 CONFIGS = {
     # tiny: Citeseer-scale (Table 1), correctness only
-    "c1": Config("c1", 1, 2_000, 1_000, ("uniform", 2, 8), ("uniform",), ("unit",),
-                 32, 3, _sweeps(3, 10)),
+    "tiny-2k": Config("tiny-2k", 1, 2_000, 1_000, ("uniform", 2, 8), ("uniform",), ("unit",),
+                      32, 3, _sweeps(3, 10)),
     # medium, hub-heavy node side (DBLP / Wordnet scale, Tables 1 and 3)
-    "c2": Config("c2", 2, 200_000, 100_000, ("zipf", 2.1, 500), ("popularity", 1.5),
-                 ("uniform", 0.5, 2.0), 64, 5, _sweeps(5, 20)),
+    "hub-200k": Config("hub-200k", 2, 200_000, 100_000, ("zipf", 2.1, 500), ("popularity", 1.5),
+                       ("uniform", 0.5, 2.0), 64, 5, _sweeps(5, 20)),
     # BF16 vs FP32 refinement at millions of rows
-    "c3": Config("c3", 3, 2_000_000, 1_500_000, ("zipf", 2.1, 2_000), ("uniform",), ("unit",),
-                 128, 8, _sweeps(8, 20), dtypes=("bf16", "f32")),
+    "zipf-2m": Config("zipf-2m", 3, 2_000_000, 1_500_000, ("zipf", 2.1, 2_000), ("uniform",), ("unit",),
+                      128, 8, _sweeps(8, 20), dtypes=("bf16", "f32")),
     # differentiable refinement: one coarsening step, 10 sweeps at the finest level only
-    "c4": Config("c4", 4, 500_000, 300_000, ("zipf", 2.1, 1_000), ("uniform",), ("unit",),
-                 128, 1, (10, 0), adjoint_sweeps=10, label_frac=0.10, n_classes=16,
-                 checkpoint_every=5),
+    "grad-500k": Config("grad-500k", 4, 500_000, 300_000, ("zipf", 2.1, 1_000), ("uniform",), ("unit",),
+                        128, 1, (10, 0), adjoint_sweeps=10, label_frac=0.10, n_classes=16,
+                        checkpoint_every=5),
     # Friendster-scale BF16 refinement + adjoint (Table 3 / Table 5 scale)
-    "c5": Config("c5", 5, 8_000_000, 10_000_000, ("zipf", 2.0, 5_000), ("uniform",), ("unit",),
-                 128, 10, _sweeps(10, 20), dtypes=("bf16",), adjoint_sweeps=5),
+    "zipf-8m": Config("zipf-8m", 5, 8_000_000, 10_000_000, ("zipf", 2.0, 5_000), ("uniform",), ("unit",),
+                      128, 10, _sweeps(10, 20), dtypes=("bf16",), adjoint_sweeps=5),
 }
 
 

@@ -120,34 +120,34 @@ def _refine_case(O, H, cfg_name, dtype, cols=None, n_levels=None, sweeps=None):
     return got[:, c], ref, _host(res), np.array(ref_res), done, K
 
 
-def test_refine_c1_f32(oracle_mod, H):
-    got, ref, res, ref_res, done, K = _refine_case(oracle_mod, H, "c1", "f32")
-    _assert_close(got, ref, F32_TOL, "c1 refine f32")
+def test_refine_tiny2k_f32(oracle_mod, H):
+    got, ref, res, ref_res, done, K = _refine_case(oracle_mod, H, "tiny-2k", "f32")
+    _assert_close(got, ref, F32_TOL, "tiny-2k refine f32")
     assert list(done) == list(K)
     np.testing.assert_allclose(res[: len(ref_res)], ref_res, rtol=1e-5)
 
 
-def test_refine_c1_bf16(oracle_mod, H):
-    got, ref, _, _, _, _ = _refine_case(oracle_mod, H, "c1", "bf16")
-    _assert_close(got, ref, BF16_TOL, "c1 refine bf16")
+def test_refine_tiny2k_bf16(oracle_mod, H):
+    got, ref, _, _, _, _ = _refine_case(oracle_mod, H, "tiny-2k", "bf16")
+    _assert_close(got, ref, BF16_TOL, "tiny-2k refine bf16")
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_refine_c2(oracle_mod, H, dtype):
+def test_refine_hub200k(oracle_mod, H, dtype):
     """Medium hub-heavy config, all columns."""
-    got, ref, res, ref_res, _, _ = _refine_case(oracle_mod, H, "c2", dtype)
-    _assert_close(got, ref, F32_TOL if dtype == "f32" else BF16_TOL, f"c2 refine {dtype}")
+    got, ref, res, ref_res, _, _ = _refine_case(oracle_mod, H, "hub-200k", dtype)
+    _assert_close(got, ref, F32_TOL if dtype == "f32" else BF16_TOL, f"hub-200k refine {dtype}")
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "f32"])
-def test_refine_c3_full_size_column_sample(oracle_mod, H, dtype):
+def test_refine_zipf2m_full_size_column_sample(oracle_mod, H, dtype):
     """The benchmark workload (2M nodes, 1.5M hyperedges, 8 coarsening
     steps, 20 sweeps per level, d = 128, default launch options) on the GPU;
     the oracle computes two of the 128 columns over every row (columns are
     independent under the sweep and the projection)."""
     cols = [0, 77]
-    got, ref, res, ref_res, done, K = _refine_case(oracle_mod, H, "c3", dtype, cols=cols)
-    _assert_close(got, ref, F32_TOL if dtype == "f32" else BF16_TOL, f"c3 refine {dtype} cols {cols}")
+    got, ref, res, ref_res, done, K = _refine_case(oracle_mod, H, "zipf-2m", dtype, cols=cols)
+    _assert_close(got, ref, F32_TOL if dtype == "f32" else BF16_TOL, f"zipf-2m refine {dtype} cols {cols}")
 
 
 def test_refine_zero_and_tol(oracle_mod, H):
@@ -232,7 +232,7 @@ def test_sweep_adjoint(oracle_mod, H, seed, small_max, chunk, d):
     _assert_close(dth.cpu().numpy(), ref_dw * w_host, GRAD_TOL, "dtheta")
 
 
-def test_refine_function_c4_shape_small(oracle_mod, H):
+def test_refine_function_grad500k_shape_small(oracle_mod, H):
     """Differentiable refinement (projection + 10 sweeps with learnable
     log-weights, checkpoint every 5) on a reduced instance of the
     differentiable-refinement workload; loss = CE of a linear head."""

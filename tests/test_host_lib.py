@@ -97,7 +97,7 @@ def test_coarsening_bit_exact_random(oracle_mod, H, seed):
         lv = c.coarse
 
 
-@pytest.mark.parametrize("name", ["c1", "c2"])
+@pytest.mark.parametrize("name", ["tiny-2k", "hub-200k"])
 def test_coarsening_bit_exact_configs(oracle_mod, H, name):
     from tests.cases import both_hierarchies
     cfg = CONFIGS[name]

@@ -106,7 +106,7 @@ def test_coarsen_invariants_random(oracle_mod, seed):
 
 def test_coarsen_invariants_c1(oracle_mod):
     O = oracle_mod
-    cfg = CONFIGS["c1"]
+    cfg = CONFIGS["tiny-2k"]
     hg = make_hypergraph(cfg)
     levels, maps = O.build_hierarchy(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, cfg.levels)
     for lvl, c in enumerate(maps):
