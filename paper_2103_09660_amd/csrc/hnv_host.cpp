@@ -6,11 +6,15 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <memory>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "hnv_internal.h"
@@ -49,6 +53,42 @@ void lane_layout(int cols, int elem, int *lanes, int *elems_per_lane)
 static constexpr int64_t kMaxI32 = std::numeric_limits<int32_t>::max();
 static constexpr int kDefaultSmallMax = 64;
 static constexpr int kDefaultChunk = 512;
+
+// ---------------------------------------------------------------------------
+// host parallelism
+// ---------------------------------------------------------------------------
+
+// Threads for host loops: OMP_NUM_THREADS if set, else the hardware count.
+static int host_threads()
+{
+    int t = 0;
+    if (const char *e = std::getenv("OMP_NUM_THREADS"))
+        t = std::atoi(e);
+    if (t <= 0)
+        t = (int)std::thread::hardware_concurrency();
+    return std::max(1, std::min(t, 64));
+}
+
+// f(begin, end) over [0, n) in contiguous static chunks.  Every loop run this
+// way writes disjoint outputs (or commutative atomic counts), so results do
+// not depend on the thread count.
+template <class F>
+static void parallel_for(int64_t n, F f, int64_t grain = 1 << 15)
+{
+    const int T = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), n / grain));
+    if (T <= 1) {
+        f((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> pool;
+    pool.reserve(T);
+    for (int t = 0; t < T; ++t) {
+        const int64_t b = n * t / T, e = n * (t + 1) / T;
+        pool.emplace_back([=, &f] { f(b, e); });
+    }
+    for (auto &th : pool)
+        th.join();
+}
 
 // ---------------------------------------------------------------------------
 // validation
@@ -96,19 +136,53 @@ static hnv_status validate(const hnv_level *lv, bool full = true)
 // coarsening
 // ---------------------------------------------------------------------------
 
-// node -> incident hyperedges, ascending hyperedge id, via a counting pass
+// node -> incident hyperedges, each list in ascending hyperedge id.  The
+// hyperedges are cut into T contiguous ranges of about equal incidence
+// count; thread t counts its range's incidences per node, the counts are
+// turned into per-(node, range) offsets, and thread t fills its slots.
+// Ranges are in hyperedge order, so every list comes out ascending without
+// atomics or sorting, whatever the thread count.
 static void incidence_by_node(const hnv_level *lv, std::vector<int32_t> &nptr, std::vector<int32_t> &nedge)
 {
-    nptr.assign(lv->n_nodes + 1, 0);
-    for (int64_t j = 0; j < lv->nnz; ++j)
-        ++nptr[lv->edge_idx[j] + 1];
-    for (int64_t v = 0; v < lv->n_nodes; ++v)
+    const int64_t nV = lv->n_nodes, nE = lv->n_edges, nnz = lv->nnz;
+    const int T = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), nnz / (1 << 16)));
+    std::vector<int64_t> cut(T + 1, nE);
+    cut[0] = 0;
+    for (int t = 1; t < T; ++t)
+        cut[t] = std::upper_bound(lv->edge_ptr, lv->edge_ptr + nE + 1, nnz * t / T) - lv->edge_ptr - 1;
+    std::vector<int32_t> cnt((size_t)T * nV, 0);
+    parallel_for(T, [&](int64_t tb, int64_t te) {
+        for (int64_t t = tb; t < te; ++t) {
+            int32_t *c = cnt.data() + t * nV;
+            for (int64_t j = lv->edge_ptr[cut[t]]; j < lv->edge_ptr[cut[t + 1]]; ++j)
+                ++c[lv->edge_idx[j]];
+        }
+    }, 1);
+    nptr.assign(nV + 1, 0);
+    parallel_for(nV, [&](int64_t vb, int64_t ve) {
+        for (int64_t v = vb; v < ve; ++v) {
+            int32_t run = 0;
+            for (int t = 0; t < T; ++t) {
+                const int32_t c = cnt[(size_t)t * nV + v];
+                cnt[(size_t)t * nV + v] = run;
+                run += c;
+            }
+            nptr[v + 1] = run;
+        }
+    });
+    for (int64_t v = 0; v < nV; ++v)
         nptr[v + 1] += nptr[v];
-    nedge.resize(lv->nnz);
-    std::vector<int32_t> cursor(nptr.begin(), nptr.end() - 1);
-    for (int64_t e = 0; e < lv->n_edges; ++e)
-        for (int64_t j = lv->edge_ptr[e]; j < lv->edge_ptr[e + 1]; ++j)
-            nedge[cursor[lv->edge_idx[j]]++] = (int32_t)e;
+    nedge.resize(nnz);
+    parallel_for(T, [&](int64_t tb, int64_t te) {
+        for (int64_t t = tb; t < te; ++t) {
+            int32_t *c = cnt.data() + t * nV;
+            for (int64_t e = cut[t]; e < cut[t + 1]; ++e)
+                for (int64_t j = lv->edge_ptr[e]; j < lv->edge_ptr[e + 1]; ++j) {
+                    const int32_t v = lv->edge_idx[j];
+                    nedge[nptr[v] + c[v]++] = (int32_t)e;
+                }
+        }
+    }, 1);
 }
 
 static hnv_status coarsen(const hnv_level *lv, int32_t *node_rep, int32_t *edge_rep, int64_t *c_ptr,
@@ -123,21 +197,23 @@ static hnv_status coarsen(const hnv_level *lv, int32_t *node_rep, int32_t *edge_
     auto wt = [&](int32_t e) { return lv->edge_w ? lv->edge_w[e] : 1.0f; };
     auto size = [&](int32_t e) { return lv->edge_ptr[e + 1] - lv->edge_ptr[e]; };
     std::vector<int32_t> choice(nV, -1);
-    for (int64_t v = 0; v < nV; ++v) {
-        int32_t best = -1;
-        for (int32_t j = nptr[v]; j < nptr[v + 1]; ++j) {
-            const int32_t e = nedge[j];
-            if (best < 0) {
-                best = e;
-                continue;
+    parallel_for(nV, [&](int64_t vb, int64_t ve) {
+        for (int64_t v = vb; v < ve; ++v) {
+            int32_t best = -1;
+            for (int32_t j = nptr[v]; j < nptr[v + 1]; ++j) {
+                const int32_t e = nedge[j];
+                if (best < 0) {
+                    best = e;
+                    continue;
+                }
+                const float we = wt(e), wb = wt(best);
+                const int64_t se = size(e), sb = size(best);
+                if (we > wb || (we == wb && (se < sb || (se == sb && e < best))))
+                    best = e;
             }
-            const float we = wt(e), wb = wt(best);
-            const int64_t se = size(e), sb = size(best);
-            if (we > wb || (we == wb && (se < sb || (se == sb && e < best))))
-                best = e;
+            choice[v] = best;
         }
-        choice[v] = best;
-    }
+    });
 
     // Coarse node numbering: first appearance of a group in ascending v.
     std::vector<int32_t> group_of_edge(nE, -1);
@@ -160,27 +236,39 @@ static hnv_status coarsen(const hnv_level *lv, int32_t *node_rep, int32_t *edge_
     for (int64_t e = 0; e < nE; ++e)
         edge_rep[e] = (chosen_count[e] == size((int32_t)e)) ? -1 : kept++;
 
-    // Coarse member sets through rep(), ascending, repeats collapsed.
-    int64_t pos = 0;
+    // Coarse member sets through rep(), ascending, repeats collapsed: map and
+    // sort every kept row in place in a scratch copy, count its distinct
+    // members, then lay the rows out in order.
+    std::vector<int32_t> mapped(lv->nnz);
+    std::vector<int64_t> distinct(nE, 0);
+    parallel_for(nE, [&](int64_t eb, int64_t ee) {
+        for (int64_t e = eb; e < ee; ++e) {
+            if (edge_rep[e] < 0)
+                continue;
+            const int64_t a = lv->edge_ptr[e], b = lv->edge_ptr[e + 1];
+            for (int64_t j = a; j < b; ++j)
+                mapped[j] = node_rep[lv->edge_idx[j]];
+            std::sort(mapped.begin() + a, mapped.begin() + b);
+            distinct[e] = std::unique(mapped.begin() + a, mapped.begin() + b) - (mapped.begin() + a);
+        }
+    }, 1 << 12);
     c_ptr[0] = 0;
-    std::vector<int32_t> buf;
-    for (int64_t e = 0; e < nE; ++e) {
-        if (edge_rep[e] < 0)
-            continue;
-        buf.assign(lv->edge_idx + lv->edge_ptr[e], lv->edge_idx + lv->edge_ptr[e + 1]);
-        for (auto &v : buf)
-            v = node_rep[v];
-        std::sort(buf.begin(), buf.end());
-        const auto end = std::unique(buf.begin(), buf.end());
-        for (auto it = buf.begin(); it != end; ++it)
-            c_idx[pos++] = *it;
-        c_ptr[edge_rep[e] + 1] = pos;
-        if (c_w)
-            c_w[edge_rep[e]] = wt((int32_t)e);
-    }
+    for (int64_t e = 0; e < nE; ++e)
+        if (edge_rep[e] >= 0)
+            c_ptr[edge_rep[e] + 1] = c_ptr[edge_rep[e]] + distinct[e];
+    parallel_for(nE, [&](int64_t eb, int64_t ee) {
+        for (int64_t e = eb; e < ee; ++e) {
+            if (edge_rep[e] < 0)
+                continue;
+            std::copy(mapped.begin() + lv->edge_ptr[e], mapped.begin() + lv->edge_ptr[e] + distinct[e],
+                      c_idx + c_ptr[edge_rep[e]]);
+            if (c_w)
+                c_w[edge_rep[e]] = wt((int32_t)e);
+        }
+    }, 1 << 12);
     *c_nodes = n_groups;
     *c_edges = kept;
-    *c_nnz = pos;
+    *c_nnz = c_ptr[kept];
     return HNV_OK;
 }
 
@@ -331,11 +419,15 @@ static void build_level(const hnv_level *levels, const hnv_map *maps, int n_leve
     for (int64_t e = 0; e <= h.nE; ++e)
         h.ptr[0][e] = (int32_t)L.edge_ptr[e];
     // side 1: node rows -> incident hyperedges (Z row = n_nodes + e)
-    h.ptr[1].assign(h.nV + 1, 0);
-    for (int64_t j = 0; j < h.nnz; ++j)
-        ++h.ptr[1][L.edge_idx[j] + 1];
-    for (int64_t v = 0; v < h.nV; ++v)
-        h.ptr[1][v + 1] += h.ptr[1][v];
+    if (with_arrays) {
+        incidence_by_node(&L, h.ptr[1], h.idx[1]);
+    } else {
+        h.ptr[1].assign(h.nV + 1, 0);
+        for (int64_t j = 0; j < h.nnz; ++j)
+            ++h.ptr[1][L.edge_idx[j] + 1];
+        for (int64_t v = 0; v < h.nV; ++v)
+            h.ptr[1][v + 1] += h.ptr[1][v];
+    }
 
     int32_t slots = 0;
     tier_side(h.ptr[0].data(), (int32_t)h.nE, small_max, o.chunk, &slots, h.tier[0]);
@@ -345,13 +437,10 @@ static void build_level(const hnv_level *levels, const hnv_map *maps, int n_leve
         return;
 
     h.idx[0].assign(L.edge_idx, L.edge_idx + h.nnz);
-    h.idx[1].resize(h.nnz);
-    {
-        std::vector<int32_t> cursor(h.ptr[1].begin(), h.ptr[1].end() - 1);
-        for (int64_t e = 0; e < h.nE; ++e)
-            for (int64_t j = L.edge_ptr[e]; j < L.edge_ptr[e + 1]; ++j)
-                h.idx[1][cursor[L.edge_idx[j]]++] = (int32_t)(h.nV + e);
-    }
+    parallel_for(h.nnz, [&](int64_t b, int64_t e) {
+        for (int64_t j = b; j < e; ++j)
+            h.idx[1][j] += (int32_t)h.nV;
+    });
     if (!h.has_coarse)
         return;
 
@@ -368,8 +457,10 @@ static void build_level(const hnv_level *levels, const hnv_map *maps, int n_leve
     }
     for (int s = 0; s < 2; ++s) {
         h.cidx[s].resize(h.nnz);
-        for (int64_t j = 0; j < h.nnz; ++j)
-            h.cidx[s][j] = h.rowmap[h.idx[s][j]];
+        parallel_for(h.nnz, [&](int64_t b, int64_t e) {
+            for (int64_t j = b; j < e; ++j)
+                h.cidx[s][j] = h.rowmap[h.idx[s][j]];
+        });
         // lane-group items carry the coarse row their own value comes from
         const int64_t base = (s == 0) ? h.nV : 0;
         for (auto &it : h.tier[s].small)

@@ -132,11 +132,12 @@ def _fill_members(rng: np.random.Generator, sizes: np.ndarray, n_nodes: int, dra
     while active.size:
         lens = sizes[active]
         pos = _segment_positions(ptr[active], lens)
-        sub = idx[pos]
         rid = np.repeat(np.arange(active.size, dtype=np.int64), lens)
-        order = np.argsort(rid * np.int64(n_nodes) + sub, kind="stable")
-        sub = sub[order]
-        same = (sub[1:] == sub[:-1]) & (rid[1:] == rid[:-1])
+        key = rid * np.int64(n_nodes) + idx[pos]
+        key.sort()                       # sorts within each row (rows are key-disjoint)
+        sub = key - rid * np.int64(n_nodes)
+        same = sub[1:] == sub[:-1]
+        same &= rid[1:] == rid[:-1]
         dpos = np.nonzero(same)[0] + 1
         if dpos.size:
             sub[dpos] = draw(dpos.size)
