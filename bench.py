@@ -117,7 +117,7 @@ def run_gpu(H, torch, hier, cfg, dtype, zc_f32, steps, warmup):
         "kernel_ms_per_step": (kernel_ms + msf) / steps,
         "final_residual": float(res[sum(sweeps) - 1].item()),
     }
-    return result, (out if dtype == "f32" else H.cast(out, "f32")), plan
+    return result, out, plan
 
 
 def run_differentiable(H, torch, steps, warmup):
@@ -176,25 +176,71 @@ def run_differentiable(H, torch, steps, warmup):
             "reverse_node_rows_avg_ms": tn / max(nn_, 1), "reverse_hyperedge_rows_avg_ms": te / max(ne_, 1)}
 
 
-def cpu_baseline(O, hg, cfg, budget_s=12.0, max_sweeps=20):
+def run_reverse(H, torch, plan, z_start, cfg, steps):
+    """Reverse sweeps at the finest level (the zipf-8m workload's adjoint
+    leg): cfg.adjoint_sweeps forward sweeps from z_start are kept, then as
+    many reverse sweeps run from a seeded N(0,1) cotangent, accumulating the
+    hyperedge-weight gradient.  Timed over `steps` repetitions."""
+    from synth import cotangent
+    K = cfg.adjoint_sweeps
+    states = [z_start]
+    for _ in range(K):
+        states.append(plan.sweep(0, states[-1], 0.5))
+    rows = plan.rows(0)
+    g0 = torch.empty((rows, cfg.d), dtype=plan.torch_dtype, device="cuda")
+    chunk = 1 << 20
+    for r0 in range(0, rows, chunk):     # seeded cotangent, generated in row blocks
+        r1 = min(rows, r0 + chunk)
+        gen = torch.Generator(device="cuda").manual_seed(300 + cfg.seed + r0)
+        g0[r0:r1] = torch.randn((r1 - r0, cfg.d), generator=gen, device="cuda").to(plan.torch_dtype)
+    n_edges = plan.level_info(0)[1]
+    dw = torch.zeros(n_edges, dtype=torch.float32, device="cuda")
+    bufs = [plan.empty(0), plan.empty(0)]
+
+    def once():
+        g = g0
+        for i in range(K, 0, -1):
+            out = bufs[i % 2]
+            g = plan.sweep_adjoint(0, g, states[i - 1], states[i], 0.5, dw=dw, out=out)
+        return g
+
+    once()
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        once()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / steps
+    nn_, tn = plan.profile_read(2, 0)
+    ne_, te = plan.profile_read(3, 0)
+    plan.set_profiling(False)
+    nnz = plan.level_info(0)[2]
+    return {"reverse_sweeps": K, "ms_per_pass": ms,
+            "updates_per_s": K * 2 * nnz * cfg.d / (ms / 1000.0),
+            "reverse_node_rows_avg_ms": tn / max(nn_, 1), "reverse_hyperedge_rows_avg_ms": te / max(ne_, 1)}
+
+
+def cpu_baseline(O, hg, cfg, budget_s=12.0, max_sweeps=20, d=None):
     """The oracle as it stands, on a bounded sample of the same workload:
     Jacobi sweeps of the finest level at full width d (FP64), repeated until
     about budget_s seconds of work.  The oracle's time does not depend on the
     values, so the start embedding is a tiled seeded block."""
     import numpy as np
     from synth import coarsest_embedding
+    d = cfg.d if d is None else d
     lv = O.Level(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w)
-    z = np.resize(coarsest_embedding(cfg, 4096, cfg.d).astype(np.float64), (lv.rows, cfg.d))
+    z = np.resize(coarsest_embedding(cfg, 4096, d).astype(np.float64), (lv.rows, d))
     n, t = 0, 0.0
     while n < max_sweeps and t < budget_s:
         t0 = time.perf_counter()
         z = O.sweep(lv, z, 0.5)
         t += time.perf_counter() - t0
         n += 1
-    upd = n * 2 * lv.nnz * cfg.d
+    upd = n * 2 * lv.nnz * d
     return {"value": upd / t, "unit": "updates/s", "cores": O.threads(), "kind": "oracle",
             "sample": f"{n} Jacobi sweeps of the finest level ({lv.n_nodes} nodes, {lv.n_edges} hyperedges, "
-                      f"{lv.nnz} incidences) at d={cfg.d}, FP64, {t:.1f} s"}
+                      f"{lv.nnz} incidences) at d={d}, FP64, {t:.1f} s"}
 
 
 def oracle_errors(O, hg, cfg, zc, outs, cols=(0, 77)):
@@ -205,7 +251,7 @@ def oracle_errors(O, hg, cfg, zc, outs, cols=(0, 77)):
     ref = O.refine(levels, maps, np.ascontiguousarray(zc[:, list(cols)], dtype=np.float64), list(cfg.sweeps), 0.5)
     errs = {}
     for name, out in outs.items():
-        got = out[:, list(cols)].cpu().numpy().astype(np.float64)
+        got = out[:, list(cols)].float().cpu().numpy().astype(np.float64)
         errs[name] = {"rel_fro": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
                       "max_abs": float(np.max(np.abs(got - ref))),
                       "max_abs_rel": float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))),
@@ -218,8 +264,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="zipf-2m", choices=["tiny-2k", "hub-200k", "zipf-2m"])
-    ap.add_argument("--dtypes", default="bf16,f32", help="storage types to time; the first is the headline")
+    ap.add_argument("--config", default="zipf-2m", choices=["tiny-2k", "hub-200k", "zipf-2m", "zipf-8m"])
+    ap.add_argument("--dtypes", default=None,
+                    help="storage types to time, the first is the headline (default bf16,f32; bf16 for zipf-8m)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--no-differentiable", action="store_true",
@@ -263,14 +310,23 @@ def main():
     zc = coarsest_embedding(cfg, hier.levels[-1].rows, cfg.d)
     zc_dev = torch.as_tensor(zc).cuda()
 
-    dtypes = [d for d in args.dtypes.split(",") if d]
+    large = args.config == "zipf-8m"
+    dtypes = [d for d in (args.dtypes or ("bf16" if large else "bf16,f32")).split(",") if d]
     results, outs = {}, {}
+    reverse = None
     for dt in dtypes:
+        t = time.perf_counter()
         r, out, plan = run_gpu(H, torch, hier, cfg, dt, zc_dev, args.steps, args.warmup)
         results[dt], outs[dt] = r, out
         log(f"{dt}: {r['ms_per_step']:.2f} ms/step, {r['value'] / 1e12:.3f} T updates/s, sweep kernel "
-            f"{r['sweep_kernel_avg_ms'] * 1e3:.1f} us avg over {r['sweep_kernel_launches']} launches")
+            f"{r['sweep_kernel_avg_ms'] * 1e3:.1f} us avg over {r['sweep_kernel_launches']} launches "
+            f"({time.perf_counter() - t:.1f} s with plan creation)")
+        if large and dt == dtypes[0] and cfg.adjoint_sweeps:
+            reverse = run_reverse(H, torch, plan, out, cfg, max(2, args.steps // 2))
+            log(f"reverse: {reverse}")
         del plan
+        if large:
+            outs[dt] = None
         torch.cuda.empty_cache()
 
     head = results[dtypes[0]]
@@ -316,6 +372,8 @@ def main():
                     / HBM_PEAK_GBS}
         line[f"{dtypes[0]}_over_{dt}"] = head["value"] / r["value"]
     line["fused_projection_sweep_avg_ms"] = head["fused_kernel_avg_ms"]
+    if reverse is not None:
+        line["reverse"] = reverse
     if not args.no_differentiable and args.config == "zipf-2m":
         t = time.perf_counter()
         line["differentiable"] = run_differentiable(H, torch, max(2, args.steps // 2), 1)
@@ -324,12 +382,12 @@ def main():
     need_oracle = not (args.no_cpu_baseline and args.no_oracle_check)
     if need_oracle:
         from oracle import oracle as O
-        if not args.no_oracle_check:
+        if not args.no_oracle_check and not large:
             t = time.perf_counter()
             line["error_vs_fp64_oracle"] = oracle_errors(O, hg, cfg, zc, outs)
             log(f"oracle check ({time.perf_counter() - t:.1f} s): {line['error_vs_fp64_oracle']}")
         if not args.no_cpu_baseline:
-            line["cpu_baseline"] = cpu_baseline(O, hg, cfg)
+            line["cpu_baseline"] = cpu_baseline(O, hg, cfg, d=16 if large else None)
             log(f"cpu baseline: {line['cpu_baseline']}")
     print(json.dumps(line), flush=True)
 

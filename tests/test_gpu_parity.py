@@ -263,3 +263,90 @@ def test_refine_function_grad500k_shape_small(oracle_mod, H):
     assert abs(loss.item() - ref_loss) <= 1e-5 * abs(ref_loss)
     _assert_close(_host(zc_t.grad), ref_gc, GRAD_TOL, "dL/dZc")
     _assert_close(th_t.grad.cpu().numpy(), ref_dw * w_dev, GRAD_TOL, "dL/dtheta")
+
+
+# ---------------------------------------------------------------------------
+# full-size instances of the large workloads
+# ---------------------------------------------------------------------------
+
+def test_zipf8m_two_levels_forward_and_reverse(oracle_mod, H):
+    """Friendster-scale hypergraph (8M nodes, 10M hyperedges, 125.5M
+    incidences), BF16 storage: the full-size finest level and its first
+    coarsening, 4 sweeps per level (the finest level's first one fused with
+    the projection), then 3 reverse sweeps at the finest level.  The oracle
+    computes two of the 128 columns; the reverse pass uses a cotangent that
+    is zero outside those columns, so the hyperedge-weight gradient (a sum
+    over columns) is exactly the two-column one."""
+    import torch
+    O = oracle_mod
+    cfg = CONFIGS["zipf-8m"]
+    hg = make_hypergraph(cfg)
+    levels, maps, hier = both_hierarchies(O, H, hg, 1)
+    cols = [5, 101]
+    d = cfg.d
+    plan = H.Plan(hier, d, "bf16")
+    zc = coarsest_embedding(cfg, levels[1].rows, d, columns=cols)
+    zfull = torch.zeros((levels[1].rows, d), dtype=torch.bfloat16, device="cuda")
+    zfull[:, cols] = _dev(zc, "bf16")
+    zin = _bf16_round(zc)
+    K = [4, 4]
+    out, _, _ = plan.refine(zfull, K, 0.5)
+    ref = O.refine(levels, maps, zin, K, 0.5)
+    _assert_close(_host(out[:, cols].contiguous()), ref, BF16_TOL, "zipf-8m forward")
+    # reverse: 3 sweeps at level 0 from the refined state, seeded cotangent on two columns
+    y0 = out
+    states = [y0]
+    for _ in range(3):
+        states.append(plan.sweep(0, states[-1], 0.5))
+    gsmall = np.random.default_rng(305).standard_normal((levels[0].rows, 2)).astype(np.float32)
+    gd = torch.zeros((levels[0].rows, d), dtype=torch.bfloat16, device="cuda")
+    gd[:, cols] = _dev(gsmall, "bf16")
+    dw = torch.zeros(levels[0].n_edges, dtype=torch.float32, device="cuda")
+    for i in range(3, 0, -1):
+        gd = plan.sweep_adjoint(0, gd, states[i - 1], states[i], 0.5, dw=dw)
+    # oracle on the same two columns, from its own FP64 forward state
+    ys = [ref]
+    for _ in range(3):
+        ys.append(O.sweep(levels[0], ys[-1], 0.5))
+    go = _bf16_round(gsmall)
+    dwo = np.zeros(levels[0].n_edges)
+    for i in range(3, 0, -1):
+        go, dwi = O.sweep_vjp(levels[0], ys[i - 1], go, 0.5)
+        dwo += dwi
+    _assert_close(_host(gd[:, cols].contiguous()), go, BF16_TOL, "zipf-8m reverse g")
+    _assert_close(dw.cpu().numpy(), dwo, 2 * BF16_TOL, "zipf-8m reverse dw")
+    other = torch.as_tensor([c for c in range(d) if c not in cols], device="cuda")
+    assert float(gd.index_select(1, other).abs().max().float().item()) == 0.0
+
+
+def test_grad500k_full_size_gradients(oracle_mod, H):
+    """Differentiable refinement at full size (500K nodes, 300K hyperedges,
+    d = 128 FP32): projection + 10 sweeps with learnable log-weights,
+    checkpoint every 5, CE head on 10% of the nodes with seeded labels."""
+    import torch
+    from synth import labelled_nodes, linear_head
+    O = oracle_mod
+    cfg = CONFIGS["grad-500k"]
+    hg = make_hypergraph(cfg)
+    levels, maps, hier = both_hierarchies(O, H, hg, cfg.levels)
+    plan = H.Plan(hier, cfg.d, "f32")
+    K = cfg.sweeps[0]
+    zc = coarsest_embedding(cfg, levels[1].rows, cfg.d)
+    theta = (np.random.default_rng(304).uniform(-0.3, 0.3, size=hg.n_edges)).astype(np.float32)
+    nodes, labels = labelled_nodes(cfg)
+    W, b = linear_head(cfg)
+    zc_t = _dev(zc).requires_grad_(True)
+    th_t = _dev(theta).requires_grad_(True)
+    out = H.refine_level(zc_t, th_t, plan, 0, K, 0.5, from_coarse=True, ckpt_every=cfg.checkpoint_every)
+    logits = out[torch.as_tensor(nodes).cuda()] @ _dev(W).t() + _dev(b)
+    loss = torch.nn.functional.cross_entropy(logits, torch.as_tensor(labels).cuda())
+    loss.backward()
+    w = torch.as_tensor(theta).cuda().exp().cpu().numpy()
+    zK, _, _ = O.finest_refine_vjp(levels[0], maps[0], zc, w, K, 0.5, np.zeros((levels[0].rows, cfg.d)))
+    ref_loss, dz_nodes = O.ce_head(zK[nodes], labels, W, b)
+    gK = np.zeros((levels[0].rows, cfg.d))
+    gK[nodes] = dz_nodes
+    _, ref_gc, ref_dw = O.finest_refine_vjp(levels[0], maps[0], zc, w, K, 0.5, gK)
+    assert abs(loss.item() - ref_loss) <= 1e-5 * abs(ref_loss)
+    _assert_close(_host(zc_t.grad), ref_gc, GRAD_TOL, "grad-500k dL/dZc")
+    _assert_close(th_t.grad.cpu().numpy(), ref_dw * w, GRAD_TOL, "grad-500k dL/dtheta")
