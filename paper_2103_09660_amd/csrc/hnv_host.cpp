@@ -43,9 +43,11 @@ int64_t blocks_for(int64_t items, int64_t per_block) { return (items + per_block
 
 void lane_layout(int cols, int elem, int *lanes, int *elems_per_lane)
 {
+    // FP32 slices of 128 columns or more take 32 B per lane so that a
+    // wavefront still covers four rows; narrower ones, and BF16, 16 B.
     int epl = 16 / elem;
-    if (cols / epl > kWave)
-        epl = 32 / elem;
+    if (elem == 4 && cols / epl > 16)
+        epl = 8;
     *elems_per_lane = epl;
     *lanes = next_pow2((cols + epl - 1) / epl);
 }

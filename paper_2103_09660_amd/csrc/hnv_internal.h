@@ -112,8 +112,8 @@ hnv_status fail(hnv_status st, const std::string &msg);
 void clear_error();
 
 int next_pow2(int x);
-// Lane layout of a row slice of `cols` elements of `elem` bytes: every lane
-// moves 16 B (32 B when a 64-lane wavefront would not cover the slice).
+// Lane layout of a row slice of `cols` elements of `elem` bytes: lanes move
+// 16 B each, or 32 B for FP32 slices of 128 columns or more.
 void lane_layout(int cols, int elem, int *lanes, int *elems_per_lane);
 constexpr int kIdxRegs = 4;          // neighbour indices a lane preloads in the lane-group tier
 int64_t blocks_for(int64_t items, int64_t per_block);

@@ -323,19 +323,40 @@ HNV_DEV float group_sum(float x)
 }
 
 // ---------------------------------------------------------------------------
-// row epilogues (`self` is the row's own slice, already fetched)
+// row epilogues
 // ---------------------------------------------------------------------------
+
+// A row's own slices, fetched before its neighbours so that their latency
+// overlaps the gather: forward, the row's previous value (or the coarser
+// row it is projected from); reverse, its cotangent g and, for rows with
+// neighbours, the sweep's input y (and, on node rows, its output z).
+template <typename T, int EPL>
+struct Own {
+    typename Slice<T, EPL>::Raw x, y, z;
+};
+
+template <typename T, int EPL, int MODE>
+HNV_DEV void load_own(Own<T, EPL> &o, const GatherArgs &a, int64_t zrow, int64_t srow, int deg, int col)
+{
+    using S = Slice<T, EPL>;
+    o.x = S::load(static_cast<const T *>(a.src) + srow * a.ld + col);
+    if (MODE != kFwd && deg > 0) {
+        o.y = S::load(static_cast<const T *>(a.yprev) + zrow * a.ld + col);
+        if (MODE == kAdjNode)
+            o.z = S::load(static_cast<const T *>(a.zcur) + zrow * a.ld + col);
+    }
+}
 
 // Forward: z'_u = (1 - omega) z_u + omega r_u acc (rows with neighbours),
 // z'_u = z_u otherwise.  Returns the row's contribution to ||z' - z||^2.
 template <typename T, int EPL>
 HNV_DEV double epilogue_fwd(const GatherArgs &a, int zrow, int deg, int col, bool col_ok, float (&acc)[EPL],
-                            const typename Slice<T, EPL>::Raw &self)
+                            const Own<T, EPL> &own)
 {
     if (!col_ok)
         return 0.0;
     float z[EPL], o[EPL];
-    Slice<T, EPL>::unpack(self, z);
+    Slice<T, EPL>::unpack(own.x, z);
     if (deg > 0) {
         const float keep = 1.0f - a.omega;
         const float mix = a.omega * a.r[zrow];
@@ -363,18 +384,18 @@ HNV_DEV double epilogue_fwd(const GatherArgs &a, int zrow, int deg, int col, boo
 // sum_e g_e / |e|; c_v = <g_v, zt_v> / S_v with zt_v = (z_v - (1-omega) y_v) / omega.
 template <typename T, int EPL, int G>
 HNV_DEV void epilogue_adj_node(const GatherArgs &a, int row, int deg, int col, bool col_ok, float (&acc)[EPL],
-                               const typename Slice<T, EPL>::Raw &self, bool writer)
+                               const Own<T, EPL> &own, bool writer)
 {
     using S = Slice<T, EPL>;
     const int64_t zrow = row;  // node rows start at Z row 0
     float dot = 0.0f;
     if (col_ok) {
         float g[EPL], o[EPL];
-        S::unpack(self, g);
+        S::unpack(own.x, g);
         if (deg > 0) {
             float y[EPL], z[EPL];
-            S::unpack(S::load(static_cast<const T *>(a.yprev) + zrow * a.ld + col), y);
-            S::unpack(S::load(static_cast<const T *>(a.zcur) + zrow * a.ld + col), z);
+            S::unpack(own.y, y);
+            S::unpack(own.z, z);
             const float keep = 1.0f - a.omega;
             const float inv_om = 1.0f / a.omega;
 #pragma unroll
@@ -400,17 +421,17 @@ HNV_DEV void epilogue_adj_node(const GatherArgs &a, int row, int deg, int col, b
 // acc = sum_v g_v / S_v; dL/dw_e += omega (<acc, y_e> - sum_v c_v).
 template <typename T, int EPL, int G>
 HNV_DEV void epilogue_adj_edge(const GatherArgs &a, int row, int deg, int col, bool col_ok, float (&acc)[EPL],
-                               float csum, const typename Slice<T, EPL>::Raw &self, bool writer)
+                               float csum, const Own<T, EPL> &own, bool writer)
 {
     using S = Slice<T, EPL>;
     const int64_t zrow = (int64_t)a.side[0].row_base + row;
     float dot = 0.0f;
     if (col_ok) {
         float g[EPL], o[EPL];
-        S::unpack(self, g);
+        S::unpack(own.x, g);
         if (deg > 0) {
             float y[EPL];
-            S::unpack(S::load(static_cast<const T *>(a.yprev) + zrow * a.ld + col), y);
+            S::unpack(own.y, y);
             const float keep = 1.0f - a.omega;
             const float mix = a.omega * a.w[row];
 #pragma unroll
@@ -462,7 +483,6 @@ HNV_DEV void block_resid(const GatherArgs &a, double r2)
 template <typename T, int EPL, int G, int MODE, bool FUSED>
 __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
 {
-    using S = Slice<T, EPL>;
     int b = blockIdx.x;
     const int panel = b / a.blocks_per_panel;
     b -= panel * a.blocks_per_panel;
@@ -508,10 +528,10 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
             const Item c = Sd.chunks[item];
             const int zrow = Sd.row_base + c.row;
             const bool whole = c.aux < 0;
-            typename S::Raw self{};
+            Own<T, EPL> self{};
             if (whole && col_ok) {
                 const int64_t srow = (MODE == kFwd && FUSED) ? (int64_t)a.rowmap[zrow] : (int64_t)zrow;
-                self = S::load(src + srow * a.ld + col);
+                load_own<T, EPL, MODE>(self, a, zrow, srow, c.len, col);
             }
             if (use_scale)
                 gather_wave<T, EPL, G, true, kScalar>(nb, sc, a.cvec, c.start, c.len, src, a.ld, col, col_ok, lane, g,
@@ -545,10 +565,10 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
             if (valid)
                 it = Sd.small[item];
             const int zrow = Sd.row_base + it.row;
-            typename S::Raw self{};
+            Own<T, EPL> self{};
             if (valid && col_ok) {
                 const int64_t srow = (MODE == kFwd && FUSED) ? (int64_t)it.aux : (int64_t)zrow;
-                self = S::load(src + srow * a.ld + col);
+                load_own<T, EPL, MODE>(self, a, zrow, srow, it.len, col);
             }
             if (rr > 0) {
                 zero(acc);
@@ -582,7 +602,6 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
 template <typename T, int EPL, int G, int MODE, bool FUSED>
 __global__ __launch_bounds__(kBlock) void k_finalize(GatherArgs a)
 {
-    using S = Slice<T, EPL>;
     constexpr int Q = kWave / G;
     int b = blockIdx.x;
     const int per_panel = a.nb_split[0] + a.nb_split[1];
@@ -609,10 +628,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(GatherArgs a)
     if (active) {   // uniform over the wavefront
         const Split sp = Sd.splits[item];
         const int zrow = Sd.row_base + sp.row;
-        typename S::Raw self{};
+        Own<T, EPL> self{};
         if (col_ok) {
             const int64_t srow = (MODE == kFwd && FUSED) ? (int64_t)a.rowmap[zrow] : (int64_t)zrow;
-            self = S::load(static_cast<const T *>(a.src) + srow * a.ld + col);
+            load_own<T, EPL, MODE>(self, a, zrow, srow, sp.deg, col);
         }
         for (int k = g; k < sp.n_slots; k += Q) {
             const float *pp = a.partials + (int64_t)(sp.first_slot + k) * a.pstride;
@@ -931,7 +950,7 @@ static void launch_pair(const GatherArgs &a, int panels, hipStream_t s, ProfScop
 }
 
 // Instantiated lane layouts: BF16 always 8 elements per lane; FP32 4 per
-// lane, or 8 when a row slice is wider than 256 elements (then G = 64).
+// lane, or 8 for full-width rows of 128 columns or more (G = 16 .. 64).
 template <typename T, int MODE, bool FUSED>
 static hnv_status dispatch_g(int G, int EPL, const GatherArgs &a, int panels, hipStream_t s, ProfScope *ps)
 {
@@ -947,8 +966,13 @@ static hnv_status dispatch_g(int G, int EPL, const GatherArgs &a, int panels, hi
         case 64: launch_pair<T, E, 64, MODE, FUSED>(a, panels, s, ps); break;
         default: return fail(HNV_EUNSUPPORTED, "lane group width");
         }
-    } else if (E == 4 && EPL == 8 && G == 64) {
-        launch_pair<T, 8, 64, MODE, FUSED>(a, panels, s, ps);
+    } else if (E == 4 && EPL == 8) {
+        switch (G) {
+        case 16: launch_pair<T, 8, 16, MODE, FUSED>(a, panels, s, ps); break;
+        case 32: launch_pair<T, 8, 32, MODE, FUSED>(a, panels, s, ps); break;
+        case 64: launch_pair<T, 8, 64, MODE, FUSED>(a, panels, s, ps); break;
+        default: return fail(HNV_EUNSUPPORTED, "lane group width");
+        }
     } else {
         return fail(HNV_EUNSUPPORTED, "lane layout");
     }
@@ -1283,6 +1307,10 @@ extern "C" hnv_status hnv_project_adjoint(hnv_plan *plan, int level, const void 
     if (plan->dtype == HNV_F32) {
         if (E == 4) {
             HNV_PADJ_G(float, 4)
+        } else if (G == 16) {
+            HNV_PADJ(float, 8, 16);
+        } else if (G == 32) {
+            HNV_PADJ(float, 8, 32);
         } else {
             HNV_PADJ(float, 8, 64);
         }

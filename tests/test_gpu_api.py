@@ -1,0 +1,102 @@
+"""The device calls of the C ABI reject bad arguments with the documented
+status codes (no kernel is launched for them), and the kernel-timing hook
+counts every sweep launch."""
+import numpy as np
+import pytest
+
+from tests.cases import random_hypergraph
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2103_09660_amd as H
+    hg = random_hypergraph(3, 300, 200, 1, 8, weighted=True)
+    hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, 2)
+    plan = H.Plan(hier, 32, "f32")
+    return H, torch, hier, plan
+
+
+def _status(fn):
+    from paper_2103_09660_amd._lib import HnvError
+    with pytest.raises(HnvError) as ei:
+        fn()
+    return ei.value.status
+
+
+def test_device_call_argument_errors(setup):
+    from paper_2103_09660_amd import _lib as L
+    H, torch, hier, plan = setup
+    z0 = plan.empty(0).normal_()
+    s = torch.cuda.current_stream().cuda_stream
+    lib = L.lib()
+    # aliasing, omega out of range, level out of range, from_coarse at the coarsest level
+    assert lib.hnv_sweep(plan._h, 0, z0.data_ptr(), z0.data_ptr(), 0.5, 0, None, s) == L.HNV_EINVAL
+    assert lib.hnv_sweep(plan._h, 0, z0.data_ptr(), plan.empty(0).data_ptr(), 1.5, 0, None, s) == L.HNV_EINVAL
+    assert lib.hnv_sweep(plan._h, 5, z0.data_ptr(), plan.empty(0).data_ptr(), 0.5, 0, None, s) == L.HNV_EINVAL
+    z2 = plan.empty(2)
+    assert lib.hnv_sweep(plan._h, 2, z2.data_ptr(), plan.empty(2).data_ptr(), 0.5, 1, None, s) == L.HNV_EINVAL
+    # misaligned pointer
+    raw = torch.empty(plan.rows(0) * 32 + 4, device="cuda")
+    assert lib.hnv_sweep(plan._h, 0, raw.data_ptr() + 4, z0.data_ptr(), 0.5, 0, None, s) == L.HNV_EINVAL
+    assert "aligned" in H.last_error()
+    # reverse sweep needs omega > 0
+    g = plan.empty(0).normal_()
+    assert lib.hnv_sweep_adjoint(plan._h, 0, g.data_ptr(), plan.empty(0).data_ptr(), z0.data_ptr(),
+                                 z0.data_ptr(), None, 0.0, s) == L.HNV_EINVAL
+    # projection adjoint at the coarsest level, refine with aliased buffers, negative sweep count
+    assert lib.hnv_project_adjoint(plan._h, 2, z2.data_ptr(), z2.data_ptr(), s) == L.HNV_EINVAL
+    sw = np.array([1, 1, 1], dtype=np.int32)
+    assert lib.hnv_refine(plan._h, z0.data_ptr(), z0.data_ptr(), sw.ctypes.data_as(L.i32p), 0.5, 0.0,
+                          None, None, s) == L.HNV_EINVAL
+    sw_bad = np.array([1, -1, 1], dtype=np.int32)
+    assert lib.hnv_refine(plan._h, z2.data_ptr(), z0.data_ptr(), sw_bad.ctypes.data_as(L.i32p), 0.5, 0.0,
+                          None, None, s) == L.HNV_EINVAL
+    # the binding checks shapes and dtypes before calling
+    with pytest.raises(ValueError):
+        plan.sweep(0, z0.to(torch.bfloat16), 0.5)
+    with pytest.raises(ValueError):
+        plan.sweep(0, z0[:-1], 0.5)
+    torch.cuda.synchronize()
+
+
+def test_workspace_and_plan_errors(setup):
+    from paper_2103_09660_amd import _lib as L
+    import ctypes
+    H, torch, hier, plan = setup
+    lv, mp = hier.c_arrays()
+    need = H.plan_workspace_bytes(hier, 32, "f32")
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    out = ctypes.c_void_p()
+    s = torch.cuda.current_stream().cuda_stream
+    st = L.lib().hnv_plan_create(lv, mp, hier.n_levels, 32, L.HNV_F32, None, 1, ws.data_ptr(), need - 256, s,
+                                 ctypes.byref(out))
+    assert st == L.HNV_EWORKSPACE and not out.value
+    st = L.lib().hnv_plan_create(lv, mp, hier.n_levels, 32, L.HNV_F32, None, 1, ws.data_ptr() + 16, need, s,
+                                 ctypes.byref(out))
+    assert st == L.HNV_EWORKSPACE
+    # a map entry out of range is caught even without full validation
+    bad = H.HostMap(hier.maps[0].node_rep.copy(), hier.maps[0].edge_rep.copy())
+    bad.node_rep[3] = hier.levels[1].n_nodes
+    h2 = H.Hierarchy(hier.levels, [bad, hier.maps[1]])
+    lv2, mp2 = h2.c_arrays()
+    st = L.lib().hnv_plan_create(lv2, mp2, h2.n_levels, 32, L.HNV_F32, None, 0, ws.data_ptr(), need, s,
+                                 ctypes.byref(out))
+    assert st == L.HNV_ERANGE
+
+
+def test_profiling_counts_launches(setup):
+    H, torch, hier, plan = setup
+    zc = plan.empty(2).normal_()
+    plan.set_profiling(True)
+    plan.refine(zc, [2, 3, 4], 0.5)
+    n_sweep, ms = plan.profile_read(0)      # non-fused forward sweeps
+    n_fused, _ = plan.profile_read(1)
+    assert (n_sweep, n_fused) == (4 + 2 + 1, 2) and ms > 0      # level 2: 4; level 1: 1 fused + 2; level 0: 1 + 1
+    assert plan.profile_read(0, 2)[0] == 4
+    plan.set_profiling(False)
+    assert plan.profile_read(0)[0] == 0

@@ -74,6 +74,11 @@ def test_sweep_and_fused_projection(oracle_mod, H, seed, n_nodes, n_edges, d, we
         _assert_close(fused, ref_f, F32_TOL, f"fused omega={omega}")
     proj = _host(plan.project(0, _dev(zc)))
     np.testing.assert_array_equal(proj, O.project(O.rowmap(levels[0], maps[0]), zc))
+    # full-width FP32 rows (one pass, 32 B per lane from 128 columns up)
+    full = H.Plan(hier, d, "f32", options={"panel_cols": d})
+    _assert_close(_host(full.sweep(0, _dev(z0), 0.5)), O.sweep(levels[0], z0, 0.5), F32_TOL, "full-width sweep")
+    _assert_close(_host(full.sweep(0, _dev(zc), 0.5, from_coarse=True)),
+                  O.sweep(levels[0], O.project(O.rowmap(levels[0], maps[0]), zc), 0.5), F32_TOL, "full-width fused")
 
 
 @pytest.mark.parametrize("small_max,chunk", [(4, 64), (8, 64), (32, 128), (1, 64)])
