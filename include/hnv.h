@@ -80,11 +80,16 @@ typedef struct {
 } hnv_map;
 
 /* Tuning knobs; zero fields take the library's defaults. */
+#define HNV_ORDER_JACOBI 0      /* every row reads the previous iterate (Algorithm 2 as written) */
+#define HNV_ORDER_EDGE_FIRST 1  /* hyperedge rows first, then node rows from the new hyperedge rows */
 typedef struct {
     int32_t panel_cols;  /* columns per pass of a forward sweep (divides d, multiple of 8) */
     int32_t small_max;   /* rows with at most this many neighbours go to a lane group (capped
                             at 4 lanes' worth of indices per lane of the group) */
     int32_t chunk;       /* neighbours per wavefront work item; longer rows are split */
+    int32_t order;       /* HNV_ORDER_*: update order of a sweep (Section 3.3 describes both; the
+                            edge-first order is the text's "SOR" reading, two half-sweeps that may
+                            run in place; the reverse sweep supports HNV_ORDER_JACOBI only) */
 } hnv_options;
 
 typedef struct hnv_plan hnv_plan;
@@ -184,7 +189,8 @@ hnv_status hnv_project(hnv_plan *plan, int level, const void *z_coarse, void *z_
 
 /* One sweep at `level` (Algorithm 2, one iteration).  If from_coarse != 0,
  * z_in is the embedding of level+1 and the sweep runs on its projection
- * (fused; equal to hnv_project then hnv_sweep).  z_out must not alias z_in.
+ * (fused; equal to hnv_project then hnv_sweep).  z_out must not alias z_in,
+ * except for an edge-first plan with from_coarse = 0 (in place).
  * resid_dev: DEVICE double[1] or NULL, receives ||z_out - z_start||_F. */
 hnv_status hnv_sweep(hnv_plan *plan, int level, const void *z_in, void *z_out, float omega,
                      int from_coarse, double *resid_dev, void *stream);

@@ -16,6 +16,7 @@ HNV_OK, HNV_EINVAL, HNV_ERANGE, HNV_EUNSORTED, HNV_EUNSUPPORTED, HNV_EWORKSPACE,
 STATUS_NAMES = {0: "HNV_OK", 1: "HNV_EINVAL", 2: "HNV_ERANGE", 3: "HNV_EUNSORTED", 4: "HNV_EUNSUPPORTED",
                 5: "HNV_EWORKSPACE", 6: "HNV_EDEVICE", 7: "HNV_ENOMEM"}
 HNV_F32, HNV_BF16 = 0, 1
+HNV_ORDER_JACOBI, HNV_ORDER_EDGE_FIRST = 0, 1
 HNV_PROF_SWEEP, HNV_PROF_FUSED, HNV_PROF_ADJ_NODE, HNV_PROF_ADJ_EDGE = 0, 1, 2, 3
 
 i64 = ctypes.c_int64
@@ -37,7 +38,7 @@ class HnvMap(ctypes.Structure):
 
 
 class HnvOptions(ctypes.Structure):
-    _fields_ = [("panel_cols", i32), ("small_max", i32), ("chunk", i32)]
+    _fields_ = [("panel_cols", i32), ("small_max", i32), ("chunk", i32), ("order", i32)]
 
 
 class HnvError(RuntimeError):

@@ -122,8 +122,11 @@ def _options(options) -> Optional[L.HnvOptions]:
         return None
     if isinstance(options, L.HnvOptions):
         return options
+    order = options.get("order", 0)
+    if isinstance(order, str):
+        order = {"jacobi": L.HNV_ORDER_JACOBI, "edge_first": L.HNV_ORDER_EDGE_FIRST}[order]
     return L.HnvOptions(int(options.get("panel_cols", 0)), int(options.get("small_max", 0)),
-                        int(options.get("chunk", 0)))
+                        int(options.get("chunk", 0)), int(order))
 
 
 def plan_workspace_bytes(hier: Hierarchy, d: int, dtype: str = "f32", options=None) -> int:
@@ -256,6 +259,7 @@ class Plan:
         return z_out, res, done
 
     def sweep(self, level: int, z_in, omega: float = 0.5, from_coarse: bool = False, out=None, resid=None):
+        """One sweep; ``out`` may be ``z_in`` itself for an edge-first plan."""
         self._check(z_in, level + 1 if from_coarse else level, "z_in")
         z_out = self.empty(level) if out is None else out
         self._check(z_out, level, "out")

@@ -368,6 +368,8 @@ static hnv_status check_shape(const hnv_level *levels, const hnv_map *maps, int 
         return fail(HNV_EUNSUPPORTED, "panel_cols must be a multiple of 8 dividing d");
     if (o.small_max > 4096 || o.chunk > (1 << 20))
         return fail(HNV_EUNSUPPORTED, "small_max <= 4096 and chunk <= 2^20");
+    if (o.order != HNV_ORDER_JACOBI && o.order != HNV_ORDER_EDGE_FIRST)
+        return fail(HNV_EINVAL, "unknown sweep order");
     for (int l = 0; l < n_levels; ++l) {
         const hnv_level &L = levels[l];
         if (L.n_nodes < 0 || L.n_edges < 0 || L.nnz < 0 || !L.edge_ptr || (L.nnz > 0 && !L.edge_idx))

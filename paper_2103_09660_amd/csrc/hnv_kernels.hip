@@ -184,6 +184,8 @@ struct GatherArgs {
     int32_t pstride;
     double *resid;            // per-block residual partials or null
     int32_t resid_offset;     // first partial index of this launch
+    const void *self_src;     // forward: matrix a row's own value is read from
+    int32_t self_mapped;      // forward: own value read through the projection row map
 };
 
 // ---------------------------------------------------------------------------
@@ -339,7 +341,7 @@ template <typename T, int EPL, int MODE>
 HNV_DEV void load_own(Own<T, EPL> &o, const GatherArgs &a, int64_t zrow, int64_t srow, int deg, int col)
 {
     using S = Slice<T, EPL>;
-    o.x = S::load(static_cast<const T *>(a.src) + srow * a.ld + col);
+    o.x = S::load(static_cast<const T *>(MODE == kFwd ? a.self_src : a.src) + srow * a.ld + col);
     if (MODE != kFwd && deg > 0) {
         o.y = S::load(static_cast<const T *>(a.yprev) + zrow * a.ld + col);
         if (MODE == kAdjNode)
@@ -530,7 +532,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
             const bool whole = c.aux < 0;
             Own<T, EPL> self{};
             if (whole && col_ok) {
-                const int64_t srow = (MODE == kFwd && FUSED) ? (int64_t)a.rowmap[zrow] : (int64_t)zrow;
+                const int64_t srow =
+                    (MODE == kFwd && (FUSED || a.self_mapped)) ? (int64_t)a.rowmap[zrow] : (int64_t)zrow;
                 load_own<T, EPL, MODE>(self, a, zrow, srow, c.len, col);
             }
             if (use_scale)
@@ -567,7 +570,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
             const int zrow = Sd.row_base + it.row;
             Own<T, EPL> self{};
             if (valid && col_ok) {
-                const int64_t srow = (MODE == kFwd && FUSED) ? (int64_t)it.aux : (int64_t)zrow;
+                const int64_t srow = (MODE == kFwd && (FUSED || a.self_mapped)) ? (int64_t)it.aux : (int64_t)zrow;
                 load_own<T, EPL, MODE>(self, a, zrow, srow, it.len, col);
             }
             if (rr > 0) {
@@ -630,7 +633,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(GatherArgs a)
         const int zrow = Sd.row_base + sp.row;
         Own<T, EPL> self{};
         if (col_ok) {
-            const int64_t srow = (MODE == kFwd && FUSED) ? (int64_t)a.rowmap[zrow] : (int64_t)zrow;
+            const int64_t srow =
+                (MODE == kFwd && (FUSED || a.self_mapped)) ? (int64_t)a.rowmap[zrow] : (int64_t)zrow;
             load_own<T, EPL, MODE>(self, a, zrow, srow, sp.deg, col);
         }
         for (int k = g; k < sp.n_slots; k += Q) {
@@ -884,6 +888,7 @@ static GatherArgs base_args(hnv_plan *p, LevelPlan &L, int G, int dp)
     a.rowmap = L.rowmap;
     a.partials = p->partials;
     a.pstride = p->pstride;
+    a.self_mapped = 0;
     return a;
 }
 
@@ -979,7 +984,17 @@ static hnv_status dispatch_g(int G, int EPL, const GatherArgs &a, int panels, hi
     return dev_check("sweep kernels");
 }
 
+template <typename T>
+static hnv_status dispatch_fwd(hnv_plan *p, bool fused, const GatherArgs &a, hipStream_t s, ProfScope *ps)
+{
+    return fused ? dispatch_g<T, kFwd, true>(p->g_fwd, p->epl_fwd, a, p->panels, s, ps)
+                 : dispatch_g<T, kFwd, false>(p->g_fwd, p->epl_fwd, a, p->panels, s, ps);
+}
+
 // One forward sweep of `level` (src -> dst); fused reads the coarser level.
+// Jacobi: both sides in one launch, every row reading src.  Edge-first:
+// hyperedge rows first (from src), then node rows, whose neighbours are the
+// new hyperedge rows in dst and whose own value still comes from src.
 static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, float omega, bool fused,
                             double *resid_out, hipStream_t s)
 {
@@ -987,18 +1002,28 @@ static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, 
     GatherArgs a = base_args(p, L, p->g_fwd, p->dp);
     a.omega = omega;
     a.src = src;
+    a.self_src = src;
     a.dst = dst;
     a.resid = resid_out ? p->resid_part : nullptr;
     a.resid_offset = 0;
-    ProfScope ps{p, s, fused ? HNV_PROF_FUSED : HNV_PROF_SWEEP, level};
-    const int G = p->g_fwd, E = p->epl_fwd;
+    const bool bf = p->dtype == HNV_BF16;
     hnv_status st;
-    if (p->dtype == HNV_F32)
-        st = fused ? dispatch_g<float, kFwd, true>(G, E, a, p->panels, s, &ps)
-                   : dispatch_g<float, kFwd, false>(G, E, a, p->panels, s, &ps);
-    else
-        st = fused ? dispatch_g<bf16_t, kFwd, true>(G, E, a, p->panels, s, &ps)
-                   : dispatch_g<bf16_t, kFwd, false>(G, E, a, p->panels, s, &ps);
+    if (p->opts.order == HNV_ORDER_JACOBI) {
+        ProfScope ps{p, s, fused ? HNV_PROF_FUSED : HNV_PROF_SWEEP, level};
+        st = bf ? dispatch_fwd<bf16_t>(p, fused, a, s, &ps) : dispatch_fwd<float>(p, fused, a, s, &ps);
+    } else {
+        GatherArgs e = only_side(a, 0);
+        ProfScope pe{p, s, fused ? HNV_PROF_FUSED : HNV_PROF_SWEEP, level};
+        st = bf ? dispatch_fwd<bf16_t>(p, fused, e, s, &pe) : dispatch_fwd<float>(p, fused, e, s, &pe);
+        if (st != HNV_OK)
+            return st;
+        GatherArgs n = only_side(a, 1);
+        n.src = dst;                      // neighbours: the hyperedge rows just written
+        n.self_mapped = fused ? 1 : 0;    // own value: from the coarser level in a fused sweep
+        n.resid_offset = (int32_t)((e.blocks_per_panel + e.nb_split[0]) * p->panels);
+        ProfScope pn{p, s, HNV_PROF_SWEEP, level};
+        st = bf ? dispatch_fwd<bf16_t>(p, false, n, s, &pn) : dispatch_fwd<float>(p, false, n, s, &pn);
+    }
     if (st != HNV_OK)
         return st;
     if (resid_out) {
@@ -1124,8 +1149,10 @@ extern "C" hnv_status hnv_sweep(hnv_plan *plan, int level, const void *z_in, voi
     hnv_status st = check_level(plan, level);
     if (st != HNV_OK)
         return st;
-    if (!z_in || !z_out || z_in == z_out)
-        return fail(HNV_EINVAL, "z_in / z_out NULL or aliased");
+    if (!z_in || !z_out)
+        return fail(HNV_EINVAL, "z_in / z_out is NULL");
+    if (z_in == z_out && (plan->opts.order != HNV_ORDER_EDGE_FIRST || from_coarse))
+        return fail(HNV_EINVAL, "z_in and z_out may alias only for an edge-first sweep within a level");
     if (!aligned16(z_in) || !aligned16(z_out))
         return fail(HNV_EINVAL, "z_in / z_out must be 16-byte aligned");
     if (!(omega >= 0.0f && omega <= 1.0f))
@@ -1247,6 +1274,8 @@ extern "C" hnv_status hnv_sweep_adjoint(hnv_plan *plan, int level, const void *g
         return fail(HNV_EINVAL, "matrices must be 16-byte aligned");
     if (!(omega > 0.0f && omega <= 1.0f))
         return fail(HNV_EINVAL, "omega must be in (0, 1] for the reverse sweep");
+    if (plan->opts.order != HNV_ORDER_JACOBI)
+        return fail(HNV_EUNSUPPORTED, "the reverse sweep is implemented for the Jacobi order");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     LevelPlan &L = plan->lv[level];
     const int G = plan->g_full, E = plan->epl_full;

@@ -355,3 +355,45 @@ def test_grad500k_full_size_gradients(oracle_mod, H):
     assert abs(loss.item() - ref_loss) <= 1e-5 * abs(ref_loss)
     _assert_close(_host(zc_t.grad), ref_gc, GRAD_TOL, "grad-500k dL/dZc")
     _assert_close(th_t.grad.cpu().numpy(), ref_dw * w, GRAD_TOL, "grad-500k dL/dtheta")
+
+
+# ---------------------------------------------------------------------------
+# edge-first order (hyperedge rows first, then node rows from the new ones)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("small_max,chunk", [(64, 512), (4, 64)])
+def test_edge_first_sweeps(oracle_mod, H, dtype, small_max, chunk):
+    import torch
+    O = oracle_mod
+    hg = tier_hypergraph(7, max(small_max, 2), chunk)
+    levels, maps, hier = both_hierarchies(O, H, hg, 2)
+    d = 64
+    plan = H.Plan(hier, d, dtype, options={"order": "edge_first", "small_max": small_max, "chunk": chunk})
+    tol = F32_TOL if dtype == "f32" else BF16_TOL
+    rng = np.random.default_rng(8)
+    z0 = rng.standard_normal((levels[0].rows, d)).astype(np.float32)
+    zc = rng.standard_normal((levels[1].rows, d)).astype(np.float32)
+    z0r = z0 if dtype == "f32" else _bf16_round(z0)
+    zcr = zc if dtype == "f32" else _bf16_round(zc)
+    resid = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ref = O.sweep(levels[0], z0r, 0.5, 1)
+    _assert_close(_host(plan.sweep(0, _dev(z0, dtype), 0.5, resid=resid)), ref, tol, "edge-first sweep")
+    assert abs(resid.item() - O.residual(ref, z0r)) <= 10 * tol * O.residual(ref, z0r)
+    # in place
+    zi = _dev(z0, dtype)
+    plan.sweep(0, zi, 0.5, out=zi)
+    _assert_close(_host(zi), ref, tol, "edge-first in place")
+    # fused with the projection
+    ref_f = O.sweep(levels[0], O.project(O.rowmap(levels[0], maps[0]), zcr), 0.5, 1)
+    _assert_close(_host(plan.sweep(0, _dev(zc, dtype), 0.5, from_coarse=True)), ref_f, tol, "edge-first fused")
+    # multi-level
+    ztop = rng.standard_normal((levels[2].rows, d)).astype(np.float32)
+    ztr = ztop if dtype == "f32" else _bf16_round(ztop)
+    out, _, _ = plan.refine(_dev(ztop, dtype), [3, 2, 4], 0.5)
+    _assert_close(_host(out), O.refine(levels, maps, ztr, [3, 2, 4], 0.5, order=1), tol, "edge-first refine")
+    # the Jacobi-only reverse sweep refuses this plan
+    from paper_2103_09660_amd._lib import HNV_EUNSUPPORTED, HnvError
+    with pytest.raises(HnvError) as ei:
+        plan.sweep_adjoint(0, plan.empty(0), plan.empty(0), plan.empty(0), 0.5)
+    assert ei.value.status == HNV_EUNSUPPORTED
