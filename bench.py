@@ -19,6 +19,8 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+
+import numpy as np
 import json
 import os
 import sys
@@ -221,6 +223,28 @@ def run_reverse(H, torch, plan, z_start, cfg, steps):
             "reverse_node_rows_avg_ms": tn / max(nn_, 1), "reverse_hyperedge_rows_avg_ms": te / max(ne_, 1)}
 
 
+def run_scoring(H, torch, hg, z_out, cfg, steps):
+    """Hyperedge-prediction features of the finest level's hyperedges taken
+    as candidate sets: per-dimension variance of the member rows of the
+    refined embedding (Section 4).  Returns time and rates."""
+    z_nodes = z_out[: hg.n_nodes]
+    plan = H.ScorePlan(hg.edge_ptr, hg.edge_idx, hg.n_nodes, cfg.d,
+                       "f32" if z_out.dtype == torch.float32 else "bf16")
+    out = plan.score(z_nodes)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        plan.score(z_nodes, out=out)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    s = z_out.element_size()
+    nbytes = hg.nnz * (cfg.d * s + 4) + hg.n_edges * (8 + cfg.d * 4)
+    return {"candidates": hg.n_edges, "members": hg.nnz, "op": "variance", "ms": ms,
+            "candidates_per_s": hg.n_edges / (ms / 1000.0), "stream_GBps": nbytes / (ms / 1000.0) / 1e9}
+
+
 def cpu_baseline(O, hg, cfg, budget_s=12.0, max_sweeps=20, d=None):
     """The oracle as it stands, on a bounded sample of the same workload:
     Jacobi sweeps of the finest level at full width d (FP64), repeated until
@@ -321,6 +345,9 @@ def main():
         log(f"{dt}: {r['ms_per_step']:.2f} ms/step, {r['value'] / 1e12:.3f} T updates/s, sweep kernel "
             f"{r['sweep_kernel_avg_ms'] * 1e3:.1f} us avg over {r['sweep_kernel_launches']} launches "
             f"({time.perf_counter() - t:.1f} s with plan creation)")
+        if dt == dtypes[0] and not large:
+            results["scoring"] = run_scoring(H, torch, hg, out, cfg, max(2, args.steps))
+            log(f"scoring: {results['scoring']}")
         if large and dt == dtypes[0] and cfg.adjoint_sweeps:
             reverse = run_reverse(H, torch, plan, out, cfg, max(2, args.steps // 2))
             log(f"reverse: {reverse}")
@@ -363,6 +390,8 @@ def main():
                      "compulsory_bytes_per_launch": head["sweep_min_bytes_per_launch"],
                      "compulsory_GBps": compulsory, "compulsory_frac": compulsory / HBM_PEAK_GBS},
     }
+    if "scoring" in results:
+        line["hyperedge_scoring"] = results["scoring"]
     for dt in dtypes[1:]:
         r = results[dt]
         line[dt] = {"value": r["value"], "ms_per_step": r["ms_per_step"],

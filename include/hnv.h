@@ -241,6 +241,36 @@ hnv_status hnv_plan_set_profiling(hnv_plan *plan, int enable);
  * hnv_plan_set_profiling(plan, 0). */
 hnv_status hnv_plan_profile_read(hnv_plan *plan, int kind, int level, int64_t *launches, double *total_ms);
 
+/* Hyperedge-prediction features (Section 4, hyperedge prediction): for each
+ * candidate node set c, out[c, :] = a per-dimension statistic of the member
+ * rows z[v, :] (node embeddings of level 0):
+ *   HNV_SCORE_VARIANCE  population variance (the paper's choice)
+ *   HNV_SCORE_MEAN, HNV_SCORE_MIN, HNV_SCORE_MAX  the alternatives it names.
+ * A score plan holds the candidates: cand_ptr[n_cand+1] (int64) and
+ * cand_idx[cand_ptr[n_cand]] (int32) are HOST arrays listing each
+ * candidate's members, ids in [0, z_rows) (checked: HNV_ERANGE otherwise).
+ * The plan tiers the candidates by size like the sweep's rows and copies
+ * itself into `workspace` (DEVICE, >= hnv_score_workspace_bytes, 256-byte
+ * aligned, the caller's; it must outlive the plan), then synchronises
+ * `stream`.  Scoring visits members in list order with Welford's FP32
+ * update; partial results of long candidates are combined in a fixed
+ * order, so the output is reproducible.  An empty candidate gets a row of
+ * NaN. */
+#define HNV_SCORE_VARIANCE 0
+#define HNV_SCORE_MEAN 1
+#define HNV_SCORE_MIN 2
+#define HNV_SCORE_MAX 3
+typedef struct hnv_score_plan hnv_score_plan;
+hnv_status hnv_score_workspace_bytes(const int64_t *cand_ptr, int64_t n_cand, int d, hnv_dtype dtype,
+                                     size_t *bytes);
+hnv_status hnv_score_plan_create(const int64_t *cand_ptr, const int32_t *cand_idx, int64_t n_cand, int64_t z_rows,
+                                 int d, hnv_dtype dtype, void *workspace, size_t ws_bytes, void *stream,
+                                 hnv_score_plan **out);
+hnv_status hnv_score_plan_destroy(hnv_score_plan *plan);
+/* z: DEVICE [z_rows x d] of the plan's dtype, 16-byte aligned; out: DEVICE
+ * float [n_cand x d], 16-byte aligned; op: HNV_SCORE_*. */
+hnv_status hnv_score_candidates(hnv_score_plan *plan, const void *z, int op, float *out, void *stream);
+
 /* Element-wise conversion between storage types on the device (FP32 ->
  * BF16 rounds to nearest even; BF16 -> FP32 is exact).  n elements. */
 hnv_status hnv_cast(const void *src, hnv_dtype src_dtype, void *dst, hnv_dtype dst_dtype,

@@ -13,7 +13,9 @@ three phases in order:
 * Algorithm 2 (Section 3.3), ``k`` smoothing sweeps per level, from the
   coarsest level to the finest;
 * the reverse mode of the projection and of each sweep, and the linear
-  cross-entropy head used downstream (Section 4, experimental settings).
+  cross-entropy head used downstream (Section 4, experimental settings);
+* the hyperedge-prediction features (Section 4, hyperedge prediction): the
+  per-dimension variance of a candidate set's member embeddings.
 
 The function groups that have no external pin are listed under
 ``PARITY_UNPINNED`` below (empty: every function is pinned by a test in
@@ -269,3 +271,32 @@ def ce_head(z_nodes: np.ndarray, labels: np.ndarray, W: np.ndarray, b: np.ndarra
     p[np.arange(n), labels] -= 1.0
     dz = (p / n) @ W64
     return loss, dz
+
+
+def score_candidates(z_nodes: np.ndarray, cand_ptr: np.ndarray, cand_idx: np.ndarray, op: str = "variance"):
+    """Hyperedge-prediction features (Section 4, hyperedge prediction): for
+    each candidate node set, a per-dimension statistic of its members' rows
+    in FP64 -- the population variance (the paper's operator), or the mean,
+    min or max it names as alternatives.  The variance is computed in two
+    passes, mean first, then the mean squared deviation.  Empty sets and
+    member ids outside the matrix give NaN rows."""
+    z = np.asarray(z_nodes, dtype=np.float64)
+    n_cand = len(cand_ptr) - 1
+    out = np.full((n_cand, z.shape[1]), np.nan)
+    for c in range(n_cand):
+        members = np.asarray(cand_idx[cand_ptr[c]:cand_ptr[c + 1]], dtype=np.int64)
+        if len(members) == 0 or members.min() < 0 or members.max() >= z.shape[0]:
+            continue
+        rows = z[members]
+        if op == "variance":
+            mean = rows.sum(axis=0) / len(members)
+            out[c] = ((rows - mean) ** 2).sum(axis=0) / len(members)
+        elif op == "mean":
+            out[c] = rows.sum(axis=0) / len(members)
+        elif op == "min":
+            out[c] = rows.min(axis=0)
+        elif op == "max":
+            out[c] = rows.max(axis=0)
+        else:
+            raise ValueError(op)
+    return out

@@ -10,12 +10,14 @@ from .api import (  # noqa: F401
     HostLevel,
     HostMap,
     Plan,
+    ScorePlan,
     abi_version,
     cast,
     coarsen_level,
     last_error,
     plan_workspace_bytes,
     refine_level,
+    score_candidates,
     validate_level,
 )
 from ._lib import HnvError  # noqa: F401

@@ -17,6 +17,7 @@ STATUS_NAMES = {0: "HNV_OK", 1: "HNV_EINVAL", 2: "HNV_ERANGE", 3: "HNV_EUNSORTED
                 5: "HNV_EWORKSPACE", 6: "HNV_EDEVICE", 7: "HNV_ENOMEM"}
 HNV_F32, HNV_BF16 = 0, 1
 HNV_ORDER_JACOBI, HNV_ORDER_EDGE_FIRST = 0, 1
+HNV_SCORE_VARIANCE, HNV_SCORE_MEAN, HNV_SCORE_MIN, HNV_SCORE_MAX = 0, 1, 2, 3
 HNV_PROF_SWEEP, HNV_PROF_FUSED, HNV_PROF_ADJ_NODE, HNV_PROF_ADJ_EDGE = 0, 1, 2, 3
 
 i64 = ctypes.c_int64
@@ -70,6 +71,12 @@ _SIGS = {
     "hnv_logweight_grad": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
     "hnv_plan_set_profiling": (ctypes.c_int, [vp, ctypes.c_int]),
     "hnv_plan_profile_read": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, i64p, f64p]),
+    "hnv_score_workspace_bytes": (ctypes.c_int, [i64p, i64, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "hnv_score_plan_create": (ctypes.c_int, [i64p, i32p, i64, i64, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t,
+                                             vp, ctypes.POINTER(vp)]),
+    "hnv_score_plan_destroy": (ctypes.c_int, [vp]),
+    "hnv_score_candidates": (ctypes.c_int, [vp, vp, ctypes.c_int, vp, vp]),
     "hnv_cast": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.c_int, i64, vp]),
 }
 

@@ -292,6 +292,61 @@ class Plan:
         return g_out
 
 
+_SCORE_OPS = {"variance": L.HNV_SCORE_VARIANCE, "mean": L.HNV_SCORE_MEAN, "min": L.HNV_SCORE_MIN,
+              "max": L.HNV_SCORE_MAX}
+
+
+class ScorePlan:
+    """Candidate node sets for hyperedge-prediction features (Section 4),
+    planned once on the host (``cand_ptr`` / ``cand_idx``: CSR of member node
+    ids) and kept in a device workspace."""
+
+    def __init__(self, cand_ptr, cand_idx, z_rows: int, d: int, dtype: str = "f32", device=None):
+        torch = _torch()
+        self.device = torch.device("cuda" if device is None else device)
+        ptr = np.ascontiguousarray(np.asarray(cand_ptr), dtype=np.int64)
+        idx = np.ascontiguousarray(np.asarray(cand_idx), dtype=np.int32)
+        self.n_cand = len(ptr) - 1
+        self.d = int(d)
+        self.dtype = dtype
+        dt = _dt(dtype)
+        need = ctypes.c_size_t()
+        L.call("hnv_score_workspace_bytes", ptr.ctypes.data_as(L.i64p), self.n_cand, self.d, dt, ctypes.byref(need))
+        self.workspace = torch.empty(max(need.value, 256), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        L.call("hnv_score_plan_create", ptr.ctypes.data_as(L.i64p), idx.ctypes.data_as(L.i32p), self.n_cand,
+               int(z_rows), self.d, dt, self.workspace.data_ptr(), self.workspace.numel(), _stream(self.device),
+               ctypes.byref(h))
+        self._h = h
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                L.lib().hnv_score_plan_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def score(self, z_nodes, op: str = "variance", out=None):
+        torch = _torch()
+        want = torch.float32 if _dt(self.dtype) == L.HNV_F32 else torch.bfloat16
+        if z_nodes.dtype != want or not z_nodes.is_contiguous() or z_nodes.dim() != 2 or z_nodes.shape[1] != self.d:
+            raise ValueError(f"z_nodes: contiguous {want} [rows x {self.d}] expected")
+        if out is None:
+            out = torch.empty((self.n_cand, self.d), dtype=torch.float32, device=self.device)
+        L.call("hnv_score_candidates", self._h, z_nodes.data_ptr(), _SCORE_OPS[op], out.data_ptr(),
+               _stream(self.device))
+        return out
+
+
+def score_candidates(z_nodes, cand_ptr, cand_idx, op: str = "variance"):
+    """One-shot hyperedge-prediction features (plans, then scores)."""
+    torch = _torch()
+    dtype = "f32" if z_nodes.dtype == torch.float32 else "bf16"
+    plan = ScorePlan(cand_ptr, cand_idx, z_nodes.shape[0], z_nodes.shape[1], dtype, z_nodes.device)
+    return plan.score(z_nodes, op)
+
+
 def cast(src, dst_dtype: str):
     """Storage conversion on the device (FP32 -> BF16 rounds to nearest even)."""
     torch = _torch()

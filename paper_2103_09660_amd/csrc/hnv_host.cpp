@@ -779,3 +779,179 @@ extern "C" hnv_status hnv_plan_level_info(const hnv_plan *plan, int level, int64
         *nnz = L.nnz;
     return HNV_OK;
 }
+
+// ---------------------------------------------------------------------------
+// hyperedge-prediction features: host plan
+// ---------------------------------------------------------------------------
+
+namespace hnv {
+
+static constexpr int kScoreChunk = 512;
+
+struct ScoreLayout {
+    HostTier tier;
+    int32_t slots = 0;
+    size_t bytes = 0;
+    size_t off_idx = 0, off_small = 0, off_chunks = 0, off_splits = 0, off_part = 0;
+};
+
+static hnv_status score_layout(const int64_t *cand_ptr, int64_t n_cand, int d, hnv_dtype dtype, ScoreLayout &L)
+{
+    if (n_cand < 0 || (n_cand > 0 && !cand_ptr))
+        return fail(HNV_EINVAL, "bad candidate arrays");
+    if (d < 8 || d > 512 || d % 8 != 0)
+        return fail(HNV_EUNSUPPORTED, "d must be a multiple of 8 in [8, 512]");
+    if (dtype != HNV_F32 && dtype != HNV_BF16)
+        return fail(HNV_EINVAL, "unknown dtype");
+    if (n_cand >= kMaxI32)
+        return fail(HNV_EUNSUPPORTED, "too many candidates");
+    if (n_cand == 0) {
+        L.bytes = 256;
+        return HNV_OK;
+    }
+    if (cand_ptr[0] != 0)
+        return fail(HNV_EINVAL, "cand_ptr must start at 0");
+    for (int64_t c = 0; c < n_cand; ++c)
+        if (cand_ptr[c + 1] < cand_ptr[c])
+            return fail(HNV_EINVAL, "cand_ptr decreases at candidate " + std::to_string(c));
+    const int64_t nnz = cand_ptr[n_cand];
+    if (nnz >= kMaxI32)
+        return fail(HNV_EUNSUPPORTED, "at most 2^31 - 1 members");
+    std::vector<int32_t> ptr32(n_cand + 1);
+    for (int64_t c = 0; c <= n_cand; ++c)
+        ptr32[c] = (int32_t)cand_ptr[c];
+    int G = 1, E = 8;
+    lane_layout(d, dtype == HNV_BF16 ? 2 : 4, &G, &E);
+    tier_side(ptr32.data(), (int32_t)n_cand, kIdxRegs * G, kScoreChunk, &L.slots, L.tier);
+    Carver c{nullptr};
+    c.take<int32_t>(nnz);
+    L.off_idx = 0;
+    c.take<Item>((int64_t)L.tier.small.size());
+    L.off_small = (c.off - std::max<size_t>(L.tier.small.size(), 1) * sizeof(Item));
+    c.take<Item>((int64_t)L.tier.chunks.size());
+    L.off_chunks = (c.off - std::max<size_t>(L.tier.chunks.size(), 1) * sizeof(Item));
+    c.take<Split>((int64_t)L.tier.splits.size());
+    L.off_splits = (c.off - std::max<size_t>(L.tier.splits.size(), 1) * sizeof(Split));
+    c.take<float>((int64_t)std::max<int32_t>(L.slots, 1) * (2 * d + 8));
+    L.off_part = (c.off - (size_t)std::max<int32_t>(L.slots, 1) * (2 * d + 8) * sizeof(float));
+    L.bytes = (c.off + 255) & ~size_t(255);
+    return HNV_OK;
+}
+
+}  // namespace hnv
+
+extern "C" hnv_status hnv_score_workspace_bytes(const int64_t *cand_ptr, int64_t n_cand, int d, hnv_dtype dtype,
+                                                size_t *bytes)
+{
+    clear_error();
+    if (!bytes)
+        return fail(HNV_EINVAL, "bytes is NULL");
+    try {
+        ScoreLayout L;
+        hnv_status st = score_layout(cand_ptr, n_cand, d, dtype, L);
+        if (st == HNV_OK)
+            *bytes = L.bytes;
+        return st;
+    } catch (const std::bad_alloc &) {
+        return fail(HNV_ENOMEM, "host allocation failed in hnv_score_workspace_bytes");
+    }
+}
+
+struct hnv_score_plan {
+    hnv::ScorePlan sp;
+    int64_t n_cand = 0, z_rows = 0;
+    int d = 0;
+    hnv_dtype dtype = HNV_F32;
+};
+
+extern "C" hnv_status hnv_score_plan_create(const int64_t *cand_ptr, const int32_t *cand_idx, int64_t n_cand,
+                                            int64_t z_rows, int d, hnv_dtype dtype, void *workspace,
+                                            size_t ws_bytes, void *stream, hnv_score_plan **out)
+{
+    clear_error();
+    if (!out)
+        return fail(HNV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (z_rows < 0 || (n_cand > 0 && !workspace))
+        return fail(HNV_EINVAL, "bad arguments");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255)
+        return fail(HNV_EWORKSPACE, "workspace must be 256-byte aligned");
+    try {
+        ScoreLayout L;
+        hnv_status st = score_layout(cand_ptr, n_cand, d, dtype, L);
+        if (st != HNV_OK)
+            return st;
+        if (n_cand > 0 && L.bytes > ws_bytes)
+            return fail(HNV_EWORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " +
+                                            std::to_string(L.bytes));
+        const int64_t nnz = n_cand > 0 ? cand_ptr[n_cand] : 0;
+        if (nnz > 0 && !cand_idx)
+            return fail(HNV_EINVAL, "cand_idx is NULL");
+        for (int64_t j = 0; j < nnz; ++j)
+            if (cand_idx[j] < 0 || cand_idx[j] >= z_rows)
+                return fail(HNV_ERANGE, "member id " + std::to_string(cand_idx[j]) + " outside [0, z_rows)");
+        auto *plan = new hnv_score_plan;
+        plan->n_cand = n_cand;
+        plan->z_rows = z_rows;
+        plan->d = d;
+        plan->dtype = dtype;
+        if (n_cand > 0) {
+            char *base = static_cast<char *>(workspace);
+            hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+            auto up = [&](size_t off, const void *src, size_t n) -> hnv_status {
+                if (n == 0)
+                    return HNV_OK;
+                hipError_t e = hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, s);
+                return e == hipSuccess ? HNV_OK
+                                       : fail(HNV_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+            };
+            if ((st = up(L.off_idx, cand_idx, (size_t)nnz * 4)) == HNV_OK &&
+                (st = up(L.off_small, L.tier.small.data(), L.tier.small.size() * sizeof(Item))) == HNV_OK &&
+                (st = up(L.off_chunks, L.tier.chunks.data(), L.tier.chunks.size() * sizeof(Item))) == HNV_OK &&
+                (st = up(L.off_splits, L.tier.splits.data(), L.tier.splits.size() * sizeof(Split))) == HNV_OK) {
+                hipError_t e = hipStreamSynchronize(s);
+                if (e != hipSuccess)
+                    st = fail(HNV_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+            }
+            if (st != HNV_OK) {
+                delete plan;
+                return st;
+            }
+            plan->sp.idx = reinterpret_cast<const int32_t *>(base + L.off_idx);
+            plan->sp.small = reinterpret_cast<const Item *>(base + L.off_small);
+            plan->sp.n_small = (int32_t)L.tier.small.size();
+            plan->sp.chunks = reinterpret_cast<const Item *>(base + L.off_chunks);
+            plan->sp.n_chunks = (int32_t)L.tier.chunks.size();
+            plan->sp.splits = reinterpret_cast<const Split *>(base + L.off_splits);
+            plan->sp.n_splits = (int32_t)L.tier.splits.size();
+            plan->sp.partials = reinterpret_cast<float *>(base + L.off_part);
+        }
+        *out = plan;
+        return HNV_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(HNV_ENOMEM, "host allocation failed in hnv_score_plan_create");
+    }
+}
+
+extern "C" hnv_status hnv_score_plan_destroy(hnv_score_plan *plan)
+{
+    clear_error();
+    delete plan;
+    return HNV_OK;
+}
+
+extern "C" hnv_status hnv_score_candidates(hnv_score_plan *plan, const void *z, int op, float *out, void *stream)
+{
+    clear_error();
+    if (!plan)
+        return fail(HNV_EINVAL, "plan is NULL");
+    if (op < HNV_SCORE_VARIANCE || op > HNV_SCORE_MAX)
+        return fail(HNV_EINVAL, "unknown statistic");
+    if (plan->n_cand == 0)
+        return HNV_OK;
+    if (!z || !out)
+        return fail(HNV_EINVAL, "NULL argument");
+    if ((reinterpret_cast<uintptr_t>(z) & 15) || (reinterpret_cast<uintptr_t>(out) & 15))
+        return fail(HNV_EINVAL, "z and out must be 16-byte aligned");
+    return dev_score(plan->sp, z, plan->dtype, plan->d, op, out, reinterpret_cast<hipStream_t>(stream));
+}

@@ -8,6 +8,8 @@
 
 #include "hnv.h"
 
+typedef struct ihipStream_t *hipStream_t;
+
 namespace hnv {
 
 constexpr int kBlock = 256;   // threads per workgroup (4 wavefronts of 64)
@@ -121,8 +123,22 @@ int64_t blocks_for(int64_t items, int64_t per_block);
 // Forward-sweep launch geometry of a level (blocks per panel and finalize blocks).
 void forward_geometry(const hnv_plan *p, const LevelPlan &L, int64_t *main_blocks, int64_t *fin_blocks);
 
+// Device arrays of a candidate-scoring plan (carved from the caller's workspace)
+struct ScorePlan {
+    const int32_t *idx = nullptr;
+    const Item *small = nullptr;
+    int32_t n_small = 0;
+    const Item *chunks = nullptr;
+    int32_t n_chunks = 0;
+    const Split *splits = nullptr;
+    int32_t n_splits = 0;
+    float *partials = nullptr;
+};
+
 // Device-side pieces implemented in hnv_kernels.hip
 hnv_status dev_recompute_reciprocals(hnv_plan *p, int level, void *stream);
 hnv_status dev_check(const char *what);
+hnv_status dev_score(const ScorePlan &sp, const void *z, hnv_dtype dtype, int d, int op, float *out,
+                     hipStream_t s);
 
 }  // namespace hnv

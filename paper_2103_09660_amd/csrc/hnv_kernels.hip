@@ -745,6 +745,271 @@ __global__ __launch_bounds__(kBlock) void k_project_adj(const T *__restrict__ gf
 }
 
 // ---------------------------------------------------------------------------
+// hyperedge-prediction features
+// ---------------------------------------------------------------------------
+
+// Running statistic of one lane's column slice: count, and per column the
+// mean and sum of squared deviations (Welford), or the min / max.
+template <int EPL>
+struct Stat {
+    float n;
+    float m[EPL], q[EPL];
+};
+
+template <int EPL>
+HNV_DEV void stat_init(Stat<EPL> &s, int op)
+{
+    s.n = 0.0f;
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+        s.m[i] = (op == HNV_SCORE_MIN) ? INFINITY : (op == HNV_SCORE_MAX) ? -INFINITY : 0.0f;
+        s.q[i] = 0.0f;
+    }
+}
+
+template <int EPL>
+HNV_DEV void stat_add(Stat<EPL> &s, const float (&x)[EPL], int op)
+{
+    s.n += 1.0f;
+    const float inv = 1.0f / s.n;
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+        if (op == HNV_SCORE_MIN) {
+            s.m[i] = fminf(s.m[i], x[i]);
+        } else if (op == HNV_SCORE_MAX) {
+            s.m[i] = fmaxf(s.m[i], x[i]);
+        } else {
+            const float delta = x[i] - s.m[i];
+            s.m[i] = fmaf(delta, inv, s.m[i]);
+            s.q[i] = fmaf(delta, x[i] - s.m[i], s.q[i]);
+        }
+    }
+}
+
+// a <- combination of a (earlier members) and b (later members): Chan et
+// al.'s pairwise update for mean / squared deviations, or min / max.
+template <int EPL>
+HNV_DEV void stat_merge(Stat<EPL> &a, float bn, const float (&bm)[EPL], const float (&bq)[EPL], int op)
+{
+    const float n = a.n + bn;
+    if (bn == 0.0f)
+        return;
+    const float fb = bn / n, cross = a.n * bn / n;
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+        if (op == HNV_SCORE_MIN) {
+            a.m[i] = fminf(a.m[i], bm[i]);
+        } else if (op == HNV_SCORE_MAX) {
+            a.m[i] = fmaxf(a.m[i], bm[i]);
+        } else if (a.n == 0.0f) {
+            a.m[i] = bm[i];
+            a.q[i] = bq[i];
+        } else {
+            const float delta = bm[i] - a.m[i];
+            a.m[i] = fmaf(delta, fb, a.m[i]);
+            a.q[i] = a.q[i] + bq[i] + delta * delta * cross;
+        }
+    }
+    a.n = n;
+}
+
+// Combine the Q lane groups of a wavefront, lower group first at every
+// level of the tree, so that both partners of a step compute the same value
+// and the order is fixed.
+template <int EPL, int G>
+HNV_DEV void stat_wave_combine(Stat<EPL> &s, int g, int op)
+{
+#pragma unroll
+    for (int off = G; off < kWave; off <<= 1) {
+        float pn = __shfl_xor(s.n, off, kWave);
+        float pm[EPL], pq[EPL];
+#pragma unroll
+        for (int i = 0; i < EPL; ++i) {
+            pm[i] = __shfl_xor(s.m[i], off, kWave);
+            pq[i] = __shfl_xor(s.q[i], off, kWave);
+        }
+        const bool low = ((g * G) & off) == 0;
+        if (low) {
+            stat_merge(s, pn, pm, pq, op);
+        } else {
+            Stat<EPL> t;
+            t.n = pn;
+#pragma unroll
+            for (int i = 0; i < EPL; ++i) {
+                t.m[i] = pm[i];
+                t.q[i] = pq[i];
+            }
+            stat_merge(t, s.n, s.m, s.q, op);
+            s = t;
+        }
+    }
+}
+
+template <int EPL>
+HNV_DEV void stat_write(float *po, const Stat<EPL> &s, int op)
+{
+    float o[EPL];
+#pragma unroll
+    for (int i = 0; i < EPL; ++i)
+        o[i] = (s.n == 0.0f) ? NAN : (op == HNV_SCORE_VARIANCE) ? s.q[i] / s.n : s.m[i];
+#pragma unroll
+    for (int i = 0; i < EPL; i += 4)
+        *reinterpret_cast<float4 *>(po + i) = make_float4(o[i], o[i + 1], o[i + 2], o[i + 3]);
+}
+
+struct ScoreArgs {
+    const Item *small;        // candidates of at most kIdxRegs * G members, largest first
+    int32_t n_small;
+    const Item *chunks;       // wavefront work items (aux = partial slot or -1)
+    int32_t n_chunks;
+    const Split *splits;      // candidates split over several chunks
+    int32_t n_splits;
+    int32_t nb_chunk, nb_small;
+    const int32_t *idx;       // member node ids
+    const void *z;
+    int64_t ld;
+    int op;
+    float *out;
+    float *partials;          // [slots x pstride]: mean [d], squared deviations [d], count
+    int32_t pstride;
+};
+
+template <typename T, int EPL, int G>
+__global__ __launch_bounds__(kBlock) void k_score(ScoreArgs a)
+{
+    using S = Slice<T, EPL>;
+    constexpr int Q = kWave / G;
+    const int lane = threadIdx.x % kWave;
+    const int g = lane / G, gl = lane % G;
+    const int col = gl * EPL;
+    const bool col_ok = col < a.ld;
+    const T *z = static_cast<const T *>(a.z);
+    Stat<EPL> st;
+    stat_init(st, a.op);
+    int b = blockIdx.x;
+    if (b < a.nb_chunk) {
+        const int item = b * kWavesPerBlock + (int)(threadIdx.x / kWave);
+        if (item >= a.n_chunks)
+            return;   // uniform over the wavefront
+        const Item c = a.chunks[item];
+        for (int base = 0; base < c.len; base += kWave) {
+            const int my = (base + lane < c.len) ? a.idx[c.start + base + lane] : 0;
+            const int n = min(kWave, c.len - base);
+            for (int t = 0; t < n; t += 4 * Q) {
+                typename S::Raw raw[4];
+                bool ok[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int q = t + k * Q + g;
+                    ok[k] = q < n;
+                    const int v = __shfl(my, q & (kWave - 1), kWave);
+                    if (ok[k] && col_ok)
+                        raw[k] = S::load(z + (int64_t)v * a.ld + col);
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (!ok[k])
+                        continue;
+                    float x[EPL];
+                    if (col_ok)
+                        S::unpack(raw[k], x);
+                    else
+                        zero(x);
+                    stat_add(st, x, a.op);
+                }
+            }
+        }
+        stat_wave_combine<EPL, G>(st, g, a.op);
+        if (g != 0 || !col_ok)
+            return;
+        if (c.aux < 0) {
+            stat_write(a.out + (int64_t)c.row * a.ld + col, st, a.op);
+        } else {
+            float *pp = a.partials + (int64_t)c.aux * a.pstride;
+#pragma unroll
+            for (int i = 0; i < EPL; ++i) {
+                pp[col + i] = st.m[i];
+                pp[a.ld + col + i] = st.q[i];
+            }
+            if (gl == 0)
+                pp[2 * a.ld] = st.n;
+        }
+        return;
+    }
+    b -= a.nb_chunk;
+    const int item = b * (kBlock / G) + (int)(threadIdx.x / G);
+    const bool valid = item < a.n_small;
+    Item it{0, 0, 0, 0};
+    if (valid)
+        it = a.small[item];
+    int ix[kIdxRegs];
+#pragma unroll
+    for (int r = 0; r < kIdxRegs; ++r) {
+        const int p = gl + r * G;
+        ix[r] = (p < it.len) ? a.idx[it.start + p] : 0;
+    }
+    for (int j = 0; j < it.len; j += 4) {
+        typename S::Raw raw[4];
+        bool ok[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int q = j + k;
+            const int r = q / G;
+            const int xr = (r == 0) ? ix[0] : (r == 1) ? ix[1] : (r == 2) ? ix[2] : ix[3];
+            ok[k] = q < it.len;
+            const int v = __shfl(xr, g * G + (q & (G - 1)), kWave);
+            if (ok[k] && col_ok)
+                raw[k] = S::load(z + (int64_t)v * a.ld + col);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!ok[k])
+                continue;
+            float x[EPL];
+            if (col_ok)
+                S::unpack(raw[k], x);
+            else
+                zero(x);
+            stat_add(st, x, a.op);
+        }
+    }
+    if (valid && col_ok)
+        stat_write(a.out + (int64_t)it.row * a.ld + col, st, a.op);
+}
+
+// Candidates split over several chunks: one wavefront merges the chunk
+// partials in slot order (group g takes slots g, g+Q, ..., then the groups
+// are combined lower first).
+template <int EPL, int G>
+__global__ __launch_bounds__(kBlock) void k_score_final(ScoreArgs a)
+{
+    constexpr int Q = kWave / G;
+    const int item = blockIdx.x * kWavesPerBlock + (int)(threadIdx.x / kWave);
+    if (item >= a.n_splits)
+        return;   // uniform over the wavefront
+    const int lane = threadIdx.x % kWave;
+    const int g = lane / G, gl = lane % G;
+    const int col = gl * EPL;
+    const bool col_ok = col < a.ld;
+    const Split sp = a.splits[item];
+    Stat<EPL> st;
+    stat_init(st, a.op);
+    for (int k = g; k < sp.n_slots; k += Q) {
+        const float *pp = a.partials + (int64_t)(sp.first_slot + k) * a.pstride;
+        float bm[EPL], bq[EPL];
+#pragma unroll
+        for (int i = 0; i < EPL; ++i) {
+            bm[i] = col_ok ? pp[col + i] : 0.0f;
+            bq[i] = col_ok ? pp[a.ld + col + i] : 0.0f;
+        }
+        stat_merge(st, pp[2 * a.ld], bm, bq, a.op);
+    }
+    stat_wave_combine<EPL, G>(st, g, a.op);
+    if (g == 0 && col_ok)
+        stat_write(a.out + (int64_t)sp.row * a.ld + col, st, a.op);
+}
+
+// ---------------------------------------------------------------------------
 // reciprocals (FP64) and per-star-edge scale arrays
 // ---------------------------------------------------------------------------
 
@@ -1427,3 +1692,63 @@ hnv_plan::~hnv_plan()
     for (void *ev : ev_pool)
         (void)hipEventDestroy(reinterpret_cast<hipEvent_t>(ev));
 }
+
+namespace hnv {
+// Launches the scoring kernels on a plan that hnv_host.cpp built and
+// uploaded (see hnv_score_candidates there).
+hnv_status dev_score(const ScorePlan &sp, const void *z, hnv_dtype dtype, int d, int op, float *out,
+                     hipStream_t s)
+{
+    int G = 1, E = 8;
+    lane_layout(d, dtype == HNV_BF16 ? 2 : 4, &G, &E);
+    ScoreArgs a{};
+    a.small = sp.small;
+    a.n_small = sp.n_small;
+    a.chunks = sp.chunks;
+    a.n_chunks = sp.n_chunks;
+    a.splits = sp.splits;
+    a.n_splits = sp.n_splits;
+    a.nb_chunk = (int32_t)blocks_for(sp.n_chunks, kWavesPerBlock);
+    a.nb_small = (int32_t)blocks_for(sp.n_small, kBlock / G);
+    a.idx = sp.idx;
+    a.z = z;
+    a.ld = d;
+    a.op = op;
+    a.out = out;
+    a.partials = sp.partials;
+    a.pstride = 2 * d + 8;
+    const unsigned grid = (unsigned)(a.nb_chunk + a.nb_small);
+    const unsigned fgrid = (unsigned)blocks_for(sp.n_splits, kWavesPerBlock);
+#define HNV_SCORE(TT, EE, GG)                                                   \
+    do {                                                                        \
+        if (grid)                                                               \
+            k_score<TT, EE, GG><<<grid, kBlock, 0, s>>>(a);                     \
+        if (fgrid)                                                              \
+            k_score_final<EE, GG><<<fgrid, kBlock, 0, s>>>(a);                  \
+    } while (0)
+#define HNV_SCORE_G(TT, EE)                                                     \
+    switch (G) {                                                                \
+    case 1: HNV_SCORE(TT, EE, 1); break;                                        \
+    case 2: HNV_SCORE(TT, EE, 2); break;                                        \
+    case 4: HNV_SCORE(TT, EE, 4); break;                                        \
+    case 8: HNV_SCORE(TT, EE, 8); break;                                        \
+    case 16: HNV_SCORE(TT, EE, 16); break;                                      \
+    case 32: HNV_SCORE(TT, EE, 32); break;                                      \
+    default: HNV_SCORE(TT, EE, 64); break;                                      \
+    }
+    if (dtype == HNV_BF16) {
+        HNV_SCORE_G(bf16_t, 8)
+    } else if (E == 4) {
+        HNV_SCORE_G(float, 4)
+    } else if (G == 16) {
+        HNV_SCORE(float, 8, 16);
+    } else if (G == 32) {
+        HNV_SCORE(float, 8, 32);
+    } else {
+        HNV_SCORE(float, 8, 64);
+    }
+#undef HNV_SCORE_G
+#undef HNV_SCORE
+    return dev_check("candidate scoring kernels");
+}
+}  // namespace hnv

@@ -397,3 +397,40 @@ def test_edge_first_sweeps(oracle_mod, H, dtype, small_max, chunk):
     with pytest.raises(HnvError) as ei:
         plan.sweep_adjoint(0, plan.empty(0), plan.empty(0), plan.empty(0), 0.5)
     assert ei.value.status == HNV_EUNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# hyperedge-prediction features
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype,d", [("f32", 128), ("bf16", 128), ("f32", 24), ("bf16", 64), ("f32", 512)])
+@pytest.mark.parametrize("op", ["variance", "mean", "min", "max"])
+def test_score_candidates(oracle_mod, H, dtype, d, op):
+    import torch
+    O = oracle_mod
+    rng = np.random.default_rng(d)
+    n_nodes = 3000
+    sizes = list(rng.integers(1, 12, size=400)) + [0, 600, 1500, 70, 64, 65, 512, 513, 2]
+    sets = [sorted(rng.choice(n_nodes, size=k, replace=False).tolist()) for k in sizes]
+    ptr = np.concatenate([[0], np.cumsum([len(s) for s in sets])]).astype(np.int64)
+    idx = np.array([v for s in sets for v in s], dtype=np.int32)
+    z = rng.standard_normal((n_nodes, d)).astype(np.float32) * 3 + 1
+    zin = z if dtype == "f32" else _bf16_round(z)
+    plan = H.ScorePlan(ptr, idx, n_nodes, d, dtype)
+    got = plan.score(_dev(z, dtype), op).cpu().numpy()
+    ref = O.score_candidates(zin, ptr, idx, op)
+    # repeatable bit for bit
+    np.testing.assert_array_equal(plan.score(_dev(z, dtype), op).cpu().numpy(), got)
+    # a member outside the matrix is rejected when planning
+    from paper_2103_09660_amd._lib import HNV_ERANGE, HnvError
+    bad = idx.copy()
+    bad[7] = n_nodes
+    with pytest.raises(HnvError) as ei:
+        H.ScorePlan(ptr, bad, n_nodes, d, dtype)
+    assert ei.value.status == HNV_ERANGE
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    ok = ~np.isnan(ref[:, 0])
+    if op in ("min", "max"):
+        np.testing.assert_array_equal(got[ok], ref[ok])
+    else:
+        _assert_close(got[ok], ref[ok], F32_TOL, f"score {op} {dtype} d={d}")
