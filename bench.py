@@ -245,6 +245,41 @@ def run_scoring(H, torch, hg, z_out, cfg, steps):
             "candidates_per_s": hg.n_edges / (ms / 1000.0), "stream_GBps": nbytes / (ms / 1000.0) / 1e9}
 
 
+def run_coarsening(H, torch, hg, cfg, hier, host_ms, reps=3):
+    """The hierarchy built on the GPU (Section 3.1, featureless), from the
+    finest level already in device memory to the coarsest, against the
+    library's host coarsening; the maps must agree bit for bit."""
+    lv0 = H.DeviceLevel.from_host(hier.levels[0], "cuda")
+    ws = torch.empty(H.coarsen_workspace_bytes(lv0.n_nodes, lv0.n_edges, lv0.nnz), dtype=torch.uint8,
+                     device="cuda")
+
+    def build():
+        levels, maps = [lv0], []
+        for _ in range(cfg.levels):
+            nrep, erep, c = H.coarsen_level_device(levels[-1], ws)
+            maps.append((nrep, erep))
+            levels.append(c)
+        return levels, maps
+
+    build()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        levels, maps = build()
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t) * 1e3)
+    same = all(np.array_equal(a.cpu().numpy(), m.node_rep) and np.array_equal(b.cpu().numpy(), m.edge_rep)
+               for (a, b), m in zip(maps, hier.maps))
+    same = same and all(np.array_equal(x.edge_idx.cpu().numpy(), y.edge_idx)
+                        for x, y in zip(levels[1:], hier.levels[1:]))
+    gpu_ms = min(times)
+    nnz = sum(l.nnz for l in hier.levels[:-1])
+    return {"steps": cfg.levels, "gpu_ms": gpu_ms, "host_ms": host_ms, "host_threads": min(64, int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())),
+            "speedup_vs_host": host_ms / gpu_ms, "incidences_per_s": nnz / (gpu_ms / 1000.0),
+            "maps_equal_host": bool(same), "timing": "wall clock, min of %d, synchronous per step" % reps}
+
+
 def cpu_baseline(O, hg, cfg, budget_s=12.0, max_sweeps=20, d=None):
     """The oracle as it stands, on a bounded sample of the same workload:
     Jacobi sweeps of the finest level at full width d (FP64), repeated until
@@ -295,6 +330,7 @@ def main():
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--no-differentiable", action="store_true",
                     help="skip the forward + backward (reverse-mode) leg")
+    ap.add_argument("--no-coarsening", action="store_true", help="skip the GPU coarsening leg")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -329,10 +365,16 @@ def main():
         f"({time.perf_counter() - t:.1f} s)")
     t = time.perf_counter()
     hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, cfg.levels)
+    host_coarsen_ms = (time.perf_counter() - t) * 1e3
     log(f"coarsened to {hier.n_levels} levels ({time.perf_counter() - t:.1f} s): "
         + ", ".join(f"({l.n_nodes},{l.n_edges},{l.nnz})" for l in hier.levels))
     zc = coarsest_embedding(cfg, hier.levels[-1].rows, cfg.d)
     zc_dev = torch.as_tensor(zc).cuda()
+    coarsening = None
+    if not args.no_coarsening:
+        coarsening = run_coarsening(H, torch, hg, cfg, hier, host_coarsen_ms)
+        log(f"coarsening: {coarsening}")
+        torch.cuda.empty_cache()
 
     large = args.config == "zipf-8m"
     dtypes = [d for d in (args.dtypes or ("bf16" if large else "bf16,f32")).split(",") if d]
@@ -401,6 +443,8 @@ def main():
                     / HBM_PEAK_GBS}
         line[f"{dtypes[0]}_over_{dt}"] = head["value"] / r["value"]
     line["fused_projection_sweep_avg_ms"] = head["fused_kernel_avg_ms"]
+    if coarsening is not None:
+        line["coarsening"] = coarsening
     if reverse is not None:
         line["reverse"] = reverse
     if not args.no_differentiable and args.config == "zipf-2m":

@@ -7,7 +7,8 @@
  * level by level back to the finest (Section 3.3, Algorithm 2).  This library
  * runs the refinement on the GPU: per level, the projection of the coarser
  * embedding and repeated smoothing sweeps over the star expansion H*
- * (Section 1.1), plus the reverse mode of both.  Coarsening runs on the host.
+ * (Section 1.1), plus the reverse mode of both.  Coarsening runs on the host
+ * or on the GPU, with identical results.
  *
  * Conventions used by every call
  *   - Star-expansion rows of a level: nodes first, then hyperedges.  Row v is
@@ -124,6 +125,29 @@ hnv_status hnv_validate_level(const hnv_level *level);
 hnv_status hnv_coarsen_level(const hnv_level *fine, int32_t *node_rep, int32_t *edge_rep,
                              int64_t *c_edge_ptr, int32_t *c_edge_idx, float *c_edge_w,
                              int64_t *c_n_nodes, int64_t *c_n_edges, int64_t *c_nnz);
+
+/* The same coarsening step on the GPU, with the same maps and coarse level
+ * bit for bit as hnv_coarsen_level (Section 3.1, Algorithm 1; the choice
+ * c(v) is an atomic minimum of each hyperedge's rank in the key order, so it
+ * does not depend on scheduling).  Arrays are in DEVICE memory with 32-bit
+ * offsets, so that the output of one call is the input of the next:
+ *   edge_ptr[n_edges+1] (int32), edge_idx[nnz], edge_w[n_edges] or NULL;
+ *   outputs node_rep[n_nodes], edge_rep[n_edges], c_edge_ptr[n_edges+1],
+ *   c_edge_idx[nnz], c_edge_w[n_edges] (may be NULL), sized for the fine
+ *   level and owned by the caller; only the first c_n_edges+1 / c_nnz /
+ *   c_n_edges entries of the coarse arrays are written.
+ * c_sizes: HOST int64[3] receiving coarse n_nodes, n_edges, nnz.  The call
+ * checks the input on the device first (same statuses as
+ * hnv_validate_level), then enqueues the kernels on `stream` and waits for
+ * the sizes, so it returns with the outputs complete.  workspace: DEVICE,
+ * >= hnv_coarsen_workspace_bytes, 256-byte aligned; its contents need not
+ * be initialised and are scratch afterwards.  Calls sharing a workspace on
+ * different streams race. */
+hnv_status hnv_coarsen_workspace_bytes(int64_t n_nodes, int64_t n_edges, int64_t nnz, size_t *bytes);
+hnv_status hnv_coarsen_level_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const int32_t *edge_ptr,
+                                    const int32_t *edge_idx, const float *edge_w, int32_t *node_rep,
+                                    int32_t *edge_rep, int32_t *c_edge_ptr, int32_t *c_edge_idx, float *c_edge_w,
+                                    int64_t *c_sizes, void *workspace, size_t ws_bytes, void *stream);
 
 /* Device workspace a plan over these levels needs, in bytes.  levels[0] is
  * the finest, levels[n_levels-1] the coarsest; maps[l] maps level l to l+1

@@ -6,6 +6,7 @@ plus its reverse mode -- runs in hand-written HIP kernels for gfx950 behind
 the C ABI of include/hnv.h.  This package is the thin Python binding.
 """
 from .api import (  # noqa: F401
+    DeviceLevel,
     Hierarchy,
     HostLevel,
     HostMap,
@@ -13,7 +14,10 @@ from .api import (  # noqa: F401
     ScorePlan,
     abi_version,
     cast,
+    coarsen_hierarchy_device,
     coarsen_level,
+    coarsen_level_device,
+    coarsen_workspace_bytes,
     last_error,
     plan_workspace_bytes,
     refine_level,

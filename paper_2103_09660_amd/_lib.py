@@ -53,6 +53,9 @@ _SIGS = {
     "hnv_last_error": (ctypes.c_char_p, []),
     "hnv_validate_level": (ctypes.c_int, [ctypes.POINTER(HnvLevel)]),
     "hnv_coarsen_level": (ctypes.c_int, [ctypes.POINTER(HnvLevel), i32p, i32p, i64p, i32p, f32p, i64p, i64p, i64p]),
+    "hnv_coarsen_workspace_bytes": (ctypes.c_int, [i64, i64, i64, ctypes.POINTER(ctypes.c_size_t)]),
+    "hnv_coarsen_level_device": (ctypes.c_int, [i64, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, i64p, vp,
+                                                ctypes.c_size_t, vp]),
     "hnv_plan_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(HnvLevel), ctypes.POINTER(HnvMap), ctypes.c_int,
                                                 ctypes.c_int, ctypes.c_int, ctypes.POINTER(HnvOptions),
                                                 ctypes.POINTER(ctypes.c_size_t)]),

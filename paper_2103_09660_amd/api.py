@@ -3,8 +3,8 @@
 Every function here marshals arguments into one C-ABI call; the refinement
 itself (projection, sweeps, residuals, reverse sweeps, reciprocals, casts)
 runs in the library's HIP kernels.  PyTorch provides device memory and the
-current HIP stream.  The hierarchy (coarsening, Section 3.1) is built on the
-host by the library's own C++ code.
+current HIP stream.  The hierarchy (coarsening, Section 3.1) is built by the
+library either on the host (C++) or on the GPU (HIP), with identical maps.
 """
 from __future__ import annotations
 
@@ -89,6 +89,80 @@ def coarsen_level(level: HostLevel):
     return HostMap(node_rep[: level.n_nodes].copy(), edge_rep[: level.n_edges].copy()), coarse
 
 
+@dataclasses.dataclass
+class DeviceLevel:
+    """A level in device memory: int32 offsets and members, float32 weights
+    or None (torch tensors on one GPU)."""
+    n_nodes: int
+    n_edges: int
+    nnz: int
+    edge_ptr: "object"                # torch.int32 [n_edges+1]
+    edge_idx: "object"                # torch.int32 [nnz]
+    edge_w: "object" = None           # torch.float32 [n_edges] or None
+
+    @classmethod
+    def from_host(cls, level: HostLevel, device=None) -> "DeviceLevel":
+        torch = _torch()
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        return cls(level.n_nodes, level.n_edges, level.nnz,
+                   torch.as_tensor(level.edge_ptr.astype(np.int32)).to(dev),
+                   torch.as_tensor(level.edge_idx).to(dev),
+                   None if level.edge_w is None else torch.as_tensor(level.edge_w).to(dev))
+
+    def to_host(self) -> HostLevel:
+        return HostLevel(self.n_nodes, self.n_edges, self.edge_ptr.cpu().numpy().astype(np.int64),
+                         self.edge_idx.cpu().numpy(), None if self.edge_w is None else self.edge_w.cpu().numpy())
+
+
+def coarsen_workspace_bytes(n_nodes: int, n_edges: int, nnz: int) -> int:
+    out = ctypes.c_size_t()
+    L.call("hnv_coarsen_workspace_bytes", n_nodes, n_edges, nnz, ctypes.byref(out))
+    return int(out.value)
+
+
+def coarsen_level_device(level: DeviceLevel, workspace=None):
+    """One featureless coarsening step on the GPU (library HIP): returns
+    (node_rep, edge_rep, coarse DeviceLevel), all on the level's device.
+    The call waits for the coarse sizes; ``workspace`` (a uint8 tensor of at
+    least :func:`coarsen_workspace_bytes`) may be reused between calls."""
+    torch = _torch()
+    dev = level.edge_ptr.device
+    for t, dt in ((level.edge_ptr, torch.int32), (level.edge_idx, torch.int32), (level.edge_w, torch.float32)):
+        if t is not None and (t.dtype != dt or not t.is_contiguous() or t.device != dev):
+            raise ValueError("level arrays must be contiguous int32 / float32 tensors on one device")
+    need = coarsen_workspace_bytes(level.n_nodes, level.n_edges, level.nnz)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    i32 = dict(dtype=torch.int32, device=dev)
+    node_rep = torch.empty(max(level.n_nodes, 1), **i32)
+    edge_rep = torch.empty(max(level.n_edges, 1), **i32)
+    c_ptr = torch.empty(level.n_edges + 1, **i32)
+    c_idx = torch.empty(max(level.nnz, 1), **i32)
+    c_w = None if level.edge_w is None else torch.empty(max(level.n_edges, 1), dtype=torch.float32, device=dev)
+    sizes = (ctypes.c_int64 * 3)()
+    with torch.cuda.device(dev):
+        L.call("hnv_coarsen_level_device", level.n_nodes, level.n_edges, level.nnz, _ptr(level.edge_ptr),
+               _ptr(level.edge_idx), _ptr(level.edge_w), _ptr(node_rep), _ptr(edge_rep), _ptr(c_ptr), _ptr(c_idx),
+               _ptr(c_w), ctypes.cast(sizes, L.i64p), _ptr(workspace), workspace.numel(), _stream(dev))
+    nv, ne, nz = int(sizes[0]), int(sizes[1]), int(sizes[2])
+    coarse = DeviceLevel(nv, ne, nz, c_ptr[: ne + 1], c_idx[:nz], None if c_w is None else c_w[:ne])
+    return node_rep[: level.n_nodes], edge_rep[: level.n_edges], coarse
+
+
+def coarsen_hierarchy_device(level: DeviceLevel, n_coarsen: int):
+    """n_coarsen GPU coarsening steps from ``level``, one shared workspace:
+    returns (device levels 0..n_coarsen, [(node_rep, edge_rep)] per step)."""
+    torch = _torch()
+    ws = torch.empty(coarsen_workspace_bytes(level.n_nodes, level.n_edges, level.nnz), dtype=torch.uint8,
+                     device=level.edge_ptr.device)
+    levels, maps = [level], []
+    for _ in range(n_coarsen):
+        nrep, erep, coarse = coarsen_level_device(levels[-1], ws)
+        maps.append((nrep, erep))
+        levels.append(coarse)
+    return levels, maps
+
+
 class Hierarchy:
     """Levels 0 (finest) .. L (coarsest) and the maps between them."""
 
@@ -98,9 +172,16 @@ class Hierarchy:
         self.maps = maps
 
     @classmethod
-    def build(cls, n_nodes, n_edges, edge_ptr, edge_idx, edge_w, n_coarsen: int) -> "Hierarchy":
+    def build(cls, n_nodes, n_edges, edge_ptr, edge_idx, edge_w, n_coarsen: int, device=None) -> "Hierarchy":
+        """Coarsens n_coarsen times, on the host, or on ``device`` (a GPU)
+        with the result copied back (a plan is built from host levels)."""
         levels = [HostLevel(n_nodes, n_edges, edge_ptr, edge_idx, edge_w)]
         maps = []
+        if device is not None:
+            dl, dm = coarsen_hierarchy_device(DeviceLevel.from_host(levels[0], device), n_coarsen)
+            levels += [x.to_host() for x in dl[1:]]
+            maps = [HostMap(a.cpu().numpy(), b.cpu().numpy()) for a, b in dm]
+            return cls(levels, maps)
         for _ in range(n_coarsen):
             m, c = coarsen_level(levels[-1])
             maps.append(m)
