@@ -149,6 +149,33 @@ hnv_status hnv_coarsen_level_device(int64_t n_nodes, int64_t n_edges, int64_t nn
                                     int32_t *edge_rep, int32_t *c_edge_ptr, int32_t *c_edge_idx, float *c_edge_w,
                                     int64_t *c_sizes, void *workspace, size_t ws_bytes, void *stream);
 
+/* The same step with node features (Section 3.1, Algorithm 1 with X):
+ * ComputeEdgeFeature takes f(e) = the mean of the member rows of X;
+ * AssignHyperedge takes c(v) = the hyperedge of N(v) with the largest cosine
+ * of f(e) and f(v), and among equal scores the first in the featureless
+ * order above (in place of the paper's random choice); the coarse feature
+ * matrix X' gives each coarse node the sum of its fine nodes' rows (merged
+ * bags of words).  Maps and coarse level as hnv_coarsen_level_device.
+ *   x: DEVICE int32 [n_nodes x k], row-major, 16-byte aligned: counts >= 0
+ *      whose total is below 2^31 (checked; HNV_EINVAL otherwise), k a
+ *      multiple of 4 up to 65536 (pad with zero columns: they change no
+ *      cosine and no sum).
+ *   c_x: DEVICE int32 [n_nodes x k], 16-byte aligned: the first c_n_nodes
+ *      rows receive X'.
+ * The cosine is compared exactly as far as the arithmetic goes: member sums,
+ * dot products d and squared norms |s_e|^2 are exact integers, the score
+ * d|d| / |s_e|^2 (an increasing function of the cosine for a fixed node) is
+ * evaluated in IEEE FP64 with one rounding per operation, and a hyperedge
+ * with s_e = 0 scores 0.  workspace: >= hnv_coarsen_features_workspace_bytes. */
+hnv_status hnv_coarsen_features_workspace_bytes(int64_t n_nodes, int64_t n_edges, int64_t nnz, int k,
+                                                size_t *bytes);
+hnv_status hnv_coarsen_level_features_device(int64_t n_nodes, int64_t n_edges, int64_t nnz,
+                                             const int32_t *edge_ptr, const int32_t *edge_idx,
+                                             const float *edge_w, const int32_t *x, int k, int32_t *node_rep,
+                                             int32_t *edge_rep, int32_t *c_edge_ptr, int32_t *c_edge_idx,
+                                             float *c_edge_w, int32_t *c_x, int64_t *c_sizes, void *workspace,
+                                             size_t ws_bytes, void *stream);
+
 /* Device workspace a plan over these levels needs, in bytes.  levels[0] is
  * the finest, levels[n_levels-1] the coarsest; maps[l] maps level l to l+1
  * (n_levels-1 entries, may be NULL if n_levels == 1).  d: embedding width,

@@ -86,43 +86,17 @@ static int cmp_i32(const void *x, const void *y)
     return (a > b) - (a < b);
 }
 
-/* One application of Algorithm 1's loop body without features.
- *   node_rep[n_nodes]   coarse node of each fine node (rep(v))
- *   edge_rep[n_edges]   coarse hyperedge of each fine hyperedge, -1 if removed
- *   c_eptr[n_edges+1], c_eidx[nnz], c_w[n_edges]: coarse CSR (sizes bounded
- *   by the fine ones); *out_nodes, *out_edges, *out_nnz receive the sizes.
- * Returns 0, or -1 if memory ran out. */
-int oracle_coarsen(int64_t n_nodes, int64_t n_edges, const int64_t *eptr,
-                   const int32_t *eidx, const float *w, int32_t *node_rep,
-                   int32_t *edge_rep, int64_t *out_nodes, int64_t *out_edges,
-                   int64_t *out_nnz, int64_t *c_eptr, int32_t *c_eidx, float *c_w)
+/* Algorithm 1's steps after AssignHyperedge, given assigned[v] = c(v) (-1 for
+ * an isolated node): FindAssignedNodes + Merge + addNode, addHedge, addEdge.
+ * Outputs as for oracle_coarsen below. */
+static void merge_assigned(int64_t n_nodes, int64_t n_edges, const int64_t *eptr, const int32_t *eidx,
+                           const float *w, const int32_t *assigned, int32_t *group_id, int32_t *scratch,
+                           int32_t *node_rep, int32_t *edge_rep, int64_t *out_nodes, int64_t *out_edges,
+                           int64_t *out_nnz, int64_t *c_eptr, int32_t *c_eidx, float *c_w)
 {
-    int64_t nnz = eptr[n_edges];
-    int64_t *nptr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_nodes + 1));
-    int32_t *nidx = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
-    int32_t *assigned = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_nodes > 0 ? n_nodes : 1));
-    int32_t *group_id = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_edges > 0 ? n_edges : 1));
-    int32_t *scratch = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
-    if (!nptr || !nidx || !assigned || !group_id || !scratch) {
-        free(nptr); free(nidx); free(assigned); free(group_id); free(scratch);
-        return -1;
-    }
-    oracle_transpose(n_nodes, n_edges, eptr, eidx, nptr, nidx);
-
-    /* AssignHyperedge: c(v) = best hyperedge in N(v); none for isolated v. */
-    for (int64_t v = 0; v < n_nodes; ++v) {
-        int32_t best = -1;
-        for (int64_t j = nptr[v]; j < nptr[v + 1]; ++j) {
-            int32_t e = nidx[j];
-            if (best < 0 || better_edge(e, best, eptr, w))
-                best = e;
-        }
-        assigned[v] = best;
-    }
-
-    /* FindAssignedNodes + Merge + addNode: the nodes assigned to one
-     * hyperedge become one coarse node; an isolated node is its own group.
-     * Coarse ids are issued in order of each group's smallest fine node. */
+    /* The nodes assigned to one hyperedge become one coarse node; an
+     * isolated node is its own group.  Coarse ids are issued in order of
+     * each group's smallest fine node. */
     for (int64_t e = 0; e < n_edges; ++e)
         group_id[e] = -1;
     int32_t next = 0;
@@ -169,8 +143,151 @@ int oracle_coarsen(int64_t n_nodes, int64_t n_edges, const int64_t *eptr,
             c_w[edge_rep[e]] = w ? w[e] : 1.0f;
     }
     *out_nnz = pos;
+}
 
+/* One application of Algorithm 1's loop body without features.
+ *   node_rep[n_nodes]   coarse node of each fine node (rep(v))
+ *   edge_rep[n_edges]   coarse hyperedge of each fine hyperedge, -1 if removed
+ *   c_eptr[n_edges+1], c_eidx[nnz], c_w[n_edges]: coarse CSR (sizes bounded
+ *   by the fine ones); *out_nodes, *out_edges, *out_nnz receive the sizes.
+ * Returns 0, or -1 if memory ran out. */
+int oracle_coarsen(int64_t n_nodes, int64_t n_edges, const int64_t *eptr,
+                   const int32_t *eidx, const float *w, int32_t *node_rep,
+                   int32_t *edge_rep, int64_t *out_nodes, int64_t *out_edges,
+                   int64_t *out_nnz, int64_t *c_eptr, int32_t *c_eidx, float *c_w)
+{
+    int64_t nnz = eptr[n_edges];
+    int64_t *nptr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_nodes + 1));
+    int32_t *nidx = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    int32_t *assigned = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_nodes > 0 ? n_nodes : 1));
+    int32_t *group_id = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_edges > 0 ? n_edges : 1));
+    int32_t *scratch = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!nptr || !nidx || !assigned || !group_id || !scratch) {
+        free(nptr); free(nidx); free(assigned); free(group_id); free(scratch);
+        return -1;
+    }
+    oracle_transpose(n_nodes, n_edges, eptr, eidx, nptr, nidx);
+
+    /* AssignHyperedge: c(v) = best hyperedge in N(v); none for isolated v. */
+    for (int64_t v = 0; v < n_nodes; ++v) {
+        int32_t best = -1;
+        for (int64_t j = nptr[v]; j < nptr[v + 1]; ++j) {
+            int32_t e = nidx[j];
+            if (best < 0 || better_edge(e, best, eptr, w))
+                best = e;
+        }
+        assigned[v] = best;
+    }
+    merge_assigned(n_nodes, n_edges, eptr, eidx, w, assigned, group_id, scratch, node_rep, edge_rep, out_nodes,
+                   out_edges, out_nnz, c_eptr, c_eidx, c_w);
     free(nptr); free(nidx); free(assigned); free(group_id); free(scratch);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Coarsening, one level, with node features (Section 3.1, Algorithm 1)     */
+/* ------------------------------------------------------------------------ */
+
+/* The cosine score of hyperedge e for node v, as the value the argmax is
+ * taken on.  f(e) is the mean of the member features (ComputeEdgeFeature);
+ * the cosine of f(e) and f(v) equals d / (|s_e| |x_v|) with s_e the member
+ * sum, d = s_e . x_v, because the factor 1/|e| cancels.  The features are
+ * bag-of-words counts, so d and |s_e|^2 are exact integers.  For a fixed v
+ * the value q = d |d| / |s_e|^2 equals cos |cos| |x_v|^2, an increasing
+ * function of the cosine; it is evaluated in IEEE FP64 (one product, one
+ * quotient, each rounded once).  q = 0 when s_e = 0 (the cosine is then
+ * undefined and no hyperedge is preferred on features). */
+static double cosine_score(int64_t d, int64_t s2)
+{
+    if (s2 == 0)
+        return 0.0;
+    double dd = (double)d;
+    double num = dd * fabs(dd);
+    return num / (double)s2;
+}
+
+/* Algorithm 1's loop body once with node features X [n_nodes x k] (int32
+ * counts, >= 0, total below 2^31).
+ *   ComputeEdgeFeature: s_e = sum of member rows (the mean up to 1/|e|).
+ *   AssignHyperedge:    c(v) = argmax over e in N(v) of the cosine of f(e)
+ *                       and f(v); equal scores are broken by the featureless
+ *                       order (heavier, then fewer members, then lower id),
+ *                       in place of the paper's random choice.
+ *   Merge etc.:         as without features.
+ *   X':                 each coarse node's row is the sum of its fine
+ *                       nodes' rows (the merged bags of words).
+ * Other arguments as oracle_coarsen; c_x[n_nodes x k] receives X' (the
+ * first *out_nodes rows).  Returns 0, or -1 if memory ran out. */
+int oracle_coarsen_features(int64_t n_nodes, int64_t n_edges, const int64_t *eptr, const int32_t *eidx,
+                            const float *w, const int32_t *x, int k, int32_t *node_rep, int32_t *edge_rep,
+                            int64_t *out_nodes, int64_t *out_edges, int64_t *out_nnz, int64_t *c_eptr,
+                            int32_t *c_eidx, float *c_w, int32_t *c_x)
+{
+    int64_t nnz = eptr[n_edges];
+    int64_t *nptr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_nodes + 1));
+    int32_t *nidx = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    int32_t *assigned = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_nodes > 0 ? n_nodes : 1));
+    int32_t *group_id = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_edges > 0 ? n_edges : 1));
+    int32_t *scratch = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    /* member sums fit int32: the counts total below 2^31 */
+    int32_t *s = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_edges > 0 ? n_edges : 1) * (size_t)k);
+    int64_t *s2 = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_edges > 0 ? n_edges : 1));
+    if (!nptr || !nidx || !assigned || !group_id || !scratch || !s || !s2) {
+        free(nptr); free(nidx); free(assigned); free(group_id); free(scratch); free(s); free(s2);
+        return -1;
+    }
+    oracle_transpose(n_nodes, n_edges, eptr, eidx, nptr, nidx);
+
+    /* ComputeEdgeFeature for every hyperedge, and |s_e|^2. */
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t e = 0; e < n_edges; ++e) {
+        int32_t *se = s + (size_t)e * k;
+        for (int j = 0; j < k; ++j)
+            se[j] = 0;
+        for (int64_t m = eptr[e]; m < eptr[e + 1]; ++m) {
+            const int32_t *xv = x + (size_t)eidx[m] * k;
+            for (int j = 0; j < k; ++j)
+                se[j] += xv[j];
+        }
+        int64_t q = 0;
+        for (int j = 0; j < k; ++j)
+            q += (int64_t)se[j] * se[j];
+        s2[e] = q;
+    }
+
+    /* AssignHyperedge: the best cosine over N(v), ties by the fixed order. */
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t v = 0; v < n_nodes; ++v) {
+        const int32_t *xv = x + (size_t)v * k;
+        int32_t best = -1;
+        double best_q = 0.0;
+        for (int64_t j = nptr[v]; j < nptr[v + 1]; ++j) {
+            int32_t e = nidx[j];
+            const int32_t *se = s + (size_t)e * k;
+            int64_t d = 0;
+            for (int c = 0; c < k; ++c)
+                d += (int64_t)se[c] * xv[c];
+            double q = cosine_score(d, s2[e]);
+            if (best < 0 || q > best_q || (q == best_q && better_edge(e, best, eptr, w))) {
+                best = e;
+                best_q = q;
+            }
+        }
+        assigned[v] = best;
+    }
+    merge_assigned(n_nodes, n_edges, eptr, eidx, w, assigned, group_id, scratch, node_rep, edge_rep, out_nodes,
+                   out_edges, out_nnz, c_eptr, c_eidx, c_w);
+
+    /* X': the merged nodes' rows summed (int32 suffices: the counts total
+     * below 2^31). */
+    memset(c_x, 0, sizeof(int32_t) * (size_t)*out_nodes * (size_t)k);
+    for (int64_t v = 0; v < n_nodes; ++v) {
+        int32_t *dst = c_x + (size_t)node_rep[v] * k;
+        const int32_t *xv = x + (size_t)v * k;
+        for (int j = 0; j < k; ++j)
+            dst[j] += xv[j];
+    }
+    free(nptr); free(nidx); free(assigned); free(group_id); free(scratch); free(s); free(s2);
     return 0;
 }
 

@@ -7,7 +7,8 @@ does.  It shares no code with the GPU library: the arithmetic lives in
 ``hnv_oracle.c`` (plain C, FP64) and the driver below follows the paper's
 three phases in order:
 
-* Algorithm 1 (Section 3.1), one featureless coarsening step per level;
+* Algorithm 1 (Section 3.1), one coarsening step per level, featureless or
+  with bag-of-words node features (cosine assignment, merged feature rows);
 * the projection rule at the end of Section 3.3 (a merged node's embedding is
   given to every fine node of its set);
 * Algorithm 2 (Section 3.3), ``k`` smoothing sweeps per level, from the
@@ -66,6 +67,10 @@ def _L():
         lib.oracle_coarsen.restype = ctypes.c_int
         lib.oracle_coarsen.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _f32p, _i32p, _i32p,
                                        _i64p, _i64p, _i64p, _i64p, _i32p, _f32p]
+        lib.oracle_coarsen_features.restype = ctypes.c_int
+        lib.oracle_coarsen_features.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _f32p, _i32p,
+                                                ctypes.c_int, _i32p, _i32p, _i64p, _i64p, _i64p, _i64p, _i32p,
+                                                _f32p, _i32p]
         lib.oracle_rowmap.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _i32p, _i32p,
                                       ctypes.c_int64, _i64p]
         lib.oracle_project.argtypes = [ctypes.c_int64, _i64p, ctypes.c_int64, _f64p, _f64p]
@@ -146,6 +151,47 @@ def coarsen_level(lv: Level) -> Coarsening:
     coarse = Level(nv.value, ne_, c_eptr[: ne_ + 1].copy(), c_eidx[:nz_].copy(),
                    None if lv.w is None else c_w[:ne_].copy())
     return Coarsening(node_rep[: lv.n_nodes].copy(), edge_rep[: lv.n_edges].copy(), coarse)
+
+
+def coarsen_level_features(lv: Level, x: np.ndarray):
+    """Algorithm 1's loop body once with node features (Section 3.1): x is
+    the int32 [n_nodes x k] bag-of-words count matrix.  Returns
+    (Coarsening, X' int32 [coarse n_nodes x k])."""
+    x = np.ascontiguousarray(x, dtype=np.int32)
+    assert x.ndim == 2 and x.shape[0] == lv.n_nodes
+    k = x.shape[1]
+    nnz = lv.nnz
+    node_rep = np.zeros(max(lv.n_nodes, 1), dtype=np.int32)
+    edge_rep = np.zeros(max(lv.n_edges, 1), dtype=np.int32)
+    c_eptr = np.zeros(lv.n_edges + 1, dtype=np.int64)
+    c_eidx = np.zeros(max(nnz, 1), dtype=np.int32)
+    c_w = np.zeros(max(lv.n_edges, 1), dtype=np.float32)
+    c_x = np.zeros((max(lv.n_nodes, 1), k), dtype=np.int32)
+    nv = ctypes.c_int64(); ne = ctypes.c_int64(); nz = ctypes.c_int64()
+    rc = _L().oracle_coarsen_features(lv.n_nodes, lv.n_edges, _p(lv.eptr, _i64p), _p(lv.eidx, _i32p),
+                                      _p(lv.w, _f32p), _p(x, _i32p), k, _p(node_rep, _i32p), _p(edge_rep, _i32p),
+                                      ctypes.byref(nv), ctypes.byref(ne), ctypes.byref(nz), _p(c_eptr, _i64p),
+                                      _p(c_eidx, _i32p), _p(c_w, _f32p), _p(c_x, _i32p))
+    if rc != 0:
+        raise MemoryError("oracle_coarsen_features")
+    ne_, nz_ = ne.value, nz.value
+    coarse = Level(nv.value, ne_, c_eptr[: ne_ + 1].copy(), c_eidx[:nz_].copy(),
+                   None if lv.w is None else c_w[:ne_].copy())
+    return Coarsening(node_rep[: lv.n_nodes].copy(), edge_rep[: lv.n_edges].copy(), coarse), c_x[: nv.value].copy()
+
+
+def build_hierarchy_features(n_nodes, n_edges, eptr, eidx, w, x, n_coarsen: int):
+    """Levels 0 .. n_coarsen with feature-based coarsening; also returns the
+    feature matrix of every level."""
+    levels = [Level(n_nodes, n_edges, eptr, eidx, w)]
+    feats = [np.ascontiguousarray(x, dtype=np.int32)]
+    maps: List[Coarsening] = []
+    for _ in range(n_coarsen):
+        c, xc = coarsen_level_features(levels[-1], feats[-1])
+        maps.append(c)
+        levels.append(c.coarse)
+        feats.append(xc)
+    return levels, maps, feats
 
 
 def build_hierarchy(n_nodes, n_edges, eptr, eidx, w, n_coarsen: int):

@@ -14,9 +14,12 @@ from .api import (  # noqa: F401
     ScorePlan,
     abi_version,
     cast,
+    coarsen_features_workspace_bytes,
     coarsen_hierarchy_device,
+    coarsen_hierarchy_features_device,
     coarsen_level,
     coarsen_level_device,
+    coarsen_level_features_device,
     coarsen_workspace_bytes,
     last_error,
     plan_workspace_bytes,

@@ -56,6 +56,10 @@ _SIGS = {
     "hnv_coarsen_workspace_bytes": (ctypes.c_int, [i64, i64, i64, ctypes.POINTER(ctypes.c_size_t)]),
     "hnv_coarsen_level_device": (ctypes.c_int, [i64, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, i64p, vp,
                                                 ctypes.c_size_t, vp]),
+    "hnv_coarsen_features_workspace_bytes": (ctypes.c_int, [i64, i64, i64, ctypes.c_int,
+                                                            ctypes.POINTER(ctypes.c_size_t)]),
+    "hnv_coarsen_level_features_device": (ctypes.c_int, [i64, i64, i64, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp,
+                                                         vp, vp, vp, i64p, vp, ctypes.c_size_t, vp]),
     "hnv_plan_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(HnvLevel), ctypes.POINTER(HnvMap), ctypes.c_int,
                                                 ctypes.c_int, ctypes.c_int, ctypes.POINTER(HnvOptions),
                                                 ctypes.POINTER(ctypes.c_size_t)]),

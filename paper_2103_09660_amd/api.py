@@ -149,6 +149,58 @@ def coarsen_level_device(level: DeviceLevel, workspace=None):
     return node_rep[: level.n_nodes], edge_rep[: level.n_edges], coarse
 
 
+def coarsen_features_workspace_bytes(n_nodes: int, n_edges: int, nnz: int, k: int) -> int:
+    out = ctypes.c_size_t()
+    L.call("hnv_coarsen_features_workspace_bytes", n_nodes, n_edges, nnz, k, ctypes.byref(out))
+    return int(out.value)
+
+
+def coarsen_level_features_device(level: DeviceLevel, x, workspace=None):
+    """One coarsening step on the GPU driven by node features (bag-of-words
+    counts, int32 [n_nodes x k], k a multiple of 4): returns (node_rep,
+    edge_rep, coarse DeviceLevel, coarse features int32 [coarse n_nodes x k])."""
+    torch = _torch()
+    dev = level.edge_ptr.device
+    if x.dtype != torch.int32 or x.dim() != 2 or x.shape[0] != level.n_nodes or not x.is_contiguous() \
+            or x.device != dev:
+        raise ValueError("x must be a contiguous int32 [n_nodes x k] tensor on the level's device")
+    k = int(x.shape[1])
+    need = coarsen_features_workspace_bytes(level.n_nodes, level.n_edges, level.nnz, k)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    i32 = dict(dtype=torch.int32, device=dev)
+    node_rep = torch.empty(max(level.n_nodes, 1), **i32)
+    edge_rep = torch.empty(max(level.n_edges, 1), **i32)
+    c_ptr = torch.empty(level.n_edges + 1, **i32)
+    c_idx = torch.empty(max(level.nnz, 1), **i32)
+    c_w = None if level.edge_w is None else torch.empty(max(level.n_edges, 1), dtype=torch.float32, device=dev)
+    c_x = torch.empty((max(level.n_nodes, 1), k), **i32)
+    sizes = (ctypes.c_int64 * 3)()
+    with torch.cuda.device(dev):
+        L.call("hnv_coarsen_level_features_device", level.n_nodes, level.n_edges, level.nnz, _ptr(level.edge_ptr),
+               _ptr(level.edge_idx), _ptr(level.edge_w), _ptr(x), k, _ptr(node_rep), _ptr(edge_rep), _ptr(c_ptr),
+               _ptr(c_idx), _ptr(c_w), _ptr(c_x), ctypes.cast(sizes, L.i64p), _ptr(workspace), workspace.numel(),
+               _stream(dev))
+    nv, ne, nz = int(sizes[0]), int(sizes[1]), int(sizes[2])
+    coarse = DeviceLevel(nv, ne, nz, c_ptr[: ne + 1], c_idx[:nz], None if c_w is None else c_w[:ne])
+    return node_rep[: level.n_nodes], edge_rep[: level.n_edges], coarse, c_x[:nv]
+
+
+def coarsen_hierarchy_features_device(level: DeviceLevel, x, n_coarsen: int):
+    """n_coarsen feature-driven GPU coarsening steps, one shared workspace:
+    returns (device levels, [(node_rep, edge_rep)], feature matrices)."""
+    torch = _torch()
+    ws = torch.empty(coarsen_features_workspace_bytes(level.n_nodes, level.n_edges, level.nnz, int(x.shape[1])),
+                     dtype=torch.uint8, device=level.edge_ptr.device)
+    levels, maps, feats = [level], [], [x]
+    for _ in range(n_coarsen):
+        nrep, erep, coarse, xc = coarsen_level_features_device(levels[-1], feats[-1], ws)
+        maps.append((nrep, erep))
+        levels.append(coarse)
+        feats.append(xc)
+    return levels, maps, feats
+
+
 def coarsen_hierarchy_device(level: DeviceLevel, n_coarsen: int):
     """n_coarsen GPU coarsening steps from ``level``, one shared workspace:
     returns (device levels 0..n_coarsen, [(node_rep, edge_rep)] per step)."""

@@ -1,6 +1,6 @@
-// Featureless coarsening of one level on the GPU (Section 3.1, Algorithm 1),
-// with the same reading as the host coarsening in hnv_host.cpp and the same
-// maps bit for bit:
+// Coarsening of one level on the GPU (Section 3.1, Algorithm 1).  The
+// featureless form has the same reading as the host coarsening in
+// hnv_host.cpp and the same maps bit for bit:
 //   1. every hyperedge gets a rank in the order (weight descending, size
 //      ascending, id ascending): a stable radix sort of a 64-bit key
 //      (inverted weight bits, size) over the ids;
@@ -16,6 +16,14 @@
 //      coarse offsets, then the distinct values copied.
 // Integer work only (the key compares FP32 weights through their bit
 // patterns, which order like the values for positive finite floats).
+//
+// With node features (bag-of-words counts), step 2 instead takes, per node,
+// the hyperedge of largest cosine between the hyperedge feature (the mean of
+// its members' rows) and the node's row, equal scores going to the least
+// rank of step 1; the coarse node's row is the sum of its fine nodes' rows.
+// The member sums, the dot products and the squared norms are exact
+// integers, and the score d|d|/|s_e|^2 is one IEEE FP64 product and one
+// quotient, so the choice does not depend on summation order.
 #include <hip/hip_runtime.h>
 
 #include <hipcub/hipcub.hpp>
@@ -220,6 +228,165 @@ __global__ void k_sizes(const int32_t *__restrict__ gflag, const int32_t *__rest
     c_ptr[ne] = (int32_t)nz;
 }
 
+// ---------------------------------------------------------------------------
+// feature-based assignment (bag-of-words counts, int32 [rows x k], k % 4 == 0)
+// ---------------------------------------------------------------------------
+
+// counts must be >= 0 (flag bit 4) and their total below 2^31 (checked on
+// the host from `total`); with that bound every sum, product and dot below
+// fits its integer type exactly
+__global__ __launch_bounds__(kThreads) void k_fcheck(const int4 *__restrict__ x, int64_t n4, int *__restrict__ flag,
+                                                     unsigned long long *__restrict__ total)
+{
+    __shared__ unsigned long long part[kThreads / kWave];
+    unsigned long long sum = 0;
+    int neg = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n4; i += (int64_t)gridDim.x * kThreads) {
+        const int4 v = x[i];
+        neg |= (v.x | v.y | v.z | v.w) < 0;
+        sum += (unsigned long long)(uint32_t)v.x + (uint32_t)v.y + (uint32_t)v.z + (uint32_t)v.w;
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1)
+        sum += __shfl_xor(sum, o);
+    if ((threadIdx.x & (kWave - 1)) == 0)
+        part[threadIdx.x / kWave] = sum;
+    if (neg)
+        atomicOr(flag, 16);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long b = 0;
+        for (int w = 0; w < kThreads / kWave; ++w)
+            b += part[w];
+        atomicAdd(total, b);
+    }
+}
+
+// out[r] = sum of the rows x[idx[j]], j in [ptr[r], ptr[r+1]), for r below
+// *limit (all rows if limit is NULL); one wavefront per row, 4 counts per
+// lane per pass.  SQ: also sq[r] = |out[r]|^2 (int64).
+template <bool SQ>
+__global__ __launch_bounds__(kThreads) void k_rowsum(const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                                     const int32_t *__restrict__ x, int k, int64_t n_rows,
+                                                     const int64_t *__restrict__ limit, int32_t *__restrict__ out,
+                                                     int64_t *__restrict__ sq)
+{
+    const int64_t r = (int64_t)blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (r >= n_rows || (limit && r >= *limit))
+        return;
+    const int32_t a = ptr[r], b = ptr[r + 1];
+    int64_t q = 0;
+    for (int c = lane * 4; c < k; c += kWave * 4) {
+        int4 acc = make_int4(0, 0, 0, 0);
+        for (int32_t j = a; j < b; ++j) {
+            const int4 v = *reinterpret_cast<const int4 *>(x + (int64_t)idx[j] * k + c);
+            acc.x += v.x;
+            acc.y += v.y;
+            acc.z += v.z;
+            acc.w += v.w;
+        }
+        *reinterpret_cast<int4 *>(out + r * k + c) = acc;
+        if (SQ)
+            q += (int64_t)acc.x * acc.x + (int64_t)acc.y * acc.y + (int64_t)acc.z * acc.z + (int64_t)acc.w * acc.w;
+    }
+    if (SQ) {
+        for (int o = kWave / 2; o > 0; o >>= 1)
+            q += __shfl_xor(q, o);
+        if (lane == 0)
+            sq[r] = q;
+    }
+}
+
+// IEEE FP64 cosine score d|d| / |s_e|^2 (0 when s_e = 0); d and |s_e|^2 are
+// exact integers, the product and the quotient are each rounded once
+__device__ inline double cosine_score(int64_t d, int64_t s2)
+{
+    if (s2 == 0)
+        return 0.0;
+    const double dd = (double)d;
+    const double num = dd * fabs(dd);
+    return num / (double)s2;
+}
+
+// order-preserving map of a double onto unsigned 64-bit integers
+__device__ inline unsigned long long ordered_bits(double q)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(q);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// per incidence (e, v): q = cosine score of e for v, kept in CSR order;
+// bestq[v] = max over v's incidences (atomic max: order-independent)
+__global__ __launch_bounds__(kThreads) void k_qscore(const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                                     const int32_t *__restrict__ s, const int64_t *__restrict__ s2,
+                                                     const int32_t *__restrict__ x, int k, int64_t n_edges,
+                                                     double *__restrict__ q, unsigned long long *__restrict__ bestq)
+{
+    const int64_t e = (int64_t)blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (e >= n_edges)
+        return;
+    const int32_t *se = s + e * k;
+    const int64_t n2 = s2[e];
+    for (int32_t j = ptr[e]; j < ptr[e + 1]; ++j) {
+        const int32_t v = idx[j];
+        const int32_t *xv = x + (int64_t)v * k;
+        int64_t d = 0;
+        for (int c = lane * 4; c < k; c += kWave * 4) {
+            const int4 f = *reinterpret_cast<const int4 *>(se + c);
+            const int4 u = *reinterpret_cast<const int4 *>(xv + c);
+            d += (int64_t)f.x * u.x + (int64_t)f.y * u.y + (int64_t)f.z * u.z + (int64_t)f.w * u.w;
+        }
+        for (int o = kWave / 2; o > 0; o >>= 1)
+            d += __shfl_xor(d, o);
+        if (lane == 0) {
+            const double sc = cosine_score(d, n2);
+            q[j] = sc;
+            atomicMax(bestq + v, ordered_bits(sc));
+        }
+    }
+}
+
+// best[v] = least rank among v's hyperedges whose score equals bestq[v]
+__global__ __launch_bounds__(kThreads) void k_best_feat(const int32_t *__restrict__ ptr,
+                                                        const int32_t *__restrict__ idx,
+                                                        const int32_t *__restrict__ rank,
+                                                        const double *__restrict__ q,
+                                                        const unsigned long long *__restrict__ bestq, int64_t n_edges,
+                                                        int32_t *__restrict__ best)
+{
+    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= n_edges)
+        return;
+    const int32_t r = rank[e];
+    for (int32_t j = ptr[e]; j < ptr[e + 1]; ++j) {
+        const int32_t v = idx[j];
+        if (ordered_bits(q[j]) == bestq[v])
+            atomicMin(best + v, r);
+    }
+}
+
+// coarse-node member lists: count, then place (the order inside a group is
+// free; the sums over it are exact integers)
+__global__ __launch_bounds__(kThreads) void k_group_count(const int32_t *__restrict__ node_rep, int64_t n_nodes,
+                                                          int32_t *__restrict__ gcount)
+{
+    const int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (v < n_nodes)
+        atomicAdd(gcount + node_rep[v], 1);
+}
+
+__global__ __launch_bounds__(kThreads) void k_group_fill(const int32_t *__restrict__ node_rep,
+                                                         const int32_t *__restrict__ gptr, int64_t n_nodes,
+                                                         int32_t *__restrict__ gcur, int32_t *__restrict__ gnodes)
+{
+    const int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (v >= n_nodes)
+        return;
+    const int32_t g = node_rep[v];
+    gnodes[gptr[g] + atomicAdd(gcur + g, 1)] = (int32_t)v;
+}
+
 // Temporary storage of the two sorts for the given key widths in bits.
 hnv_status sort_storage(int64_t nE, int64_t nnz, int key_bits, int member_bits, size_t &t_keys, size_t &t_members)
 {
@@ -247,10 +414,13 @@ int bits_for(int64_t n)
 
 struct CoarsenLayout {
     size_t keys_in, keys_out, ids_in, order, rank, best, choice, first, count, gflag, gid, kept, krank, mapped,
-        sorted, dcount, cstart, sizes, flag, temp, temp_bytes, total;
+        sorted, dcount, cstart, sizes, flag;
+    // feature path (k > 0)
+    size_t fsum, fsq, q, bestq, gcount, gptr, gcur, gnodes;
+    size_t temp, temp_bytes, total;
 };
 
-hnv_status layout(int64_t nV, int64_t nE, int64_t nnz, CoarsenLayout &L)
+hnv_status layout(int64_t nV, int64_t nE, int64_t nnz, int k, CoarsenLayout &L)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -277,12 +447,23 @@ hnv_status layout(int64_t nV, int64_t nE, int64_t nnz, CoarsenLayout &L)
     L.dcount = take(4 * nE);
     L.cstart = take(4 * nE);
     L.sizes = take(8 * 4);
-    L.flag = take(8);
+    L.flag = take(16);
+    L.fsum = L.fsq = L.q = L.bestq = L.gcount = L.gptr = L.gcur = L.gnodes = 0;
+    if (k > 0) {
+        L.fsum = take(4 * (size_t)nE * k);
+        L.fsq = take(8 * nE);
+        L.q = take(8 * nnz);
+        L.bestq = take(8 * nV);
+        L.gcount = take(4 * (nV + 1));
+        L.gptr = take(4 * (nV + 1));
+        L.gcur = take(4 * nV);
+        L.gnodes = take(4 * nV);
+    }
     size_t t1 = 0, t2 = 0, t3 = 0, t4 = 0;
     if (hnv_status st = sort_storage(nE, nnz, 64, 32, t1, t4); st != HNV_OK)
         return st;
     hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, t2, (int32_t *)nullptr, (int32_t *)nullptr,
-                                                    (int)std::max<int64_t>(nV, 1));
+                                                    (int)std::max<int64_t>(nV + 1, 1));
     if (e == hipSuccess)
         e = hipcub::DeviceScan::ExclusiveSum(nullptr, t3, (int32_t *)nullptr, (int32_t *)nullptr,
                                              (int)std::max<int64_t>(nE, 1));
@@ -294,42 +475,40 @@ hnv_status layout(int64_t nV, int64_t nE, int64_t nnz, CoarsenLayout &L)
     return HNV_OK;
 }
 
-}  // namespace
-}  // namespace hnv
-
-using namespace hnv;
-
-extern "C" hnv_status hnv_coarsen_workspace_bytes(int64_t n_nodes, int64_t n_edges, int64_t nnz, size_t *bytes)
+hnv_status check_sizes(int64_t n_nodes, int64_t n_edges, int64_t nnz, int k)
 {
-    clear_error();
-    if (!bytes || n_nodes < 0 || n_edges < 0 || nnz < 0)
-        return fail(HNV_EINVAL, "bad arguments");
+    if (n_nodes < 0 || n_edges < 0 || nnz < 0 || k < 0)
+        return fail(HNV_EINVAL, "negative size");
     if (n_nodes >= INT_MAX || n_edges >= INT_MAX || nnz >= INT_MAX)
         return fail(HNV_EUNSUPPORTED, "sizes must be below 2^31");
-    CoarsenLayout L;
-    hnv_status st = layout(n_nodes, n_edges, nnz, L);
-    if (st == HNV_OK)
-        *bytes = L.total;
-    return st;
+    if (k % 4 != 0 || k > (1 << 16) || (int64_t)n_edges * k >= INT64_MAX / 8)
+        return fail(HNV_EUNSUPPORTED, "feature width k must be a multiple of 4 up to 65536");
+    return HNV_OK;
 }
 
-extern "C" hnv_status hnv_coarsen_level_device(int64_t n_nodes, int64_t n_edges, int64_t nnz,
-                                               const int32_t *edge_ptr, const int32_t *edge_idx,
-                                               const float *edge_w, int32_t *node_rep, int32_t *edge_rep,
-                                               int32_t *c_edge_ptr, int32_t *c_edge_idx, float *c_edge_w,
-                                               int64_t *c_sizes, void *workspace, size_t ws_bytes, void *stream)
+// One coarsening step; featureless when x is NULL (k = 0), else on the
+// cosine of bag-of-words features with X' summed into c_x.
+hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const int32_t *edge_ptr,
+                          const int32_t *edge_idx, const float *edge_w, const int32_t *x, int k, int32_t *node_rep,
+                          int32_t *edge_rep, int32_t *c_edge_ptr, int32_t *c_edge_idx, float *c_edge_w,
+                          int32_t *c_x, int64_t *c_sizes, void *workspace, size_t ws_bytes, void *stream)
 {
     clear_error();
-    if (n_nodes < 0 || n_edges < 0 || nnz < 0 || !c_sizes || !edge_ptr || !c_edge_ptr ||
-        (nnz > 0 && (!edge_idx || !c_edge_idx)) || (n_nodes > 0 && !node_rep) || (n_edges > 0 && !edge_rep))
-        return fail(HNV_EINVAL, "bad arguments");
-    if (n_nodes >= INT_MAX || n_edges >= INT_MAX || nnz >= INT_MAX)
-        return fail(HNV_EUNSUPPORTED, "sizes must be below 2^31");
+    hnv_status st = check_sizes(n_nodes, n_edges, nnz, k);
+    if (st != HNV_OK)
+        return st;
+    if (!c_sizes || !edge_ptr || !c_edge_ptr || (nnz > 0 && (!edge_idx || !c_edge_idx)) ||
+        (n_nodes > 0 && !node_rep) || (n_edges > 0 && !edge_rep))
+        return fail(HNV_EINVAL, "a required pointer is NULL");
+    const bool feat = k > 0;
+    if (feat && n_nodes > 0 && (!x || !c_x))
+        return fail(HNV_EINVAL, "features: x and c_x are required");
+    if (feat && ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(c_x)) & 15))
+        return fail(HNV_EINVAL, "features: x and c_x must be 16-byte aligned");
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
         return fail(HNV_EWORKSPACE, "workspace must be non-NULL and 256-byte aligned");
     CoarsenLayout L;
-    hnv_status st = layout(n_nodes, n_edges, nnz, L);
-    if (st != HNV_OK)
+    if ((st = layout(n_nodes, n_edges, nnz, k, L)) != HNV_OK)
         return st;
     if (L.total > ws_bytes)
         return fail(HNV_EWORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " +
@@ -345,36 +524,48 @@ extern "C" hnv_status hnv_coarsen_level_device(int64_t n_nodes, int64_t n_edges,
         return e == hipSuccess ? HNV_OK : fail(HNV_EDEVICE, std::string("read-back: ") + hipGetErrorString(e));
     };
 
-    // 0. input check (every later kernel trusts offsets and member ids)
+    // 0. input check (every later kernel trusts offsets, member ids, counts)
     int *flag = reinterpret_cast<int *>(base + L.flag);
-    k_fill<<<1, kThreads, 0, s>>>(flag, 1, 0);
+    unsigned long long *total = reinterpret_cast<unsigned long long *>(base + L.flag + 8);
+    k_fill<<<1, kThreads, 0, s>>>(flag, 4, 0);
     if (nE > 0)
         k_check<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, edge_idx, edge_w, n_nodes, n_edges, nnz, flag);
+    if (feat && nV > 0) {
+        const int64_t n4 = (int64_t)nV * k / 4;
+        k_fcheck<<<(unsigned)std::min<int64_t>(grid_for(n4), 2048), kThreads, 0, s>>>(
+            reinterpret_cast<const int4 *>(x), n4, flag, total);
+    }
     if ((st = dev_check("coarsening input check")) != HNV_OK)
         return st;
-    int bad = 0;
+    struct {
+        int bad, pad;
+        unsigned long long total;
+    } chk{};
+    if ((st = sync_read(&chk, flag, sizeof(chk))) != HNV_OK)
+        return st;
     if (nE == 0) {
         int32_t p0 = 0;
         if ((st = sync_read(&p0, edge_ptr, 4)) != HNV_OK)
             return st;
         if (p0 != 0 || nz != 0)
-            bad |= 1;
-    } else if ((st = sync_read(&bad, flag, sizeof(int))) != HNV_OK) {
-        return st;
+            chk.bad |= 1;
     }
-    if (bad & 1)
+    if (chk.bad & 1)
         return fail(HNV_EINVAL, "edge_ptr: offsets must start at 0, increase, end at nnz, no empty hyperedge");
-    if (bad & 2)
+    if (chk.bad & 2)
         return fail(HNV_ERANGE, "a member id is outside [0, n_nodes)");
-    if (bad & 4)
+    if (chk.bad & 4)
         return fail(HNV_EUNSORTED, "member lists must be strictly ascending");
-    if (bad & 8)
+    if (chk.bad & 8)
         return fail(HNV_EINVAL, "weights must be finite and > 0");
+    if ((chk.bad & 16) || chk.total >= (1ull << 31))
+        return fail(HNV_EINVAL, "features must be counts >= 0 with a total below 2^31");
 
     int32_t *order = at(L.order), *rank = at(L.rank), *best = at(L.best), *choice = at(L.choice);
     int32_t *first = at(L.first), *count = at(L.count), *gflag = at(L.gflag), *gid = at(L.gid);
     int32_t *kept = at(L.kept), *krank = at(L.krank), *mapped = at(L.mapped), *sorted = at(L.sorted);
     int32_t *dcount = at(L.dcount), *cstart = at(L.cstart);
+    int64_t *sizes = reinterpret_cast<int64_t *>(base + L.sizes);
     void *temp = base + L.temp;
     size_t tb = L.temp_bytes;
     // Without weights the upper half of every key is the same: sort the size
@@ -388,7 +579,7 @@ extern "C" hnv_status hnv_coarsen_level_device(int64_t n_nodes, int64_t n_edges,
             return fail(HNV_EDEVICE, "sort storage exceeds the queried size");
     }
     if (nE > 0) {
-        // 1. ranks
+        // 1. ranks in the order (weight descending, size ascending, id ascending)
         uint64_t *kin = reinterpret_cast<uint64_t *>(base + L.keys_in);
         uint64_t *kout = reinterpret_cast<uint64_t *>(base + L.keys_out);
         k_keys<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, edge_w, n_edges, kin, at(L.ids_in));
@@ -399,10 +590,23 @@ extern "C" hnv_status hnv_coarsen_level_device(int64_t n_nodes, int64_t n_edges,
         k_fill<<<grid_for(nE), kThreads, 0, s>>>(count, n_edges, 0);
     }
     if (nV > 0) {
-        // 2. choices
+        // 2. choices: the least rank, or (features) the least rank among the
+        // hyperedges of best cosine score
         k_fill<<<grid_for(nV), kThreads, 0, s>>>(best, n_nodes, INT_MAX);
-        if (nE > 0)
+        if (nE > 0 && !feat)
             k_best<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, edge_idx, rank, n_edges, best);
+        if (nE > 0 && feat) {
+            int32_t *fsum = at(L.fsum);
+            int64_t *fsq = reinterpret_cast<int64_t *>(base + L.fsq);
+            double *q = reinterpret_cast<double *>(base + L.q);
+            unsigned long long *bestq = reinterpret_cast<unsigned long long *>(base + L.bestq);
+            const unsigned wave_grid = (unsigned)((n_edges + kThreads / kWave - 1) / (kThreads / kWave));
+            k_fill<<<grid_for(2 * (int64_t)nV), kThreads, 0, s>>>(reinterpret_cast<int32_t *>(bestq),
+                                                                   2 * (int64_t)nV, 0);
+            k_rowsum<true><<<wave_grid, kThreads, 0, s>>>(edge_ptr, edge_idx, x, k, n_edges, nullptr, fsum, fsq);
+            k_qscore<<<wave_grid, kThreads, 0, s>>>(edge_ptr, edge_idx, fsum, fsq, x, k, n_edges, q, bestq);
+            k_best_feat<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, edge_idx, rank, q, bestq, n_edges, best);
+        }
         k_choice<<<grid_for(nV), kThreads, 0, s>>>(best, order, n_nodes, choice, first, count);
         // 3. group numbering by smallest node
         k_group_flags<<<grid_for(nV), kThreads, 0, s>>>(choice, first, n_nodes, gflag);
@@ -434,9 +638,72 @@ extern "C" hnv_status hnv_coarsen_level_device(int64_t n_nodes, int64_t n_edges,
         k_emit<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, sorted, kept, krank, cstart, edge_w, n_edges, edge_rep,
                                                  c_edge_ptr, c_edge_idx, c_edge_w);
     }
-    int64_t *sizes = reinterpret_cast<int64_t *>(base + L.sizes);
     k_sizes<<<1, 64, 0, s>>>(gflag, gid, n_nodes, kept, krank, dcount, cstart, n_edges, c_edge_ptr, sizes);
+    if (feat && nV > 0) {
+        // 6. X': each coarse node's row is the sum of its fine nodes' rows
+        int32_t *gcount = at(L.gcount), *gptr = at(L.gptr), *gcur = at(L.gcur), *gnodes = at(L.gnodes);
+        k_fill<<<grid_for(nV + 1), kThreads, 0, s>>>(gcount, n_nodes + 1, 0);
+        k_fill<<<grid_for(nV), kThreads, 0, s>>>(gcur, n_nodes, 0);
+        k_group_count<<<grid_for(nV), kThreads, 0, s>>>(node_rep, n_nodes, gcount);
+        tb = L.temp_bytes;
+        if (hipcub::DeviceScan::ExclusiveSum(temp, tb, gcount, gptr, nV + 1, s) != hipSuccess)
+            return fail(HNV_EDEVICE, "scan of group sizes");
+        k_group_fill<<<grid_for(nV), kThreads, 0, s>>>(node_rep, gptr, n_nodes, gcur, gnodes);
+        const unsigned wave_grid = (unsigned)((n_nodes + kThreads / kWave - 1) / (kThreads / kWave));
+        k_rowsum<false><<<wave_grid, kThreads, 0, s>>>(gptr, gnodes, x, k, n_nodes, sizes, c_x, nullptr);
+    }
     if ((st = dev_check("coarsening kernels")) != HNV_OK)
         return st;
     return sync_read(c_sizes, sizes, 3 * sizeof(int64_t));
+}
+
+}  // namespace
+}  // namespace hnv
+
+using namespace hnv;
+
+extern "C" hnv_status hnv_coarsen_workspace_bytes(int64_t n_nodes, int64_t n_edges, int64_t nnz, size_t *bytes)
+{
+    return hnv_coarsen_features_workspace_bytes(n_nodes, n_edges, nnz, 0, bytes);
+}
+
+extern "C" hnv_status hnv_coarsen_features_workspace_bytes(int64_t n_nodes, int64_t n_edges, int64_t nnz, int k,
+                                                           size_t *bytes)
+{
+    clear_error();
+    if (!bytes)
+        return fail(HNV_EINVAL, "bytes is NULL");
+    hnv_status st = check_sizes(n_nodes, n_edges, nnz, k);
+    if (st != HNV_OK)
+        return st;
+    CoarsenLayout L;
+    if ((st = layout(n_nodes, n_edges, nnz, k, L)) == HNV_OK)
+        *bytes = L.total;
+    return st;
+}
+
+extern "C" hnv_status hnv_coarsen_level_device(int64_t n_nodes, int64_t n_edges, int64_t nnz,
+                                               const int32_t *edge_ptr, const int32_t *edge_idx,
+                                               const float *edge_w, int32_t *node_rep, int32_t *edge_rep,
+                                               int32_t *c_edge_ptr, int32_t *c_edge_idx, float *c_edge_w,
+                                               int64_t *c_sizes, void *workspace, size_t ws_bytes, void *stream)
+{
+    return coarsen_device(n_nodes, n_edges, nnz, edge_ptr, edge_idx, edge_w, nullptr, 0, node_rep, edge_rep,
+                          c_edge_ptr, c_edge_idx, c_edge_w, nullptr, c_sizes, workspace, ws_bytes, stream);
+}
+
+extern "C" hnv_status hnv_coarsen_level_features_device(int64_t n_nodes, int64_t n_edges, int64_t nnz,
+                                                        const int32_t *edge_ptr, const int32_t *edge_idx,
+                                                        const float *edge_w, const int32_t *x, int k,
+                                                        int32_t *node_rep, int32_t *edge_rep, int32_t *c_edge_ptr,
+                                                        int32_t *c_edge_idx, float *c_edge_w, int32_t *c_x,
+                                                        int64_t *c_sizes, void *workspace, size_t ws_bytes,
+                                                        void *stream)
+{
+    if (k <= 0) {
+        clear_error();
+        return fail(HNV_EUNSUPPORTED, "feature width k must be a multiple of 4 up to 65536");
+    }
+    return coarsen_device(n_nodes, n_edges, nnz, edge_ptr, edge_idx, edge_w, x, k, node_rep, edge_rep, c_edge_ptr,
+                          c_edge_idx, c_edge_w, c_x, c_sizes, workspace, ws_bytes, stream);
 }

@@ -9,14 +9,19 @@ datasets is available here, so every input is synthetic and seeded:
 * members are drawn without replacement, either uniformly over the nodes or in
   proportion to a node popularity p_v = rank_v^-b (rank = seeded permutation);
 * hyperedge weights are unit or uniform in [lo, hi] (float32);
-* coarsest-level embeddings are N(0, 1) float32.
+* coarsest-level embeddings are N(0, 1) float32;
+* node features, where a workload has them, are bag-of-words counts (the
+  paper's citation datasets encode each document that way, Section 3.1 and
+  Section 4): each node holds a few distinct words drawn by a Zipf word
+  popularity over a k-word vocabulary, each with a small count; some nodes
+  are empty documents and some repeat another node's document exactly.
 
 A hypergraph is returned in canonical form: each hyperedge row lists its
 members in ascending order without duplicates (hyperedges are sets of nodes,
 Section 1), offsets are int64 and member ids int32.
 
 Each named configuration carries a seed k: structure k, weights 100+k,
-embeddings 200+k, labels / head / cotangent 300+k.
+embeddings 200+k, labels / head / cotangent 300+k, features 400+k.
 """
 from __future__ import annotations
 
@@ -43,6 +48,7 @@ class Config:
     label_frac: float = 0.0
     n_classes: int = 0
     checkpoint_every: int = 0
+    features: tuple = ()    # ("bow", k, words_lo, words_hi) or ()
 
 
 def _sweeps(levels: int, k: int) -> tuple:
@@ -63,6 +69,12 @@ CONFIGS = {
     "grad-500k": Config("grad-500k", 4, 500_000, 300_000, ("zipf", 2.1, 1_000), ("uniform",), ("unit",),
                         128, 1, (10, 0), adjoint_sweeps=10, label_frac=0.10, n_classes=16,
                         checkpoint_every=5),
+    # feature-driven coarsening: Pubmed-sized (Table 1), k = 500 words
+    "bow-20k": Config("bow-20k", 6, 19_717, 7_963, ("zipf", 2.1, 171), ("uniform",), ("unit",),
+                      32, 4, _sweeps(4, 10), features=("bow", 500, 5, 50)),
+    # feature-driven coarsening at a million nodes, k = 512 words
+    "bow-1m": Config("bow-1m", 7, 1_000_000, 600_000, ("zipf", 2.1, 500), ("uniform",), ("unit",),
+                     64, 6, _sweeps(6, 10), features=("bow", 512, 5, 40)),
     # Friendster-scale BF16 refinement + adjoint (Table 3 / Table 5 scale)
     "zipf-8m": Config("zipf-8m", 5, 8_000_000, 10_000_000, ("zipf", 2.0, 5_000), ("uniform",), ("unit",),
                       128, 10, _sweeps(10, 20), dtypes=("bf16",), adjoint_sweeps=5),
@@ -213,6 +225,38 @@ def coarsest_embedding(cfg_or_seed, n_rows: int, d: int, columns: Optional[Seque
         rng = np.random.default_rng([200 + seed, int(c)])
         out[:, j] = rng.standard_normal(n_rows, dtype=np.float32)
     return out
+
+
+def bag_of_words(seed: int, n_nodes: int, k: int, words_lo: int, words_hi: int, zipf_a: float = 1.1,
+                 max_count: int = 3, empty_frac: float = 0.02, repeat_frac: float = 0.05) -> np.ndarray:
+    """int32 [n_nodes x k] word counts: words_lo..words_hi distinct words per
+    node (word rank r drawn with probability proportional to r^-zipf_a),
+    counts uniform on 1..max_count, a fraction of empty rows and a fraction
+    of rows copied from a random other row."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(k)
+    cdf = np.cumsum(np.arange(1, k + 1, dtype=np.float64) ** (-zipf_a))
+    cdf /= cdf[-1]
+    x = np.zeros((n_nodes, k), dtype=np.int32)
+    n_words = rng.integers(words_lo, min(words_hi, k) + 1, size=n_nodes)
+    total = int(n_words.sum())
+    rows = np.repeat(np.arange(n_nodes, dtype=np.int64), n_words)
+    cols = perm[np.searchsorted(cdf, rng.random(total), side="right").clip(0, k - 1)]
+    counts = rng.integers(1, max_count + 1, size=total).astype(np.int32)
+    x[rows, cols] = counts                      # a repeated word keeps one count
+    empty = rng.random(n_nodes) < empty_frac
+    x[empty] = 0
+    rep = np.nonzero(rng.random(n_nodes) < repeat_frac)[0]
+    if rep.size and n_nodes > 1:
+        x[rep] = x[rng.integers(0, n_nodes, size=rep.size)]
+    return x
+
+
+def node_features(cfg: Config) -> np.ndarray:
+    """The bag-of-words matrix of a named configuration that has features."""
+    kind, k, lo, hi = cfg.features
+    assert kind == "bow"
+    return bag_of_words(400 + cfg.seed, cfg.n_nodes, k, lo, hi)
 
 
 def labelled_nodes(cfg: Config) -> tuple:
