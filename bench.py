@@ -472,6 +472,12 @@ def main():
                      "compulsory_bytes_per_launch": head["sweep_min_bytes_per_launch"],
                      "compulsory_GBps": compulsory, "compulsory_frac": compulsory / HBM_PEAK_GBS},
     }
+    if traffic is not None:
+        # the no-reuse stream model counts Infinity Cache and L2 hits as HBM
+        # bytes, so `frac` can pass 1; the counters give the bytes that did
+        # cross the L2 / fabric boundary
+        line["roofline"]["traffic_GBps"] = traffic / (head["sweep_kernel_avg_ms"] / 1000.0) / 1e9
+        line["roofline"]["traffic_frac"] = line["roofline"]["traffic_GBps"] / HBM_PEAK_GBS
     if "scoring" in results:
         line["hyperedge_scoring"] = results["scoring"]
     for dt in dtypes[1:]:
