@@ -12,8 +12,11 @@
 //   4. a hyperedge is removed iff every member chose it (a count per
 //      hyperedge); a scan numbers the kept ones in order;
 //   5. the coarse member sets: every member mapped through rep(), a
-//      segmented sort per hyperedge, distinct values counted, a scan for the
-//      coarse offsets, then the distinct values copied.
+//      segmented sort per hyperedge, the first of each run of equal values
+//      flagged, one scan over the flags for positions and offsets.
+// Incidence-parallel steps find their hyperedge through inc_edge (a max-scan
+// of each hyperedge's id placed at its first incidence), so no thread walks a
+// whole hyperedge.
 // Integer work only (the key compares FP32 weights through their bit
 // patterns, which order like the values for positive finite floats).
 //
@@ -40,29 +43,58 @@ constexpr int kThreads = 256;
 
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
-// input check: bit 0 offsets, bit 1 member range, bit 2 member order, bit 3 weights
-__global__ __launch_bounds__(kThreads) void k_check(const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                                                    const float *__restrict__ w, int64_t n_nodes, int64_t n_edges,
-                                                    int64_t nnz, int *__restrict__ flag)
+// Input check.  Flag bits: 0 offsets, 1 member range, 2 member order,
+// 3 weights.  Offsets and weights per hyperedge:
+__global__ __launch_bounds__(kThreads) void k_check_edges(const int32_t *__restrict__ ptr,
+                                                          const float *__restrict__ w, int64_t n_edges,
+                                                          int64_t nnz, int *__restrict__ flag)
 {
     const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (e >= n_edges)
         return;
     const int64_t a = ptr[e], b = ptr[e + 1];
     int bad = 0;
-    if (a < 0 || b < a || b > nnz || (e == 0 && a != 0) || (e == n_edges - 1 && b != nnz) || a == b)
+    if (a < 0 || b <= a || b > nnz || (e == 0 && a != 0) || (e == n_edges - 1 && b != nnz))
         bad |= 1;
-    if (!(bad & 1)) {
-        for (int64_t j = a; j < b; ++j) {
-            const int32_t v = idx[j];
-            if (v < 0 || v >= n_nodes)
-                bad |= 2;
-            else if (j > a && idx[j - 1] >= v)
-                bad |= 4;
-        }
-    }
     if (w && !(w[e] > 0.0f && w[e] < INFINITY))
         bad |= 8;
+    if (bad)
+        atomicOr(flag, bad);
+}
+
+// inc_edge[j] = the hyperedge of incidence j: each hyperedge writes its id at
+// its first incidence (over a zero fill), an inclusive max-scan spreads it.
+// Offsets outside [0, nnz) are skipped here and reported by k_check_edges.
+__global__ __launch_bounds__(kThreads) void k_heads(const int32_t *__restrict__ ptr, int64_t n_edges, int64_t nnz,
+                                                    int32_t *__restrict__ inc_edge)
+{
+    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= n_edges)
+        return;
+    const int32_t a = ptr[e];
+    if (a >= 0 && a < nnz && ptr[e + 1] > a)
+        inc_edge[a] = (int32_t)e;
+}
+
+// member range and order per incidence (inc_edge is only meaningful when
+// the offsets are valid; every read stays in bounds either way)
+__global__ __launch_bounds__(kThreads) void k_check_members(const int32_t *__restrict__ ptr,
+                                                            const int32_t *__restrict__ idx,
+                                                            const int32_t *__restrict__ inc_edge, int64_t n_nodes,
+                                                            int64_t n_edges, int64_t nnz, int *__restrict__ flag)
+{
+    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (j >= nnz)
+        return;
+    const int32_t v = idx[j];
+    int bad = 0;
+    if (v < 0 || v >= n_nodes) {
+        bad = 2;
+    } else if (j > 0) {
+        const int32_t e = inc_edge[j];
+        if (e >= 0 && e < n_edges && j > ptr[e] && idx[j - 1] >= v)
+            bad = 4;
+    }
     if (bad)
         atomicOr(flag, bad);
 }
@@ -95,17 +127,16 @@ __global__ __launch_bounds__(kThreads) void k_rank(const int32_t *__restrict__ o
         rank[order[i]] = (int32_t)i;
 }
 
-// best[v] = least rank over the hyperedges containing v
-__global__ __launch_bounds__(kThreads) void k_best(const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                                                   const int32_t *__restrict__ rank, int64_t n_edges,
+// best[v] = least rank over the hyperedges containing v, one incidence per
+// thread
+__global__ __launch_bounds__(kThreads) void k_best(const int32_t *__restrict__ idx,
+                                                   const int32_t *__restrict__ inc_edge,
+                                                   const int32_t *__restrict__ rank, int64_t nnz,
                                                    int32_t *__restrict__ best)
 {
-    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (e >= n_edges)
-        return;
-    const int32_t r = rank[e];
-    for (int32_t j = ptr[e]; j < ptr[e + 1]; ++j)
-        atomicMin(best + idx[j], r);
+    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (j < nnz)
+        atomicMin(best + idx[j], rank[inc_edge[j]]);
 }
 
 // choice, then per hyperedge: smallest node that chose it, and how many did
@@ -167,31 +198,41 @@ __global__ __launch_bounds__(kThreads) void k_map(const int32_t *__restrict__ id
         mapped[j] = node_rep[idx[j]];
 }
 
-// distinct values of each kept hyperedge's sorted mapped members
+// dflag[j] = 1 where sorted[j] starts a new distinct value inside a kept
+// hyperedge's sorted mapped members
 __global__ __launch_bounds__(kThreads) void k_distinct(const int32_t *__restrict__ ptr,
                                                        const int32_t *__restrict__ sorted,
-                                                       const int32_t *__restrict__ kept, int64_t n_edges,
-                                                       int32_t *__restrict__ dcount)
+                                                       const int32_t *__restrict__ inc_edge,
+                                                       const int32_t *__restrict__ kept, int64_t nnz,
+                                                       int32_t *__restrict__ dflag)
 {
-    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (e >= n_edges)
+    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (j >= nnz)
         return;
-    int32_t n = 0;
-    if (kept[e]) {
-        for (int32_t j = ptr[e]; j < ptr[e + 1]; ++j)
-            n += (j == ptr[e] || sorted[j] != sorted[j - 1]) ? 1 : 0;
-    }
-    dcount[e] = n;
+    const int32_t e = inc_edge[j];
+    dflag[j] = (kept[e] && (j == ptr[e] || sorted[j] != sorted[j - 1])) ? 1 : 0;
 }
 
-__global__ __launch_bounds__(kThreads) void k_emit(const int32_t *__restrict__ ptr,
-                                                   const int32_t *__restrict__ sorted,
-                                                   const int32_t *__restrict__ kept,
-                                                   const int32_t *__restrict__ krank,
-                                                   const int32_t *__restrict__ cstart, const float *__restrict__ w,
-                                                   int64_t n_edges, int32_t *__restrict__ edge_rep,
-                                                   int32_t *__restrict__ c_ptr, int32_t *__restrict__ c_idx,
-                                                   float *__restrict__ c_w)
+// coarse members: the flagged values at their scanned positions
+__global__ __launch_bounds__(kThreads) void k_emit_members(const int32_t *__restrict__ sorted,
+                                                           const int32_t *__restrict__ dflag,
+                                                           const int32_t *__restrict__ dpos, int64_t nnz,
+                                                           int32_t *__restrict__ c_idx)
+{
+    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (j < nnz && dflag[j])
+        c_idx[dpos[j]] = sorted[j];
+}
+
+// per hyperedge: edge_rep, coarse offset (the scanned position of its first
+// incidence, which is always flagged when kept) and weight
+__global__ __launch_bounds__(kThreads) void k_emit_edges(const int32_t *__restrict__ ptr,
+                                                         const int32_t *__restrict__ kept,
+                                                         const int32_t *__restrict__ krank,
+                                                         const int32_t *__restrict__ dpos,
+                                                         const float *__restrict__ w, int64_t n_edges,
+                                                         int32_t *__restrict__ edge_rep, int32_t *__restrict__ c_ptr,
+                                                         float *__restrict__ c_w)
 {
     const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (e >= n_edges)
@@ -202,26 +243,22 @@ __global__ __launch_bounds__(kThreads) void k_emit(const int32_t *__restrict__ p
     }
     const int32_t r = krank[e];
     edge_rep[e] = r;
-    c_ptr[r] = cstart[e];
+    c_ptr[r] = dpos[ptr[e]];
     if (c_w)
         c_w[r] = w ? w[e] : 1.0f;
-    int32_t pos = cstart[e];
-    for (int32_t j = ptr[e]; j < ptr[e + 1]; ++j)
-        if (j == ptr[e] || sorted[j] != sorted[j - 1])
-            c_idx[pos++] = sorted[j];
 }
 
 // sizes[0..2] = coarse nodes, kept hyperedges, coarse incidences; closes c_ptr
 __global__ void k_sizes(const int32_t *__restrict__ gflag, const int32_t *__restrict__ gid, int64_t n_nodes,
-                        const int32_t *__restrict__ kept, const int32_t *__restrict__ krank,
-                        const int32_t *__restrict__ dcount, const int32_t *__restrict__ cstart, int64_t n_edges,
+                        const int32_t *__restrict__ kept, const int32_t *__restrict__ krank, int64_t n_edges,
+                        const int32_t *__restrict__ dflag, const int32_t *__restrict__ dpos, int64_t nnz,
                         int32_t *__restrict__ c_ptr, int64_t *__restrict__ sizes)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0)
         return;
     const int64_t nv = n_nodes ? (int64_t)gid[n_nodes - 1] + gflag[n_nodes - 1] : 0;
     const int64_t ne = n_edges ? (int64_t)krank[n_edges - 1] + kept[n_edges - 1] : 0;
-    const int64_t nz = n_edges ? (int64_t)cstart[n_edges - 1] + dcount[n_edges - 1] : 0;
+    const int64_t nz = nnz ? (int64_t)dpos[nnz - 1] + dflag[nnz - 1] : 0;
     sizes[0] = nv;
     sizes[1] = ne;
     sizes[2] = nz;
@@ -348,22 +385,19 @@ __global__ __launch_bounds__(kThreads) void k_qscore(const int32_t *__restrict__
 }
 
 // best[v] = least rank among v's hyperedges whose score equals bestq[v]
-__global__ __launch_bounds__(kThreads) void k_best_feat(const int32_t *__restrict__ ptr,
-                                                        const int32_t *__restrict__ idx,
+__global__ __launch_bounds__(kThreads) void k_best_feat(const int32_t *__restrict__ idx,
+                                                        const int32_t *__restrict__ inc_edge,
                                                         const int32_t *__restrict__ rank,
                                                         const double *__restrict__ q,
-                                                        const unsigned long long *__restrict__ bestq, int64_t n_edges,
+                                                        const unsigned long long *__restrict__ bestq, int64_t nnz,
                                                         int32_t *__restrict__ best)
 {
-    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (e >= n_edges)
+    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (j >= nnz)
         return;
-    const int32_t r = rank[e];
-    for (int32_t j = ptr[e]; j < ptr[e + 1]; ++j) {
-        const int32_t v = idx[j];
-        if (ordered_bits(q[j]) == bestq[v])
-            atomicMin(best + v, r);
-    }
+    const int32_t v = idx[j];
+    if (ordered_bits(q[j]) == bestq[v])
+        atomicMin(best + v, rank[inc_edge[j]]);
 }
 
 // coarse-node member lists: count, then place (the order inside a group is
@@ -414,7 +448,7 @@ int bits_for(int64_t n)
 
 struct CoarsenLayout {
     size_t keys_in, keys_out, ids_in, order, rank, best, choice, first, count, gflag, gid, kept, krank, mapped,
-        sorted, dcount, cstart, sizes, flag;
+        sorted, inc_edge, dflag, dpos, sizes, flag;
     // feature path (k > 0)
     size_t fsum, fsq, q, bestq, gcount, gptr, gcur, gnodes;
     size_t temp, temp_bytes, total;
@@ -444,8 +478,9 @@ hnv_status layout(int64_t nV, int64_t nE, int64_t nnz, int k, CoarsenLayout &L)
     L.krank = take(4 * nE);
     L.mapped = take(4 * nnz);
     L.sorted = take(4 * nnz);
-    L.dcount = take(4 * nE);
-    L.cstart = take(4 * nE);
+    L.inc_edge = take(4 * nnz);
+    L.dflag = take(4 * nnz);
+    L.dpos = take(4 * nnz);
     L.sizes = take(8 * 4);
     L.flag = take(16);
     L.fsum = L.fsq = L.q = L.bestq = L.gcount = L.gptr = L.gcur = L.gnodes = 0;
@@ -466,10 +501,14 @@ hnv_status layout(int64_t nV, int64_t nE, int64_t nnz, int k, CoarsenLayout &L)
                                                     (int)std::max<int64_t>(nV + 1, 1));
     if (e == hipSuccess)
         e = hipcub::DeviceScan::ExclusiveSum(nullptr, t3, (int32_t *)nullptr, (int32_t *)nullptr,
-                                             (int)std::max<int64_t>(nE, 1));
+                                             (int)std::max<int64_t>(std::max(nE, nnz), 1));
+    size_t t5 = 0;
+    if (e == hipSuccess)
+        e = hipcub::DeviceScan::InclusiveScan(nullptr, t5, (int32_t *)nullptr, (int32_t *)nullptr, hipcub::Max(),
+                                              (int)std::max<int64_t>(nnz, 1));
     if (e != hipSuccess)
         return fail(HNV_EDEVICE, std::string("scan storage query (needs a visible GPU): ") + hipGetErrorString(e));
-    L.temp_bytes = std::max(std::max(t1, t2), std::max(t3, t4));
+    L.temp_bytes = std::max(std::max(std::max(t1, t2), std::max(t3, t4)), t5);
     L.temp = take(L.temp_bytes);
     L.total = (off + 255) & ~size_t(255);
     return HNV_OK;
@@ -528,8 +567,20 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
     int *flag = reinterpret_cast<int *>(base + L.flag);
     unsigned long long *total = reinterpret_cast<unsigned long long *>(base + L.flag + 8);
     k_fill<<<1, kThreads, 0, s>>>(flag, 4, 0);
-    if (nE > 0)
-        k_check<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, edge_idx, edge_w, n_nodes, n_edges, nnz, flag);
+    int32_t *inc_edge = at(L.inc_edge), *dflag = at(L.dflag), *dpos = at(L.dpos);
+    if (nE > 0) {
+        k_check_edges<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, edge_w, n_edges, nnz, flag);
+        if (nz > 0) {
+            k_fill<<<grid_for(nz), kThreads, 0, s>>>(dpos, nnz, 0);
+            k_heads<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, n_edges, nnz, dpos);
+            size_t tbs = L.temp_bytes;
+            if (hipcub::DeviceScan::InclusiveScan(base + L.temp, tbs, dpos, inc_edge, hipcub::Max(), nz, s) !=
+                hipSuccess)
+                return fail(HNV_EDEVICE, "scan of hyperedge heads");
+            k_check_members<<<grid_for(nz), kThreads, 0, s>>>(edge_ptr, edge_idx, inc_edge, n_nodes, n_edges, nnz,
+                                                              flag);
+        }
+    }
     if (feat && nV > 0) {
         const int64_t n4 = (int64_t)nV * k / 4;
         k_fcheck<<<(unsigned)std::min<int64_t>(grid_for(n4), 2048), kThreads, 0, s>>>(
@@ -564,7 +615,6 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
     int32_t *order = at(L.order), *rank = at(L.rank), *best = at(L.best), *choice = at(L.choice);
     int32_t *first = at(L.first), *count = at(L.count), *gflag = at(L.gflag), *gid = at(L.gid);
     int32_t *kept = at(L.kept), *krank = at(L.krank), *mapped = at(L.mapped), *sorted = at(L.sorted);
-    int32_t *dcount = at(L.dcount), *cstart = at(L.cstart);
     int64_t *sizes = reinterpret_cast<int64_t *>(base + L.sizes);
     void *temp = base + L.temp;
     size_t tb = L.temp_bytes;
@@ -594,7 +644,7 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
         // hyperedges of best cosine score
         k_fill<<<grid_for(nV), kThreads, 0, s>>>(best, n_nodes, INT_MAX);
         if (nE > 0 && !feat)
-            k_best<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, edge_idx, rank, n_edges, best);
+            k_best<<<grid_for(nz), kThreads, 0, s>>>(edge_idx, inc_edge, rank, nnz, best);
         if (nE > 0 && feat) {
             int32_t *fsum = at(L.fsum);
             int64_t *fsq = reinterpret_cast<int64_t *>(base + L.fsq);
@@ -605,7 +655,7 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
                                                                    2 * (int64_t)nV, 0);
             k_rowsum<true><<<wave_grid, kThreads, 0, s>>>(edge_ptr, edge_idx, x, k, n_edges, nullptr, fsum, fsq);
             k_qscore<<<wave_grid, kThreads, 0, s>>>(edge_ptr, edge_idx, fsum, fsq, x, k, n_edges, q, bestq);
-            k_best_feat<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, edge_idx, rank, q, bestq, n_edges, best);
+            k_best_feat<<<grid_for(nz), kThreads, 0, s>>>(edge_idx, inc_edge, rank, q, bestq, nnz, best);
         }
         k_choice<<<grid_for(nV), kThreads, 0, s>>>(best, order, n_nodes, choice, first, count);
         // 3. group numbering by smallest node
@@ -631,14 +681,15 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
                                                            edge_ptr + 1, 0, member_bits, s) != hipSuccess)
                 return fail(HNV_EDEVICE, "segmented sort of coarse members");
         }
-        k_distinct<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, sorted, kept, n_edges, dcount);
+        k_distinct<<<grid_for(nz), kThreads, 0, s>>>(edge_ptr, sorted, inc_edge, kept, nnz, dflag);
         tb = L.temp_bytes;
-        if (hipcub::DeviceScan::ExclusiveSum(temp, tb, dcount, cstart, nE, s) != hipSuccess)
-            return fail(HNV_EDEVICE, "scan of coarse sizes");
-        k_emit<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, sorted, kept, krank, cstart, edge_w, n_edges, edge_rep,
-                                                 c_edge_ptr, c_edge_idx, c_edge_w);
+        if (hipcub::DeviceScan::ExclusiveSum(temp, tb, dflag, dpos, nz, s) != hipSuccess)
+            return fail(HNV_EDEVICE, "scan of coarse members");
+        k_emit_members<<<grid_for(nz), kThreads, 0, s>>>(sorted, dflag, dpos, nnz, c_edge_idx);
+        k_emit_edges<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, kept, krank, dpos, edge_w, n_edges, edge_rep,
+                                                       c_edge_ptr, c_edge_w);
     }
-    k_sizes<<<1, 64, 0, s>>>(gflag, gid, n_nodes, kept, krank, dcount, cstart, n_edges, c_edge_ptr, sizes);
+    k_sizes<<<1, 64, 0, s>>>(gflag, gid, n_nodes, kept, krank, n_edges, dflag, dpos, nnz, c_edge_ptr, sizes);
     if (feat && nV > 0) {
         // 6. X': each coarse node's row is the sum of its fine nodes' rows
         int32_t *gcount = at(L.gcount), *gptr = at(L.gptr), *gcur = at(L.gcur), *gnodes = at(L.gnodes);
