@@ -298,39 +298,134 @@ __global__ __launch_bounds__(kThreads) void k_fcheck(const int4 *__restrict__ x,
     }
 }
 
+// Members handled together by one wavefront in the feature kernels: their
+// row loads are independent, so this many rows are in flight per lane
+// (fewer for wide rows held in registers, to keep the register count down).
+template <int NC>
+constexpr int members_in_flight()
+{
+    return (NC == 0 || NC <= 2) ? 4 : 8 / NC;
+}
+
+// A feature row of k counts is read by one wavefront as NC passes of 256
+// counts (4 per lane, 16 B); NC is a compile-time bound (k <= 256 NC) so the
+// per-lane pieces of a row live in registers.  NC = 0: any k, one pass at a
+// time (wide rows).
+template <int NC>
+struct RowPieces {
+    int4 p[NC];
+    __device__ void zero()
+    {
+#pragma unroll
+        for (int i = 0; i < NC; ++i)
+            p[i] = make_int4(0, 0, 0, 0);
+    }
+    __device__ void load(const int32_t *row, int lane, int k)
+    {
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            const int c = lane * 4 + i * kWave * 4;
+            p[i] = (c < k) ? *reinterpret_cast<const int4 *>(row + c) : make_int4(0, 0, 0, 0);
+        }
+    }
+    __device__ void add(const RowPieces &o)
+    {
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            p[i].x += o.p[i].x;
+            p[i].y += o.p[i].y;
+            p[i].z += o.p[i].z;
+            p[i].w += o.p[i].w;
+        }
+    }
+    __device__ int64_t dot(const RowPieces &o) const
+    {
+        int64_t d = 0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i)
+            d += (int64_t)p[i].x * o.p[i].x + (int64_t)p[i].y * o.p[i].y + (int64_t)p[i].z * o.p[i].z +
+                 (int64_t)p[i].w * o.p[i].w;
+        return d;
+    }
+    __device__ void store(int32_t *row, int lane, int k) const
+    {
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            const int c = lane * 4 + i * kWave * 4;
+            if (c < k)
+                *reinterpret_cast<int4 *>(row + c) = p[i];
+        }
+    }
+};
+
+__device__ inline int64_t wave_sum(int64_t v)
+{
+    for (int o = kWave / 2; o > 0; o >>= 1)
+        v += __shfl_xor(v, o);
+    return v;
+}
+
 // out[r] = sum of the rows x[idx[j]], j in [ptr[r], ptr[r+1]), for r below
-// *limit (all rows if limit is NULL); one wavefront per row, 4 counts per
-// lane per pass.  SQ: also sq[r] = |out[r]|^2 (int64).
-template <bool SQ>
+// *limit (all rows if limit is NULL); one wavefront per row.  SQ: also
+// sq[r] = |out[r]|^2 (int64).  Integer sums: the order of the additions
+// does not change the result.
+template <bool SQ, int NC>
 __global__ __launch_bounds__(kThreads) void k_rowsum(const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
                                                      const int32_t *__restrict__ x, int k, int64_t n_rows,
                                                      const int64_t *__restrict__ limit, int32_t *__restrict__ out,
                                                      int64_t *__restrict__ sq)
 {
+    constexpr int U = members_in_flight<NC>();
     const int64_t r = (int64_t)blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     if (r >= n_rows || (limit && r >= *limit))
         return;
     const int32_t a = ptr[r], b = ptr[r + 1];
-    int64_t q = 0;
-    for (int c = lane * 4; c < k; c += kWave * 4) {
-        int4 acc = make_int4(0, 0, 0, 0);
-        for (int32_t j = a; j < b; ++j) {
-            const int4 v = *reinterpret_cast<const int4 *>(x + (int64_t)idx[j] * k + c);
-            acc.x += v.x;
-            acc.y += v.y;
-            acc.z += v.z;
-            acc.w += v.w;
+    if constexpr (NC > 0) {
+        RowPieces<NC> acc;
+        acc.zero();
+        int32_t j = a;
+        for (; j + U <= b; j += U) {
+            RowPieces<NC> m[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                m[u].load(x + (int64_t)idx[j + u] * k, lane, k);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                acc.add(m[u]);
         }
-        *reinterpret_cast<int4 *>(out + r * k + c) = acc;
-        if (SQ)
-            q += (int64_t)acc.x * acc.x + (int64_t)acc.y * acc.y + (int64_t)acc.z * acc.z + (int64_t)acc.w * acc.w;
-    }
-    if (SQ) {
-        for (int o = kWave / 2; o > 0; o >>= 1)
-            q += __shfl_xor(q, o);
-        if (lane == 0)
-            sq[r] = q;
+        for (; j < b; ++j) {
+            RowPieces<NC> m;
+            m.load(x + (int64_t)idx[j] * k, lane, k);
+            acc.add(m);
+        }
+        acc.store(out + r * k, lane, k);
+        if (SQ) {
+            const int64_t q = wave_sum(acc.dot(acc));
+            if (lane == 0)
+                sq[r] = q;
+        }
+    } else {
+        int64_t q = 0;
+        for (int c = lane * 4; c < k; c += kWave * 4) {
+            int4 acc = make_int4(0, 0, 0, 0);
+            for (int32_t j = a; j < b; ++j) {
+                const int4 v = *reinterpret_cast<const int4 *>(x + (int64_t)idx[j] * k + c);
+                acc.x += v.x;
+                acc.y += v.y;
+                acc.z += v.z;
+                acc.w += v.w;
+            }
+            *reinterpret_cast<int4 *>(out + r * k + c) = acc;
+            if (SQ)
+                q += (int64_t)acc.x * acc.x + (int64_t)acc.y * acc.y + (int64_t)acc.z * acc.z +
+                     (int64_t)acc.w * acc.w;
+        }
+        if (SQ) {
+            q = wave_sum(q);
+            if (lane == 0)
+                sq[r] = q;
+        }
     }
 }
 
@@ -353,35 +448,109 @@ __device__ inline unsigned long long ordered_bits(double q)
 }
 
 // per incidence (e, v): q = cosine score of e for v, kept in CSR order;
-// bestq[v] = max over v's incidences (atomic max: order-independent)
-__global__ __launch_bounds__(kThreads) void k_qscore(const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+// bestq[v] = max over v's incidences (atomic max: order-independent).
+// One wavefront takes 64 consecutive incidences, whatever their hyperedges:
+// lane l loads incidence l's node, hyperedge and |s_e|^2, the wavefront then
+// walks the 64 in steps of score_batch (rows broadcast by __shfl, the next
+// step's rows loaded before this step's reduction), and at the end lane l
+// finishes incidence l.
+template <int NC>
+constexpr int score_batch()
+{
+    return (NC == 0 || NC == 1) ? 4 : NC == 2 ? 2 : 1;
+}
+
+template <int NC>
+__global__ __launch_bounds__(kThreads) void k_qscore(const int32_t *__restrict__ idx,
+                                                     const int32_t *__restrict__ inc_edge,
                                                      const int32_t *__restrict__ s, const int64_t *__restrict__ s2,
-                                                     const int32_t *__restrict__ x, int k, int64_t n_edges,
+                                                     const int32_t *__restrict__ x, int k, int64_t nnz,
                                                      double *__restrict__ q, unsigned long long *__restrict__ bestq)
 {
-    const int64_t e = (int64_t)blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+    constexpr int U = score_batch<NC>();
+    static_assert(kWave % U == 0, "a step must divide the wavefront");
+    const int64_t j0 = ((int64_t)blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave) * kWave;
     const int lane = threadIdx.x & (kWave - 1);
-    if (e >= n_edges)
+    if (j0 >= nnz)
         return;
-    const int32_t *se = s + e * k;
-    const int64_t n2 = s2[e];
-    for (int32_t j = ptr[e]; j < ptr[e + 1]; ++j) {
-        const int32_t v = idx[j];
-        const int32_t *xv = x + (int64_t)v * k;
-        int64_t d = 0;
-        for (int c = lane * 4; c < k; c += kWave * 4) {
-            const int4 f = *reinterpret_cast<const int4 *>(se + c);
-            const int4 u = *reinterpret_cast<const int4 *>(xv + c);
-            d += (int64_t)f.x * u.x + (int64_t)f.y * u.y + (int64_t)f.z * u.z + (int64_t)f.w * u.w;
+    const int n = (int)std::min<int64_t>(kWave, nnz - j0);
+    const int32_t my_v = lane < n ? idx[j0 + lane] : 0;
+    const int32_t my_e = lane < n ? inc_edge[j0 + lane] : 0;
+    const int64_t my_s2 = lane < n ? s2[my_e] : 0;
+    int64_t mine = 0;
+    if constexpr (NC > 0) {
+        RowPieces<NC> f[U], m[U];
+        auto load_step = [&](int t) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t v = __shfl(my_v, t + u), e = __shfl(my_e, t + u);
+                if (t + u < n) {
+                    f[u].load(s + (int64_t)e * k, lane, k);
+                    m[u].load(x + (int64_t)v * k, lane, k);
+                } else {
+                    f[u].zero();
+                    m[u].zero();
+                }
+            }
+        };
+        load_step(0);
+        for (int t = 0; t < n; t += U) {
+            int64_t d[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                d[u] = f[u].dot(m[u]);
+            if (t + U < n)
+                load_step(t + U);
+            for (int o = kWave / 2; o > 0; o >>= 1) {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    d[u] += __shfl_xor(d[u], o);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (lane == t + u)
+                    mine = d[u];
         }
-        for (int o = kWave / 2; o > 0; o >>= 1)
-            d += __shfl_xor(d, o);
-        if (lane == 0) {
-            const double sc = cosine_score(d, n2);
-            q[j] = sc;
-            atomicMax(bestq + v, ordered_bits(sc));
+    } else {
+        for (int t = 0; t < n; ++t) {
+            const int32_t v = __shfl(my_v, t), e = __shfl(my_e, t);
+            int64_t d = 0;
+            for (int c = lane * 4; c < k; c += kWave * 4) {
+                const int4 fc = *reinterpret_cast<const int4 *>(s + (int64_t)e * k + c);
+                const int4 mc = *reinterpret_cast<const int4 *>(x + (int64_t)v * k + c);
+                d += (int64_t)fc.x * mc.x + (int64_t)fc.y * mc.y + (int64_t)fc.z * mc.z + (int64_t)fc.w * mc.w;
+            }
+            d = wave_sum(d);
+            if (lane == t)
+                mine = d;
         }
     }
+    if (lane < n) {
+        const double sc = cosine_score(mine, my_s2);
+        q[j0 + lane] = sc;
+        atomicMax(bestq + my_v, ordered_bits(sc));
+    }
+}
+
+// The register bound NC for a feature width k (0: wider than 2048).
+inline int pieces_for(int k) { return k <= 256 ? 1 : k <= 512 ? 2 : k <= 1024 ? 4 : k <= 2048 ? 8 : 0; }
+
+template <int NC>
+void launch_edge_features(unsigned grid, hipStream_t st, const int32_t *ptr, const int32_t *idx,
+                          const int32_t *inc_edge, const int32_t *x, int k, int64_t n_edges, int64_t nnz,
+                          int32_t *fsum, int64_t *fsq, double *q, unsigned long long *bestq)
+{
+    k_rowsum<true, NC><<<grid, kThreads, 0, st>>>(ptr, idx, x, k, n_edges, nullptr, fsum, fsq);
+    const int64_t waves = (nnz + kWave - 1) / kWave;
+    const unsigned sgrid = (unsigned)((waves + kThreads / kWave - 1) / (kThreads / kWave));
+    k_qscore<NC><<<sgrid, kThreads, 0, st>>>(idx, inc_edge, fsum, fsq, x, k, nnz, q, bestq);
+}
+
+template <int NC>
+void launch_group_sums(unsigned grid, hipStream_t st, const int32_t *gptr, const int32_t *gnodes, const int32_t *x,
+                       int k, int64_t n_rows, const int64_t *limit, int32_t *out)
+{
+    k_rowsum<false, NC><<<grid, kThreads, 0, st>>>(gptr, gnodes, x, k, n_rows, limit, out, nullptr);
 }
 
 // best[v] = least rank among v's hyperedges whose score equals bestq[v]
@@ -653,8 +822,13 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
             const unsigned wave_grid = (unsigned)((n_edges + kThreads / kWave - 1) / (kThreads / kWave));
             k_fill<<<grid_for(2 * (int64_t)nV), kThreads, 0, s>>>(reinterpret_cast<int32_t *>(bestq),
                                                                    2 * (int64_t)nV, 0);
-            k_rowsum<true><<<wave_grid, kThreads, 0, s>>>(edge_ptr, edge_idx, x, k, n_edges, nullptr, fsum, fsq);
-            k_qscore<<<wave_grid, kThreads, 0, s>>>(edge_ptr, edge_idx, fsum, fsq, x, k, n_edges, q, bestq);
+            switch (pieces_for(k)) {
+            case 1: launch_edge_features<1>(wave_grid, s, edge_ptr, edge_idx, inc_edge, x, k, n_edges, nnz, fsum, fsq, q, bestq); break;
+            case 2: launch_edge_features<2>(wave_grid, s, edge_ptr, edge_idx, inc_edge, x, k, n_edges, nnz, fsum, fsq, q, bestq); break;
+            case 4: launch_edge_features<4>(wave_grid, s, edge_ptr, edge_idx, inc_edge, x, k, n_edges, nnz, fsum, fsq, q, bestq); break;
+            case 8: launch_edge_features<8>(wave_grid, s, edge_ptr, edge_idx, inc_edge, x, k, n_edges, nnz, fsum, fsq, q, bestq); break;
+            default: launch_edge_features<0>(wave_grid, s, edge_ptr, edge_idx, inc_edge, x, k, n_edges, nnz, fsum, fsq, q, bestq);
+            }
             k_best_feat<<<grid_for(nz), kThreads, 0, s>>>(edge_idx, inc_edge, rank, q, bestq, nnz, best);
         }
         k_choice<<<grid_for(nV), kThreads, 0, s>>>(best, order, n_nodes, choice, first, count);
@@ -701,7 +875,13 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
             return fail(HNV_EDEVICE, "scan of group sizes");
         k_group_fill<<<grid_for(nV), kThreads, 0, s>>>(node_rep, gptr, n_nodes, gcur, gnodes);
         const unsigned wave_grid = (unsigned)((n_nodes + kThreads / kWave - 1) / (kThreads / kWave));
-        k_rowsum<false><<<wave_grid, kThreads, 0, s>>>(gptr, gnodes, x, k, n_nodes, sizes, c_x, nullptr);
+        switch (pieces_for(k)) {
+        case 1: launch_group_sums<1>(wave_grid, s, gptr, gnodes, x, k, n_nodes, sizes, c_x); break;
+        case 2: launch_group_sums<2>(wave_grid, s, gptr, gnodes, x, k, n_nodes, sizes, c_x); break;
+        case 4: launch_group_sums<4>(wave_grid, s, gptr, gnodes, x, k, n_nodes, sizes, c_x); break;
+        case 8: launch_group_sums<8>(wave_grid, s, gptr, gnodes, x, k, n_nodes, sizes, c_x); break;
+        default: launch_group_sums<0>(wave_grid, s, gptr, gnodes, x, k, n_nodes, sizes, c_x);
+        }
     }
     if ((st = dev_check("coarsening kernels")) != HNV_OK)
         return st;
