@@ -8,7 +8,8 @@
  * runs the refinement on the GPU: per level, the projection of the coarser
  * embedding and repeated smoothing sweeps over the star expansion H*
  * (Section 1.1), plus the reverse mode of both.  Coarsening runs on the host
- * or on the GPU, with identical results.
+ * or on the GPU, with identical results, and a plan can be built from host or
+ * from device-resident levels.
  *
  * Conventions used by every call
  *   - Star-expansion rows of a level: nodes first, then hyperedges.  Row v is
@@ -194,6 +195,40 @@ hnv_status hnv_plan_workspace_bytes(const hnv_level *levels, const hnv_map *maps
 hnv_status hnv_plan_create(const hnv_level *levels, const hnv_map *maps, int n_levels, int d,
                            hnv_dtype dtype, const hnv_options *opts, int validate, void *workspace,
                            size_t ws_bytes, void *stream, hnv_plan **out);
+
+/* A level in DEVICE memory with 32-bit offsets: the form the GPU coarsening
+ * (hnv_coarsen_level_device) takes and returns.  Same meaning and limits as
+ * hnv_level. */
+typedef struct {
+    int64_t n_nodes;
+    int64_t n_edges;
+    int64_t nnz;
+    const int32_t *edge_ptr;   /* DEVICE [n_edges+1] */
+    const int32_t *edge_idx;   /* DEVICE [nnz] */
+    const float *edge_w;       /* DEVICE [n_edges] or NULL */
+} hnv_level_dev;
+
+/* The same plan built on the GPU from device-resident levels and maps (the
+ * hnv_map pointers are then DEVICE pointers), so that coarsening, plan and
+ * refinement never leave the device.  The plan is identical to the one
+ * hnv_plan_create builds from host copies of the same levels: the same
+ * adjacency, work lists in the same order, the same reciprocals, hence
+ * bit-identical results from every call that takes a plan.
+ * hnv_plan_workspace_bytes_device gives the workspace size from the level
+ * sizes alone (no device reads; the work lists are sized at their upper
+ * bounds, and the build's temporaries use the plan's scratch embedding when
+ * it is large enough, else extra space after it).  The temporary storage of
+ * the GPU sorts and scans is queried from the device, so both calls need a
+ * visible GPU.  validate != 0 runs, on the device, the checks that
+ * hnv_validate_level and hnv_plan_create(validate = 1) run; offsets, index
+ * ranges and map ranges are always checked.  The level and map arrays are
+ * read during the call only.  Synchronises `stream` several times (the
+ * checks and the work-list sizes are read back) and before returning. */
+hnv_status hnv_plan_workspace_bytes_device(const hnv_level_dev *levels, const hnv_map *maps, int n_levels, int d,
+                                           hnv_dtype dtype, const hnv_options *opts, size_t *bytes);
+hnv_status hnv_plan_create_device(const hnv_level_dev *levels, const hnv_map *maps, int n_levels, int d,
+                                  hnv_dtype dtype, const hnv_options *opts, int validate, void *workspace,
+                                  size_t ws_bytes, void *stream, hnv_plan **out);
 
 /* Frees the plan's host state; the workspace stays the caller's. */
 hnv_status hnv_plan_destroy(hnv_plan *plan);

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhnv.so")
 SOURCES = [os.path.join(CSRC, "hnv_host.cpp"), os.path.join(CSRC, "hnv_kernels.hip"),
-           os.path.join(CSRC, "hnv_coarsen.hip")]
+           os.path.join(CSRC, "hnv_coarsen.hip"), os.path.join(CSRC, "hnv_devplan.hip")]
 ARCH = os.environ.get("HNV_OFFLOAD_ARCH", "gfx950")
 
 

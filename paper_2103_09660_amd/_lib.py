@@ -34,8 +34,18 @@ class HnvLevel(ctypes.Structure):
                 ("edge_ptr", i64p), ("edge_idx", i32p), ("edge_w", f32p)]
 
 
+class HnvLevelDev(ctypes.Structure):
+    _fields_ = [("n_nodes", i64), ("n_edges", i64), ("nnz", i64),
+                ("edge_ptr", vp), ("edge_idx", vp), ("edge_w", vp)]
+
+
 class HnvMap(ctypes.Structure):
     _fields_ = [("node_rep", i32p), ("edge_rep", i32p)]
+
+
+class HnvMapDev(ctypes.Structure):
+    """hnv_map holding device pointers."""
+    _fields_ = [("node_rep", vp), ("edge_rep", vp)]
 
 
 class HnvOptions(ctypes.Structure):
@@ -66,6 +76,12 @@ _SIGS = {
     "hnv_plan_create": (ctypes.c_int, [ctypes.POINTER(HnvLevel), ctypes.POINTER(HnvMap), ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int, ctypes.POINTER(HnvOptions), ctypes.c_int, vp, ctypes.c_size_t,
                                        vp, ctypes.POINTER(vp)]),
+    "hnv_plan_workspace_bytes_device": (ctypes.c_int, [ctypes.POINTER(HnvLevelDev), ctypes.POINTER(HnvMapDev),
+                                                       ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                       ctypes.POINTER(HnvOptions), ctypes.POINTER(ctypes.c_size_t)]),
+    "hnv_plan_create_device": (ctypes.c_int, [ctypes.POINTER(HnvLevelDev), ctypes.POINTER(HnvMapDev), ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_int, ctypes.POINTER(HnvOptions), ctypes.c_int,
+                                              vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
     "hnv_plan_destroy": (ctypes.c_int, [vp]),
     "hnv_plan_level_info": (ctypes.c_int, [vp, ctypes.c_int, i64p, i64p, i64p]),
     "hnv_set_edge_weights": (ctypes.c_int, [vp, ctypes.c_int, vp, vp]),

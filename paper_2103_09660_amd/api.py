@@ -323,6 +323,38 @@ class Plan:
                1 if validate else 0, self.workspace.data_ptr(), nbytes, _stream(self.device), ctypes.byref(handle))
         self._h = handle
 
+    @classmethod
+    def from_device(cls, levels: Sequence[DeviceLevel], maps: Sequence, d: int, dtype: str = "f32", options=None,
+                    validate: bool = True) -> "Plan":
+        """A plan built on the GPU from device levels (finest first, e.g. from
+        :func:`coarsen_hierarchy_device`) and device maps [(node_rep,
+        edge_rep)]: identical to the plan built from host copies."""
+        torch = _torch()
+        self = cls.__new__(cls)
+        self.device = levels[0].edge_ptr.device
+        self.hier = None
+        self.d = int(d)
+        self.dtype = dtype
+        self.torch_dtype = torch.float32 if _dt(dtype) == L.HNV_F32 else torch.bfloat16
+        self.n_levels = len(levels)
+        if len(maps) != self.n_levels - 1:
+            raise ValueError("need one map per coarsening step")
+        lv = (L.HnvLevelDev * self.n_levels)(*[L.HnvLevelDev(x.n_nodes, x.n_edges, x.nnz, _ptr(x.edge_ptr),
+                                                             _ptr(x.edge_idx), _ptr(x.edge_w)) for x in levels])
+        mp = (L.HnvMapDev * max(len(maps), 1))(*[L.HnvMapDev(_ptr(a), _ptr(b)) for a, b in maps])
+        o = _options(options)
+        ob = None if o is None else ctypes.byref(o)
+        nbytes = ctypes.c_size_t()
+        with torch.cuda.device(self.device):
+            L.call("hnv_plan_workspace_bytes_device", lv, mp, self.n_levels, self.d, _dt(dtype), ob,
+                   ctypes.byref(nbytes))
+            self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+            handle = ctypes.c_void_p()
+            L.call("hnv_plan_create_device", lv, mp, self.n_levels, self.d, _dt(dtype), ob, 1 if validate else 0,
+                   self.workspace.data_ptr(), int(nbytes.value), _stream(self.device), ctypes.byref(handle))
+        self._h = handle
+        return self
+
     def close(self):
         if getattr(self, "_h", None):
             L.lib().hnv_plan_destroy(self._h)

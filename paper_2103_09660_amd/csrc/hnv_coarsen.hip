@@ -35,76 +35,10 @@
 #include <string>
 
 #include "hnv_internal.h"
+#include "hnv_level_check.h"
 
 namespace hnv {
 namespace {
-
-constexpr int kThreads = 256;
-
-inline unsigned grid_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
-
-// Input check.  Flag bits: 0 offsets, 1 member range, 2 member order,
-// 3 weights.  Offsets and weights per hyperedge:
-__global__ __launch_bounds__(kThreads) void k_check_edges(const int32_t *__restrict__ ptr,
-                                                          const float *__restrict__ w, int64_t n_edges,
-                                                          int64_t nnz, int *__restrict__ flag)
-{
-    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (e >= n_edges)
-        return;
-    const int64_t a = ptr[e], b = ptr[e + 1];
-    int bad = 0;
-    if (a < 0 || b <= a || b > nnz || (e == 0 && a != 0) || (e == n_edges - 1 && b != nnz))
-        bad |= 1;
-    if (w && !(w[e] > 0.0f && w[e] < INFINITY))
-        bad |= 8;
-    if (bad)
-        atomicOr(flag, bad);
-}
-
-// inc_edge[j] = the hyperedge of incidence j: each hyperedge writes its id at
-// its first incidence (over a zero fill), an inclusive max-scan spreads it.
-// Offsets outside [0, nnz) are skipped here and reported by k_check_edges.
-__global__ __launch_bounds__(kThreads) void k_heads(const int32_t *__restrict__ ptr, int64_t n_edges, int64_t nnz,
-                                                    int32_t *__restrict__ inc_edge)
-{
-    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (e >= n_edges)
-        return;
-    const int32_t a = ptr[e];
-    if (a >= 0 && a < nnz && ptr[e + 1] > a)
-        inc_edge[a] = (int32_t)e;
-}
-
-// member range and order per incidence (inc_edge is only meaningful when
-// the offsets are valid; every read stays in bounds either way)
-__global__ __launch_bounds__(kThreads) void k_check_members(const int32_t *__restrict__ ptr,
-                                                            const int32_t *__restrict__ idx,
-                                                            const int32_t *__restrict__ inc_edge, int64_t n_nodes,
-                                                            int64_t n_edges, int64_t nnz, int *__restrict__ flag)
-{
-    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (j >= nnz)
-        return;
-    const int32_t v = idx[j];
-    int bad = 0;
-    if (v < 0 || v >= n_nodes) {
-        bad = 2;
-    } else if (j > 0) {
-        const int32_t e = inc_edge[j];
-        if (e >= 0 && e < n_edges && j > ptr[e] && idx[j - 1] >= v)
-            bad = 4;
-    }
-    if (bad)
-        atomicOr(flag, bad);
-}
-
-__global__ __launch_bounds__(kThreads) void k_fill(int32_t *__restrict__ p, int64_t n, int32_t v)
-{
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i < n)
-        p[i] = v;
-}
 
 __global__ __launch_bounds__(kThreads) void k_keys(const int32_t *__restrict__ ptr, const float *__restrict__ w,
                                                    int64_t n_edges, uint64_t *__restrict__ keys,
@@ -606,15 +540,6 @@ hnv_status sort_storage(int64_t nE, int64_t nnz, int key_bits, int member_bits, 
     return HNV_OK;
 }
 
-// Bits that hold every value in [0, n).
-int bits_for(int64_t n)
-{
-    int b = 1;
-    while (b < 32 && (int64_t(1) << b) < n)
-        ++b;
-    return b;
-}
-
 struct CoarsenLayout {
     size_t keys_in, keys_out, ids_in, order, rank, best, choice, first, count, gflag, gid, kept, krank, mapped,
         sorted, inc_edge, dflag, dpos, sizes, flag;
@@ -738,7 +663,7 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
     k_fill<<<1, kThreads, 0, s>>>(flag, 4, 0);
     int32_t *inc_edge = at(L.inc_edge), *dflag = at(L.dflag), *dpos = at(L.dpos);
     if (nE > 0) {
-        k_check_edges<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, edge_w, n_edges, nnz, flag);
+        k_check_edges<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, edge_w, n_edges, nnz, 1, flag);
         if (nz > 0) {
             k_fill<<<grid_for(nz), kThreads, 0, s>>>(dpos, nnz, 0);
             k_heads<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, n_edges, nnz, dpos);
@@ -746,7 +671,7 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
             if (hipcub::DeviceScan::InclusiveScan(base + L.temp, tbs, dpos, inc_edge, hipcub::Max(), nz, s) !=
                 hipSuccess)
                 return fail(HNV_EDEVICE, "scan of hyperedge heads");
-            k_check_members<<<grid_for(nz), kThreads, 0, s>>>(edge_ptr, edge_idx, inc_edge, n_nodes, n_edges, nnz,
+            k_check_members<<<grid_for(nz), kThreads, 0, s>>>(edge_ptr, edge_idx, inc_edge, n_nodes, n_edges, nnz, 1,
                                                               flag);
         }
     }

@@ -1,0 +1,724 @@
+// Plan construction on the GPU from device-resident levels (the output of
+// the GPU coarsening), producing the same plan as hnv_plan_create builds on
+// the host, array for array:
+//   side 0 (hyperedge rows): the member lists as given;
+//   side 1 (node rows): each node's hyperedges in ascending id, from a stable
+//     radix sort of the incidences by node;
+//   projection row map, composed indices, inverse map (a stable sort of the
+//     fine rows by coarse row);
+//   degree tiers: rows of at most small_max neighbours ordered by degree
+//     descending then row (a stable sort on small_max - degree), longer rows
+//     cut into chunks laid out in row order and stably sorted longest first,
+//     split rows with consecutive partial slots, side 0 before side 1;
+//   weights and the FP64 reciprocals as for a host-built plan.
+// The workspace is sized from the level sizes alone, with the work-list
+// arrays at their upper bounds; the build's temporaries live in the plan's
+// scratch embedding when it is large enough, else after the plan.
+#include <hip/hip_runtime.h>
+
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <climits>
+#include <string>
+#include <vector>
+
+#include "hnv_internal.h"
+#include "hnv_level_check.h"
+
+namespace hnv {
+namespace {
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+// Map checks.  Flag bits: 4 node map range, 5 hyperedge map range, 6 a
+// removed hyperedge without members, 7 (full) a removed hyperedge whose
+// members lie in different coarse nodes.
+__global__ __launch_bounds__(kThreads) void k_check_node_map(const int32_t *__restrict__ node_rep, int64_t n_nodes,
+                                                             int64_t n_nodes_c, int *__restrict__ flag)
+{
+    const int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (v < n_nodes && (node_rep[v] < 0 || node_rep[v] >= n_nodes_c))
+        atomicOr(flag, 1 << 4);
+}
+
+__global__ __launch_bounds__(kThreads) void k_check_edge_map(const int32_t *__restrict__ ptr,
+                                                             const int32_t *__restrict__ idx,
+                                                             const int32_t *__restrict__ node_rep,
+                                                             const int32_t *__restrict__ edge_rep, int64_t n_nodes,
+                                                             int64_t n_edges, int64_t n_edges_c, int full,
+                                                             int *__restrict__ flag)
+{
+    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= n_edges)
+        return;
+    const int32_t r = edge_rep[e];
+    int bad = 0;
+    if (r < -1 || r >= n_edges_c) {
+        bad = 1 << 5;
+    } else if (r == -1) {
+        const int32_t a = ptr[e], b = ptr[e + 1];
+        if (b == a) {
+            bad = 1 << 6;
+        } else if (full) {
+            // members were range-checked before this kernel runs
+            const int32_t first = node_rep[idx[a]];
+            for (int32_t j = a + 1; j < b; ++j)
+                if (node_rep[idx[j]] != first)
+                    bad = 1 << 7;
+        }
+    }
+    if (bad)
+        atomicOr(flag, bad);
+}
+
+__global__ __launch_bounds__(kThreads) void k_degrees(const int32_t *__restrict__ idx, int64_t nnz,
+                                                      int32_t *__restrict__ deg)
+{
+    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (j < nnz)
+        atomicAdd(deg + idx[j], 1);
+}
+
+__global__ __launch_bounds__(kThreads) void k_iota(int64_t n, int32_t *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n)
+        out[i] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(kThreads) void k_add_const(const int32_t *__restrict__ in, int64_t n, int32_t c,
+                                                        int32_t *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n)
+        out[i] = in[i] + c;
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill_f32(float *__restrict__ p, int64_t n, float v)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n)
+        p[i] = v;
+}
+
+// projection row map: node v -> rep(v); kept hyperedge -> n_nodes_c + rep(e);
+// removed hyperedge -> the coarse node its members were merged into
+__global__ __launch_bounds__(kThreads) void k_rowmap(const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                                     const int32_t *__restrict__ node_rep,
+                                                     const int32_t *__restrict__ edge_rep, int64_t n_nodes,
+                                                     int64_t n_edges, int64_t n_nodes_c, int32_t *__restrict__ rowmap)
+{
+    const int64_t u = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (u >= n_nodes + n_edges)
+        return;
+    if (u < n_nodes) {
+        rowmap[u] = node_rep[u];
+        return;
+    }
+    const int64_t e = u - n_nodes;
+    const int32_t r = edge_rep[e];
+    rowmap[u] = (r >= 0) ? (int32_t)(n_nodes_c + r) : node_rep[idx[ptr[e]]];
+}
+
+__global__ __launch_bounds__(kThreads) void k_compose(const int32_t *__restrict__ idx,
+                                                      const int32_t *__restrict__ map, int64_t n,
+                                                      int32_t *__restrict__ out)
+{
+    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (j < n)
+        out[j] = map[idx[j]];
+}
+
+// per row of one side: the small-tier sort key (small_max - degree, or
+// small_max + 1 for longer rows), the row id, its chunk count, whether it is
+// split, and its partial slots
+__global__ __launch_bounds__(kThreads) void k_tier_keys(const int32_t *__restrict__ ptr, int64_t n_rows,
+                                                        int small_max, int chunk, uint32_t *__restrict__ key,
+                                                        int32_t *__restrict__ row, int32_t *__restrict__ pieces,
+                                                        int32_t *__restrict__ split, int32_t *__restrict__ slots)
+{
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r >= n_rows)
+        return;
+    const int32_t deg = ptr[r + 1] - ptr[r];
+    const bool small = deg <= small_max;
+    const int32_t pc = small ? 0 : (deg + chunk - 1) / chunk;
+    key[r] = small ? (uint32_t)(small_max - deg) : (uint32_t)(small_max + 1);
+    row[r] = (int32_t)r;
+    pieces[r] = pc;
+    split[r] = pc > 1 ? 1 : 0;
+    slots[r] = pc > 1 ? pc : 0;
+}
+
+// counts[0..3] of one side: small rows, chunks, split rows, partial slots
+// (exclusive scans plus their last terms; the small rows from the sorted keys)
+__global__ void k_tier_counts(const uint32_t *__restrict__ sorted_key, const int32_t *__restrict__ pieces,
+                              const int32_t *__restrict__ cpos, const int32_t *__restrict__ split,
+                              const int32_t *__restrict__ spos, const int32_t *__restrict__ slots,
+                              const int32_t *__restrict__ sbase, int64_t n_rows, int small_max,
+                              int64_t *__restrict__ counts)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    if (n_rows == 0) {
+        counts[0] = counts[1] = counts[2] = counts[3] = 0;
+        return;
+    }
+    // sorted ascending: small rows first; binary search for the first long row
+    int64_t lo = 0, hi = n_rows;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (sorted_key[mid] <= (uint32_t)small_max)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    counts[0] = lo;
+    counts[1] = (int64_t)cpos[n_rows - 1] + pieces[n_rows - 1];
+    counts[2] = (int64_t)spos[n_rows - 1] + split[n_rows - 1];
+    counts[3] = (int64_t)sbase[n_rows - 1] + slots[n_rows - 1];
+}
+
+// lane-group tier items in sorted order; aux = the coarse row the row's own
+// value is projected from (0 at the coarsest level)
+__global__ __launch_bounds__(kThreads) void k_small_items(const int32_t *__restrict__ sorted_row,
+                                                          const int32_t *__restrict__ ptr, int64_t n_small,
+                                                          const int32_t *__restrict__ rowmap, int32_t row_base,
+                                                          Item *__restrict__ items)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n_small)
+        return;
+    const int32_t r = sorted_row[i];
+    items[i] = Item{r, ptr[r], ptr[r + 1] - ptr[r], rowmap ? rowmap[row_base + r] : 0};
+}
+
+// wavefront tier items in row order (pieces of a row in order), with the
+// sort key chunk - len (a stable ascending sort puts the longest first)
+__global__ __launch_bounds__(kThreads) void k_chunk_items(const int32_t *__restrict__ ptr, int64_t n_rows, int chunk,
+                                                          const int32_t *__restrict__ pieces,
+                                                          const int32_t *__restrict__ cpos,
+                                                          const int32_t *__restrict__ sbase, int32_t slot_offset,
+                                                          Item *__restrict__ items, uint32_t *__restrict__ key,
+                                                          int32_t *__restrict__ id)
+{
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r >= n_rows)
+        return;
+    const int32_t pc = pieces[r];
+    for (int32_t k = 0; k < pc; ++k) {
+        const int32_t pos = cpos[r] + k;
+        const int32_t s = ptr[r] + k * chunk;
+        const int32_t len = min(chunk, ptr[r + 1] - s);
+        items[pos] = Item{(int32_t)r, s, len, pc == 1 ? -1 : slot_offset + sbase[r] + k};
+        key[pos] = (uint32_t)(chunk - len);
+        id[pos] = pos;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_gather_items(const Item *__restrict__ in,
+                                                           const int32_t *__restrict__ order, int64_t n,
+                                                           Item *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n)
+        out[i] = in[order[i]];
+}
+
+__global__ __launch_bounds__(kThreads) void k_split_items(const int32_t *__restrict__ ptr, int64_t n_rows,
+                                                          const int32_t *__restrict__ pieces,
+                                                          const int32_t *__restrict__ spos,
+                                                          const int32_t *__restrict__ sbase, int32_t slot_offset,
+                                                          Split *__restrict__ splits)
+{
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r >= n_rows || pieces[r] <= 1)
+        return;
+    splits[spos[r]] = Split{(int32_t)r, slot_offset + sbase[r], pieces[r], ptr[r + 1] - ptr[r]};
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+// Work-list bounds from the sizes alone (see the tiering rules above): rows
+// longer than small_max number at most nnz / (small_max + 1), each has at
+// most degree / chunk + 1 pieces, and only rows longer than chunk split.
+LevelShape bound_shape(const hnv_level_dev &lv, const hnv_level_dev *coarse, int small_max, int chunk)
+{
+    LevelShape sh;
+    sh.nV = lv.n_nodes;
+    sh.nE = lv.n_edges;
+    sh.nnz = lv.nnz;
+    sh.rows = sh.nV + sh.nE;
+    sh.has_coarse = coarse != nullptr;
+    sh.rows_c = coarse ? coarse->n_nodes + coarse->n_edges : 0;
+    sh.unit_w = lv.edge_w == nullptr;
+    auto cap = [](int64_t v) { return (int32_t)std::min<int64_t>(v, INT_MAX); };
+    int64_t slots = 0;
+    for (int s = 0; s < 2; ++s) {
+        const int64_t n_rows = s == 0 ? sh.nE : sh.nV;
+        sh.n_small[s] = cap(n_rows);
+        sh.n_chunks[s] = cap(std::min<int64_t>(sh.nnz / chunk + sh.nnz / (small_max + 1) + 1, sh.nnz + 1));
+        sh.n_splits[s] = cap(sh.nnz / (chunk + 1) + 1);
+        slots += 2 * (sh.nnz / chunk) + 1;
+    }
+    sh.n_slots = cap(slots);
+    return sh;
+}
+
+// Temporaries of one level's build, carved from `base` (nullptr: sizing).
+struct Scratch {
+    int32_t *inc_edge, *heads, *deg, *csc_e, *keys_out, *rows_a, *rows_b, *pieces, *cpos, *split, *spos, *slots,
+        *sbase, *ids_a, *ids_b;
+    uint32_t *key_a, *key_b;
+    Item *items;
+    int *flag;
+    int64_t *counts;
+    void *temp;
+    size_t temp_bytes, total;
+};
+
+hnv_status cub_sizes(int64_t nnz, int64_t rows, int64_t n_chunks, size_t &bytes)
+{
+    size_t t[6] = {0, 0, 0, 0, 0, 0};
+    const int n = (int)std::max<int64_t>(std::max(nnz, rows) + 1, 1);
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, t[0], (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                                      (int32_t *)nullptr, (int32_t *)nullptr, n, 0, 32);
+    if (e == hipSuccess)
+        e = hipcub::DeviceScan::ExclusiveSum(nullptr, t[1], (int32_t *)nullptr, (int32_t *)nullptr, n);
+    if (e == hipSuccess)
+        e = hipcub::DeviceScan::InclusiveScan(nullptr, t[2], (int32_t *)nullptr, (int32_t *)nullptr, hipcub::Max(),
+                                              (int)std::max<int64_t>(nnz, 1));
+    if (e == hipSuccess)
+        e = hipcub::DeviceRadixSort::SortPairs(nullptr, t[3], (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                               (int32_t *)nullptr, (int32_t *)nullptr,
+                                               (int)std::max<int64_t>(n_chunks, 1), 0, 32);
+    if (e != hipSuccess)
+        return fail(HNV_EDEVICE, std::string("sort / scan storage query (needs a visible GPU): ") +
+                                     hipGetErrorString(e));
+    bytes = *std::max_element(t, t + 6);
+    return HNV_OK;
+}
+
+hnv_status scratch_layout(int64_t nnz, int64_t rows, int64_t n_chunks, char *base, Scratch &S)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        off = (off + 255) & ~size_t(255);
+        char *p = base ? base + off : nullptr;
+        off += std::max<size_t>(bytes, 8);
+        return p;
+    };
+    const size_t n4 = 4 * (size_t)std::max(nnz, rows + 1);
+    S.inc_edge = (int32_t *)take(4 * nnz);
+    S.heads = (int32_t *)take(4 * nnz);
+    S.deg = (int32_t *)take(n4);
+    S.csc_e = (int32_t *)take(n4);
+    S.keys_out = (int32_t *)take(n4);
+    S.rows_a = (int32_t *)take(4 * (rows + 1));
+    S.rows_b = (int32_t *)take(4 * (rows + 1));
+    S.pieces = (int32_t *)take(4 * (rows + 1));
+    S.cpos = (int32_t *)take(4 * (rows + 1));
+    S.split = (int32_t *)take(4 * (rows + 1));
+    S.spos = (int32_t *)take(4 * (rows + 1));
+    S.slots = (int32_t *)take(4 * (rows + 1));
+    S.sbase = (int32_t *)take(4 * (rows + 1));
+    S.key_a = (uint32_t *)take(4 * std::max(rows + 1, n_chunks));
+    S.key_b = (uint32_t *)take(4 * std::max(rows + 1, n_chunks));
+    S.ids_a = (int32_t *)take(4 * n_chunks);
+    S.ids_b = (int32_t *)take(4 * n_chunks);
+    S.items = (Item *)take(sizeof(Item) * n_chunks);
+    S.flag = (int *)take(16);
+    S.counts = (int64_t *)take(8 * 8);
+    if (hnv_status st = cub_sizes(nnz, rows, n_chunks, S.temp_bytes); st != HNV_OK)
+        return st;
+    S.temp = take(S.temp_bytes);
+    S.total = (off + 255) & ~size_t(255);
+    return HNV_OK;
+}
+
+// plan layout and build-scratch size for these levels
+hnv_status device_layout(const hnv_level_dev *levels, int n_levels, int d, hnv_dtype dtype, const hnv_options &o,
+                         hnv_plan *p, std::vector<LevelShape> &bounds, size_t &scratch_bytes, bool &scratch_in_zbuf,
+                         size_t &total)
+{
+    bounds.assign(n_levels, LevelShape{});
+    std::vector<LevelShape> sizes(n_levels);
+    for (int l = 0; l < n_levels; ++l) {
+        sizes[l].nV = levels[l].n_nodes;
+        sizes[l].nE = levels[l].n_edges;
+        sizes[l].nnz = levels[l].nnz;
+        sizes[l].unit_w = levels[l].edge_w == nullptr;
+    }
+    init_plan_shape(p, sizes, d, dtype, o);
+    scratch_bytes = 0;
+    for (int l = 0; l < n_levels; ++l) {
+        bounds[l] = bound_shape(levels[l], l + 1 < n_levels ? &levels[l + 1] : nullptr, p->small_max, o.chunk);
+        Scratch S{};
+        const int32_t nch = std::max(bounds[l].n_chunks[0], bounds[l].n_chunks[1]);
+        if (hnv_status st = scratch_layout(bounds[l].nnz, bounds[l].rows, nch, nullptr, S);
+            st != HNV_OK)
+            return st;
+        scratch_bytes = std::max(scratch_bytes, S.total);
+    }
+    carve(p, bounds, nullptr);
+    const size_t zbuf_bytes = (size_t)p->lv[0].rows * p->d * ((dtype == HNV_BF16) ? 2 : 4);
+    scratch_in_zbuf = scratch_bytes <= zbuf_bytes;
+    total = p->ws_bytes + (scratch_in_zbuf ? 0 : scratch_bytes);
+    return HNV_OK;
+}
+
+hnv_status check_levels(const hnv_level_dev *levels, const hnv_map *maps, int n_levels)
+{
+    if (!levels || n_levels < 1)
+        return fail(HNV_EINVAL, "need at least one level");
+    if (n_levels > 1 && !maps)
+        return fail(HNV_EINVAL, "maps is NULL with more than one level");
+    for (int l = 0; l < n_levels; ++l) {
+        const hnv_level_dev &L = levels[l];
+        if (L.n_nodes < 0 || L.n_edges < 0 || L.nnz < 0 || !L.edge_ptr || (L.nnz > 0 && !L.edge_idx))
+            return fail(HNV_EINVAL, "level " + std::to_string(l) + ": bad sizes or NULL arrays");
+        if (L.n_nodes + L.n_edges >= INT_MAX || L.nnz >= INT_MAX)
+            return fail(HNV_EUNSUPPORTED, "level " + std::to_string(l) + ": rows and nnz must be below 2^31");
+        if (l + 1 < n_levels && ((L.n_nodes > 0 && !maps[l].node_rep) || (L.n_edges > 0 && !maps[l].edge_rep)))
+            return fail(HNV_EINVAL, "map " + std::to_string(l) + " has a NULL array");
+    }
+    return HNV_OK;
+}
+
+hnv_status read_back(void *dst, const void *src, size_t n, hipStream_t s)
+{
+    hipError_t e = hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    return e == hipSuccess ? HNV_OK : fail(HNV_EDEVICE, std::string("read-back: ") + hipGetErrorString(e));
+}
+
+hnv_status copy_d2d(void *dst, const void *src, size_t n, hipStream_t s)
+{
+    if (n == 0)
+        return HNV_OK;
+    hipError_t e = hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? HNV_OK : fail(HNV_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+}
+
+// checks of level l (and of map l when there is a coarser level)
+hnv_status check_level(const hnv_level_dev &L, const hnv_level_dev *C, const hnv_map *m, int l, bool full,
+                       Scratch &S, hipStream_t s)
+{
+    const int64_t nV = L.n_nodes, nE = L.n_edges, nnz = L.nnz;
+    k_fill<<<1, kThreads, 0, s>>>(S.flag, 4, 0);
+    if (nE > 0) {
+        k_check_edges<<<grid_for(nE), kThreads, 0, s>>>(L.edge_ptr, L.edge_w, nE, nnz, full ? 1 : 0, S.flag);
+        if (nnz > 0) {
+            k_fill<<<grid_for(nnz), kThreads, 0, s>>>(S.heads, nnz, 0);
+            k_heads<<<grid_for(nE), kThreads, 0, s>>>(L.edge_ptr, nE, nnz, S.heads);
+            size_t tb = S.temp_bytes;
+            if (hipcub::DeviceScan::InclusiveScan(S.temp, tb, S.heads, S.inc_edge, hipcub::Max(), (int)nnz, s) !=
+                hipSuccess)
+                return fail(HNV_EDEVICE, "scan of hyperedge heads");
+            k_check_members<<<grid_for(nnz), kThreads, 0, s>>>(L.edge_ptr, L.edge_idx, S.inc_edge, nV, nE, nnz,
+                                                              full ? 1 : 0, S.flag);
+        }
+    }
+    if (hnv_status st = dev_check("level checks"); st != HNV_OK)
+        return st;
+    int bad = 0;
+    if (hnv_status st = read_back(&bad, S.flag, sizeof(int), s); st != HNV_OK)
+        return st;
+    if (nE == 0) {
+        int32_t p0 = 0;
+        if (hnv_status st = read_back(&p0, L.edge_ptr, 4, s); st != HNV_OK)
+            return st;
+        if (p0 != 0 || nnz != 0)
+            bad |= 1;
+    }
+    const std::string lv = "level " + std::to_string(l) + ": ";
+    if (bad & 1)
+        return fail(HNV_EINVAL, lv + "edge_ptr must start at 0, never decrease and end at nnz" +
+                                    (full ? ", and no hyperedge may be empty" : ""));
+    if (bad & 2)
+        return fail(HNV_ERANGE, lv + "a member id is outside [0, n_nodes)");
+    if (bad & 4)
+        return fail(HNV_EUNSORTED, lv + "member lists must be strictly ascending");
+    if (bad & 8)
+        return fail(HNV_EINVAL, lv + "weights must be finite and > 0");
+    if (!C)
+        return HNV_OK;
+    // the map, now that the members are known to be in range
+    k_fill<<<1, kThreads, 0, s>>>(S.flag, 4, 0);
+    if (nV > 0)
+        k_check_node_map<<<grid_for(nV), kThreads, 0, s>>>(m->node_rep, nV, C->n_nodes, S.flag);
+    if (hnv_status st = dev_check("map checks"); st != HNV_OK)
+        return st;
+    if (hnv_status st = read_back(&bad, S.flag, sizeof(int), s); st != HNV_OK)
+        return st;
+    const std::string mp = "map " + std::to_string(l) + ": ";
+    if (bad)
+        return fail(HNV_ERANGE, mp + "node_rep out of range");
+    if (nE > 0)
+        k_check_edge_map<<<grid_for(nE), kThreads, 0, s>>>(L.edge_ptr, L.edge_idx, m->node_rep, m->edge_rep, nV, nE,
+                                                           C->n_edges, full ? 1 : 0, S.flag);
+    if (hnv_status st = dev_check("map checks"); st != HNV_OK)
+        return st;
+    if (hnv_status st = read_back(&bad, S.flag, sizeof(int), s); st != HNV_OK)
+        return st;
+    if (bad & (1 << 5))
+        return fail(HNV_ERANGE, mp + "edge_rep out of range");
+    if (bad & (1 << 6))
+        return fail(HNV_ERANGE, mp + "a removed hyperedge has no members");
+    if (bad & (1 << 7))
+        return fail(HNV_ERANGE, mp + "a removed hyperedge has members in different coarse nodes");
+    return HNV_OK;
+}
+
+// The tier keys, sorts and scans of one side; counts[0..3] on the device.
+hnv_status tier_scan(const int32_t *ptr, int64_t n_rows, int small_max, int chunk, Scratch &S, int64_t *counts,
+                     hipStream_t s)
+{
+    if (n_rows == 0) {
+        k_fill<<<1, kThreads, 0, s>>>(reinterpret_cast<int32_t *>(counts), 8, 0);
+        return dev_check("tier counts");
+    }
+    const int n = (int)n_rows;
+    k_tier_keys<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, small_max, chunk, S.key_a, S.rows_a, S.pieces,
+                                                      S.split, S.slots);
+    size_t tb = S.temp_bytes;
+    if (hipcub::DeviceRadixSort::SortPairs(S.temp, tb, S.key_a, S.key_b, S.rows_a, S.rows_b, n, 0,
+                                           bits_for(small_max + 2), s) != hipSuccess)
+        return fail(HNV_EDEVICE, "sort of the lane-group tier");
+    tb = S.temp_bytes;
+    if (hipcub::DeviceScan::ExclusiveSum(S.temp, tb, S.pieces, S.cpos, n, s) != hipSuccess)
+        return fail(HNV_EDEVICE, "scan of chunk counts");
+    tb = S.temp_bytes;
+    if (hipcub::DeviceScan::ExclusiveSum(S.temp, tb, S.split, S.spos, n, s) != hipSuccess)
+        return fail(HNV_EDEVICE, "scan of split rows");
+    tb = S.temp_bytes;
+    if (hipcub::DeviceScan::ExclusiveSum(S.temp, tb, S.slots, S.sbase, n, s) != hipSuccess)
+        return fail(HNV_EDEVICE, "scan of partial slots");
+    k_tier_counts<<<1, 64, 0, s>>>(S.key_b, S.pieces, S.cpos, S.split, S.spos, S.slots, S.sbase, n_rows, small_max,
+                                   counts);
+    return dev_check("tier keys");
+}
+
+// The work lists of one side, after tier_scan and with the counts known.
+hnv_status tier_emit(const int32_t *ptr, int64_t n_rows, int small_max, int chunk, const int32_t *rowmap,
+                     int32_t row_base, int32_t slot_offset, const int64_t *cnt, Scratch &S, DevSide &D, hipStream_t s)
+{
+    (void)small_max;
+    if (n_rows == 0)
+        return HNV_OK;
+    if (cnt[0] > 0)
+        k_small_items<<<grid_for(cnt[0]), kThreads, 0, s>>>(S.rows_b, ptr, cnt[0], rowmap, row_base,
+                                                            const_cast<Item *>(D.small));
+    if (cnt[1] > 0) {
+        k_chunk_items<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, chunk, S.pieces, S.cpos, S.sbase,
+                                                            slot_offset, S.items, S.key_a, S.ids_a);
+        size_t tb = S.temp_bytes;
+        if (hipcub::DeviceRadixSort::SortPairs(S.temp, tb, S.key_a, S.key_b, S.ids_a, S.ids_b, (int)cnt[1], 0,
+                                               bits_for(chunk + 1), s) != hipSuccess)
+            return fail(HNV_EDEVICE, "sort of the wavefront tier");
+        k_gather_items<<<grid_for(cnt[1]), kThreads, 0, s>>>(S.items, S.ids_b, cnt[1],
+                                                             const_cast<Item *>(D.chunks));
+    }
+    if (cnt[2] > 0)
+        k_split_items<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, S.pieces, S.spos, S.sbase, slot_offset,
+                                                            const_cast<Split *>(D.splits));
+    return dev_check("work lists");
+}
+
+hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *maps, int n_levels, int l,
+                       bool full, Scratch &S, hipStream_t s)
+{
+    const hnv_level_dev &lv = levels[l];
+    const hnv_level_dev *C = (l + 1 < n_levels) ? &levels[l + 1] : nullptr;
+    const hnv_map *m = C ? &maps[l] : nullptr;
+    if (hnv_status st = check_level(lv, C, m, l, full, S, s); st != HNV_OK)
+        return st;
+    LevelPlan &L = p->lv[l];
+    const int64_t nV = lv.n_nodes, nE = lv.n_edges, nnz = lv.nnz;
+    const int sm = p->small_max, chunk = p->opts.chunk;
+    DevSide &S0 = L.side[0], &S1 = L.side[1];
+    hnv_status st;
+    // side 0: the member lists as given
+    if ((st = copy_d2d((void *)S0.ptr, lv.edge_ptr, 4 * (nE + 1), s)) != HNV_OK ||
+        (st = copy_d2d((void *)S0.idx, lv.edge_idx, 4 * nnz, s)) != HNV_OK)
+        return st;
+    // side 1: node -> hyperedges in ascending id (stable sort of incidences by node)
+    k_fill<<<grid_for(nV + 1), kThreads, 0, s>>>(S.deg, nV + 1, 0);
+    if (nnz > 0)
+        k_degrees<<<grid_for(nnz), kThreads, 0, s>>>(lv.edge_idx, nnz, S.deg);
+    size_t tb = S.temp_bytes;
+    if (hipcub::DeviceScan::ExclusiveSum(S.temp, tb, S.deg, const_cast<int32_t *>(S1.ptr), (int)(nV + 1), s) !=
+        hipSuccess)
+        return fail(HNV_EDEVICE, "scan of node degrees");
+    if (nnz > 0) {
+        tb = S.temp_bytes;
+        if (hipcub::DeviceRadixSort::SortPairs(S.temp, tb, reinterpret_cast<const uint32_t *>(lv.edge_idx),
+                                               reinterpret_cast<uint32_t *>(S.keys_out), S.inc_edge, S.csc_e,
+                                               (int)nnz, 0, bits_for(nV), s) != hipSuccess)
+            return fail(HNV_EDEVICE, "sort of incidences by node");
+        k_add_const<<<grid_for(nnz), kThreads, 0, s>>>(S.csc_e, nnz, (int32_t)nV, const_cast<int32_t *>(S1.idx));
+    }
+    // projection row map, composed indices, inverse map
+    if (C) {
+        k_rowmap<<<grid_for(nV + nE), kThreads, 0, s>>>(lv.edge_ptr, lv.edge_idx, m->node_rep, m->edge_rep, nV, nE,
+                                                        C->n_nodes, L.rowmap);
+        if (nnz > 0) {
+            k_compose<<<grid_for(nnz), kThreads, 0, s>>>(S0.idx, L.rowmap, nnz, const_cast<int32_t *>(S0.cidx));
+            k_compose<<<grid_for(nnz), kThreads, 0, s>>>(S1.idx, L.rowmap, nnz, const_cast<int32_t *>(S1.cidx));
+        }
+        const int64_t rows = nV + nE, rows_c = L.rows_coarse;
+        k_fill<<<grid_for(rows_c + 1), kThreads, 0, s>>>(S.deg, rows_c + 1, 0);
+        if (rows > 0) {
+            k_degrees<<<grid_for(rows), kThreads, 0, s>>>(L.rowmap, rows, S.deg);
+            k_iota<<<grid_for(rows), kThreads, 0, s>>>(rows, S.rows_a);
+        }
+        tb = S.temp_bytes;
+        if (hipcub::DeviceScan::ExclusiveSum(S.temp, tb, S.deg, L.inv_ptr, (int)(rows_c + 1), s) != hipSuccess)
+            return fail(HNV_EDEVICE, "scan of the inverse map");
+        if (rows > 0) {
+            tb = S.temp_bytes;
+            if (hipcub::DeviceRadixSort::SortPairs(S.temp, tb, reinterpret_cast<const uint32_t *>(L.rowmap),
+                                                   reinterpret_cast<uint32_t *>(S.keys_out), S.rows_a, L.inv_idx,
+                                                   (int)rows, 0, bits_for(rows_c), s) != hipSuccess)
+                return fail(HNV_EDEVICE, "sort of the inverse map");
+        }
+    }
+    if ((st = dev_check("plan arrays")) != HNV_OK)
+        return st;
+    // degree tiers: side 0 then side 1 (partial slots continue across sides)
+    int64_t cnt[2][4];
+    for (int sd = 0; sd < 2; ++sd) {
+        const int64_t n_rows = sd == 0 ? nE : nV;
+        if ((st = tier_scan(sd == 0 ? S0.ptr : S1.ptr, n_rows, sm, chunk, S, S.counts + 4 * sd, s)) != HNV_OK)
+            return st;
+        // keep this side's sorted rows and scans: read the counts, then emit
+        if ((st = read_back(cnt[sd], S.counts + 4 * sd, 4 * sizeof(int64_t), s)) != HNV_OK)
+            return st;
+        const int32_t slot_offset = sd == 0 ? 0 : (int32_t)cnt[0][3];
+        DevSide &D = L.side[sd];
+        if (cnt[sd][0] > D.n_small || cnt[sd][1] > D.n_chunks || cnt[sd][2] > D.n_splits)
+            return fail(HNV_EDEVICE, "work lists exceed their bounds");
+        if ((st = tier_emit(D.ptr, n_rows, sm, chunk, C ? L.rowmap : nullptr, D.row_base, slot_offset, cnt[sd], S, D,
+                            s)) != HNV_OK)
+            return st;
+        D.n_small = (int32_t)cnt[sd][0];
+        D.n_chunks = (int32_t)cnt[sd][1];
+        D.n_splits = (int32_t)cnt[sd][2];
+        L.n_small[sd] = D.n_small;
+        L.n_chunks[sd] = D.n_chunks;
+        L.n_splits[sd] = D.n_splits;
+    }
+    L.n_slots = (int32_t)(cnt[0][3] + cnt[1][3]);
+    if (L.n_slots > p->max_slots)
+        return fail(HNV_EDEVICE, "partial slots exceed their bound");
+    // weights and reciprocals
+    if (lv.edge_w) {
+        if ((st = copy_d2d(L.w, lv.edge_w, 4 * nE, s)) != HNV_OK)
+            return st;
+    } else if (nE > 0) {
+        k_fill_f32<<<grid_for(nE), kThreads, 0, s>>>(L.w, nE, 1.0f);
+    }
+    if ((st = dev_check("weights")) != HNV_OK)
+        return st;
+    return dev_recompute_reciprocals(p, l, s);
+}
+
+}  // namespace
+}  // namespace hnv
+
+using namespace hnv;
+
+extern "C" hnv_status hnv_plan_workspace_bytes_device(const hnv_level_dev *levels, const hnv_map *maps,
+                                                      int n_levels, int d, hnv_dtype dtype,
+                                                      const hnv_options *opts, size_t *bytes)
+{
+    clear_error();
+    if (!bytes)
+        return fail(HNV_EINVAL, "bytes is NULL");
+    hnv_options o;
+    resolve_options(opts, d, dtype, &o);
+    hnv_status st = check_plan_options(d, dtype, o);
+    if (st == HNV_OK)
+        st = check_levels(levels, maps, n_levels);
+    if (st != HNV_OK)
+        return st;
+    try {
+        hnv_plan p;
+        std::vector<LevelShape> bounds;
+        size_t scratch = 0, total = 0;
+        bool in_zbuf = false;
+        if ((st = device_layout(levels, n_levels, d, dtype, o, &p, bounds, scratch, in_zbuf, total)) != HNV_OK)
+            return st;
+        *bytes = total;
+        return HNV_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(HNV_ENOMEM, "host allocation failed in hnv_plan_workspace_bytes_device");
+    }
+}
+
+extern "C" hnv_status hnv_plan_create_device(const hnv_level_dev *levels, const hnv_map *maps, int n_levels, int d,
+                                             hnv_dtype dtype, const hnv_options *opts, int validate_inputs,
+                                             void *workspace, size_t ws_bytes, void *stream, hnv_plan **out)
+{
+    clear_error();
+    if (!out)
+        return fail(HNV_EINVAL, "out is NULL");
+    *out = nullptr;
+    hnv_options o;
+    resolve_options(opts, d, dtype, &o);
+    hnv_status st = check_plan_options(d, dtype, o);
+    if (st == HNV_OK)
+        st = check_levels(levels, maps, n_levels);
+    if (st != HNV_OK)
+        return st;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(HNV_EWORKSPACE, "workspace must be non-NULL and 256-byte aligned");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hnv_plan *p = nullptr;
+    try {
+        p = new hnv_plan;
+        std::vector<LevelShape> bounds;
+        size_t scratch_bytes = 0, total = 0;
+        bool in_zbuf = false;
+        if ((st = device_layout(levels, n_levels, d, dtype, o, p, bounds, scratch_bytes, in_zbuf, total)) != HNV_OK) {
+            delete p;
+            return st;
+        }
+        if (total > ws_bytes) {
+            delete p;
+            return fail(HNV_EWORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " +
+                                            std::to_string(total));
+        }
+        char *base = static_cast<char *>(workspace);
+        carve(p, bounds, base);
+        char *scratch_base = in_zbuf ? static_cast<char *>(p->zbuf) : base + p->ws_bytes;
+        for (int l = 0; l < n_levels && st == HNV_OK; ++l) {
+            Scratch S{};
+            const int32_t nch = std::max(bounds[l].n_chunks[0], bounds[l].n_chunks[1]);
+            st = scratch_layout(bounds[l].nnz, bounds[l].rows, nch, scratch_base, S);
+            if (st == HNV_OK)
+                st = build_level(p, levels, maps, n_levels, l, validate_inputs != 0, S, s);
+        }
+        if (st == HNV_OK) {
+            p->ws_bytes = total;
+            hipError_t e = hipStreamSynchronize(s);
+            if (e != hipSuccess)
+                st = fail(HNV_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+        }
+        if (st != HNV_OK) {
+            delete p;
+            return st;
+        }
+    } catch (const std::bad_alloc &) {
+        delete p;
+        return fail(HNV_ENOMEM, "host allocation failed in hnv_plan_create_device");
+    }
+    *out = p;
+    return HNV_OK;
+}

@@ -336,7 +336,7 @@ struct HostLevel {
     std::vector<int32_t> rowmap, inv_ptr, inv_idx;
 };
 
-static void resolve_options(const hnv_options *in, int d, hnv_dtype dtype, hnv_options *out)
+void resolve_options(const hnv_options *in, int d, hnv_dtype dtype, hnv_options *out)
 {
     hnv_options o{};
     if (in)
@@ -353,13 +353,8 @@ static void resolve_options(const hnv_options *in, int d, hnv_dtype dtype, hnv_o
     *out = o;
 }
 
-static hnv_status check_shape(const hnv_level *levels, const hnv_map *maps, int n_levels, int d,
-                              hnv_dtype dtype, const hnv_options &o)
+hnv_status check_plan_options(int d, hnv_dtype dtype, const hnv_options &o)
 {
-    if (!levels || n_levels < 1)
-        return fail(HNV_EINVAL, "need at least one level");
-    if (n_levels > 1 && !maps)
-        return fail(HNV_EINVAL, "maps is NULL with more than one level");
     if (d < 8 || d > 512 || d % 8 != 0)
         return fail(HNV_EUNSUPPORTED, "d must be a multiple of 8 in [8, 512]");
     if (dtype != HNV_F32 && dtype != HNV_BF16)
@@ -370,6 +365,18 @@ static hnv_status check_shape(const hnv_level *levels, const hnv_map *maps, int 
         return fail(HNV_EUNSUPPORTED, "small_max <= 4096 and chunk <= 2^20");
     if (o.order != HNV_ORDER_JACOBI && o.order != HNV_ORDER_EDGE_FIRST)
         return fail(HNV_EINVAL, "unknown sweep order");
+    return HNV_OK;
+}
+
+static hnv_status check_shape(const hnv_level *levels, const hnv_map *maps, int n_levels, int d,
+                              hnv_dtype dtype, const hnv_options &o)
+{
+    if (!levels || n_levels < 1)
+        return fail(HNV_EINVAL, "need at least one level");
+    if (n_levels > 1 && !maps)
+        return fail(HNV_EINVAL, "maps is NULL with more than one level");
+    if (hnv_status st = check_plan_options(d, dtype, o); st != HNV_OK)
+        return st;
     for (int l = 0; l < n_levels; ++l) {
         const hnv_level &L = levels[l];
         if (L.n_nodes < 0 || L.n_edges < 0 || L.nnz < 0 || !L.edge_ptr || (L.nnz > 0 && !L.edge_idx))
@@ -508,9 +515,28 @@ void forward_geometry(const hnv_plan *p, const LevelPlan &L, int64_t *main_block
     *fin_blocks = fin * p->panels;
 }
 
+static LevelShape shape_of(const HostLevel &h, bool unit_w)
+{
+    LevelShape sh;
+    sh.nV = h.nV;
+    sh.nE = h.nE;
+    sh.nnz = h.nnz;
+    sh.rows = h.rows;
+    sh.rows_c = h.rows_c;
+    sh.has_coarse = h.has_coarse;
+    sh.unit_w = unit_w;
+    for (int s = 0; s < 2; ++s) {
+        sh.n_small[s] = (int32_t)h.tier[s].small.size();
+        sh.n_chunks[s] = (int32_t)h.tier[s].chunks.size();
+        sh.n_splits[s] = (int32_t)h.tier[s].splits.size();
+    }
+    sh.n_slots = h.n_slots;
+    return sh;
+}
+
 // Lays out the workspace (base == nullptr: sizing only) and fills the
-// plan's device pointers.
-static void carve(hnv_plan *p, std::vector<HostLevel> &hl, char *base)
+// plan's device pointers and work-list counts.
+void carve(hnv_plan *p, const std::vector<LevelShape> &shape, char *base)
 {
     Carver c{base};
     const size_t elem = (p->dtype == HNV_BF16) ? 2 : 4;
@@ -518,7 +544,7 @@ static void carve(hnv_plan *p, std::vector<HostLevel> &hl, char *base)
     p->max_slots = 1;
     p->max_resid_blocks = 1;
     for (int l = 0; l < p->n_levels; ++l) {
-        HostLevel &h = hl[l];
+        const LevelShape &h = shape[l];
         LevelPlan &L = p->lv[l];
         for (int s = 0; s < 2; ++s) {
             DevSide &S = L.side[s];
@@ -529,9 +555,9 @@ static void carve(hnv_plan *p, std::vector<HostLevel> &hl, char *base)
             S.cidx = h.has_coarse ? c.take<int32_t>(h.nnz) : nullptr;
             S.wn = (s == 1) ? c.take<float>(h.nnz) : nullptr;
             S.sn = c.take<float>(h.nnz);
-            S.n_small = (int32_t)h.tier[s].small.size();
-            S.n_chunks = (int32_t)h.tier[s].chunks.size();
-            S.n_splits = (int32_t)h.tier[s].splits.size();
+            S.n_small = h.n_small[s];
+            S.n_chunks = h.n_chunks[s];
+            S.n_splits = h.n_splits[s];
             S.small = c.take<Item>(S.n_small);
             S.chunks = c.take<Item>(S.n_chunks);
             S.splits = c.take<Split>(S.n_splits);
@@ -563,9 +589,10 @@ static void carve(hnv_plan *p, std::vector<HostLevel> &hl, char *base)
     p->ws_bytes = (c.off + 255) & ~size_t(255);
 }
 
-static void init_plan_shape(hnv_plan *p, const hnv_level *levels, int n_levels, int d, hnv_dtype dtype,
-                            const hnv_options &o)
+void init_plan_shape(hnv_plan *p, const std::vector<LevelShape> &shape, int d, hnv_dtype dtype,
+                     const hnv_options &o)
 {
+    const int n_levels = (int)shape.size();
     p->n_levels = n_levels;
     p->d = d;
     p->dtype = dtype;
@@ -580,14 +607,30 @@ static void init_plan_shape(hnv_plan *p, const hnv_level *levels, int n_levels, 
     p->lv.assign(n_levels, LevelPlan{});
     for (int l = 0; l < n_levels; ++l) {
         LevelPlan &L = p->lv[l];
-        L.n_nodes = levels[l].n_nodes;
-        L.n_edges = levels[l].n_edges;
-        L.nnz = levels[l].nnz;
+        L.n_nodes = shape[l].nV;
+        L.n_edges = shape[l].nE;
+        L.nnz = shape[l].nnz;
         L.rows = L.n_nodes + L.n_edges;
         L.has_coarse = (l + 1 < n_levels);
-        L.rows_coarse = L.has_coarse ? levels[l + 1].n_nodes + levels[l + 1].n_edges : 0;
-        L.unit_w = (levels[l].edge_w == nullptr);
+        L.rows_coarse = L.has_coarse ? shape[l + 1].nV + shape[l + 1].nE : 0;
+        L.unit_w = shape[l].unit_w;
     }
+}
+
+// Sizes of host levels (work-list counts unknown yet).
+static std::vector<LevelShape> sizes_of(const hnv_level *levels, int n_levels)
+{
+    std::vector<LevelShape> sh(n_levels);
+    for (int l = 0; l < n_levels; ++l) {
+        sh[l].nV = levels[l].n_nodes;
+        sh[l].nE = levels[l].n_edges;
+        sh[l].nnz = levels[l].nnz;
+        sh[l].rows = sh[l].nV + sh[l].nE;
+        sh[l].has_coarse = (l + 1 < n_levels);
+        sh[l].rows_c = sh[l].has_coarse ? levels[l + 1].n_nodes + levels[l + 1].n_edges : 0;
+        sh[l].unit_w = (levels[l].edge_w == nullptr);
+    }
+    return sh;
 }
 
 }  // namespace hnv
@@ -639,11 +682,14 @@ extern "C" hnv_status hnv_plan_workspace_bytes(const hnv_level *levels, const hn
         return st;
     try {
         hnv_plan p;
-        init_plan_shape(&p, levels, n_levels, d, dtype, o);
-        std::vector<HostLevel> hl(n_levels);
-        for (int l = 0; l < n_levels; ++l)
-            build_level(levels, maps, n_levels, l, o, p.small_max, false, hl[l]);
-        carve(&p, hl, nullptr);
+        std::vector<LevelShape> sh = sizes_of(levels, n_levels);
+        init_plan_shape(&p, sh, d, dtype, o);
+        for (int l = 0; l < n_levels; ++l) {
+            HostLevel h;
+            build_level(levels, maps, n_levels, l, o, p.small_max, false, h);
+            sh[l] = shape_of(h, sh[l].unit_w);
+        }
+        carve(&p, sh, nullptr);
         *bytes = p.ws_bytes;
         return HNV_OK;
     } catch (const std::bad_alloc &) {
@@ -692,20 +738,23 @@ extern "C" hnv_status hnv_plan_create(const hnv_level *levels, const hnv_map *ma
     hnv_plan *p = nullptr;
     try {
         p = new hnv_plan;
-        init_plan_shape(p, levels, n_levels, d, dtype, o);
+        std::vector<LevelShape> sh = sizes_of(levels, n_levels);
+        init_plan_shape(p, sh, d, dtype, o);
         // sizing pass (work-list counts only), then carve for real
         {
-            std::vector<HostLevel> hl(n_levels);
-            for (int l = 0; l < n_levels; ++l)
-                build_level(levels, maps, n_levels, l, o, p->small_max, false, hl[l]);
-            carve(p, hl, nullptr);
+            for (int l = 0; l < n_levels; ++l) {
+                HostLevel h;
+                build_level(levels, maps, n_levels, l, o, p->small_max, false, h);
+                sh[l] = shape_of(h, sh[l].unit_w);
+            }
+            carve(p, sh, nullptr);
             if (p->ws_bytes > ws_bytes) {
                 const size_t need = p->ws_bytes;
                 delete p;
                 return fail(HNV_EWORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " +
                                                 std::to_string(need));
             }
-            carve(p, hl, reinterpret_cast<char *>(workspace));
+            carve(p, sh, reinterpret_cast<char *>(workspace));
         }
         // one level at a time: build host arrays, upload, wait, free
         for (int l = 0; l < n_levels; ++l) {

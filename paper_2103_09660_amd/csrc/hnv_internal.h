@@ -120,6 +120,23 @@ void lane_layout(int cols, int elem, int *lanes, int *elems_per_lane);
 constexpr int kIdxRegs = 4;          // neighbour indices a lane preloads in the lane-group tier
 int64_t blocks_for(int64_t items, int64_t per_block);
 
+// Sizes and work-list counts of one level of a plan.
+struct LevelShape {
+    int64_t nV = 0, nE = 0, nnz = 0, rows = 0, rows_c = 0;
+    bool has_coarse = false, unit_w = true;
+    int32_t n_small[2] = {0, 0}, n_chunks[2] = {0, 0}, n_splits[2] = {0, 0};
+    int32_t n_slots = 0;
+};
+
+// Plan set-up shared by the host-built and the device-built plan
+// (hnv_host.cpp): option defaults and limits, the plan's shape, and the
+// workspace layout (base == nullptr: sizing only; sets p->ws_bytes).
+void resolve_options(const hnv_options *in, int d, hnv_dtype dtype, hnv_options *out);
+hnv_status check_plan_options(int d, hnv_dtype dtype, const hnv_options &o);
+void init_plan_shape(hnv_plan *p, const std::vector<LevelShape> &shape, int d, hnv_dtype dtype,
+                     const hnv_options &o);
+void carve(hnv_plan *p, const std::vector<LevelShape> &shape, char *base);
+
 // Forward-sweep launch geometry of a level (blocks per panel and finalize blocks).
 void forward_geometry(const hnv_plan *p, const LevelPlan &L, int64_t *main_blocks, int64_t *fin_blocks);
 

@@ -1,0 +1,173 @@
+"""A plan built on the GPU from device-resident levels against the plan built
+on the host from the same levels: every result must be bit-identical
+(same adjacency, same work lists in the same order, same reciprocals), and
+the device-resident pipeline (GPU coarsening, GPU plan, refinement) must
+match the FP64 oracle."""
+import numpy as np
+import pytest
+
+from tests.cases import CONFIGS, coarsest_embedding, make_hypergraph, random_hypergraph, rel_fro, tier_hypergraph
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2103_09660_amd as H
+    return H
+
+
+def _device_copy(H, hier):
+    levels = [H.DeviceLevel.from_host(lv, "cuda") for lv in hier.levels]
+    import torch
+    maps = [(torch.as_tensor(m.node_rep).cuda(), torch.as_tensor(m.edge_rep).cuda()) for m in hier.maps]
+    return levels, maps
+
+
+def _both_plans(H, hier, d, dtype, options=None):
+    levels, maps = _device_copy(H, hier)
+    host = H.Plan(hier, d, dtype, options=options)
+    dev = H.Plan.from_device(levels, maps, d, dtype, options=options)
+    return host, dev
+
+
+def _assert_same_refine(host, dev, hier, d, sweeps, seed):
+    import torch
+    zc = torch.as_tensor(coarsest_embedding(seed, hier.levels[-1].rows, d)).cuda().to(host.torch_dtype)
+    a, ra, na = host.refine(zc, sweeps, 0.5, residuals=True)
+    b, rb, nb = dev.refine(zc, sweeps, 0.5, residuals=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a.view(torch.int16) if a.dtype == torch.bfloat16 else a.view(torch.int32),
+                       b.view(torch.int16) if b.dtype == torch.bfloat16 else b.view(torch.int32))
+    assert torch.equal(ra, rb) and np.array_equal(na, nb)
+    for l in range(hier.n_levels):
+        assert host.level_info(l) == dev.level_info(l)
+
+
+@pytest.mark.parametrize("small_max,chunk", [(0, 0), (8, 16), (16, 64), (3, 5)])
+@pytest.mark.parametrize("dtype,d,order", [("f32", 32, "jacobi"), ("bf16", 64, "jacobi"), ("f32", 128, "edge_first"),
+                                           ("bf16", 16, "edge_first")])
+def test_tiers_bit_identical(H, small_max, chunk, dtype, d, order):
+    """Every tier on both sides, split rows on both sides, both orders."""
+    sm, ch = (small_max or 64), (chunk or 512)
+    hg = tier_hypergraph(7, sm, ch)
+    hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, 2)
+    opts = {"small_max": small_max, "chunk": chunk, "order": order}
+    host, dev = _both_plans(H, hier, d, dtype, opts)
+    _assert_same_refine(host, dev, hier, d, [3, 2, 2], 11)
+
+
+@pytest.mark.parametrize("seed,n_nodes,n_edges,hi,weighted", [
+    (0, 40, 20, 4, True), (1, 3000, 2000, 12, False), (2, 700, 900, 40, True), (3, 1, 1, 1, False)])
+def test_random_bit_identical(H, seed, n_nodes, n_edges, hi, weighted):
+    hg = random_hypergraph(seed, n_nodes, n_edges, 1, hi, weighted=weighted)
+    hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, 3)
+    host, dev = _both_plans(H, hier, 24, "f32")
+    _assert_same_refine(host, dev, hier, 24, [2, 2, 2, 2], seed)
+
+
+def test_reverse_bit_identical(H):
+    """Adjoint sweep, weight gradient and projection adjoint through both plans."""
+    import torch
+    cfg = CONFIGS["hub-200k"]
+    hg = make_hypergraph(cfg)
+    hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, 1)
+    host, dev = _both_plans(H, hier, 32, "f32")
+    rng = np.random.default_rng(3)
+    y = torch.as_tensor(rng.standard_normal((hier.levels[0].rows, 32)).astype(np.float32)).cuda()
+    g = torch.as_tensor(rng.standard_normal((hier.levels[0].rows, 32)).astype(np.float32)).cuda()
+    outs = []
+    for p in (host, dev):
+        z = p.sweep(0, y, 0.5)
+        dw = torch.zeros(hier.levels[0].n_edges, dtype=torch.float32, device="cuda")
+        gy = p.sweep_adjoint(0, g, y, z, 0.5, dw=dw)
+        gc = p.project_adjoint(0, gy)
+        outs.append((z, gy, dw, gc))
+    torch.cuda.synchronize()
+    for a, b in zip(*outs):
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
+@pytest.mark.parametrize("name", ["hub-200k", "zipf-2m"])
+def test_device_pipeline_bit_identical(H, name):
+    """GPU coarsening -> GPU plan -> refinement equals host coarsening ->
+    host plan -> refinement, bit for bit, at full size."""
+    import torch
+    cfg = CONFIGS[name]
+    hg = make_hypergraph(cfg)
+    hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, cfg.levels)
+    lv0 = H.DeviceLevel.from_host(hier.levels[0], "cuda")
+    dl, dm = H.coarsen_hierarchy_device(lv0, cfg.levels)
+    dtype = cfg.dtypes[0]
+    host = H.Plan(hier, cfg.d, dtype)
+    dev = H.Plan.from_device(dl, dm, cfg.d, dtype)
+    _assert_same_refine(host, dev, hier, cfg.d, list(cfg.sweeps), cfg.seed)
+    del host, dev
+    torch.cuda.empty_cache()
+
+
+def test_device_pipeline_vs_oracle(oracle_mod, H):
+    import torch
+    O = oracle_mod
+    cfg = CONFIGS["tiny-2k"]
+    hg = make_hypergraph(cfg)
+    levels, maps = O.build_hierarchy(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, cfg.levels)
+    lv0 = H.DeviceLevel.from_host(H.HostLevel(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w), "cuda")
+    dl, dm = H.coarsen_hierarchy_device(lv0, cfg.levels)
+    plan = H.Plan.from_device(dl, dm, cfg.d, "f32")
+    zc = coarsest_embedding(cfg, levels[-1].rows, cfg.d)
+    out, _, _ = plan.refine(torch.as_tensor(zc).cuda(), list(cfg.sweeps), 0.5)
+    ref = O.refine(levels, maps, zc, list(cfg.sweeps), 0.5)
+    assert rel_fro(out.cpu().numpy(), ref) <= 1e-5
+
+
+def test_device_plan_checks(H):
+    """The device-side checks report the host statuses."""
+    import torch
+    from paper_2103_09660_amd import _lib as L
+    hg = random_hypergraph(4, 200, 120, 1, 6)
+    hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, 1)
+    levels, maps = _device_copy(H, hier)
+    # node map out of range
+    bad = maps[0][0].clone()
+    bad[5] = hier.levels[1].n_nodes
+    with pytest.raises(H.HnvError) as ei:
+        H.Plan.from_device(levels, [(bad, maps[0][1])], 16, "f32")
+    assert ei.value.status == L.HNV_ERANGE
+    # hyperedge map out of range
+    bad = maps[0][1].clone()
+    bad[0] = hier.levels[1].n_edges
+    with pytest.raises(H.HnvError) as ei:
+        H.Plan.from_device(levels, [(maps[0][0], bad)], 16, "f32")
+    assert ei.value.status == L.HNV_ERANGE
+    # unsorted members: rejected with validation, accepted without (as on the host)
+    idx = levels[0].edge_idx.clone()
+    e = int(np.nonzero(np.diff(hg.edge_ptr) >= 2)[0][0])
+    a = int(hg.edge_ptr[e])
+    idx[a], idx[a + 1] = int(idx[a + 1]), int(idx[a])
+    lv = H.DeviceLevel(levels[0].n_nodes, levels[0].n_edges, levels[0].nnz, levels[0].edge_ptr, idx,
+                       levels[0].edge_w)
+    with pytest.raises(H.HnvError) as ei:
+        H.Plan.from_device([lv], [], 16, "f32")
+    assert ei.value.status == L.HNV_EUNSORTED
+    H.Plan.from_device([lv], [], 16, "f32", validate=False)
+    # member out of range: always rejected
+    idx = levels[0].edge_idx.clone()
+    idx[3] = levels[0].n_nodes
+    lv = H.DeviceLevel(levels[0].n_nodes, levels[0].n_edges, levels[0].nnz, levels[0].edge_ptr, idx,
+                       levels[0].edge_w)
+    with pytest.raises(H.HnvError) as ei:
+        H.Plan.from_device([lv], [], 16, "f32", validate=False)
+    assert ei.value.status == L.HNV_ERANGE
+    # non-positive weight: rejected with validation
+    w = levels[0].edge_w.clone()
+    w[2] = 0.0
+    lv = H.DeviceLevel(levels[0].n_nodes, levels[0].n_edges, levels[0].nnz, levels[0].edge_ptr,
+                       levels[0].edge_idx, w)
+    with pytest.raises(H.HnvError) as ei:
+        H.Plan.from_device([lv], [], 16, "f32")
+    assert ei.value.status == L.HNV_EINVAL
+    torch.cuda.synchronize()
