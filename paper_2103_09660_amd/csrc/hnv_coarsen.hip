@@ -69,8 +69,14 @@ __global__ __launch_bounds__(kThreads) void k_best(const int32_t *__restrict__ i
                                                    int32_t *__restrict__ best)
 {
     const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (j < nnz)
-        atomicMin(best + idx[j], rank[inc_edge[j]]);
+    if (j >= nnz)
+        return;
+    // The minimum only decreases, so any value read earlier (even a stale
+    // cached one) bounds the final one from above: a rank not below it
+    // cannot win and needs no atomic.
+    const int32_t v = idx[j], r = rank[inc_edge[j]];
+    if (r < best[v])
+        atomicMin(best + v, r);
 }
 
 // choice, then per hyperedge: smallest node that chose it, and how many did
@@ -462,7 +468,9 @@ __global__ __launch_bounds__(kThreads) void k_qscore(const int32_t *__restrict__
     if (lane < n) {
         const double sc = cosine_score(mine, my_s2);
         q[j0 + lane] = sc;
-        atomicMax(bestq + my_v, ordered_bits(sc));
+        const unsigned long long ob = ordered_bits(sc);
+        if (ob > bestq[my_v])   // an earlier read bounds the maximum from below
+            atomicMax(bestq + my_v, ob);
     }
 }
 
@@ -499,8 +507,11 @@ __global__ __launch_bounds__(kThreads) void k_best_feat(const int32_t *__restric
     if (j >= nnz)
         return;
     const int32_t v = idx[j];
-    if (ordered_bits(q[j]) == bestq[v])
-        atomicMin(best + v, rank[inc_edge[j]]);
+    if (ordered_bits(q[j]) == bestq[v]) {
+        const int32_t r = rank[inc_edge[j]];
+        if (r < best[v])   // an earlier read bounds the minimum from above
+            atomicMin(best + v, r);
+    }
 }
 
 // coarse-node member lists: count, then place (the order inside a group is
