@@ -385,20 +385,41 @@ def cpu_baseline(O, hg, cfg, budget_s=12.0, max_sweeps=20, d=None):
                       f"{lv.nnz} incidences) at d={d}, FP64, {t:.1f} s"}
 
 
-def oracle_errors(O, hg, cfg, zc, outs, cols=(0, 77)):
-    """Errors of the GPU results against the FP64 oracle on a column sample
-    (columns are independent under projection and sweeps)."""
+def oracle_errors(O, hg, cfg, zc, outs, cols=(0, 77), node_frac=0.01, node_cols=16):
+    """Errors of the GPU results against the FP64 oracle: on a column sample
+    over all rows (columns are independent under projection and sweeps, so
+    each is an exact sub-computation), and on a seeded 1% node sample of an
+    oracle refinement of node_cols evenly spaced columns."""
     import numpy as np
     levels, maps = O.build_hierarchy(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, cfg.levels)
+
+    def stats(got, ref):
+        return {"rel_fro": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                "max_abs": float(np.max(np.abs(got - ref))),
+                "max_abs_rel": float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))}
+
     ref = O.refine(levels, maps, np.ascontiguousarray(zc[:, list(cols)], dtype=np.float64), list(cfg.sweeps), 0.5)
     errs = {}
     for name, out in outs.items():
         got = out[:, list(cols)].float().cpu().numpy().astype(np.float64)
-        errs[name] = {"rel_fro": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
-                      "max_abs": float(np.max(np.abs(got - ref))),
-                      "max_abs_rel": float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))),
-                      "columns": list(cols)}
+        errs[name] = {"columns": list(cols), "all_rows": stats(got, ref)}
+    if node_frac > 0:
+        t = time.perf_counter()
+        ccols = list(range(0, cfg.d, max(1, cfg.d // node_cols)))
+        full = O.refine(levels, maps, np.ascontiguousarray(zc[:, ccols], dtype=np.float64), list(cfg.sweeps), 0.5)
+        rng = np.random.default_rng(500 + cfg.seed)
+        nodes = np.sort(rng.choice(hg.n_nodes, size=max(1, int(node_frac * hg.n_nodes)), replace=False))
+        for name, out in outs.items():
+            got = out[torch_index(nodes, out)][:, ccols].float().cpu().numpy().astype(np.float64)
+            errs[name]["node_sample"] = dict(stats(got, full[nodes]), nodes=int(len(nodes)), columns=ccols,
+                                             seed=500 + cfg.seed)
+        errs["oracle_node_sample_refine_s"] = time.perf_counter() - t
     return errs
+
+
+def torch_index(rows, like):
+    import torch
+    return torch.as_tensor(rows, dtype=torch.int64, device=like.device)
 
 
 def main():
