@@ -422,6 +422,22 @@ def torch_index(rows, like):
     return torch.as_tensor(rows, dtype=torch.int64, device=like.device)
 
 
+def cpu_baseline_leg(hg, cfg, zc, outs, timing=True, errors=True, d=None):
+    """The only part of the benchmark that touches the FP64 oracle: it times
+    the oracle on a bounded sample of the workload (``cpu_baseline``) and
+    reports the GPU results' errors against it (``error_vs_fp64_oracle``)."""
+    from oracle import oracle as O
+    out = {}
+    if errors:
+        t = time.perf_counter()
+        out["error_vs_fp64_oracle"] = oracle_errors(O, hg, cfg, zc, outs)
+        log(f"oracle check ({time.perf_counter() - t:.1f} s): {out['error_vs_fp64_oracle']}")
+    if timing:
+        out["cpu_baseline"] = cpu_baseline(O, hg, cfg, d=d)
+        log(f"cpu baseline: {out['cpu_baseline']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -575,16 +591,9 @@ def main():
         line["differentiable"] = run_differentiable(H, torch, max(2, args.steps // 2), 1)
         log(f"differentiable ({time.perf_counter() - t:.1f} s): {line['differentiable']}")
 
-    need_oracle = not (args.no_cpu_baseline and args.no_oracle_check)
-    if need_oracle:
-        from oracle import oracle as O
-        if not args.no_oracle_check and not large:
-            t = time.perf_counter()
-            line["error_vs_fp64_oracle"] = oracle_errors(O, hg, cfg, zc, outs)
-            log(f"oracle check ({time.perf_counter() - t:.1f} s): {line['error_vs_fp64_oracle']}")
-        if not args.no_cpu_baseline:
-            line["cpu_baseline"] = cpu_baseline(O, hg, cfg, d=16 if large else None)
-            log(f"cpu baseline: {line['cpu_baseline']}")
+    if not (args.no_cpu_baseline and args.no_oracle_check):
+        line.update(cpu_baseline_leg(hg, cfg, zc, outs, timing=not args.no_cpu_baseline,
+                                     errors=not args.no_oracle_check and not large, d=16 if large else None))
     print(json.dumps(line), flush=True)
 
 

@@ -4,7 +4,8 @@
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
  * GPU library is checked against.  Only the test suite, the smoke check and
- * the CPU-baseline leg of the benchmark may load it; the product path never
+ * the CPU-baseline leg of the benchmark (which also reports the GPU
+ * results' errors against it) may load it; the product path never
  * does.  It shares no code, header or table with the GPU library.
  *
  * Conventions

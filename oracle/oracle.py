@@ -2,7 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY.  The oracle is the plain, slow reference the GPU
 library is checked against.  Only ``tests/``, ``__graft_entry__.smoke()`` and
-the CPU-baseline leg of ``bench.py`` may import it; the product package never
+the CPU-baseline leg of ``bench.py`` (which also reports the GPU results'
+errors against it) may import it; the product package never
 does.  It shares no code with the GPU library: the arithmetic lives in
 ``hnv_oracle.c`` (plain C, FP64) and the driver below follows the paper's
 three phases in order:
