@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "refinement nnz·d updates/s and % HBM roofline, BF16 vs FP32 sweep, 1 MI355X"
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_sweep_zipf2m_bf16.txt")
+COUNTERS_FILES = {"zipf-2m": os.path.join(ROOT, "profiles", "counters_sweep_zipf2m_bf16.txt"),
+                  "zipf-8m": os.path.join(ROOT, "profiles", "counters_sweep_zipf8m_bf16.txt")}
 KERNEL_SRC = os.path.join(ROOT, "paper_2103_09660_amd", "csrc", "hnv_kernels.hip")
 
 
@@ -61,13 +62,15 @@ def kernel_source_digest():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def read_counters():
+def read_counters(config):
     """HBM traffic per launch of the forward sweep kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
-    if not os.path.exists(COUNTERS_FILE):
+    rocprofv3 counter summary of this workload, if it was taken on the
+    current kernel source."""
+    path = COUNTERS_FILES.get(config)
+    if path is None or not os.path.exists(path):
         return None
     kv = {}
-    for line in open(COUNTERS_FILE):
+    for line in open(path):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
@@ -527,7 +530,7 @@ def main():
     head = results[dtypes[0]]
     achieved = head["sweep_alg_bytes_per_launch"] / (head["sweep_kernel_avg_ms"] / 1000.0) / 1e9
     compulsory = head["sweep_min_bytes_per_launch"] / (head["sweep_kernel_avg_ms"] / 1000.0) / 1e9
-    traffic = read_counters() if dtypes[0] == "bf16" and args.config == "zipf-2m" else None
+    traffic = read_counters(args.config) if dtypes[0] == "bf16" else None
     line = {
         "metric": METRIC,
         "value": head["value"],
