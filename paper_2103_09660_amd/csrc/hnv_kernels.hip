@@ -781,7 +781,8 @@ HNV_DEV void stat_add(Stat<EPL> &s, const float (&x)[EPL], int op)
         } else {
             const float delta = x[i] - s.m[i];
             s.m[i] = fmaf(delta, inv, s.m[i]);
-            s.q[i] = fmaf(delta, x[i] - s.m[i], s.q[i]);
+            if (op == HNV_SCORE_VARIANCE)
+                s.q[i] = fmaf(delta, x[i] - s.m[i], s.q[i]);
         }
     }
 }
@@ -807,7 +808,8 @@ HNV_DEV void stat_merge(Stat<EPL> &a, float bn, const float (&bm)[EPL], const fl
         } else {
             const float delta = bm[i] - a.m[i];
             a.m[i] = fmaf(delta, fb, a.m[i]);
-            a.q[i] = a.q[i] + bq[i] + delta * delta * cross;
+            if (op == HNV_SCORE_VARIANCE)
+                a.q[i] = a.q[i] + bq[i] + delta * delta * cross;
         }
     }
     a.n = n;
@@ -874,7 +876,9 @@ struct ScoreArgs {
     int32_t pstride;
 };
 
-template <typename T, int EPL, int G>
+// OP (HNV_SCORE_*) is a template parameter so that each statistic keeps
+// only the registers it needs.
+template <typename T, int EPL, int G, int OP>
 __global__ __launch_bounds__(kBlock) void k_score(ScoreArgs a)
 {
     using S = Slice<T, EPL>;
@@ -885,7 +889,7 @@ __global__ __launch_bounds__(kBlock) void k_score(ScoreArgs a)
     const bool col_ok = col < a.ld;
     const T *z = static_cast<const T *>(a.z);
     Stat<EPL> st;
-    stat_init(st, a.op);
+    stat_init(st, OP);
     int b = blockIdx.x;
     if (b < a.nb_chunk) {
         const int item = b * kWavesPerBlock + (int)(threadIdx.x / kWave);
@@ -915,15 +919,15 @@ __global__ __launch_bounds__(kBlock) void k_score(ScoreArgs a)
                         S::unpack(raw[k], x);
                     else
                         zero(x);
-                    stat_add(st, x, a.op);
+                    stat_add(st, x, OP);
                 }
             }
         }
-        stat_wave_combine<EPL, G>(st, g, a.op);
+        stat_wave_combine<EPL, G>(st, g, OP);
         if (g != 0 || !col_ok)
             return;
         if (c.aux < 0) {
-            stat_write(a.out + (int64_t)c.row * a.ld + col, st, a.op);
+            stat_write(a.out + (int64_t)c.row * a.ld + col, st, OP);
         } else {
             float *pp = a.partials + (int64_t)c.aux * a.pstride;
 #pragma unroll
@@ -970,17 +974,17 @@ __global__ __launch_bounds__(kBlock) void k_score(ScoreArgs a)
                 S::unpack(raw[k], x);
             else
                 zero(x);
-            stat_add(st, x, a.op);
+            stat_add(st, x, OP);
         }
     }
     if (valid && col_ok)
-        stat_write(a.out + (int64_t)it.row * a.ld + col, st, a.op);
+        stat_write(a.out + (int64_t)it.row * a.ld + col, st, OP);
 }
 
 // Candidates split over several chunks: one wavefront merges the chunk
 // partials in slot order (group g takes slots g, g+Q, ..., then the groups
 // are combined lower first).
-template <int EPL, int G>
+template <int EPL, int G, int OP>
 __global__ __launch_bounds__(kBlock) void k_score_final(ScoreArgs a)
 {
     constexpr int Q = kWave / G;
@@ -993,7 +997,7 @@ __global__ __launch_bounds__(kBlock) void k_score_final(ScoreArgs a)
     const bool col_ok = col < a.ld;
     const Split sp = a.splits[item];
     Stat<EPL> st;
-    stat_init(st, a.op);
+    stat_init(st, OP);
     for (int k = g; k < sp.n_slots; k += Q) {
         const float *pp = a.partials + (int64_t)(sp.first_slot + k) * a.pstride;
         float bm[EPL], bq[EPL];
@@ -1002,11 +1006,11 @@ __global__ __launch_bounds__(kBlock) void k_score_final(ScoreArgs a)
             bm[i] = col_ok ? pp[col + i] : 0.0f;
             bq[i] = col_ok ? pp[a.ld + col + i] : 0.0f;
         }
-        stat_merge(st, pp[2 * a.ld], bm, bq, a.op);
+        stat_merge(st, pp[2 * a.ld], bm, bq, OP);
     }
-    stat_wave_combine<EPL, G>(st, g, a.op);
+    stat_wave_combine<EPL, G>(st, g, OP);
     if (g == 0 && col_ok)
-        stat_write(a.out + (int64_t)sp.row * a.ld + col, st, a.op);
+        stat_write(a.out + (int64_t)sp.row * a.ld + col, st, OP);
 }
 
 // ---------------------------------------------------------------------------
@@ -1696,6 +1700,15 @@ hnv_plan::~hnv_plan()
 namespace hnv {
 // Launches the scoring kernels on a plan that hnv_host.cpp built and
 // uploaded (see hnv_score_candidates there).
+template <typename T, int EPL, int G, int OP>
+static void launch_score(const ScoreArgs &a, unsigned grid, unsigned fgrid, hipStream_t s)
+{
+    if (grid)
+        k_score<T, EPL, G, OP><<<grid, kBlock, 0, s>>>(a);
+    if (fgrid)
+        k_score_final<EPL, G, OP><<<fgrid, kBlock, 0, s>>>(a);
+}
+
 hnv_status dev_score(const ScorePlan &sp, const void *z, hnv_dtype dtype, int d, int op, float *out,
                      hipStream_t s)
 {
@@ -1721,10 +1734,12 @@ hnv_status dev_score(const ScorePlan &sp, const void *z, hnv_dtype dtype, int d,
     const unsigned fgrid = (unsigned)blocks_for(sp.n_splits, kWavesPerBlock);
 #define HNV_SCORE(TT, EE, GG)                                                   \
     do {                                                                        \
-        if (grid)                                                               \
-            k_score<TT, EE, GG><<<grid, kBlock, 0, s>>>(a);                     \
-        if (fgrid)                                                              \
-            k_score_final<EE, GG><<<fgrid, kBlock, 0, s>>>(a);                  \
+        switch (op) {                                                           \
+        case HNV_SCORE_VARIANCE: launch_score<TT, EE, GG, HNV_SCORE_VARIANCE>(a, grid, fgrid, s); break; \
+        case HNV_SCORE_MEAN: launch_score<TT, EE, GG, HNV_SCORE_MEAN>(a, grid, fgrid, s); break;         \
+        case HNV_SCORE_MIN: launch_score<TT, EE, GG, HNV_SCORE_MIN>(a, grid, fgrid, s); break;           \
+        default: launch_score<TT, EE, GG, HNV_SCORE_MAX>(a, grid, fgrid, s); break;                      \
+        }                                                                       \
     } while (0)
 #define HNV_SCORE_G(TT, EE)                                                     \
     switch (G) {                                                                \
