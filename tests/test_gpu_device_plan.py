@@ -171,3 +171,25 @@ def test_device_plan_checks(H):
         H.Plan.from_device([lv], [], 16, "f32")
     assert ei.value.status == L.HNV_EINVAL
     torch.cuda.synchronize()
+
+
+def test_documented_usage_flow(H):
+    """The usage shown in the README, at a small size: device pipeline in
+    BF16, then a differentiable finest-level refinement in FP32."""
+    import torch
+    cfg = CONFIGS["tiny-2k"]
+    hg = make_hypergraph(cfg)
+    lv0 = H.DeviceLevel.from_host(H.HostLevel(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w))
+    levels, maps = H.coarsen_hierarchy_device(lv0, cfg.levels)
+    plan = H.Plan.from_device(levels, maps, d=32, dtype="bf16")
+    z_coarse = H.cast(torch.randn(levels[-1].n_nodes + levels[-1].n_edges, 32, device="cuda"), "bf16")
+    z_fine, residuals, done = plan.refine(z_coarse, sweeps=[5] * plan.n_levels, omega=0.5, residuals=True)
+    assert z_fine.shape == (levels[0].n_nodes + levels[0].n_edges, 32) and list(done) == [5] * plan.n_levels
+    assert bool(torch.isfinite(residuals).all())
+    plan32 = H.Plan.from_device(levels, maps, d=32, dtype="f32")
+    theta = torch.zeros(levels[0].n_edges, device="cuda", requires_grad=True)
+    z1 = torch.randn(levels[1].n_nodes + levels[1].n_edges, 32, device="cuda", requires_grad=True)
+    z0 = H.refine_level(z1, theta, plan32, 0, 10, 0.5, from_coarse=True, ckpt_every=5)
+    z0[: levels[0].n_nodes].square().mean().backward()
+    assert theta.grad is not None and z1.grad is not None
+    assert bool(torch.isfinite(theta.grad).all()) and float(z1.grad.abs().sum()) > 0
