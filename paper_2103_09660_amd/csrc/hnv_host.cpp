@@ -96,8 +96,47 @@ static void parallel_for(int64_t n, F f, int64_t grain = 1 << 15)
 // validation
 // ---------------------------------------------------------------------------
 
+// One hyperedge's checks; the message names the first violation.
+static hnv_status check_edge(const hnv_level *lv, int64_t e, bool full)
+{
+    const int64_t a = lv->edge_ptr[e], b = lv->edge_ptr[e + 1];
+    if (b < a || b > lv->nnz)
+        return fail(HNV_EINVAL, "edge_ptr decreases at hyperedge " + std::to_string(e));
+    if (full && b == a)
+        return fail(HNV_EINVAL, "hyperedge " + std::to_string(e) + " is empty");
+    for (int64_t j = a; j < b; ++j) {
+        const int32_t v = lv->edge_idx[j];
+        if (v < 0 || v >= lv->n_nodes)
+            return fail(HNV_ERANGE, "member " + std::to_string(v) + " of hyperedge " + std::to_string(e) +
+                                        " outside [0, n_nodes)");
+        if (full && j > a && lv->edge_idx[j - 1] >= v)
+            return fail(HNV_EUNSORTED, "members of hyperedge " + std::to_string(e) + " are not strictly ascending");
+    }
+    if (full && lv->edge_w) {
+        const float w = lv->edge_w[e];
+        if (!(w > 0.0f) || !std::isfinite(w))
+            return fail(HNV_EINVAL, "weight of hyperedge " + std::to_string(e) + " is not finite and > 0");
+    }
+    return HNV_OK;
+}
+
+static bool edge_ok(const hnv_level *lv, int64_t e, bool full)
+{
+    const int64_t a = lv->edge_ptr[e], b = lv->edge_ptr[e + 1];
+    if (b < a || b > lv->nnz || (full && b == a))
+        return false;
+    for (int64_t j = a; j < b; ++j) {
+        const int32_t v = lv->edge_idx[j];
+        if (v < 0 || v >= lv->n_nodes || (full && j > a && lv->edge_idx[j - 1] >= v))
+            return false;
+    }
+    return !(full && lv->edge_w && (!(lv->edge_w[e] > 0.0f) || !std::isfinite(lv->edge_w[e])));
+}
+
 // full = false checks only what memory safety needs (offsets and index
-// ranges); full = true also checks ordering, emptiness and weights.
+// ranges); full = true also checks ordering, emptiness and weights.  The
+// offsets are checked first, then the hyperedges in parallel ranges; the
+// error reported is the one of the lowest failing hyperedge.
 static hnv_status validate(const hnv_level *lv, bool full = true)
 {
     if (!lv)
@@ -110,41 +149,36 @@ static hnv_status validate(const hnv_level *lv, bool full = true)
         return fail(HNV_EINVAL, "edge_ptr / edge_idx is NULL");
     if (lv->edge_ptr[0] != 0 || lv->edge_ptr[lv->n_edges] != lv->nnz)
         return fail(HNV_EINVAL, "edge_ptr must start at 0 and end at nnz");
-    for (int64_t e = 0; e < lv->n_edges; ++e) {
-        const int64_t a = lv->edge_ptr[e], b = lv->edge_ptr[e + 1];
-        if (b < a || b > lv->nnz)
+    // a hyperedge's members are read only once every earlier offset is known
+    // not to decrease, so no read leaves [0, nnz)
+    for (int64_t e = 0; e < lv->n_edges; ++e)
+        if (lv->edge_ptr[e + 1] < lv->edge_ptr[e] || lv->edge_ptr[e + 1] > lv->nnz)
             return fail(HNV_EINVAL, "edge_ptr decreases at hyperedge " + std::to_string(e));
-        if (full && b == a)
-            return fail(HNV_EINVAL, "hyperedge " + std::to_string(e) + " is empty");
-        for (int64_t j = a; j < b; ++j) {
-            const int32_t v = lv->edge_idx[j];
-            if (v < 0 || v >= lv->n_nodes)
-                return fail(HNV_ERANGE, "member " + std::to_string(v) + " of hyperedge " + std::to_string(e) +
-                                            " outside [0, n_nodes)");
-            if (full && j > a && lv->edge_idx[j - 1] >= v)
-                return fail(HNV_EUNSORTED, "members of hyperedge " + std::to_string(e) +
-                                               " are not strictly ascending");
-        }
-        if (full && lv->edge_w) {
-            const float w = lv->edge_w[e];
-            if (!(w > 0.0f) || !std::isfinite(w))
-                return fail(HNV_EINVAL, "weight of hyperedge " + std::to_string(e) + " is not finite and > 0");
-        }
-    }
-    return HNV_OK;
+    std::atomic<int64_t> first_bad{std::numeric_limits<int64_t>::max()};
+    parallel_for(lv->n_edges, [&](int64_t eb, int64_t ee) {
+        for (int64_t e = eb; e < ee; ++e)
+            if (!edge_ok(lv, e, full)) {
+                int64_t cur = first_bad.load();
+                while (e < cur && !first_bad.compare_exchange_weak(cur, e)) {
+                }
+                return;
+            }
+    }, 1 << 14);
+    const int64_t e = first_bad.load();
+    return e == std::numeric_limits<int64_t>::max() ? HNV_OK : check_edge(lv, e, full);
 }
 
 // ---------------------------------------------------------------------------
 // coarsening
 // ---------------------------------------------------------------------------
 
-// node -> incident hyperedges, each list in ascending hyperedge id.  The
-// hyperedges are cut into T contiguous ranges of about equal incidence
-// count; thread t counts its range's incidences per node, the counts are
-// turned into per-(node, range) offsets, and thread t fills its slots.
-// Ranges are in hyperedge order, so every list comes out ascending without
-// atomics or sorting, whatever the thread count.
-static void incidence_by_node(const hnv_level *lv, std::vector<int32_t> &nptr, std::vector<int32_t> &nedge)
+// Per-(range, node) incidence counts: the hyperedges are cut into T
+// contiguous ranges of about equal incidence count and thread t counts its
+// range's incidences per node.  Returns the cut points; cnt[t * nV + v]
+// becomes the offset of range t's first incidence of v within v's list, and
+// nptr the node offsets.  Integer counts, so the result does not depend on
+// the thread count.
+static std::vector<int64_t> count_by_node(const hnv_level *lv, std::vector<int32_t> &cnt, std::vector<int32_t> &nptr)
 {
     const int64_t nV = lv->n_nodes, nE = lv->n_edges, nnz = lv->nnz;
     const int T = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), nnz / (1 << 16)));
@@ -152,7 +186,7 @@ static void incidence_by_node(const hnv_level *lv, std::vector<int32_t> &nptr, s
     cut[0] = 0;
     for (int t = 1; t < T; ++t)
         cut[t] = std::upper_bound(lv->edge_ptr, lv->edge_ptr + nE + 1, nnz * t / T) - lv->edge_ptr - 1;
-    std::vector<int32_t> cnt((size_t)T * nV, 0);
+    cnt.assign((size_t)T * nV, 0);
     parallel_for(T, [&](int64_t tb, int64_t te) {
         for (int64_t t = tb; t < te; ++t) {
             int32_t *c = cnt.data() + t * nV;
@@ -174,7 +208,20 @@ static void incidence_by_node(const hnv_level *lv, std::vector<int32_t> &nptr, s
     });
     for (int64_t v = 0; v < nV; ++v)
         nptr[v + 1] += nptr[v];
-    nedge.resize(nnz);
+    return cut;
+}
+
+// node -> incident hyperedges, each list in ascending hyperedge id: after
+// count_by_node, thread t fills its range's slots.  Ranges are in hyperedge
+// order, so every list comes out ascending without atomics or sorting,
+// whatever the thread count.
+static void incidence_by_node(const hnv_level *lv, std::vector<int32_t> &nptr, std::vector<int32_t> &nedge)
+{
+    std::vector<int32_t> cnt;
+    const std::vector<int64_t> cut = count_by_node(lv, cnt, nptr);
+    const int T = (int)cut.size() - 1;
+    const int64_t nV = lv->n_nodes;
+    nedge.resize(lv->nnz);
     parallel_for(T, [&](int64_t tb, int64_t te) {
         for (int64_t t = tb; t < te; ++t) {
             int32_t *c = cnt.data() + t * nV;
@@ -433,11 +480,8 @@ static void build_level(const hnv_level *levels, const hnv_map *maps, int n_leve
     if (with_arrays) {
         incidence_by_node(&L, h.ptr[1], h.idx[1]);
     } else {
-        h.ptr[1].assign(h.nV + 1, 0);
-        for (int64_t j = 0; j < h.nnz; ++j)
-            ++h.ptr[1][L.edge_idx[j] + 1];
-        for (int64_t v = 0; v < h.nV; ++v)
-            h.ptr[1][v + 1] += h.ptr[1][v];
+        std::vector<int32_t> cnt;
+        count_by_node(&L, cnt, h.ptr[1]);
     }
 
     int32_t slots = 0;
