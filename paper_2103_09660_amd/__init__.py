@@ -25,6 +25,7 @@ from .api import (  # noqa: F401
     plan_workspace_bytes,
     refine_level,
     score_candidates,
+    star_edgelist,
     validate_level,
 )
 from ._lib import HnvError  # noqa: F401

@@ -201,15 +201,30 @@ def coarsen_hierarchy_features_device(level: DeviceLevel, x, n_coarsen: int):
     return levels, maps, feats
 
 
-def coarsen_hierarchy_device(level: DeviceLevel, n_coarsen: int):
-    """n_coarsen GPU coarsening steps from ``level``, one shared workspace:
-    returns (device levels 0..n_coarsen, [(node_rep, edge_rep)] per step)."""
+def _stop(rows_fine: int, rows_coarse: Optional[int], min_rows: int) -> bool:
+    """Depth rule (Section 3.1, Algorithm 1's depth K): with min_rows > 0,
+    coarsening stops once a level has at most min_rows star-expansion rows,
+    or when a step no longer shrinks the level."""
+    if min_rows <= 0:
+        return False
+    return rows_fine <= min_rows or (rows_coarse is not None and rows_coarse >= rows_fine)
+
+
+def coarsen_hierarchy_device(level: DeviceLevel, n_coarsen: int, min_rows: int = 0):
+    """Up to n_coarsen GPU coarsening steps from ``level`` (fewer when
+    min_rows > 0 stops them, see :func:`_stop`), one shared workspace:
+    returns (device levels, [(node_rep, edge_rep)] per step)."""
     torch = _torch()
     ws = torch.empty(coarsen_workspace_bytes(level.n_nodes, level.n_edges, level.nnz), dtype=torch.uint8,
                      device=level.edge_ptr.device)
     levels, maps = [level], []
     for _ in range(n_coarsen):
-        nrep, erep, coarse = coarsen_level_device(levels[-1], ws)
+        fine = levels[-1]
+        if _stop(fine.n_nodes + fine.n_edges, None, min_rows):
+            break
+        nrep, erep, coarse = coarsen_level_device(fine, ws)
+        if _stop(fine.n_nodes + fine.n_edges, coarse.n_nodes + coarse.n_edges, min_rows):
+            break
         maps.append((nrep, erep))
         levels.append(coarse)
     return levels, maps
@@ -224,21 +239,33 @@ class Hierarchy:
         self.maps = maps
 
     @classmethod
-    def build(cls, n_nodes, n_edges, edge_ptr, edge_idx, edge_w, n_coarsen: int, device=None) -> "Hierarchy":
-        """Coarsens n_coarsen times, on the host, or on ``device`` (a GPU)
-        with the result copied back (a plan is built from host levels)."""
+    def build(cls, n_nodes, n_edges, edge_ptr, edge_idx, edge_w, n_coarsen: int, device=None,
+              min_rows: int = 0) -> "Hierarchy":
+        """Coarsens up to n_coarsen times (fewer when min_rows > 0 stops
+        them: a level of at most min_rows rows, or a step that no longer
+        shrinks the level), on the host, or on ``device`` (a GPU) with the
+        result copied back."""
         levels = [HostLevel(n_nodes, n_edges, edge_ptr, edge_idx, edge_w)]
         maps = []
         if device is not None:
-            dl, dm = coarsen_hierarchy_device(DeviceLevel.from_host(levels[0], device), n_coarsen)
+            dl, dm = coarsen_hierarchy_device(DeviceLevel.from_host(levels[0], device), n_coarsen, min_rows)
             levels += [x.to_host() for x in dl[1:]]
             maps = [HostMap(a.cpu().numpy(), b.cpu().numpy()) for a, b in dm]
             return cls(levels, maps)
         for _ in range(n_coarsen):
+            if _stop(levels[-1].rows, None, min_rows):
+                break
             m, c = coarsen_level(levels[-1])
+            if _stop(levels[-1].rows, c.rows, min_rows):
+                break
             maps.append(m)
             levels.append(c)
         return cls(levels, maps)
+
+    def coarsest_edgelist(self):
+        """The coarsest level's star expansion as an edge list for an
+        external initial embedder (Section 3.2): see :func:`star_edgelist`."""
+        return star_edgelist(self.levels[-1])
 
     @property
     def n_levels(self) -> int:
@@ -248,6 +275,22 @@ class Hierarchy:
         lv = (L.HnvLevel * self.n_levels)(*[x.c() for x in self.levels])
         mp = (L.HnvMap * max(len(self.maps), 1))(*[m.c() for m in self.maps]) if self.maps else None
         return lv, mp
+
+
+def star_edgelist(level: HostLevel):
+    """The star expansion H* of a level (Section 1.1) as an edge list in the
+    library's row numbering (node v -> row v, hyperedge e -> row n_nodes + e):
+    returns (src int64 [nnz], dst int64 [nnz], weight float32 [nnz]) with
+    one edge per incidence, node row first, weighted by w_e (1 without
+    weights).  This is the graph an initial embedder such as node2vec or
+    DeepWalk takes for the coarsest level; its output rows map one to one
+    onto the coarsest embedding the refinement starts from."""
+    counts = np.diff(level.edge_ptr)
+    edges = np.repeat(np.arange(level.n_edges, dtype=np.int64), counts)
+    src = level.edge_idx.astype(np.int64)
+    dst = level.n_nodes + edges
+    w = np.ones(level.nnz, dtype=np.float32) if level.edge_w is None else level.edge_w[edges].astype(np.float32)
+    return src, dst, w
 
 
 def _options(options) -> Optional[L.HnvOptions]:

@@ -15,6 +15,7 @@ from .hypergraph import (  # noqa: F401
     make_hypergraph,
     node_features,
     coarsest_embedding,
+    drop_isolated_and_singletons,
     labelled_nodes,
     linear_head,
     cotangent,

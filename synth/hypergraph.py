@@ -227,6 +227,28 @@ def coarsest_embedding(cfg_or_seed, n_rows: int, d: int, columns: Optional[Seque
     return out
 
 
+def drop_isolated_and_singletons(hg: Hypergraph) -> tuple:
+    """The paper's dataset cleaning (Section 4): hyperedges with one member
+    are dropped, then nodes left without hyperedges, and the remaining nodes
+    are renumbered in order.  Returns (pruned Hypergraph, kept node ids of
+    the input)."""
+    sizes = np.diff(hg.edge_ptr)
+    keep_e = np.nonzero(sizes >= 2)[0]
+    seg = np.repeat(np.arange(hg.n_edges), sizes)
+    keep_inc = np.isin(seg, keep_e)
+    members = hg.edge_idx[keep_inc]
+    used = np.zeros(hg.n_nodes, dtype=bool)
+    used[members] = True
+    kept_nodes = np.nonzero(used)[0]
+    new_id = np.full(hg.n_nodes, -1, dtype=np.int64)
+    new_id[kept_nodes] = np.arange(len(kept_nodes))
+    ptr = np.zeros(len(keep_e) + 1, dtype=np.int64)
+    np.cumsum(sizes[keep_e], out=ptr[1:])
+    idx = new_id[members].astype(np.int32)     # renumbering keeps each row ascending
+    w = None if hg.edge_w is None else hg.edge_w[keep_e].copy()
+    return Hypergraph(len(kept_nodes), len(keep_e), ptr, idx, w), kept_nodes
+
+
 def bag_of_words(seed: int, n_nodes: int, k: int, words_lo: int, words_hi: int, zipf_a: float = 1.1,
                  max_count: int = 3, empty_frac: float = 0.02, repeat_frac: float = 0.05) -> np.ndarray:
     """int32 [n_nodes x k] word counts: words_lo..words_hi distinct words per

@@ -159,3 +159,17 @@ def test_workspace_errors(H):
     assert st == L.HNV_EWORKSPACE
     st = L.lib().hnv_coarsen_level_device(*args, ws.data_ptr(), need, None)
     assert st == L.HNV_OK and sizes[0] > 0
+
+
+def test_depth_rule_matches_host(H):
+    """The optional depth rule stops the GPU coarsening where it stops the
+    host coarsening."""
+    hg = random_hypergraph(5, 3000, 2000, 1, 6)
+    full = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, 6)
+    target = full.levels[3].rows
+    host = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, 6, min_rows=target)
+    dev = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, 6, device="cuda",
+                            min_rows=target)
+    assert host.n_levels == dev.n_levels == 4
+    for a, b in zip(host.maps, dev.maps):
+        assert np.array_equal(a.node_rep, b.node_rep) and np.array_equal(a.edge_rep, b.edge_rep)
