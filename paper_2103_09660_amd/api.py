@@ -345,10 +345,24 @@ class Plan:
     holds every level's adjacency, work lists, maps and reciprocals."""
 
     def __init__(self, hier: Hierarchy, d: int, dtype: str = "f32", options=None, device=None,
-                 validate: bool = True):
+                 validate: bool = True, build: str = "host"):
+        """build="host" builds the plan from the host arrays (hnv_plan_create);
+        build="device" uploads the levels and builds the identical plan on
+        the GPU (hnv_plan_create_device), much faster for large hierarchies."""
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("a GPU is required for a device plan")
+        if build == "device":
+            dev = torch.device("cuda" if device is None else device)
+            levels = [DeviceLevel.from_host(lv, dev) for lv in hier.levels]
+            maps = [(torch.as_tensor(m.node_rep).to(dev), torch.as_tensor(m.edge_rep).to(dev)) for m in hier.maps]
+            other = Plan.from_device(levels, maps, d, dtype, options, validate)
+            self.__dict__.update(other.__dict__)
+            other._h = None
+            self.hier = hier
+            return
+        if build != "host":
+            raise ValueError("build must be 'host' or 'device'")
         self.device = torch.device("cuda" if device is None else device)
         self.hier = hier
         self.d = int(d)

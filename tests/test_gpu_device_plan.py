@@ -193,3 +193,16 @@ def test_documented_usage_flow(H):
     z0[: levels[0].n_nodes].square().mean().backward()
     assert theta.grad is not None and z1.grad is not None
     assert bool(torch.isfinite(theta.grad).all()) and float(z1.grad.abs().sum()) > 0
+
+
+def test_plan_build_option(H):
+    """Plan(hierarchy, build="device") uploads the host levels and gives the
+    plan hnv_plan_create builds, bit for bit."""
+    cfg = CONFIGS["hub-200k"]
+    hg = make_hypergraph(cfg)
+    hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, cfg.levels)
+    host = H.Plan(hier, cfg.d, "bf16")
+    dev = H.Plan(hier, cfg.d, "bf16", build="device")
+    _assert_same_refine(host, dev, hier, cfg.d, list(cfg.sweeps), 2)
+    with pytest.raises(ValueError):
+        H.Plan(hier, cfg.d, "bf16", build="somewhere")
