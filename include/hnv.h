@@ -19,7 +19,7 @@
  *     round-to-nearest-even), 16-byte aligned, in device memory.
  *   - A hyperedge is a nonempty set of nodes (Section 1): its member list is
  *     strictly ascending.  Weights are finite and > 0; a NULL weight array
- *     means unit weights (Section 3.3: "a value of 1 is used").
+ *     means unit weights (Section 3.3 takes unit weights when none are given).
  *   - The star edge between node v and hyperedge e carries the weight w_e in
  *     both directions.  So a hyperedge row is relaxed towards the plain mean
  *     of its members and a node row towards the w-weighted mean of its
@@ -90,7 +90,7 @@ typedef struct {
                             at 4 lanes' worth of indices per lane of the group) */
     int32_t chunk;       /* neighbours per wavefront work item; longer rows are split */
     int32_t order;       /* HNV_ORDER_*: update order of a sweep (Section 3.3 describes both; the
-                            edge-first order is the text's "SOR" reading, two half-sweeps that may
+                            edge-first order is the text's SOR reading, two half-sweeps that may
                             run in place; the reverse sweep supports HNV_ORDER_JACOBI only) */
 } hnv_options;
 
@@ -110,7 +110,7 @@ hnv_status hnv_validate_level(const hnv_level *level);
 /* One step of Algorithm 1 without node features (Section 3.1), on the host.
  * Each node v with hyperedges is assigned to c(v), the hyperedge of N(v)
  * with the largest weight, then the fewest members, then the lowest id (the
- * paper's featureless rule "weights or degrees of a hyperedge", with its
+ * paper's featureless rule, which assigns by hyperedge weight or degree, with its
  * random tie-break replaced by a fixed order so the maps are reproducible).
  * Nodes with the same c(v) merge into one coarse node; a node without
  * hyperedges stays a node of its own.  Coarse node ids follow the smallest
