@@ -1,0 +1,69 @@
+"""Randomised parity sweep: seeded random shapes, widths, storage types,
+tier bounds, update orders and plan builders, each refined over a small
+hierarchy on the GPU and compared with the FP64 oracle run on the same
+(storage-rounded) input.  Every case is reproducible from its seed."""
+import numpy as np
+import pytest
+
+from tests.cases import max_abs_rel, random_hypergraph, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2103_09660_amd as H
+    return H
+
+
+def _case(seed):
+    rng = np.random.default_rng(10_000 + seed)
+    n_nodes = int(rng.integers(1, 4000))
+    n_edges = int(rng.integers(1, 3000))
+    hi = int(rng.choice([2, 4, 9, 30, 120]))
+    d = int(8 * rng.integers(1, 65))
+    dtype = str(rng.choice(["f32", "bf16"]))
+    small_max = int(rng.choice([0, 1, 3, 8, 17, 64]))
+    chunk = int(rng.choice([0, 5, 32, 100, 512]))
+    order = str(rng.choice(["jacobi", "edge_first"]))
+    weighted = bool(rng.integers(0, 2))
+    levels = int(rng.integers(0, 4))
+    sweeps = [int(k) for k in rng.integers(0, 4, size=levels + 1)]
+    omega = float(rng.choice([0.25, 0.5, 0.9, 1.0]))
+    build = str(rng.choice(["host", "device"]))
+    return dict(n_nodes=n_nodes, n_edges=n_edges, hi=hi, d=d, dtype=dtype, small_max=small_max, chunk=chunk,
+                order=order, weighted=weighted, levels=levels, sweeps=sweeps, omega=omega, build=build)
+
+
+@pytest.mark.parametrize("seed", range(100))
+def test_random_configuration(oracle_mod, H, seed):
+    import torch
+    O = oracle_mod
+    c = _case(seed)
+    print("case", seed, c, flush=True)
+    hg = random_hypergraph(seed, c["n_nodes"], c["n_edges"], 1, c["hi"], weighted=c["weighted"])
+    levels, maps = O.build_hierarchy(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, c["levels"])
+    hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, c["levels"])
+    opts = {"small_max": c["small_max"], "chunk": c["chunk"], "order": c["order"]}
+    plan = H.Plan(hier, c["d"], c["dtype"], options=opts, build=c["build"])
+    rng = np.random.default_rng(seed)
+    zc = rng.standard_normal((levels[-1].rows, c["d"])).astype(np.float32)
+    zdev = torch.as_tensor(zc).cuda()
+    if c["dtype"] == "bf16":
+        zdev = zdev.to(torch.bfloat16)
+        zin = zdev.float().cpu().numpy().astype(np.float64)
+    else:
+        zin = zc.astype(np.float64)
+    out, _, done = plan.refine(zdev, c["sweeps"], c["omega"])
+    got = out.float().cpu().numpy().astype(np.float64)
+    order = 1 if c["order"] == "edge_first" else 0
+    ref = O.refine(levels, maps, zin, c["sweeps"], c["omega"], order=order)
+    tol = 1e-5 if c["dtype"] == "f32" else 1e-2
+    assert list(done) == c["sweeps"]
+    if np.linalg.norm(ref) == 0:
+        assert np.abs(got).max() == 0
+    else:
+        assert rel_fro(got, ref) <= tol and max_abs_rel(got, ref) <= 10 * tol, (rel_fro(got, ref), c)
