@@ -67,3 +67,34 @@ def test_random_configuration(oracle_mod, H, seed):
         assert np.abs(got).max() == 0
     else:
         assert rel_fro(got, ref) <= tol and max_abs_rel(got, ref) <= 10 * tol, (rel_fro(got, ref), c)
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_random_coarsening(oracle_mod, H, seed):
+    """GPU coarsening, featureless and feature-driven, against the oracle bit
+    for bit on seeded random shapes (integer weights force many key ties)."""
+    import torch
+    from synth import bag_of_words
+    O = oracle_mod
+    rng = np.random.default_rng(20_000 + seed)
+    n_nodes = int(rng.integers(1, 3000))
+    n_edges = int(rng.integers(1, 2500))
+    hi = int(rng.choice([1, 2, 5, 20, 80]))
+    weights = str(rng.choice(["none", "int", "float"]))
+    k = int(4 * rng.integers(1, 40))
+    print("case", seed, n_nodes, n_edges, hi, weights, k, flush=True)
+    hg = random_hypergraph(seed, n_nodes, n_edges, 1, hi, weighted=weights != "none",
+                           integer_weights=weights == "int")
+    lv = O.Level(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w)
+    dl = H.DeviceLevel.from_host(H.HostLevel(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w), "cuda")
+    ref = O.coarsen_level(lv)
+    nrep, erep, c = H.coarsen_level_device(dl)
+    assert np.array_equal(nrep.cpu().numpy(), ref.node_rep) and np.array_equal(erep.cpu().numpy(), ref.edge_rep)
+    assert np.array_equal(c.edge_ptr.cpu().numpy(), ref.coarse.eptr)
+    assert np.array_equal(c.edge_idx.cpu().numpy(), ref.coarse.eidx)
+    x = bag_of_words(30_000 + seed, n_nodes, k, 1, min(12, k), empty_frac=0.1, repeat_frac=0.3)
+    fref, xref = O.coarsen_level_features(lv, x)
+    fnrep, ferep, fc, xc = H.coarsen_level_features_device(dl, torch.as_tensor(x).cuda())
+    assert np.array_equal(fnrep.cpu().numpy(), fref.node_rep) and np.array_equal(ferep.cpu().numpy(), fref.edge_rep)
+    assert np.array_equal(fc.edge_idx.cpu().numpy(), fref.coarse.eidx)
+    assert np.array_equal(xc.cpu().numpy(), xref)
