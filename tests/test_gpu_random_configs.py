@@ -98,3 +98,54 @@ def test_random_coarsening(oracle_mod, H, seed):
     assert np.array_equal(fnrep.cpu().numpy(), fref.node_rep) and np.array_equal(ferep.cpu().numpy(), fref.edge_rep)
     assert np.array_equal(fc.edge_idx.cpu().numpy(), fref.coarse.eidx)
     assert np.array_equal(xc.cpu().numpy(), xref)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_reverse_mode(oracle_mod, H, seed):
+    """Adjoint sweep, weight gradient and projection adjoint (FP32) against
+    the oracle's reverse pass on seeded random shapes, widths, tier bounds,
+    ω and hyperedge weights."""
+    import torch
+    O = oracle_mod
+    rng = np.random.default_rng(40_000 + seed)
+    n_nodes = int(rng.integers(2, 3000))
+    n_edges = int(rng.integers(1, 2000))
+    hi = int(rng.choice([2, 5, 20, 90]))
+    d = int(8 * rng.integers(1, 33))
+    small_max = int(rng.choice([0, 1, 4, 16]))
+    chunk = int(rng.choice([0, 7, 64]))
+    omega = float(rng.choice([0.3, 0.5, 1.0]))
+    build = str(rng.choice(["host", "device"]))
+    print("case", seed, n_nodes, n_edges, hi, d, small_max, chunk, omega, build, flush=True)
+    hg = random_hypergraph(seed, n_nodes, n_edges, 1, hi, weighted=True)
+    levels, maps = O.build_hierarchy(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, 1)
+    hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, 1)
+    plan = H.Plan(hier, d, "f32", options={"small_max": small_max, "chunk": chunk}, build=build)
+    w = hg.edge_w.astype(np.float32)
+    y = rng.standard_normal((levels[0].rows, d)).astype(np.float32)
+    g = rng.standard_normal((levels[0].rows, d)).astype(np.float32)
+    yd, gd = torch.as_tensor(y).cuda(), torch.as_tensor(g).cuda()
+    z = plan.sweep(0, yd, omega)
+    dw = torch.zeros(levels[0].n_edges, dtype=torch.float32, device="cuda")
+    gy = plan.sweep_adjoint(0, gd, yd, z, omega, dw=dw)
+    ref_gy, ref_dw = O.sweep_vjp(levels[0], y, g, omega, w)
+    assert rel_fro(gy.cpu().numpy(), ref_gy) <= 1e-5
+    # dw_e = ω Σ_{v∈e} <g_v, y_e - z~_v> / S_v can cancel to ~0 (a member with
+    # one hyperedge has z~_v = y_e), so each entry is held to 1e-4 of the size
+    # of its own terms rather than to the norm of dw
+    lv0 = levels[0]
+    z_ref = O.sweep(lv0, y, omega, 0, w)
+    nv = lv0.n_nodes
+    ztil = (z_ref[:nv] - (1 - omega) * y[:nv].astype(np.float64)) / omega
+    S = np.zeros(nv)
+    np.add.at(S, lv0.eidx, np.repeat(w.astype(np.float64), np.diff(lv0.eptr)))
+    e_of = np.repeat(np.arange(lv0.n_edges), np.diff(lv0.eptr))
+    gv = g[lv0.eidx].astype(np.float64)
+    terms = (np.abs(np.einsum("ij,ij->i", gv, y[nv + e_of].astype(np.float64))) +
+             np.abs(np.einsum("ij,ij->i", gv, ztil[lv0.eidx]))) / S[lv0.eidx]
+    scale = omega * np.bincount(e_of, weights=terms, minlength=lv0.n_edges)
+    err = np.abs(dw.cpu().numpy().astype(np.float64) - ref_dw)
+    assert np.all(err <= 1e-4 * scale + 1e-30), float(np.max(err / np.maximum(scale, 1e-30)))
+    gc = plan.project_adjoint(0, gd)
+    ref_gc = O.project_vjp(O.rowmap(levels[0], maps[0]), levels[1].rows, g)
+    assert rel_fro(gc.cpu().numpy(), ref_gc) <= 1e-5
