@@ -143,7 +143,9 @@ hnv_status hnv_coarsen_level(const hnv_level *fine, int32_t *node_rep, int32_t *
  * the sizes, so it returns with the outputs complete.  workspace: DEVICE,
  * >= hnv_coarsen_workspace_bytes, 256-byte aligned; its contents need not
  * be initialised and are scratch afterwards.  Calls sharing a workspace on
- * different streams race. */
+ * different streams race.  The workspace size includes the temporary
+ * storage of the GPU sorts and scans, which is queried from the device, so
+ * hnv_coarsen_workspace_bytes needs a visible GPU (HNV_EDEVICE otherwise). */
 hnv_status hnv_coarsen_workspace_bytes(int64_t n_nodes, int64_t n_edges, int64_t nnz, size_t *bytes);
 hnv_status hnv_coarsen_level_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const int32_t *edge_ptr,
                                     const int32_t *edge_idx, const float *edge_w, int32_t *node_rep,
