@@ -269,6 +269,36 @@ def run_pipeline(H, torch, hier, cfg, dtype, zc, host_plan, refine_ms, host_coar
                       "path), min of %d; refine_ms is one timed refinement step" % reps}
 
 
+def run_graph_replay(H, torch, reps=50):
+    """Launch-bound sizes: the 2,000-node, 1,000-hyperedge refinement (d = 32,
+    4 levels, 10 sweeps each), eager through hnv_refine against a replay of
+    the same launches captured in a HIP graph."""
+    from synth import CONFIGS, coarsest_embedding, make_hypergraph
+    cfg = CONFIGS["tiny-2k"]
+    hg = make_hypergraph(cfg)
+    hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, cfg.levels)
+    plan = H.Plan(hier, cfg.d, "f32")
+    zc = torch.as_tensor(coarsest_embedding(cfg, hier.levels[-1].rows, cfg.d)).cuda()
+    sweeps = list(cfg.sweeps)
+    out = plan.empty(0)
+    graph = plan.capture_refine(zc, sweeps, 0.5, residuals=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / reps
+
+    eager = timed(lambda: plan.refine(zc, sweeps, 0.5, residuals=True, out=out))
+    replay = timed(graph.replay)
+    return {"workload": f"{cfg.name}: {cfg.n_nodes} nodes, {cfg.n_edges} hyperedges, d={cfg.d}, "
+                        f"{hier.n_levels} levels x {cfg.sweeps[0]} sweeps, FP32",
+            "eager_ms": eager, "graph_replay_ms": replay, "speedup": eager / replay}
+
+
 def run_scoring(H, torch, hg, z_out, cfg, steps):
     """Hyperedge-prediction features of the finest level's hyperedges taken
     as candidate sets: per-dimension variance of the member rows of the
@@ -592,6 +622,9 @@ def main():
         torch.cuda.empty_cache()
     if reverse is not None:
         line["reverse"] = reverse
+    if args.config == "zipf-2m":
+        line["graph_replay"] = run_graph_replay(H, torch)
+        log(f"graph replay: {line['graph_replay']}")
     if not args.no_differentiable and args.config == "zipf-2m":
         t = time.perf_counter()
         line["differentiable"] = run_differentiable(H, torch, max(2, args.steps // 2), 1)

@@ -480,6 +480,14 @@ class Plan:
                float(omega), float(tol), _ptr(res), done.ctypes.data_as(L.i32p), _stream(self.device))
         return z_out, res, done
 
+    def capture_refine(self, z_coarsest, sweeps: Sequence[int], omega: float = 0.5, residuals: bool = False):
+        """Captures one fixed-count refinement into a HIP graph (through
+        torch.cuda.CUDAGraph) for launch-bound sizes: returns a RefineGraph
+        whose replay() reruns every launch on the current stream, reading
+        ``z_coarsest`` (the same tensor, refill it in place) and writing
+        its ``out`` (and ``residuals``) tensors."""
+        return RefineGraph(self, z_coarsest, sweeps, omega, residuals)
+
     def sweep(self, level: int, z_in, omega: float = 0.5, from_coarse: bool = False, out=None, resid=None):
         """One sweep; ``out`` may be ``z_in`` itself for an edge-first plan."""
         self._check(z_in, level + 1 if from_coarse else level, "z_in")
@@ -516,6 +524,41 @@ class Plan:
 
 _SCORE_OPS = {"variance": L.HNV_SCORE_VARIANCE, "mean": L.HNV_SCORE_MEAN, "min": L.HNV_SCORE_MIN,
               "max": L.HNV_SCORE_MAX}
+
+
+class RefineGraph:
+    """A refinement captured into a HIP graph (see Plan.capture_refine).
+    Early stop (tol) and kernel profiling synchronise with the host and are
+    not captured."""
+
+    def __init__(self, plan: "Plan", z_coarsest, sweeps: Sequence[int], omega: float, residuals: bool):
+        torch = _torch()
+        plan._check(z_coarsest, plan.n_levels - 1, "z_coarsest")
+        self.plan, self.z_coarsest, self.omega = plan, z_coarsest, float(omega)
+        self.sweeps = np.ascontiguousarray(sweeps, dtype=np.int32)
+        assert len(self.sweeps) == plan.n_levels
+        self.out = plan.empty(0)
+        self.residuals = (torch.zeros(max(int(self.sweeps.sum()), 1), dtype=torch.float64, device=plan.device)
+                          if residuals else None)
+        self._done = np.zeros(plan.n_levels, dtype=np.int32)
+        side = torch.cuda.Stream(device=plan.device)
+        side.wait_stream(torch.cuda.current_stream(plan.device))
+        with torch.cuda.stream(side):                 # first run outside the graph
+            self._launch()
+        torch.cuda.current_stream(plan.device).wait_stream(side)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._launch()
+
+    def _launch(self):
+        L.call("hnv_refine", self.plan._h, self.z_coarsest.data_ptr(), self.out.data_ptr(),
+               self.sweeps.ctypes.data_as(L.i32p), self.omega, 0.0,
+               _ptr(self.residuals), self._done.ctypes.data_as(L.i32p), _stream(self.plan.device))
+
+    def replay(self):
+        """Reruns the captured refinement; returns (out, residuals)."""
+        self.graph.replay()
+        return self.out, self.residuals
 
 
 class ScorePlan:
