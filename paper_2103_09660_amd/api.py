@@ -445,6 +445,7 @@ class Plan:
     # kernel timing ---------------------------------------------------------
     def set_profiling(self, enable: bool):
         L.call("hnv_plan_set_profiling", self._h, 1 if enable else 0)
+        self._profiling = bool(enable)
 
     def profile_read(self, kind: int, level: int = -1):
         """(launches, total milliseconds) of one kernel kind (see hnv.h)."""
@@ -533,6 +534,8 @@ class RefineGraph:
 
     def __init__(self, plan: "Plan", z_coarsest, sweeps: Sequence[int], omega: float, residuals: bool):
         torch = _torch()
+        if getattr(plan, "_profiling", False):
+            raise RuntimeError("turn kernel profiling off before capturing a refinement")
         plan._check(z_coarsest, plan.n_levels - 1, "z_coarsest")
         self.plan, self.z_coarsest, self.omega = plan, z_coarsest, float(omega)
         self.sweeps = np.ascontiguousarray(sweeps, dtype=np.int32)
