@@ -118,3 +118,19 @@ def test_invalid_features_are_rejected(H):
             x.data_ptr(), k, *[t.data_ptr() for t in out[:4]], out[4].data_ptr(), cx.data_ptr(),
             ctypes.cast(sizes, L.i64p), ws.data_ptr(), need, None)
         assert st == L.HNV_EUNSUPPORTED
+
+
+def test_features_without_hyperedges(H):
+    """Nodes only: every node is its own coarse node and X' = X; and an empty
+    level."""
+    import torch
+    x = torch.randint(0, 4, (9, 12), dtype=torch.int32, device="cuda")
+    lv = H.DeviceLevel(9, 0, 0, torch.zeros(1, dtype=torch.int32, device="cuda"),
+                       torch.zeros(0, dtype=torch.int32, device="cuda"))
+    nrep, erep, c, xc = H.coarsen_level_features_device(lv, x)
+    assert nrep.cpu().tolist() == list(range(9)) and (c.n_nodes, c.n_edges, c.nnz) == (9, 0, 0)
+    assert torch.equal(xc, x)
+    lv = H.DeviceLevel(0, 0, 0, torch.zeros(1, dtype=torch.int32, device="cuda"),
+                       torch.zeros(0, dtype=torch.int32, device="cuda"))
+    nrep, erep, c, xc = H.coarsen_level_features_device(lv, torch.zeros((0, 8), dtype=torch.int32, device="cuda"))
+    assert (c.n_nodes, c.n_edges, c.nnz) == (0, 0, 0) and xc.shape[0] == 0
