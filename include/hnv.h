@@ -359,6 +359,21 @@ hnv_status hnv_score_plan_destroy(hnv_score_plan *plan);
  * float [n_cand x d], 16-byte aligned; op: HNV_SCORE_*. */
 hnv_status hnv_score_candidates(hnv_score_plan *plan, const void *z, int op, float *out, void *stream);
 
+/* The same score plan built on the GPU from DEVICE candidate arrays (for
+ * candidates generated on the device): cand_ptr[n_cand+1] (int32, starts at
+ * 0, never decreases, ends at n_members) and cand_idx[n_members], ids in
+ * [0, z_rows) (checked on the device: HNV_EINVAL / HNV_ERANGE).  The work
+ * lists are those hnv_score_plan_create builds, so the scores are
+ * identical.  The workspace size comes from the sizes alone, with the work
+ * lists at their upper bounds; its sort storage is queried from the device,
+ * so hnv_score_workspace_bytes_device needs a visible GPU.  The candidate
+ * arrays are read during the call only; the call synchronises `stream`. */
+hnv_status hnv_score_workspace_bytes_device(int64_t n_cand, int64_t n_members, int d, hnv_dtype dtype,
+                                            size_t *bytes);
+hnv_status hnv_score_plan_create_device(const int32_t *cand_ptr, const int32_t *cand_idx, int64_t n_cand,
+                                        int64_t n_members, int64_t z_rows, int d, hnv_dtype dtype, void *workspace,
+                                        size_t ws_bytes, void *stream, hnv_score_plan **out);
+
 /* Element-wise conversion between storage types on the device (FP32 ->
  * BF16 rounds to nearest even; BF16 -> FP32 is exact).  n elements. */
 hnv_status hnv_cast(const void *src, hnv_dtype src_dtype, void *dst, hnv_dtype dst_dtype,

@@ -98,6 +98,10 @@ _SIGS = {
                                                  ctypes.POINTER(ctypes.c_size_t)]),
     "hnv_score_plan_create": (ctypes.c_int, [i64p, i32p, i64, i64, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t,
                                              vp, ctypes.POINTER(vp)]),
+    "hnv_score_workspace_bytes_device": (ctypes.c_int, [i64, i64, ctypes.c_int, ctypes.c_int,
+                                                        ctypes.POINTER(ctypes.c_size_t)]),
+    "hnv_score_plan_create_device": (ctypes.c_int, [vp, vp, i64, i64, i64, ctypes.c_int, ctypes.c_int, vp,
+                                                    ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
     "hnv_score_plan_destroy": (ctypes.c_int, [vp]),
     "hnv_score_candidates": (ctypes.c_int, [vp, vp, ctypes.c_int, vp, vp]),
     "hnv_cast": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.c_int, i64, vp]),

@@ -567,7 +567,7 @@ class RefineGraph:
 class ScorePlan:
     """Candidate node sets for hyperedge-prediction features (Section 4),
     planned once on the host (``cand_ptr`` / ``cand_idx``: CSR of member node
-    ids) and kept in a device workspace."""
+    ids) or on the GPU (:meth:`from_device`) and kept in a device workspace."""
 
     def __init__(self, cand_ptr, cand_idx, z_rows: int, d: int, dtype: str = "f32", device=None):
         torch = _torch()
@@ -586,6 +586,32 @@ class ScorePlan:
                int(z_rows), self.d, dt, self.workspace.data_ptr(), self.workspace.numel(), _stream(self.device),
                ctypes.byref(h))
         self._h = h
+
+    @classmethod
+    def from_device(cls, cand_ptr, cand_idx, z_rows: int, d: int, dtype: str = "f32") -> "ScorePlan":
+        """The same plan built on the GPU from device tensors (int32
+        ``cand_ptr`` [n_cand+1] and ``cand_idx`` [n_members])."""
+        torch = _torch()
+        for t in (cand_ptr, cand_idx):
+            if t.dtype != torch.int32 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError("cand_ptr / cand_idx: contiguous int32 device tensors expected")
+        self = cls.__new__(cls)
+        self.device = cand_ptr.device
+        self.n_cand = int(cand_ptr.numel()) - 1
+        n_members = int(cand_idx.numel())
+        self.d = int(d)
+        self.dtype = dtype
+        dt = _dt(dtype)
+        need = ctypes.c_size_t()
+        with torch.cuda.device(self.device):
+            L.call("hnv_score_workspace_bytes_device", self.n_cand, n_members, self.d, dt, ctypes.byref(need))
+            self.workspace = torch.empty(need.value, dtype=torch.uint8, device=self.device)
+            h = ctypes.c_void_p()
+            L.call("hnv_score_plan_create_device", cand_ptr.data_ptr(), _ptr(cand_idx) if n_members else None,
+                   self.n_cand, n_members, int(z_rows), self.d, dt, self.workspace.data_ptr(), self.workspace.numel(),
+                   _stream(self.device), ctypes.byref(h))
+        self._h = h
+        return self
 
     def __del__(self):
         try:

@@ -629,6 +629,56 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
     return dev_recompute_reciprocals(p, l, s);
 }
 
+// Candidate-scoring plan from device arrays: the candidates are the rows of
+// one side (offsets cand_ptr, members cand_idx), tiered exactly as the host
+// score plan tiers them (small_max = kIdxRegs lanes' worth of the scoring
+// lane group, kScoreChunk members per wavefront item).
+struct ScoreDevLayout {
+    size_t off_idx = 0, off_small = 0, off_chunks = 0, off_splits = 0, off_part = 0, off_scratch = 0;
+    int32_t n_small = 0, n_chunks = 0, n_splits = 0, n_slots = 0;
+    int small_max = 0;
+    size_t scratch_bytes = 0, total = 0;
+};
+
+hnv_status score_dev_layout(int64_t n_cand, int64_t n_members, int d, hnv_dtype dtype, ScoreDevLayout &L)
+{
+    if (n_cand < 0 || n_members < 0)
+        return fail(HNV_EINVAL, "negative size");
+    if (d < 8 || d > 512 || d % 8 != 0)
+        return fail(HNV_EUNSUPPORTED, "d must be a multiple of 8 in [8, 512]");
+    if (dtype != HNV_F32 && dtype != HNV_BF16)
+        return fail(HNV_EINVAL, "unknown dtype");
+    if (n_cand >= INT_MAX || n_members >= INT_MAX)
+        return fail(HNV_EUNSUPPORTED, "candidates and members must be below 2^31");
+    int G = 1, E = 8;
+    lane_layout(d, dtype == HNV_BF16 ? 2 : 4, &G, &E);
+    L.small_max = kIdxRegs * G;
+    auto cap = [](int64_t v) { return (int32_t)std::min<int64_t>(std::max<int64_t>(v, 1), INT_MAX); };
+    L.n_small = cap(n_cand);
+    L.n_chunks = cap(std::min<int64_t>(n_members / kScoreChunk + n_members / (L.small_max + 1) + 1, n_members + 1));
+    L.n_splits = cap(n_members / (kScoreChunk + 1) + 1);
+    L.n_slots = cap(2 * (n_members / kScoreChunk) + 1);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = (off + 255) & ~size_t(255);
+        const size_t p = off;
+        off += std::max<size_t>(bytes, 8);
+        return p;
+    };
+    L.off_idx = take(4 * (size_t)n_members);
+    L.off_small = take(sizeof(Item) * (size_t)L.n_small);
+    L.off_chunks = take(sizeof(Item) * (size_t)L.n_chunks);
+    L.off_splits = take(sizeof(Split) * (size_t)L.n_splits);
+    L.off_part = take(sizeof(float) * (size_t)L.n_slots * (2 * d + 8));
+    Scratch S{};
+    if (hnv_status st = scratch_layout(n_members, n_cand, L.n_chunks, nullptr, S); st != HNV_OK)
+        return st;
+    L.scratch_bytes = S.total;
+    L.off_scratch = take(L.scratch_bytes);
+    L.total = (off + 255) & ~size_t(255);
+    return HNV_OK;
+}
+
 }  // namespace
 }  // namespace hnv
 
@@ -720,5 +770,108 @@ extern "C" hnv_status hnv_plan_create_device(const hnv_level_dev *levels, const 
         return fail(HNV_ENOMEM, "host allocation failed in hnv_plan_create_device");
     }
     *out = p;
+    return HNV_OK;
+}
+
+extern "C" hnv_status hnv_score_workspace_bytes_device(int64_t n_cand, int64_t n_members, int d, hnv_dtype dtype,
+                                                      size_t *bytes)
+{
+    clear_error();
+    if (!bytes)
+        return fail(HNV_EINVAL, "bytes is NULL");
+    ScoreDevLayout L;
+    hnv_status st = score_dev_layout(n_cand, n_members, d, dtype, L);
+    if (st == HNV_OK)
+        *bytes = L.total;
+    return st;
+}
+
+extern "C" hnv_status hnv_score_plan_create_device(const int32_t *cand_ptr, const int32_t *cand_idx, int64_t n_cand,
+                                                   int64_t n_members, int64_t z_rows, int d, hnv_dtype dtype,
+                                                   void *workspace, size_t ws_bytes, void *stream,
+                                                   hnv_score_plan **out)
+{
+    clear_error();
+    if (!out)
+        return fail(HNV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (z_rows < 0 || !cand_ptr || (n_members > 0 && !cand_idx))
+        return fail(HNV_EINVAL, "bad arguments");
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
+        return fail(HNV_EWORKSPACE, "workspace must be non-NULL and 256-byte aligned");
+    ScoreDevLayout L;
+    hnv_status st = score_dev_layout(n_cand, n_members, d, dtype, L);
+    if (st != HNV_OK)
+        return st;
+    if (L.total > ws_bytes)
+        return fail(HNV_EWORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " +
+                                        std::to_string(L.total));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(workspace);
+    Scratch S{};
+    if ((st = scratch_layout(n_members, n_cand, L.n_chunks, base + L.off_scratch, S)) != HNV_OK)
+        return st;
+    // checks: offsets (start 0, never decrease, end at n_members) and member
+    // ids in [0, z_rows); empty candidates are allowed (their rows are NaN)
+    k_fill<<<1, kThreads, 0, s>>>(S.flag, 4, 0);
+    if (n_cand > 0)
+        k_check_edges<<<grid_for(n_cand), kThreads, 0, s>>>(cand_ptr, nullptr, n_cand, n_members, 0, S.flag);
+    if (n_members > 0)
+        k_check_members<<<grid_for(n_members), kThreads, 0, s>>>(cand_ptr, cand_idx, nullptr, z_rows, n_cand,
+                                                                n_members, 0, S.flag);
+    if ((st = dev_check("candidate checks")) != HNV_OK)
+        return st;
+    int bad = 0;
+    if ((st = read_back(&bad, S.flag, sizeof(int), s)) != HNV_OK)
+        return st;
+    if (n_cand == 0) {
+        int32_t p0 = 0;
+        if ((st = read_back(&p0, cand_ptr, 4, s)) != HNV_OK)
+            return st;
+        if (p0 != 0 || n_members != 0)
+            bad |= 1;
+    }
+    if (bad & 1)
+        return fail(HNV_EINVAL, "cand_ptr must start at 0, never decrease and end at n_members");
+    if (bad & 2)
+        return fail(HNV_ERANGE, "a member id is outside [0, z_rows)");
+    // members, then the work lists as the host score plan lays them out
+    if ((st = copy_d2d(base + L.off_idx, cand_idx, 4 * (size_t)n_members, s)) != HNV_OK)
+        return st;
+    int64_t cnt[4] = {0, 0, 0, 0};
+    DevSide D{};
+    D.small = reinterpret_cast<const Item *>(base + L.off_small);
+    D.chunks = reinterpret_cast<const Item *>(base + L.off_chunks);
+    D.splits = reinterpret_cast<const Split *>(base + L.off_splits);
+    if (n_cand > 0) {
+        if ((st = tier_scan(cand_ptr, n_cand, L.small_max, kScoreChunk, S, S.counts, s)) != HNV_OK ||
+            (st = read_back(cnt, S.counts, sizeof(cnt), s)) != HNV_OK)
+            return st;
+        if (cnt[0] > L.n_small || cnt[1] > L.n_chunks || cnt[2] > L.n_splits || cnt[3] > L.n_slots)
+            return fail(HNV_EDEVICE, "work lists exceed their bounds");
+        if ((st = tier_emit(cand_ptr, n_cand, L.small_max, kScoreChunk, nullptr, 0, 0, cnt, S, D, s)) != HNV_OK)
+            return st;
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return fail(HNV_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    try {
+        auto *plan = new hnv_score_plan;
+        plan->n_cand = n_cand;
+        plan->z_rows = z_rows;
+        plan->d = d;
+        plan->dtype = dtype;
+        plan->sp.idx = reinterpret_cast<const int32_t *>(base + L.off_idx);
+        plan->sp.small = D.small;
+        plan->sp.n_small = (int32_t)cnt[0];
+        plan->sp.chunks = D.chunks;
+        plan->sp.n_chunks = (int32_t)cnt[1];
+        plan->sp.splits = D.splits;
+        plan->sp.n_splits = (int32_t)cnt[2];
+        plan->sp.partials = reinterpret_cast<float *>(base + L.off_part);
+        *out = plan;
+    } catch (const std::bad_alloc &) {
+        return fail(HNV_ENOMEM, "host allocation failed in hnv_score_plan_create_device");
+    }
     return HNV_OK;
 }

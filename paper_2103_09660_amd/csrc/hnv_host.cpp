@@ -879,7 +879,6 @@ extern "C" hnv_status hnv_plan_level_info(const hnv_plan *plan, int level, int64
 
 namespace hnv {
 
-static constexpr int kScoreChunk = 512;
 
 struct ScoreLayout {
     HostTier tier;
@@ -949,13 +948,6 @@ extern "C" hnv_status hnv_score_workspace_bytes(const int64_t *cand_ptr, int64_t
         return fail(HNV_ENOMEM, "host allocation failed in hnv_score_workspace_bytes");
     }
 }
-
-struct hnv_score_plan {
-    hnv::ScorePlan sp;
-    int64_t n_cand = 0, z_rows = 0;
-    int d = 0;
-    hnv_dtype dtype = HNV_F32;
-};
 
 extern "C" hnv_status hnv_score_plan_create(const int64_t *cand_ptr, const int32_t *cand_idx, int64_t n_cand,
                                             int64_t z_rows, int d, hnv_dtype dtype, void *workspace,

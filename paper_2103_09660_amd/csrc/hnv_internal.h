@@ -152,6 +152,8 @@ struct ScorePlan {
     float *partials = nullptr;
 };
 
+constexpr int kScoreChunk = 512;     // members per wavefront work item of the scoring kernel
+
 // Device-side pieces implemented in hnv_kernels.hip
 hnv_status dev_recompute_reciprocals(hnv_plan *p, int level, void *stream);
 hnv_status dev_check(const char *what);
@@ -159,3 +161,11 @@ hnv_status dev_score(const ScorePlan &sp, const void *z, hnv_dtype dtype, int d,
                      hipStream_t s);
 
 }  // namespace hnv
+
+// A candidate-scoring plan: the device arrays above plus the sizes.
+struct hnv_score_plan {
+    hnv::ScorePlan sp;
+    int64_t n_cand = 0, z_rows = 0;
+    int d = 0;
+    hnv_dtype dtype = HNV_F32;
+};

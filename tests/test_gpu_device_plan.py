@@ -206,3 +206,41 @@ def test_plan_build_option(H):
     _assert_same_refine(host, dev, hier, cfg.d, list(cfg.sweeps), 2)
     with pytest.raises(ValueError):
         H.Plan(hier, cfg.d, "bf16", build="somewhere")
+
+
+@pytest.mark.parametrize("dtype,d", [("bf16", 128), ("f32", 64), ("f32", 256), ("bf16", 8)])
+def test_device_score_plan_bit_identical(H, dtype, d):
+    """Candidates planned on the GPU give the host score plan's features bit
+    for bit, for every statistic; candidates include empty ones and ones long
+    enough to split."""
+    import torch
+    rng = np.random.default_rng(d)
+    n_nodes = 5000
+    sizes = np.concatenate([rng.integers(0, 6, 3000), rng.integers(60, 200, 50), [0, 1, 1500, 600]])
+    ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    idx = rng.integers(0, n_nodes, int(ptr[-1])).astype(np.int32)
+    z = torch.randn(n_nodes, d, device="cuda").to(torch.float32 if dtype == "f32" else torch.bfloat16)
+    host = H.ScorePlan(ptr, idx, n_nodes, d, dtype)
+    dev = H.ScorePlan.from_device(torch.as_tensor(ptr.astype(np.int32)).cuda(), torch.as_tensor(idx).cuda(),
+                                  n_nodes, d, dtype)
+    for op in ("variance", "mean", "min", "max"):
+        a, b = host.score(z, op), dev.score(z, op)
+        torch.cuda.synchronize()
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32)), op
+
+
+def test_device_score_plan_checks(H):
+    import torch
+    from paper_2103_09660_amd import _lib as L
+    ptr = torch.tensor([0, 2, 5], dtype=torch.int32, device="cuda")
+    with pytest.raises(H.HnvError) as ei:
+        H.ScorePlan.from_device(ptr, torch.tensor([0, 1, 2, 9, 3], dtype=torch.int32, device="cuda"), 9, 16)
+    assert ei.value.status == L.HNV_ERANGE
+    with pytest.raises(H.HnvError) as ei:
+        H.ScorePlan.from_device(torch.tensor([0, 3, 2], dtype=torch.int32, device="cuda"),
+                                torch.tensor([0, 1], dtype=torch.int32, device="cuda"), 9, 16)
+    assert ei.value.status == L.HNV_EINVAL
+    # no candidates at all
+    p = H.ScorePlan.from_device(torch.zeros(1, dtype=torch.int32, device="cuda"),
+                                torch.zeros(0, dtype=torch.int32, device="cuda"), 9, 16)
+    assert p.score(torch.zeros(9, 16, device="cuda")).shape == (0, 16)
