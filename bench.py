@@ -413,9 +413,28 @@ def cpu_baseline(O, hg, cfg, budget_s=12.0, max_sweeps=20, d=None):
         t += time.perf_counter() - t0
         n += 1
     upd = n * 2 * lv.nnz * d
-    return {"value": upd / t, "unit": "updates/s", "cores": O.threads(), "kind": "oracle",
+    cores = O.threads()
+    # one thread, one sweep at a quarter of the width (the oracle's time is
+    # linear in d): the single-core figure
+    d1 = max(8, d // 4)
+    z1 = np.ascontiguousarray(z[:, :d1])
+    O.set_threads(1)
+    t0 = time.perf_counter()
+    O.sweep(lv, z1, 0.5)
+    t1 = time.perf_counter() - t0
+    O.set_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": upd / t, "unit": "updates/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} Jacobi sweeps of the finest level ({lv.n_nodes} nodes, {lv.n_edges} hyperedges, "
-                      f"{lv.nnz} incidences) at d={d}, FP64, {t:.1f} s"}
+                      f"{lv.nnz} incidences) at d={d}, FP64, {t:.1f} s",
+            "cpu_model": model,
+            "single_thread": {"value": 2 * lv.nnz * d1 / t1, "unit": "updates/s",
+                              "sample": f"1 Jacobi sweep of the finest level at d={d1}, FP64, 1 thread, {t1:.1f} s"}}
 
 
 def oracle_errors(O, hg, cfg, zc, outs, cols=(0, 77), node_frac=0.01, node_cols=16):

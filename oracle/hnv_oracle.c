@@ -37,6 +37,17 @@ int oracle_threads(void)
 #endif
 }
 
+/* Threads for the parallel loops that follow (timing runs only). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Star-expansion neighbourhoods                                            */
 /* ------------------------------------------------------------------------ */

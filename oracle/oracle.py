@@ -64,6 +64,7 @@ def _L():
         build()
         lib = ctypes.CDLL(_LIB_PATH)
         lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_transpose.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _i64p, _i32p]
         lib.oracle_coarsen.restype = ctypes.c_int
         lib.oracle_coarsen.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _f32p, _i32p, _i32p,
@@ -86,6 +87,12 @@ def _L():
 
 def threads() -> int:
     return int(_L().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (timing only: the
+    results do not depend on it)."""
+    _L().oracle_set_threads(int(n))
 
 
 def _p(a: Optional[np.ndarray], t):
