@@ -450,11 +450,18 @@ def oracle_errors(O, hg, cfg, zc, outs, cols=(0, 77), node_frac=0.01, node_cols=
                 "max_abs": float(np.max(np.abs(got - ref))),
                 "max_abs_rel": float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))}
 
-    ref = O.refine(levels, maps, np.ascontiguousarray(zc[:, list(cols)], dtype=np.float64), list(cfg.sweeps), 0.5)
+    zcol = np.ascontiguousarray(zc[:, list(cols)], dtype=np.float64)
+    ref = O.refine(levels, maps, zcol, list(cfg.sweeps), 0.5)
     errs = {}
     for name, out in outs.items():
         got = out[:, list(cols)].float().cpu().numpy().astype(np.float64)
         errs[name] = {"columns": list(cols), "all_rows": stats(got, ref)}
+        if name == "bf16":
+            # the sweeps' own error: the oracle starts from the same BF16-rounded
+            # coarsest embedding (round to nearest even, done by torch on the CPU)
+            import torch
+            zr = torch.as_tensor(zcol.astype(np.float32)).to(torch.bfloat16).double().numpy()
+            errs[name]["all_rows_bf16_input"] = stats(got, O.refine(levels, maps, zr, list(cfg.sweeps), 0.5))
     if node_frac > 0:
         t = time.perf_counter()
         ccols = list(range(0, cfg.d, max(1, cfg.d // node_cols)))

@@ -31,7 +31,10 @@
  *   - Device work is enqueued on the caller's HIP stream (hipStream_t passed
  *     as void*; NULL = the default stream) and is asynchronous unless stated.
  *     The library allocates no device memory: it carves the caller's
- *     workspace.  A plan is not thread-safe; distinct plans are independent.
+ *     workspace.  A plan is not thread-safe, and its device calls share
+ *     scratch space in its workspace, so calls on one plan must not overlap
+ *     on the device (one stream per plan, or streams ordered by events);
+ *     distinct plans are independent and may run on different streams.
  */
 #ifndef HNV_H
 #define HNV_H

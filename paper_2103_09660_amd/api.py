@@ -109,6 +109,21 @@ class DeviceLevel:
                    torch.as_tensor(level.edge_idx).to(dev),
                    None if level.edge_w is None else torch.as_tensor(level.edge_w).to(dev))
 
+    def check(self):
+        """Types, sizes and placement of the arrays (their contents are
+        checked by the library on the device)."""
+        torch = _torch()
+        dev = self.edge_ptr.device
+        for t, dt, n, name in ((self.edge_ptr, torch.int32, self.n_edges + 1, "edge_ptr"),
+                               (self.edge_idx, torch.int32, self.nnz, "edge_idx"),
+                               (self.edge_w, torch.float32, self.n_edges, "edge_w")):
+            if t is not None and (t.dtype != dt or not t.is_contiguous() or t.device != dev or t.numel() < n
+                                  or dev.type != "cuda"):
+                raise ValueError(f"{name}: expected a contiguous {dt} GPU tensor of at least {n} elements on "
+                                 f"{dev}, got {t.dtype} {tuple(t.shape)} on {t.device}")
+        if min(self.n_nodes, self.n_edges, self.nnz) < 0:
+            raise ValueError("negative size")
+
     def to_host(self) -> HostLevel:
         return HostLevel(self.n_nodes, self.n_edges, self.edge_ptr.cpu().numpy().astype(np.int64),
                          self.edge_idx.cpu().numpy(), None if self.edge_w is None else self.edge_w.cpu().numpy())
@@ -127,9 +142,7 @@ def coarsen_level_device(level: DeviceLevel, workspace=None):
     least :func:`coarsen_workspace_bytes`) may be reused between calls."""
     torch = _torch()
     dev = level.edge_ptr.device
-    for t, dt in ((level.edge_ptr, torch.int32), (level.edge_idx, torch.int32), (level.edge_w, torch.float32)):
-        if t is not None and (t.dtype != dt or not t.is_contiguous() or t.device != dev):
-            raise ValueError("level arrays must be contiguous int32 / float32 tensors on one device")
+    level.check()
     need = coarsen_workspace_bytes(level.n_nodes, level.n_edges, level.nnz)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=dev)
@@ -161,6 +174,7 @@ def coarsen_level_features_device(level: DeviceLevel, x, workspace=None):
     edge_rep, coarse DeviceLevel, coarse features int32 [coarse n_nodes x k])."""
     torch = _torch()
     dev = level.edge_ptr.device
+    level.check()
     if x.dtype != torch.int32 or x.dim() != 2 or x.shape[0] != level.n_nodes or not x.is_contiguous() \
             or x.device != dev:
         raise ValueError("x must be a contiguous int32 [n_nodes x k] tensor on the level's device")
@@ -340,6 +354,22 @@ def _ptr(t) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
+def _check_vec(t, n: int, dtype, name: str):
+    """A device vector the kernels read or write n entries of (None passes)."""
+    if t is None:
+        return
+    if t.dtype != dtype or not t.is_contiguous() or t.device.type != "cuda" or t.numel() < n:
+        raise ValueError(f"{name}: expected a contiguous {dtype} GPU tensor of at least {n} elements, got "
+                         f"{t.dtype} {tuple(t.shape)} on {t.device}")
+
+
+def _check_sweeps(sweeps, n_levels: int) -> np.ndarray:
+    sw = np.ascontiguousarray(sweeps, dtype=np.int32)
+    if sw.ndim != 1 or len(sw) != n_levels:
+        raise ValueError(f"sweeps: one count per level expected ({n_levels}), got {len(np.atleast_1d(sw))}")
+    return sw
+
+
 class Plan:
     """A device plan over a hierarchy: the workspace (a torch uint8 tensor)
     holds every level's adjacency, work lists, maps and reciprocals."""
@@ -396,6 +426,11 @@ class Plan:
         self.n_levels = len(levels)
         if len(maps) != self.n_levels - 1:
             raise ValueError("need one map per coarsening step")
+        for x in levels:
+            x.check()
+        for l, (a, b) in enumerate(maps):
+            _check_vec(a, levels[l].n_nodes, torch.int32, f"node_rep of map {l}")
+            _check_vec(b, levels[l].n_edges, torch.int32, f"edge_rep of map {l}")
         lv = (L.HnvLevelDev * self.n_levels)(*[L.HnvLevelDev(x.n_nodes, x.n_edges, x.nnz, _ptr(x.edge_ptr),
                                                              _ptr(x.edge_idx), _ptr(x.edge_w)) for x in levels])
         mp = (L.HnvMapDev * max(len(maps), 1))(*[L.HnvMapDev(_ptr(a), _ptr(b)) for a, b in maps])
@@ -454,14 +489,22 @@ class Plan:
         return n.value, ms.value
 
     # weights ---------------------------------------------------------------
+    def _check_edge_vec(self, level: int, t, name: str):
+        _check_vec(t, self.level_info(level)[1], _torch().float32, name)
+
     def set_edge_weights(self, level: int, w):
+        self._check_edge_vec(level, w, "w")
         L.call("hnv_set_edge_weights", self._h, level, _ptr(w), _stream(self.device))
 
     def set_edge_logweights(self, level: int, theta, w_out=None):
+        self._check_edge_vec(level, theta, "theta")
+        self._check_edge_vec(level, w_out, "w_out")
         L.call("hnv_set_edge_logweights", self._h, level, _ptr(theta), _ptr(w_out), _stream(self.device))
 
     def logweight_grad(self, level: int, dw, dtheta=None):
         out = dw if dtheta is None else dtheta
+        self._check_edge_vec(level, dw, "dw")
+        self._check_edge_vec(level, out, "dtheta")
         L.call("hnv_logweight_grad", self._h, level, _ptr(dw), _ptr(out), _stream(self.device))
         return out
 
@@ -473,8 +516,7 @@ class Plan:
         self._check(z_coarsest, self.n_levels - 1, "z_coarsest")
         z_out = self.empty(0) if out is None else out
         self._check(z_out, 0, "out")
-        sw = np.ascontiguousarray(sweeps, dtype=np.int32)
-        assert len(sw) == self.n_levels
+        sw = _check_sweeps(sweeps, self.n_levels)
         res = torch.zeros(max(int(sw.sum()), 1), dtype=torch.float64, device=self.device) if residuals else None
         done = np.zeros(self.n_levels, dtype=np.int32)
         L.call("hnv_refine", self._h, z_coarsest.data_ptr(), z_out.data_ptr(), sw.ctypes.data_as(L.i32p),
@@ -494,6 +536,7 @@ class Plan:
         self._check(z_in, level + 1 if from_coarse else level, "z_in")
         z_out = self.empty(level) if out is None else out
         self._check(z_out, level, "out")
+        _check_vec(resid, 1, _torch().float64, "resid")
         L.call("hnv_sweep", self._h, level, z_in.data_ptr(), z_out.data_ptr(), float(omega), 1 if from_coarse else 0,
                _ptr(resid), _stream(self.device))
         return z_out
@@ -511,6 +554,7 @@ class Plan:
             self._check(t, level, n)
         g_out = self.empty(level) if out is None else out
         self._check(g_out, level, "out")
+        self._check_edge_vec(level, dw, "dw")
         L.call("hnv_sweep_adjoint", self._h, level, g_in.data_ptr(), g_out.data_ptr(), z_prev.data_ptr(),
                z_cur.data_ptr(), _ptr(dw), float(omega), _stream(self.device))
         return g_out
@@ -538,8 +582,7 @@ class RefineGraph:
             raise RuntimeError("turn kernel profiling off before capturing a refinement")
         plan._check(z_coarsest, plan.n_levels - 1, "z_coarsest")
         self.plan, self.z_coarsest, self.omega = plan, z_coarsest, float(omega)
-        self.sweeps = np.ascontiguousarray(sweeps, dtype=np.int32)
-        assert len(self.sweeps) == plan.n_levels
+        self.sweeps = _check_sweeps(sweeps, plan.n_levels)
         self.out = plan.empty(0)
         self.residuals = (torch.zeros(max(int(self.sweeps.sum()), 1), dtype=torch.float64, device=plan.device)
                           if residuals else None)
@@ -575,6 +618,7 @@ class ScorePlan:
         ptr = np.ascontiguousarray(np.asarray(cand_ptr), dtype=np.int64)
         idx = np.ascontiguousarray(np.asarray(cand_idx), dtype=np.int32)
         self.n_cand = len(ptr) - 1
+        self.z_rows = int(z_rows)
         self.d = int(d)
         self.dtype = dtype
         dt = _dt(dtype)
@@ -598,6 +642,7 @@ class ScorePlan:
         self = cls.__new__(cls)
         self.device = cand_ptr.device
         self.n_cand = int(cand_ptr.numel()) - 1
+        self.z_rows = int(z_rows)
         n_members = int(cand_idx.numel())
         self.d = int(d)
         self.dtype = dtype
@@ -624,10 +669,13 @@ class ScorePlan:
     def score(self, z_nodes, op: str = "variance", out=None):
         torch = _torch()
         want = torch.float32 if _dt(self.dtype) == L.HNV_F32 else torch.bfloat16
-        if z_nodes.dtype != want or not z_nodes.is_contiguous() or z_nodes.dim() != 2 or z_nodes.shape[1] != self.d:
-            raise ValueError(f"z_nodes: contiguous {want} [rows x {self.d}] expected")
+        if z_nodes.dtype != want or not z_nodes.is_contiguous() or z_nodes.dim() != 2 or \
+                z_nodes.shape[1] != self.d or z_nodes.shape[0] < self.z_rows or z_nodes.device.type != "cuda":
+            raise ValueError(f"z_nodes: contiguous {want} [>= {self.z_rows} x {self.d}] GPU tensor expected, got "
+                             f"{z_nodes.dtype} {tuple(z_nodes.shape)} on {z_nodes.device}")
         if out is None:
             out = torch.empty((self.n_cand, self.d), dtype=torch.float32, device=self.device)
+        _check_vec(out, self.n_cand * self.d, torch.float32, "out")
         L.call("hnv_score_candidates", self._h, z_nodes.data_ptr(), _SCORE_OPS[op], out.data_ptr(),
                _stream(self.device))
         return out

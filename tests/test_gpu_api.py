@@ -100,3 +100,41 @@ def test_profiling_counts_launches(setup):
     assert plan.profile_read(0, 2)[0] == 4
     plan.set_profiling(False)
     assert plan.profile_read(0)[0] == 0
+
+
+def test_binding_checks_vectors_before_calling(setup):
+    """Every device vector a kernel reads or writes is checked for type,
+    contiguity and length by the binding, so a short tensor is a ValueError
+    and never an out-of-bounds access."""
+    H, torch, hier, plan = setup
+    ne = plan.level_info(0)[1]
+    f32 = dict(dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        plan.set_edge_weights(0, torch.ones(ne - 1, **f32))
+    with pytest.raises(ValueError):
+        plan.set_edge_weights(0, torch.ones(ne, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        plan.set_edge_logweights(0, torch.zeros(2 * ne, **f32)[::2])
+    with pytest.raises(ValueError):
+        plan.set_edge_logweights(0, torch.zeros(ne, **f32), w_out=torch.zeros(ne - 1, **f32))
+    with pytest.raises(ValueError):
+        plan.logweight_grad(0, torch.zeros(ne, **f32), torch.zeros(1, **f32))
+    z0 = plan.empty(0).normal_()
+    with pytest.raises(ValueError):
+        plan.sweep(0, z0, resid=torch.zeros(1, **f32))
+    with pytest.raises(ValueError):
+        plan.sweep_adjoint(0, z0, z0, z0, dw=torch.zeros(ne - 1, **f32))
+    with pytest.raises(ValueError):
+        plan.refine(plan.empty(plan.n_levels - 1), [1] * (plan.n_levels + 1))
+    sp = H.ScorePlan(np.array([0, 2, 3]), np.array([0, 5, 7], dtype=np.int32), 10, 32)
+    with pytest.raises(ValueError):
+        sp.score(torch.zeros(9, 32, **f32))                        # fewer rows than the plan's ids need
+    with pytest.raises(ValueError):
+        sp.score(torch.zeros(10, 32, **f32), out=torch.empty(1, 32, **f32))
+    lv = H.DeviceLevel(4, 2, 4, torch.tensor([0, 2, 4], dtype=torch.int32, device="cuda"),
+                       torch.tensor([0, 1, 2], dtype=torch.int32, device="cuda"))   # one member short
+    with pytest.raises(ValueError):
+        H.coarsen_level_device(lv)
+    # valid vectors still pass
+    plan.set_edge_weights(0, torch.ones(ne, **f32))
+    assert torch.isfinite(sp.score(torch.ones(10, 32, **f32))).all()
