@@ -135,6 +135,6 @@ def test_binding_checks_vectors_before_calling(setup):
                        torch.tensor([0, 1, 2], dtype=torch.int32, device="cuda"))   # one member short
     with pytest.raises(ValueError):
         H.coarsen_level_device(lv)
-    # valid vectors still pass
-    plan.set_edge_weights(0, torch.ones(ne, **f32))
+    # valid vectors still pass (the level's own weights, so the shared plan is unchanged)
+    plan.set_edge_weights(0, torch.as_tensor(hier.levels[0].edge_w).cuda())
     assert torch.isfinite(sp.score(torch.ones(10, 32, **f32))).all()
