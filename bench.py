@@ -294,9 +294,36 @@ def run_graph_replay(H, torch, reps=50):
 
     eager = timed(lambda: plan.refine(zc, sweeps, 0.5, residuals=True, out=out))
     replay = timed(graph.replay)
-    return {"workload": f"{cfg.name}: {cfg.n_nodes} nodes, {cfg.n_edges} hyperedges, d={cfg.d}, "
+    line = {"workload": f"{cfg.name}: {cfg.n_nodes} nodes, {cfg.n_edges} hyperedges, d={cfg.d}, "
                         f"{hier.n_levels} levels x {cfg.sweeps[0]} sweeps, FP32",
             "eager_ms": eager, "graph_replay_ms": replay, "speedup": eager / replay}
+
+    # Early stop (epsilon rule): up to 100 sweeps per level, tol = 1e-4 of the
+    # first sweep's change.  Decided on the device (eager, and replayed from
+    # a graph) against a loop that reads every residual back on the host.
+    cap = [100] * hier.n_levels
+    r0 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    plan.sweep(hier.n_levels - 1, zc, 0.5, resid=r0)
+    tol = 1e-4 * r0.item()
+    _, _, done = plan.refine(zc, cap, 0.5, tol=tol)
+    es_graph = plan.capture_refine(zc, cap, 0.5, tol=tol)
+
+    def host_loop():
+        z = zc
+        for lvl in range(hier.n_levels - 1, -1, -1):
+            for k in range(cap[lvl]):
+                r = torch.zeros(1, dtype=torch.float64, device="cuda")
+                z = plan.sweep(lvl, z, 0.5, from_coarse=(k == 0 and lvl < hier.n_levels - 1), resid=r)
+                if r.item() <= tol:
+                    break
+        return z
+
+    line["early_stop"] = {"sweeps_cap": cap[0], "tol": "1e-4 x the first sweep's change",
+                          "sweeps_run": [int(x) for x in done],
+                          "device_eager_ms": timed(lambda: plan.refine(zc, cap, 0.5, tol=tol, out=out)),
+                          "device_graph_replay_ms": timed(es_graph.replay),
+                          "host_loop_ms": timed(host_loop)}
+    return line
 
 
 def run_scoring(H, torch, hg, z_out, cfg, steps):

@@ -264,13 +264,18 @@ hnv_status hnv_set_edge_logweights(hnv_plan *plan, int level, const float *theta
  *   sweeps_per_level: HOST [n_levels], index = level, each >= 0.
  *   omega: relaxation, 0 <= omega <= 1 (Algorithm 2).
  *   tol: <= 0 runs the fixed counts; > 0 also stops a level after the first
- *        sweep whose change ||Z^i - Z^{i-1}||_F is <= tol (this synchronises
- *        the stream after every sweep).
+ *        sweep whose change ||Z^i - Z^{i-1}||_F is <= tol.  The test is made
+ *        on the device: every sweep is enqueued, and once a level has
+ *        stopped its remaining sweeps return without work, so the host never
+ *        waits for a residual and the call can be captured into a HIP graph
+ *        (with sweeps_done = NULL).
  *   residuals_dev: DEVICE double [sum of sweeps_per_level] or NULL; entry k
  *        receives ||Z^i - Z^{i-1}||_F of the k-th sweep run (coarsest level
  *        first), reduced in FP64 in a fixed order.  Entries past the last
  *        sweep run (when tol stops levels early) are left untouched.
- *   sweeps_done: HOST int32 [n_levels] or NULL: sweeps actually run. */
+ *   sweeps_done: HOST int32 [n_levels] or NULL: sweeps actually run.  With
+ *        tol > 0 the counts are known on the device only, and a non-NULL
+ *        sweeps_done makes the call wait for the stream to read them. */
 hnv_status hnv_refine(hnv_plan *plan, const void *z_coarsest, void *z_finest,
                       const int32_t *sweeps_per_level, float omega, double tol,
                       double *residuals_dev, int32_t *sweeps_done, void *stream);

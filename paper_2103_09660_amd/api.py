@@ -523,13 +523,15 @@ class Plan:
                float(omega), float(tol), _ptr(res), done.ctypes.data_as(L.i32p), _stream(self.device))
         return z_out, res, done
 
-    def capture_refine(self, z_coarsest, sweeps: Sequence[int], omega: float = 0.5, residuals: bool = False):
-        """Captures one fixed-count refinement into a HIP graph (through
+    def capture_refine(self, z_coarsest, sweeps: Sequence[int], omega: float = 0.5, residuals: bool = False,
+                       tol: float = 0.0):
+        """Captures one refinement into a HIP graph (through
         torch.cuda.CUDAGraph) for launch-bound sizes: returns a RefineGraph
         whose replay() reruns every launch on the current stream, reading
         ``z_coarsest`` (the same tensor, refill it in place) and writing
-        its ``out`` (and ``residuals``) tensors."""
-        return RefineGraph(self, z_coarsest, sweeps, omega, residuals)
+        its ``out`` (and ``residuals``) tensors.  With ``tol`` > 0 the
+        early stop is decided on the device at every replay."""
+        return RefineGraph(self, z_coarsest, sweeps, omega, residuals, tol)
 
     def sweep(self, level: int, z_in, omega: float = 0.5, from_coarse: bool = False, out=None, resid=None):
         """One sweep; ``out`` may be ``z_in`` itself for an edge-first plan."""
@@ -573,15 +575,15 @@ _SCORE_OPS = {"variance": L.HNV_SCORE_VARIANCE, "mean": L.HNV_SCORE_MEAN, "min":
 
 class RefineGraph:
     """A refinement captured into a HIP graph (see Plan.capture_refine).
-    Early stop (tol) and kernel profiling synchronise with the host and are
-    not captured."""
+    Kernel profiling records host-side events and is not captured."""
 
-    def __init__(self, plan: "Plan", z_coarsest, sweeps: Sequence[int], omega: float, residuals: bool):
+    def __init__(self, plan: "Plan", z_coarsest, sweeps: Sequence[int], omega: float, residuals: bool,
+                 tol: float = 0.0):
         torch = _torch()
         if getattr(plan, "_profiling", False):
             raise RuntimeError("turn kernel profiling off before capturing a refinement")
         plan._check(z_coarsest, plan.n_levels - 1, "z_coarsest")
-        self.plan, self.z_coarsest, self.omega = plan, z_coarsest, float(omega)
+        self.plan, self.z_coarsest, self.omega, self.tol = plan, z_coarsest, float(omega), float(tol)
         self.sweeps = _check_sweeps(sweeps, plan.n_levels)
         self.out = plan.empty(0)
         self.residuals = (torch.zeros(max(int(self.sweeps.sum()), 1), dtype=torch.float64, device=plan.device)
@@ -590,16 +592,17 @@ class RefineGraph:
         side = torch.cuda.Stream(device=plan.device)
         side.wait_stream(torch.cuda.current_stream(plan.device))
         with torch.cuda.stream(side):                 # first run outside the graph
-            self._launch()
+            self._launch(self._done.ctypes.data_as(L.i32p))
         torch.cuda.current_stream(plan.device).wait_stream(side)
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            self._launch()
+            # no sweep counts: with tol they would be read back on the host
+            self._launch(None)
 
-    def _launch(self):
+    def _launch(self, done):
         L.call("hnv_refine", self.plan._h, self.z_coarsest.data_ptr(), self.out.data_ptr(),
-               self.sweeps.ctypes.data_as(L.i32p), self.omega, 0.0,
-               _ptr(self.residuals), self._done.ctypes.data_as(L.i32p), _stream(self.plan.device))
+               self.sweeps.ctypes.data_as(L.i32p), self.omega, self.tol,
+               _ptr(self.residuals), done, _stream(self.plan.device))
 
     def replay(self):
         """Reruns the captured refinement; returns (out, residuals)."""

@@ -630,6 +630,8 @@ void carve(hnv_plan *p, const std::vector<LevelShape> &shape, char *base)
     p->resid_stage = c.take<double>(2 * p->resid_stage_len);
     p->cscratch = c.take<float>(max_nodes);
     p->resid_tmp = c.take<double>(1);
+    p->ctl = c.take<SweepCtl>(1);
+    p->ctl_flags = c.take<int32_t>(2 * (int64_t)p->n_levels);
     p->ws_bytes = (c.off + 255) & ~size_t(255);
 }
 

@@ -54,6 +54,24 @@ struct DevSide {
     int32_t n_splits = 0;
 };
 
+// Device-side state of a refinement that stops a level early (Section 3.3's
+// epsilon rule) without reading residuals back on the host.  The sweeps and
+// projections of such a refinement take their input and output matrices
+// from here; the last kernel of each operation advances them, and the
+// residual of each sweep is compared with tol on the device, setting the
+// level's stop flag, after which that level's remaining sweeps do nothing.
+struct SweepCtl {
+    const void *cur;      // matrix holding the latest iterate
+    void *next;           // buffer the next operation writes
+    void *buf[2];         // the two buffers the refinement alternates between
+    double *res;          // residual of each sweep run, packed in run order, or null
+    double *res_tmp;      // [1] residual of the last sweep when res is null
+    int32_t *stop;        // [n_levels] 1 once a sweep of the level changed Z by <= tol
+    int32_t *done;        // [n_levels] sweeps run per level
+    double tol;
+    int64_t n_res;        // sweeps run so far (next index into res)
+};
+
 struct LevelPlan {
     int64_t n_nodes = 0, n_edges = 0, nnz = 0, rows = 0;
     int64_t rows_coarse = 0;         // rows of level + 1 (0 at the coarsest level)
@@ -88,6 +106,8 @@ struct hnv_plan {
     int64_t resid_stage_len = 0;
     float *cscratch = nullptr;       // [max n_nodes] per-node scalar of the reverse sweep
     double *resid_tmp = nullptr;     // [1]
+    hnv::SweepCtl *ctl = nullptr;    // [1] early-stop control (device)
+    int32_t *ctl_flags = nullptr;    // [2 x n_levels] its stop flags and sweep counts
     int panels = 1;                  // column passes of a forward sweep
     int dp = 0;                      // columns per pass
     int g_fwd = 1;                   // lanes per row in a forward pass

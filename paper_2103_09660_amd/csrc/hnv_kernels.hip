@@ -186,7 +186,31 @@ struct GatherArgs {
     int32_t resid_offset;     // first partial index of this launch
     const void *self_src;     // forward: matrix a row's own value is read from
     int32_t self_mapped;      // forward: own value read through the projection row map
+    SweepCtl *ctl;            // early-stop refinement: the matrices and the stop flag come from here
+    int32_t ctl_level;        // level of the sweep (its stop flag)
+    int32_t ctl_src_next;     // gathered rows from ctl->next (the node half of an edge-first sweep)
 };
+
+// The matrices one launch reads and writes.  Fixed ones come from the
+// arguments; in an early-stop refinement they are known on the device only:
+// the own rows and (Jacobi) the gathered rows are the latest iterate, the
+// output is the other buffer.  (Kept apart from GatherArgs, which the
+// kernels index by side at run time and so must not copy.)
+struct Mats {
+    const void *src, *self;
+    void *dst;
+};
+
+template <bool CTL>
+HNV_DEV Mats mats_of(const GatherArgs &a)
+{
+    if constexpr (CTL) {
+        const SweepCtl *c = a.ctl;
+        return Mats{a.ctl_src_next ? c->next : c->cur, c->cur, c->next};
+    } else {
+        return Mats{a.src, a.self_src, a.dst};
+    }
+}
 
 // ---------------------------------------------------------------------------
 // gathers
@@ -338,10 +362,11 @@ struct Own {
 };
 
 template <typename T, int EPL, int MODE>
-HNV_DEV void load_own(Own<T, EPL> &o, const GatherArgs &a, int64_t zrow, int64_t srow, int deg, int col)
+HNV_DEV void load_own(Own<T, EPL> &o, const GatherArgs &a, const Mats &m, int64_t zrow, int64_t srow, int deg,
+                      int col)
 {
     using S = Slice<T, EPL>;
-    o.x = S::load(static_cast<const T *>(MODE == kFwd ? a.self_src : a.src) + srow * a.ld + col);
+    o.x = S::load(static_cast<const T *>(MODE == kFwd ? m.self : m.src) + srow * a.ld + col);
     if (MODE != kFwd && deg > 0) {
         o.y = S::load(static_cast<const T *>(a.yprev) + zrow * a.ld + col);
         if (MODE == kAdjNode)
@@ -352,7 +377,8 @@ HNV_DEV void load_own(Own<T, EPL> &o, const GatherArgs &a, int64_t zrow, int64_t
 // Forward: z'_u = (1 - omega) z_u + omega r_u acc (rows with neighbours),
 // z'_u = z_u otherwise.  Returns the row's contribution to ||z' - z||^2.
 template <typename T, int EPL>
-HNV_DEV double epilogue_fwd(const GatherArgs &a, int zrow, int deg, int col, bool col_ok, float (&acc)[EPL],
+HNV_DEV double epilogue_fwd(const GatherArgs &a, void *dst, int zrow, int deg, int col, bool col_ok,
+                            float (&acc)[EPL],
                             const Own<T, EPL> &own)
 {
     if (!col_ok)
@@ -370,7 +396,7 @@ HNV_DEV double epilogue_fwd(const GatherArgs &a, int zrow, int deg, int col, boo
         for (int i = 0; i < EPL; ++i)
             o[i] = z[i];
     }
-    Slice<T, EPL>::store(static_cast<T *>(a.dst) + (int64_t)zrow * a.ld + col, o);
+    Slice<T, EPL>::store(static_cast<T *>(dst) + (int64_t)zrow * a.ld + col, o);
     double r2 = 0.0;
     if (a.resid) {
 #pragma unroll
@@ -482,9 +508,14 @@ HNV_DEV void block_resid(const GatherArgs &a, double r2)
 // main kernel: wavefront tier + lane-group tier of both sides, all panels
 // ---------------------------------------------------------------------------
 
-template <typename T, int EPL, int G, int MODE, bool FUSED>
+template <typename T, int EPL, int G, int MODE, bool FUSED, bool CTL>
 __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
 {
+    if constexpr (CTL) {
+        if (a.ctl->stop[a.ctl_level])   // the level has converged: this sweep does nothing
+            return;
+    }
+    const Mats mats = mats_of<CTL>(a);
     int b = blockIdx.x;
     const int panel = b / a.blocks_per_panel;
     b -= panel * a.blocks_per_panel;
@@ -494,7 +525,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
     const int gl = lane % G;
     const int col = panel * a.dp + gl * EPL;
     const bool col_ok = gl * EPL < a.dp;
-    const T *src = static_cast<const T *>(a.src);
+    const T *src = static_cast<const T *>(mats.src);
     float acc[EPL];
     zero(acc);
     float csum = 0.0f;
@@ -534,7 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
             if (whole && col_ok) {
                 const int64_t srow =
                     (MODE == kFwd && (FUSED || a.self_mapped)) ? (int64_t)a.rowmap[zrow] : (int64_t)zrow;
-                load_own<T, EPL, MODE>(self, a, zrow, srow, c.len, col);
+                load_own<T, EPL, MODE>(self, a, mats, zrow, srow, c.len, col);
             }
             if (use_scale)
                 gather_wave<T, EPL, G, true, kScalar>(nb, sc, a.cvec, c.start, c.len, src, a.ld, col, col_ok, lane, g,
@@ -553,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
                 }
             } else if (MODE == kFwd) {
                 if (g == 0)
-                    r2 = epilogue_fwd<T, EPL>(a, zrow, c.len, col, col_ok, acc, self);
+                    r2 = epilogue_fwd<T, EPL>(a, mats.dst, zrow, c.len, col, col_ok, acc, self);
             } else if (MODE == kAdjNode) {
                 epilogue_adj_node<T, EPL, G>(a, c.row, c.len, col, col_ok, acc, self, g == 0);
             } else {
@@ -571,7 +602,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
             Own<T, EPL> self{};
             if (valid && col_ok) {
                 const int64_t srow = (MODE == kFwd && (FUSED || a.self_mapped)) ? (int64_t)it.aux : (int64_t)zrow;
-                load_own<T, EPL, MODE>(self, a, zrow, srow, it.len, col);
+                load_own<T, EPL, MODE>(self, a, mats, zrow, srow, it.len, col);
             }
             if (rr > 0) {
                 zero(acc);
@@ -585,7 +616,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
                                                         g * G, acc, csum);
             if (MODE == kFwd) {
                 if (valid)
-                    r2 += epilogue_fwd<T, EPL>(a, zrow, it.len, col, col_ok, acc, self);
+                    r2 += epilogue_fwd<T, EPL>(a, mats.dst, zrow, it.len, col, col_ok, acc, self);
             } else if (MODE == kAdjNode) {
                 epilogue_adj_node<T, EPL, G>(a, it.row, it.len, col, col_ok, acc, self, valid);
             } else {
@@ -602,9 +633,14 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
 // row adds the row's partial slots in slot order (group g takes slots
 // g, g+Q, ...; groups combined by the xor butterfly), then applies the
 // row's epilogue.
-template <typename T, int EPL, int G, int MODE, bool FUSED>
+template <typename T, int EPL, int G, int MODE, bool FUSED, bool CTL>
 __global__ __launch_bounds__(kBlock) void k_finalize(GatherArgs a)
 {
+    if constexpr (CTL) {
+        if (a.ctl->stop[a.ctl_level])
+            return;
+    }
+    const Mats mats = mats_of<CTL>(a);
     constexpr int Q = kWave / G;
     int b = blockIdx.x;
     const int per_panel = a.nb_split[0] + a.nb_split[1];
@@ -635,7 +671,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(GatherArgs a)
         if (col_ok) {
             const int64_t srow =
                 (MODE == kFwd && (FUSED || a.self_mapped)) ? (int64_t)a.rowmap[zrow] : (int64_t)zrow;
-            load_own<T, EPL, MODE>(self, a, zrow, srow, sp.deg, col);
+            load_own<T, EPL, MODE>(self, a, mats, zrow, srow, sp.deg, col);
         }
         for (int k = g; k < sp.n_slots; k += Q) {
             const float *pp = a.partials + (int64_t)(sp.first_slot + k) * a.pstride;
@@ -662,7 +698,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(GatherArgs a)
         }
         if (MODE == kFwd) {
             if (g == 0)
-                r2 = epilogue_fwd<T, EPL>(a, zrow, sp.deg, col, col_ok, acc, self);
+                r2 = epilogue_fwd<T, EPL>(a, mats.dst, zrow, sp.deg, col, col_ok, acc, self);
         } else if (MODE == kAdjNode) {
             epilogue_adj_node<T, EPL, G>(a, sp.row, sp.deg, col, col_ok, acc, self, g == 0);
         } else {
@@ -676,11 +712,18 @@ __global__ __launch_bounds__(kBlock) void k_finalize(GatherArgs a)
 // Residual reduction, one stage: block b sums partials [b*2048, (b+1)*2048)
 // (each thread eight strided loads, all in flight at once, added in a fixed
 // order, then a tree over the block) and writes one value; the last stage
-// (a single block) writes the square root.
+// (a single block) writes the square root.  In an early-stop refinement
+// (ctl != null) nothing runs once the level has stopped, and the last stage
+// instead stores the residual at the next packed position, counts the
+// sweep, raises the level's stop flag if the residual is <= tol, and makes
+// the sweep's output the latest iterate.
 constexpr int kResidPer = kBlock * 8;
 __global__ __launch_bounds__(kBlock) void k_resid_stage(const double *__restrict__ part, int64_t n,
-                                                        double *__restrict__ out, int final_sqrt)
+                                                        double *__restrict__ out, int final_sqrt, SweepCtl *ctl,
+                                                        int level)
 {
+    if (ctl && ctl->stop[level])
+        return;
     __shared__ double s[kBlock];
     const int64_t base = (int64_t)blockIdx.x * kResidPer + threadIdx.x;
     double x[8];
@@ -696,8 +739,65 @@ __global__ __launch_bounds__(kBlock) void k_resid_stage(const double *__restrict
             s[threadIdx.x] += s[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0)
-        out[blockIdx.x] = final_sqrt ? sqrt(s[0]) : s[0];
+    if (threadIdx.x == 0) {
+        if (!final_sqrt) {
+            out[blockIdx.x] = s[0];
+        } else if (!ctl) {
+            out[0] = sqrt(s[0]);
+        } else {
+            const double r = sqrt(s[0]);
+            (ctl->res ? ctl->res + ctl->n_res : ctl->res_tmp)[0] = r;
+            ctl->n_res += 1;
+            ctl->done[level] += 1;
+            if (r <= ctl->tol)
+                ctl->stop[level] = 1;
+            void *w = ctl->next;
+            ctl->cur = w;
+            ctl->next = (w == ctl->buf[0]) ? ctl->buf[1] : ctl->buf[0];
+        }
+    }
+}
+
+// Sets up an early-stop refinement (one block): the first operation reads
+// z_in and writes first_out; stop flags and sweep counts start at zero.
+__global__ __launch_bounds__(kBlock) void k_ctl_init(SweepCtl *ctl, int32_t *flags, int n_levels, const void *z_in,
+                                                     void *first_out, void *buf0, void *buf1, double *res,
+                                                     double *res_tmp, double tol)
+{
+    for (int i = threadIdx.x; i < 2 * n_levels; i += kBlock)
+        flags[i] = 0;
+    if (threadIdx.x == 0) {
+        ctl->cur = z_in;
+        ctl->next = first_out;
+        ctl->buf[0] = buf0;
+        ctl->buf[1] = buf1;
+        ctl->res = res;
+        ctl->res_tmp = res_tmp;
+        ctl->stop = flags;
+        ctl->done = flags + n_levels;
+        ctl->tol = tol;
+        ctl->n_res = 0;
+    }
+}
+
+// After a projection (which always runs): its output is the latest iterate.
+__global__ void k_ctl_advance(SweepCtl *ctl)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        void *w = ctl->next;
+        ctl->cur = w;
+        ctl->next = (w == ctl->buf[0]) ? ctl->buf[1] : ctl->buf[0];
+    }
+}
+
+// Copies the latest iterate to out (n16 16-byte words) unless it is there.
+__global__ __launch_bounds__(kBlock) void k_ctl_result(const SweepCtl *ctl, void *out, int64_t n16)
+{
+    const uint4 *src = static_cast<const uint4 *>(ctl->cur);
+    if (src == out)
+        return;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n16; i += (int64_t)gridDim.x * kBlock)
+        static_cast<uint4 *>(out)[i] = src[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -706,10 +806,14 @@ __global__ __launch_bounds__(kBlock) void k_resid_stage(const double *__restrict
 
 // z_fine[u] = z_coarse[rowmap[u]], one lane slice per thread
 template <typename T, int EPL>
-__global__ __launch_bounds__(kBlock) void k_project(const T *__restrict__ zc, T *__restrict__ zf,
-                                                    const int32_t *__restrict__ rowmap, int64_t rows, int d)
+__global__ __launch_bounds__(kBlock) void k_project(const T *__restrict__ zc, T *__restrict__ zf, const int32_t *__restrict__ rowmap,
+                                                    int64_t rows, int d, const SweepCtl *ctl)
 {
     using S = Slice<T, EPL>;
+    if (ctl) {   // early-stop refinement: the matrices come from the control block
+        zc = static_cast<const T *>(ctl->cur);
+        zf = static_cast<T *>(ctl->next);
+    }
     const int per_row = d / EPL;
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= rows * per_row)
@@ -1205,46 +1309,46 @@ struct ProfScope {
     }
 };
 
-template <typename T, int EPL, int G, int MODE, bool FUSED>
+template <typename T, int EPL, int G, int MODE, bool FUSED, bool CTL>
 static void launch_pair(const GatherArgs &a, int panels, hipStream_t s, ProfScope *ps)
 {
     const unsigned main_blocks = (unsigned)a.blocks_per_panel * panels;
     if (ps)
         ps->begin();
     if (main_blocks)
-        k_gather<T, EPL, G, MODE, FUSED><<<main_blocks, kBlock, 0, s>>>(a);
+        k_gather<T, EPL, G, MODE, FUSED, CTL><<<main_blocks, kBlock, 0, s>>>(a);
     if (ps)
         ps->end();
     const unsigned fin_blocks = (unsigned)(a.nb_split[0] + a.nb_split[1]) * panels;
     if (fin_blocks) {
         GatherArgs f = a;
         f.resid_offset = a.resid_offset + (int32_t)main_blocks;
-        k_finalize<T, EPL, G, MODE, FUSED><<<fin_blocks, kBlock, 0, s>>>(f);
+        k_finalize<T, EPL, G, MODE, FUSED, CTL><<<fin_blocks, kBlock, 0, s>>>(f);
     }
 }
 
 // Instantiated lane layouts: BF16 always 8 elements per lane; FP32 4 per
 // lane, or 8 for full-width rows of 128 columns or more (G = 16 .. 64).
-template <typename T, int MODE, bool FUSED>
+template <typename T, int MODE, bool FUSED, bool CTL = false>
 static hnv_status dispatch_g(int G, int EPL, const GatherArgs &a, int panels, hipStream_t s, ProfScope *ps)
 {
     constexpr int E = 16 / (int)sizeof(T);
     if (EPL == E) {
         switch (G) {
-        case 1: launch_pair<T, E, 1, MODE, FUSED>(a, panels, s, ps); break;
-        case 2: launch_pair<T, E, 2, MODE, FUSED>(a, panels, s, ps); break;
-        case 4: launch_pair<T, E, 4, MODE, FUSED>(a, panels, s, ps); break;
-        case 8: launch_pair<T, E, 8, MODE, FUSED>(a, panels, s, ps); break;
-        case 16: launch_pair<T, E, 16, MODE, FUSED>(a, panels, s, ps); break;
-        case 32: launch_pair<T, E, 32, MODE, FUSED>(a, panels, s, ps); break;
-        case 64: launch_pair<T, E, 64, MODE, FUSED>(a, panels, s, ps); break;
+        case 1: launch_pair<T, E, 1, MODE, FUSED, CTL>(a, panels, s, ps); break;
+        case 2: launch_pair<T, E, 2, MODE, FUSED, CTL>(a, panels, s, ps); break;
+        case 4: launch_pair<T, E, 4, MODE, FUSED, CTL>(a, panels, s, ps); break;
+        case 8: launch_pair<T, E, 8, MODE, FUSED, CTL>(a, panels, s, ps); break;
+        case 16: launch_pair<T, E, 16, MODE, FUSED, CTL>(a, panels, s, ps); break;
+        case 32: launch_pair<T, E, 32, MODE, FUSED, CTL>(a, panels, s, ps); break;
+        case 64: launch_pair<T, E, 64, MODE, FUSED, CTL>(a, panels, s, ps); break;
         default: return fail(HNV_EUNSUPPORTED, "lane group width");
         }
     } else if (E == 4 && EPL == 8) {
         switch (G) {
-        case 16: launch_pair<T, 8, 16, MODE, FUSED>(a, panels, s, ps); break;
-        case 32: launch_pair<T, 8, 32, MODE, FUSED>(a, panels, s, ps); break;
-        case 64: launch_pair<T, 8, 64, MODE, FUSED>(a, panels, s, ps); break;
+        case 16: launch_pair<T, 8, 16, MODE, FUSED, CTL>(a, panels, s, ps); break;
+        case 32: launch_pair<T, 8, 32, MODE, FUSED, CTL>(a, panels, s, ps); break;
+        case 64: launch_pair<T, 8, 64, MODE, FUSED, CTL>(a, panels, s, ps); break;
         default: return fail(HNV_EUNSUPPORTED, "lane group width");
         }
     } else {
@@ -1256,6 +1360,9 @@ static hnv_status dispatch_g(int G, int EPL, const GatherArgs &a, int panels, hi
 template <typename T>
 static hnv_status dispatch_fwd(hnv_plan *p, bool fused, const GatherArgs &a, hipStream_t s, ProfScope *ps)
 {
+    if (a.ctl)
+        return fused ? dispatch_g<T, kFwd, true, true>(p->g_fwd, p->epl_fwd, a, p->panels, s, ps)
+                     : dispatch_g<T, kFwd, false, true>(p->g_fwd, p->epl_fwd, a, p->panels, s, ps);
     return fused ? dispatch_g<T, kFwd, true>(p->g_fwd, p->epl_fwd, a, p->panels, s, ps)
                  : dispatch_g<T, kFwd, false>(p->g_fwd, p->epl_fwd, a, p->panels, s, ps);
 }
@@ -1263,9 +1370,11 @@ static hnv_status dispatch_fwd(hnv_plan *p, bool fused, const GatherArgs &a, hip
 // One forward sweep of `level` (src -> dst); fused reads the coarser level.
 // Jacobi: both sides in one launch, every row reading src.  Edge-first:
 // hyperedge rows first (from src), then node rows, whose neighbours are the
-// new hyperedge rows in dst and whose own value still comes from src.
+// new hyperedge rows in dst and whose own value still comes from src.  With
+// ctl (an early-stop refinement) src and dst come from the control block and
+// the residual stage decides on the device whether the level goes on.
 static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, float omega, bool fused,
-                            double *resid_out, hipStream_t s)
+                            double *resid_out, hipStream_t s, SweepCtl *ctl = nullptr)
 {
     LevelPlan &L = p->lv[level];
     GatherArgs a = base_args(p, L, p->g_fwd, p->dp);
@@ -1273,7 +1382,10 @@ static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, 
     a.src = src;
     a.self_src = src;
     a.dst = dst;
-    a.resid = resid_out ? p->resid_part : nullptr;
+    a.ctl = ctl;
+    a.ctl_level = level;
+    a.ctl_src_next = 0;
+    a.resid = (resid_out || ctl) ? p->resid_part : nullptr;
     a.resid_offset = 0;
     const bool bf = p->dtype == HNV_BF16;
     hnv_status st;
@@ -1288,6 +1400,7 @@ static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, 
             return st;
         GatherArgs n = only_side(a, 1);
         n.src = dst;                      // neighbours: the hyperedge rows just written
+        n.ctl_src_next = 1;
         n.self_mapped = fused ? 1 : 0;    // own value: from the coarser level in a fused sweep
         n.resid_offset = (int32_t)((e.blocks_per_panel + e.nb_split[0]) * p->panels);
         ProfScope pn{p, s, HNV_PROF_SWEEP, level};
@@ -1295,7 +1408,7 @@ static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, 
     }
     if (st != HNV_OK)
         return st;
-    if (resid_out) {
+    if (resid_out || ctl) {
         int64_t mb = 0, fb = 0;
         forward_geometry(p, L, &mb, &fb);
         const double *in = p->resid_part;
@@ -1304,36 +1417,42 @@ static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, 
         while (n > kResidPer) {
             const int64_t nb = blocks_for(n, kResidPer);
             double *out = p->resid_stage + which * p->resid_stage_len;
-            k_resid_stage<<<(unsigned)nb, kBlock, 0, s>>>(in, n, out, 0);
+            k_resid_stage<<<(unsigned)nb, kBlock, 0, s>>>(in, n, out, 0, ctl, level);
             in = out;
             n = nb;
             which ^= 1;
         }
-        k_resid_stage<<<1, kBlock, 0, s>>>(in, n, resid_out, 1);
+        k_resid_stage<<<1, kBlock, 0, s>>>(in, n, resid_out, 1, ctl, level);
         return dev_check("residual kernels");
     }
     return HNV_OK;
 }
 
-static hnv_status run_project(hnv_plan *p, int level, const void *zc, void *zf, hipStream_t s)
+// The projection onto `level` (zc -> zf); with ctl (an early-stop
+// refinement) the matrices come from the control block, which then takes
+// the projection's output as the latest iterate.
+static hnv_status run_project(hnv_plan *p, int level, const void *zc, void *zf, hipStream_t s,
+                              SweepCtl *ctl = nullptr)
 {
     LevelPlan &L = p->lv[level];
     const int E = p->epl_full;
     const int64_t threads = L.rows * (p->d / E);
-    if (threads == 0)
-        return HNV_OK;
-    const unsigned grid = grid1d(threads, kBlock);
-    if (p->dtype == HNV_F32) {
-        if (E == 4)
-            k_project<float, 4><<<grid, kBlock, 0, s>>>(static_cast<const float *>(zc), static_cast<float *>(zf),
-                                                        L.rowmap, L.rows, p->d);
-        else
-            k_project<float, 8><<<grid, kBlock, 0, s>>>(static_cast<const float *>(zc), static_cast<float *>(zf),
-                                                        L.rowmap, L.rows, p->d);
-    } else {
-        k_project<bf16_t, 8><<<grid, kBlock, 0, s>>>(static_cast<const bf16_t *>(zc), static_cast<bf16_t *>(zf),
-                                                     L.rowmap, L.rows, p->d);
+    if (threads > 0) {
+        const unsigned grid = grid1d(threads, kBlock);
+        if (p->dtype == HNV_F32) {
+            if (E == 4)
+                k_project<float, 4><<<grid, kBlock, 0, s>>>(static_cast<const float *>(zc),
+                                                            static_cast<float *>(zf), L.rowmap, L.rows, p->d, ctl);
+            else
+                k_project<float, 8><<<grid, kBlock, 0, s>>>(static_cast<const float *>(zc),
+                                                            static_cast<float *>(zf), L.rowmap, L.rows, p->d, ctl);
+        } else {
+            k_project<bf16_t, 8><<<grid, kBlock, 0, s>>>(static_cast<const bf16_t *>(zc),
+                                                         static_cast<bf16_t *>(zf), L.rowmap, L.rows, p->d, ctl);
+        }
     }
+    if (ctl)
+        k_ctl_advance<<<1, 1, 0, s>>>(ctl);
     return dev_check("projection kernel");
 }
 
@@ -1445,6 +1564,49 @@ extern "C" hnv_status hnv_project(hnv_plan *plan, int level, const void *z_coars
     return run_project(plan, level, z_coarse, z_fine, reinterpret_cast<hipStream_t>(stream));
 }
 
+// Refinement with the epsilon rule (Section 3.3), decided on the device:
+// every sweep of every level is enqueued at once; each sweep's residual
+// stage compares its change with tol and raises the level's stop flag, after
+// which that level's remaining sweeps return at once.  The operations read
+// and write the matrices the control block names, so where the iterate ends
+// up is known on the device only; a last kernel copies it to z_finest if it
+// is not there already.  Nothing waits for the host except the optional
+// read-back of the sweep counts, so the whole refinement can be captured
+// into a graph.
+static hnv_status refine_early_stop(hnv_plan *plan, const void *z_coarsest, void *z_finest,
+                                    const int32_t *sweeps_per_level, float omega, double tol,
+                                    double *residuals_dev, int32_t *sweeps_done, hipStream_t s, void *first_out)
+{
+    const int Lc = plan->n_levels - 1;
+    k_ctl_init<<<1, kBlock, 0, s>>>(plan->ctl, plan->ctl_flags, plan->n_levels, z_coarsest, first_out, z_finest,
+                                    plan->zbuf, residuals_dev, plan->resid_tmp, tol);
+    hnv_status st = dev_check("early-stop set-up");
+    for (int l = Lc; l >= 0 && st == HNV_OK; --l) {
+        const int K = sweeps_per_level[l];
+        if (K == 0 && l < Lc)
+            st = run_project(plan, l, nullptr, nullptr, s, plan->ctl);
+        for (int k = 0; k < K && st == HNV_OK; ++k)
+            st = run_sweep(plan, l, nullptr, nullptr, omega, k == 0 && l < Lc, nullptr, s, plan->ctl);
+    }
+    if (st != HNV_OK)
+        return st;
+    const int64_t n16 = plan->lv[0].rows * plan->d * (int64_t)elem_bytes(plan) / 16;
+    if (n16 > 0)
+        k_ctl_result<<<grid1d(std::min<int64_t>(n16, 2048LL * kBlock), kBlock), kBlock, 0, s>>>(plan->ctl, z_finest,
+                                                                                                 n16);
+    if ((st = dev_check("result copy")) != HNV_OK)
+        return st;
+    if (sweeps_done) {
+        hipError_t e = hipMemcpyAsync(sweeps_done, plan->ctl_flags + plan->n_levels,
+                                      sizeof(int32_t) * plan->n_levels, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess)
+            return fail(HNV_EDEVICE, std::string("sweep-count read-back: ") + hipGetErrorString(e));
+    }
+    return HNV_OK;
+}
+
 extern "C" hnv_status hnv_refine(hnv_plan *plan, const void *z_coarsest, void *z_finest,
                                  const int32_t *sweeps_per_level, float omega, double tol, double *residuals_dev,
                                  int32_t *sweeps_done, void *stream)
@@ -1467,9 +1629,7 @@ extern "C" hnv_status hnv_refine(hnv_plan *plan, const void *z_coarsest, void *z
 
     // Operations in order: per level (coarsest first) the sweeps, or a bare
     // projection when a finer level has no sweeps.  Writes alternate between
-    // z_finest and the scratch buffer.  With fixed counts the alternation is
-    // counted back from the last operation so that it writes z_finest; with
-    // tol the count is not known ahead and a final copy may be needed.
+    // z_finest and the scratch buffer.
     int64_t n_ops = 0;
     for (int l = Lc; l >= 0; --l)
         n_ops += (sweeps_per_level[l] > 0) ? sweeps_per_level[l] : (l < Lc ? 1 : 0);
@@ -1484,14 +1644,17 @@ extern "C" hnv_status hnv_refine(hnv_plan *plan, const void *z_coarsest, void *z
         return HNV_OK;
     }
     void *bufs[2] = {z_finest, plan->zbuf};
+    if (tol > 0)
+        return refine_early_stop(plan, z_coarsest, z_finest, sweeps_per_level, omega, tol, residuals_dev,
+                                 sweeps_done, s, bufs[(n_ops - 1) % 2]);
     int64_t op = 0;
     const void *cur = z_coarsest;
-    auto target = [&](int64_t k) { return tol > 0 ? bufs[k % 2] : bufs[(n_ops - 1 - k) % 2]; };
+    // the alternation is counted back from the last operation, which writes z_finest
+    auto target = [&](int64_t k) { return bufs[(n_ops - 1 - k) % 2]; };
     int64_t resid_k = 0;
     hnv_status st = HNV_OK;
     for (int l = Lc; l >= 0; --l) {
         const int K = sweeps_per_level[l];
-        int done = 0;
         if (K == 0 && l < Lc) {
             void *out = target(op++);
             if ((st = run_project(plan, l, cur, out, s)) != HNV_OK)
@@ -1501,30 +1664,14 @@ extern "C" hnv_status hnv_refine(hnv_plan *plan, const void *z_coarsest, void *z
         for (int k = 0; k < K; ++k) {
             void *out = target(op++);
             const bool fused = (k == 0 && l < Lc);
-            double *rd = residuals_dev ? residuals_dev + resid_k : (tol > 0 ? plan->resid_tmp : nullptr);
+            double *rd = residuals_dev ? residuals_dev + resid_k : nullptr;
             if ((st = run_sweep(plan, l, cur, out, omega, fused, rd, s)) != HNV_OK)
                 return st;
             ++resid_k;
             cur = out;
-            ++done;
-            if (tol > 0) {
-                double host_r = 0.0;
-                hipError_t e = hipMemcpyAsync(&host_r, rd, sizeof(double), hipMemcpyDeviceToHost, s);
-                if (e == hipSuccess)
-                    e = hipStreamSynchronize(s);
-                if (e != hipSuccess)
-                    return fail(HNV_EDEVICE, std::string("residual read-back: ") + hipGetErrorString(e));
-                if (host_r <= tol)
-                    break;
-            }
         }
         if (sweeps_done)
-            sweeps_done[l] = done;
-    }
-    if (cur != z_finest) {
-        hipError_t e = hipMemcpyAsync(z_finest, cur, plan->lv[0].rows * plan->d * eb, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess)
-            return fail(HNV_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+            sweeps_done[l] = K;
     }
     return HNV_OK;
 }
