@@ -537,6 +537,8 @@ def main():
     ap.add_argument("--no-differentiable", action="store_true",
                     help="skip the forward + backward (reverse-mode) leg")
     ap.add_argument("--no-coarsening", action="store_true", help="skip the GPU coarsening leg")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the HIP-graph leg (the counter passes need only the sweep kernel)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -675,7 +677,7 @@ def main():
         torch.cuda.empty_cache()
     if reverse is not None:
         line["reverse"] = reverse
-    if args.config == "zipf-2m":
+    if args.config == "zipf-2m" and not args.no_graph:
         line["graph_replay"] = run_graph_replay(H, torch)
         log(f"graph replay: {line['graph_replay']}")
     if not args.no_differentiable and args.config == "zipf-2m":

@@ -265,10 +265,12 @@ hnv_status hnv_set_edge_logweights(hnv_plan *plan, int level, const float *theta
  *   omega: relaxation, 0 <= omega <= 1 (Algorithm 2).
  *   tol: <= 0 runs the fixed counts; > 0 also stops a level after the first
  *        sweep whose change ||Z^i - Z^{i-1}||_F is <= tol.  The test is made
- *        on the device: every sweep is enqueued, and once a level has
- *        stopped its remaining sweeps return without work, so the host never
- *        waits for a residual and the call can be captured into a HIP graph
- *        (with sweeps_done = NULL).
+ *        on the device: once a level has stopped, its remaining sweeps return
+ *        without work.  The host enqueues a level's sweeps in batches of 1,
+ *        2, 4, .. 16 and reads the level's stop flag between batches (a few
+ *        waits per level, none per sweep); while the stream is being
+ *        captured into a HIP graph it enqueues every sweep and never waits
+ *        (sweeps_done must then be NULL: HNV_EINVAL otherwise).
  *   residuals_dev: DEVICE double [sum of sweeps_per_level] or NULL; entry k
  *        receives ||Z^i - Z^{i-1}||_F of the k-th sweep run (coarsest level
  *        first), reduced in FP64 in a fixed order.  Entries past the last

@@ -1565,19 +1565,29 @@ extern "C" hnv_status hnv_project(hnv_plan *plan, int level, const void *z_coars
 }
 
 // Refinement with the epsilon rule (Section 3.3), decided on the device:
-// every sweep of every level is enqueued at once; each sweep's residual
-// stage compares its change with tol and raises the level's stop flag, after
-// which that level's remaining sweeps return at once.  The operations read
-// and write the matrices the control block names, so where the iterate ends
-// up is known on the device only; a last kernel copies it to z_finest if it
-// is not there already.  Nothing waits for the host except the optional
-// read-back of the sweep counts, so the whole refinement can be captured
-// into a graph.
+// each sweep's residual stage compares its change with tol and raises the
+// level's stop flag, after which that level's remaining sweeps return at
+// once.  The operations read and write the matrices the control block
+// names, so where the iterate ends up is known on the device only; a last
+// kernel copies it to z_finest if it is not there already.  Sweeps are
+// enqueued in batches of 1, 2, 4, .. kMaxStopBatch per level, and the host
+// reads the level's flag between batches only to stop enqueueing launches
+// that would do nothing: O(log K) waits per level instead of one per sweep.
+// While the stream is being captured into a graph every sweep is enqueued
+// and nothing waits for the host.
+constexpr int kMaxStopBatch = 16;
+
 static hnv_status refine_early_stop(hnv_plan *plan, const void *z_coarsest, void *z_finest,
                                     const int32_t *sweeps_per_level, float omega, double tol,
                                     double *residuals_dev, int32_t *sweeps_done, hipStream_t s, void *first_out)
 {
     const int Lc = plan->n_levels - 1;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess)
+        return fail(HNV_EDEVICE, "hipStreamIsCapturing failed");
+    const bool capturing = cap != hipStreamCaptureStatusNone;
+    if (capturing && sweeps_done)
+        return fail(HNV_EINVAL, "sweeps_done must be NULL while the stream is being captured");
     k_ctl_init<<<1, kBlock, 0, s>>>(plan->ctl, plan->ctl_flags, plan->n_levels, z_coarsest, first_out, z_finest,
                                     plan->zbuf, residuals_dev, plan->resid_tmp, tol);
     hnv_status st = dev_check("early-stop set-up");
@@ -1585,8 +1595,26 @@ static hnv_status refine_early_stop(hnv_plan *plan, const void *z_coarsest, void
         const int K = sweeps_per_level[l];
         if (K == 0 && l < Lc)
             st = run_project(plan, l, nullptr, nullptr, s, plan->ctl);
-        for (int k = 0; k < K && st == HNV_OK; ++k)
-            st = run_sweep(plan, l, nullptr, nullptr, omega, k == 0 && l < Lc, nullptr, s, plan->ctl);
+        int k = 0, batch = 1;
+        while (k < K && st == HNV_OK) {
+            for (const int end = std::min(K, k + batch); k < end && st == HNV_OK; ++k)
+                st = run_sweep(plan, l, nullptr, nullptr, omega, k == 0 && l < Lc, nullptr, s, plan->ctl);
+            if (st != HNV_OK || k >= K)
+                break;
+            if (capturing) {   // no waits in a graph: the rest of the level at once
+                batch = K;
+                continue;
+            }
+            int32_t stopped = 0;
+            hipError_t e = hipMemcpyAsync(&stopped, plan->ctl_flags + l, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(s);
+            if (e != hipSuccess)
+                return fail(HNV_EDEVICE, std::string("stop-flag read-back: ") + hipGetErrorString(e));
+            if (stopped)
+                break;
+            batch = std::min(2 * batch, kMaxStopBatch);
+        }
     }
     if (st != HNV_OK)
         return st;
