@@ -388,11 +388,14 @@ void resolve_options(const hnv_options *in, int d, hnv_dtype dtype, hnv_options 
     hnv_options o{};
     if (in)
         o = *in;
-    // FP32 rows wider than 64 columns run in 64-column passes: 16 lanes per
-    // row slice keep four rows per wavefront (measured faster than full-width
-    // rows at two per wavefront, despite reading the indices once per pass).
-    if (o.panel_cols <= 0)
-        o.panel_cols = (dtype == HNV_F32 && d > 64 && d % 64 == 0) ? 64 : d;
+    // Rows wider than 256 bytes run in passes of 256-byte column slices (64
+    // FP32 or 128 BF16 columns): 16 lanes per slice keep four rows per
+    // wavefront, measured faster than wider slices at fewer rows per
+    // wavefront despite reading the indices once per pass.
+    if (o.panel_cols <= 0) {
+        const int pc = (dtype == HNV_F32) ? 64 : 128;
+        o.panel_cols = (d > pc && d % pc == 0) ? pc : d;
+    }
     if (o.small_max <= 0)
         o.small_max = kDefaultSmallMax;
     if (o.chunk <= 0)
