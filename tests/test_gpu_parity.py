@@ -270,6 +270,56 @@ def test_refine_function_grad500k_shape_small(oracle_mod, H):
     _assert_close(th_t.grad.cpu().numpy(), ref_dw * w_dev, GRAD_TOL, "dL/dtheta")
 
 
+def test_gradients_through_every_level(oracle_mod, H):
+    """Reverse mode across the whole hierarchy: K sweeps at the coarsest
+    level, then projection and K sweeps at each finer level, every level
+    with learnable log-weights of its own; loss = <G, node rows of Z_0>.
+    The gradients of the coarsest embedding and of every level's
+    log-weights against the oracle's FP64 reverse pass composed level by
+    level (the projection adjoint at every level boundary)."""
+    import torch
+    O = oracle_mod
+    hg = random_hypergraph(14, 3000, 2000, 2, 10, weighted=True)
+    levels, maps, hier = both_hierarchies(O, H, hg, 3)
+    L = len(levels) - 1
+    d, K, omega = 16, 4, 0.5
+    plan = H.Plan(hier, d, "f32")
+    rng = np.random.default_rng(14)
+    zc = rng.standard_normal((levels[L].rows, d)).astype(np.float32)
+    thetas = [rng.uniform(-0.5, 0.5, size=lv.n_edges).astype(np.float32) for lv in levels]
+    G = rng.standard_normal((levels[0].n_nodes, d))
+    zc_t = _dev(zc).requires_grad_(True)
+    th_t = [_dev(t).requires_grad_(True) for t in thetas]
+    z = H.refine_level(zc_t, th_t[L], plan, L, K, omega, from_coarse=False, ckpt_every=2)
+    for l in range(L - 1, -1, -1):
+        z = H.refine_level(z, th_t[l], plan, l, K, omega, from_coarse=True, ckpt_every=3)
+    loss = (z[: levels[0].n_nodes] * _dev(G)).sum()
+    loss.backward()
+
+    ws = [np.exp(t.astype(np.float64)).astype(np.float32) for t in thetas]
+    states = [zc.astype(np.float64)]
+    for _ in range(K):
+        states.append(O.sweep(levels[L], states[-1], omega, 0, ws[L]))
+    zs = {L: states[-1]}
+    for l in range(L - 1, -1, -1):
+        zs[l] = O.finest_refine_vjp(levels[l], maps[l], zs[l + 1], ws[l], K, omega,
+                                    np.zeros((levels[l].rows, d)))[0]
+    g = np.zeros((levels[0].rows, d))
+    g[: levels[0].n_nodes] = G
+    dws = {}
+    for l in range(L):
+        _, g, dws[l] = O.finest_refine_vjp(levels[l], maps[l], zs[l + 1], ws[l], K, omega, g)
+    dws[L] = np.zeros(levels[L].n_edges)
+    for i in range(K, 0, -1):
+        g, dwi = O.sweep_vjp(levels[L], states[i - 1], g, omega, ws[L])
+        dws[L] += dwi
+    ref_loss = float((zs[0][: levels[0].n_nodes] * G).sum())
+    assert abs(loss.item() - ref_loss) <= 1e-5 * np.abs(zs[0][: levels[0].n_nodes] * G).sum()
+    _assert_close(_host(zc_t.grad), g, GRAD_TOL, "dL/dZ at the coarsest level")
+    for l in range(L + 1):
+        _assert_close(th_t[l].grad.cpu().numpy(), dws[l] * ws[l], GRAD_TOL, f"dL/dtheta at level {l}")
+
+
 # ---------------------------------------------------------------------------
 # full-size instances of the large workloads
 # ---------------------------------------------------------------------------
