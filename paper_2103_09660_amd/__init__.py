@@ -23,6 +23,7 @@ from .api import (  # noqa: F401
     coarsen_workspace_bytes,
     last_error,
     plan_workspace_bytes,
+    refine_hierarchy,
     refine_level,
     score_candidates,
     star_edgelist,

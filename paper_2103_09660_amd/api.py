@@ -788,3 +788,20 @@ def refine_level(z_start, theta, plan: Plan, level: int, sweeps: int, omega: flo
     if _RF is None:
         _RF = _refine_function()
     return _RF.apply(z_start, theta, plan, level, sweeps, omega, from_coarse, ckpt_every)
+
+
+def refine_hierarchy(z_coarsest, thetas, plan: Plan, sweeps: Sequence[int], omega: float = 0.5,
+                     ckpt_every: int = 5):
+    """Differentiable multi-level refinement (Section 3.3): the sweeps of the
+    coarsest level, then projection and sweeps at each finer level, one
+    :func:`refine_level` per level.  ``thetas[l]`` are level l's learnable
+    log-weights (or None to keep the plan's weights); gradients reach
+    ``z_coarsest`` and every ``thetas[l]``.  Returns the finest embedding."""
+    L = plan.n_levels - 1
+    if len(thetas) != plan.n_levels:
+        raise ValueError(f"thetas: one entry per level expected ({plan.n_levels})")
+    sw = _check_sweeps(sweeps, plan.n_levels)
+    z = refine_level(z_coarsest, thetas[L], plan, L, int(sw[L]), omega, from_coarse=False, ckpt_every=ckpt_every)
+    for lvl in range(L - 1, -1, -1):
+        z = refine_level(z, thetas[lvl], plan, lvl, int(sw[lvl]), omega, from_coarse=True, ckpt_every=ckpt_every)
+    return z

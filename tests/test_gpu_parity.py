@@ -290,9 +290,7 @@ def test_gradients_through_every_level(oracle_mod, H):
     G = rng.standard_normal((levels[0].n_nodes, d))
     zc_t = _dev(zc).requires_grad_(True)
     th_t = [_dev(t).requires_grad_(True) for t in thetas]
-    z = H.refine_level(zc_t, th_t[L], plan, L, K, omega, from_coarse=False, ckpt_every=2)
-    for l in range(L - 1, -1, -1):
-        z = H.refine_level(z, th_t[l], plan, l, K, omega, from_coarse=True, ckpt_every=3)
+    z = H.refine_hierarchy(zc_t, th_t, plan, [K] * (L + 1), omega, ckpt_every=3)
     loss = (z[: levels[0].n_nodes] * _dev(G)).sum()
     loss.backward()
 
