@@ -283,14 +283,19 @@ def run_graph_replay(H, torch, reps=50):
     out = plan.empty(0)
     graph = plan.capture_refine(zc, sweeps, 0.5, residuals=True)
 
-    def timed(fn):
+    def timed(fn, rounds=3):
+        """Mean wall time of `reps` calls, the best of `rounds` rounds (host
+        wake-up latencies make single rounds of short calls noisy)."""
         fn()
         torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(reps):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t) * 1e3 / reps
+        best = float("inf")
+        for _ in range(rounds):
+            t = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            best = min(best, (time.perf_counter() - t) * 1e3 / reps)
+        return best
 
     eager = timed(lambda: plan.refine(zc, sweeps, 0.5, residuals=True, out=out))
     replay = timed(graph.replay)
