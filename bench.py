@@ -190,7 +190,10 @@ def run_reverse(H, torch, plan, z_start, cfg, steps):
     """Reverse sweeps at the finest level (the zipf-8m workload's adjoint
     leg): cfg.adjoint_sweeps forward sweeps from z_start are kept, then as
     many reverse sweeps run from a seeded N(0,1) cotangent, accumulating the
-    hyperedge-weight gradient.  Timed over `steps` repetitions."""
+    hyperedge-weight gradient as the autograd path does (split: the per-node
+    part summed over the sweeps, gathered per hyperedge once at the end).
+    Timed over `steps` repetitions; also the same pass with the gradient
+    completed in every sweep, for comparison."""
     from synth import cotangent
     K = cfg.adjoint_sweeps
     states = [z_start]
@@ -203,32 +206,43 @@ def run_reverse(H, torch, plan, z_start, cfg, steps):
         r1 = min(rows, r0 + chunk)
         gen = torch.Generator(device="cuda").manual_seed(300 + cfg.seed + r0)
         g0[r0:r1] = torch.randn((r1 - r0, cfg.d), generator=gen, device="cuda").to(plan.torch_dtype)
-    n_edges = plan.level_info(0)[1]
+    n_nodes, n_edges, nnz = plan.level_info(0)
     dw = torch.zeros(n_edges, dtype=torch.float32, device="cuda")
+    nacc = torch.zeros(n_nodes, dtype=torch.float32, device="cuda")
     bufs = [plan.empty(0), plan.empty(0)]
 
-    def once():
+    def once(split):
         g = g0
+        if split:
+            nacc.zero_()
         for i in range(K, 0, -1):
             out = bufs[i % 2]
-            g = plan.sweep_adjoint(0, g, states[i - 1], states[i], 0.5, dw=dw, out=out)
+            g = plan.sweep_adjoint(0, g, states[i - 1], states[i], 0.5, dw=dw, out=out,
+                                   node_acc=nacc if split else None)
+        if split:
+            plan.weight_grad_finish(0, nacc, dw)
         return g
 
-    once()
-    torch.cuda.synchronize()
-    plan.set_profiling(True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        once()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1000.0 / steps
-    nn_, tn = plan.profile_read(2, 0)
-    ne_, te = plan.profile_read(3, 0)
-    plan.set_profiling(False)
-    nnz = plan.level_info(0)[2]
-    return {"reverse_sweeps": K, "ms_per_pass": ms,
-            "updates_per_s": K * 2 * nnz * cfg.d / (ms / 1000.0),
-            "reverse_node_rows_avg_ms": tn / max(nn_, 1), "reverse_hyperedge_rows_avg_ms": te / max(ne_, 1)}
+    line = {"reverse_sweeps": K}
+    for split in (True, False):
+        once(split)
+        torch.cuda.synchronize()
+        plan.set_profiling(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            once(split)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / steps
+        nn_, tn = plan.profile_read(2, 0)
+        ne_, te = plan.profile_read(3, 0)
+        plan.set_profiling(False)
+        r = {"ms_per_pass": ms, "updates_per_s": K * 2 * nnz * cfg.d / (ms / 1000.0),
+             "reverse_node_rows_avg_ms": tn / max(nn_, 1), "reverse_hyperedge_rows_avg_ms": te / max(ne_, 1)}
+        if split:
+            line.update(r)
+        else:
+            line["weight_gradient_every_sweep"] = r
+    return line
 
 
 def run_pipeline(H, torch, hier, cfg, dtype, zc, host_plan, refine_ms, host_coarsen_ms, host_plan_ms, reps=2):

@@ -304,10 +304,26 @@ hnv_status hnv_sweep(hnv_plan *plan, int level, const void *z_in, void *z_out, f
  * <g_v, y_e - zt_v> / S_v to dw_accum[e] (DEVICE float [n_edges]), where
  * zt_v = (z_v - (1-omega) y_v) / omega is node v's neighbour mean.  Needs
  * omega > 0.  All matrices [rows x d] of the plan's storage type; g_out must
- * not alias g_in. */
+ * not alias g_in.  With dw_accum = NULL, z_prev and z_cur are not read. */
 hnv_status hnv_sweep_adjoint(hnv_plan *plan, int level, const void *g_in, void *g_out,
                              const void *z_prev, const void *z_cur, float *dw_accum, float omega,
                              void *stream);
+
+/* The same reverse sweep with the weight gradient split in two, for several
+ * reverse sweeps in a row whose weight gradients add up.  The hyperedge part
+ * omega <sum_{v in e} g_v / S_v, y_e> is added to dw_accum[e] (DEVICE float
+ * [n_edges]) and the node part omega <g_v, zt_v> / S_v to node_accum[v]
+ * (DEVICE float [n_nodes], zeroed by the caller before the first sweep).
+ * hnv_weight_grad_finish then subtracts from every dw_accum[e] the sum of
+ * node_accum over the members of e.  After the finish, dw_accum holds what
+ * hnv_sweep_adjoint calls would have added over the same sweeps, up to
+ * rounding; the node part is gathered per incidence once instead of in every
+ * sweep.  g_out and the other arguments as hnv_sweep_adjoint. */
+hnv_status hnv_sweep_adjoint_split(hnv_plan *plan, int level, const void *g_in, void *g_out,
+                                   const void *z_prev, const void *z_cur, float *dw_accum, float *node_accum,
+                                   float omega, void *stream);
+hnv_status hnv_weight_grad_finish(hnv_plan *plan, int level, const float *node_accum, float *dw_accum,
+                                  void *stream);
 
 /* Reverse mode of the projection onto `level`: g_coarse[r] = sum of g_fine[u]
  * over the fine rows u with rowmap(u) = r, summed in ascending u.  Coarse

@@ -90,6 +90,8 @@ _SIGS = {
     "hnv_project": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
     "hnv_sweep": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_float, ctypes.c_int, vp, vp]),
     "hnv_sweep_adjoint": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_float, vp]),
+    "hnv_sweep_adjoint_split": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp, vp, vp, vp, ctypes.c_float, vp]),
+    "hnv_weight_grad_finish": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
     "hnv_project_adjoint": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
     "hnv_logweight_grad": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
     "hnv_plan_set_profiling": (ctypes.c_int, [vp, ctypes.c_int]),

@@ -551,15 +551,34 @@ class Plan:
         return z_out
 
     # reverse ---------------------------------------------------------------
-    def sweep_adjoint(self, level: int, g_in, z_prev, z_cur, omega: float = 0.5, dw=None, out=None):
+    def sweep_adjoint(self, level: int, g_in, z_prev, z_cur, omega: float = 0.5, dw=None, out=None,
+                      node_acc=None):
+        """Reverse mode of one sweep.  With ``dw`` the weight gradient is added
+        to it; with ``node_acc`` too (float32 [n_nodes], zeroed before the
+        first of several sweeps) it is split, and :meth:`weight_grad_finish`
+        completes ``dw`` after the last sweep."""
         for t, n in ((g_in, "g_in"), (z_prev, "z_prev"), (z_cur, "z_cur")):
             self._check(t, level, n)
         g_out = self.empty(level) if out is None else out
         self._check(g_out, level, "out")
         self._check_edge_vec(level, dw, "dw")
-        L.call("hnv_sweep_adjoint", self._h, level, g_in.data_ptr(), g_out.data_ptr(), z_prev.data_ptr(),
-               z_cur.data_ptr(), _ptr(dw), float(omega), _stream(self.device))
+        if node_acc is None:
+            L.call("hnv_sweep_adjoint", self._h, level, g_in.data_ptr(), g_out.data_ptr(), z_prev.data_ptr(),
+                   z_cur.data_ptr(), _ptr(dw), float(omega), _stream(self.device))
+        else:
+            if dw is None:
+                raise ValueError("node_acc needs dw")
+            _check_vec(node_acc, self.level_info(level)[0], _torch().float32, "node_acc")
+            L.call("hnv_sweep_adjoint_split", self._h, level, g_in.data_ptr(), g_out.data_ptr(), z_prev.data_ptr(),
+                   z_cur.data_ptr(), _ptr(dw), _ptr(node_acc), float(omega), _stream(self.device))
         return g_out
+
+    def weight_grad_finish(self, level: int, node_acc, dw):
+        """dw[e] -= sum of node_acc over the members of e (completes a split weight gradient)."""
+        _check_vec(node_acc, self.level_info(level)[0], _torch().float32, "node_acc")
+        self._check_edge_vec(level, dw, "dw")
+        L.call("hnv_weight_grad_finish", self._h, level, _ptr(node_acc), _ptr(dw), _stream(self.device))
+        return dw
 
     def project_adjoint(self, level: int, g_fine, out=None):
         self._check(g_fine, level, "g_fine")
@@ -750,8 +769,12 @@ def _refine_function():
             if theta is not None:
                 plan.set_edge_logweights(level, theta)
             g = g_out.contiguous().to(plan.torch_dtype)
-            n_edges = plan.level_info(level)[1]
+            n_nodes, n_edges, _ = plan.level_info(level)
             dw = torch.zeros(max(n_edges, 1), dtype=torch.float32, device=plan.device) if theta is not None else None
+            # the weight gradient of all K reverse sweeps, split: the per-node
+            # part is summed over the sweeps and gathered per hyperedge once
+            nacc = torch.zeros(max(n_nodes, 1), dtype=torch.float32, device=plan.device) if theta is not None \
+                else None
             bounds = ctx.ckpt_keys
             for si in range(len(bounds) - 1, 0, -1):
                 s0, s1 = bounds[si - 1], bounds[si]
@@ -765,13 +788,15 @@ def _refine_function():
                     states[i] = plan.sweep(level, states[i - 1], omega)
                 states[s1] = ckpts[s1]
                 for i in range(s1, s0, -1):
-                    g = plan.sweep_adjoint(level, g, states[i - 1], states[i], omega, dw=dw)
+                    g = plan.sweep_adjoint(level, g, states[i - 1], states[i], omega, dw=dw, node_acc=nacc)
             if K == 0 and not ctx.from_coarse:
                 gz = g
             elif ctx.from_coarse:
                 gz = plan.project_adjoint(level, g)
             else:
                 gz = g
+            if theta is not None:
+                plan.weight_grad_finish(level, nacc, dw)
             gtheta = plan.logweight_grad(level, dw)[:n_edges] if theta is not None else None
             return gz, gtheta, None, None, None, None, None, None
 

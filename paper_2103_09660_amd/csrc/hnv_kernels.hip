@@ -159,7 +159,8 @@ HNV_DEV void accumulate(float (&acc)[EPL], float s, const typename Slice<T, EPL>
 enum Mode : int {
     kFwd = 0,       // forward sweep
     kAdjNode = 1,   // reverse sweep, node rows
-    kAdjEdge = 2,   // reverse sweep, hyperedge rows
+    kAdjEdge = 2,   // reverse sweep, hyperedge rows, summing the per-node scalars of their members
+    kAdjEdgeNoSum = 3,   // reverse sweep, hyperedge rows, without that sum
 };
 
 struct GatherArgs {
@@ -179,6 +180,7 @@ struct GatherArgs {
     const void *yprev;        // reverse: sweep input y
     const void *zcur;         // reverse: sweep output z
     float *cvec;              // reverse: per-node scalar (written on node rows, read on hyperedge rows)
+    int32_t wgrad;            // reverse: weight gradient 0 none, 1 in one sweep (cvec = c), 2 split (cvec += omega c)
     float *dw;                // reverse: dL/dw accumulator or null
     float *partials;          // split-row partial sums
     int32_t pstride;
@@ -367,7 +369,8 @@ HNV_DEV void load_own(Own<T, EPL> &o, const GatherArgs &a, const Mats &m, int64_
 {
     using S = Slice<T, EPL>;
     o.x = S::load(static_cast<const T *>(MODE == kFwd ? m.self : m.src) + srow * a.ld + col);
-    if (MODE != kFwd && deg > 0) {
+    // the sweep's input and output rows serve the weight gradient only
+    if (MODE != kFwd && deg > 0 && a.wgrad != 0) {
         o.y = S::load(static_cast<const T *>(a.yprev) + zrow * a.ld + col);
         if (MODE == kAdjNode)
             o.z = S::load(static_cast<const T *>(a.zcur) + zrow * a.ld + col);
@@ -409,7 +412,8 @@ HNV_DEV double epilogue_fwd(const GatherArgs &a, void *dst, int zrow, int deg, i
 }
 
 // Reverse, node row v (side 1): g'_v = (1-omega) g_v + omega acc where acc =
-// sum_e g_e / |e|; c_v = <g_v, zt_v> / S_v with zt_v = (z_v - (1-omega) y_v) / omega.
+// sum_e g_e / |e|; c_v = <g_v, zt_v> / S_v with zt_v = (z_v - (1-omega) y_v) / omega
+// (stored, added times omega, or not formed: a.wgrad = 1, 2, 0).
 template <typename T, int EPL, int G>
 HNV_DEV void epilogue_adj_node(const GatherArgs &a, int row, int deg, int col, bool col_ok, float (&acc)[EPL],
                                const Own<T, EPL> &own, bool writer)
@@ -441,8 +445,13 @@ HNV_DEV void epilogue_adj_node(const GatherArgs &a, int row, int deg, int col, b
             S::store(static_cast<T *>(a.dst) + zrow * a.ld + col, o);
     }
     dot = group_sum<G>(dot);
-    if (writer && (threadIdx.x % G) == 0)
-        a.cvec[row] = (deg > 0) ? a.r[zrow] * dot : 0.0f;
+    if (writer && (threadIdx.x % G) == 0 && a.wgrad != 0) {
+        const float c = (deg > 0) ? a.r[zrow] * dot : 0.0f;
+        if (a.wgrad == 1)
+            a.cvec[row] = c;
+        else
+            a.cvec[row] += a.omega * c;
+    }
 }
 
 // Reverse, hyperedge row e (side 0): g'_e = (1-omega) g_e + omega w_e acc with
@@ -552,7 +561,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
     const int32_t *nb = FUSED ? Sd.cidx : Sd.idx;
 
     // In reverse mode only one side is active per launch.
-    if ((MODE == kAdjNode && side != 1) || (MODE == kAdjEdge && side != 0))
+    if ((MODE == kAdjNode && side != 1) || ((MODE == kAdjEdge || MODE == kAdjEdgeNoSum) && side != 0))
         return;
 
     if (tier == 0) {
@@ -663,7 +672,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(GatherArgs a)
     zero(acc);
     float csum = 0.0f;
     double r2 = 0.0;
-    const bool active = item < Sd.n_splits && !((MODE == kAdjNode && side != 1) || (MODE == kAdjEdge && side != 0));
+    const bool active = item < Sd.n_splits && !((MODE == kAdjNode && side != 1) ||
+                                                ((MODE == kAdjEdge || MODE == kAdjEdgeNoSum) && side != 0));
     if (active) {   // uniform over the wavefront
         const Split sp = Sd.splits[item];
         const int zrow = Sd.row_base + sp.row;
@@ -788,6 +798,32 @@ __global__ void k_ctl_advance(SweepCtl *ctl)
         ctl->cur = w;
         ctl->next = (w == ctl->buf[0]) ? ctl->buf[1] : ctl->buf[0];
     }
+}
+
+// Second half of a split weight gradient: dw[e] -= sum of node_acc over the
+// members of e.  16 lanes per hyperedge, each summing a strided share in
+// member order, combined by a fixed butterfly (reproducible).
+__global__ __launch_bounds__(kBlock) void k_wgrad_finish(const int32_t *__restrict__ ptr,
+                                                         const int32_t *__restrict__ idx,
+                                                         const float *__restrict__ node_acc, float *__restrict__ dw,
+                                                         int64_t n_edges)
+{
+    constexpr int GW = 16;
+    const int64_t e = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / GW;
+    const int gl = threadIdx.x % GW;
+    int32_t a0 = 0, a1 = 0;
+    if (e < n_edges) {   // whole lane groups share e
+        a0 = ptr[e];
+        a1 = ptr[e + 1];
+    }
+    float sum = 0.0f;
+    for (int32_t j = a0 + gl; j < a1; j += GW)
+        sum += node_acc[idx[j]];
+#pragma unroll
+    for (int off = 1; off < GW; off <<= 1)
+        sum += __shfl_xor(sum, off, kWave);
+    if (e < n_edges && gl == 0)
+        dw[e] -= sum;
 }
 
 // Copies the latest iterate to out (n16 16-byte words) unless it is there.
@@ -1704,11 +1740,47 @@ extern "C" hnv_status hnv_refine(hnv_plan *plan, const void *z_coarsest, void *z
     return HNV_OK;
 }
 
-extern "C" hnv_status hnv_sweep_adjoint(hnv_plan *plan, int level, const void *g_in, void *g_out,
-                                        const void *z_prev, const void *z_cur, float *dw_accum, float omega,
-                                        void *stream)
+// One reverse sweep of `level`.  wgrad: 0 no weight gradient (the sweep's
+// input and output rows are not read), 1 the whole gradient into dw in this
+// sweep (node rows store their scalar, hyperedge rows sum it over their
+// members), 2 split: node rows add omega times their scalar to node_acc,
+// hyperedge rows add only their own term to dw.
+static hnv_status run_adjoint(hnv_plan *plan, int level, const void *g_in, void *g_out, const void *z_prev,
+                              const void *z_cur, float *dw, float *node_acc, float omega, int wgrad, hipStream_t s)
 {
-    clear_error();
+    LevelPlan &L = plan->lv[level];
+    const int G = plan->g_full, E = plan->epl_full;
+    GatherArgs a = base_args(plan, L, G, plan->d);
+    a.omega = omega;
+    a.src = g_in;
+    a.dst = g_out;
+    a.yprev = z_prev;
+    a.zcur = z_cur;
+    a.cvec = (wgrad == 2) ? node_acc : plan->cscratch;
+    a.dw = (wgrad == 0) ? nullptr : dw;
+    a.wgrad = wgrad;
+    a.resid = nullptr;
+    // node rows first (they produce the per-node scalars), then hyperedge rows
+    const GatherArgs an = only_side(a, 1), ae = only_side(a, 0);
+    ProfScope pn{plan, s, HNV_PROF_ADJ_NODE, level}, pe{plan, s, HNV_PROF_ADJ_EDGE, level};
+    hnv_status st;
+    if (plan->dtype == HNV_F32) {
+        if ((st = dispatch_g<float, kAdjNode, false>(G, E, an, 1, s, &pn)) != HNV_OK)
+            return st;
+        st = (wgrad == 1) ? dispatch_g<float, kAdjEdge, false>(G, E, ae, 1, s, &pe)
+                          : dispatch_g<float, kAdjEdgeNoSum, false>(G, E, ae, 1, s, &pe);
+    } else {
+        if ((st = dispatch_g<bf16_t, kAdjNode, false>(G, E, an, 1, s, &pn)) != HNV_OK)
+            return st;
+        st = (wgrad == 1) ? dispatch_g<bf16_t, kAdjEdge, false>(G, E, ae, 1, s, &pe)
+                          : dispatch_g<bf16_t, kAdjEdgeNoSum, false>(G, E, ae, 1, s, &pe);
+    }
+    return st;
+}
+
+static hnv_status check_adjoint_args(hnv_plan *plan, int level, const void *g_in, void *g_out, const void *z_prev,
+                                     const void *z_cur, float omega)
+{
     hnv_status st = check_level(plan, level);
     if (st != HNV_OK)
         return st;
@@ -1720,31 +1792,52 @@ extern "C" hnv_status hnv_sweep_adjoint(hnv_plan *plan, int level, const void *g
         return fail(HNV_EINVAL, "omega must be in (0, 1] for the reverse sweep");
     if (plan->opts.order != HNV_ORDER_JACOBI)
         return fail(HNV_EUNSUPPORTED, "the reverse sweep is implemented for the Jacobi order");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    LevelPlan &L = plan->lv[level];
-    const int G = plan->g_full, E = plan->epl_full;
-    GatherArgs a = base_args(plan, L, G, plan->d);
-    a.omega = omega;
-    a.src = g_in;
-    a.dst = g_out;
-    a.yprev = z_prev;
-    a.zcur = z_cur;
-    a.cvec = plan->cscratch;
-    a.dw = dw_accum;
-    a.resid = nullptr;
-    // node rows first (they produce the per-node scalars), then hyperedge rows
-    const GatherArgs an = only_side(a, 1), ae = only_side(a, 0);
-    ProfScope pn{plan, s, HNV_PROF_ADJ_NODE, level}, pe{plan, s, HNV_PROF_ADJ_EDGE, level};
-    if (plan->dtype == HNV_F32) {
-        if ((st = dispatch_g<float, kAdjNode, false>(G, E, an, 1, s, &pn)) != HNV_OK)
-            return st;
-        st = dispatch_g<float, kAdjEdge, false>(G, E, ae, 1, s, &pe);
-    } else {
-        if ((st = dispatch_g<bf16_t, kAdjNode, false>(G, E, an, 1, s, &pn)) != HNV_OK)
-            return st;
-        st = dispatch_g<bf16_t, kAdjEdge, false>(G, E, ae, 1, s, &pe);
-    }
-    return st;
+    return HNV_OK;
+}
+
+extern "C" hnv_status hnv_sweep_adjoint(hnv_plan *plan, int level, const void *g_in, void *g_out,
+                                        const void *z_prev, const void *z_cur, float *dw_accum, float omega,
+                                        void *stream)
+{
+    clear_error();
+    hnv_status st = check_adjoint_args(plan, level, g_in, g_out, z_prev, z_cur, omega);
+    if (st != HNV_OK)
+        return st;
+    return run_adjoint(plan, level, g_in, g_out, z_prev, z_cur, dw_accum, nullptr, omega, dw_accum ? 1 : 0,
+                       reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" hnv_status hnv_sweep_adjoint_split(hnv_plan *plan, int level, const void *g_in, void *g_out,
+                                              const void *z_prev, const void *z_cur, float *dw_accum,
+                                              float *node_accum, float omega, void *stream)
+{
+    clear_error();
+    hnv_status st = check_adjoint_args(plan, level, g_in, g_out, z_prev, z_cur, omega);
+    if (st != HNV_OK)
+        return st;
+    const LevelPlan &L = plan->lv[level];
+    if ((!dw_accum && L.n_edges > 0) || (!node_accum && L.n_nodes > 0))
+        return fail(HNV_EINVAL, "dw_accum / node_accum is NULL");
+    return run_adjoint(plan, level, g_in, g_out, z_prev, z_cur, dw_accum, node_accum, omega, 2,
+                       reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" hnv_status hnv_weight_grad_finish(hnv_plan *plan, int level, const float *node_accum, float *dw_accum,
+                                             void *stream)
+{
+    clear_error();
+    hnv_status st = check_level(plan, level);
+    if (st != HNV_OK)
+        return st;
+    const LevelPlan &L = plan->lv[level];
+    if (L.n_edges == 0)
+        return HNV_OK;
+    if (!dw_accum || (!node_accum && L.n_nodes > 0))
+        return fail(HNV_EINVAL, "dw_accum / node_accum is NULL");
+    const int64_t threads = L.n_edges * 16;
+    k_wgrad_finish<<<grid1d(threads, kBlock), kBlock, 0, reinterpret_cast<hipStream_t>(stream)>>>(
+        L.side[0].ptr, L.side[0].idx, node_accum, dw_accum, L.n_edges);
+    return dev_check("weight-gradient finish");
 }
 
 extern "C" hnv_status hnv_project_adjoint(hnv_plan *plan, int level, const void *g_fine, void *g_coarse,

@@ -237,6 +237,58 @@ def test_sweep_adjoint(oracle_mod, H, seed, small_max, chunk, d):
     _assert_close(dth.cpu().numpy(), ref_dw * w_host, GRAD_TOL, "dtheta")
 
 
+@pytest.mark.parametrize("dtype,small_max,chunk", [("f32", 32, 512), ("f32", 4, 64), ("bf16", 8, 128)])
+def test_split_weight_gradient(oracle_mod, H, dtype, small_max, chunk):
+    """K reverse sweeps with the weight gradient split (per-node part summed
+    over the sweeps, gathered per hyperedge once by hnv_weight_grad_finish)
+    against the gradient completed in every sweep and against the oracle;
+    the cotangents are the same bit for bit with the gradient split, whole
+    or not requested (without it the sweep reads neither y nor z)."""
+    import torch
+    O = oracle_mod
+    hg = random_hypergraph(21, 3000, 2000, 1, 40, weighted=True)
+    levels, maps, hier = both_hierarchies(O, H, hg, 1)
+    d, K, omega = 32, 3, 0.5
+    plan = H.Plan(hier, d, dtype, options={"small_max": small_max, "chunk": chunk})
+    rng = np.random.default_rng(21)
+    theta = rng.uniform(-0.5, 0.5, size=levels[0].n_edges).astype(np.float32)
+    wt = torch.empty(levels[0].n_edges, dtype=torch.float32, device="cuda")
+    plan.set_edge_logweights(0, _dev(theta), w_out=wt)
+    w_host = wt.cpu().numpy()
+    y0 = rng.standard_normal((levels[0].rows, d)).astype(np.float32)
+    g0 = rng.standard_normal((levels[0].rows, d)).astype(np.float32)
+    states = [_dev(y0, dtype)]
+    for _ in range(K):
+        states.append(plan.sweep(0, states[-1], omega))
+    n_nodes, n_edges, _ = plan.level_info(0)
+
+    def backward(mode):
+        dw = torch.zeros(n_edges, dtype=torch.float32, device="cuda") if mode else None
+        nacc = torch.zeros(n_nodes, dtype=torch.float32, device="cuda") if mode == "split" else None
+        g = _dev(g0, dtype)
+        for i in range(K, 0, -1):
+            g = plan.sweep_adjoint(0, g, states[i - 1], states[i], omega, dw=dw, node_acc=nacc)
+        if mode == "split":
+            plan.weight_grad_finish(0, nacc, dw)
+        return g, dw
+
+    g_split, dw_split = backward("split")
+    g_whole, dw_whole = backward("whole")
+    g_none, _ = backward(None)
+    assert torch.equal(g_split, g_whole) and torch.equal(g_split, g_none)
+    assert rel_fro(dw_split.cpu().numpy(), dw_whole.cpu().numpy().astype(np.float64)) <= 1e-5
+    # the oracle on the same (stored) forward states
+    ref_dw = np.zeros(n_edges)
+    gr = (_host(_dev(g0, dtype)))
+    for i in range(K, 0, -1):
+        gr, dwi = O.sweep_vjp(levels[0], _host(states[i - 1]), gr, omega, w_host)
+        ref_dw += dwi
+    # BF16: the stored cotangents and the stored sweep output (from which the
+    # node term's neighbour mean is recovered) round at 2^-8
+    tol = GRAD_TOL if dtype == "f32" else 2 * BF16_TOL
+    _assert_close(dw_split.cpu().numpy(), ref_dw, tol, f"split dw {dtype}")
+
+
 def test_refine_function_grad500k_shape_small(oracle_mod, H):
     """Differentiable refinement (projection + 10 sweeps with learnable
     log-weights, checkpoint every 5) on a reduced instance of the
