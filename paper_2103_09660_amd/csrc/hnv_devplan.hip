@@ -74,12 +74,21 @@ __global__ __launch_bounds__(kThreads) void k_check_edge_map(const int32_t *__re
         atomicOr(flag, bad);
 }
 
-__global__ __launch_bounds__(kThreads) void k_degrees(const int32_t *__restrict__ idx, int64_t nnz,
-                                                      int32_t *__restrict__ deg)
+// CSR offsets from keys sorted ascending (keys in [0, n_keys)): ptr[v] is
+// the first position whose key is >= v, for v in [0, n_keys].  Thread j
+// (0 <= j <= n) writes the offsets of the keys in (keys[j-1], keys[j]],
+// with keys[-1] = -1 and keys[n] = n_keys, so every entry is written once
+// and keys missing from the list (rows without entries) get empty ranges.
+__global__ __launch_bounds__(kThreads) void k_offsets_sorted(const uint32_t *__restrict__ keys, int64_t n,
+                                                             int64_t n_keys, int32_t *__restrict__ ptr)
 {
     const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (j < nnz)
-        atomicAdd(deg + idx[j], 1);
+    if (j > n)
+        return;
+    const int64_t lo = (j == 0) ? -1 : (int64_t)keys[j - 1];
+    const int64_t hi = (j == n) ? n_keys : (int64_t)keys[j];
+    for (int64_t v = lo + 1; v <= hi; ++v)
+        ptr[v] = (int32_t)j;
 }
 
 __global__ __launch_bounds__(kThreads) void k_iota(int64_t n, int32_t *__restrict__ out)
@@ -272,7 +281,7 @@ LevelShape bound_shape(const hnv_level_dev &lv, const hnv_level_dev *coarse, int
 
 // Temporaries of one level's build, carved from `base` (nullptr: sizing).
 struct Scratch {
-    int32_t *inc_edge, *heads, *deg, *csc_e, *keys_out, *rows_a, *rows_b, *pieces, *cpos, *split, *spos, *slots,
+    int32_t *inc_edge, *heads, *csc_e, *keys_out, *rows_a, *rows_b, *pieces, *cpos, *split, *spos, *slots,
         *sbase, *ids_a, *ids_b;
     uint32_t *key_a, *key_b;
     Item *items;
@@ -316,7 +325,6 @@ hnv_status scratch_layout(int64_t nnz, int64_t rows, int64_t n_chunks, char *bas
     const size_t n4 = 4 * (size_t)std::max(nnz, rows + 1);
     S.inc_edge = (int32_t *)take(4 * nnz);
     S.heads = (int32_t *)take(4 * nnz);
-    S.deg = (int32_t *)take(n4);
     S.csc_e = (int32_t *)take(n4);
     S.keys_out = (int32_t *)take(n4);
     S.rows_a = (int32_t *)take(4 * (rows + 1));
@@ -548,22 +556,18 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
     if ((st = copy_d2d((void *)S0.ptr, lv.edge_ptr, 4 * (nE + 1), s)) != HNV_OK ||
         (st = copy_d2d((void *)S0.idx, lv.edge_idx, 4 * nnz, s)) != HNV_OK)
         return st;
-    // side 1: node -> hyperedges in ascending id (stable sort of incidences by node)
-    k_fill<<<grid_for(nV + 1), kThreads, 0, s>>>(S.deg, nV + 1, 0);
-    if (nnz > 0)
-        k_degrees<<<grid_for(nnz), kThreads, 0, s>>>(lv.edge_idx, nnz, S.deg);
+    // side 1: node -> hyperedges in ascending id (stable sort of incidences
+    // by node; the offsets come from the sorted node ids)
     size_t tb = S.temp_bytes;
-    if (hipcub::DeviceScan::ExclusiveSum(S.temp, tb, S.deg, const_cast<int32_t *>(S1.ptr), (int)(nV + 1), s) !=
-        hipSuccess)
-        return fail(HNV_EDEVICE, "scan of node degrees");
     if (nnz > 0) {
-        tb = S.temp_bytes;
         if (hipcub::DeviceRadixSort::SortPairs(S.temp, tb, reinterpret_cast<const uint32_t *>(lv.edge_idx),
                                                reinterpret_cast<uint32_t *>(S.keys_out), S.inc_edge, S.csc_e,
                                                (int)nnz, 0, bits_for(nV), s) != hipSuccess)
             return fail(HNV_EDEVICE, "sort of incidences by node");
         k_add_const<<<grid_for(nnz), kThreads, 0, s>>>(S.csc_e, nnz, (int32_t)nV, const_cast<int32_t *>(S1.idx));
     }
+    k_offsets_sorted<<<grid_for(nnz + 1), kThreads, 0, s>>>(reinterpret_cast<const uint32_t *>(S.keys_out), nnz, nV,
+                                                            const_cast<int32_t *>(S1.ptr));
     // projection row map, composed indices, inverse map
     if (C) {
         k_rowmap<<<grid_for(nV + nE), kThreads, 0, s>>>(lv.edge_ptr, lv.edge_idx, m->node_rep, m->edge_rep, nV, nE,
@@ -573,21 +577,16 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
             k_compose<<<grid_for(nnz), kThreads, 0, s>>>(S1.idx, L.rowmap, nnz, const_cast<int32_t *>(S1.cidx));
         }
         const int64_t rows = nV + nE, rows_c = L.rows_coarse;
-        k_fill<<<grid_for(rows_c + 1), kThreads, 0, s>>>(S.deg, rows_c + 1, 0);
         if (rows > 0) {
-            k_degrees<<<grid_for(rows), kThreads, 0, s>>>(L.rowmap, rows, S.deg);
             k_iota<<<grid_for(rows), kThreads, 0, s>>>(rows, S.rows_a);
-        }
-        tb = S.temp_bytes;
-        if (hipcub::DeviceScan::ExclusiveSum(S.temp, tb, S.deg, L.inv_ptr, (int)(rows_c + 1), s) != hipSuccess)
-            return fail(HNV_EDEVICE, "scan of the inverse map");
-        if (rows > 0) {
             tb = S.temp_bytes;
             if (hipcub::DeviceRadixSort::SortPairs(S.temp, tb, reinterpret_cast<const uint32_t *>(L.rowmap),
                                                    reinterpret_cast<uint32_t *>(S.keys_out), S.rows_a, L.inv_idx,
                                                    (int)rows, 0, bits_for(rows_c), s) != hipSuccess)
                 return fail(HNV_EDEVICE, "sort of the inverse map");
         }
+        k_offsets_sorted<<<grid_for(rows + 1), kThreads, 0, s>>>(reinterpret_cast<const uint32_t *>(S.keys_out),
+                                                                 rows, rows_c, L.inv_ptr);
     }
     if ((st = dev_check("plan arrays")) != HNV_OK)
         return st;
