@@ -475,12 +475,43 @@ def cpu_baseline(O, hg, cfg, budget_s=12.0, max_sweeps=20, d=None):
             model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": upd / t, "unit": "updates/s", "cores": cores, "kind": "oracle",
+    line = {"value": upd / t, "unit": "updates/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} Jacobi sweeps of the finest level ({lv.n_nodes} nodes, {lv.n_edges} hyperedges, "
                       f"{lv.nnz} incidences) at d={d}, FP64, {t:.1f} s",
             "cpu_model": model,
             "single_thread": {"value": 2 * lv.nnz * d1 / t1, "unit": "updates/s",
                               "sample": f"1 Jacobi sweep of the finest level at d={d1}, FP64, 1 thread, {t1:.1f} s"}}
+    if cfg.name == "zipf-2m":
+        line["single_thread_small_workloads"] = single_thread_small(O)
+    return line
+
+
+def single_thread_small(O, names=("tiny-2k", "hub-200k"), budget_s=1.0):
+    """The oracle on one thread over the finest level of the two small
+    workloads at their own widths (a fraction of a second each)."""
+    import numpy as np
+    from synth import CONFIGS, coarsest_embedding, make_hypergraph
+    out = {}
+    cores = O.threads()
+    O.set_threads(1)
+    try:
+        for name in names:
+            c = CONFIGS[name]
+            h = make_hypergraph(c)
+            lv = O.Level(h.n_nodes, h.n_edges, h.edge_ptr, h.edge_idx, h.edge_w)
+            z = np.resize(coarsest_embedding(c, 4096, c.d).astype(np.float64), (lv.rows, c.d))
+            n, t = 0, 0.0
+            while n < 1000 and t < budget_s:
+                t0 = time.perf_counter()
+                z = O.sweep(lv, z, 0.5)
+                t += time.perf_counter() - t0
+                n += 1
+            out[name] = {"value": n * 2 * lv.nnz * c.d / t, "unit": "updates/s",
+                         "sample": f"{n} Jacobi sweeps of the finest level ({lv.nnz} incidences) at d={c.d}, "
+                                   f"FP64, 1 thread, {t:.2f} s"}
+    finally:
+        O.set_threads(cores)
+    return out
 
 
 def oracle_errors(O, hg, cfg, zc, outs, cols=(0, 77), node_frac=0.01, node_cols=16):
