@@ -130,6 +130,28 @@ def run_gpu(H, torch, hier, cfg, dtype, zc_f32, steps, warmup):
     return result, out, plan
 
 
+def run_small_workloads(H, torch, steps=20, warmup=3):
+    """Plain FP32 refinement of the two small workloads (their own widths,
+    levels and sweep counts): updates/s and the sweep kernel's rate in the
+    stream model.  Both fit in the Infinity Cache, so the model can exceed
+    the HBM peak."""
+    from synth import CONFIGS, coarsest_embedding, make_hypergraph
+    out = {}
+    for name in ("tiny-2k", "hub-200k"):
+        c = CONFIGS[name]
+        h = make_hypergraph(c)
+        hier = H.Hierarchy.build(h.n_nodes, h.n_edges, h.edge_ptr, h.edge_idx, h.edge_w, c.levels)
+        zc = torch.as_tensor(coarsest_embedding(c, hier.levels[-1].rows, c.d)).cuda()
+        r, _, plan = run_gpu(H, torch, hier, c, "f32", zc, steps, warmup)
+        del plan
+        out[name] = {"workload": f"{name}: {h.n_nodes} nodes, {h.n_edges} hyperedges, {h.nnz} incidences, d={c.d}, "
+                                 f"{hier.n_levels} levels x {c.sweeps[0]} sweeps, FP32",
+                     "ms_per_step": r["ms_per_step"], "updates_per_s": r["value"],
+                     "sweep_kernel_avg_ms": r["sweep_kernel_avg_ms"],
+                     "sweep_stream_GBps": r["sweep_alg_bytes_per_launch"] / (r["sweep_kernel_avg_ms"] / 1e3) / 1e9}
+    return out
+
+
 def run_differentiable(H, torch, steps, warmup):
     """Differentiable refinement workload (500,000 nodes, 300,000 hyperedges,
     truncated Zipf(2.1) sizes on [2, 1000], d = 128 FP32): projection of a
@@ -588,7 +610,7 @@ def main():
                     help="skip the forward + backward (reverse-mode) leg")
     ap.add_argument("--no-coarsening", action="store_true", help="skip the GPU coarsening leg")
     ap.add_argument("--no-graph", action="store_true",
-                    help="skip the HIP-graph leg (the counter passes need only the sweep kernel)")
+                    help="skip the HIP-graph and small-workload legs (profiling passes need only the sweep kernels)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -730,6 +752,8 @@ def main():
     if args.config == "zipf-2m" and not args.no_graph:
         line["graph_replay"] = run_graph_replay(H, torch)
         log(f"graph replay: {line['graph_replay']}")
+        line["small_workloads"] = run_small_workloads(H, torch)
+        log(f"small workloads: {line['small_workloads']}")
     if not args.no_differentiable and args.config == "zipf-2m":
         t = time.perf_counter()
         line["differentiable"] = run_differentiable(H, torch, max(2, args.steps // 2), 1)
