@@ -143,10 +143,19 @@ def run_small_workloads(H, torch, steps=20, warmup=3):
         hier = H.Hierarchy.build(h.n_nodes, h.n_edges, h.edge_ptr, h.edge_idx, h.edge_w, c.levels)
         zc = torch.as_tensor(coarsest_embedding(c, hier.levels[-1].rows, c.d)).cuda()
         r, _, plan = run_gpu(H, torch, hier, c, "f32", zc, steps, warmup)
+        # run_gpu times with the kernel events on; at these sizes their host
+        # cost shows, so the step time is taken again without them
+        sweeps = list(c.sweeps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.refine(zc, sweeps, 0.5, residuals=True)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
         del plan
         out[name] = {"workload": f"{name}: {h.n_nodes} nodes, {h.n_edges} hyperedges, {h.nnz} incidences, d={c.d}, "
                                  f"{hier.n_levels} levels x {c.sweeps[0]} sweeps, FP32",
-                     "ms_per_step": r["ms_per_step"], "updates_per_s": r["value"],
+                     "ms_per_step": ms, "updates_per_s": r["updates_per_step"] / (ms / 1e3),
                      "sweep_kernel_avg_ms": r["sweep_kernel_avg_ms"],
                      "sweep_stream_GBps": r["sweep_alg_bytes_per_launch"] / (r["sweep_kernel_avg_ms"] / 1e3) / 1e9}
     return out
