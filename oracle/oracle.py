@@ -5,7 +5,7 @@ library is checked against.  Only ``tests/``, ``__graft_entry__.smoke()`` and
 the CPU-baseline leg of ``bench.py`` (which also reports the GPU results'
 errors against it) may import it; the product package never
 does.  It shares no code with the GPU library: the arithmetic lives in
-``hnv_oracle.c`` (plain C, FP64) and the driver below follows the paper's
+``hnv_oracle.c`` (plain C, FP64) and the Python code below follows the paper's
 three phases in order:
 
 * Algorithm 1 (Section 3.1), one coarsening step per level, featureless or

@@ -34,7 +34,7 @@ hnv_status dev_score(const ScorePlan &, const void *, hnv_dtype, int, int, float
 }
 }  // namespace hnv
 
-// --- driver ----------------------------------------------------------------
+// --- test harness: random hypergraphs through the host library -----------
 struct Graph {
     int64_t n = 0, m = 0;
     std::vector<int64_t> ptr{0};

@@ -1,4 +1,4 @@
-"""Pins for the oracle's sweep, projection and multi-level driver against the
+"""Pins for the oracle's sweep, projection and multi-level loop against the
 paper's matrix statement and against closed forms and invariants that the
 mathematics fixes (Section 3.3, Algorithm 2)."""
 import numpy as np
