@@ -626,7 +626,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: the refinement is measured on one MI355X "
-              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              "(sharding over several GPUs is described in the design notes, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
