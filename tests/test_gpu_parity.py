@@ -177,6 +177,52 @@ def test_refine_zero_and_tol(oracle_mod, H):
     torch.cuda.synchronize()
 
 
+def _hg(n_nodes, members, w=None):
+    ptr = np.concatenate([[0], np.cumsum([len(m) for m in members])]).astype(np.int64)
+    idx = np.array([v for m in members for v in m], dtype=np.int32)
+    return n_nodes, len(members), ptr, idx, None if w is None else np.asarray(w, dtype=np.float32)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_degenerate_hypergraphs(oracle_mod, H, dtype):
+    """Refinement and its reverse on degenerate inputs, against the oracle:
+    nodes without any hyperedge (every row a fixed point, a coarsening
+    step changes nothing), one hyperedge holding every node (the coarse
+    level is one node and no hyperedge), hyperedges of one member, the
+    narrowest width (d = 8) and omega = 1."""
+    import torch
+    O = oracle_mod
+    tol = F32_TOL if dtype == "f32" else BF16_TOL
+    rng = np.random.default_rng(41)
+    cases = {
+        "nodes only": _hg(7, []),
+        "one hyperedge with every node": _hg(300, [list(range(300))]),
+        "one-member hyperedges": _hg(50, [[v] for v in range(0, 50, 2)] + [[1, 3, 5], [7]], rng.uniform(0.5, 2, 27)),
+    }
+    for name, (n, m, ptr, idx, w) in cases.items():
+        levels, maps = O.build_hierarchy(n, m, ptr, idx, w, 2)
+        hier = H.Hierarchy.build(n, m, ptr, idx, w, 2)
+        for d, omega in ((8, 0.5), (16, 1.0)):
+            plan = H.Plan(hier, d, dtype)
+            zc = rng.standard_normal((levels[-1].rows, d)).astype(np.float32)
+            zr = zc if dtype == "f32" else _bf16_round(zc)
+            out, _, _ = plan.refine(_dev(zc, dtype), [2, 3, 1], omega)
+            ref = O.refine(levels, maps, zr, [2, 3, 1], omega)
+            _assert_close(_host(out), ref, tol, f"{name} d={d} omega={omega}")
+            if dtype == "f32" and omega > 0:
+                y = rng.standard_normal((levels[0].rows, d)).astype(np.float32)
+                g = rng.standard_normal((levels[0].rows, d)).astype(np.float32)
+                z = plan.sweep(0, _dev(y), omega)
+                dw = torch.zeros(max(levels[0].n_edges, 1), dtype=torch.float32, device="cuda")
+                gy = plan.sweep_adjoint(0, _dev(g), _dev(y), z, omega, dw=dw)
+                ref_gy, ref_dw = O.sweep_vjp(levels[0], y, g, omega)
+                _assert_close(_host(gy), ref_gy, F32_TOL, f"{name} reverse")
+                if levels[0].n_edges:
+                    got = dw.cpu().numpy()[: levels[0].n_edges].astype(np.float64)
+                    assert np.max(np.abs(got - ref_dw)) <= 1e-4 * max(1.0, np.max(np.abs(ref_dw))), name
+    torch.cuda.synchronize()
+
+
 def test_determinism_bitwise(oracle_mod, H):
     O = oracle_mod
     hg = tier_hypergraph(5, 8, 64)
