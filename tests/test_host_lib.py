@@ -122,3 +122,28 @@ def test_tier_inputs_are_valid_and_coarsen_identically(oracle_mod, H, seed, smal
     hg = tier_hypergraph(seed, small_max, chunk)
     H.validate_level(H.HostLevel(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w))
     both_hierarchies(oracle_mod, H, hg, 2)
+
+
+def test_size_limits_rejected_before_any_read(H):
+    """Levels of 2^31 incidences or star-expansion rows are refused with
+    HNV_EUNSUPPORTED from their sizes alone: the arrays passed are far
+    shorter than the sizes claim and are never read past their ends."""
+    import ctypes
+    from paper_2103_09660_amd import _lib as L
+    lib = L.lib()
+    big = 1 << 31
+    ptr = (ctypes.c_int64 * 2)(0, big)
+    idx = (ctypes.c_int32 * 1)(0)
+    size = ctypes.c_size_t()
+    for n_nodes, n_edges, nnz in ((4, 1, big), (big - 1, 1, 2), (big, 1, 2)):
+        lv = L.HnvLevel(n_nodes, n_edges, nnz, ctypes.cast(ptr, L.i64p), ctypes.cast(idx, L.i32p), None)
+        assert lib.hnv_validate_level(ctypes.byref(lv)) == L.HNV_EUNSUPPORTED, (n_nodes, n_edges, nnz)
+        assert "2^31" in H.last_error()
+        assert lib.hnv_plan_workspace_bytes(ctypes.byref(lv), None, 1, 64, 0, None,
+                                            ctypes.byref(size)) == L.HNV_EUNSUPPORTED
+        # the GPU coarsening's sizing refuses them before it queries any device
+        assert lib.hnv_coarsen_workspace_bytes(n_nodes, n_edges, nnz, ctypes.byref(size)) == L.HNV_EUNSUPPORTED
+    # a small valid level passes the same checks
+    lv = L.HnvLevel(4, 1, 2, ctypes.cast((ctypes.c_int64 * 2)(0, 2), L.i64p),
+                    ctypes.cast((ctypes.c_int32 * 2)(0, 1), L.i32p), None)
+    assert lib.hnv_validate_level(ctypes.byref(lv)) == L.HNV_OK
