@@ -34,6 +34,7 @@
 #include <climits>
 #include <string>
 
+#include "hnv_grid.h"
 #include "hnv_internal.h"
 #include "hnv_level_check.h"
 
@@ -316,7 +317,7 @@ __global__ __launch_bounds__(kThreads) void k_rowsum(const int32_t *__restrict__
                                                      int64_t *__restrict__ sq)
 {
     constexpr int U = members_in_flight<NC>();
-    const int64_t r = (int64_t)blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+    const int64_t r = linear_block() * (kThreads / kWave) + threadIdx.x / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     if (r >= n_rows || (limit && r >= *limit))
         return;
@@ -478,7 +479,7 @@ __global__ __launch_bounds__(kThreads) void k_qscore(const int32_t *__restrict__
 inline int pieces_for(int k) { return k <= 256 ? 1 : k <= 512 ? 2 : k <= 1024 ? 4 : k <= 2048 ? 8 : 0; }
 
 template <int NC>
-void launch_edge_features(unsigned grid, hipStream_t st, const int32_t *ptr, const int32_t *idx,
+void launch_edge_features(dim3 grid, hipStream_t st, const int32_t *ptr, const int32_t *idx,
                           const int32_t *inc_edge, const int32_t *x, int k, int64_t n_edges, int64_t nnz,
                           int32_t *fsum, int64_t *fsq, double *q, unsigned long long *bestq)
 {
@@ -489,7 +490,7 @@ void launch_edge_features(unsigned grid, hipStream_t st, const int32_t *ptr, con
 }
 
 template <int NC>
-void launch_group_sums(unsigned grid, hipStream_t st, const int32_t *gptr, const int32_t *gnodes, const int32_t *x,
+void launch_group_sums(dim3 grid, hipStream_t st, const int32_t *gptr, const int32_t *gnodes, const int32_t *x,
                        int k, int64_t n_rows, const int64_t *limit, int32_t *out)
 {
     k_rowsum<false, NC><<<grid, kThreads, 0, st>>>(gptr, gnodes, x, k, n_rows, limit, out, nullptr);
@@ -755,7 +756,7 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
             int64_t *fsq = reinterpret_cast<int64_t *>(base + L.fsq);
             double *q = reinterpret_cast<double *>(base + L.q);
             unsigned long long *bestq = reinterpret_cast<unsigned long long *>(base + L.bestq);
-            const unsigned wave_grid = (unsigned)((n_edges + kThreads / kWave - 1) / (kThreads / kWave));
+            const dim3 wave_grid = fold_grid((n_edges + kThreads / kWave - 1) / (kThreads / kWave));
             k_fill<<<grid_for(2 * (int64_t)nV), kThreads, 0, s>>>(reinterpret_cast<int32_t *>(bestq),
                                                                    2 * (int64_t)nV, 0);
             switch (pieces_for(k)) {
@@ -810,7 +811,7 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
         if (hipcub::DeviceScan::ExclusiveSum(temp, tb, gcount, gptr, nV + 1, s) != hipSuccess)
             return fail(HNV_EDEVICE, "scan of group sizes");
         k_group_fill<<<grid_for(nV), kThreads, 0, s>>>(node_rep, gptr, n_nodes, gcur, gnodes);
-        const unsigned wave_grid = (unsigned)((n_nodes + kThreads / kWave - 1) / (kThreads / kWave));
+        const dim3 wave_grid = fold_grid((n_nodes + kThreads / kWave - 1) / (kThreads / kWave));
         switch (pieces_for(k)) {
         case 1: launch_group_sums<1>(wave_grid, s, gptr, gnodes, x, k, n_nodes, sizes, c_x); break;
         case 2: launch_group_sums<2>(wave_grid, s, gptr, gnodes, x, k, n_nodes, sizes, c_x); break;

@@ -34,6 +34,7 @@
 #include <cmath>
 #include <string>
 
+#include "hnv_grid.h"
 #include "hnv_internal.h"
 
 #define HNV_DEV __device__ __forceinline__
@@ -191,6 +192,7 @@ struct GatherArgs {
     SweepCtl *ctl;            // early-stop refinement: the matrices and the stop flag come from here
     int32_t ctl_level;        // level of the sweep (its stop flag)
     int32_t ctl_src_next;     // gathered rows from ctl->next (the node half of an edge-first sweep)
+    int64_t n_blocks;         // blocks of this launch (the grid may hold padding blocks past them)
 };
 
 // The matrices one launch reads and writes.  Fixed ones come from the
@@ -493,7 +495,7 @@ HNV_DEV void epilogue_adj_edge(const GatherArgs &a, int row, int deg, int col, b
 // block-level residual reduction (FP64, fixed order)
 // ---------------------------------------------------------------------------
 
-HNV_DEV void block_resid(const GatherArgs &a, double r2)
+HNV_DEV void block_resid(const GatherArgs &a, double r2, int64_t lb)
 {
     if (!a.resid)
         return;
@@ -509,7 +511,7 @@ HNV_DEV void block_resid(const GatherArgs &a, double r2)
         double s = 0.0;
         for (int i = 0; i < kWavesPerBlock; ++i)
             s += wsum[i];
-        a.resid[a.resid_offset + blockIdx.x] = s;
+        a.resid[a.resid_offset + lb] = s;
     }
 }
 
@@ -520,12 +522,15 @@ HNV_DEV void block_resid(const GatherArgs &a, double r2)
 template <typename T, int EPL, int G, int MODE, bool FUSED, bool CTL>
 __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
 {
+    const int64_t lb = linear_block();
+    if (lb >= a.n_blocks)
+        return;
     if constexpr (CTL) {
         if (a.ctl->stop[a.ctl_level])   // the level has converged: this sweep does nothing
             return;
     }
     const Mats mats = mats_of<CTL>(a);
-    int b = blockIdx.x;
+    int b = (int)lb;
     const int panel = b / a.blocks_per_panel;
     b -= panel * a.blocks_per_panel;
     const int lane = threadIdx.x % kWave;
@@ -635,7 +640,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
         }
     }
     if (MODE == kFwd)
-        block_resid(a, r2);
+        block_resid(a, r2, lb);
 }
 
 // Finalize rows that were split over several wavefronts: one wavefront per
@@ -645,13 +650,16 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
 template <typename T, int EPL, int G, int MODE, bool FUSED, bool CTL>
 __global__ __launch_bounds__(kBlock) void k_finalize(GatherArgs a)
 {
+    const int64_t lb = linear_block();
+    if (lb >= a.n_blocks)
+        return;
     if constexpr (CTL) {
         if (a.ctl->stop[a.ctl_level])
             return;
     }
     const Mats mats = mats_of<CTL>(a);
     constexpr int Q = kWave / G;
-    int b = blockIdx.x;
+    int b = (int)lb;
     const int per_panel = a.nb_split[0] + a.nb_split[1];
     const int panel = b / per_panel;
     b -= panel * per_panel;
@@ -716,7 +724,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(GatherArgs a)
         }
     }
     if (MODE == kFwd)
-        block_resid(a, r2);
+        block_resid(a, r2, lb);
 }
 
 // Residual reduction, one stage: block b sums partials [b*2048, (b+1)*2048)
@@ -809,7 +817,7 @@ __global__ __launch_bounds__(kBlock) void k_wgrad_finish(const int32_t *__restri
                                                          int64_t n_edges)
 {
     constexpr int GW = 16;
-    const int64_t e = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / GW;
+    const int64_t e = (linear_block() * kBlock + threadIdx.x) / GW;
     const int gl = threadIdx.x % GW;
     int32_t a0 = 0, a1 = 0;
     if (e < n_edges) {   // whole lane groups share e
@@ -851,7 +859,7 @@ __global__ __launch_bounds__(kBlock) void k_project(const T *__restrict__ zc, T 
         zf = static_cast<T *>(ctl->next);
     }
     const int per_row = d / EPL;
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t t = linear_block() * kBlock + threadIdx.x;
     if (t >= rows * per_row)
         return;
     const int64_t u = t / per_row;
@@ -868,7 +876,7 @@ __global__ __launch_bounds__(kBlock) void k_project_adj(const T *__restrict__ gf
                                                         const int32_t *__restrict__ inv_ptr,
                                                         const int32_t *__restrict__ inv_idx, int64_t rows_c, int d)
 {
-    const int64_t r = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t r = linear_block() * kWavesPerBlock + threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
     const int g = lane / G, gl = lane % G;
     const int col = gl * EPL;
@@ -1030,7 +1038,10 @@ __global__ __launch_bounds__(kBlock) void k_score(ScoreArgs a)
     const T *z = static_cast<const T *>(a.z);
     Stat<EPL> st;
     stat_init(st, OP);
-    int b = blockIdx.x;
+    const int64_t lb = linear_block();
+    if (lb >= (int64_t)a.nb_chunk + a.nb_small)
+        return;
+    int b = (int)lb;
     if (b < a.nb_chunk) {
         const int item = b * kWavesPerBlock + (int)(threadIdx.x / kWave);
         if (item >= a.n_chunks)
@@ -1128,7 +1139,7 @@ template <int EPL, int G, int OP>
 __global__ __launch_bounds__(kBlock) void k_score_final(ScoreArgs a)
 {
     constexpr int Q = kWave / G;
-    const int item = blockIdx.x * kWavesPerBlock + (int)(threadIdx.x / kWave);
+    const int64_t item = linear_block() * kWavesPerBlock + (int)(threadIdx.x / kWave);
     if (item >= a.n_splits)
         return;   // uniform over the wavefront
     const int lane = threadIdx.x % kWave;
@@ -1164,7 +1175,7 @@ __global__ __launch_bounds__(kBlock) void k_recip_nodes(const int32_t *__restric
                                                         const float *__restrict__ w, int64_t n_nodes,
                                                         int64_t row_base_edges, float *__restrict__ r)
 {
-    const int64_t v = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t v = linear_block() * kWavesPerBlock + threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
     if (v >= n_nodes)
         return;
@@ -1231,7 +1242,7 @@ __global__ __launch_bounds__(kBlock) void k_mul(const float *__restrict__ a, con
 __global__ __launch_bounds__(kBlock) void k_cast_f32_bf16(const float *__restrict__ src, bf16_t *__restrict__ dst,
                                                           int64_t n)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i = linear_block() * kBlock + threadIdx.x;
     if (i < n)
         dst[i] = (bf16_t)to_bf16(src[i]);
 }
@@ -1239,7 +1250,7 @@ __global__ __launch_bounds__(kBlock) void k_cast_f32_bf16(const float *__restric
 __global__ __launch_bounds__(kBlock) void k_cast_bf16_f32(const bf16_t *__restrict__ src, float *__restrict__ dst,
                                                           int64_t n)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i = linear_block() * kBlock + threadIdx.x;
     if (i < n)
         dst[i] = __uint_as_float((uint32_t)src[i] << 16);
 }
@@ -1263,7 +1274,7 @@ hnv_status dev_recompute_reciprocals(hnv_plan *p, int level, void *stream)
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     LevelPlan &L = p->lv[level];
     if (L.n_nodes > 0)
-        k_recip_nodes<<<grid1d(L.n_nodes, kWavesPerBlock), kBlock, 0, s>>>(L.side[1].ptr, L.side[1].idx, L.w,
+        k_recip_nodes<<<fold_grid(blocks_for(L.n_nodes, kWavesPerBlock)), kBlock, 0, s>>>(L.side[1].ptr, L.side[1].idx, L.w,
                                                                              L.n_nodes, L.n_nodes, L.r);
     if (L.n_edges > 0)
         k_recip_edges<<<grid1d(L.n_edges, kBlock), kBlock, 0, s>>>(L.side[0].ptr, L.n_edges, L.n_nodes, L.r);
@@ -1348,18 +1359,22 @@ struct ProfScope {
 template <typename T, int EPL, int G, int MODE, bool FUSED, bool CTL>
 static void launch_pair(const GatherArgs &a, int panels, hipStream_t s, ProfScope *ps)
 {
-    const unsigned main_blocks = (unsigned)a.blocks_per_panel * panels;
+    const int64_t main_blocks = (int64_t)a.blocks_per_panel * panels;
     if (ps)
         ps->begin();
-    if (main_blocks)
-        k_gather<T, EPL, G, MODE, FUSED, CTL><<<main_blocks, kBlock, 0, s>>>(a);
+    if (main_blocks) {
+        GatherArgs m = a;
+        m.n_blocks = main_blocks;
+        k_gather<T, EPL, G, MODE, FUSED, CTL><<<fold_grid(main_blocks), kBlock, 0, s>>>(m);
+    }
     if (ps)
         ps->end();
-    const unsigned fin_blocks = (unsigned)(a.nb_split[0] + a.nb_split[1]) * panels;
+    const int64_t fin_blocks = (int64_t)(a.nb_split[0] + a.nb_split[1]) * panels;
     if (fin_blocks) {
         GatherArgs f = a;
         f.resid_offset = a.resid_offset + (int32_t)main_blocks;
-        k_finalize<T, EPL, G, MODE, FUSED, CTL><<<fin_blocks, kBlock, 0, s>>>(f);
+        f.n_blocks = fin_blocks;
+        k_finalize<T, EPL, G, MODE, FUSED, CTL><<<fold_grid(fin_blocks), kBlock, 0, s>>>(f);
     }
 }
 
@@ -1474,7 +1489,7 @@ static hnv_status run_project(hnv_plan *p, int level, const void *zc, void *zf, 
     const int E = p->epl_full;
     const int64_t threads = L.rows * (p->d / E);
     if (threads > 0) {
-        const unsigned grid = grid1d(threads, kBlock);
+        const dim3 grid = fold_grid(blocks_for(threads, kBlock));
         if (p->dtype == HNV_F32) {
             if (E == 4)
                 k_project<float, 4><<<grid, kBlock, 0, s>>>(static_cast<const float *>(zc),
@@ -1835,7 +1850,7 @@ extern "C" hnv_status hnv_weight_grad_finish(hnv_plan *plan, int level, const fl
     if (!dw_accum || (!node_accum && L.n_nodes > 0))
         return fail(HNV_EINVAL, "dw_accum / node_accum is NULL");
     const int64_t threads = L.n_edges * 16;
-    k_wgrad_finish<<<grid1d(threads, kBlock), kBlock, 0, reinterpret_cast<hipStream_t>(stream)>>>(
+    k_wgrad_finish<<<fold_grid(blocks_for(threads, kBlock)), kBlock, 0, reinterpret_cast<hipStream_t>(stream)>>>(
         L.side[0].ptr, L.side[0].idx, node_accum, dw_accum, L.n_edges);
     return dev_check("weight-gradient finish");
 }
@@ -1854,9 +1869,10 @@ extern "C" hnv_status hnv_project_adjoint(hnv_plan *plan, int level, const void 
         return fail(HNV_EINVAL, "g_fine / g_coarse NULL or not 16-byte aligned");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int G = plan->g_full, E = plan->epl_full;
-    const unsigned blocks = grid1d(L.rows_coarse, kWavesPerBlock);
-    if (blocks == 0)
+    const int64_t n_blocks = blocks_for(L.rows_coarse, kWavesPerBlock);
+    if (n_blocks == 0)
         return HNV_OK;
+    const dim3 blocks = fold_grid(n_blocks);
 #define HNV_PADJ(TT, EE, GG)                                                                                     \
     k_project_adj<TT, EE, GG><<<blocks, kBlock, 0, s>>>(static_cast<const TT *>(g_fine), static_cast<TT *>(g_coarse), \
                                                         L.inv_ptr, L.inv_idx, L.rows_coarse, plan->d)
@@ -1898,11 +1914,11 @@ extern "C" hnv_status hnv_cast(const void *src, hnv_dtype src_dtype, void *dst, 
         return HNV_OK;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (src_dtype == HNV_F32 && dst_dtype == HNV_BF16)
-        k_cast_f32_bf16<<<grid1d(n, kBlock), kBlock, 0, s>>>(static_cast<const float *>(src),
-                                                             static_cast<bf16_t *>(dst), n);
+        k_cast_f32_bf16<<<fold_grid(blocks_for(n, kBlock)), kBlock, 0, s>>>(static_cast<const float *>(src),
+                                                                            static_cast<bf16_t *>(dst), n);
     else if (src_dtype == HNV_BF16 && dst_dtype == HNV_F32)
-        k_cast_bf16_f32<<<grid1d(n, kBlock), kBlock, 0, s>>>(static_cast<const bf16_t *>(src),
-                                                             static_cast<float *>(dst), n);
+        k_cast_bf16_f32<<<fold_grid(blocks_for(n, kBlock)), kBlock, 0, s>>>(static_cast<const bf16_t *>(src),
+                                                                            static_cast<float *>(dst), n);
     else if (src_dtype == dst_dtype) {
         hipError_t e = hipMemcpyAsync(dst, src, n * (src_dtype == HNV_BF16 ? 2 : 4), hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess)
@@ -1969,12 +1985,12 @@ namespace hnv {
 // Launches the scoring kernels on a plan that hnv_host.cpp built and
 // uploaded (see hnv_score_candidates there).
 template <typename T, int EPL, int G, int OP>
-static void launch_score(const ScoreArgs &a, unsigned grid, unsigned fgrid, hipStream_t s)
+static void launch_score(const ScoreArgs &a, int64_t grid, int64_t fgrid, hipStream_t s)
 {
     if (grid)
-        k_score<T, EPL, G, OP><<<grid, kBlock, 0, s>>>(a);
+        k_score<T, EPL, G, OP><<<fold_grid(grid), kBlock, 0, s>>>(a);
     if (fgrid)
-        k_score_final<EPL, G, OP><<<fgrid, kBlock, 0, s>>>(a);
+        k_score_final<EPL, G, OP><<<fold_grid(fgrid), kBlock, 0, s>>>(a);
 }
 
 hnv_status dev_score(const ScorePlan &sp, const void *z, hnv_dtype dtype, int d, int op, float *out,
@@ -1998,8 +2014,8 @@ hnv_status dev_score(const ScorePlan &sp, const void *z, hnv_dtype dtype, int d,
     a.out = out;
     a.partials = sp.partials;
     a.pstride = 2 * d + 8;
-    const unsigned grid = (unsigned)(a.nb_chunk + a.nb_small);
-    const unsigned fgrid = (unsigned)blocks_for(sp.n_splits, kWavesPerBlock);
+    const int64_t grid = (int64_t)a.nb_chunk + a.nb_small;
+    const int64_t fgrid = blocks_for(sp.n_splits, kWavesPerBlock);
 #define HNV_SCORE(TT, EE, GG)                                                   \
     do {                                                                        \
         switch (op) {                                                           \
