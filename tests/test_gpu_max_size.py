@@ -93,3 +93,91 @@ def test_index_range_limit(oracle_mod):
         got_dw = dw[e0:e1].cpu().numpy()[inner_edges]
         err = np.max(np.abs(got_dw - ref_dw[inner_edges])) / np.max(np.abs(ref_dw[inner_edges]))
         assert err <= 1e-4, f"weight gradient at node {a}: {err:.3e}"
+
+
+def test_index_range_limit_two_levels(oracle_mod):
+    """The same scale through the GPU coarsening, the fused projection sweep
+    and the projection adjoint.  Level 0 adds to the band a partition of
+    the nodes into blocks of B, one heavier hyperedge per block (ids first),
+    so that by the featureless rule every node joins its block's hyperedge:
+    the coarse level has one node per block, the block hyperedges are
+    removed and each band hyperedge keeps the one or two blocks it touches.
+    That coarse level is small enough for the oracle; the GPU coarsening
+    must produce it exactly, and the refinement of both levels must match
+    the oracle on windows of level 0."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2103_09660_amd as H
+    O = oracle_mod
+    B, M = 100, 198_000
+    n = B * M
+    eb = n - K + 1                         # band hyperedges
+    nnz = M * B + eb * K
+    assert nnz < 2 ** 31 - 1
+    print(f"two levels: {n} nodes, {M} block + {eb} band hyperedges, {nnz} incidences", flush=True)
+    dev = torch.device("cuda")
+    i32 = dict(dtype=torch.int32, device=dev)
+    ptr = torch.cat([torch.arange(M, **i32) * B, M * B + torch.arange(eb + 1, **i32) * K])
+    idx = torch.cat([torch.arange(n, **i32),
+                     (torch.arange(eb, **i32)[:, None] + torch.arange(K, **i32)[None, :]).reshape(-1)])
+    w = torch.cat([torch.full((M,), 2.0, device=dev), torch.ones(eb, device=dev)])
+    lv0 = H.DeviceLevel(n, M + eb, nnz, ptr, idx, w)
+    print("coarsening", flush=True)
+    nrep, erep, lv1 = H.coarsen_level_device(lv0)
+    # the coarse level by the featureless rule, written out
+    assert torch.equal(nrep, torch.arange(n, **i32) // B)
+    assert torch.equal(erep, torch.cat([torch.full((M,), -1, **i32), torch.arange(eb, **i32)]))
+    first = torch.arange(eb, **i32) // B
+    last = (torch.arange(eb, **i32) + K - 1) // B
+    two = last != first
+    sizes = 1 + two.to(torch.int32)
+    assert (lv1.n_nodes, lv1.n_edges, lv1.nnz) == (M, eb, int(sizes.sum().item()))
+    assert torch.equal(lv1.edge_ptr, torch.cat([torch.zeros(1, **i32), torch.cumsum(sizes, 0).to(torch.int32)]))
+    members = torch.stack([first, torch.where(two, last, first)], 1).reshape(-1)
+    keep = torch.stack([torch.ones_like(two), two], 1).reshape(-1)
+    assert torch.equal(lv1.edge_idx, members[keep])
+    assert torch.equal(lv1.edge_w, torch.ones(eb, device=dev))
+    print("plan", flush=True)
+    plan = H.Plan.from_device([lv0, lv1], [(nrep, erep)], D, "f32", options={"chunk": 64})
+    rows1 = M + eb
+    zc = _z0(torch.arange(rows1, device=dev) * 3 + 1, torch)
+    out, _, _ = plan.refine(zc, [1, 1], OMEGA)
+    print("projection adjoint", flush=True)
+    gf = _z0(torch.arange(n + M + eb, device=dev) * 5 + 2, torch)
+    gc = plan.project_adjoint(0, gf)
+    rowmap = torch.cat([torch.arange(n, device=dev) // B,            # node v -> its block
+                        torch.arange(M, device=dev),                  # a removed block hyperedge -> its block
+                        M + torch.arange(eb, device=dev)])            # a band hyperedge -> its coarse row
+    ref_gc = torch.zeros(rows1, D, dtype=torch.float64, device=dev).index_add_(0, rowmap, gf.double())
+    assert float((gc.double() - ref_gc).abs().max() / ref_gc.abs().max()) <= 1e-5
+    torch.cuda.synchronize()
+    # the oracle: the coarse level as written out above, one sweep there, then windows of level 0
+    print("oracle, coarse level", flush=True)
+    f, l, t = first.cpu().numpy(), last.cpu().numpy(), two.cpu().numpy()
+    c_ptr = np.concatenate([[0], np.cumsum(1 + t)]).astype(np.int64)
+    c_idx = np.stack([f, np.where(t, l, f)], 1).reshape(-1)[np.stack([np.ones_like(t), t], 1).reshape(-1)]
+    z1 = O.sweep(O.Level(M, eb, c_ptr, c_idx.astype(np.int32), np.ones(eb, np.float32)),
+                 zc.cpu().numpy(), OMEGA)
+    outn = out.cpu().numpy()
+    Wb = 4                                   # window: 4 blocks of nodes
+    for blk in (0, M // 2, M - Wb):
+        a, wn = blk * B, Wb * B
+        print(f"window at node {a}", flush=True)
+        e0, e1 = a, min(a + wn - K + 1, eb)  # band hyperedges inside the window
+        blocks = np.arange(blk, blk + Wb)
+        h_ptr = np.arange(Wb + 1, dtype=np.int64) * B
+        b_ptr = Wb * B + np.arange(e1 - e0 + 1, dtype=np.int64) * K
+        lw_idx = np.concatenate([np.arange(wn), (np.arange(e1 - e0)[:, None] + np.arange(K)[None, :]).ravel()])
+        lw = O.Level(wn, Wb + e1 - e0, np.concatenate([h_ptr, b_ptr[1:]]), lw_idx.astype(np.int32),
+                     np.concatenate([np.full(Wb, 2.0), np.ones(e1 - e0)]).astype(np.float32))
+        # start values: level 0 rows projected from the swept coarse level
+        start = np.concatenate([z1[(a + np.arange(wn)) // B], z1[blocks], z1[M + np.arange(e0, e1)]])
+        ref = O.sweep(lw, start, OMEGA)
+        grow = np.concatenate([a + np.arange(wn), n + blocks, n + M + np.arange(e0, e1)])
+        got = outn[grow]
+        node_lo = 0 if a == 0 else K - 1
+        node_hi = wn - 1 if a + wn - K >= eb - 1 else wn - K
+        rr = np.concatenate([np.arange(node_lo, node_hi + 1), wn + np.arange(Wb + e1 - e0)])
+        err = np.max(np.abs(got[rr] - ref[rr])) / np.max(np.abs(ref[rr]))
+        assert err <= 1e-5, f"window at node {a}: {err:.3e}"
