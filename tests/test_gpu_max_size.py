@@ -181,3 +181,20 @@ def test_index_range_limit_two_levels(oracle_mod):
         rr = np.concatenate([np.arange(node_lo, node_hi + 1), wn + np.arange(Wb + e1 - e0)])
         err = np.max(np.abs(got[rr] - ref[rr])) / np.max(np.abs(ref[rr]))
         assert err <= 1e-5, f"window at node {a}: {err:.3e}"
+
+
+def test_cast_beyond_one_grid_dimension():
+    """A conversion of 2^32 + 5 elements (a launch folded into three grid
+    rows) rounds every element to nearest even, as torch does."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2103_09660_amd as H
+    n = 2 ** 32 + 5
+    x = torch.empty(n, dtype=torch.float32, device="cuda")
+    x.uniform_(-3.0, 3.0)
+    y = H.cast(x, "bf16")
+    assert torch.equal(y, x.to(torch.bfloat16))
+    del y
+    back = H.cast(x[-1000:].to(torch.bfloat16).contiguous(), "f32")
+    assert torch.equal(back, x[-1000:].to(torch.bfloat16).float())
