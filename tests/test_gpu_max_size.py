@@ -11,6 +11,22 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
+
+@pytest.fixture(autouse=True)
+def _release_device_memory():
+    """These tests take up to about 150 GB of device memory: start and end
+    with torch's cached blocks returned."""
+    import torch
+    if torch.cuda.is_available():
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    yield
+    if torch.cuda.is_available():
+        import gc
+        gc.collect()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
 K = 100                     # members per hyperedge (above the lane-group bound: wavefront tier)
 E = 20_000_000              # hyperedges: nnz = 2.0e9
 N = E + K - 1               # nodes
