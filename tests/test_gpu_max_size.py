@@ -109,6 +109,29 @@ def test_index_range_limit(oracle_mod):
         got_dw = dw[e0:e1].cpu().numpy()[inner_edges]
         err = np.max(np.abs(got_dw - ref_dw[inner_edges])) / np.max(np.abs(ref_dw[inner_edges]))
         assert err <= 1e-4, f"weight gradient at node {a}: {err:.3e}"
+    # hyperedge-prediction features over the same 2.0e9 memberships: every
+    # hyperedge as a candidate set, scored on the node rows of Z'
+    del plan, g, g1, dw, nacc
+    torch.cuda.empty_cache()
+    print("candidate scores", flush=True)
+    cptr = torch.arange(E + 1, dtype=torch.int32, device=dev) * K
+    cidx = (torch.arange(E, dtype=torch.int32, device=dev)[:, None] +
+            torch.arange(K, dtype=torch.int32, device=dev)[None, :]).reshape(-1)
+    sp = H.ScorePlan.from_device(cptr, cidx, N, D, "f32")
+    del cptr, cidx
+    zn = z1[:N].contiguous()
+    var = sp.score(zn, "variance")
+    torch.cuda.synchronize()
+    for c0 in (0, E // 2, E - 3):
+        cs = np.arange(c0, c0 + 3)
+        nodes = np.arange(c0, c0 + 3 + K - 1)
+        zsub = zn[torch.as_tensor(nodes, device=dev)].cpu().numpy()
+        lptr = np.arange(4, dtype=np.int64) * K
+        lidx = (np.arange(3)[:, None] + np.arange(K)[None, :]).astype(np.int32).ravel()
+        ref = O.score_candidates(zsub, lptr, lidx, "variance")
+        got = var[torch.as_tensor(cs, device=dev)].cpu().numpy()
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        assert err <= 1e-5, f"scores of candidates {c0}..: {err:.3e}"
 
 
 def test_index_range_limit_two_levels(oracle_mod):
