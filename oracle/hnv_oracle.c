@@ -474,6 +474,99 @@ void oracle_sweep_vjp(int64_t n_nodes, int64_t n_edges, const int64_t *eptr,
     free(zt);
 }
 
+/* Reverse mode of one edge-first sweep (Section 3.3's reading as two
+ * partial relaxations: hyperedge rows from the old node rows, then node rows
+ * from the new hyperedge rows).  With y the sweep's input and g = dL/dZ':
+ *   e'_e  = (1-omega) y_e + omega mean_{v in e} y_v      (the new hyperedge rows)
+ *   zt_v  = sum_{e ∋ v} w_e e'_e / S_v,  S_v = sum_{e ∋ v} w_e
+ * the node half gives
+ *   dL/dy_v  = (1-omega) g_v            (g_v for a node without hyperedges)
+ *   dL/de'_e = g_e + omega w_e sum_{v in e} g_v / S_v
+ *   dL/dw_e += omega sum_{v in e} <g_v, e'_e - zt_v> / S_v
+ * and the hyperedge half then adds
+ *   dL/dy_e  = (1-omega) dL/de'_e
+ *   dL/dy_v += omega sum_{e ∋ v} dL/de'_e / |e|.
+ * Every hyperedge has members, so every hyperedge row is relaxed. */
+void oracle_sweep_vjp_edge_first(int64_t n_nodes, int64_t n_edges, const int64_t *eptr,
+                                 const int32_t *eidx, const int64_t *nptr, const int32_t *nidx,
+                                 const float *w, int64_t d, double omega, const double *y,
+                                 const double *g, double *gy, double *dw)
+{
+    const size_t ne = (size_t)(n_edges > 0 ? n_edges : 1), nv = (size_t)(n_nodes > 0 ? n_nodes : 1);
+    double *ep = (double *)malloc(sizeof(double) * ne * (size_t)d);   /* e' */
+    double *gep = (double *)malloc(sizeof(double) * ne * (size_t)d);  /* dL/de' */
+    double *S = (double *)malloc(sizeof(double) * nv);
+    double *zt = (double *)malloc(sizeof(double) * nv * (size_t)d);
+    /* the hyperedge half of the forward sweep */
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t e = 0; e < n_edges; ++e) {
+        const double size = (double)(eptr[e + 1] - eptr[e]);
+        for (int64_t c = 0; c < d; ++c) {
+            double m = 0.0;
+            for (int64_t j = eptr[e]; j < eptr[e + 1]; ++j)
+                m += y[(int64_t)eidx[j] * d + c];
+            ep[e * d + c] = (1.0 - omega) * y[(n_nodes + e) * d + c] + omega * m / size;
+        }
+    }
+    /* per node: S_v and the weighted mean of its new hyperedge rows */
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t v = 0; v < n_nodes; ++v) {
+        double s = 0.0;
+        double *t = zt + v * d;
+        for (int64_t c = 0; c < d; ++c)
+            t[c] = 0.0;
+        for (int64_t j = nptr[v]; j < nptr[v + 1]; ++j) {
+            int64_t e = nidx[j];
+            double we = w ? (double)w[e] : 1.0;
+            s += we;
+            for (int64_t c = 0; c < d; ++c)
+                t[c] += we * ep[e * d + c];
+        }
+        S[v] = s;
+        if (s != 0.0)
+            for (int64_t c = 0; c < d; ++c)
+                t[c] /= s;
+    }
+    /* the node half in reverse: dL/de' and the weight gradient per hyperedge */
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t e = 0; e < n_edges; ++e) {
+        double we = w ? (double)w[e] : 1.0;
+        double gw = 0.0;
+        for (int64_t c = 0; c < d; ++c)
+            gep[e * d + c] = g[(n_nodes + e) * d + c];
+        for (int64_t j = eptr[e]; j < eptr[e + 1]; ++j) {
+            int64_t v = eidx[j];
+            double dot = 0.0;
+            for (int64_t c = 0; c < d; ++c) {
+                gep[e * d + c] += omega * (we / S[v]) * g[v * d + c];
+                dot += g[v * d + c] * (ep[e * d + c] - zt[v * d + c]);
+            }
+            gw += omega * dot / S[v];
+        }
+        if (dw)
+            dw[e] += gw;
+        for (int64_t c = 0; c < d; ++c)
+            gy[(n_nodes + e) * d + c] = (1.0 - omega) * gep[e * d + c];
+    }
+    /* node rows: their own term from the node half, then the hyperedge half */
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t v = 0; v < n_nodes; ++v) {
+        double self = (nptr[v + 1] > nptr[v]) ? 1.0 - omega : 1.0;
+        for (int64_t c = 0; c < d; ++c)
+            gy[v * d + c] = self * g[v * d + c];
+        for (int64_t j = nptr[v]; j < nptr[v + 1]; ++j) {
+            int64_t e = nidx[j];
+            double size = (double)(eptr[e + 1] - eptr[e]);
+            for (int64_t c = 0; c < d; ++c)
+                gy[v * d + c] += omega * gep[e * d + c] / size;
+        }
+    }
+    free(ep);
+    free(gep);
+    free(S);
+    free(zt);
+}
+
 /* Reverse mode of the projection: every fine row's gradient is added to the
  * coarse row it was copied from, in ascending fine-row order. */
 void oracle_project_vjp(int64_t rows_fine, int64_t rows_coarse, const int64_t *rowmap,

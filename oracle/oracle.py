@@ -80,6 +80,7 @@ def _L():
                                      ctypes.c_int64, ctypes.c_double, ctypes.c_int, _f64p, _f64p]
         lib.oracle_sweep_vjp.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _i64p, _i32p, _f32p,
                                          ctypes.c_int64, ctypes.c_double, _f64p, _f64p, _f64p, _f64p]
+        lib.oracle_sweep_vjp_edge_first.argtypes = lib.oracle_sweep_vjp.argtypes
         lib.oracle_project_vjp.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, ctypes.c_int64, _f64p, _f64p]
         _lib = lib
     return _lib
@@ -271,14 +272,17 @@ def refine(levels: Sequence[Level], maps: Sequence[Coarsening], z_coarsest: np.n
     return (z, res) if return_residuals else z
 
 
-def sweep_vjp(lv: Level, y: np.ndarray, g: np.ndarray, omega: float, w: Optional[np.ndarray] = None):
-    """Reverse mode of one order-0 sweep at inputs ``y``: returns (dL/dy, dL/dw)."""
+def sweep_vjp(lv: Level, y: np.ndarray, g: np.ndarray, omega: float, w: Optional[np.ndarray] = None,
+              order: int = 0):
+    """Reverse mode of one sweep at inputs ``y`` (order 0 Jacobi, order 1
+    edge-first): returns (dL/dy, dL/dw)."""
     y = np.ascontiguousarray(y, dtype=np.float64)
     g = np.ascontiguousarray(g, dtype=np.float64)
     gy = np.empty_like(y)
     dw = np.zeros(max(lv.n_edges, 1), dtype=np.float64)
     ww = lv.w if w is None else np.ascontiguousarray(w, dtype=np.float32)
-    _L().oracle_sweep_vjp(lv.n_nodes, lv.n_edges, _p(lv.eptr, _i64p), _p(lv.eidx, _i32p), _p(lv.nptr, _i64p),
+    fn = _L().oracle_sweep_vjp if order == 0 else _L().oracle_sweep_vjp_edge_first
+    fn(lv.n_nodes, lv.n_edges, _p(lv.eptr, _i64p), _p(lv.eidx, _i32p), _p(lv.nptr, _i64p),
                           _p(lv.nidx, _i32p), _p(ww, _f32p), y.shape[1], float(omega), _p(y, _f64p),
                           _p(g, _f64p), _p(gy, _f64p), _p(dw, _f64p))
     return gy, dw[: lv.n_edges]

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from synth import random_hypergraph
-from tests.dense_ref import jacobi_matrix, star_adjacency
+from tests.dense_ref import edge_first_matrix, jacobi_matrix, star_adjacency
 
 
 def _level(O, hg):
@@ -28,6 +28,52 @@ def test_vjp_is_dense_transpose_and_dot_identity(oracle_mod, seed):
     lhs = np.sum(O.sweep(lv, x, 0.4, 0) * g)
     rhs = np.sum(x * O.sweep_vjp(lv, x, g, 0.4)[0])
     assert abs(lhs - rhs) <= 1e-13 * max(1.0, abs(lhs))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_edge_first_vjp_is_dense_transpose_and_dot_identity(oracle_mod, seed):
+    """The edge-first sweep is the product of two partial relaxations (the
+    hyperedge rows, then the node rows), so its reverse mode is that product's
+    transpose.  The random hypergraphs include nodes in no hyperedge."""
+    O = oracle_mod
+    hg = random_hypergraph(40 + seed, 33, 21, 1, 6, weighted=True)
+    lv = _level(O, hg)
+    rng = np.random.default_rng(seed)
+    y = rng.standard_normal((lv.rows, 3))
+    g = rng.standard_normal((lv.rows, 3))
+    gy, _ = O.sweep_vjp(lv, y, g, 0.7, order=1)
+    A = star_adjacency(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w)
+    M = edge_first_matrix(A, 0.7, hg.n_nodes)
+    np.testing.assert_allclose(gy, M.T @ g, atol=1e-13)
+    x = rng.standard_normal((lv.rows, 3))
+    lhs = np.sum(O.sweep(lv, x, 0.7, 1) * g)
+    rhs = np.sum(x * O.sweep_vjp(lv, x, g, 0.7, order=1)[0])
+    assert abs(lhs - rhs) <= 1e-13 * max(1.0, abs(lhs))
+    # the two orders differ, so neither reverse mode can stand in for the other
+    assert np.abs(gy - O.sweep_vjp(lv, y, g, 0.7, order=0)[0]).max() > 1e-3
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_edge_first_weight_gradient_finite_differences(oracle_mod, seed):
+    """dL/dw of one edge-first sweep, L = <sweep(y; w), G>, against central
+    differences with steps exact in float32 (the weights' storage type)."""
+    O = oracle_mod
+    hg = random_hypergraph(60 + seed, 30, 18, 1, 6, weighted=True)
+    lv = _level(O, hg)
+    rng = np.random.default_rng(seed)
+    y = rng.standard_normal((lv.rows, 4))
+    G = rng.standard_normal((lv.rows, 4))
+    w0 = np.asarray(hg.edge_w, dtype=np.float32)
+    _, dw = O.sweep_vjp(lv, y, G, 0.6, w=w0, order=1)
+    for e in range(hg.n_edges):
+        step = np.float32(w0[e] * (1 + 1e-3)) - w0[e]
+        wp = w0.copy(); wm = w0.copy()
+        wp[e] += step; wm[e] -= step
+        fd = (np.sum(O.sweep(lv, y, 0.6, 1, w=wp) * G) - np.sum(O.sweep(lv, y, 0.6, 1, w=wm) * G)) / (2 * float(step))
+        assert abs(fd - dw[e]) <= 1e-6 * max(1.0, abs(dw[e])), (e, fd, dw[e])
+    # scaling every weight by one factor leaves the sweep unchanged (node rows
+    # take weighted means, hyperedge rows plain means): sum_e w_e dL/dw_e = 0
+    assert abs(float(np.dot(w0.astype(np.float64), dw))) <= 1e-10 * max(1.0, np.abs(dw).sum())
 
 
 @pytest.mark.parametrize("seed", range(3))
