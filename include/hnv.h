@@ -185,7 +185,10 @@ hnv_status hnv_coarsen_level_features_device(int64_t n_nodes, int64_t n_edges, i
 /* Device workspace a plan over these levels needs, in bytes.  levels[0] is
  * the finest, levels[n_levels-1] the coarsest; maps[l] maps level l to l+1
  * (n_levels-1 entries, may be NULL if n_levels == 1).  d: embedding width,
- * a multiple of 8 up to 512.  opts may be NULL.  Host only. */
+ * a multiple of 8 up to 512.  opts may be NULL.  No level may have more rows
+ * (n_nodes + n_edges) than levels[0]: the refinement keeps every level's
+ * iterates in buffers of the finest level's size (HNV_EUNSUPPORTED
+ * otherwise; coarsening never grows a level).  Host only. */
 hnv_status hnv_plan_workspace_bytes(const hnv_level *levels, const hnv_map *maps, int n_levels,
                                     int d, hnv_dtype dtype, const hnv_options *opts, size_t *bytes);
 
@@ -293,25 +296,35 @@ hnv_status hnv_project(hnv_plan *plan, int level, const void *z_coarse, void *z_
 hnv_status hnv_sweep(hnv_plan *plan, int level, const void *z_in, void *z_out, float omega,
                      int from_coarse, double *resid_dev, void *stream);
 
-/* Reverse mode of one sweep at `level` (from_coarse = 0).  With y = z_prev
- * (the sweep's input), z = z_cur (its output) and g_in = dL/dz, writes
- * g_out = dL/dy:
+/* Reverse mode of one sweep at `level` (from_coarse = 0), in the plan's
+ * sweep order.  With y = z_prev (the sweep's input), z = z_cur (its output)
+ * and g_in = dL/dz, writes g_out = dL/dy.  Jacobi order:
  *   node v:      (1-omega) g_v + omega sum_{e ∋ v} g_e / |e|
  *   hyperedge e: (1-omega) g_e + omega w_e sum_{v in e} g_v / S_v,
  *                S_v = sum_{e' ∋ v} w_e'
  *   rows without neighbours: g_out = g_in,
  * and if dw_accum != NULL adds dL/dw_e = omega sum_{v in e}
  * <g_v, y_e - zt_v> / S_v to dw_accum[e] (DEVICE float [n_edges]), where
- * zt_v = (z_v - (1-omega) y_v) / omega is node v's neighbour mean.  Needs
- * omega > 0.  All matrices [rows x d] of the plan's storage type; g_out must
- * not alias g_in.  With dw_accum = NULL, z_prev and z_cur are not read. */
+ * zt_v = (z_v - (1-omega) y_v) / omega is node v's neighbour mean.
+ * Edge-first order (hyperedge rows relaxed from the old node rows, then node
+ * rows from the new hyperedge rows e'_e = z_e): with
+ * ge_e = g_e + omega w_e sum_{v in e} g_v / S_v (= dL/de'_e),
+ *   hyperedge e: (1-omega) ge_e
+ *   node v:      (1-omega) g_v + omega sum_{e ∋ v} ge_e / |e|
+ *   rows without neighbours: g_out = g_in,
+ * and dL/dw_e = omega sum_{v in e} <g_v, e'_e - zt_v> / S_v, zt_v as above
+ * (the mean of the new hyperedge rows).  This order uses the plan's scratch
+ * embedding for ge.  Needs omega > 0.  All matrices [rows x d] of the plan's
+ * storage type; g_out must not alias g_in.  With dw_accum = NULL, z_prev and
+ * z_cur are not read. */
 hnv_status hnv_sweep_adjoint(hnv_plan *plan, int level, const void *g_in, void *g_out,
                              const void *z_prev, const void *z_cur, float *dw_accum, float omega,
                              void *stream);
 
 /* The same reverse sweep with the weight gradient split in two, for several
  * reverse sweeps in a row whose weight gradients add up.  The hyperedge part
- * omega <sum_{v in e} g_v / S_v, y_e> is added to dw_accum[e] (DEVICE float
+ * omega <sum_{v in e} g_v / S_v, y_e> (e'_e in place of y_e in the
+ * edge-first order) is added to dw_accum[e] (DEVICE float
  * [n_edges]) and the node part omega <g_v, zt_v> / S_v to node_accum[v]
  * (DEVICE float [n_nodes], zeroed by the caller before the first sweep).
  * hnv_weight_grad_finish then subtracts from every dw_accum[e] the sum of

@@ -296,18 +296,18 @@ def project_vjp(rmap: np.ndarray, rows_coarse: int, gf: np.ndarray) -> np.ndarra
 
 
 def finest_refine_vjp(fine: Level, cm: Coarsening, z_coarse: np.ndarray, w: Optional[np.ndarray],
-                      k: int, omega: float, g_out: np.ndarray):
+                      k: int, omega: float, g_out: np.ndarray, order: int = 0):
     """Forward and reverse of: project the coarse embedding onto the finest
-    level, then ``k`` sweeps with hyperedge weights ``w``.  Returns
-    (Z_k, dL/dZ_coarse, dL/dw) for the cotangent ``g_out`` = dL/dZ_k."""
+    level, then ``k`` sweeps of the given order with hyperedge weights ``w``.
+    Returns (Z_k, dL/dZ_coarse, dL/dw) for the cotangent ``g_out`` = dL/dZ_k."""
     rm = rowmap(fine, cm)
     states = [project(rm, z_coarse)]
     for _ in range(k):
-        states.append(sweep(fine, states[-1], omega, 0, w))
+        states.append(sweep(fine, states[-1], omega, order, w))
     g = np.ascontiguousarray(g_out, dtype=np.float64)
     dw = np.zeros(fine.n_edges, dtype=np.float64)
     for i in range(k, 0, -1):
-        g, dwi = sweep_vjp(fine, states[i - 1], g, omega, w)
+        g, dwi = sweep_vjp(fine, states[i - 1], g, omega, w, order)
         dw += dwi
     gc = project_vjp(rm, cm.coarse.rows, g)
     return states[-1], gc, dw

@@ -392,6 +392,9 @@ hnv_status check_levels(const hnv_level_dev *levels, const hnv_map *maps, int n_
             return fail(HNV_EINVAL, "level " + std::to_string(l) + ": bad sizes or NULL arrays");
         if (L.n_nodes + L.n_edges >= INT_MAX || L.nnz >= INT_MAX)
             return fail(HNV_EUNSUPPORTED, "level " + std::to_string(l) + ": rows and nnz must be below 2^31");
+        if (L.n_nodes + L.n_edges > levels[0].n_nodes + levels[0].n_edges)
+            return fail(HNV_EUNSUPPORTED, "level " + std::to_string(l) +
+                                              " has more rows than level 0 (iterates live in buffers of its size)");
         if (l + 1 < n_levels && ((L.n_nodes > 0 && !maps[l].node_rep) || (L.n_edges > 0 && !maps[l].edge_rep)))
             return fail(HNV_EINVAL, "map " + std::to_string(l) + " has a NULL array");
     }

@@ -433,6 +433,9 @@ static hnv_status check_shape(const hnv_level *levels, const hnv_map *maps, int 
             return fail(HNV_EINVAL, "level " + std::to_string(l) + ": bad sizes or NULL arrays");
         if (L.n_nodes + L.n_edges >= kMaxI32 || L.nnz >= kMaxI32)
             return fail(HNV_EUNSUPPORTED, "level " + std::to_string(l) + ": rows and nnz must be below 2^31");
+        if (L.n_nodes + L.n_edges > levels[0].n_nodes + levels[0].n_edges)
+            return fail(HNV_EUNSUPPORTED, "level " + std::to_string(l) +
+                                              " has more rows than level 0 (iterates live in buffers of its size)");
         if (l + 1 < n_levels && (!maps[l].node_rep || (L.n_edges > 0 && !maps[l].edge_rep)))
             return fail(HNV_EINVAL, "map " + std::to_string(l) + " has a NULL array");
     }

@@ -181,6 +181,7 @@ struct GatherArgs {
     const void *yprev;        // reverse: sweep input y
     const void *zcur;         // reverse: sweep output z
     float *cvec;              // reverse: per-node scalar (written on node rows, read on hyperedge rows)
+    void *dst2;               // reverse, edge-first order: hyperedge rows' dL/de' (read by the node launch)
     int32_t wgrad;            // reverse: weight gradient 0 none, 1 in one sweep (cvec = c), 2 split (cvec += omega c)
     float *dw;                // reverse: dL/dw accumulator or null
     float *partials;          // split-row partial sums
@@ -359,7 +360,9 @@ HNV_DEV float group_sum(float x)
 // A row's own slices, fetched before its neighbours so that their latency
 // overlaps the gather: forward, the row's previous value (or the coarser
 // row it is projected from); reverse, its cotangent g and, for rows with
-// neighbours, the sweep's input y (and, on node rows, its output z).
+// neighbours, the sweep's input y (and, on node rows, its output z).  On
+// the hyperedge rows of an edge-first reverse sweep, y is the sweep's
+// output row e' (the caller passes z as yprev).
 template <typename T, int EPL>
 struct Own {
     typename Slice<T, EPL>::Raw x, y, z;
@@ -370,7 +373,7 @@ HNV_DEV void load_own(Own<T, EPL> &o, const GatherArgs &a, const Mats &m, int64_
                       int col)
 {
     using S = Slice<T, EPL>;
-    o.x = S::load(static_cast<const T *>(MODE == kFwd ? m.self : m.src) + srow * a.ld + col);
+    o.x = S::load(static_cast<const T *>(m.self) + srow * a.ld + col);
     // the sweep's input and output rows serve the weight gradient only
     if (MODE != kFwd && deg > 0 && a.wgrad != 0) {
         o.y = S::load(static_cast<const T *>(a.yprev) + zrow * a.ld + col);
@@ -458,6 +461,9 @@ HNV_DEV void epilogue_adj_node(const GatherArgs &a, int row, int deg, int col, b
 
 // Reverse, hyperedge row e (side 0): g'_e = (1-omega) g_e + omega w_e acc with
 // acc = sum_v g_v / S_v; dL/dw_e += omega (<acc, y_e> - sum_v c_v).
+// Edge-first order (a.dst2 != null): the node half runs last forward, so
+// its reverse comes first: ge_e = g_e + omega w_e acc is dL/de'_e, stored to
+// dst2 for the node launch, and g'_e = (1-omega) ge_e; y_e is then e'_e.
 template <typename T, int EPL, int G>
 HNV_DEV void epilogue_adj_edge(const GatherArgs &a, int row, int deg, int col, bool col_ok, float (&acc)[EPL],
                                float csum, const Own<T, EPL> &own, bool writer)
@@ -473,15 +479,29 @@ HNV_DEV void epilogue_adj_edge(const GatherArgs &a, int row, int deg, int col, b
             S::unpack(own.y, y);
             const float keep = 1.0f - a.omega;
             const float mix = a.omega * a.w[row];
+            if (a.dst2) {
+                float ge[EPL];
 #pragma unroll
-            for (int i = 0; i < EPL; ++i) {
-                o[i] = fmaf(mix, acc[i], keep * g[i]);
-                dot = fmaf(acc[i], y[i], dot);
+                for (int i = 0; i < EPL; ++i) {
+                    ge[i] = fmaf(mix, acc[i], g[i]);
+                    o[i] = keep * ge[i];
+                    dot = fmaf(acc[i], y[i], dot);
+                }
+                if (writer)
+                    S::store(static_cast<T *>(a.dst2) + zrow * a.ld + col, ge);
+            } else {
+#pragma unroll
+                for (int i = 0; i < EPL; ++i) {
+                    o[i] = fmaf(mix, acc[i], keep * g[i]);
+                    dot = fmaf(acc[i], y[i], dot);
+                }
             }
         } else {
 #pragma unroll
             for (int i = 0; i < EPL; ++i)
                 o[i] = g[i];
+            if (writer && a.dst2)
+                S::store(static_cast<T *>(a.dst2) + zrow * a.ld + col, o);
         }
         if (writer)
             S::store(static_cast<T *>(a.dst) + zrow * a.ld + col, o);
@@ -808,13 +828,13 @@ __global__ void k_ctl_advance(SweepCtl *ctl)
     }
 }
 
-// Second half of a split weight gradient: dw[e] -= sum of node_acc over the
-// members of e.  16 lanes per hyperedge, each summing a strided share in
-// member order, combined by a fixed butterfly (reproducible).
+// Second half of a split weight gradient: dw[e] -= scale * (sum of node_acc
+// over the members of e).  16 lanes per hyperedge, each summing a strided
+// share in member order, combined by a fixed butterfly (reproducible).
 __global__ __launch_bounds__(kBlock) void k_wgrad_finish(const int32_t *__restrict__ ptr,
                                                          const int32_t *__restrict__ idx,
                                                          const float *__restrict__ node_acc, float *__restrict__ dw,
-                                                         int64_t n_edges)
+                                                         int64_t n_edges, float scale)
 {
     constexpr int GW = 16;
     const int64_t e = (linear_block() * kBlock + threadIdx.x) / GW;
@@ -831,7 +851,7 @@ __global__ __launch_bounds__(kBlock) void k_wgrad_finish(const int32_t *__restri
     for (int off = 1; off < GW; off <<= 1)
         sum += __shfl_xor(sum, off, kWave);
     if (e < n_edges && gl == 0)
-        dw[e] -= sum;
+        dw[e] -= scale * sum;
 }
 
 // Copies the latest iterate to out (n16 16-byte words) unless it is there.
@@ -1757,17 +1777,27 @@ extern "C" hnv_status hnv_refine(hnv_plan *plan, const void *z_coarsest, void *z
 
 // One reverse sweep of `level`.  wgrad: 0 no weight gradient (the sweep's
 // input and output rows are not read), 1 the whole gradient into dw in this
-// sweep (node rows store their scalar, hyperedge rows sum it over their
-// members), 2 split: node rows add omega times their scalar to node_acc,
+// sweep, 2 split: node rows add omega times their scalar to node_acc,
 // hyperedge rows add only their own term to dw.
+//
+// Jacobi order: node rows first (they produce the per-node scalars), then
+// hyperedge rows, which with wgrad = 1 sum the scalars of their members.
+// Edge-first order: the forward node half read the new hyperedge rows, so
+// the hyperedge rows go first, writing dL/de' to the plan's scratch
+// embedding; the node rows then gather it.  There the per-node scalars come
+// last, so wgrad = 1 runs as the split form over one sweep: the scalars go
+// to the plan's per-node scratch and a finish pass subtracts omega times
+// their member sums.
 static hnv_status run_adjoint(hnv_plan *plan, int level, const void *g_in, void *g_out, const void *z_prev,
                               const void *z_cur, float *dw, float *node_acc, float omega, int wgrad, hipStream_t s)
 {
     LevelPlan &L = plan->lv[level];
     const int G = plan->g_full, E = plan->epl_full;
+    const bool edge_first = plan->opts.order == HNV_ORDER_EDGE_FIRST;
     GatherArgs a = base_args(plan, L, G, plan->d);
     a.omega = omega;
     a.src = g_in;
+    a.self_src = g_in;
     a.dst = g_out;
     a.yprev = z_prev;
     a.zcur = z_cur;
@@ -1775,10 +1805,32 @@ static hnv_status run_adjoint(hnv_plan *plan, int level, const void *g_in, void 
     a.dw = (wgrad == 0) ? nullptr : dw;
     a.wgrad = wgrad;
     a.resid = nullptr;
-    // node rows first (they produce the per-node scalars), then hyperedge rows
-    const GatherArgs an = only_side(a, 1), ae = only_side(a, 0);
+    GatherArgs an = only_side(a, 1), ae = only_side(a, 0);
     ProfScope pn{plan, s, HNV_PROF_ADJ_NODE, level}, pe{plan, s, HNV_PROF_ADJ_EDGE, level};
     hnv_status st;
+    if (edge_first) {
+        ae.dst2 = plan->zbuf;
+        ae.yprev = z_cur;     // the dot of the weight gradient takes e'_e
+        an.src = plan->zbuf;  // node rows gather dL/de'
+        const bool whole = (wgrad == 1);
+        if (whole)
+            an.wgrad = 1;     // store the scalars (plain, not times omega)
+        if (plan->dtype == HNV_F32) {
+            if ((st = dispatch_g<float, kAdjEdgeNoSum, false>(G, E, ae, 1, s, &pe)) != HNV_OK)
+                return st;
+            st = dispatch_g<float, kAdjNode, false>(G, E, an, 1, s, &pn);
+        } else {
+            if ((st = dispatch_g<bf16_t, kAdjEdgeNoSum, false>(G, E, ae, 1, s, &pe)) != HNV_OK)
+                return st;
+            st = dispatch_g<bf16_t, kAdjNode, false>(G, E, an, 1, s, &pn);
+        }
+        if (st != HNV_OK || !whole || L.n_edges == 0)
+            return st;
+        const int64_t threads = L.n_edges * 16;
+        k_wgrad_finish<<<fold_grid(blocks_for(threads, kBlock)), kBlock, 0, s>>>(
+            L.side[0].ptr, L.side[0].idx, plan->cscratch, dw, L.n_edges, omega);
+        return dev_check("weight-gradient finish");
+    }
     if (plan->dtype == HNV_F32) {
         if ((st = dispatch_g<float, kAdjNode, false>(G, E, an, 1, s, &pn)) != HNV_OK)
             return st;
@@ -1805,8 +1857,6 @@ static hnv_status check_adjoint_args(hnv_plan *plan, int level, const void *g_in
         return fail(HNV_EINVAL, "matrices must be 16-byte aligned");
     if (!(omega > 0.0f && omega <= 1.0f))
         return fail(HNV_EINVAL, "omega must be in (0, 1] for the reverse sweep");
-    if (plan->opts.order != HNV_ORDER_JACOBI)
-        return fail(HNV_EUNSUPPORTED, "the reverse sweep is implemented for the Jacobi order");
     return HNV_OK;
 }
 
@@ -1851,7 +1901,7 @@ extern "C" hnv_status hnv_weight_grad_finish(hnv_plan *plan, int level, const fl
         return fail(HNV_EINVAL, "dw_accum / node_accum is NULL");
     const int64_t threads = L.n_edges * 16;
     k_wgrad_finish<<<fold_grid(blocks_for(threads, kBlock)), kBlock, 0, reinterpret_cast<hipStream_t>(stream)>>>(
-        L.side[0].ptr, L.side[0].idx, node_accum, dw_accum, L.n_edges);
+        L.side[0].ptr, L.side[0].idx, node_accum, dw_accum, L.n_edges, 1.0f);
     return dev_check("weight-gradient finish");
 }
 

@@ -69,13 +69,14 @@ def test_random_bit_identical(H, seed, n_nodes, n_edges, hi, weighted):
     _assert_same_refine(host, dev, hier, 24, [2, 2, 2, 2], seed)
 
 
-def test_reverse_bit_identical(H):
+@pytest.mark.parametrize("order", ["jacobi", "edge_first"])
+def test_reverse_bit_identical(H, order):
     """Adjoint sweep, weight gradient and projection adjoint through both plans."""
     import torch
     cfg = CONFIGS["hub-200k"]
     hg = make_hypergraph(cfg)
     hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, 1)
-    host, dev = _both_plans(H, hier, 32, "f32")
+    host, dev = _both_plans(H, hier, 32, "f32", options={"order": order})
     rng = np.random.default_rng(3)
     y = torch.as_tensor(rng.standard_normal((hier.levels[0].rows, 32)).astype(np.float32)).cuda()
     g = torch.as_tensor(rng.standard_normal((hier.levels[0].rows, 32)).astype(np.float32)).cuda()
@@ -170,6 +171,14 @@ def test_device_plan_checks(H):
     with pytest.raises(H.HnvError) as ei:
         H.Plan.from_device([lv], [], 16, "f32")
     assert ei.value.status == L.HNV_EINVAL
+    # a coarser level with more rows than the finest (a valid map onto a
+    # level with unused nodes) does not fit the refinement's buffers
+    big = H.DeviceLevel.from_host(H.HostLevel(hier.levels[0].rows + 5, 1, np.array([0, 1], np.int64),
+                                              np.array([0], np.int32), None), "cuda")
+    with pytest.raises(H.HnvError) as ei:
+        H.Plan.from_device([levels[0], big], [(torch.zeros_like(maps[0][0]), torch.full_like(maps[0][1], -1))],
+                           16, "f32")
+    assert ei.value.status == L.HNV_EUNSUPPORTED
     torch.cuda.synchronize()
 
 

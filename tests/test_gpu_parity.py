@@ -368,7 +368,8 @@ def test_refine_function_grad500k_shape_small(oracle_mod, H):
     _assert_close(th_t.grad.cpu().numpy(), ref_dw * w_dev, GRAD_TOL, "dL/dtheta")
 
 
-def test_gradients_through_every_level(oracle_mod, H):
+@pytest.mark.parametrize("order", ["jacobi", "edge_first"])
+def test_gradients_through_every_level(oracle_mod, H, order):
     """Reverse mode across the whole hierarchy: K sweeps at the coarsest
     level, then projection and K sweeps at each finer level, every level
     with learnable log-weights of its own; loss = <G, node rows of Z_0>.
@@ -381,7 +382,8 @@ def test_gradients_through_every_level(oracle_mod, H):
     levels, maps, hier = both_hierarchies(O, H, hg, 3)
     L = len(levels) - 1
     d, K, omega = 16, 4, 0.5
-    plan = H.Plan(hier, d, "f32")
+    plan = H.Plan(hier, d, "f32", options={"order": order})
+    o = 1 if order == "edge_first" else 0
     rng = np.random.default_rng(14)
     zc = rng.standard_normal((levels[L].rows, d)).astype(np.float32)
     thetas = [rng.uniform(-0.5, 0.5, size=lv.n_edges).astype(np.float32) for lv in levels]
@@ -395,19 +397,19 @@ def test_gradients_through_every_level(oracle_mod, H):
     ws = [np.exp(t.astype(np.float64)).astype(np.float32) for t in thetas]
     states = [zc.astype(np.float64)]
     for _ in range(K):
-        states.append(O.sweep(levels[L], states[-1], omega, 0, ws[L]))
+        states.append(O.sweep(levels[L], states[-1], omega, o, ws[L]))
     zs = {L: states[-1]}
     for l in range(L - 1, -1, -1):
         zs[l] = O.finest_refine_vjp(levels[l], maps[l], zs[l + 1], ws[l], K, omega,
-                                    np.zeros((levels[l].rows, d)))[0]
+                                    np.zeros((levels[l].rows, d)), o)[0]
     g = np.zeros((levels[0].rows, d))
     g[: levels[0].n_nodes] = G
     dws = {}
     for l in range(L):
-        _, g, dws[l] = O.finest_refine_vjp(levels[l], maps[l], zs[l + 1], ws[l], K, omega, g)
+        _, g, dws[l] = O.finest_refine_vjp(levels[l], maps[l], zs[l + 1], ws[l], K, omega, g, o)
     dws[L] = np.zeros(levels[L].n_edges)
     for i in range(K, 0, -1):
-        g, dwi = O.sweep_vjp(levels[L], states[i - 1], g, omega, ws[L])
+        g, dwi = O.sweep_vjp(levels[L], states[i - 1], g, omega, ws[L], o)
         dws[L] += dwi
     ref_loss = float((zs[0][: levels[0].n_nodes] * G).sum())
     assert abs(loss.item() - ref_loss) <= 1e-5 * np.abs(zs[0][: levels[0].n_nodes] * G).sum()
@@ -538,11 +540,66 @@ def test_edge_first_sweeps(oracle_mod, H, dtype, small_max, chunk):
     ztr = ztop if dtype == "f32" else _bf16_round(ztop)
     out, _, _ = plan.refine(_dev(ztop, dtype), [3, 2, 4], 0.5)
     _assert_close(_host(out), O.refine(levels, maps, ztr, [3, 2, 4], 0.5, order=1), tol, "edge-first refine")
-    # the Jacobi-only reverse sweep refuses this plan
-    from paper_2103_09660_amd._lib import HNV_EUNSUPPORTED, HnvError
-    with pytest.raises(HnvError) as ei:
-        plan.sweep_adjoint(0, plan.empty(0), plan.empty(0), plan.empty(0), 0.5)
-    assert ei.value.status == HNV_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("dtype,small_max,chunk,d", [("f32", 32, 512, 32), ("f32", 4, 64, 64), ("bf16", 8, 128, 128),
+                                                     ("bf16", 1, 64, 16)])
+def test_edge_first_adjoint(oracle_mod, H, dtype, small_max, chunk, d):
+    """Reverse mode of the edge-first order: one reverse sweep (cotangent and
+    the hyperedge-weight gradient) against the oracle's, then K reverse
+    sweeps with the weight gradient whole, split and not requested: the
+    cotangents are the same bit for bit, the split gradient matches the
+    whole one and the oracle's."""
+    import torch
+    O = oracle_mod
+    hg = tier_hypergraph(31, max(small_max, 2), chunk) if small_max < 32 else \
+        random_hypergraph(31, 2000, 1200, 1, 12, weighted=True)
+    levels, maps, hier = both_hierarchies(O, H, hg, 1)
+    plan = H.Plan(hier, d, dtype, options={"order": "edge_first", "small_max": small_max, "chunk": chunk})
+    tol = F32_TOL if dtype == "f32" else BF16_TOL
+    gtol = GRAD_TOL if dtype == "f32" else 2 * BF16_TOL
+    rng = np.random.default_rng(31)
+    theta = rng.uniform(-0.5, 0.5, size=levels[0].n_edges).astype(np.float32)
+    wt = torch.empty(levels[0].n_edges, dtype=torch.float32, device="cuda")
+    plan.set_edge_logweights(0, _dev(theta), w_out=wt)
+    w_host = wt.cpu().numpy()
+    omega, K = 0.6, 3
+    y0 = rng.standard_normal((levels[0].rows, d)).astype(np.float32)
+    g0 = rng.standard_normal((levels[0].rows, d)).astype(np.float32)
+    states = [_dev(y0, dtype)]
+    for _ in range(K):
+        states.append(plan.sweep(0, states[-1], omega))
+    _assert_close(_host(states[1]), O.sweep(levels[0], _host(states[0]), omega, 1, w_host), tol, "forward")
+    n_nodes, n_edges, _ = plan.level_info(0)
+    # one reverse sweep
+    dw1 = torch.zeros(n_edges, dtype=torch.float32, device="cuda")
+    g1 = plan.sweep_adjoint(0, _dev(g0, dtype), states[0], states[1], omega, dw=dw1)
+    ref_g1, ref_dw1 = O.sweep_vjp(levels[0], _host(states[0]), _host(_dev(g0, dtype)), omega, w_host, order=1)
+    _assert_close(_host(g1), ref_g1, tol, "edge-first adjoint g")
+    _assert_close(dw1.cpu().numpy(), ref_dw1, gtol, "edge-first adjoint dw")
+
+    def backward(mode):
+        dw = torch.zeros(n_edges, dtype=torch.float32, device="cuda") if mode else None
+        nacc = torch.zeros(n_nodes, dtype=torch.float32, device="cuda") if mode == "split" else None
+        g = _dev(g0, dtype)
+        for i in range(K, 0, -1):
+            g = plan.sweep_adjoint(0, g, states[i - 1], states[i], omega, dw=dw, node_acc=nacc)
+        if mode == "split":
+            plan.weight_grad_finish(0, nacc, dw)
+        return g, dw
+
+    g_split, dw_split = backward("split")
+    g_whole, dw_whole = backward("whole")
+    g_none, _ = backward(None)
+    assert torch.equal(g_split, g_whole) and torch.equal(g_split, g_none)
+    assert rel_fro(dw_split.cpu().numpy(), dw_whole.cpu().numpy().astype(np.float64)) <= 1e-5
+    ref_dw = np.zeros(n_edges)
+    gr = _host(_dev(g0, dtype))
+    for i in range(K, 0, -1):
+        gr, dwi = O.sweep_vjp(levels[0], _host(states[i - 1]), gr, omega, w_host, order=1)
+        ref_dw += dwi
+    _assert_close(_host(g_split), gr, tol * K, "edge-first K reverse sweeps g")
+    _assert_close(dw_split.cpu().numpy(), ref_dw, gtol, "edge-first K reverse sweeps dw")
 
 
 # ---------------------------------------------------------------------------

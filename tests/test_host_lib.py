@@ -75,6 +75,14 @@ def test_workspace_sizing_errors(H):
         assert ei.value.status == HNV_EUNSUPPORTED
     with pytest.raises(HnvError):
         H.plan_workspace_bytes(hier, 64, "f32", options={"panel_cols": 24})
+    # a coarser level with more rows than the finest would not fit the
+    # refinement's buffers (a valid map onto a level with unused nodes)
+    fine = _lvl(H, 4, [[0, 1], [2, 3]])
+    big = _lvl(H, 6, [[0, 1]])
+    grown = H.Hierarchy([fine, big], [H.HostMap(np.array([0, 0, 1, 1], np.int32), np.array([0, -1], np.int32))])
+    with pytest.raises(HnvError) as ei:
+        H.plan_workspace_bytes(grown, 16, "f32")
+    assert ei.value.status == HNV_EUNSUPPORTED and "more rows than level 0" in str(ei.value)
     # more panels / smaller tiers never shrink below the embedding buffer
     a = H.plan_workspace_bytes(hier, 64, "f32", options={"panel_cols": 32, "small_max": 1, "chunk": 64})
     assert a >= hier.levels[0].rows * 64 * 4

@@ -76,10 +76,12 @@ def test_edge_first_weight_gradient_finite_differences(oracle_mod, seed):
     assert abs(float(np.dot(w0.astype(np.float64), dw))) <= 1e-10 * max(1.0, np.abs(dw).sum())
 
 
+@pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("seed", range(3))
-def test_finite_differences_theta_and_coarse(oracle_mod, seed):
+def test_finite_differences_theta_and_coarse(oracle_mod, seed, order):
     """L(theta, Zc) = <Z_k, G> with Z_k = k sweeps (weights exp(theta)) after
-    projecting Zc.  Central differences, h = 1e-6, FP64."""
+    projecting Zc, in either sweep order.  Central differences, h = 1e-6,
+    FP64."""
     O = oracle_mod
     hg = random_hypergraph(20 + seed, 40, 25, 2, 6, weighted=False)
     fine = _level(O, hg)
@@ -91,20 +93,20 @@ def test_finite_differences_theta_and_coarse(oracle_mod, seed):
     k, omega = 4, 0.5
 
     def loss(th, zcoarse):
-        zk, _, _ = O.finest_refine_vjp(fine, c, zcoarse, np.exp(th).astype(np.float32), k, omega, G)
+        zk, _, _ = O.finest_refine_vjp(fine, c, zcoarse, np.exp(th).astype(np.float32), k, omega, G, order)
         return float(np.sum(zk * G))
 
     # weights enter as float32, so dL/dw is checked with steps that are exact
     # in float32 (relative 1e-3); dL/dtheta = w dL/dw is the chain rule.
     w0 = np.exp(theta).astype(np.float32)
-    _, gc, dw = O.finest_refine_vjp(fine, c, zc, w0, k, omega, G)
+    _, gc, dw = O.finest_refine_vjp(fine, c, zc, w0, k, omega, G, order)
     h = 1e-6
     for e in range(0, hg.n_edges, 3):
         wp = w0.astype(np.float64).copy(); wm = wp.copy()
         step = np.float32(w0[e] * (1 + 1e-3)) - w0[e]          # exact float32 step
         wp[e] += step; wm[e] -= step
-        lp = float(np.sum(O.finest_refine_vjp(fine, c, zc, wp.astype(np.float32), k, omega, G)[0] * G))
-        lm = float(np.sum(O.finest_refine_vjp(fine, c, zc, wm.astype(np.float32), k, omega, G)[0] * G))
+        lp = float(np.sum(O.finest_refine_vjp(fine, c, zc, wp.astype(np.float32), k, omega, G, order)[0] * G))
+        lm = float(np.sum(O.finest_refine_vjp(fine, c, zc, wm.astype(np.float32), k, omega, G, order)[0] * G))
         fd = (lp - lm) / (2 * float(step))
         assert abs(fd - dw[e]) <= 1e-5 * max(1.0, abs(dw[e])), (e, fd, dw[e])
     for r in range(0, c.coarse.rows, 4):
