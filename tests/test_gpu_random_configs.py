@@ -104,7 +104,7 @@ def test_random_coarsening(oracle_mod, H, seed):
 def test_random_reverse_mode(oracle_mod, H, seed):
     """Adjoint sweep, weight gradient and projection adjoint (FP32) against
     the oracle's reverse pass on seeded random shapes, widths, tier bounds,
-    ω and hyperedge weights."""
+    ω, hyperedge weights and sweep orders."""
     import torch
     O = oracle_mod
     rng = np.random.default_rng(40_000 + seed)
@@ -116,11 +116,13 @@ def test_random_reverse_mode(oracle_mod, H, seed):
     chunk = int(rng.choice([0, 7, 64]))
     omega = float(rng.choice([0.3, 0.5, 1.0]))
     build = str(rng.choice(["host", "device"]))
-    print("case", seed, n_nodes, n_edges, hi, d, small_max, chunk, omega, build, flush=True)
+    order = str(rng.choice(["jacobi", "edge_first"]))
+    o = 1 if order == "edge_first" else 0
+    print("case", seed, n_nodes, n_edges, hi, d, small_max, chunk, omega, build, order, flush=True)
     hg = random_hypergraph(seed, n_nodes, n_edges, 1, hi, weighted=True)
     levels, maps = O.build_hierarchy(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, 1)
     hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, 1)
-    plan = H.Plan(hier, d, "f32", options={"small_max": small_max, "chunk": chunk}, build=build)
+    plan = H.Plan(hier, d, "f32", options={"small_max": small_max, "chunk": chunk, "order": order}, build=build)
     w = hg.edge_w.astype(np.float32)
     y = rng.standard_normal((levels[0].rows, d)).astype(np.float32)
     g = rng.standard_normal((levels[0].rows, d)).astype(np.float32)
@@ -128,20 +130,22 @@ def test_random_reverse_mode(oracle_mod, H, seed):
     z = plan.sweep(0, yd, omega)
     dw = torch.zeros(levels[0].n_edges, dtype=torch.float32, device="cuda")
     gy = plan.sweep_adjoint(0, gd, yd, z, omega, dw=dw)
-    ref_gy, ref_dw = O.sweep_vjp(levels[0], y, g, omega, w)
+    ref_gy, ref_dw = O.sweep_vjp(levels[0], y, g, omega, w, o)
     assert rel_fro(gy.cpu().numpy(), ref_gy) <= 1e-5
-    # dw_e = ω Σ_{v∈e} <g_v, y_e - z~_v> / S_v can cancel to ~0 (a member with
-    # one hyperedge has z~_v = y_e), so each entry is held to 1e-4 of the size
-    # of its own terms rather than to the norm of dw
+    # dw_e = ω Σ_{v∈e} <g_v, y_e - z~_v> / S_v (e'_e, the new hyperedge row, in
+    # place of y_e in the edge-first order) can cancel to ~0 (a member with one
+    # hyperedge has z~_v = y_e), so each entry is held to 1e-4 of the size of
+    # its own terms rather than to the norm of dw
     lv0 = levels[0]
-    z_ref = O.sweep(lv0, y, omega, 0, w)
+    z_ref = O.sweep(lv0, y, omega, o, w)
     nv = lv0.n_nodes
     ztil = (z_ref[:nv] - (1 - omega) * y[:nv].astype(np.float64)) / omega
     S = np.zeros(nv)
     np.add.at(S, lv0.eidx, np.repeat(w.astype(np.float64), np.diff(lv0.eptr)))
     e_of = np.repeat(np.arange(lv0.n_edges), np.diff(lv0.eptr))
     gv = g[lv0.eidx].astype(np.float64)
-    terms = (np.abs(np.einsum("ij,ij->i", gv, y[nv + e_of].astype(np.float64))) +
+    ye = (y[nv + e_of].astype(np.float64) if o == 0 else z_ref[nv + e_of])
+    terms = (np.abs(np.einsum("ij,ij->i", gv, ye)) +
              np.abs(np.einsum("ij,ij->i", gv, ztil[lv0.eidx]))) / S[lv0.eidx]
     scale = omega * np.bincount(e_of, weights=terms, minlength=lv0.n_edges)
     err = np.abs(dw.cpu().numpy().astype(np.float64) - ref_dw)
