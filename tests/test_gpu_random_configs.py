@@ -134,19 +134,21 @@ def test_random_reverse_mode(oracle_mod, H, seed):
     assert rel_fro(gy.cpu().numpy(), ref_gy) <= 1e-5
     # dw_e = ω Σ_{v∈e} <g_v, y_e - z~_v> / S_v (e'_e, the new hyperedge row, in
     # place of y_e in the edge-first order) can cancel to ~0 (a member with one
-    # hyperedge has z~_v = y_e), so each entry is held to 1e-4 of the size of
-    # its own terms rather than to the norm of dw
+    # hyperedge has z~_v = y_e), and so can each dot product, so each entry is
+    # held to 1e-4 of the sizes its rounding errors scale with: the products
+    # |g_v|·|y_e| of the dot products (a floating-point dot product's error is
+    # bounded by a multiple of sum_i |x_i y_i|) and, for z~_v = (z_v - (1-ω) y_v)/ω
+    # recovered from the stored rows, |g_v|·(|z_v| + (1-ω)|y_v|)/ω
     lv0 = levels[0]
     z_ref = O.sweep(lv0, y, omega, o, w)
     nv = lv0.n_nodes
-    ztil = (z_ref[:nv] - (1 - omega) * y[:nv].astype(np.float64)) / omega
     S = np.zeros(nv)
     np.add.at(S, lv0.eidx, np.repeat(w.astype(np.float64), np.diff(lv0.eptr)))
     e_of = np.repeat(np.arange(lv0.n_edges), np.diff(lv0.eptr))
-    gv = g[lv0.eidx].astype(np.float64)
-    ye = (y[nv + e_of].astype(np.float64) if o == 0 else z_ref[nv + e_of])
-    terms = (np.abs(np.einsum("ij,ij->i", gv, ye)) +
-             np.abs(np.einsum("ij,ij->i", gv, ztil[lv0.eidx]))) / S[lv0.eidx]
+    ag = np.abs(g[lv0.eidx].astype(np.float64))
+    ye = np.abs(y[nv + e_of].astype(np.float64) if o == 0 else z_ref[nv + e_of])
+    rec = (np.abs(z_ref[:nv]) + (1 - omega) * np.abs(y[:nv].astype(np.float64))) / omega
+    terms = (np.einsum("ij,ij->i", ag, ye) + np.einsum("ij,ij->i", ag, rec[lv0.eidx])) / S[lv0.eidx]
     scale = omega * np.bincount(e_of, weights=terms, minlength=lv0.n_edges)
     err = np.abs(dw.cpu().numpy().astype(np.float64) - ref_dw)
     assert np.all(err <= 1e-4 * scale + 1e-30), float(np.max(err / np.maximum(scale, 1e-30)))
