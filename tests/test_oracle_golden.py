@@ -1,5 +1,6 @@
 """The oracle against the hand-worked example in tests/golden/worked_example.txt
-(Algorithm 2 sweeps, Algorithm 1 coarsening, the projection rule)."""
+(Algorithm 2 sweeps in both orders, their reverse mode, Algorithm 1 coarsening,
+the projection rule)."""
 import numpy as np
 
 from tests.golden_io import as_floats, read_fixture
@@ -45,6 +46,17 @@ def test_vjp(oracle_mod):
     gy, dw = O.sweep_vjp(lv, z0, g, float(FX["omega"][0][0]))
     np.testing.assert_allclose(gy, _col("vjp_gz0"), atol=1e-15)
     np.testing.assert_allclose(dw, as_floats(FX["vjp_dw"][0]), atol=1e-15)
+
+
+def test_vjp_edge_first(oracle_mod):
+    O = oracle_mod
+    lv = _level(O)
+    y = _col("ef_vjp_y")
+    g = np.zeros_like(y)
+    g[int(FX["vjp_target_row"][0][0]), 0] = 1.0
+    gy, dw = O.sweep_vjp(lv, y, g, float(FX["omega"][0][0]), order=1)
+    np.testing.assert_allclose(gy, _col("ef_vjp_gz0"), atol=1e-15)
+    np.testing.assert_allclose(dw, as_floats(FX["ef_vjp_dw"][0]), atol=1e-15)
 
 
 def test_coarsen_and_project(oracle_mod):
