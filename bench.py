@@ -217,6 +217,34 @@ def run_differentiable(H, torch, steps, warmup):
             "reverse_node_rows_avg_ms": tn / max(nn_, 1), "reverse_hyperedge_rows_avg_ms": te / max(ne_, 1)}
 
 
+def measure_streams(torch, mib=2048, reps=10):
+    """Two plain streaming operations over `mib` MiB FP32 buffers (each reads
+    the buffer once and writes one of the same size), timed with events on
+    torch's current stream, which both run on: a device-to-device copy
+    (hipMemcpyAsync) and torch's elementwise multiply by a constant.  They
+    give the rate a simple streaming kernel reaches on this part, for
+    comparison with the 8 TB/s peak."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    ops = {"device_copy": lambda: b.copy_(a), "elementwise_scale": lambda: torch.mul(a, 2.0, out=b)}
+    moved = 2 * mib * (1 << 20)
+    out = {}
+    for name, op in ops.items():
+        for _ in range(3):
+            op()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            op()
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"bytes": moved, "ms": ms, "GBps": moved / (ms / 1000.0) / 1e9}
+    del a, b
+    return out
+
+
 def run_reverse(H, torch, plan, z_start, cfg, steps):
     """Reverse sweeps at the finest level (the zipf-8m workload's adjoint
     leg): cfg.adjoint_sweeps forward sweeps from z_start are kept, then as
@@ -736,6 +764,11 @@ def main():
     line["roofline"]["note"] = ("achieved counts every gathered row as streamed (no-reuse model), so L2 hits can "
                                 "lift frac above 1; traffic_GBps / traffic_frac are the bytes the counters saw "
                                 "cross the L2/fabric boundary")
+    streams = measure_streams(torch)
+    line["roofline"]["plain_streams"] = streams
+    if traffic is not None:
+        best = max(v["GBps"] for v in streams.values())
+        line["roofline"]["traffic_over_best_plain_stream"] = line["roofline"]["traffic_GBps"] / best
     if "scoring" in results:
         line["hyperedge_scoring"] = results["scoring"]
     if "pipeline" in results:
