@@ -94,7 +94,7 @@ typedef struct {
     int32_t chunk;       /* neighbours per wavefront work item; longer rows are split */
     int32_t order;       /* HNV_ORDER_*: update order of a sweep (Section 3.3 describes both; the
                             edge-first order is the text's SOR reading, two half-sweeps that may
-                            run in place; the reverse sweep supports HNV_ORDER_JACOBI only) */
+                            run in place; the reverse sweep follows the plan's order) */
 } hnv_options;
 
 typedef struct hnv_plan hnv_plan;

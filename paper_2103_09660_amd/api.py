@@ -553,7 +553,8 @@ class Plan:
     # reverse ---------------------------------------------------------------
     def sweep_adjoint(self, level: int, g_in, z_prev, z_cur, omega: float = 0.5, dw=None, out=None,
                       node_acc=None):
-        """Reverse mode of one sweep.  With ``dw`` the weight gradient is added
+        """Reverse mode of one sweep, in the plan's sweep order (Jacobi or
+        edge-first).  With ``dw`` the weight gradient is added
         to it; with ``node_acc`` too (float32 [n_nodes], zeroed before the
         first of several sweeps) it is split, and :meth:`weight_grad_finish`
         completes ``dw`` after the last sweep."""
