@@ -225,7 +225,8 @@ typedef struct {
  * hnv_plan_workspace_bytes_device gives the workspace size from the level
  * sizes alone (no device reads; the work lists are sized at their upper
  * bounds, and the build's temporaries use the plan's scratch embedding when
- * it is large enough, else extra space after it).  The temporary storage of
+ * it is large enough, else extra space after it).  No level may have more
+ * rows than levels[0], as for hnv_plan_workspace_bytes.  The temporary storage of
  * the GPU sorts and scans is queried from the device, so both calls need a
  * visible GPU.  validate != 0 runs, on the device, the checks that
  * hnv_validate_level and hnv_plan_create(validate = 1) run; offsets, index
