@@ -5,6 +5,9 @@ per-hyperedge log-weights), plus the cross-entropy head."""
 import numpy as np
 import pytest
 
+from hypothesis import given, settings
+from hypothesis import strategies as st
+
 from synth import random_hypergraph
 from tests.dense_ref import edge_first_matrix, jacobi_matrix, star_adjacency
 
@@ -134,3 +137,46 @@ def test_ce_head_gradient(oracle_mod):
             zp[i, j] += h; zm[i, j] -= h
             fd = (O.ce_head(zp, y, W, b)[0] - O.ce_head(zm, y, W, b)[0]) / (2 * h)
             assert abs(fd - dz[i, j]) < 1e-8
+
+
+@st.composite
+def _tiny(draw):
+    n = draw(st.integers(1, 9))
+    m = draw(st.integers(0, 7))
+    edges = [sorted(draw(st.sets(st.integers(0, n - 1), min_size=1, max_size=min(4, n)))) for _ in range(m)]
+    w = [float(draw(st.sampled_from([0.5, 1.0, 2.0, 3.0]))) for _ in range(m)]
+    omega = draw(st.sampled_from([0.25, 0.5, 1.0]))
+    order = draw(st.sampled_from([0, 1]))
+    seed = draw(st.integers(0, 2**31 - 1))
+    return n, edges, w, omega, order, seed
+
+
+@settings(max_examples=200, deadline=None)
+@given(t=_tiny())
+def test_vjp_properties_on_tiny_hypergraphs(t):
+    """Either order on random tiny hypergraphs (empty hyperedge sets,
+    isolated nodes, single-member hyperedges): dL/dy is the dense sweep
+    matrix's transpose times g, and dL/dw equals central differences of the
+    dense FP64 forward form, which shares no code with the oracle."""
+    from oracle import oracle as O
+    n, edges, w, omega, order, seed = t
+    ptr = np.concatenate([[0], np.cumsum([len(e) for e in edges])]).astype(np.int64)
+    idx = np.array([v for e in edges for v in e], dtype=np.int32)
+    wf = np.array(w, dtype=np.float32)
+    lv = O.Level(n, len(edges), ptr, idx, wf)
+    rng = np.random.default_rng(seed)
+    y = rng.standard_normal((lv.rows, 2))
+    g = rng.standard_normal((lv.rows, 2))
+
+    def dense(wv):
+        A = star_adjacency(n, len(edges), ptr, idx, wv)
+        return edge_first_matrix(A, omega, n) if order else jacobi_matrix(A, omega)
+
+    gy, dw = O.sweep_vjp(lv, y, g, omega, wf, order)
+    np.testing.assert_allclose(gy, dense(wf.astype(np.float64)).T @ g, atol=1e-12)
+    h = 1e-6
+    for e in range(len(edges)):
+        wp = wf.astype(np.float64).copy(); wm = wp.copy()
+        wp[e] += h; wm[e] -= h
+        fd = (np.sum((dense(wp) @ y) * g) - np.sum((dense(wm) @ y) * g)) / (2 * h)
+        assert abs(fd - dw[e]) <= 1e-6 * max(1.0, abs(fd)), (e, fd, dw[e])
