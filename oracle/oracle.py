@@ -20,8 +20,10 @@ three phases in order:
   per-dimension variance of a candidate set's member embeddings.
 
 The function groups that have no external pin are listed under
-``PARITY_UNPINNED`` below (empty: every function is pinned by a test in
-``tests/test_oracle_*.py``).
+``PARITY_UNPINNED`` below.  It is empty: every function, the early stop of
+``refine`` included (``tests/test_oracle_early_stop.py``: a closed form of
+the residual and the dense matrix chain), is pinned by a test in
+``tests/test_oracle_*.py``.
 """
 from __future__ import annotations
 
@@ -251,14 +253,24 @@ def residual(z_new: np.ndarray, z_old: np.ndarray) -> float:
 
 def refine(levels: Sequence[Level], maps: Sequence[Coarsening], z_coarsest: np.ndarray,
            sweeps: Sequence[int], omega: float, order: int = 0, tol: float = 0.0,
-           return_residuals: bool = False):
+           return_residuals: bool = False, return_counts: bool = False):
     """Refinement from the coarsest level to the finest (Section 3.3): sweeps
     at the coarsest level, then for each finer level project and sweep.
-    ``sweeps[l]`` is the count for level l.  ``tol > 0`` stops a level early
-    once a sweep changes Z by at most ``tol`` in Frobenius norm."""
+    ``sweeps[l]`` is the count for level l.
+
+    ``tol > 0`` replaces the fixed count of a level by the stopping rule that
+    Section 4 names as the alternative to a fixed iteration count: the
+    level's sweeps end after the first sweep whose change
+    ||Z^i - Z^(i-1)||_F (the whole level's matrix, absolute) is <= tol, or
+    after ``sweeps[l]`` sweeps.  The rule is per level: the next finer level
+    starts from the projection and runs its own sweeps.  The stopping
+    sweep's residual is recorded.  Returns Z of level 0, plus the residuals
+    (coarsest level first) and the sweeps run per level (index = level) when
+    asked for."""
     L = len(levels) - 1
     z = np.ascontiguousarray(z_coarsest, dtype=np.float64)
     res = []
+    counts = [0] * (L + 1)
     for lvl in range(L, -1, -1):
         if lvl < L:
             z = project(rowmap(levels[lvl], maps[lvl]), z)
@@ -266,10 +278,16 @@ def refine(levels: Sequence[Level], maps: Sequence[Coarsening], z_coarsest: np.n
             zn = sweep(levels[lvl], z, omega, order)
             r = residual(zn, z)
             res.append(r)
+            counts[lvl] += 1
             z = zn
             if tol > 0 and r <= tol:
                 break
-    return (z, res) if return_residuals else z
+    out = (z,)
+    if return_residuals:
+        out += (res,)
+    if return_counts:
+        out += (counts,)
+    return out if len(out) > 1 else z
 
 
 def sweep_vjp(lv: Level, y: np.ndarray, g: np.ndarray, omega: float, w: Optional[np.ndarray] = None,
