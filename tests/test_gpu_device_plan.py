@@ -6,7 +6,7 @@ match the FP64 oracle."""
 import numpy as np
 import pytest
 
-from tests.cases import CONFIGS, coarsest_embedding, make_hypergraph, random_hypergraph, rel_fro, tier_hypergraph
+from tests.cases import CONFIGS, assert_close, coarsest_embedding, make_hypergraph, random_hypergraph, tier_hypergraph
 
 pytestmark = pytest.mark.gpu
 
@@ -122,7 +122,7 @@ def test_device_pipeline_vs_oracle(oracle_mod, H):
     zc = coarsest_embedding(cfg, levels[-1].rows, cfg.d)
     out, _, _ = plan.refine(torch.as_tensor(zc).cuda(), list(cfg.sweeps), 0.5)
     ref = O.refine(levels, maps, zc, list(cfg.sweeps), 0.5)
-    assert rel_fro(out.cpu().numpy(), ref) <= 1e-5
+    assert_close(out.cpu().numpy(), ref, 1e-5, "device pipeline vs oracle")
 
 
 def test_device_plan_checks(H):
