@@ -286,6 +286,27 @@ hnv_status hnv_refine(hnv_plan *plan, const void *z_coarsest, void *z_finest,
                       const int32_t *sweeps_per_level, float omega, double tol,
                       double *residuals_dev, int32_t *sweeps_done, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sweep of
+ * hnv_sweep, with the same kernels and bit-identical results, whose scratch --
+ * the FP32 partial sums of rows split over several wavefronts and, when
+ * resid_dev is given, the per-block FP64 residual partials and their two
+ * reduction buffers -- lives in a static device array of
+ * HNV_NOALLOC_SCRATCH_BYTES instead of the plan's workspace.  Each GPU the
+ * library runs on holds that array until the process ends; its address is
+ * looked up once per device, on the first call with the device current.  The
+ * call allocates nothing (no hipMalloc, no hipFree, no allocating library
+ * routine) and enqueues only kernels.  A level whose sweep needs more scratch
+ * than the array holds (reported in the message) returns HNV_EUNSUPPORTED;
+ * hnv_sweep still serves it.  The array keeps the last call's contents and
+ * nothing in it has to start cleared (every entry is written before it is
+ * read).  Every call on one GPU shares that GPU's array: calls that overlap on
+ * one GPU, from any plan or stream, race.  Arguments and the other statuses
+ * as hnv_sweep. */
+#define HNV_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+hnv_status hnv_sweep_noalloc(hnv_plan *plan, int level, const void *z_in, void *z_out, float omega,
+                             int from_coarse, double *resid_dev, void *stream);
+
 /* Projection alone onto level `level` (< L): z_fine[u] = z_coarse[rowmap(u)]. */
 hnv_status hnv_project(hnv_plan *plan, int level, const void *z_coarse, void *z_fine, void *stream);
 

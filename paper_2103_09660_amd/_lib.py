@@ -89,6 +89,7 @@ _SIGS = {
     "hnv_refine": (ctypes.c_int, [vp, vp, vp, i32p, ctypes.c_float, ctypes.c_double, vp, i32p, vp]),
     "hnv_project": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
     "hnv_sweep": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_float, ctypes.c_int, vp, vp]),
+    "hnv_sweep_noalloc": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_float, ctypes.c_int, vp, vp]),
     "hnv_sweep_adjoint": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_float, vp]),
     "hnv_sweep_adjoint_split": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp, vp, vp, vp, ctypes.c_float, vp]),
     "hnv_weight_grad_finish": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),

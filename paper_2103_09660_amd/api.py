@@ -543,6 +543,18 @@ class Plan:
                _ptr(resid), _stream(self.device))
         return z_out
 
+    def sweep_noalloc(self, level: int, z_in, omega: float = 0.5, from_coarse: bool = False, out=None, resid=None):
+        """The same sweep through hnv_sweep_noalloc (scratch in the library's
+        static device array, no allocation by the call itself; ``out`` should
+        be passed by callers that must not allocate)."""
+        self._check(z_in, level + 1 if from_coarse else level, "z_in")
+        z_out = self.empty(level) if out is None else out
+        self._check(z_out, level, "out")
+        _check_vec(resid, 1, _torch().float64, "resid")
+        L.call("hnv_sweep_noalloc", self._h, level, z_in.data_ptr(), z_out.data_ptr(), float(omega),
+               1 if from_coarse else 0, _ptr(resid), _stream(self.device))
+        return z_out
+
     def project(self, level: int, z_coarse, out=None):
         self._check(z_coarse, level + 1, "z_coarse")
         z_out = self.empty(level) if out is None else out

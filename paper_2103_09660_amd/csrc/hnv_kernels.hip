@@ -32,6 +32,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "hnv_grid.h"
@@ -1438,17 +1439,37 @@ static hnv_status dispatch_fwd(hnv_plan *p, bool fused, const GatherArgs &a, hip
                  : dispatch_g<T, kFwd, false>(p->g_fwd, p->epl_fwd, a, p->panels, s, ps);
 }
 
+// Scratch of one forward sweep: the FP32 partial sums of rows split over
+// several wavefronts, and the per-block FP64 residual partials with the two
+// buffers of their reduction stages.  Every entry is written before it is
+// read within the sweep, so nothing needs clearing.
+struct SweepScratch {
+    float *partials;
+    double *resid_part;
+    double *resid_stage;        // [2 x resid_stage_len]
+    int64_t resid_stage_len;
+};
+
+static SweepScratch plan_scratch(const hnv_plan *p)
+{
+    return SweepScratch{p->partials, p->resid_part, p->resid_stage, p->resid_stage_len};
+}
+
 // One forward sweep of `level` (src -> dst); fused reads the coarser level.
 // Jacobi: both sides in one launch, every row reading src.  Edge-first:
 // hyperedge rows first (from src), then node rows, whose neighbours are the
 // new hyperedge rows in dst and whose own value still comes from src.  With
 // ctl (an early-stop refinement) src and dst come from the control block and
-// the residual stage decides on the device whether the level goes on.
+// the residual stage decides on the device whether the level goes on.  The
+// scratch is the plan's workspace unless `scr` names other memory.
 static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, float omega, bool fused,
-                            double *resid_out, hipStream_t s, SweepCtl *ctl = nullptr)
+                            double *resid_out, hipStream_t s, SweepCtl *ctl = nullptr,
+                            const SweepScratch *scr = nullptr)
 {
     LevelPlan &L = p->lv[level];
+    const SweepScratch sc = scr ? *scr : plan_scratch(p);
     GatherArgs a = base_args(p, L, p->g_fwd, p->dp);
+    a.partials = sc.partials;
     a.omega = omega;
     a.src = src;
     a.self_src = src;
@@ -1456,7 +1477,7 @@ static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, 
     a.ctl = ctl;
     a.ctl_level = level;
     a.ctl_src_next = 0;
-    a.resid = (resid_out || ctl) ? p->resid_part : nullptr;
+    a.resid = (resid_out || ctl) ? sc.resid_part : nullptr;
     a.resid_offset = 0;
     const bool bf = p->dtype == HNV_BF16;
     hnv_status st;
@@ -1482,12 +1503,12 @@ static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, 
     if (resid_out || ctl) {
         int64_t mb = 0, fb = 0;
         forward_geometry(p, L, &mb, &fb);
-        const double *in = p->resid_part;
+        const double *in = sc.resid_part;
         int64_t n = mb + fb;
         int which = 0;
         while (n > kResidPer) {
             const int64_t nb = blocks_for(n, kResidPer);
-            double *out = p->resid_stage + which * p->resid_stage_len;
+            double *out = sc.resid_stage + which * sc.resid_stage_len;
             k_resid_stage<<<(unsigned)nb, kBlock, 0, s>>>(in, n, out, 0, ctl, level);
             in = out;
             n = nb;
@@ -1620,6 +1641,86 @@ extern "C" hnv_status hnv_sweep(hnv_plan *plan, int level, const void *z_in, voi
         return fail(HNV_EINVAL, "from_coarse at the coarsest level");
     return run_sweep(plan, level, z_in, z_out, omega, from_coarse != 0, resid_dev,
                      reinterpret_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------------------
+// the forward sweep for callers that cannot allocate: its scratch lives in a
+// static device array instead of the plan's workspace
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[HNV_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];   // per device: the address of `scratch` there (null until looked up)
+}  // namespace
+
+// The device address of `scratch` on the current device, looked up once per
+// device with that device current.  The array's name is a host-side stand-in
+// for the symbol; only this address may reach a kernel.
+static hnv_status scratch_address(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(HNV_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(HNV_EUNSUPPORTED, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(HNV_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                         (e != hipSuccess ? hipGetErrorString(e) : "null address"));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return HNV_OK;
+}
+
+static int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+extern "C" hnv_status hnv_sweep_noalloc(hnv_plan *plan, int level, const void *z_in, void *z_out, float omega,
+                                        int from_coarse, double *resid_dev, void *stream)
+{
+    clear_error();
+    hnv_status st = check_level(plan, level);
+    if (st != HNV_OK)
+        return st;
+    if (!z_in || !z_out)
+        return fail(HNV_EINVAL, "z_in / z_out is NULL");
+    if (z_in == z_out && (plan->opts.order != HNV_ORDER_EDGE_FIRST || from_coarse))
+        return fail(HNV_EINVAL, "z_in and z_out may alias only for an edge-first sweep within a level");
+    if (!aligned16(z_in) || !aligned16(z_out))
+        return fail(HNV_EINVAL, "z_in / z_out must be 16-byte aligned");
+    if (!(omega >= 0.0f && omega <= 1.0f))
+        return fail(HNV_EINVAL, "omega must be in [0, 1]");
+    if (from_coarse && !plan->lv[level].has_coarse)
+        return fail(HNV_EINVAL, "from_coarse at the coarsest level");
+    // the level's scratch, laid out in the static array: residual partials
+    // and stages (only with a residual), then the split-row partial slots
+    const LevelPlan &L = plan->lv[level];
+    int64_t mb = 0, fb = 0;
+    forward_geometry(plan, L, &mb, &fb);
+    const int64_t n_part = resid_dev ? mb + fb : 0;
+    const int64_t stage_len = resid_dev ? blocks_for(n_part, kResidPer) + 1 : 0;
+    const int64_t off_stage = align256(n_part * (int64_t)sizeof(double));
+    const int64_t off_slots = off_stage + align256(2 * stage_len * (int64_t)sizeof(double));
+    const int64_t need = off_slots + (int64_t)L.n_slots * plan->pstride * (int64_t)sizeof(float);
+    if (need > (int64_t)HNV_NOALLOC_SCRATCH_BYTES)
+        return fail(HNV_EUNSUPPORTED, "level " + std::to_string(level) + " needs " + std::to_string(need) +
+                                          " bytes of sweep scratch, more than the static " +
+                                          std::to_string((int64_t)HNV_NOALLOC_SCRATCH_BYTES));
+    void *base = nullptr;
+    if ((st = scratch_address(&base)) != HNV_OK)
+        return st;
+    char *b = static_cast<char *>(base);
+    const SweepScratch sc{reinterpret_cast<float *>(b + off_slots), reinterpret_cast<double *>(b),
+                          reinterpret_cast<double *>(b + off_stage), stage_len};
+    return run_sweep(plan, level, z_in, z_out, omega, from_coarse != 0, resid_dev,
+                     reinterpret_cast<hipStream_t>(stream), nullptr, &sc);
 }
 
 extern "C" hnv_status hnv_project(hnv_plan *plan, int level, const void *z_coarse, void *z_fine, void *stream)
