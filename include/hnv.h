@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define HNV_ABI_VERSION 1
+#define HNV_ABI_VERSION 2
 
 typedef enum {
     HNV_OK = 0,
@@ -61,11 +61,18 @@ typedef enum {
 
 typedef enum { HNV_F32 = 0, HNV_BF16 = 1 } hnv_dtype;
 
-/* One hypergraph of the hierarchy, in HOST memory.
+/* One hypergraph of the hierarchy, in HOST memory: the incidence of the
+ * star expansion H* (Section 1.1) in both directions.
  * edge_ptr[n_edges+1] (edge_ptr[0] = 0, edge_ptr[n_edges] = nnz) and
  * edge_idx[nnz] list each hyperedge's members (node ids in [0, n_nodes),
- * strictly ascending).  edge_w[n_edges] or NULL.  Limits: nnz, n_nodes +
- * n_edges < 2^31. */
+ * strictly ascending): the CSR, hyperedge -> members.  edge_w[n_edges] or
+ * NULL.  node_ptr[n_nodes+1] and node_idx[nnz] are the CSC, node -> its
+ * hyperedges (each list strictly ascending), or both NULL: the library then
+ * derives it from the CSR.  A CSC given by the caller is used by the plan
+ * builders in place of the derived one and is always checked to be the
+ * exact transpose of the CSR (HNV_EINVAL otherwise; only one of the two
+ * pointers NULL is HNV_EINVAL too).  Coarsening ignores it.  Limits: nnz,
+ * n_nodes + n_edges < 2^31. */
 typedef struct {
     int64_t n_nodes;
     int64_t n_edges;
@@ -73,6 +80,8 @@ typedef struct {
     const int64_t *edge_ptr;
     const int32_t *edge_idx;
     const float *edge_w;
+    const int64_t *node_ptr;
+    const int32_t *node_idx;
 } hnv_level;
 
 /* Coarsening maps from level l to level l+1, in HOST memory (Section 3.1:
@@ -107,7 +116,8 @@ int hnv_abi_version(void);
 const char *hnv_last_error(void);
 
 /* Checks a level: offsets, index range, ascending unique member lists,
- * weights finite and > 0, size limits.  Host only. */
+ * weights finite and > 0, size limits, and a CSC if one is given (the exact
+ * transpose of the CSR).  Host only. */
 hnv_status hnv_validate_level(const hnv_level *level);
 
 /* One step of Algorithm 1 without node features (Section 3.1), on the host.
@@ -193,8 +203,11 @@ hnv_status hnv_plan_workspace_bytes(const hnv_level *levels, const hnv_map *maps
                                     int d, hnv_dtype dtype, const hnv_options *opts, size_t *bytes);
 
 /* Builds a plan: the star-expansion adjacency of every level in both
- * directions, the degree-tiered work lists, the row maps of the projection,
- * their inverse, and the FP64-computed reciprocals of the row weight sums.
+ * directions (Section 1.1: V* = V and E, with an edge between each
+ * hyperedge and each of its members), the degree-tiered work lists, the row
+ * maps of the projection (Section 3.3, last paragraph before Algorithm 2),
+ * their inverse, and the FP64-computed reciprocals of the row weight sums
+ * (the denominators of the neighbour mean in Section 3.3).
  * Everything is copied into `workspace` (device memory of ws_bytes >=
  * hnv_plan_workspace_bytes, 256-byte aligned, owned by the caller, must
  * outlive the plan).  The host arrays are not retained.  validate != 0 runs
@@ -248,7 +261,9 @@ hnv_status hnv_plan_level_info(const hnv_plan *plan, int level, int64_t *n_nodes
 
 /* Replaces the hyperedge weights of one level with w_dev[n_edges] (DEVICE,
  * finite, > 0; not checked on the device) and recomputes the row
- * reciprocals 1 / sum_{e ∋ v} w_e in FP64. */
+ * reciprocals 1 / sum_{e ∋ v} w_e in FP64 (Section 3.3: the weight w_uv of
+ * a star edge normalised by the sum over the row's neighbours; a hyperedge
+ * row's own weight cancels in its mean). */
 hnv_status hnv_set_edge_weights(hnv_plan *plan, int level, const float *w_dev, void *stream);
 
 /* As hnv_set_edge_weights with w = exp(theta): theta_dev[n_edges] DEVICE
@@ -268,7 +283,11 @@ hnv_status hnv_set_edge_logweights(hnv_plan *plan, int level, const float *theta
  *   sweeps_per_level: HOST [n_levels], index = level, each >= 0.
  *   omega: relaxation, 0 <= omega <= 1 (Algorithm 2).
  *   tol: <= 0 runs the fixed counts; > 0 also stops a level after the first
- *        sweep whose change ||Z^i - Z^{i-1}||_F is <= tol.  The test is made
+ *        sweep whose change ||Z^i - Z^{i-1}||_F is <= tol (Section 4 names a
+ *        difference of epsilon between consecutive iterations as the
+ *        alternative to a fixed count; the test is absolute, on the whole
+ *        level's matrix, and ends that level only; the next finer level
+ *        starts from the projection and runs its own sweeps).  The test is made
  *        on the device: once a level has stopped, its remaining sweeps return
  *        without work.  The host enqueues a level's sweeps in batches of 1,
  *        2, 4, .. 16 and reads the level's stop flag between batches (a few
@@ -307,7 +326,10 @@ hnv_status hnv_refine(hnv_plan *plan, const void *z_coarsest, void *z_finest,
 hnv_status hnv_sweep_noalloc(hnv_plan *plan, int level, const void *z_in, void *z_out, float omega,
                              int from_coarse, double *resid_dev, void *stream);
 
-/* Projection alone onto level `level` (< L): z_fine[u] = z_coarse[rowmap(u)]. */
+/* Projection alone onto level `level` (< L): z_fine[u] = z_coarse[rowmap(u)]
+ * (Section 3.3: the embedding of a coarse node is given to every fine node
+ * merged into it; a kept hyperedge takes rep(e)'s row and a removed one the
+ * row of the coarse node its members were merged into, Section 3.1). */
 hnv_status hnv_project(hnv_plan *plan, int level, const void *z_coarse, void *z_fine, void *stream);
 
 /* One sweep at `level` (Algorithm 2, one iteration).  If from_coarse != 0,
@@ -360,7 +382,8 @@ hnv_status hnv_sweep_adjoint_split(hnv_plan *plan, int level, const void *g_in, 
 hnv_status hnv_weight_grad_finish(hnv_plan *plan, int level, const float *node_accum, float *dw_accum,
                                   void *stream);
 
-/* Reverse mode of the projection onto `level`: g_coarse[r] = sum of g_fine[u]
+/* Reverse mode of the projection onto `level` (the transpose of the copy
+ * rule of Section 3.3 quoted at hnv_project): g_coarse[r] = sum of g_fine[u]
  * over the fine rows u with rowmap(u) = r, summed in ascending u.  Coarse
  * rows with no preimage get 0. */
 hnv_status hnv_project_adjoint(hnv_plan *plan, int level, const void *g_fine, void *g_coarse,

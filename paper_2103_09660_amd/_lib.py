@@ -31,7 +31,8 @@ vp = ctypes.c_void_p
 
 class HnvLevel(ctypes.Structure):
     _fields_ = [("n_nodes", i64), ("n_edges", i64), ("nnz", i64),
-                ("edge_ptr", i64p), ("edge_idx", i32p), ("edge_w", f32p)]
+                ("edge_ptr", i64p), ("edge_idx", i32p), ("edge_w", f32p),
+                ("node_ptr", i64p), ("node_idx", i32p)]
 
 
 class HnvLevelDev(ctypes.Structure):

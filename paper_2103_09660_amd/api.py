@@ -33,15 +33,21 @@ def last_error() -> str:
 class HostLevel:
     n_nodes: int
     n_edges: int
-    edge_ptr: np.ndarray              # int64 [n_edges+1]
+    edge_ptr: np.ndarray              # int64 [n_edges+1]  CSR: hyperedge -> members
     edge_idx: np.ndarray              # int32 [nnz]
     edge_w: Optional[np.ndarray]      # float32 [n_edges] or None
+    node_ptr: Optional[np.ndarray] = None   # int64 [n_nodes+1]  CSC: node -> hyperedges, or None
+    node_idx: Optional[np.ndarray] = None   # int32 [nnz]
 
     def __post_init__(self):
         self.edge_ptr = np.ascontiguousarray(self.edge_ptr, dtype=np.int64)
         self.edge_idx = np.ascontiguousarray(self.edge_idx, dtype=np.int32)
         if self.edge_w is not None:
             self.edge_w = np.ascontiguousarray(self.edge_w, dtype=np.float32)
+        if self.node_ptr is not None:
+            self.node_ptr = np.ascontiguousarray(self.node_ptr, dtype=np.int64)
+        if self.node_idx is not None:
+            self.node_idx = np.ascontiguousarray(self.node_idx, dtype=np.int32)
 
     @property
     def nnz(self) -> int:
@@ -54,7 +60,9 @@ class HostLevel:
     def c(self) -> L.HnvLevel:
         return L.HnvLevel(self.n_nodes, self.n_edges, self.nnz,
                           self.edge_ptr.ctypes.data_as(L.i64p), self.edge_idx.ctypes.data_as(L.i32p),
-                          None if self.edge_w is None else self.edge_w.ctypes.data_as(L.f32p))
+                          None if self.edge_w is None else self.edge_w.ctypes.data_as(L.f32p),
+                          None if self.node_ptr is None else self.node_ptr.ctypes.data_as(L.i64p),
+                          None if self.node_idx is None else self.node_idx.ctypes.data_as(L.i32p))
 
 
 @dataclasses.dataclass

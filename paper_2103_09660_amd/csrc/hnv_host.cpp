@@ -133,10 +133,40 @@ static bool edge_ok(const hnv_level *lv, int64_t e, bool full)
     return !(full && lv->edge_w && (!(lv->edge_w[e] > 0.0f) || !std::isfinite(lv->edge_w[e])));
 }
 
+// A CSC given with the level must be the exact transpose of the CSR: offsets
+// from 0 to nnz that never decrease, and, walking the hyperedges in
+// ascending id, every member v's next unread CSC entry is that hyperedge.
+// Each entry is then read exactly once, so the lists hold precisely the
+// hyperedges of each node in ascending order.  Needs the CSR checked first.
+static hnv_status check_csc(const hnv_level *lv)
+{
+    if (!lv->node_ptr && !lv->node_idx)
+        return HNV_OK;
+    if (!lv->node_ptr || (!lv->node_idx && lv->nnz > 0))
+        return fail(HNV_EINVAL, "node_ptr and node_idx must both be given or both be NULL");
+    const int64_t nV = lv->n_nodes;
+    if (lv->node_ptr[0] != 0 || lv->node_ptr[nV] != lv->nnz)
+        return fail(HNV_EINVAL, "node_ptr must start at 0 and end at nnz");
+    for (int64_t v = 0; v < nV; ++v)
+        if (lv->node_ptr[v + 1] < lv->node_ptr[v])
+            return fail(HNV_EINVAL, "node_ptr decreases at node " + std::to_string(v));
+    std::vector<int64_t> next(lv->node_ptr, lv->node_ptr + nV);
+    for (int64_t e = 0; e < lv->n_edges; ++e)
+        for (int64_t j = lv->edge_ptr[e]; j < lv->edge_ptr[e + 1]; ++j) {
+            const int32_t v = lv->edge_idx[j];
+            if (next[v] >= lv->node_ptr[v + 1] || lv->node_idx[next[v]] != e)
+                return fail(HNV_EINVAL, "node_idx is not the transpose of edge_idx (node " + std::to_string(v) +
+                                            ", hyperedge " + std::to_string(e) + ")");
+            ++next[v];
+        }
+    return HNV_OK;
+}
+
 // full = false checks only what memory safety needs (offsets and index
 // ranges); full = true also checks ordering, emptiness and weights.  The
 // offsets are checked first, then the hyperedges in parallel ranges; the
-// error reported is the one of the lowest failing hyperedge.
+// error reported is the one of the lowest failing hyperedge.  A CSC given
+// with the level is always checked (the kernels trust it).
 static hnv_status validate(const hnv_level *lv, bool full = true)
 {
     if (!lv)
@@ -165,7 +195,9 @@ static hnv_status validate(const hnv_level *lv, bool full = true)
             }
     }, 1 << 14);
     const int64_t e = first_bad.load();
-    return e == std::numeric_limits<int64_t>::max() ? HNV_OK : check_edge(lv, e, full);
+    if (e != std::numeric_limits<int64_t>::max())
+        return check_edge(lv, e, full);
+    return check_csc(lv);
 }
 
 // ---------------------------------------------------------------------------
@@ -438,6 +470,19 @@ static hnv_status check_shape(const hnv_level *levels, const hnv_map *maps, int 
                                               " has more rows than level 0 (iterates live in buffers of its size)");
         if (l + 1 < n_levels && (!maps[l].node_rep || (L.n_edges > 0 && !maps[l].edge_rep)))
             return fail(HNV_EINVAL, "map " + std::to_string(l) + " has a NULL array");
+        // a caller's CSC: its offsets size the node side before the full
+        // transpose check, so they are checked here
+        if (L.node_ptr || L.node_idx) {
+            if (!L.node_ptr || (!L.node_idx && L.nnz > 0))
+                return fail(HNV_EINVAL, "level " + std::to_string(l) + ": node_ptr and node_idx must both be given "
+                                                                           "or both be NULL");
+            if (L.node_ptr[0] != 0 || L.node_ptr[L.n_nodes] != L.nnz)
+                return fail(HNV_EINVAL, "level " + std::to_string(l) + ": node_ptr must start at 0 and end at nnz");
+            for (int64_t v = 0; v < L.n_nodes; ++v)
+                if (L.node_ptr[v + 1] < L.node_ptr[v])
+                    return fail(HNV_EINVAL, "level " + std::to_string(l) + ": node_ptr decreases at node " +
+                                                std::to_string(v));
+        }
     }
     return HNV_OK;
 }
@@ -482,8 +527,15 @@ static void build_level(const hnv_level *levels, const hnv_map *maps, int n_leve
     h.ptr[0].resize(h.nE + 1);
     for (int64_t e = 0; e <= h.nE; ++e)
         h.ptr[0][e] = (int32_t)L.edge_ptr[e];
-    // side 1: node rows -> incident hyperedges (Z row = n_nodes + e)
-    if (with_arrays) {
+    // side 1: node rows -> incident hyperedges (Z row = n_nodes + e), the
+    // caller's CSC (checked to be the transpose) or derived from the CSR
+    if (L.node_ptr) {
+        h.ptr[1].resize(h.nV + 1);
+        for (int64_t v = 0; v <= h.nV; ++v)
+            h.ptr[1][v] = (int32_t)L.node_ptr[v];
+        if (with_arrays)
+            h.idx[1].assign(L.node_idx, L.node_idx + h.nnz);
+    } else if (with_arrays) {
         incidence_by_node(&L, h.ptr[1], h.idx[1]);
     } else {
         std::vector<int32_t> cnt;

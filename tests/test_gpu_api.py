@@ -138,3 +138,37 @@ def test_binding_checks_vectors_before_calling(setup):
     # valid vectors still pass (the level's own weights, so the shared plan is unchanged)
     plan.set_edge_weights(0, torch.as_tensor(hier.levels[0].edge_w).cuda())
     assert torch.isfinite(sp.score(torch.ones(10, 32, **f32))).all()
+
+
+def test_plan_from_a_caller_csc(setup):
+    """A level that carries its own CSC (node -> hyperedges) gives the plan
+    the derived CSC gives, hence a bit-identical refinement and reverse
+    sweep; a CSC that is not the transpose is refused at plan creation."""
+    import dataclasses
+    from paper_2103_09660_amd._lib import HNV_EINVAL, HnvError
+    H, torch, hier, plan = setup
+    lv0 = hier.levels[0]
+    order = np.argsort(lv0.edge_idx, kind="stable")          # incidences by node, hyperedges ascending
+    e_of = np.repeat(np.arange(lv0.n_edges, dtype=np.int32), np.diff(lv0.edge_ptr))
+    nptr = np.concatenate([[0], np.cumsum(np.bincount(lv0.edge_idx, minlength=lv0.n_nodes))]).astype(np.int64)
+    nidx = e_of[order]
+    with_csc = H.Hierarchy([dataclasses.replace(lv0, node_ptr=nptr, node_idx=nidx)] + hier.levels[1:], hier.maps)
+    p2 = H.Plan(with_csc, 32, "f32")
+    zc = torch.randn((hier.levels[-1].rows, 32), device="cuda")
+    a, _, _ = plan.refine(zc, [2, 2, 2], 0.5)
+    b, _, _ = p2.refine(zc, [2, 2, 2], 0.5)
+    assert torch.equal(a, b)
+    g = torch.randn_like(a)
+    dw1 = torch.zeros(lv0.n_edges, device="cuda")
+    dw2 = torch.zeros(lv0.n_edges, device="cuda")
+    z1 = plan.sweep(0, a, 0.5)
+    assert torch.equal(plan.sweep_adjoint(0, g, a, z1, 0.5, dw=dw1), p2.sweep_adjoint(0, g, a, z1, 0.5, dw=dw2))
+    assert torch.equal(dw1, dw2)
+    bad = nidx.copy()
+    bad[0] = (bad[0] + 1) % lv0.n_edges
+    with pytest.raises(HnvError) as ei:
+        H.Plan(H.Hierarchy([dataclasses.replace(lv0, node_ptr=nptr, node_idx=bad)] + hier.levels[1:], hier.maps),
+               32, "f32")
+    assert ei.value.status == HNV_EINVAL
+    torch.cuda.synchronize()
+

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_call(H):
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(_lib.exported_names()) == names
-    assert H.abi_version() == 1
+    assert H.abi_version() == 2
 
 
 def _lvl(H, n_nodes, edges, w=None):
@@ -62,6 +62,66 @@ def test_validation_status_codes(H):
         assert H.last_error() != ""
         with pytest.raises(HnvError):
             H.coarsen_level(lv)
+
+
+def _csc(n_nodes, ptr, idx):
+    """The transpose written out from its definition: node v's hyperedges in
+    ascending id."""
+    lists = [[] for _ in range(n_nodes)]
+    for e in range(len(ptr) - 1):
+        for j in range(ptr[e], ptr[e + 1]):
+            lists[idx[j]].append(e)
+    nptr = np.concatenate([[0], np.cumsum([len(x) for x in lists])]).astype(np.int64)
+    nidx = np.array([e for x in lists for e in x], dtype=np.int32)
+    return nptr, nidx
+
+
+def test_caller_csc_is_checked_as_the_exact_transpose(H):
+    """A level may carry its CSC (node -> hyperedges); it must be the exact
+    transpose of the CSR, and a plan sized from it is the one sized from the
+    CSR alone."""
+    import dataclasses
+    from paper_2103_09660_amd._lib import HNV_EINVAL, HnvError
+    hg = random_hypergraph(4, 300, 200, 1, 9, weighted=True)
+    nptr, nidx = _csc(hg.n_nodes, hg.edge_ptr, hg.edge_idx)
+    base = H.HostLevel(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w)
+    good = dataclasses.replace(base, node_ptr=nptr, node_idx=nidx)
+    H.validate_level(good)
+    bad = []
+    swapped = nidx.copy()                       # a list out of order
+    v = int(np.argmax(np.diff(nptr) >= 2))
+    swapped[nptr[v]], swapped[nptr[v] + 1] = swapped[nptr[v] + 1], swapped[nptr[v]]
+    bad.append(("unsorted list", nptr, swapped))
+    wrong = nidx.copy()                         # a hyperedge that does not hold the node
+    wrong[nptr[v]] = (wrong[nptr[v]] + 1) % hg.n_edges
+    bad.append(("foreign hyperedge", nptr, wrong))
+    moved = nptr.copy()                         # an entry moved to the next node
+    moved[v + 1] -= 1
+    bad.append(("shifted offsets", moved, nidx))
+    short = nptr.copy()
+    short[-1] -= 1
+    bad.append(("does not end at nnz", short, nidx))
+    for what, p, i in bad:
+        with pytest.raises(HnvError) as ei:
+            H.validate_level(dataclasses.replace(base, node_ptr=p, node_idx=i))
+        assert ei.value.status == HNV_EINVAL, what
+    with pytest.raises(HnvError) as ei:
+        H.validate_level(dataclasses.replace(base, node_ptr=nptr))
+    assert ei.value.status == HNV_EINVAL
+    # the plan's size does not depend on where the CSC comes from
+    hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, 1)
+    with_csc = H.Hierarchy([dataclasses.replace(hier.levels[0], node_ptr=nptr, node_idx=nidx)] + hier.levels[1:],
+                           hier.maps)
+    for d, dt in ((64, "bf16"), (32, "f32")):
+        assert H.plan_workspace_bytes(with_csc, d, dt) == H.plan_workspace_bytes(hier, d, dt)
+    # sizing reads the CSC's offsets, so they are checked there too
+    dec = nptr.copy()
+    dec[v + 1] = dec[v] - 1
+    bad_hier = H.Hierarchy([dataclasses.replace(hier.levels[0], node_ptr=dec, node_idx=nidx)] + hier.levels[1:],
+                           hier.maps)
+    with pytest.raises(HnvError) as ei:
+        H.plan_workspace_bytes(bad_hier, 64, "bf16")
+    assert ei.value.status == HNV_EINVAL
 
 
 def test_workspace_sizing_errors(H):
@@ -155,3 +215,4 @@ def test_size_limits_rejected_before_any_read(H):
     lv = L.HnvLevel(4, 1, 2, ctypes.cast((ctypes.c_int64 * 2)(0, 2), L.i64p),
                     ctypes.cast((ctypes.c_int32 * 2)(0, 1), L.i32p), None)
     assert lib.hnv_validate_level(ctypes.byref(lv)) == L.HNV_OK
+
