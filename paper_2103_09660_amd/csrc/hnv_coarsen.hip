@@ -29,7 +29,7 @@
 // quotient, so the choice does not depend on summation order.
 #include <hip/hip_runtime.h>
 
-#include <hipcub/hipcub.hpp>
+#include "hnv_prim.h"
 
 #include <climits>
 #include <string>
@@ -540,11 +540,11 @@ __global__ __launch_bounds__(kThreads) void k_group_fill(const int32_t *__restri
 hnv_status sort_storage(int64_t nE, int64_t nnz, int key_bits, int member_bits, size_t &t_keys, size_t &t_members)
 {
     t_keys = t_members = 0;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, t_keys, (uint64_t *)nullptr, (uint64_t *)nullptr,
+    hipError_t e = prim_sort_pairs(nullptr, t_keys, (uint64_t *)nullptr, (uint64_t *)nullptr,
                                                       (int32_t *)nullptr, (int32_t *)nullptr,
                                                       (int)std::max<int64_t>(nE, 1), 0, key_bits);
     if (e == hipSuccess)
-        e = hipcub::DeviceSegmentedRadixSort::SortKeys(nullptr, t_members, (uint32_t *)nullptr, (uint32_t *)nullptr,
+        e = prim_segmented_sort_keys(nullptr, t_members, (uint32_t *)nullptr, (uint32_t *)nullptr,
                                                        (int)std::max<int64_t>(nnz, 1), (int)std::max<int64_t>(nE, 1),
                                                        (int32_t *)nullptr, (int32_t *)nullptr, 0, member_bits);
     if (e != hipSuccess)
@@ -603,15 +603,14 @@ hnv_status layout(int64_t nV, int64_t nE, int64_t nnz, int k, CoarsenLayout &L)
     size_t t1 = 0, t2 = 0, t3 = 0, t4 = 0;
     if (hnv_status st = sort_storage(nE, nnz, 64, 32, t1, t4); st != HNV_OK)
         return st;
-    hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, t2, (int32_t *)nullptr, (int32_t *)nullptr,
+    hipError_t e = prim_exclusive_sum(nullptr, t2, (int32_t *)nullptr, (int32_t *)nullptr,
                                                     (int)std::max<int64_t>(nV + 1, 1));
     if (e == hipSuccess)
-        e = hipcub::DeviceScan::ExclusiveSum(nullptr, t3, (int32_t *)nullptr, (int32_t *)nullptr,
+        e = prim_exclusive_sum(nullptr, t3, (int32_t *)nullptr, (int32_t *)nullptr,
                                              (int)std::max<int64_t>(std::max(nE, nnz), 1));
     size_t t5 = 0;
     if (e == hipSuccess)
-        e = hipcub::DeviceScan::InclusiveScan(nullptr, t5, (int32_t *)nullptr, (int32_t *)nullptr, hipcub::Max(),
-                                              (int)std::max<int64_t>(nnz, 1));
+        e = prim_inclusive_max(nullptr, t5, (int32_t *)nullptr, (int32_t *)nullptr, (int)std::max<int64_t>(nnz, 1));
     if (e != hipSuccess)
         return fail(HNV_EDEVICE, std::string("scan storage query (needs a visible GPU): ") + hipGetErrorString(e));
     L.temp_bytes = std::max(std::max(std::max(t1, t2), std::max(t3, t4)), t5);
@@ -680,7 +679,7 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
             k_fill<<<grid_for(nz), kThreads, 0, s>>>(dpos, nnz, 0);
             k_heads<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, n_edges, nnz, dpos);
             size_t tbs = L.temp_bytes;
-            if (hipcub::DeviceScan::InclusiveScan(base + L.temp, tbs, dpos, inc_edge, hipcub::Max(), nz, s) !=
+            if (prim_inclusive_max(base + L.temp, tbs, dpos, inc_edge, nz, s) !=
                 hipSuccess)
                 return fail(HNV_EDEVICE, "scan of hyperedge heads");
             k_check_members<<<grid_for(nz), kThreads, 0, s>>>(edge_ptr, edge_idx, inc_edge, n_nodes, n_edges, nnz, 1,
@@ -739,7 +738,7 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
         uint64_t *kin = reinterpret_cast<uint64_t *>(base + L.keys_in);
         uint64_t *kout = reinterpret_cast<uint64_t *>(base + L.keys_out);
         k_keys<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, edge_w, n_edges, kin, at(L.ids_in));
-        if (hipcub::DeviceRadixSort::SortPairs(temp, tb, kin, kout, at(L.ids_in), order, nE, 0, key_bits, s) != hipSuccess)
+        if (prim_sort_pairs(temp, tb, kin, kout, at(L.ids_in), order, nE, 0, key_bits, s) != hipSuccess)
             return fail(HNV_EDEVICE, "radix sort of hyperedge keys");
         k_rank<<<grid_for(nE), kThreads, 0, s>>>(order, n_edges, rank);
         k_fill<<<grid_for(nE), kThreads, 0, s>>>(first, n_edges, INT_MAX);
@@ -772,7 +771,7 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
         // 3. group numbering by smallest node
         k_group_flags<<<grid_for(nV), kThreads, 0, s>>>(choice, first, n_nodes, gflag);
         tb = L.temp_bytes;
-        if (hipcub::DeviceScan::ExclusiveSum(temp, tb, gflag, gid, nV, s) != hipSuccess)
+        if (prim_exclusive_sum(temp, tb, gflag, gid, nV, s) != hipSuccess)
             return fail(HNV_EDEVICE, "scan of group flags");
         k_node_rep<<<grid_for(nV), kThreads, 0, s>>>(choice, first, gid, n_nodes, node_rep);
     }
@@ -780,21 +779,21 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
         // 4. removed hyperedges
         k_kept_flags<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, count, n_edges, kept);
         tb = L.temp_bytes;
-        if (hipcub::DeviceScan::ExclusiveSum(temp, tb, kept, krank, nE, s) != hipSuccess)
+        if (prim_exclusive_sum(temp, tb, kept, krank, nE, s) != hipSuccess)
             return fail(HNV_EDEVICE, "scan of kept flags");
         // 5. coarse member sets
         if (nz > 0) {
             k_map<<<grid_for(nz), kThreads, 0, s>>>(edge_idx, node_rep, nnz, mapped);
             tb = L.temp_bytes;
             // non-negative ids: sorted as unsigned so only the low bits count
-            if (hipcub::DeviceSegmentedRadixSort::SortKeys(temp, tb, reinterpret_cast<const uint32_t *>(mapped),
+            if (prim_segmented_sort_keys(temp, tb, reinterpret_cast<const uint32_t *>(mapped),
                                                            reinterpret_cast<uint32_t *>(sorted), nz, nE, edge_ptr,
                                                            edge_ptr + 1, 0, member_bits, s) != hipSuccess)
                 return fail(HNV_EDEVICE, "segmented sort of coarse members");
         }
         k_distinct<<<grid_for(nz), kThreads, 0, s>>>(edge_ptr, sorted, inc_edge, kept, nnz, dflag);
         tb = L.temp_bytes;
-        if (hipcub::DeviceScan::ExclusiveSum(temp, tb, dflag, dpos, nz, s) != hipSuccess)
+        if (prim_exclusive_sum(temp, tb, dflag, dpos, nz, s) != hipSuccess)
             return fail(HNV_EDEVICE, "scan of coarse members");
         k_emit_members<<<grid_for(nz), kThreads, 0, s>>>(sorted, dflag, dpos, nnz, c_edge_idx);
         k_emit_edges<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, kept, krank, dpos, edge_w, n_edges, edge_rep,
@@ -808,7 +807,7 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
         k_fill<<<grid_for(nV), kThreads, 0, s>>>(gcur, n_nodes, 0);
         k_group_count<<<grid_for(nV), kThreads, 0, s>>>(node_rep, n_nodes, gcount);
         tb = L.temp_bytes;
-        if (hipcub::DeviceScan::ExclusiveSum(temp, tb, gcount, gptr, nV + 1, s) != hipSuccess)
+        if (prim_exclusive_sum(temp, tb, gcount, gptr, nV + 1, s) != hipSuccess)
             return fail(HNV_EDEVICE, "scan of group sizes");
         k_group_fill<<<grid_for(nV), kThreads, 0, s>>>(node_rep, gptr, n_nodes, gcur, gnodes);
         const dim3 wave_grid = fold_grid((n_nodes + kThreads / kWave - 1) / (kThreads / kWave));

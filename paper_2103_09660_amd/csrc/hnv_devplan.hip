@@ -16,7 +16,7 @@
 // scratch embedding when it is large enough, else after the plan.
 #include <hip/hip_runtime.h>
 
-#include <hipcub/hipcub.hpp>
+#include "hnv_prim.h"
 
 #include <algorithm>
 #include <climits>
@@ -295,15 +295,14 @@ hnv_status cub_sizes(int64_t nnz, int64_t rows, int64_t n_chunks, size_t &bytes)
 {
     size_t t[6] = {0, 0, 0, 0, 0, 0};
     const int n = (int)std::max<int64_t>(std::max(nnz, rows) + 1, 1);
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, t[0], (uint32_t *)nullptr, (uint32_t *)nullptr,
+    hipError_t e = prim_sort_pairs(nullptr, t[0], (uint32_t *)nullptr, (uint32_t *)nullptr,
                                                       (int32_t *)nullptr, (int32_t *)nullptr, n, 0, 32);
     if (e == hipSuccess)
-        e = hipcub::DeviceScan::ExclusiveSum(nullptr, t[1], (int32_t *)nullptr, (int32_t *)nullptr, n);
+        e = prim_exclusive_sum(nullptr, t[1], (int32_t *)nullptr, (int32_t *)nullptr, n);
     if (e == hipSuccess)
-        e = hipcub::DeviceScan::InclusiveScan(nullptr, t[2], (int32_t *)nullptr, (int32_t *)nullptr, hipcub::Max(),
-                                              (int)std::max<int64_t>(nnz, 1));
+        e = prim_inclusive_max(nullptr, t[2], (int32_t *)nullptr, (int32_t *)nullptr, (int)std::max<int64_t>(nnz, 1));
     if (e == hipSuccess)
-        e = hipcub::DeviceRadixSort::SortPairs(nullptr, t[3], (uint32_t *)nullptr, (uint32_t *)nullptr,
+        e = prim_sort_pairs(nullptr, t[3], (uint32_t *)nullptr, (uint32_t *)nullptr,
                                                (int32_t *)nullptr, (int32_t *)nullptr,
                                                (int)std::max<int64_t>(n_chunks, 1), 0, 32);
     if (e != hipSuccess)
@@ -429,7 +428,7 @@ hnv_status check_level(const hnv_level_dev &L, const hnv_level_dev *C, const hnv
             k_fill<<<grid_for(nnz), kThreads, 0, s>>>(S.heads, nnz, 0);
             k_heads<<<grid_for(nE), kThreads, 0, s>>>(L.edge_ptr, nE, nnz, S.heads);
             size_t tb = S.temp_bytes;
-            if (hipcub::DeviceScan::InclusiveScan(S.temp, tb, S.heads, S.inc_edge, hipcub::Max(), (int)nnz, s) !=
+            if (prim_inclusive_max(S.temp, tb, S.heads, S.inc_edge, (int)nnz, s) !=
                 hipSuccess)
                 return fail(HNV_EDEVICE, "scan of hyperedge heads");
             k_check_members<<<grid_for(nnz), kThreads, 0, s>>>(L.edge_ptr, L.edge_idx, S.inc_edge, nV, nE, nnz,
@@ -499,17 +498,17 @@ hnv_status tier_scan(const int32_t *ptr, int64_t n_rows, int small_max, int chun
     k_tier_keys<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, small_max, chunk, S.key_a, S.rows_a, S.pieces,
                                                       S.split, S.slots);
     size_t tb = S.temp_bytes;
-    if (hipcub::DeviceRadixSort::SortPairs(S.temp, tb, S.key_a, S.key_b, S.rows_a, S.rows_b, n, 0,
+    if (prim_sort_pairs(S.temp, tb, S.key_a, S.key_b, S.rows_a, S.rows_b, n, 0,
                                            bits_for(small_max + 2), s) != hipSuccess)
         return fail(HNV_EDEVICE, "sort of the lane-group tier");
     tb = S.temp_bytes;
-    if (hipcub::DeviceScan::ExclusiveSum(S.temp, tb, S.pieces, S.cpos, n, s) != hipSuccess)
+    if (prim_exclusive_sum(S.temp, tb, S.pieces, S.cpos, n, s) != hipSuccess)
         return fail(HNV_EDEVICE, "scan of chunk counts");
     tb = S.temp_bytes;
-    if (hipcub::DeviceScan::ExclusiveSum(S.temp, tb, S.split, S.spos, n, s) != hipSuccess)
+    if (prim_exclusive_sum(S.temp, tb, S.split, S.spos, n, s) != hipSuccess)
         return fail(HNV_EDEVICE, "scan of split rows");
     tb = S.temp_bytes;
-    if (hipcub::DeviceScan::ExclusiveSum(S.temp, tb, S.slots, S.sbase, n, s) != hipSuccess)
+    if (prim_exclusive_sum(S.temp, tb, S.slots, S.sbase, n, s) != hipSuccess)
         return fail(HNV_EDEVICE, "scan of partial slots");
     k_tier_counts<<<1, 64, 0, s>>>(S.key_b, S.pieces, S.cpos, S.split, S.spos, S.slots, S.sbase, n_rows, small_max,
                                    counts);
@@ -530,7 +529,7 @@ hnv_status tier_emit(const int32_t *ptr, int64_t n_rows, int small_max, int chun
         k_chunk_items<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, chunk, S.pieces, S.cpos, S.sbase,
                                                             slot_offset, S.items, S.key_a, S.ids_a);
         size_t tb = S.temp_bytes;
-        if (hipcub::DeviceRadixSort::SortPairs(S.temp, tb, S.key_a, S.key_b, S.ids_a, S.ids_b, (int)cnt[1], 0,
+        if (prim_sort_pairs(S.temp, tb, S.key_a, S.key_b, S.ids_a, S.ids_b, (int)cnt[1], 0,
                                                bits_for(chunk + 1), s) != hipSuccess)
             return fail(HNV_EDEVICE, "sort of the wavefront tier");
         k_gather_items<<<grid_for(cnt[1]), kThreads, 0, s>>>(S.items, S.ids_b, cnt[1],
@@ -563,7 +562,7 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
     // by node; the offsets come from the sorted node ids)
     size_t tb = S.temp_bytes;
     if (nnz > 0) {
-        if (hipcub::DeviceRadixSort::SortPairs(S.temp, tb, reinterpret_cast<const uint32_t *>(lv.edge_idx),
+        if (prim_sort_pairs(S.temp, tb, reinterpret_cast<const uint32_t *>(lv.edge_idx),
                                                reinterpret_cast<uint32_t *>(S.keys_out), S.inc_edge, S.csc_e,
                                                (int)nnz, 0, bits_for(nV), s) != hipSuccess)
             return fail(HNV_EDEVICE, "sort of incidences by node");
@@ -583,7 +582,7 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
         if (rows > 0) {
             k_iota<<<grid_for(rows), kThreads, 0, s>>>(rows, S.rows_a);
             tb = S.temp_bytes;
-            if (hipcub::DeviceRadixSort::SortPairs(S.temp, tb, reinterpret_cast<const uint32_t *>(L.rowmap),
+            if (prim_sort_pairs(S.temp, tb, reinterpret_cast<const uint32_t *>(L.rowmap),
                                                    reinterpret_cast<uint32_t *>(S.keys_out), S.rows_a, L.inv_idx,
                                                    (int)rows, 0, bits_for(rows_c), s) != hipSuccess)
                 return fail(HNV_EDEVICE, "sort of the inverse map");

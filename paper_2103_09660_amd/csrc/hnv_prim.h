@@ -1,0 +1,54 @@
+// Library sort and scan primitives of the GPU coarsening and the device plan
+// builder, called straight from rocPRIM.  Each takes rocPRIM's two-phase
+// form: with temp == nullptr it only writes the temporary storage it needs
+// to `bytes`; otherwise it enqueues the work on `s`.  The radix sorts are
+// stable (least significant digit first), which the callers rely on for
+// their tie orders.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+#include <rocprim/device/device_segmented_radix_sort.hpp>
+#include <rocprim/functional.hpp>
+
+namespace hnv {
+
+// (key, value) pairs by key bits [begin_bit, end_bit), stable.
+template <typename K, typename V>
+inline hipError_t prim_sort_pairs(void *temp, size_t &bytes, const K *keys_in, K *keys_out, const V *vals_in,
+                                  V *vals_out, int64_t n, int begin_bit, int end_bit, hipStream_t s = 0)
+{
+    return rocprim::radix_sort_pairs(temp, bytes, keys_in, keys_out, vals_in, vals_out, (size_t)n,
+                                     (unsigned)begin_bit, (unsigned)end_bit, s);
+}
+
+// Keys of each segment [begin[i], end[i]) sorted independently, stable.
+template <typename K, typename O>
+inline hipError_t prim_segmented_sort_keys(void *temp, size_t &bytes, const K *keys_in, K *keys_out, int64_t n,
+                                           int64_t segments, O begin, O end, int begin_bit, int end_bit,
+                                           hipStream_t s = 0)
+{
+    return rocprim::segmented_radix_sort_keys(temp, bytes, keys_in, keys_out, (unsigned)n, (unsigned)segments,
+                                              begin, end, (unsigned)begin_bit, (unsigned)end_bit, s);
+}
+
+// out[i] = in[0] + .. + in[i-1], out[0] = 0.
+template <typename T>
+inline hipError_t prim_exclusive_sum(void *temp, size_t &bytes, const T *in, T *out, int64_t n, hipStream_t s = 0)
+{
+    return rocprim::exclusive_scan(temp, bytes, in, out, T(0), (size_t)n, rocprim::plus<T>(), s);
+}
+
+// out[i] = max(in[0], .., in[i]).
+template <typename T>
+inline hipError_t prim_inclusive_max(void *temp, size_t &bytes, const T *in, T *out, int64_t n, hipStream_t s = 0)
+{
+    return rocprim::inclusive_scan(temp, bytes, in, out, (size_t)n, rocprim::maximum<T>(), s);
+}
+
+}  // namespace hnv
