@@ -31,10 +31,61 @@ def test_byte_models():
 def test_counters_follow_the_kernel_source(tmp_path, monkeypatch):
     import bench
     path = tmp_path / "counters.txt"
-    path.write_text("# header\nhbm_bytes_per_launch = 1.5e9\nkernel_source_sha256 = %s\n" % bench.kernel_source_digest())
+    path.write_text("# header\nbf16.traffic_bytes_per_launch = 1.5e9\nbf16.l2_hit_rate = 0.25\n"
+                    "kernel_source_sha256 = %s\n" % bench.kernel_source_digest())
     monkeypatch.setitem(bench.COUNTERS_FILES, "x", str(path))
-    assert bench.read_counters("x") == pytest.approx(1.5e9)
-    path.write_text("hbm_bytes_per_launch = 1.5e9\nkernel_source_sha256 = 0000\n")
-    assert bench.read_counters("x") is None
-    assert bench.read_counters("no-such-workload") is None
+    got = bench.read_counters("x", "bf16")
+    assert got["traffic_bytes_per_launch"] == pytest.approx(1.5e9) and got["l2_hit_rate"] == 0.25
+    assert bench.read_counters("x", "f32") is None
+    path.write_text("bf16.traffic_bytes_per_launch = 1.5e9\nkernel_source_sha256 = 0000\n")
+    assert bench.read_counters("x", "bf16") is None
+    assert bench.read_counters("no-such-workload", "bf16") is None
 
+
+def _write_pass(d, rows):
+    import csv
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "1_counter_collection.csv"), "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for r in rows:
+            w.writerow(dict(zip(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"], r)))
+
+
+def test_counter_summary_bytes_from_sized_requests(tmp_path):
+    """Bytes per launch from the size-split request counts, averaged over the
+    kernel's dispatches, for the sweep kernel and the copy calibration."""
+    import bench
+    k = bench.SWEEP_KERNELS["bf16"]
+    cp = "__amd_rocclr_copyBuffer"
+    reads = []
+    for disp, (r128, r64, r32) in ((1, (100, 10, 4)), (2, (300, 30, 0))):
+        reads += [(disp, k, "TCC_EA0_RDREQ_sum", r128 + r64 + r32), (disp, k, "TCC_EA0_RDREQ_128B_sum", r128),
+                  (disp, k, "TCC_EA0_RDREQ_64B_sum", r64), (disp, k, "TCC_EA0_RDREQ_32B_sum", r32)]
+    reads += [(9, cp, "TCC_EA0_RDREQ_sum", 8), (9, cp, "TCC_EA0_RDREQ_128B_sum", 8),
+              (9, cp, "TCC_EA0_RDREQ_64B_sum", 0), (9, cp, "TCC_EA0_RDREQ_32B_sum", 0)]
+    writes = []
+    for disp, (w, w64) in ((1, (50, 40)), (2, (70, 70))):
+        writes += [(disp, k, "TCC_EA0_WRREQ_sum", w), (disp, k, "TCC_EA0_WRREQ_64B_sum", w64),
+                   (disp, k, "TCC_EA0_RDREQ_DRAM_32B_sum", 4 * 100), (disp, k, "TCC_EA0_WRREQ_WRITE_DRAM_32B_sum", 8)]
+    writes += [(9, cp, "TCC_EA0_WRREQ_sum", 16), (9, cp, "TCC_EA0_WRREQ_64B_sum", 16),
+               (9, cp, "TCC_EA0_RDREQ_DRAM_32B_sum", 32), (9, cp, "TCC_EA0_WRREQ_WRITE_DRAM_32B_sum", 32)]
+    l2 = []
+    for disp in (1, 2, 9):
+        kn = cp if disp == 9 else k
+        l2 += [(disp, kn, "TCC_REQ_sum", 10), (disp, kn, "TCC_HIT_sum", 3), (disp, kn, "TCC_MISS_sum", 7),
+               (disp, kn, "TCC_READ_sum", 9)]
+    dirs = [str(tmp_path / n) for n in ("reads", "writes", "l2")]
+    for d, rows in zip(dirs, (reads, writes, l2)):
+        _write_pass(d, rows)
+    text = bench.counter_summary(dirs, "zipf-2m", ["cmd one", "cmd two"])
+    kv = dict(l.split(" = ", 1) for l in text.splitlines() if " = " in l and not l.startswith("#"))
+    rd = ((128 * 100 + 64 * 10 + 32 * 4) + (128 * 300 + 64 * 30)) / 2
+    wr = ((64 * 40 + 32 * 10) + 64 * 70) / 2
+    assert float(kv["bf16.read_bytes_per_launch"]) == pytest.approx(rd)
+    assert float(kv["bf16.write_bytes_per_launch"]) == pytest.approx(wr)
+    assert float(kv["bf16.traffic_bytes_per_launch"]) == pytest.approx(rd + wr)
+    assert float(kv["bf16.l2_hit_rate"]) == pytest.approx(0.3)
+    assert float(kv["copy.read_bytes_per_launch"]) == 1024 and float(kv["copy.write_bytes_per_launch"]) == 1024
+    assert kv["kernel_source_sha256"] == bench.kernel_source_digest()
+    assert "#   cmd one" in text
