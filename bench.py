@@ -38,6 +38,16 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2103_09660_amd", "csrc", "hnv_kernels.hip
 # type, as rocprofv3 names its instantiation: k_gather<T, EPL, G, MODE, FUSED, CTL>.
 SWEEP_KERNELS = {"bf16": "k_gather<unsigned short, 8, 16, 0, false, false>",
                  "f32": "k_gather<float, 4, 16, 0, false, false>"}
+# Other kernels of the path, reported in the same counter summary when the
+# run has them: the fused projection + sweep, the reverse sweep's node-row
+# launch, its hyperedge-row launch with and without the member sum of the
+# weight gradient (modes 2 and 3), and the split gradient's finish pass.
+OTHER_KERNELS = {"bf16_fused": "k_gather<unsigned short, 8, 16, 0, true, false>",
+                 "f32_fused": "k_gather<float, 4, 16, 0, true, false>",
+                 "bf16_reverse_node": "k_gather<unsigned short, 8, 16, 1, false, false>",
+                 "bf16_reverse_edge_sum": "k_gather<unsigned short, 8, 16, 2, false, false>",
+                 "bf16_reverse_edge": "k_gather<unsigned short, 8, 16, 3, false, false>",
+                 "wgrad_finish": "k_wgrad_finish"}
 # Hardware counters of the L2 (TCC) to fabric (EA) interface on gfx950, in
 # passes of at most four TCC counters each.  Read requests are counted by
 # size (128, 64 and 32 bytes) and write requests as 64-byte or 32-byte ones,
@@ -170,12 +180,12 @@ def counter_summary(dirs, config, commands):
               f"kernel_source_sha256 = {kernel_source_digest()}"]
     kernels = sorted(per)
     found = False
-    for dt, short in SWEEP_KERNELS.items():
+    for dt, short in list(SWEEP_KERNELS.items()) + list(OTHER_KERNELS.items()):
         names = [k for k in kernels if short in k]      # rocprofv3 names carry namespace and arguments
         b = block(names[0]) if len(names) == 1 else None
         if b is None:
             continue
-        found = True
+        found = found or dt in SWEEP_KERNELS
         kname = names[0]
         lines.append(f"# {dt}: {kname}")
         lines += [f"{dt}.{k} = {v:.6g}" if isinstance(v, float) else f"{dt}.{k} = {v}" for k, v in b.items()]
@@ -888,6 +898,35 @@ def cpu_baseline_leg(hg, cfg, zc, outs, timing=True, errors=True, d=None):
     return out
 
 
+def trace_summary(dirs, title, commands, top=40):
+    """A markdown table of the kernels in rocprofv3 --kernel-trace --stats
+    output (the *_kernel_stats.csv files): calls, average and total time,
+    share of the traced kernel time, for the `top` kernels by total time."""
+    import csv
+    import glob
+    rows = []
+    for d in dirs:
+        for path in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
+            with open(path, newline="") as f:
+                rows += list(csv.DictReader(f))
+    if not rows:
+        raise SystemExit("no *_kernel_stats.csv in " + ", ".join(dirs))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = [f"# Kernel trace: {title}", "", "Commands:", ""]
+    out += [f"    {c}" for c in commands]
+    out += ["", "| kernel | calls | avg us | min us | max us | total ms | % of traced kernel time |",
+            "|---|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        name = r["Name"].replace("|", "/")
+        name = name if len(name) <= 90 else name[:87] + "..."
+        out.append(f"| `{name}` | {int(r['Calls'])} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.2f} | {100 * float(r['TotalDurationNs']) / total:.1f} |")
+    out += ["", f"kernel_source_sha256 = {kernel_source_digest()}", ""]
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -910,10 +949,18 @@ def main():
                     help="reduce rocprofv3 --pmc output directories (one per counter pass) of a --config run to "
                          "the key = value summary kept under profiles/, print it and exit (no GPU needed)")
     ap.add_argument("--summary-command", action="append", default=[],
-                    help="with --counter-summary: a command that produced the directories (recorded verbatim)")
+                    help="with --counter-summary / --trace-summary: a command that produced the directories "
+                         "(recorded verbatim)")
+    ap.add_argument("--trace-summary", nargs="+", default=None, metavar="DIR",
+                    help="format rocprofv3 --kernel-trace --stats output directories as a markdown table, print "
+                         "it and exit (no GPU needed)")
+    ap.add_argument("--summary-title", default="", help="with --trace-summary: the table's title")
     args = ap.parse_args()
     if args.counter_summary:
         print(counter_summary(args.counter_summary, args.config, args.summary_command), end="")
+        return
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary, args.summary_title or args.config, args.summary_command), end="")
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -139,6 +139,169 @@ __global__ __launch_bounds__(kThreads) void k_map(const int32_t *__restrict__ id
         mapped[j] = node_rep[idx[j]];
 }
 
+// ---------------------------------------------------------------------------
+// Coarse member lists sorted per hyperedge.  A library segmented sort spends
+// most of its time on per-segment overhead when, as here, most segments hold
+// two to four keys.  So: lists of at most kSortThread members are sorted by
+// one thread in registers; lists of at most kSortWave members by one
+// wavefront (a bitonic network over 64 lanes x up to 16 registers); the few
+// longer ones go to the library's segmented sort.  Each list's result is the
+// same whatever order the lists are taken in.
+// ---------------------------------------------------------------------------
+
+constexpr int kSortThread = 8;
+constexpr int kSortWave = 1024;
+
+// Appends the lanes with `pred` to a list through one atomic per wavefront;
+// returns each such lane's slot (-1 for the others).  Every lane of the
+// wavefront must call it.
+__device__ __forceinline__ int32_t wave_append(int32_t *counter, bool pred)
+{
+    const uint64_t m = __ballot(pred);
+    if (m == 0)
+        return -1;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int leader = __ffsll((long long)m) - 1;
+    int32_t base = 0;
+    if (lane == leader)
+        base = atomicAdd(counter, (int32_t)__popcll(m));
+    base = __shfl(base, leader, kWave);
+    return pred ? base + (int32_t)__popcll(m & ((1ull << lane) - 1ull)) : -1;
+}
+
+// One thread per hyperedge: a list of at most kSortThread members is sorted
+// here (Batcher's odd-even merge network of 19 comparators, INT_MAX
+// padding); one of more than kSortWave members is appended to the library
+// sort's segment list (a few per level, so one atomic per wavefront that
+// has any is cheap).  The lists in between are left to k_sort_wave.
+__global__ __launch_bounds__(kThreads) void k_sort_short(const int32_t *__restrict__ ptr,
+                                                         const int32_t *__restrict__ mapped, int64_t n_edges,
+                                                         int32_t *__restrict__ sorted, int32_t *__restrict__ big_begin,
+                                                         int32_t *__restrict__ big_end, int32_t *__restrict__ n_big)
+{
+    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    int32_t s = 0, n = 0;
+    if (e < n_edges) {
+        s = ptr[e];
+        n = ptr[e + 1] - s;
+    }
+    if (e < n_edges && n <= kSortThread) {
+        int32_t v[kSortThread];
+#pragma unroll
+        for (int i = 0; i < kSortThread; ++i)
+            v[i] = (i < n) ? mapped[s + i] : INT_MAX;
+        constexpr int net[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {1, 2}, {5, 6},
+                                    {0, 4}, {3, 7}, {1, 5}, {2, 6}, {1, 4}, {3, 6}, {2, 4}, {3, 5}, {3, 4}};
+#pragma unroll
+        for (int c = 0; c < 19; ++c) {
+            const int32_t a = v[net[c][0]], b = v[net[c][1]];
+            v[net[c][0]] = min(a, b);
+            v[net[c][1]] = max(a, b);
+        }
+#pragma unroll
+        for (int i = 0; i < kSortThread; ++i)
+            if (i < n)
+                sorted[s + i] = v[i];
+    }
+    const bool is_big = e < n_edges && n > kSortWave;
+    const int32_t b = wave_append(n_big, is_big);
+    if (is_big) {
+        big_begin[b] = s;
+        big_end[b] = s + n;
+    }
+}
+
+// Bitonic sorting network over 64 K keys held as v[r] in lane `lane`, key
+// index r * 64 + lane: partners at distance j < 64 are in other lanes of the
+// same register (exchanged by shuffles), at j >= 64 in other registers of
+// the same lane.  All loop bounds are compile-time, so every register index
+// is a constant.
+template <int K>
+__device__ __forceinline__ void wave_bitonic(int32_t (&v)[K], int lane)
+{
+    constexpr int LOGN = (K == 1) ? 6 : (K == 2) ? 7 : (K == 4) ? 8 : (K == 8) ? 9 : 10;
+#pragma unroll
+    for (int lk = 1; lk <= LOGN; ++lk) {
+        const int k = 1 << lk;
+#pragma unroll
+        for (int lj = lk - 1; lj >= 0; --lj) {
+            const int j = 1 << lj;
+            if (j >= kWave) {
+                const int rj = j / kWave;
+#pragma unroll
+                for (int r = 0; r < K; ++r) {
+                    if (r & rj)
+                        continue;
+                    const bool asc = ((r * kWave) & k) == 0;   // k > 64: the direction is the register's
+                    const int32_t a = v[r], b = v[r | rj];
+                    v[r] = asc ? min(a, b) : max(a, b);
+                    v[r | rj] = asc ? max(a, b) : min(a, b);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < K; ++r) {
+                    const bool asc = ((r * kWave + lane) & k) == 0;
+                    const int32_t y = __shfl_xor(v[r], j, kWave);
+                    const bool keep_min = ((lane & j) == 0) == asc;
+                    v[r] = keep_min ? min(v[r], y) : max(v[r], y);
+                }
+            }
+        }
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void wave_sort(const int32_t *__restrict__ in, int32_t *__restrict__ out, int n, int lane)
+{
+    int32_t v[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const int i = r * kWave + lane;
+        v[r] = (i < n) ? in[i] : INT_MAX;
+    }
+    wave_bitonic<K>(v, lane);
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const int i = r * kWave + lane;
+        if (i < n)
+            out[i] = v[r];
+    }
+}
+
+// The lists of more than kSortThread and at most kSortWave members: each
+// wavefront takes a window of 64 consecutive hyperedges (one per lane),
+// finds those lists by a ballot, and sorts them one after the other with
+// all 64 lanes.  No list of work, no atomics.
+__global__ __launch_bounds__(kThreads) void k_sort_wave(const int32_t *__restrict__ ptr,
+                                                        const int32_t *__restrict__ mapped, int64_t n_edges,
+                                                        int32_t *__restrict__ sorted)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t window = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kWave;
+    const int64_t e = window * kWave + lane;
+    int32_t s = 0, n = 0;
+    if (e < n_edges) {
+        s = ptr[e];
+        n = ptr[e + 1] - s;
+    }
+    uint64_t todo = __ballot(n > kSortThread && n <= kSortWave);
+    while (todo) {
+        const int src = __ffsll((long long)todo) - 1;
+        todo &= todo - 1;
+        const int32_t ss = __shfl(s, src, kWave), nn = __shfl(n, src, kWave);
+        if (nn <= 64)
+            wave_sort<1>(mapped + ss, sorted + ss, nn, lane);
+        else if (nn <= 128)
+            wave_sort<2>(mapped + ss, sorted + ss, nn, lane);
+        else if (nn <= 256)
+            wave_sort<4>(mapped + ss, sorted + ss, nn, lane);
+        else if (nn <= 512)
+            wave_sort<8>(mapped + ss, sorted + ss, nn, lane);
+        else
+            wave_sort<16>(mapped + ss, sorted + ss, nn, lane);
+    }
+}
+
 // dflag[j] = 1 where sorted[j] starts a new distinct value inside a kept
 // hyperedge's sorted mapped members
 __global__ __launch_bounds__(kThreads) void k_distinct(const int32_t *__restrict__ ptr,
@@ -536,7 +699,11 @@ __global__ __launch_bounds__(kThreads) void k_group_fill(const int32_t *__restri
     gnodes[gptr[g] + atomicAdd(gcur + g, 1)] = (int32_t)v;
 }
 
-// Temporary storage of the two sorts for the given key widths in bits.
+// Member lists longer than kSortWave that one level can hold.
+int64_t max_big_lists(int64_t nnz) { return nnz / (kSortWave + 1) + 1; }
+
+// Temporary storage of the two sorts for the given key widths in bits (the
+// segmented sort over at most max_big_lists segments).
 hnv_status sort_storage(int64_t nE, int64_t nnz, int key_bits, int member_bits, size_t &t_keys, size_t &t_members)
 {
     t_keys = t_members = 0;
@@ -545,7 +712,7 @@ hnv_status sort_storage(int64_t nE, int64_t nnz, int key_bits, int member_bits, 
                                                       (int)std::max<int64_t>(nE, 1), 0, key_bits);
     if (e == hipSuccess)
         e = prim_segmented_sort_keys(nullptr, t_members, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                                                       (int)std::max<int64_t>(nnz, 1), (int)std::max<int64_t>(nE, 1),
+                                                       (int)std::max<int64_t>(nnz, 1), max_big_lists(nnz),
                                                        (int32_t *)nullptr, (int32_t *)nullptr, 0, member_bits);
     if (e != hipSuccess)
         return fail(HNV_EDEVICE, std::string("sort storage query (needs a visible GPU): ") + hipGetErrorString(e));
@@ -554,7 +721,7 @@ hnv_status sort_storage(int64_t nE, int64_t nnz, int key_bits, int member_bits, 
 
 struct CoarsenLayout {
     size_t keys_in, keys_out, ids_in, order, rank, best, choice, first, count, gflag, gid, kept, krank, mapped,
-        sorted, inc_edge, dflag, dpos, sizes, flag;
+        sorted, inc_edge, dflag, dpos, sizes, flag, big_begin, big_end, sort_counts;
     // feature path (k > 0)
     size_t fsum, fsq, q, bestq, gcount, gptr, gcur, gnodes;
     size_t temp, temp_bytes, total;
@@ -589,6 +756,9 @@ hnv_status layout(int64_t nV, int64_t nE, int64_t nnz, int k, CoarsenLayout &L)
     L.dpos = take(4 * nnz);
     L.sizes = take(8 * 4);
     L.flag = take(16);
+    L.big_begin = take(4 * max_big_lists(nnz));
+    L.big_end = take(4 * max_big_lists(nnz));
+    L.sort_counts = take(8);
     L.fsum = L.fsq = L.q = L.bestq = L.gcount = L.gptr = L.gcur = L.gnodes = 0;
     if (k > 0) {
         L.fsum = take(4 * (size_t)nE * k);
@@ -781,15 +951,29 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
         tb = L.temp_bytes;
         if (prim_exclusive_sum(temp, tb, kept, krank, nE, s) != hipSuccess)
             return fail(HNV_EDEVICE, "scan of kept flags");
-        // 5. coarse member sets
+        // 5. coarse member sets: every hyperedge's mapped members sorted (short
+        // lists by a thread, medium ones by a wavefront, long ones by the
+        // library's segmented sort over a list of them)
         if (nz > 0) {
             k_map<<<grid_for(nz), kThreads, 0, s>>>(edge_idx, node_rep, nnz, mapped);
-            tb = L.temp_bytes;
-            // non-negative ids: sorted as unsigned so only the low bits count
-            if (prim_segmented_sort_keys(temp, tb, reinterpret_cast<const uint32_t *>(mapped),
-                                                           reinterpret_cast<uint32_t *>(sorted), nz, nE, edge_ptr,
-                                                           edge_ptr + 1, 0, member_bits, s) != hipSuccess)
-                return fail(HNV_EDEVICE, "segmented sort of coarse members");
+            int32_t *big_begin = at(L.big_begin), *big_end = at(L.big_end), *n_big_dev = at(L.sort_counts);
+            const int64_t n_big = max_big_lists(nnz);
+            k_fill<<<1, kThreads, 0, s>>>(n_big_dev, 1, 0);
+            k_fill<<<grid_for(n_big), kThreads, 0, s>>>(big_begin, n_big, 0);
+            k_fill<<<grid_for(n_big), kThreads, 0, s>>>(big_end, n_big, 0);
+            k_sort_short<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, mapped, n_edges, sorted, big_begin, big_end,
+                                                            n_big_dev);
+            if (nnz > kSortThread)
+                k_sort_wave<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, mapped, n_edges, sorted);
+            if (nnz > kSortWave) {
+                tb = L.temp_bytes;
+                // non-negative ids: sorted as unsigned so only the low bits count;
+                // unused segments are empty
+                if (prim_segmented_sort_keys(temp, tb, reinterpret_cast<const uint32_t *>(mapped),
+                                             reinterpret_cast<uint32_t *>(sorted), nz, n_big, big_begin, big_end, 0,
+                                             member_bits, s) != hipSuccess)
+                    return fail(HNV_EDEVICE, "segmented sort of long coarse member lists");
+            }
         }
         k_distinct<<<grid_for(nz), kThreads, 0, s>>>(edge_ptr, sorted, inc_edge, kept, nnz, dflag);
         tb = L.temp_bytes;

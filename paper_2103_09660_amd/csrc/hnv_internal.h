@@ -77,6 +77,7 @@ struct LevelPlan {
     int64_t rows_coarse = 0;         // rows of level + 1 (0 at the coarsest level)
     bool has_coarse = false;
     bool unit_w = true;
+    bool scales_ready = false;       // the reverse-mode scales (side[*].sn) hold the current weights
     DevSide side[2];
     float *r = nullptr;              // [rows] 1 / (row weight sum), 0 for rows without neighbours
     float *w = nullptr;              // [n_edges] current hyperedge weights

@@ -1189,24 +1189,38 @@ __global__ __launch_bounds__(kBlock) void k_score_final(ScoreArgs a)
 // reciprocals (FP64) and per-star-edge scale arrays
 // ---------------------------------------------------------------------------
 
-// node v: S_v = sum_{e ∋ v} w_e in FP64 (one wavefront per node, lanes
-// strided, fixed butterfly), r_v = 1 / S_v (0 without hyperedges).
+// node v: S_v = sum_{e ∋ v} w_e in FP64, r_v = 1 / S_v (0 without
+// hyperedges).  A group of kRecipLanes lanes per node: lane i adds the
+// positions i, i + 16, i + 32, ... in that order (four loads in flight),
+// then a fixed butterfly over the group.
+constexpr int kRecipLanes = 16;
 __global__ __launch_bounds__(kBlock) void k_recip_nodes(const int32_t *__restrict__ ptr,
                                                         const int32_t *__restrict__ idx,
                                                         const float *__restrict__ w, int64_t n_nodes,
                                                         int64_t row_base_edges, float *__restrict__ r)
 {
-    const int64_t v = linear_block() * kWavesPerBlock + threadIdx.x / kWave;
-    const int lane = threadIdx.x % kWave;
-    if (v >= n_nodes)
-        return;
+    const int64_t v = (linear_block() * kBlock + threadIdx.x) / kRecipLanes;
+    const int gl = threadIdx.x % kRecipLanes;
     double s = 0.0;
-    for (int j = ptr[v] + lane; j < ptr[v + 1]; j += kWave)
-        s += (double)w[idx[j] - row_base_edges];
+    if (v < n_nodes) {
+        const int32_t end = ptr[v + 1];
+        int32_t j = ptr[v] + gl;
+        for (; j + 3 * kRecipLanes < end; j += 4 * kRecipLanes) {
+            const float w0 = w[idx[j] - row_base_edges], w1 = w[idx[j + kRecipLanes] - row_base_edges];
+            const float w2 = w[idx[j + 2 * kRecipLanes] - row_base_edges];
+            const float w3 = w[idx[j + 3 * kRecipLanes] - row_base_edges];
+            s += (double)w0;
+            s += (double)w1;
+            s += (double)w2;
+            s += (double)w3;
+        }
+        for (; j < end; j += kRecipLanes)
+            s += (double)w[idx[j] - row_base_edges];
+    }
 #pragma unroll
-    for (int off = 1; off < kWave; off <<= 1)
+    for (int off = 1; off < kRecipLanes; off <<= 1)
         s += __shfl_xor(s, off, kWave);
-    if (lane == 0)
+    if (v < n_nodes && gl == 0)
         r[v] = (s > 0.0) ? (float)(1.0 / s) : 0.0f;
 }
 
@@ -1221,22 +1235,30 @@ __global__ __launch_bounds__(kBlock) void k_recip_edges(const int32_t *__restric
     r[n_nodes + e] = (deg > 0) ? (float)(1.0 / (double)deg) : 0.0f;
 }
 
-// per star edge: node side (neighbour = hyperedge e): weight w_e and reverse
-// scale r_e; hyperedge side (neighbour = node v): reverse scale r_v.
-__global__ __launch_bounds__(kBlock) void k_fill_edge_scales(const int32_t *__restrict__ idx_node_side,
-                                                             const int32_t *__restrict__ idx_edge_side,
-                                                             const float *__restrict__ w,
-                                                             const float *__restrict__ r, int64_t nnz,
-                                                             int64_t n_nodes, float *__restrict__ wn,
-                                                             float *__restrict__ sn_node_side,
-                                                             float *__restrict__ sn_edge_side)
+// per star edge of the node side (neighbour = hyperedge e): its weight w_e,
+// which the forward sweep multiplies by (not needed for unit weights)
+__global__ __launch_bounds__(kBlock) void k_fill_weights(const int32_t *__restrict__ idx_node_side,
+                                                         const float *__restrict__ w, int64_t nnz, int64_t n_nodes,
+                                                         float *__restrict__ wn)
+{
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j < nnz)
+        wn[j] = w[idx_node_side[j] - n_nodes];
+}
+
+// per star edge, the reverse sweep's scale, the reciprocal row sum of the
+// neighbour: node side (neighbour = hyperedge e) r_e, hyperedge side
+// (neighbour = node v) r_v
+__global__ __launch_bounds__(kBlock) void k_fill_reverse_scales(const int32_t *__restrict__ idx_node_side,
+                                                                const int32_t *__restrict__ idx_edge_side,
+                                                                const float *__restrict__ r, int64_t nnz,
+                                                                float *__restrict__ sn_node_side,
+                                                                float *__restrict__ sn_edge_side)
 {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= nnz)
         return;
-    const int32_t erow = idx_node_side[j];
-    wn[j] = w[erow - n_nodes];
-    sn_node_side[j] = r[erow];
+    sn_node_side[j] = r[idx_node_side[j]];
     sn_edge_side[j] = r[idx_edge_side[j]];
 }
 
@@ -1295,15 +1317,33 @@ hnv_status dev_recompute_reciprocals(hnv_plan *p, int level, void *stream)
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     LevelPlan &L = p->lv[level];
     if (L.n_nodes > 0)
-        k_recip_nodes<<<fold_grid(blocks_for(L.n_nodes, kWavesPerBlock)), kBlock, 0, s>>>(L.side[1].ptr, L.side[1].idx, L.w,
-                                                                             L.n_nodes, L.n_nodes, L.r);
+        k_recip_nodes<<<fold_grid(blocks_for(L.n_nodes, kBlock / kRecipLanes)), kBlock, 0, s>>>(
+            L.side[1].ptr, L.side[1].idx, L.w, L.n_nodes, L.n_nodes, L.r);
     if (L.n_edges > 0)
         k_recip_edges<<<grid1d(L.n_edges, kBlock), kBlock, 0, s>>>(L.side[0].ptr, L.n_edges, L.n_nodes, L.r);
-    if (L.nnz > 0)
-        k_fill_edge_scales<<<grid1d(L.nnz, kBlock), kBlock, 0, s>>>(L.side[1].idx, L.side[0].idx, L.w, L.r, L.nnz,
-                                                                    L.n_nodes, L.side[1].wn, L.side[1].sn,
-                                                                    L.side[0].sn);
+    if (L.nnz > 0 && !L.unit_w)
+        k_fill_weights<<<grid1d(L.nnz, kBlock), kBlock, 0, s>>>(L.side[1].idx, L.w, L.nnz, L.n_nodes, L.side[1].wn);
+    L.scales_ready = false;   // the reverse sweep refills them from these reciprocals
     return dev_check("reciprocal kernels");
+}
+
+// The reverse sweep's per-star-edge scales of a level, filled from the
+// current reciprocals before the first reverse sweep after a weight change
+// (forward sweeps never read them).  While the stream is being captured the
+// fill goes into the graph and is not taken as done.
+static hnv_status ensure_reverse_scales(hnv_plan *p, int level, hipStream_t s)
+{
+    LevelPlan &L = p->lv[level];
+    if (L.scales_ready)
+        return HNV_OK;
+    if (L.nnz > 0)
+        k_fill_reverse_scales<<<grid1d(L.nnz, kBlock), kBlock, 0, s>>>(L.side[1].idx, L.side[0].idx, L.r, L.nnz,
+                                                                       L.side[1].sn, L.side[0].sn);
+    hnv_status st = dev_check("reverse-mode scales");
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (st == HNV_OK && hipStreamIsCapturing(s, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone)
+        L.scales_ready = true;
+    return st;
 }
 
 static GatherArgs base_args(hnv_plan *p, LevelPlan &L, int G, int dp)
@@ -1893,6 +1933,8 @@ static hnv_status run_adjoint(hnv_plan *plan, int level, const void *g_in, void 
                               const void *z_cur, float *dw, float *node_acc, float omega, int wgrad, hipStream_t s)
 {
     LevelPlan &L = plan->lv[level];
+    if (hnv_status st = ensure_reverse_scales(plan, level, s); st != HNV_OK)
+        return st;
     const int G = plan->g_full, E = plan->epl_full;
     const bool edge_first = plan->opts.order == HNV_ORDER_EDGE_FIRST;
     GatherArgs a = base_args(plan, L, G, plan->d);

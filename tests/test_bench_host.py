@@ -89,3 +89,23 @@ def test_counter_summary_bytes_from_sized_requests(tmp_path):
     assert float(kv["copy.read_bytes_per_launch"]) == 1024 and float(kv["copy.write_bytes_per_launch"]) == 1024
     assert kv["kernel_source_sha256"] == bench.kernel_source_digest()
     assert "#   cmd one" in text
+
+
+def test_trace_summary_table(tmp_path):
+    import csv
+    import bench
+    d = tmp_path / "trace"
+    d.mkdir()
+    with open(d / "x_kernel_stats.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs",
+                                          "MaxNs", "StdDev"])
+        w.writeheader()
+        w.writerow(dict(Name="k_small", Calls=10, TotalDurationNs=1000, AverageNs=100, Percentage=10, MinNs=90,
+                        MaxNs=110, StdDev=1))
+        w.writerow(dict(Name="k_big", Calls=3, TotalDurationNs=9000, AverageNs=3000, Percentage=90, MinNs=2900,
+                        MaxNs=3100, StdDev=1))
+    text = bench.trace_summary([str(d)], "t", ["cmd"])
+    lines = [l for l in text.splitlines() if l.startswith("| `")]
+    assert lines[0].startswith("| `k_big` | 3 | 3.0 |") and lines[0].endswith("| 90.0 |")
+    assert lines[1].startswith("| `k_small` | 10 | 0.1 |")
+    assert "    cmd" in text and bench.kernel_source_digest() in text

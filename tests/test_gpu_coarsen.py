@@ -173,3 +173,18 @@ def test_depth_rule_matches_host(H):
     assert host.n_levels == dev.n_levels == 4
     for a, b in zip(host.maps, dev.maps):
         assert np.array_equal(a.node_rep, b.node_rep) and np.array_equal(a.edge_rep, b.edge_rep)
+
+
+def test_member_sort_boundaries(oracle_mod, H):
+    """Coarse member lists sorted by a thread (up to 8 members), a wavefront
+    (up to 1,024, in 64-lane registers x 1..16) or the library's segmented
+    sort (longer): hyperedges at every boundary, with members whose coarse
+    ids come out in every order, against the oracle bit for bit."""
+    rng = np.random.default_rng(77)
+    n_nodes = 6000
+    sizes = [1, 2, 7, 8, 9, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 3000]
+    sizes += list(rng.integers(2, 12, size=3000))      # small hyperedges that merge nodes into groups
+    edges = [sorted(rng.choice(n_nodes, size=k, replace=False).tolist()) for k in sizes]
+    ptr = np.concatenate([[0], np.cumsum([len(e) for e in edges])]).astype(np.int64)
+    idx = np.array([v for e in edges for v in e], dtype=np.int32)
+    _compare(oracle_mod, H, n_nodes, len(edges), ptr, idx, None, 2, "member sort boundaries")
