@@ -41,8 +41,11 @@
 namespace hnv {
 namespace {
 
+// Sort key of hyperedge e: the complemented weight bits above the size, which
+// takes size_bits bits (a size is at most n_nodes), so that an ascending
+// stable sort gives weight descending, size ascending, id ascending.
 __global__ __launch_bounds__(kThreads) void k_keys(const int32_t *__restrict__ ptr, const float *__restrict__ w,
-                                                   int64_t n_edges, uint64_t *__restrict__ keys,
+                                                   int64_t n_edges, int size_bits, uint64_t *__restrict__ keys,
                                                    int32_t *__restrict__ ids)
 {
     const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -50,7 +53,7 @@ __global__ __launch_bounds__(kThreads) void k_keys(const int32_t *__restrict__ p
         return;
     const uint32_t wb = __float_as_uint(w ? w[e] : 1.0f);
     const uint32_t size = (uint32_t)(ptr[e + 1] - ptr[e]);
-    keys[e] = ((uint64_t)(~wb) << 32) | size;
+    keys[e] = ((uint64_t)(~wb) << size_bits) | size;
     ids[e] = (int32_t)e;
 }
 
@@ -893,9 +896,10 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
     int64_t *sizes = reinterpret_cast<int64_t *>(base + L.sizes);
     void *temp = base + L.temp;
     size_t tb = L.temp_bytes;
-    // Without weights the upper half of every key is the same: sort the size
-    // half only.  Coarse member ids are below n_nodes.
-    const int key_bits = edge_w ? 64 : 32, member_bits = bits_for(n_nodes);
+    // Without weights every key's weight part is the same: sort the size bits
+    // only.  Coarse member ids are below n_nodes.
+    const int size_bits = bits_for(n_nodes + 1);
+    const int key_bits = edge_w ? 32 + size_bits : size_bits, member_bits = bits_for(n_nodes);
     {
         size_t need_keys = 0, need_members = 0;
         if ((st = sort_storage(n_edges, nnz, key_bits, member_bits, need_keys, need_members)) != HNV_OK)
@@ -907,7 +911,7 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
         // 1. ranks in the order (weight descending, size ascending, id ascending)
         uint64_t *kin = reinterpret_cast<uint64_t *>(base + L.keys_in);
         uint64_t *kout = reinterpret_cast<uint64_t *>(base + L.keys_out);
-        k_keys<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, edge_w, n_edges, kin, at(L.ids_in));
+        k_keys<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, edge_w, n_edges, size_bits, kin, at(L.ids_in));
         if (prim_sort_pairs(temp, tb, kin, kout, at(L.ids_in), order, nE, 0, key_bits, s) != hipSuccess)
             return fail(HNV_EDEVICE, "radix sort of hyperedge keys");
         k_rank<<<grid_for(nE), kThreads, 0, s>>>(order, n_edges, rank);

@@ -44,15 +44,19 @@ __global__ __launch_bounds__(kThreads) void k_check_node_map(const int32_t *__re
         atomicOr(flag, 1 << 4);
 }
 
+// Runs after the level's own checks in the same stream and does nothing
+// when they found bad offsets or member ids (level_flag bits 0 and 1), so
+// every member it follows is in range.
 __global__ __launch_bounds__(kThreads) void k_check_edge_map(const int32_t *__restrict__ ptr,
                                                              const int32_t *__restrict__ idx,
                                                              const int32_t *__restrict__ node_rep,
                                                              const int32_t *__restrict__ edge_rep, int64_t n_nodes,
                                                              int64_t n_edges, int64_t n_edges_c, int full,
+                                                             const int *__restrict__ level_flag,
                                                              int *__restrict__ flag)
 {
     const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (e >= n_edges)
+    if (e >= n_edges || (*level_flag & 3))
         return;
     const int32_t r = edge_rep[e];
     int bad = 0;
@@ -63,7 +67,6 @@ __global__ __launch_bounds__(kThreads) void k_check_edge_map(const int32_t *__re
         if (b == a) {
             bad = 1 << 6;
         } else if (full) {
-            // members were range-checked before this kernel runs
             const int32_t first = node_rep[idx[a]];
             for (int32_t j = a + 1; j < b; ++j)
                 if (node_rep[idx[j]] != first)
@@ -72,6 +75,105 @@ __global__ __launch_bounds__(kThreads) void k_check_edge_map(const int32_t *__re
     }
     if (bad)
         atomicOr(flag, bad);
+}
+
+// A level without hyperedges: its offsets are the single 0 and it has no
+// incidences (flag bit 0 otherwise).
+__global__ void k_check_no_edges(const int32_t *__restrict__ ptr, int64_t nnz, int *__restrict__ flag)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0 && (ptr[0] != 0 || nnz != 0))
+        atomicOr(flag, 1);
+}
+
+// Stable sort of (key, value) pairs by a key below n_bins <= kBinsMax (the
+// degree tiers have at most small_max + 2 <= 258 keys): per-tile counts of
+// every key, an exclusive scan of the counts laid out key-major (key b of
+// tile t at b * n_tiles + t), and a scatter in which each tile places its
+// elements in input order.  The result equals a stable radix sort's.
+constexpr int kBinsMax = 512;
+constexpr int kBinRounds = 16;
+constexpr int kBinTile = kThreads * kBinRounds;
+constexpr int kBinWaves = kThreads / kWave;
+
+__global__ __launch_bounds__(kThreads) void k_bin_count(const uint32_t *__restrict__ key, int64_t n, int n_bins,
+                                                        int64_t n_tiles, int32_t *__restrict__ counts)
+{
+    __shared__ int32_t h[kBinsMax];
+    for (int b = threadIdx.x; b < n_bins; b += kThreads)
+        h[b] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kBinTile;
+    for (int k = 0; k < kBinRounds; ++k) {
+        const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
+        if (i < n)
+            atomicAdd(&h[key[i]], 1);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < n_bins; b += kThreads)
+        counts[(int64_t)b * n_tiles + blockIdx.x] = h[b];
+}
+
+// The lanes of the wavefront that hold the same key (active lanes only):
+// one ballot per key bit.  Every lane of the wavefront must call it.
+__device__ inline uint64_t same_key_lanes(uint32_t key, int bits, bool active)
+{
+    uint64_t m = __ballot(active);
+    for (int b = 0; b < bits; ++b) {
+        const bool one = (key >> b) & 1u;
+        const uint64_t ones = __ballot(active && one);
+        m &= one ? ones : ~ones;
+    }
+    return m;
+}
+
+// Round k of a tile places elements base + k * kThreads + [0, kThreads):
+// an element goes to the next free position of its key, after the elements
+// of the same key in lower lanes of its wavefront and in lower wavefronts.
+__global__ __launch_bounds__(kThreads) void k_bin_scatter(const uint32_t *__restrict__ key,
+                                                          const int32_t *__restrict__ val, int64_t n, int n_bins,
+                                                          int bits, int64_t n_tiles,
+                                                          const int32_t *__restrict__ offs,
+                                                          uint32_t *__restrict__ key_out,
+                                                          int32_t *__restrict__ val_out)
+{
+    __shared__ int32_t next[kBinsMax];
+    __shared__ int32_t wcount[kBinWaves][kBinsMax];
+    for (int b = threadIdx.x; b < n_bins; b += kThreads) {
+        next[b] = offs[(int64_t)b * n_tiles + blockIdx.x];
+        for (int w = 0; w < kBinWaves; ++w)
+            wcount[w][b] = 0;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    const int64_t base = (int64_t)blockIdx.x * kBinTile;
+    for (int k = 0; k < kBinRounds && base + (int64_t)k * kThreads < n; ++k) {   // uniform over the block
+        const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
+        const bool act = i < n;
+        const uint32_t kk = act ? key[i] : 0u;
+        const uint64_t peers = same_key_lanes(kk, bits, act);
+        const int rank = __popcll(peers & below);
+        if (act && rank == 0)
+            wcount[wave][kk] = __popcll(peers);
+        __syncthreads();
+        if (act) {
+            int32_t pos = next[kk] + rank;
+            for (int w = 0; w < wave; ++w)
+                pos += wcount[w][kk];
+            key_out[pos] = kk;
+            val_out[pos] = val[i];
+        }
+        __syncthreads();
+        for (int b = threadIdx.x; b < n_bins; b += kThreads) {
+            int32_t add = 0;
+            for (int w = 0; w < kBinWaves; ++w) {
+                add += wcount[w][b];
+                wcount[w][b] = 0;
+            }
+            next[b] += add;
+        }
+        __syncthreads();
+    }
 }
 
 // CSR offsets from keys sorted ascending (keys in [0, n_keys)): ptr[v] is
@@ -279,19 +381,41 @@ LevelShape bound_shape(const hnv_level_dev &lv, const hnv_level_dev *coarse, int
     return sh;
 }
 
-// Temporaries of one level's build, carved from `base` (nullptr: sizing).
-struct Scratch {
-    int32_t *inc_edge, *heads, *csc_e, *keys_out, *rows_a, *rows_b, *pieces, *cpos, *split, *spos, *slots,
-        *sbase, *ids_a, *ids_b;
+// The per-row arrays of one side's degree tiers.
+struct TierArrays {
+    int32_t *rows_a, *rows_b, *pieces, *cpos, *split, *spos, *slots, *sbase;
     uint32_t *key_a, *key_b;
+};
+
+// Temporaries of one level's build, carved from `base` (nullptr: sizing).
+// The tier arrays hold rows + 2 + kTierAlign entries: side 0 uses them from
+// 0, side 1 from side1_offset(n_edges), so both sides' scans can run before
+// their counts are read.
+struct Scratch {
+    int32_t *inc_edge, *heads, *csc_e, *keys_out, *ids_a, *ids_b, *bin_counts, *bin_offs;
+    uint32_t *ckey_a, *ckey_b;
+    TierArrays tier;
     Item *items;
     int *flag;
-    int64_t *counts;
+    int64_t *counts;   // [side][small rows, chunks, split rows, partial slots]
     void *temp;
     size_t temp_bytes, total;
 };
 
-hnv_status cub_sizes(int64_t nnz, int64_t rows, int64_t n_chunks, size_t &bytes)
+constexpr int64_t kTierAlign = 64;   // side 1 starts on a 256-byte boundary
+int64_t side1_offset(int64_t n_edges) { return (n_edges + 1 + kTierAlign - 1) / kTierAlign * kTierAlign; }
+
+TierArrays side_arrays(const Scratch &S, int64_t off)
+{
+    const TierArrays &t = S.tier;
+    return TierArrays{t.rows_a + off, t.rows_b + off, t.pieces + off, t.cpos + off, t.split + off,
+                      t.spos + off,   t.slots + off,  t.sbase + off,  t.key_a + off, t.key_b + off};
+}
+
+// entries of the key-count arrays of a bin sort of up to `rows` pairs
+int64_t bin_cap(int64_t rows, int n_bins) { return (int64_t)n_bins * (rows / kBinTile + 1); }
+
+hnv_status cub_sizes(int64_t nnz, int64_t rows, int64_t n_chunks, int64_t bins, size_t &bytes)
 {
     size_t t[6] = {0, 0, 0, 0, 0, 0};
     const int n = (int)std::max<int64_t>(std::max(nnz, rows) + 1, 1);
@@ -305,6 +429,8 @@ hnv_status cub_sizes(int64_t nnz, int64_t rows, int64_t n_chunks, size_t &bytes)
         e = prim_sort_pairs(nullptr, t[3], (uint32_t *)nullptr, (uint32_t *)nullptr,
                                                (int32_t *)nullptr, (int32_t *)nullptr,
                                                (int)std::max<int64_t>(n_chunks, 1), 0, 32);
+    if (e == hipSuccess)
+        e = prim_exclusive_sum(nullptr, t[4], (int32_t *)nullptr, (int32_t *)nullptr, (int)bins);
     if (e != hipSuccess)
         return fail(HNV_EDEVICE, std::string("sort / scan storage query (needs a visible GPU): ") +
                                      hipGetErrorString(e));
@@ -312,7 +438,7 @@ hnv_status cub_sizes(int64_t nnz, int64_t rows, int64_t n_chunks, size_t &bytes)
     return HNV_OK;
 }
 
-hnv_status scratch_layout(int64_t nnz, int64_t rows, int64_t n_chunks, char *base, Scratch &S)
+hnv_status scratch_layout(int64_t nnz, int64_t rows, int64_t n_chunks, int n_bins, char *base, Scratch &S)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
@@ -326,27 +452,37 @@ hnv_status scratch_layout(int64_t nnz, int64_t rows, int64_t n_chunks, char *bas
     S.heads = (int32_t *)take(4 * nnz);
     S.csc_e = (int32_t *)take(n4);
     S.keys_out = (int32_t *)take(n4);
-    S.rows_a = (int32_t *)take(4 * (rows + 1));
-    S.rows_b = (int32_t *)take(4 * (rows + 1));
-    S.pieces = (int32_t *)take(4 * (rows + 1));
-    S.cpos = (int32_t *)take(4 * (rows + 1));
-    S.split = (int32_t *)take(4 * (rows + 1));
-    S.spos = (int32_t *)take(4 * (rows + 1));
-    S.slots = (int32_t *)take(4 * (rows + 1));
-    S.sbase = (int32_t *)take(4 * (rows + 1));
-    S.key_a = (uint32_t *)take(4 * std::max(rows + 1, n_chunks));
-    S.key_b = (uint32_t *)take(4 * std::max(rows + 1, n_chunks));
+    const size_t t4 = 4 * (size_t)(rows + 2 + kTierAlign);
+    S.tier.rows_a = (int32_t *)take(t4);
+    S.tier.rows_b = (int32_t *)take(t4);
+    S.tier.pieces = (int32_t *)take(t4);
+    S.tier.cpos = (int32_t *)take(t4);
+    S.tier.split = (int32_t *)take(t4);
+    S.tier.spos = (int32_t *)take(t4);
+    S.tier.slots = (int32_t *)take(t4);
+    S.tier.sbase = (int32_t *)take(t4);
+    S.tier.key_a = (uint32_t *)take(t4);
+    S.tier.key_b = (uint32_t *)take(t4);
+    const int64_t bins = bin_cap(rows, n_bins);
+    S.bin_counts = (int32_t *)take(4 * bins);
+    S.bin_offs = (int32_t *)take(4 * bins);
+    S.ckey_a = (uint32_t *)take(4 * n_chunks);
+    S.ckey_b = (uint32_t *)take(4 * n_chunks);
     S.ids_a = (int32_t *)take(4 * n_chunks);
     S.ids_b = (int32_t *)take(4 * n_chunks);
     S.items = (Item *)take(sizeof(Item) * n_chunks);
     S.flag = (int *)take(16);
     S.counts = (int64_t *)take(8 * 8);
-    if (hnv_status st = cub_sizes(nnz, rows, n_chunks, S.temp_bytes); st != HNV_OK)
+    if (hnv_status st = cub_sizes(nnz, rows, n_chunks, bins, S.temp_bytes); st != HNV_OK)
         return st;
     S.temp = take(S.temp_bytes);
     S.total = (off + 255) & ~size_t(255);
     return HNV_OK;
 }
+
+// check flags of every level, [level][level flags, map flags], ahead of the
+// per-level temporaries
+size_t flags_bytes(int n_levels) { return ((size_t)n_levels * 4 * sizeof(int) + 255) & ~size_t(255); }
 
 // plan layout and build-scratch size for these levels
 hnv_status device_layout(const hnv_level_dev *levels, int n_levels, int d, hnv_dtype dtype, const hnv_options &o,
@@ -367,11 +503,12 @@ hnv_status device_layout(const hnv_level_dev *levels, int n_levels, int d, hnv_d
         bounds[l] = bound_shape(levels[l], l + 1 < n_levels ? &levels[l + 1] : nullptr, p->small_max, o.chunk);
         Scratch S{};
         const int32_t nch = std::max(bounds[l].n_chunks[0], bounds[l].n_chunks[1]);
-        if (hnv_status st = scratch_layout(bounds[l].nnz, bounds[l].rows, nch, nullptr, S);
+        if (hnv_status st = scratch_layout(bounds[l].nnz, bounds[l].rows, nch, p->small_max + 2, nullptr, S);
             st != HNV_OK)
             return st;
         scratch_bytes = std::max(scratch_bytes, S.total);
     }
+    scratch_bytes += flags_bytes(n_levels);
     carve(p, bounds, nullptr);
     const size_t zbuf_bytes = (size_t)p->lv[0].rows * p->d * ((dtype == HNV_BF16) ? 2 : 4);
     scratch_in_zbuf = scratch_bytes <= zbuf_bytes;
@@ -416,37 +553,51 @@ hnv_status copy_d2d(void *dst, const void *src, size_t n, hipStream_t s)
     return e == hipSuccess ? HNV_OK : fail(HNV_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
 }
 
-// checks of level l (and of map l when there is a coarser level)
-hnv_status check_level(const hnv_level_dev &L, const hnv_level_dev *C, const hnv_map *m, int l, bool full,
-                       Scratch &S, hipStream_t s)
+// S.inc_edge[j] = the hyperedge of incidence j (heads over a zero fill, then
+// an inclusive max-scan).
+hnv_status incidence_edges(const int32_t *ptr, int64_t nE, int64_t nnz, Scratch &S, hipStream_t s)
+{
+    k_fill<<<grid_for(nnz), kThreads, 0, s>>>(S.heads, nnz, 0);
+    k_heads<<<grid_for(nE), kThreads, 0, s>>>(ptr, nE, nnz, S.heads);
+    size_t tb = S.temp_bytes;
+    if (prim_inclusive_max(S.temp, tb, S.heads, S.inc_edge, (int)nnz, s) != hipSuccess)
+        return fail(HNV_EDEVICE, "scan of hyperedge heads");
+    return HNV_OK;
+}
+
+// Checks of level l and (with a coarser level) of map l, launched without
+// waiting: flags[0] gets the level's bits, flags[1] the map's.  The map's
+// member-following check does nothing unless the level's offsets and member
+// ids passed, so every kernel stays in bounds on any input.
+hnv_status launch_checks(const hnv_level_dev &L, const hnv_level_dev *C, const hnv_map *m, bool full, Scratch &S,
+                         int *flags, hipStream_t s)
 {
     const int64_t nV = L.n_nodes, nE = L.n_edges, nnz = L.nnz;
-    k_fill<<<1, kThreads, 0, s>>>(S.flag, 4, 0);
     if (nE > 0) {
-        k_check_edges<<<grid_for(nE), kThreads, 0, s>>>(L.edge_ptr, L.edge_w, nE, nnz, full ? 1 : 0, S.flag);
+        k_check_edges<<<grid_for(nE), kThreads, 0, s>>>(L.edge_ptr, L.edge_w, nE, nnz, full ? 1 : 0, flags);
         if (nnz > 0) {
-            k_fill<<<grid_for(nnz), kThreads, 0, s>>>(S.heads, nnz, 0);
-            k_heads<<<grid_for(nE), kThreads, 0, s>>>(L.edge_ptr, nE, nnz, S.heads);
-            size_t tb = S.temp_bytes;
-            if (prim_inclusive_max(S.temp, tb, S.heads, S.inc_edge, (int)nnz, s) !=
-                hipSuccess)
-                return fail(HNV_EDEVICE, "scan of hyperedge heads");
+            if (hnv_status st = incidence_edges(L.edge_ptr, nE, nnz, S, s); st != HNV_OK)
+                return st;
             k_check_members<<<grid_for(nnz), kThreads, 0, s>>>(L.edge_ptr, L.edge_idx, S.inc_edge, nV, nE, nnz,
-                                                              full ? 1 : 0, S.flag);
+                                                              full ? 1 : 0, flags);
         }
+    } else {
+        k_check_no_edges<<<1, 64, 0, s>>>(L.edge_ptr, nnz, flags);
     }
-    if (hnv_status st = dev_check("level checks"); st != HNV_OK)
-        return st;
-    int bad = 0;
-    if (hnv_status st = read_back(&bad, S.flag, sizeof(int), s); st != HNV_OK)
-        return st;
-    if (nE == 0) {
-        int32_t p0 = 0;
-        if (hnv_status st = read_back(&p0, L.edge_ptr, 4, s); st != HNV_OK)
-            return st;
-        if (p0 != 0 || nnz != 0)
-            bad |= 1;
+    if (C) {
+        if (nV > 0)
+            k_check_node_map<<<grid_for(nV), kThreads, 0, s>>>(m->node_rep, nV, C->n_nodes, flags + 1);
+        if (nE > 0)
+            k_check_edge_map<<<grid_for(nE), kThreads, 0, s>>>(L.edge_ptr, L.edge_idx, m->node_rep, m->edge_rep, nV,
+                                                               nE, C->n_edges, full ? 1 : 0, flags, flags + 1);
     }
+    return dev_check("level checks");
+}
+
+// The error for level l's flags (HNV_OK when there is none), level before map.
+hnv_status report_checks(int l, const int *flags, bool full)
+{
+    const int bad = flags[0], mbad = flags[1];
     const std::string lv = "level " + std::to_string(l) + ": ";
     if (bad & 1)
         return fail(HNV_EINVAL, lv + "edge_ptr must start at 0, never decrease and end at nnz" +
@@ -457,98 +608,88 @@ hnv_status check_level(const hnv_level_dev &L, const hnv_level_dev *C, const hnv
         return fail(HNV_EUNSORTED, lv + "member lists must be strictly ascending");
     if (bad & 8)
         return fail(HNV_EINVAL, lv + "weights must be finite and > 0");
-    if (!C)
-        return HNV_OK;
-    // the map, now that the members are known to be in range
-    k_fill<<<1, kThreads, 0, s>>>(S.flag, 4, 0);
-    if (nV > 0)
-        k_check_node_map<<<grid_for(nV), kThreads, 0, s>>>(m->node_rep, nV, C->n_nodes, S.flag);
-    if (hnv_status st = dev_check("map checks"); st != HNV_OK)
-        return st;
-    if (hnv_status st = read_back(&bad, S.flag, sizeof(int), s); st != HNV_OK)
-        return st;
     const std::string mp = "map " + std::to_string(l) + ": ";
-    if (bad)
+    if (mbad & (1 << 4))
         return fail(HNV_ERANGE, mp + "node_rep out of range");
-    if (nE > 0)
-        k_check_edge_map<<<grid_for(nE), kThreads, 0, s>>>(L.edge_ptr, L.edge_idx, m->node_rep, m->edge_rep, nV, nE,
-                                                           C->n_edges, full ? 1 : 0, S.flag);
-    if (hnv_status st = dev_check("map checks"); st != HNV_OK)
-        return st;
-    if (hnv_status st = read_back(&bad, S.flag, sizeof(int), s); st != HNV_OK)
-        return st;
-    if (bad & (1 << 5))
+    if (mbad & (1 << 5))
         return fail(HNV_ERANGE, mp + "edge_rep out of range");
-    if (bad & (1 << 6))
+    if (mbad & (1 << 6))
         return fail(HNV_ERANGE, mp + "a removed hyperedge has no members");
-    if (bad & (1 << 7))
+    if (mbad & (1 << 7))
         return fail(HNV_ERANGE, mp + "a removed hyperedge has members in different coarse nodes");
     return HNV_OK;
 }
 
-// The tier keys, sorts and scans of one side; counts[0..3] on the device.
-hnv_status tier_scan(const int32_t *ptr, int64_t n_rows, int small_max, int chunk, Scratch &S, int64_t *counts,
-                     hipStream_t s)
+// The tier keys, sorts and scans of one side (arrays T); counts[0..3] on the
+// device.
+hnv_status tier_scan(const int32_t *ptr, int64_t n_rows, int small_max, int chunk, const TierArrays &T, Scratch &S,
+                     int64_t *counts, hipStream_t s)
 {
     if (n_rows == 0) {
         k_fill<<<1, kThreads, 0, s>>>(reinterpret_cast<int32_t *>(counts), 8, 0);
         return dev_check("tier counts");
     }
     const int n = (int)n_rows;
-    k_tier_keys<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, small_max, chunk, S.key_a, S.rows_a, S.pieces,
-                                                      S.split, S.slots);
+    k_tier_keys<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, small_max, chunk, T.key_a, T.rows_a, T.pieces,
+                                                      T.split, T.slots);
+    // the lane-group tier order: a stable sort on the small_max + 2 keys
+    const int n_bins = small_max + 2;
+    if (n_bins > kBinsMax)
+        return fail(HNV_EUNSUPPORTED, "small_max above the tier sort's key range");
+    const int64_t tiles = (n_rows + kBinTile - 1) / kBinTile;
+    k_bin_count<<<(unsigned)tiles, kThreads, 0, s>>>(T.key_a, n_rows, n_bins, tiles, S.bin_counts);
     size_t tb = S.temp_bytes;
-    if (prim_sort_pairs(S.temp, tb, S.key_a, S.key_b, S.rows_a, S.rows_b, n, 0,
-                                           bits_for(small_max + 2), s) != hipSuccess)
-        return fail(HNV_EDEVICE, "sort of the lane-group tier");
+    if (prim_exclusive_sum(S.temp, tb, S.bin_counts, S.bin_offs, (int)(tiles * n_bins), s) != hipSuccess)
+        return fail(HNV_EDEVICE, "scan of the lane-group tier's key counts");
+    k_bin_scatter<<<(unsigned)tiles, kThreads, 0, s>>>(T.key_a, T.rows_a, n_rows, n_bins, bits_for(n_bins), tiles,
+                                                       S.bin_offs, T.key_b, T.rows_b);
     tb = S.temp_bytes;
-    if (prim_exclusive_sum(S.temp, tb, S.pieces, S.cpos, n, s) != hipSuccess)
+    if (prim_exclusive_sum(S.temp, tb, T.pieces, T.cpos, n, s) != hipSuccess)
         return fail(HNV_EDEVICE, "scan of chunk counts");
     tb = S.temp_bytes;
-    if (prim_exclusive_sum(S.temp, tb, S.split, S.spos, n, s) != hipSuccess)
+    if (prim_exclusive_sum(S.temp, tb, T.split, T.spos, n, s) != hipSuccess)
         return fail(HNV_EDEVICE, "scan of split rows");
     tb = S.temp_bytes;
-    if (prim_exclusive_sum(S.temp, tb, S.slots, S.sbase, n, s) != hipSuccess)
+    if (prim_exclusive_sum(S.temp, tb, T.slots, T.sbase, n, s) != hipSuccess)
         return fail(HNV_EDEVICE, "scan of partial slots");
-    k_tier_counts<<<1, 64, 0, s>>>(S.key_b, S.pieces, S.cpos, S.split, S.spos, S.slots, S.sbase, n_rows, small_max,
+    k_tier_counts<<<1, 64, 0, s>>>(T.key_b, T.pieces, T.cpos, T.split, T.spos, T.slots, T.sbase, n_rows, small_max,
                                    counts);
     return dev_check("tier keys");
 }
 
 // The work lists of one side, after tier_scan and with the counts known.
-hnv_status tier_emit(const int32_t *ptr, int64_t n_rows, int small_max, int chunk, const int32_t *rowmap,
-                     int32_t row_base, int32_t slot_offset, const int64_t *cnt, Scratch &S, DevSide &D, hipStream_t s)
+hnv_status tier_emit(const int32_t *ptr, int64_t n_rows, int chunk, const int32_t *rowmap, int32_t row_base,
+                     int32_t slot_offset, const int64_t *cnt, const TierArrays &T, Scratch &S, DevSide &D,
+                     hipStream_t s)
 {
-    (void)small_max;
     if (n_rows == 0)
         return HNV_OK;
     if (cnt[0] > 0)
-        k_small_items<<<grid_for(cnt[0]), kThreads, 0, s>>>(S.rows_b, ptr, cnt[0], rowmap, row_base,
+        k_small_items<<<grid_for(cnt[0]), kThreads, 0, s>>>(T.rows_b, ptr, cnt[0], rowmap, row_base,
                                                             const_cast<Item *>(D.small));
     if (cnt[1] > 0) {
-        k_chunk_items<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, chunk, S.pieces, S.cpos, S.sbase,
-                                                            slot_offset, S.items, S.key_a, S.ids_a);
+        k_chunk_items<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, chunk, T.pieces, T.cpos, T.sbase,
+                                                            slot_offset, S.items, S.ckey_a, S.ids_a);
         size_t tb = S.temp_bytes;
-        if (prim_sort_pairs(S.temp, tb, S.key_a, S.key_b, S.ids_a, S.ids_b, (int)cnt[1], 0,
-                                               bits_for(chunk + 1), s) != hipSuccess)
+        if (prim_sort_pairs(S.temp, tb, S.ckey_a, S.ckey_b, S.ids_a, S.ids_b, (int)cnt[1], 0, bits_for(chunk + 1),
+                            s) != hipSuccess)
             return fail(HNV_EDEVICE, "sort of the wavefront tier");
         k_gather_items<<<grid_for(cnt[1]), kThreads, 0, s>>>(S.items, S.ids_b, cnt[1],
                                                              const_cast<Item *>(D.chunks));
     }
     if (cnt[2] > 0)
-        k_split_items<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, S.pieces, S.spos, S.sbase, slot_offset,
+        k_split_items<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, T.pieces, T.spos, T.sbase, slot_offset,
                                                             const_cast<Split *>(D.splits));
     return dev_check("work lists");
 }
 
+// Level l of a plan whose inputs have passed their checks.
 hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *maps, int n_levels, int l,
-                       bool full, Scratch &S, hipStream_t s)
+                       Scratch &S, hipStream_t s)
 {
     const hnv_level_dev &lv = levels[l];
     const hnv_level_dev *C = (l + 1 < n_levels) ? &levels[l + 1] : nullptr;
     const hnv_map *m = C ? &maps[l] : nullptr;
-    if (hnv_status st = check_level(lv, C, m, l, full, S, s); st != HNV_OK)
-        return st;
     LevelPlan &L = p->lv[l];
     const int64_t nV = lv.n_nodes, nE = lv.n_edges, nnz = lv.nnz;
     const int sm = p->small_max, chunk = p->opts.chunk;
@@ -562,6 +703,9 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
     // by node; the offsets come from the sorted node ids)
     size_t tb = S.temp_bytes;
     if (nnz > 0) {
+        // (the checks of all levels ran before, so the map is this level's again)
+        if ((st = incidence_edges(lv.edge_ptr, nE, nnz, S, s)) != HNV_OK)
+            return st;
         if (prim_sort_pairs(S.temp, tb, reinterpret_cast<const uint32_t *>(lv.edge_idx),
                                                reinterpret_cast<uint32_t *>(S.keys_out), S.inc_edge, S.csc_e,
                                                (int)nnz, 0, bits_for(nV), s) != hipSuccess)
@@ -580,10 +724,10 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
         }
         const int64_t rows = nV + nE, rows_c = L.rows_coarse;
         if (rows > 0) {
-            k_iota<<<grid_for(rows), kThreads, 0, s>>>(rows, S.rows_a);
+            k_iota<<<grid_for(rows), kThreads, 0, s>>>(rows, S.tier.rows_a);
             tb = S.temp_bytes;
             if (prim_sort_pairs(S.temp, tb, reinterpret_cast<const uint32_t *>(L.rowmap),
-                                                   reinterpret_cast<uint32_t *>(S.keys_out), S.rows_a, L.inv_idx,
+                                                   reinterpret_cast<uint32_t *>(S.keys_out), S.tier.rows_a, L.inv_idx,
                                                    (int)rows, 0, bits_for(rows_c), s) != hipSuccess)
                 return fail(HNV_EDEVICE, "sort of the inverse map");
         }
@@ -592,21 +736,24 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
     }
     if ((st = dev_check("plan arrays")) != HNV_OK)
         return st;
-    // degree tiers: side 0 then side 1 (partial slots continue across sides)
+    // degree tiers: both sides' scans, one read of their counts, then the
+    // work lists, side 0 then side 1 (partial slots continue across sides)
+    const TierArrays T[2] = {side_arrays(S, 0), side_arrays(S, side1_offset(nE))};
+    for (int sd = 0; sd < 2; ++sd)
+        if ((st = tier_scan(sd == 0 ? S0.ptr : S1.ptr, sd == 0 ? nE : nV, sm, chunk, T[sd], S, S.counts + 4 * sd,
+                            s)) != HNV_OK)
+            return st;
     int64_t cnt[2][4];
+    if ((st = read_back(cnt, S.counts, sizeof(cnt), s)) != HNV_OK)
+        return st;
     for (int sd = 0; sd < 2; ++sd) {
         const int64_t n_rows = sd == 0 ? nE : nV;
-        if ((st = tier_scan(sd == 0 ? S0.ptr : S1.ptr, n_rows, sm, chunk, S, S.counts + 4 * sd, s)) != HNV_OK)
-            return st;
-        // keep this side's sorted rows and scans: read the counts, then emit
-        if ((st = read_back(cnt[sd], S.counts + 4 * sd, 4 * sizeof(int64_t), s)) != HNV_OK)
-            return st;
         const int32_t slot_offset = sd == 0 ? 0 : (int32_t)cnt[0][3];
         DevSide &D = L.side[sd];
         if (cnt[sd][0] > D.n_small || cnt[sd][1] > D.n_chunks || cnt[sd][2] > D.n_splits)
             return fail(HNV_EDEVICE, "work lists exceed their bounds");
-        if ((st = tier_emit(D.ptr, n_rows, sm, chunk, C ? L.rowmap : nullptr, D.row_base, slot_offset, cnt[sd], S, D,
-                            s)) != HNV_OK)
+        if ((st = tier_emit(D.ptr, n_rows, chunk, C ? L.rowmap : nullptr, D.row_base, slot_offset, cnt[sd], T[sd], S,
+                            D, s)) != HNV_OK)
             return st;
         D.n_small = (int32_t)cnt[sd][0];
         D.n_chunks = (int32_t)cnt[sd][1];
@@ -672,7 +819,7 @@ hnv_status score_dev_layout(int64_t n_cand, int64_t n_members, int d, hnv_dtype 
     L.off_splits = take(sizeof(Split) * (size_t)L.n_splits);
     L.off_part = take(sizeof(float) * (size_t)L.n_slots * (2 * d + 8));
     Scratch S{};
-    if (hnv_status st = scratch_layout(n_members, n_cand, L.n_chunks, nullptr, S); st != HNV_OK)
+    if (hnv_status st = scratch_layout(n_members, n_cand, L.n_chunks, L.small_max + 2, nullptr, S); st != HNV_OK)
         return st;
     L.scratch_bytes = S.total;
     L.off_scratch = take(L.scratch_bytes);
@@ -749,12 +896,30 @@ extern "C" hnv_status hnv_plan_create_device(const hnv_level_dev *levels, const 
         char *base = static_cast<char *>(workspace);
         carve(p, bounds, base);
         char *scratch_base = in_zbuf ? static_cast<char *>(p->zbuf) : base + p->ws_bytes;
+        int *flags = reinterpret_cast<int *>(scratch_base);
+        char *level_base = scratch_base + flags_bytes(n_levels);
+        auto level_scratch = [&](int l, Scratch &S) {
+            const int32_t nch = std::max(bounds[l].n_chunks[0], bounds[l].n_chunks[1]);
+            return scratch_layout(bounds[l].nnz, bounds[l].rows, nch, p->small_max + 2, level_base, S);
+        };
+        // every level's and map's checks, then one read of their flags
+        const bool full = validate_inputs != 0;
+        k_fill<<<grid_for(4 * (int64_t)n_levels), kThreads, 0, s>>>(flags, 4 * (int64_t)n_levels, 0);
         for (int l = 0; l < n_levels && st == HNV_OK; ++l) {
             Scratch S{};
-            const int32_t nch = std::max(bounds[l].n_chunks[0], bounds[l].n_chunks[1]);
-            st = scratch_layout(bounds[l].nnz, bounds[l].rows, nch, scratch_base, S);
-            if (st == HNV_OK)
-                st = build_level(p, levels, maps, n_levels, l, validate_inputs != 0, S, s);
+            if ((st = level_scratch(l, S)) == HNV_OK)
+                st = launch_checks(levels[l], l + 1 < n_levels ? &levels[l + 1] : nullptr,
+                                   l + 1 < n_levels ? &maps[l] : nullptr, full, S, flags + 4 * l, s);
+        }
+        std::vector<int> hflags(4 * (size_t)n_levels, 0);
+        if (st == HNV_OK)
+            st = read_back(hflags.data(), flags, hflags.size() * sizeof(int), s);
+        for (int l = 0; l < n_levels && st == HNV_OK; ++l)
+            st = report_checks(l, &hflags[4 * (size_t)l], full);
+        for (int l = 0; l < n_levels && st == HNV_OK; ++l) {
+            Scratch S{};
+            if ((st = level_scratch(l, S)) == HNV_OK)
+                st = build_level(p, levels, maps, n_levels, l, S, s);
         }
         if (st == HNV_OK) {
             p->ws_bytes = total;
@@ -810,7 +975,7 @@ extern "C" hnv_status hnv_score_plan_create_device(const int32_t *cand_ptr, cons
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *base = static_cast<char *>(workspace);
     Scratch S{};
-    if ((st = scratch_layout(n_members, n_cand, L.n_chunks, base + L.off_scratch, S)) != HNV_OK)
+    if ((st = scratch_layout(n_members, n_cand, L.n_chunks, L.small_max + 2, base + L.off_scratch, S)) != HNV_OK)
         return st;
     // checks: offsets (start 0, never decrease, end at n_members) and member
     // ids in [0, z_rows); empty candidates are allowed (their rows are NaN)
@@ -845,12 +1010,13 @@ extern "C" hnv_status hnv_score_plan_create_device(const int32_t *cand_ptr, cons
     D.chunks = reinterpret_cast<const Item *>(base + L.off_chunks);
     D.splits = reinterpret_cast<const Split *>(base + L.off_splits);
     if (n_cand > 0) {
-        if ((st = tier_scan(cand_ptr, n_cand, L.small_max, kScoreChunk, S, S.counts, s)) != HNV_OK ||
+        const TierArrays T = side_arrays(S, 0);
+        if ((st = tier_scan(cand_ptr, n_cand, L.small_max, kScoreChunk, T, S, S.counts, s)) != HNV_OK ||
             (st = read_back(cnt, S.counts, sizeof(cnt), s)) != HNV_OK)
             return st;
         if (cnt[0] > L.n_small || cnt[1] > L.n_chunks || cnt[2] > L.n_splits || cnt[3] > L.n_slots)
             return fail(HNV_EDEVICE, "work lists exceed their bounds");
-        if ((st = tier_emit(cand_ptr, n_cand, L.small_max, kScoreChunk, nullptr, 0, 0, cnt, S, D, s)) != HNV_OK)
+        if ((st = tier_emit(cand_ptr, n_cand, kScoreChunk, nullptr, 0, 0, cnt, T, S, D, s)) != HNV_OK)
             return st;
     }
     hipError_t e = hipStreamSynchronize(s);

@@ -367,14 +367,35 @@ HNV_DEV float group_sum(float x)
 template <typename T, int EPL>
 struct Own {
     typename Slice<T, EPL>::Raw x, y, z;
+    float rs;     // the row's scalar factor: r_u (forward, node rows) or w_e (hyperedge rows)
+    float prev;   // the accumulator the row adds to: dL/dw_e (hyperedge rows) or c_v (split node rows)
 };
 
 template <typename T, int EPL, int MODE>
-HNV_DEV void load_own(Own<T, EPL> &o, const GatherArgs &a, const Mats &m, int64_t zrow, int64_t srow, int deg,
-                      int col)
+HNV_DEV void load_own(Own<T, EPL> &o, const GatherArgs &a, const Mats &m, int row, int64_t zrow, int64_t srow,
+                      int deg, int col)
 {
     using S = Slice<T, EPL>;
     o.x = S::load(static_cast<const T *>(m.self) + srow * a.ld + col);
+    // The epilogue's scalars are fetched here too: issued after the gather
+    // they would add a dependent memory round trip to every row.  (Each row
+    // is finished by one lane group, so no other wave of the launch writes
+    // the accumulator in between.)
+    if (MODE == kFwd) {
+        if (deg > 0)
+            o.rs = a.r[zrow];
+    } else if (MODE == kAdjNode) {
+        if (deg > 0 && a.wgrad != 0)
+            o.rs = a.r[zrow];
+        if (a.wgrad == 2)
+            o.prev = a.cvec[row];
+    } else {
+        if (deg > 0) {
+            o.rs = a.w[row];
+            if (a.dw)
+                o.prev = a.dw[row];
+        }
+    }
     // the sweep's input and output rows serve the weight gradient only
     if (MODE != kFwd && deg > 0 && a.wgrad != 0) {
         o.y = S::load(static_cast<const T *>(a.yprev) + zrow * a.ld + col);
@@ -396,7 +417,7 @@ HNV_DEV double epilogue_fwd(const GatherArgs &a, void *dst, int zrow, int deg, i
     Slice<T, EPL>::unpack(own.x, z);
     if (deg > 0) {
         const float keep = 1.0f - a.omega;
-        const float mix = a.omega * a.r[zrow];
+        const float mix = a.omega * own.rs;
 #pragma unroll
         for (int i = 0; i < EPL; ++i)
             o[i] = fmaf(mix, acc[i], keep * z[i]);
@@ -452,11 +473,11 @@ HNV_DEV void epilogue_adj_node(const GatherArgs &a, int row, int deg, int col, b
     }
     dot = group_sum<G>(dot);
     if (writer && (threadIdx.x % G) == 0 && a.wgrad != 0) {
-        const float c = (deg > 0) ? a.r[zrow] * dot : 0.0f;
+        const float c = (deg > 0) ? own.rs * dot : 0.0f;
         if (a.wgrad == 1)
             a.cvec[row] = c;
         else
-            a.cvec[row] += a.omega * c;
+            a.cvec[row] = own.prev + a.omega * c;
     }
 }
 
@@ -479,7 +500,7 @@ HNV_DEV void epilogue_adj_edge(const GatherArgs &a, int row, int deg, int col, b
             float y[EPL];
             S::unpack(own.y, y);
             const float keep = 1.0f - a.omega;
-            const float mix = a.omega * a.w[row];
+            const float mix = a.omega * own.rs;
             if (a.dst2) {
                 float ge[EPL];
 #pragma unroll
@@ -509,7 +530,7 @@ HNV_DEV void epilogue_adj_edge(const GatherArgs &a, int row, int deg, int col, b
     }
     dot = group_sum<G>(dot);
     if (writer && a.dw && deg > 0 && (threadIdx.x % G) == 0)
-        a.dw[row] += a.omega * (dot - csum);
+        a.dw[row] = own.prev + a.omega * (dot - csum);
 }
 
 // ---------------------------------------------------------------------------
@@ -600,7 +621,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
             if (whole && col_ok) {
                 const int64_t srow =
                     (MODE == kFwd && (FUSED || a.self_mapped)) ? (int64_t)a.rowmap[zrow] : (int64_t)zrow;
-                load_own<T, EPL, MODE>(self, a, mats, zrow, srow, c.len, col);
+                load_own<T, EPL, MODE>(self, a, mats, c.row, zrow, srow, c.len, col);
             }
             if (use_scale)
                 gather_wave<T, EPL, G, true, kScalar>(nb, sc, a.cvec, c.start, c.len, src, a.ld, col, col_ok, lane, g,
@@ -637,7 +658,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
             Own<T, EPL> self{};
             if (valid && col_ok) {
                 const int64_t srow = (MODE == kFwd && (FUSED || a.self_mapped)) ? (int64_t)it.aux : (int64_t)zrow;
-                load_own<T, EPL, MODE>(self, a, mats, zrow, srow, it.len, col);
+                load_own<T, EPL, MODE>(self, a, mats, it.row, zrow, srow, it.len, col);
             }
             if (rr > 0) {
                 zero(acc);
@@ -710,7 +731,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(GatherArgs a)
         if (col_ok) {
             const int64_t srow =
                 (MODE == kFwd && (FUSED || a.self_mapped)) ? (int64_t)a.rowmap[zrow] : (int64_t)zrow;
-            load_own<T, EPL, MODE>(self, a, mats, zrow, srow, sp.deg, col);
+            load_own<T, EPL, MODE>(self, a, mats, sp.row, zrow, srow, sp.deg, col);
         }
         for (int k = g; k < sp.n_slots; k += Q) {
             const float *pp = a.partials + (int64_t)(sp.first_slot + k) * a.pstride;
