@@ -85,28 +85,39 @@ __global__ void k_check_no_edges(const int32_t *__restrict__ ptr, int64_t nnz, i
         atomicOr(flag, 1);
 }
 
-// Stable sort of (key, value) pairs by a key below n_bins <= kBinsMax (the
-// degree tiers have at most small_max + 2 <= 258 keys): per-tile counts of
-// every key, an exclusive scan of the counts laid out key-major (key b of
-// tile t at b * n_tiles + t), and a scatter in which each tile places its
-// elements in input order.  The result equals a stable radix sort's.
+// One pass of a stable counting sort of (key, value) pairs by the digit
+// (key >> shift) & mask, which is below n_bins <= kBinsMax: per-tile counts
+// of every digit, an exclusive scan of the counts laid out digit-major
+// (digit b of tile t at b * n_tiles + t), and a scatter in which each tile
+// places its elements in input order.  The degree tiers need one pass (at
+// most small_max + 2 <= 258 keys), the wavefront tier's chunk keys one pass
+// per 9 bits; the result equals a stable radix sort's.  The number of pairs
+// is n_max, or *n_dev when that is given (the grid is sized for n_max).
 constexpr int kBinsMax = 512;
+constexpr int kBinBits = 9;   // digit width of the multi-pass form
 constexpr int kBinRounds = 16;
 constexpr int kBinTile = kThreads * kBinRounds;
 constexpr int kBinWaves = kThreads / kWave;
 
-__global__ __launch_bounds__(kThreads) void k_bin_count(const uint32_t *__restrict__ key, int64_t n, int n_bins,
-                                                        int64_t n_tiles, int32_t *__restrict__ counts)
+__device__ inline int64_t pairs_of(int64_t n_max, const int64_t *n_dev)
+{
+    return n_dev ? min(n_max, *n_dev) : n_max;
+}
+
+__global__ __launch_bounds__(kThreads) void k_bin_count(const uint32_t *__restrict__ key, int64_t n_max,
+                                                        const int64_t *__restrict__ n_dev, int shift, uint32_t mask,
+                                                        int n_bins, int64_t n_tiles, int32_t *__restrict__ counts)
 {
     __shared__ int32_t h[kBinsMax];
     for (int b = threadIdx.x; b < n_bins; b += kThreads)
         h[b] = 0;
     __syncthreads();
+    const int64_t n = pairs_of(n_max, n_dev);
     const int64_t base = (int64_t)blockIdx.x * kBinTile;
     for (int k = 0; k < kBinRounds; ++k) {
         const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
         if (i < n)
-            atomicAdd(&h[key[i]], 1);
+            atomicAdd(&h[(key[i] >> shift) & mask], 1);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < n_bins; b += kThreads)
@@ -130,8 +141,9 @@ __device__ inline uint64_t same_key_lanes(uint32_t key, int bits, bool active)
 // an element goes to the next free position of its key, after the elements
 // of the same key in lower lanes of its wavefront and in lower wavefronts.
 __global__ __launch_bounds__(kThreads) void k_bin_scatter(const uint32_t *__restrict__ key,
-                                                          const int32_t *__restrict__ val, int64_t n, int n_bins,
-                                                          int bits, int64_t n_tiles,
+                                                          const int32_t *__restrict__ val, int64_t n_max,
+                                                          const int64_t *__restrict__ n_dev, int shift,
+                                                          uint32_t mask, int n_bins, int bits, int64_t n_tiles,
                                                           const int32_t *__restrict__ offs,
                                                           uint32_t *__restrict__ key_out,
                                                           int32_t *__restrict__ val_out)
@@ -146,21 +158,23 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(const uint32_t *__rest
     __syncthreads();
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    const int64_t n = pairs_of(n_max, n_dev);
     const int64_t base = (int64_t)blockIdx.x * kBinTile;
     for (int k = 0; k < kBinRounds && base + (int64_t)k * kThreads < n; ++k) {   // uniform over the block
         const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
         const bool act = i < n;
-        const uint32_t kk = act ? key[i] : 0u;
-        const uint64_t peers = same_key_lanes(kk, bits, act);
+        const uint32_t kv = act ? key[i] : 0u;
+        const uint32_t dg = (kv >> shift) & mask;
+        const uint64_t peers = same_key_lanes(dg, bits, act);
         const int rank = __popcll(peers & below);
         if (act && rank == 0)
-            wcount[wave][kk] = __popcll(peers);
+            wcount[wave][dg] = __popcll(peers);
         __syncthreads();
         if (act) {
-            int32_t pos = next[kk] + rank;
+            int32_t pos = next[dg] + rank;
             for (int w = 0; w < wave; ++w)
-                pos += wcount[w][kk];
-            key_out[pos] = kk;
+                pos += wcount[w][dg];
+            key_out[pos] = kv;
             val_out[pos] = val[i];
         }
         __syncthreads();
@@ -176,17 +190,31 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(const uint32_t *__rest
     }
 }
 
+// A level's build runs to its end even when its checks failed, so that the
+// plan needs a single synchronisation: the kernels below that would follow
+// the level's offsets, ids or map entries read the check flags first (the
+// level's word and the map's) and then write an empty but well-formed
+// result instead (zero offsets, zero ids, zero degrees).  Every later
+// kernel stays in bounds on those.
+__device__ inline bool level_failed(const int *bad) { return bad && (bad[0] | bad[1]) != 0; }
+
 // CSR offsets from keys sorted ascending (keys in [0, n_keys)): ptr[v] is
 // the first position whose key is >= v, for v in [0, n_keys].  Thread j
 // (0 <= j <= n) writes the offsets of the keys in (keys[j-1], keys[j]],
 // with keys[-1] = -1 and keys[n] = n_keys, so every entry is written once
 // and keys missing from the list (rows without entries) get empty ranges.
 __global__ __launch_bounds__(kThreads) void k_offsets_sorted(const uint32_t *__restrict__ keys, int64_t n,
-                                                             int64_t n_keys, int32_t *__restrict__ ptr)
+                                                             int64_t n_keys, const int *__restrict__ bad,
+                                                             int32_t *__restrict__ ptr)
 {
     const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (j > n)
         return;
+    if (level_failed(bad)) {   // the n + 1 threads clear the n_keys + 1 entries
+        for (int64_t v = j; v <= n_keys; v += n + 1)
+            ptr[v] = 0;
+        return;
+    }
     const int64_t lo = (j == 0) ? -1 : (int64_t)keys[j - 1];
     const int64_t hi = (j == n) ? n_keys : (int64_t)keys[j];
     for (int64_t v = lo + 1; v <= hi; ++v)
@@ -220,11 +248,16 @@ __global__ __launch_bounds__(kThreads) void k_fill_f32(float *__restrict__ p, in
 __global__ __launch_bounds__(kThreads) void k_rowmap(const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
                                                      const int32_t *__restrict__ node_rep,
                                                      const int32_t *__restrict__ edge_rep, int64_t n_nodes,
-                                                     int64_t n_edges, int64_t n_nodes_c, int32_t *__restrict__ rowmap)
+                                                     int64_t n_edges, int64_t n_nodes_c, const int *__restrict__ bad,
+                                                     int32_t *__restrict__ rowmap)
 {
     const int64_t u = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (u >= n_nodes + n_edges)
         return;
+    if (level_failed(bad)) {
+        rowmap[u] = 0;
+        return;
+    }
     if (u < n_nodes) {
         rowmap[u] = node_rep[u];
         return;
@@ -236,40 +269,48 @@ __global__ __launch_bounds__(kThreads) void k_rowmap(const int32_t *__restrict__
 
 __global__ __launch_bounds__(kThreads) void k_compose(const int32_t *__restrict__ idx,
                                                       const int32_t *__restrict__ map, int64_t n,
-                                                      int32_t *__restrict__ out)
+                                                      const int *__restrict__ bad, int32_t *__restrict__ out)
 {
     const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (j < n)
-        out[j] = map[idx[j]];
+        out[j] = level_failed(bad) ? 0 : map[idx[j]];
 }
 
+// A row's wavefront-tier counts: its chunks, whether it is split, its
+// partial slots.  One exclusive scan of them (componentwise sums) gives each
+// row's first chunk item, split-row entry and partial slot.
+struct TierCount {
+    int32_t pieces, split, slots;
+};
+struct TierCountPlus {
+    __host__ __device__ TierCount operator()(const TierCount &x, const TierCount &y) const
+    {
+        return TierCount{x.pieces + y.pieces, x.split + y.split, x.slots + y.slots};
+    }
+};
+
 // per row of one side: the small-tier sort key (small_max - degree, or
-// small_max + 1 for longer rows), the row id, its chunk count, whether it is
-// split, and its partial slots
+// small_max + 1 for longer rows), the row id and its tier counts
 __global__ __launch_bounds__(kThreads) void k_tier_keys(const int32_t *__restrict__ ptr, int64_t n_rows,
-                                                        int small_max, int chunk, uint32_t *__restrict__ key,
-                                                        int32_t *__restrict__ row, int32_t *__restrict__ pieces,
-                                                        int32_t *__restrict__ split, int32_t *__restrict__ slots)
+                                                        int small_max, int chunk, const int *__restrict__ bad,
+                                                        uint32_t *__restrict__ key, int32_t *__restrict__ row,
+                                                        TierCount *__restrict__ tc)
 {
     const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (r >= n_rows)
         return;
-    const int32_t deg = ptr[r + 1] - ptr[r];
+    const int32_t deg = level_failed(bad) ? 0 : ptr[r + 1] - ptr[r];
     const bool small = deg <= small_max;
     const int32_t pc = small ? 0 : (deg + chunk - 1) / chunk;
     key[r] = small ? (uint32_t)(small_max - deg) : (uint32_t)(small_max + 1);
     row[r] = (int32_t)r;
-    pieces[r] = pc;
-    split[r] = pc > 1 ? 1 : 0;
-    slots[r] = pc > 1 ? pc : 0;
+    tc[r] = TierCount{pc, pc > 1 ? 1 : 0, pc > 1 ? pc : 0};
 }
 
 // counts[0..3] of one side: small rows, chunks, split rows, partial slots
-// (exclusive scans plus their last terms; the small rows from the sorted keys)
-__global__ void k_tier_counts(const uint32_t *__restrict__ sorted_key, const int32_t *__restrict__ pieces,
-                              const int32_t *__restrict__ cpos, const int32_t *__restrict__ split,
-                              const int32_t *__restrict__ spos, const int32_t *__restrict__ slots,
-                              const int32_t *__restrict__ sbase, int64_t n_rows, int small_max,
+// (the exclusive scan plus its last term; the small rows from the sorted keys)
+__global__ void k_tier_counts(const uint32_t *__restrict__ sorted_key, const TierCount *__restrict__ tc,
+                              const TierCount *__restrict__ tpos, int64_t n_rows, int small_max,
                               int64_t *__restrict__ counts)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0)
@@ -288,20 +329,22 @@ __global__ void k_tier_counts(const uint32_t *__restrict__ sorted_key, const int
             hi = mid;
     }
     counts[0] = lo;
-    counts[1] = (int64_t)cpos[n_rows - 1] + pieces[n_rows - 1];
-    counts[2] = (int64_t)spos[n_rows - 1] + split[n_rows - 1];
-    counts[3] = (int64_t)sbase[n_rows - 1] + slots[n_rows - 1];
+    const TierCount c = tc[n_rows - 1], p = tpos[n_rows - 1];
+    counts[1] = (int64_t)p.pieces + c.pieces;
+    counts[2] = (int64_t)p.split + c.split;
+    counts[3] = (int64_t)p.slots + c.slots;
 }
 
 // lane-group tier items in sorted order; aux = the coarse row the row's own
 // value is projected from (0 at the coarsest level)
 __global__ __launch_bounds__(kThreads) void k_small_items(const int32_t *__restrict__ sorted_row,
-                                                          const int32_t *__restrict__ ptr, int64_t n_small,
+                                                          const int32_t *__restrict__ ptr,
+                                                          const int64_t *__restrict__ n_small,
                                                           const int32_t *__restrict__ rowmap, int32_t row_base,
                                                           Item *__restrict__ items)
 {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n_small)
+    if (i >= *n_small)
         return;
     const int32_t r = sorted_row[i];
     items[i] = Item{r, ptr[r], ptr[r + 1] - ptr[r], rowmap ? rowmap[row_base + r] : 0};
@@ -310,45 +353,51 @@ __global__ __launch_bounds__(kThreads) void k_small_items(const int32_t *__restr
 // wavefront tier items in row order (pieces of a row in order), with the
 // sort key chunk - len (a stable ascending sort puts the longest first)
 __global__ __launch_bounds__(kThreads) void k_chunk_items(const int32_t *__restrict__ ptr, int64_t n_rows, int chunk,
-                                                          const int32_t *__restrict__ pieces,
-                                                          const int32_t *__restrict__ cpos,
-                                                          const int32_t *__restrict__ sbase, int32_t slot_offset,
+                                                          const TierCount *__restrict__ tc,
+                                                          const TierCount *__restrict__ tpos,
+                                                          const int64_t *__restrict__ slot_base,
                                                           Item *__restrict__ items, uint32_t *__restrict__ key,
                                                           int32_t *__restrict__ id)
 {
     const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (r >= n_rows)
         return;
-    const int32_t pc = pieces[r];
+    const int32_t pc = tc[r].pieces;
+    if (pc == 0)
+        return;
+    const TierCount at = tpos[r];
+    const int32_t slot_offset = slot_base ? (int32_t)*slot_base : 0;
     for (int32_t k = 0; k < pc; ++k) {
-        const int32_t pos = cpos[r] + k;
+        const int32_t pos = at.pieces + k;
         const int32_t s = ptr[r] + k * chunk;
         const int32_t len = min(chunk, ptr[r + 1] - s);
-        items[pos] = Item{(int32_t)r, s, len, pc == 1 ? -1 : slot_offset + sbase[r] + k};
+        items[pos] = Item{(int32_t)r, s, len, pc == 1 ? -1 : slot_offset + at.slots + k};
         key[pos] = (uint32_t)(chunk - len);
         id[pos] = pos;
     }
 }
 
 __global__ __launch_bounds__(kThreads) void k_gather_items(const Item *__restrict__ in,
-                                                           const int32_t *__restrict__ order, int64_t n,
-                                                           Item *__restrict__ out)
+                                                           const int32_t *__restrict__ order,
+                                                           const int64_t *__restrict__ n, Item *__restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i < n)
+    if (i < *n)
         out[i] = in[order[i]];
 }
 
 __global__ __launch_bounds__(kThreads) void k_split_items(const int32_t *__restrict__ ptr, int64_t n_rows,
-                                                          const int32_t *__restrict__ pieces,
-                                                          const int32_t *__restrict__ spos,
-                                                          const int32_t *__restrict__ sbase, int32_t slot_offset,
+                                                          const TierCount *__restrict__ tc,
+                                                          const TierCount *__restrict__ tpos,
+                                                          const int64_t *__restrict__ slot_base,
                                                           Split *__restrict__ splits)
 {
     const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (r >= n_rows || pieces[r] <= 1)
+    if (r >= n_rows || tc[r].pieces <= 1)
         return;
-    splits[spos[r]] = Split{(int32_t)r, slot_offset + sbase[r], pieces[r], ptr[r + 1] - ptr[r]};
+    const int32_t slot_offset = slot_base ? (int32_t)*slot_base : 0;
+    const TierCount at = tpos[r];
+    splits[at.split] = Split{(int32_t)r, slot_offset + at.slots, tc[r].pieces, ptr[r + 1] - ptr[r]};
 }
 
 // ---------------------------------------------------------------------------
@@ -383,7 +432,8 @@ LevelShape bound_shape(const hnv_level_dev &lv, const hnv_level_dev *coarse, int
 
 // The per-row arrays of one side's degree tiers.
 struct TierArrays {
-    int32_t *rows_a, *rows_b, *pieces, *cpos, *split, *spos, *slots, *sbase;
+    int32_t *rows_a, *rows_b;
+    TierCount *tc, *tpos;   // per-row tier counts and their exclusive scan
     uint32_t *key_a, *key_b;
 };
 
@@ -408,8 +458,7 @@ int64_t side1_offset(int64_t n_edges) { return (n_edges + 1 + kTierAlign - 1) / 
 TierArrays side_arrays(const Scratch &S, int64_t off)
 {
     const TierArrays &t = S.tier;
-    return TierArrays{t.rows_a + off, t.rows_b + off, t.pieces + off, t.cpos + off, t.split + off,
-                      t.spos + off,   t.slots + off,  t.sbase + off,  t.key_a + off, t.key_b + off};
+    return TierArrays{t.rows_a + off, t.rows_b + off, t.tc + off, t.tpos + off, t.key_a + off, t.key_b + off};
 }
 
 // entries of the key-count arrays of a bin sort of up to `rows` pairs
@@ -431,6 +480,9 @@ hnv_status cub_sizes(int64_t nnz, int64_t rows, int64_t n_chunks, int64_t bins, 
                                                (int)std::max<int64_t>(n_chunks, 1), 0, 32);
     if (e == hipSuccess)
         e = prim_exclusive_sum(nullptr, t[4], (int32_t *)nullptr, (int32_t *)nullptr, (int)bins);
+    if (e == hipSuccess)
+        e = prim_exclusive_scan(nullptr, t[5], (TierCount *)nullptr, (TierCount *)nullptr, TierCount{0, 0, 0},
+                                (int)std::max<int64_t>(rows + 1, 1), TierCountPlus());
     if (e != hipSuccess)
         return fail(HNV_EDEVICE, std::string("sort / scan storage query (needs a visible GPU): ") +
                                      hipGetErrorString(e));
@@ -455,15 +507,11 @@ hnv_status scratch_layout(int64_t nnz, int64_t rows, int64_t n_chunks, int n_bin
     const size_t t4 = 4 * (size_t)(rows + 2 + kTierAlign);
     S.tier.rows_a = (int32_t *)take(t4);
     S.tier.rows_b = (int32_t *)take(t4);
-    S.tier.pieces = (int32_t *)take(t4);
-    S.tier.cpos = (int32_t *)take(t4);
-    S.tier.split = (int32_t *)take(t4);
-    S.tier.spos = (int32_t *)take(t4);
-    S.tier.slots = (int32_t *)take(t4);
-    S.tier.sbase = (int32_t *)take(t4);
+    S.tier.tc = (TierCount *)take(3 * t4);
+    S.tier.tpos = (TierCount *)take(3 * t4);
     S.tier.key_a = (uint32_t *)take(t4);
     S.tier.key_b = (uint32_t *)take(t4);
-    const int64_t bins = bin_cap(rows, n_bins);
+    const int64_t bins = std::max(bin_cap(rows, n_bins), bin_cap(n_chunks, kBinsMax));
     S.bin_counts = (int32_t *)take(4 * bins);
     S.bin_offs = (int32_t *)take(4 * bins);
     S.ckey_a = (uint32_t *)take(4 * n_chunks);
@@ -480,9 +528,16 @@ hnv_status scratch_layout(int64_t nnz, int64_t rows, int64_t n_chunks, int n_bin
     return HNV_OK;
 }
 
-// check flags of every level, [level][level flags, map flags], ahead of the
-// per-level temporaries
-size_t flags_bytes(int n_levels) { return ((size_t)n_levels * 4 * sizeof(int) + 255) & ~size_t(255); }
+// What the build leaves on the device per level, read back once at its end:
+// the check flags (the level's word, the map's word) and the tier counts of
+// both sides (small rows, chunks, split rows, partial slots).  Kept ahead of
+// the per-level temporaries.
+struct LevelMeta {
+    int32_t flags[4];
+    int32_t pad[4];
+    int64_t counts[8];
+};
+size_t meta_bytes(int n_levels) { return ((size_t)n_levels * sizeof(LevelMeta) + 255) & ~size_t(255); }
 
 // plan layout and build-scratch size for these levels
 hnv_status device_layout(const hnv_level_dev *levels, int n_levels, int d, hnv_dtype dtype, const hnv_options &o,
@@ -508,7 +563,7 @@ hnv_status device_layout(const hnv_level_dev *levels, int n_levels, int d, hnv_d
             return st;
         scratch_bytes = std::max(scratch_bytes, S.total);
     }
-    scratch_bytes += flags_bytes(n_levels);
+    scratch_bytes += meta_bytes(n_levels);
     carve(p, bounds, nullptr);
     const size_t zbuf_bytes = (size_t)p->lv[0].rows * p->d * ((dtype == HNV_BF16) ? 2 : 4);
     scratch_in_zbuf = scratch_bytes <= zbuf_bytes;
@@ -526,6 +581,8 @@ hnv_status check_levels(const hnv_level_dev *levels, const hnv_map *maps, int n_
         const hnv_level_dev &L = levels[l];
         if (L.n_nodes < 0 || L.n_edges < 0 || L.nnz < 0 || !L.edge_ptr || (L.nnz > 0 && !L.edge_idx))
             return fail(HNV_EINVAL, "level " + std::to_string(l) + ": bad sizes or NULL arrays");
+        if (L.n_edges == 0 && L.nnz != 0)
+            return fail(HNV_EINVAL, "level " + std::to_string(l) + ": incidences without hyperedges");
         if (L.n_nodes + L.n_edges >= INT_MAX || L.nnz >= INT_MAX)
             return fail(HNV_EUNSUPPORTED, "level " + std::to_string(l) + ": rows and nnz must be below 2^31");
         if (L.n_nodes + L.n_edges > levels[0].n_nodes + levels[0].n_edges)
@@ -620,73 +677,101 @@ hnv_status report_checks(int l, const int *flags, bool full)
     return HNV_OK;
 }
 
+// Stable sort of the pairs (ka, va) by key (every key below key_limit) with
+// the counting passes above: n_max pairs, or *n_dev of them.  The sorted
+// pairs end in (kb, vb) after an odd number of passes, else in (ka, va);
+// `in_b` tells which.
+hnv_status bin_sort(uint32_t *ka, int32_t *va, uint32_t *kb, int32_t *vb, int64_t n_max, const int64_t *n_dev,
+                    int64_t key_limit, Scratch &S, hipStream_t s, bool &in_b)
+{
+    in_b = false;
+    if (n_max == 0)
+        return HNV_OK;
+    const int64_t tiles = (n_max + kBinTile - 1) / kBinTile;
+    const bool one = key_limit <= kBinsMax;
+    const int passes = one ? 1 : (bits_for(key_limit) + kBinBits - 1) / kBinBits;
+    const int n_bins = one ? (int)key_limit : kBinsMax;
+    const uint32_t mask = one ? 0xffffffffu : (uint32_t)(kBinsMax - 1);
+    uint32_t *kin = ka, *kout = kb;
+    int32_t *vin = va, *vout = vb;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = pass * kBinBits;
+        k_bin_count<<<(unsigned)tiles, kThreads, 0, s>>>(kin, n_max, n_dev, shift, mask, n_bins, tiles, S.bin_counts);
+        size_t tb = S.temp_bytes;
+        if (prim_exclusive_sum(S.temp, tb, S.bin_counts, S.bin_offs, tiles * n_bins, s) != hipSuccess)
+            return fail(HNV_EDEVICE, "scan of a counting sort's digit counts");
+        k_bin_scatter<<<(unsigned)tiles, kThreads, 0, s>>>(kin, vin, n_max, n_dev, shift, mask, n_bins,
+                                                           bits_for(n_bins), tiles, S.bin_offs, kout, vout);
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+        in_b = !in_b;
+    }
+    return dev_check("counting sort");
+}
+
 // The tier keys, sorts and scans of one side (arrays T); counts[0..3] on the
-// device.
-hnv_status tier_scan(const int32_t *ptr, int64_t n_rows, int small_max, int chunk, const TierArrays &T, Scratch &S,
-                     int64_t *counts, hipStream_t s)
+// device.  `bad`: the level's check flags (null: checked already).
+hnv_status tier_scan(const int32_t *ptr, int64_t n_rows, int small_max, int chunk, const int *bad,
+                     const TierArrays &T, Scratch &S, int64_t *counts, hipStream_t s)
 {
     if (n_rows == 0) {
         k_fill<<<1, kThreads, 0, s>>>(reinterpret_cast<int32_t *>(counts), 8, 0);
         return dev_check("tier counts");
     }
-    const int n = (int)n_rows;
-    k_tier_keys<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, small_max, chunk, T.key_a, T.rows_a, T.pieces,
-                                                      T.split, T.slots);
-    // the lane-group tier order: a stable sort on the small_max + 2 keys
-    const int n_bins = small_max + 2;
-    if (n_bins > kBinsMax)
+    if (small_max + 2 > kBinsMax)
         return fail(HNV_EUNSUPPORTED, "small_max above the tier sort's key range");
-    const int64_t tiles = (n_rows + kBinTile - 1) / kBinTile;
-    k_bin_count<<<(unsigned)tiles, kThreads, 0, s>>>(T.key_a, n_rows, n_bins, tiles, S.bin_counts);
+    const int n = (int)n_rows;
+    k_tier_keys<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, small_max, chunk, bad, T.key_a, T.rows_a,
+                                                      T.tc);
+    // the lane-group tier order: one counting pass over the small_max + 2
+    // keys, which leaves the sorted rows in rows_b
+    bool in_b = false;
+    if (hnv_status st = bin_sort(T.key_a, T.rows_a, T.key_b, T.rows_b, n_rows, nullptr, small_max + 2, S, s, in_b);
+        st != HNV_OK)
+        return st;
     size_t tb = S.temp_bytes;
-    if (prim_exclusive_sum(S.temp, tb, S.bin_counts, S.bin_offs, (int)(tiles * n_bins), s) != hipSuccess)
-        return fail(HNV_EDEVICE, "scan of the lane-group tier's key counts");
-    k_bin_scatter<<<(unsigned)tiles, kThreads, 0, s>>>(T.key_a, T.rows_a, n_rows, n_bins, bits_for(n_bins), tiles,
-                                                       S.bin_offs, T.key_b, T.rows_b);
-    tb = S.temp_bytes;
-    if (prim_exclusive_sum(S.temp, tb, T.pieces, T.cpos, n, s) != hipSuccess)
-        return fail(HNV_EDEVICE, "scan of chunk counts");
-    tb = S.temp_bytes;
-    if (prim_exclusive_sum(S.temp, tb, T.split, T.spos, n, s) != hipSuccess)
-        return fail(HNV_EDEVICE, "scan of split rows");
-    tb = S.temp_bytes;
-    if (prim_exclusive_sum(S.temp, tb, T.slots, T.sbase, n, s) != hipSuccess)
-        return fail(HNV_EDEVICE, "scan of partial slots");
-    k_tier_counts<<<1, 64, 0, s>>>(T.key_b, T.pieces, T.cpos, T.split, T.spos, T.slots, T.sbase, n_rows, small_max,
-                                   counts);
+    if (prim_exclusive_scan(S.temp, tb, T.tc, T.tpos, TierCount{0, 0, 0}, n, TierCountPlus(), s) != hipSuccess)
+        return fail(HNV_EDEVICE, "scan of the tier counts");
+    k_tier_counts<<<1, 64, 0, s>>>(T.key_b, T.tc, T.tpos, n_rows, small_max, counts);
     return dev_check("tier keys");
 }
 
-// The work lists of one side, after tier_scan and with the counts known.
+// The work lists of one side after tier_scan, from its counts on the device
+// (cnt[0..3]) without reading them: grids cover the bounds (max_chunks
+// wavefront-tier items) and the kernels stop at the counts.  slot_base (on
+// the device, or null for none) holds the partial slots of the side before.
 hnv_status tier_emit(const int32_t *ptr, int64_t n_rows, int chunk, const int32_t *rowmap, int32_t row_base,
-                     int32_t slot_offset, const int64_t *cnt, const TierArrays &T, Scratch &S, DevSide &D,
-                     hipStream_t s)
+                     const int64_t *slot_base, const int64_t *cnt, int64_t max_chunks, const TierArrays &T,
+                     Scratch &S, DevSide &D, hipStream_t s)
 {
     if (n_rows == 0)
         return HNV_OK;
-    if (cnt[0] > 0)
-        k_small_items<<<grid_for(cnt[0]), kThreads, 0, s>>>(T.rows_b, ptr, cnt[0], rowmap, row_base,
-                                                            const_cast<Item *>(D.small));
-    if (cnt[1] > 0) {
-        k_chunk_items<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, chunk, T.pieces, T.cpos, T.sbase,
-                                                            slot_offset, S.items, S.ckey_a, S.ids_a);
-        size_t tb = S.temp_bytes;
-        if (prim_sort_pairs(S.temp, tb, S.ckey_a, S.ckey_b, S.ids_a, S.ids_b, (int)cnt[1], 0, bits_for(chunk + 1),
-                            s) != hipSuccess)
-            return fail(HNV_EDEVICE, "sort of the wavefront tier");
-        k_gather_items<<<grid_for(cnt[1]), kThreads, 0, s>>>(S.items, S.ids_b, cnt[1],
-                                                             const_cast<Item *>(D.chunks));
+    k_small_items<<<grid_for(n_rows), kThreads, 0, s>>>(T.rows_b, ptr, cnt, rowmap, row_base,
+                                                        const_cast<Item *>(D.small));
+    if (max_chunks > 0) {
+        k_chunk_items<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, chunk, T.tc, T.tpos, slot_base, S.items,
+                                                            S.ckey_a, S.ids_a);
+        // longest first: a stable sort on chunk - len, which is below chunk
+        bool in_b = false;
+        if (hnv_status st = bin_sort(S.ckey_a, S.ids_a, S.ckey_b, S.ids_b, max_chunks, cnt + 1, chunk, S, s, in_b);
+            st != HNV_OK)
+            return st;
+        k_gather_items<<<grid_for(max_chunks), kThreads, 0, s>>>(S.items, in_b ? S.ids_b : S.ids_a, cnt + 1,
+                                                                 const_cast<Item *>(D.chunks));
     }
-    if (cnt[2] > 0)
-        k_split_items<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, T.pieces, T.spos, T.sbase, slot_offset,
-                                                            const_cast<Split *>(D.splits));
+    k_split_items<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, T.tc, T.tpos, slot_base,
+                                                        const_cast<Split *>(D.splits));
     return dev_check("work lists");
 }
 
-// Level l of a plan whose inputs have passed their checks.
+// Level l of a plan, enqueued without waiting: its checks were launched
+// before (their flags in M.flags gate the kernels that follow offsets and
+// ids), and the tier counts it leaves in M.counts are read with every other
+// level's once the whole build is enqueued (finish_level).
 hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *maps, int n_levels, int l,
-                       Scratch &S, hipStream_t s)
+                       LevelMeta *M, Scratch &S, hipStream_t s)
 {
+    const int *bad = M->flags;
     const hnv_level_dev &lv = levels[l];
     const hnv_level_dev *C = (l + 1 < n_levels) ? &levels[l + 1] : nullptr;
     const hnv_map *m = C ? &maps[l] : nullptr;
@@ -703,9 +788,8 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
     // by node; the offsets come from the sorted node ids)
     size_t tb = S.temp_bytes;
     if (nnz > 0) {
-        // (the checks of all levels ran before, so the map is this level's again)
-        if ((st = incidence_edges(lv.edge_ptr, nE, nnz, S, s)) != HNV_OK)
-            return st;
+        // the values: the hyperedge of each incidence, which the level's
+        // checks left in S.inc_edge (a level with incidences has hyperedges)
         if (prim_sort_pairs(S.temp, tb, reinterpret_cast<const uint32_t *>(lv.edge_idx),
                                                reinterpret_cast<uint32_t *>(S.keys_out), S.inc_edge, S.csc_e,
                                                (int)nnz, 0, bits_for(nV), s) != hipSuccess)
@@ -713,14 +797,14 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
         k_add_const<<<grid_for(nnz), kThreads, 0, s>>>(S.csc_e, nnz, (int32_t)nV, const_cast<int32_t *>(S1.idx));
     }
     k_offsets_sorted<<<grid_for(nnz + 1), kThreads, 0, s>>>(reinterpret_cast<const uint32_t *>(S.keys_out), nnz, nV,
-                                                            const_cast<int32_t *>(S1.ptr));
+                                                            bad, const_cast<int32_t *>(S1.ptr));
     // projection row map, composed indices, inverse map
     if (C) {
         k_rowmap<<<grid_for(nV + nE), kThreads, 0, s>>>(lv.edge_ptr, lv.edge_idx, m->node_rep, m->edge_rep, nV, nE,
-                                                        C->n_nodes, L.rowmap);
+                                                        C->n_nodes, bad, L.rowmap);
         if (nnz > 0) {
-            k_compose<<<grid_for(nnz), kThreads, 0, s>>>(S0.idx, L.rowmap, nnz, const_cast<int32_t *>(S0.cidx));
-            k_compose<<<grid_for(nnz), kThreads, 0, s>>>(S1.idx, L.rowmap, nnz, const_cast<int32_t *>(S1.cidx));
+            k_compose<<<grid_for(nnz), kThreads, 0, s>>>(S0.idx, L.rowmap, nnz, bad, const_cast<int32_t *>(S0.cidx));
+            k_compose<<<grid_for(nnz), kThreads, 0, s>>>(S1.idx, L.rowmap, nnz, bad, const_cast<int32_t *>(S1.cidx));
         }
         const int64_t rows = nV + nE, rows_c = L.rows_coarse;
         if (rows > 0) {
@@ -732,39 +816,24 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
                 return fail(HNV_EDEVICE, "sort of the inverse map");
         }
         k_offsets_sorted<<<grid_for(rows + 1), kThreads, 0, s>>>(reinterpret_cast<const uint32_t *>(S.keys_out),
-                                                                 rows, rows_c, L.inv_ptr);
+                                                                 rows, rows_c, bad, L.inv_ptr);
     }
     if ((st = dev_check("plan arrays")) != HNV_OK)
         return st;
-    // degree tiers: both sides' scans, one read of their counts, then the
-    // work lists, side 0 then side 1 (partial slots continue across sides)
+    // degree tiers: each side's scans, then its work lists, side 0 then
+    // side 1 (partial slots continue across sides); the sizes of the work
+    // lists stay on the device until the build ends.  D.n_* still hold the
+    // bounds the workspace was carved for.
     const TierArrays T[2] = {side_arrays(S, 0), side_arrays(S, side1_offset(nE))};
-    for (int sd = 0; sd < 2; ++sd)
-        if ((st = tier_scan(sd == 0 ? S0.ptr : S1.ptr, sd == 0 ? nE : nV, sm, chunk, T[sd], S, S.counts + 4 * sd,
-                            s)) != HNV_OK)
-            return st;
-    int64_t cnt[2][4];
-    if ((st = read_back(cnt, S.counts, sizeof(cnt), s)) != HNV_OK)
-        return st;
     for (int sd = 0; sd < 2; ++sd) {
-        const int64_t n_rows = sd == 0 ? nE : nV;
-        const int32_t slot_offset = sd == 0 ? 0 : (int32_t)cnt[0][3];
         DevSide &D = L.side[sd];
-        if (cnt[sd][0] > D.n_small || cnt[sd][1] > D.n_chunks || cnt[sd][2] > D.n_splits)
-            return fail(HNV_EDEVICE, "work lists exceed their bounds");
-        if ((st = tier_emit(D.ptr, n_rows, chunk, C ? L.rowmap : nullptr, D.row_base, slot_offset, cnt[sd], T[sd], S,
-                            D, s)) != HNV_OK)
+        const int64_t n_rows = sd == 0 ? nE : nV;
+        int64_t *cnt = M->counts + 4 * sd;
+        if ((st = tier_scan(D.ptr, n_rows, sm, chunk, bad, T[sd], S, cnt, s)) != HNV_OK ||
+            (st = tier_emit(D.ptr, n_rows, chunk, C ? L.rowmap : nullptr, D.row_base,
+                            sd == 0 ? nullptr : M->counts + 3, cnt, D.n_chunks, T[sd], S, D, s)) != HNV_OK)
             return st;
-        D.n_small = (int32_t)cnt[sd][0];
-        D.n_chunks = (int32_t)cnt[sd][1];
-        D.n_splits = (int32_t)cnt[sd][2];
-        L.n_small[sd] = D.n_small;
-        L.n_chunks[sd] = D.n_chunks;
-        L.n_splits[sd] = D.n_splits;
     }
-    L.n_slots = (int32_t)(cnt[0][3] + cnt[1][3]);
-    if (L.n_slots > p->max_slots)
-        return fail(HNV_EDEVICE, "partial slots exceed their bound");
     // weights and reciprocals
     if (lv.edge_w) {
         if ((st = copy_d2d(L.w, lv.edge_w, 4 * nE, s)) != HNV_OK)
@@ -775,6 +844,31 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
     if ((st = dev_check("weights")) != HNV_OK)
         return st;
     return dev_recompute_reciprocals(p, l, s);
+}
+
+// Level l's work-list sizes from the counts read back after the build
+// (counts: this level's LevelMeta::counts), checked against the bounds the
+// workspace was carved for.
+hnv_status finish_level(hnv_plan *p, int l, const int64_t *counts)
+{
+    LevelPlan &L = p->lv[l];
+    for (int sd = 0; sd < 2; ++sd) {
+        const int64_t *cnt = counts + 4 * sd;
+        DevSide &D = L.side[sd];
+        if (cnt[0] > D.n_small || cnt[1] > D.n_chunks || cnt[2] > D.n_splits)
+            return fail(HNV_EDEVICE, "work lists exceed their bounds");
+        D.n_small = (int32_t)cnt[0];
+        D.n_chunks = (int32_t)cnt[1];
+        D.n_splits = (int32_t)cnt[2];
+        L.n_small[sd] = D.n_small;
+        L.n_chunks[sd] = D.n_chunks;
+        L.n_splits[sd] = D.n_splits;
+    }
+    const int64_t slots = counts[3] + counts[7];
+    if (slots > p->max_slots)
+        return fail(HNV_EDEVICE, "partial slots exceed their bound");
+    L.n_slots = (int32_t)slots;
+    return HNV_OK;
 }
 
 // Candidate-scoring plan from device arrays: the candidates are the rows of
@@ -896,37 +990,33 @@ extern "C" hnv_status hnv_plan_create_device(const hnv_level_dev *levels, const 
         char *base = static_cast<char *>(workspace);
         carve(p, bounds, base);
         char *scratch_base = in_zbuf ? static_cast<char *>(p->zbuf) : base + p->ws_bytes;
-        int *flags = reinterpret_cast<int *>(scratch_base);
-        char *level_base = scratch_base + flags_bytes(n_levels);
-        auto level_scratch = [&](int l, Scratch &S) {
-            const int32_t nch = std::max(bounds[l].n_chunks[0], bounds[l].n_chunks[1]);
-            return scratch_layout(bounds[l].nnz, bounds[l].rows, nch, p->small_max + 2, level_base, S);
-        };
-        // every level's and map's checks, then one read of their flags
+        LevelMeta *meta = reinterpret_cast<LevelMeta *>(scratch_base);
+        char *level_base = scratch_base + meta_bytes(n_levels);
+        // Each level's checks, then its build, all enqueued without waiting
+        // (the build's kernels that follow offsets and ids are gated on the
+        // check flags); then the one synchronisation of the build: every
+        // level's flags and tier counts read together.
         const bool full = validate_inputs != 0;
-        k_fill<<<grid_for(4 * (int64_t)n_levels), kThreads, 0, s>>>(flags, 4 * (int64_t)n_levels, 0);
+        const int64_t meta_words = (int64_t)n_levels * (int64_t)sizeof(LevelMeta) / 4;
+        k_fill<<<grid_for(meta_words), kThreads, 0, s>>>(reinterpret_cast<int32_t *>(meta), meta_words, 0);
         for (int l = 0; l < n_levels && st == HNV_OK; ++l) {
             Scratch S{};
-            if ((st = level_scratch(l, S)) == HNV_OK)
-                st = launch_checks(levels[l], l + 1 < n_levels ? &levels[l + 1] : nullptr,
-                                   l + 1 < n_levels ? &maps[l] : nullptr, full, S, flags + 4 * l, s);
+            const int32_t nch = std::max(bounds[l].n_chunks[0], bounds[l].n_chunks[1]);
+            const hnv_level_dev *C = l + 1 < n_levels ? &levels[l + 1] : nullptr;
+            if ((st = scratch_layout(bounds[l].nnz, bounds[l].rows, nch, p->small_max + 2, level_base, S)) ==
+                    HNV_OK &&
+                (st = launch_checks(levels[l], C, C ? &maps[l] : nullptr, full, S, meta[l].flags, s)) == HNV_OK)
+                st = build_level(p, levels, maps, n_levels, l, &meta[l], S, s);
         }
-        std::vector<int> hflags(4 * (size_t)n_levels, 0);
+        std::vector<LevelMeta> h(n_levels);
         if (st == HNV_OK)
-            st = read_back(hflags.data(), flags, hflags.size() * sizeof(int), s);
+            st = read_back(h.data(), meta, h.size() * sizeof(LevelMeta), s);
         for (int l = 0; l < n_levels && st == HNV_OK; ++l)
-            st = report_checks(l, &hflags[4 * (size_t)l], full);
-        for (int l = 0; l < n_levels && st == HNV_OK; ++l) {
-            Scratch S{};
-            if ((st = level_scratch(l, S)) == HNV_OK)
-                st = build_level(p, levels, maps, n_levels, l, S, s);
-        }
-        if (st == HNV_OK) {
+            st = report_checks(l, h[l].flags, full);
+        for (int l = 0; l < n_levels && st == HNV_OK; ++l)
+            st = finish_level(p, l, h[l].counts);
+        if (st == HNV_OK)
             p->ws_bytes = total;
-            hipError_t e = hipStreamSynchronize(s);
-            if (e != hipSuccess)
-                st = fail(HNV_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
-        }
         if (st != HNV_OK) {
             delete p;
             return st;
@@ -1011,13 +1101,13 @@ extern "C" hnv_status hnv_score_plan_create_device(const int32_t *cand_ptr, cons
     D.splits = reinterpret_cast<const Split *>(base + L.off_splits);
     if (n_cand > 0) {
         const TierArrays T = side_arrays(S, 0);
-        if ((st = tier_scan(cand_ptr, n_cand, L.small_max, kScoreChunk, T, S, S.counts, s)) != HNV_OK ||
+        if ((st = tier_scan(cand_ptr, n_cand, L.small_max, kScoreChunk, nullptr, T, S, S.counts, s)) != HNV_OK ||
+            (st = tier_emit(cand_ptr, n_cand, kScoreChunk, nullptr, 0, nullptr, S.counts, L.n_chunks, T, S, D, s)) !=
+                HNV_OK ||
             (st = read_back(cnt, S.counts, sizeof(cnt), s)) != HNV_OK)
             return st;
         if (cnt[0] > L.n_small || cnt[1] > L.n_chunks || cnt[2] > L.n_splits || cnt[3] > L.n_slots)
             return fail(HNV_EDEVICE, "work lists exceed their bounds");
-        if ((st = tier_emit(cand_ptr, n_cand, kScoreChunk, nullptr, 0, 0, cnt, T, S, D, s)) != HNV_OK)
-            return st;
     }
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess)

@@ -1245,6 +1245,18 @@ __global__ __launch_bounds__(kBlock) void k_recip_nodes(const int32_t *__restric
         r[v] = (s > 0.0) ? (float)(1.0 / s) : 0.0f;
 }
 
+// node v with unit weights: S_v is v's degree (the FP64 sum of that many
+// ones, exactly), so r_v = 1 / degree without reading the hyperedge ids
+__global__ __launch_bounds__(kBlock) void k_recip_nodes_unit(const int32_t *__restrict__ ptr, int64_t n_nodes,
+                                                             float *__restrict__ r)
+{
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n_nodes)
+        return;
+    const int deg = ptr[v + 1] - ptr[v];
+    r[v] = (deg > 0) ? (float)(1.0 / (double)deg) : 0.0f;
+}
+
 // hyperedge e: r_e = 1 / |e| (its weight cancels in its own mean)
 __global__ __launch_bounds__(kBlock) void k_recip_edges(const int32_t *__restrict__ ptr, int64_t n_edges,
                                                         int64_t n_nodes, float *__restrict__ r)
@@ -1337,7 +1349,9 @@ hnv_status dev_recompute_reciprocals(hnv_plan *p, int level, void *stream)
 {
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     LevelPlan &L = p->lv[level];
-    if (L.n_nodes > 0)
+    if (L.n_nodes > 0 && L.unit_w)
+        k_recip_nodes_unit<<<grid1d(L.n_nodes, kBlock), kBlock, 0, s>>>(L.side[1].ptr, L.n_nodes, L.r);
+    else if (L.n_nodes > 0)
         k_recip_nodes<<<fold_grid(blocks_for(L.n_nodes, kBlock / kRecipLanes)), kBlock, 0, s>>>(
             L.side[1].ptr, L.side[1].idx, L.w, L.n_nodes, L.n_nodes, L.r);
     if (L.n_edges > 0)
