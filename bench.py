@@ -898,12 +898,15 @@ def cpu_baseline_leg(hg, cfg, zc, outs, timing=True, errors=True, d=None):
     return out
 
 
-def trace_summary(dirs, title, commands, top=40):
+def trace_summary(dirs, title, commands, top=40, exclude=None):
     """A markdown table of the kernels in rocprofv3 --kernel-trace --stats
     output (the *_kernel_stats.csv files): calls, average and total time,
-    share of the traced kernel time, for the `top` kernels by total time."""
+    share of the traced kernel time, for the `top` kernels by total time.
+    `exclude`: a regular expression; kernels whose names match are left out
+    of the table and of the total it is a share of."""
     import csv
     import glob
+    import re
     rows = []
     for d in dirs:
         for path in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
@@ -911,10 +914,14 @@ def trace_summary(dirs, title, commands, top=40):
                 rows += list(csv.DictReader(f))
     if not rows:
         raise SystemExit("no *_kernel_stats.csv in " + ", ".join(dirs))
+    if exclude:
+        rows = [r for r in rows if not re.search(exclude, r["Name"])]
     total = sum(float(r["TotalDurationNs"]) for r in rows)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     out = [f"# Kernel trace: {title}", "", "Commands:", ""]
     out += [f"    {c}" for c in commands]
+    if exclude:
+        out += ["", f"Kernels whose names match `{exclude}` are left out of the table and of its total."]
     out += ["", "| kernel | calls | avg us | min us | max us | total ms | % of traced kernel time |",
             "|---|---|---|---|---|---|---|"]
     for r in rows[:top]:
@@ -955,12 +962,15 @@ def main():
                     help="format rocprofv3 --kernel-trace --stats output directories as a markdown table, print "
                          "it and exit (no GPU needed)")
     ap.add_argument("--summary-title", default="", help="with --trace-summary: the table's title")
+    ap.add_argument("--trace-exclude", default=None,
+                    help="with --trace-summary: leave out kernels whose names match this regular expression")
     args = ap.parse_args()
     if args.counter_summary:
         print(counter_summary(args.counter_summary, args.config, args.summary_command), end="")
         return
     if args.trace_summary:
-        print(trace_summary(args.trace_summary, args.summary_title or args.config, args.summary_command), end="")
+        print(trace_summary(args.trace_summary, args.summary_title or args.config, args.summary_command,
+                            exclude=args.trace_exclude), end="")
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -83,6 +83,68 @@ __global__ __launch_bounds__(kThreads) void k_best(const int32_t *__restrict__ i
         atomicMin(best + v, r);
 }
 
+// The same minima without global atomics, for large levels: the incidences'
+// (node, rank) pairs are partitioned by the node's high bits (one stable radix
+// pass, node >> shift), then one workgroup per bucket of 2^shift nodes takes
+// the minima in LDS and writes the bucket's best[] once.
+constexpr int kBucketShiftMax = 13;   // 8192 nodes, 32 KB of LDS per bucket
+constexpr int kBucketThreads = 1024;
+
+bool bucketed_best(int64_t n_nodes, int64_t nnz) { return nnz >= (int64_t(1) << 20) && bits_for(n_nodes) > 8; }
+
+int bucket_shift(int64_t n_nodes) { return std::min(bits_for(n_nodes) - 8, kBucketShiftMax); }
+
+int64_t bucket_count(int64_t n_nodes) { return ((n_nodes - 1) >> bucket_shift(n_nodes)) + 1; }
+
+// the hyperedge rank of every incidence
+__global__ __launch_bounds__(kThreads) void k_inc_rank(const int32_t *__restrict__ inc_edge,
+                                                       const int32_t *__restrict__ rank, int64_t nnz,
+                                                       int32_t *__restrict__ out)
+{
+    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (j < nnz)
+        out[j] = rank[inc_edge[j]];
+}
+
+// start[b] = the first position of bucket b in node ids sorted on their bits
+// from `shift` up (b in [0, n_buckets]; start[n_buckets] = n)
+__global__ __launch_bounds__(kThreads) void k_bucket_starts(const uint32_t *__restrict__ keys, int64_t n,
+                                                            int shift, int64_t n_buckets,
+                                                            int64_t *__restrict__ start)
+{
+    const int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (b > n_buckets)
+        return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if ((int64_t)(keys[mid] >> shift) < b)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    start[b] = lo;
+}
+
+__global__ __launch_bounds__(kBucketThreads) void k_bucket_min(const uint32_t *__restrict__ keys,
+                                                               const int32_t *__restrict__ vals,
+                                                               const int64_t *__restrict__ start, int shift,
+                                                               int64_t n_nodes, int32_t *__restrict__ best)
+{
+    __shared__ int32_t m[1 << kBucketShiftMax];
+    const int span = 1 << shift;
+    const int64_t base = (int64_t)blockIdx.x << shift;
+    for (int t = threadIdx.x; t < span; t += kBucketThreads)
+        m[t] = INT_MAX;
+    __syncthreads();
+    const int64_t a = start[blockIdx.x], b = start[blockIdx.x + 1];
+    for (int64_t i = a + threadIdx.x; i < b; i += kBucketThreads)
+        atomicMin(&m[(int64_t)keys[i] - base], vals[i]);
+    __syncthreads();
+    for (int t = threadIdx.x; t < span && base + t < n_nodes; t += kBucketThreads)
+        best[base + t] = m[t];
+}
+
 // choice, then per hyperedge: smallest node that chose it, and how many did
 __global__ __launch_bounds__(kThreads) void k_choice(const int32_t *__restrict__ best,
                                                      const int32_t *__restrict__ order, int64_t n_nodes,
@@ -724,7 +786,7 @@ hnv_status sort_storage(int64_t nE, int64_t nnz, int key_bits, int member_bits, 
 
 struct CoarsenLayout {
     size_t keys_in, keys_out, ids_in, order, rank, best, choice, first, count, gflag, gid, kept, krank, mapped,
-        sorted, inc_edge, dflag, dpos, sizes, flag, big_begin, big_end, sort_counts;
+        sorted, inc_edge, dflag, dpos, sizes, flag, big_begin, big_end, sort_counts, bstart;
     // feature path (k > 0)
     size_t fsum, fsq, q, bestq, gcount, gptr, gcur, gnodes;
     size_t temp, temp_bytes, total;
@@ -762,6 +824,7 @@ hnv_status layout(int64_t nV, int64_t nE, int64_t nnz, int k, CoarsenLayout &L)
     L.big_begin = take(4 * max_big_lists(nnz));
     L.big_end = take(4 * max_big_lists(nnz));
     L.sort_counts = take(8);
+    L.bstart = take(8 * (size_t)(std::max<int64_t>(nV >> kBucketShiftMax, 256) + 2));
     L.fsum = L.fsq = L.q = L.bestq = L.gcount = L.gptr = L.gcur = L.gnodes = 0;
     if (k > 0) {
         L.fsum = take(4 * (size_t)nE * k);
@@ -781,12 +844,13 @@ hnv_status layout(int64_t nV, int64_t nE, int64_t nnz, int k, CoarsenLayout &L)
     if (e == hipSuccess)
         e = prim_exclusive_sum(nullptr, t3, (int32_t *)nullptr, (int32_t *)nullptr,
                                              (int)std::max<int64_t>(std::max(nE, nnz), 1));
-    size_t t5 = 0;
-    if (e == hipSuccess)
-        e = prim_inclusive_max(nullptr, t5, (int32_t *)nullptr, (int32_t *)nullptr, (int)std::max<int64_t>(nnz, 1));
+    size_t t6 = 0;
+    if (e == hipSuccess && bucketed_best(nV, nnz))
+        e = prim_sort_pairs(nullptr, t6, (uint32_t *)nullptr, (uint32_t *)nullptr, (int32_t *)nullptr,
+                            (int32_t *)nullptr, nnz, bucket_shift(nV), bits_for(nV));
     if (e != hipSuccess)
         return fail(HNV_EDEVICE, std::string("scan storage query (needs a visible GPU): ") + hipGetErrorString(e));
-    L.temp_bytes = std::max(std::max(std::max(t1, t2), std::max(t3, t4)), t5);
+    L.temp_bytes = std::max(std::max(std::max(t1, t2), std::max(t3, t4)), t6);
     L.temp = take(L.temp_bytes);
     L.total = (off + 255) & ~size_t(255);
     return HNV_OK;
@@ -849,12 +913,8 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
     if (nE > 0) {
         k_check_edges<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, edge_w, n_edges, nnz, 1, flag);
         if (nz > 0) {
-            k_fill<<<grid_for(nz), kThreads, 0, s>>>(dpos, nnz, 0);
-            k_heads<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, n_edges, nnz, dpos);
-            size_t tbs = L.temp_bytes;
-            if (prim_inclusive_max(base + L.temp, tbs, dpos, inc_edge, nz, s) !=
-                hipSuccess)
-                return fail(HNV_EDEVICE, "scan of hyperedge heads");
+            k_fill<<<grid_for(nz), kThreads, 0, s>>>(inc_edge, nnz, 0);
+            k_inc_edge<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, n_edges, nnz, inc_edge);
             k_check_members<<<grid_for(nz), kThreads, 0, s>>>(edge_ptr, edge_idx, inc_edge, n_nodes, n_edges, nnz, 1,
                                                               flag);
         }
@@ -922,8 +982,26 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
         // 2. choices: the least rank, or (features) the least rank among the
         // hyperedges of best cosine score
         k_fill<<<grid_for(nV), kThreads, 0, s>>>(best, n_nodes, INT_MAX);
-        if (nE > 0 && !feat)
-            k_best<<<grid_for(nz), kThreads, 0, s>>>(edge_idx, inc_edge, rank, nnz, best);
+        if (nE > 0 && !feat) {
+            if (bucketed_best(n_nodes, nnz)) {
+                // (mapped, sorted and dflag are free until step 5)
+                int32_t *pr = mapped, *pr_sorted = dflag;
+                uint32_t *nodes_sorted = reinterpret_cast<uint32_t *>(sorted);
+                const int shift = bucket_shift(n_nodes);
+                const int64_t nb = bucket_count(n_nodes);
+                int64_t *bstart = reinterpret_cast<int64_t *>(base + L.bstart);
+                k_inc_rank<<<grid_for(nz), kThreads, 0, s>>>(inc_edge, rank, nnz, pr);
+                tb = L.temp_bytes;
+                if (prim_sort_pairs(temp, tb, reinterpret_cast<const uint32_t *>(edge_idx), nodes_sorted, pr,
+                                    pr_sorted, nz, shift, bits_for(n_nodes), s) != hipSuccess)
+                    return fail(HNV_EDEVICE, "partition of incidences by node");
+                k_bucket_starts<<<grid_for(nb + 1), kThreads, 0, s>>>(nodes_sorted, nnz, shift, nb, bstart);
+                k_bucket_min<<<(unsigned)nb, kBucketThreads, 0, s>>>(nodes_sorted, pr_sorted, bstart, shift, n_nodes,
+                                                                     best);
+            } else {
+                k_best<<<grid_for(nz), kThreads, 0, s>>>(edge_idx, inc_edge, rank, nnz, best);
+            }
+        }
         if (nE > 0 && feat) {
             int32_t *fsum = at(L.fsum);
             int64_t *fsq = reinterpret_cast<int64_t *>(base + L.fsq);

@@ -442,7 +442,7 @@ struct TierArrays {
 // 0, side 1 from side1_offset(n_edges), so both sides' scans can run before
 // their counts are read.
 struct Scratch {
-    int32_t *inc_edge, *heads, *csc_e, *keys_out, *ids_a, *ids_b, *bin_counts, *bin_offs;
+    int32_t *inc_edge, *csc_e, *keys_out, *ids_a, *ids_b, *bin_counts, *bin_offs;
     uint32_t *ckey_a, *ckey_b;
     TierArrays tier;
     Item *items;
@@ -473,8 +473,6 @@ hnv_status cub_sizes(int64_t nnz, int64_t rows, int64_t n_chunks, int64_t bins, 
     if (e == hipSuccess)
         e = prim_exclusive_sum(nullptr, t[1], (int32_t *)nullptr, (int32_t *)nullptr, n);
     if (e == hipSuccess)
-        e = prim_inclusive_max(nullptr, t[2], (int32_t *)nullptr, (int32_t *)nullptr, (int)std::max<int64_t>(nnz, 1));
-    if (e == hipSuccess)
         e = prim_sort_pairs(nullptr, t[3], (uint32_t *)nullptr, (uint32_t *)nullptr,
                                                (int32_t *)nullptr, (int32_t *)nullptr,
                                                (int)std::max<int64_t>(n_chunks, 1), 0, 32);
@@ -501,7 +499,6 @@ hnv_status scratch_layout(int64_t nnz, int64_t rows, int64_t n_chunks, int n_bin
     };
     const size_t n4 = 4 * (size_t)std::max(nnz, rows + 1);
     S.inc_edge = (int32_t *)take(4 * nnz);
-    S.heads = (int32_t *)take(4 * nnz);
     S.csc_e = (int32_t *)take(n4);
     S.keys_out = (int32_t *)take(n4);
     const size_t t4 = 4 * (size_t)(rows + 2 + kTierAlign);
@@ -610,16 +607,12 @@ hnv_status copy_d2d(void *dst, const void *src, size_t n, hipStream_t s)
     return e == hipSuccess ? HNV_OK : fail(HNV_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
 }
 
-// S.inc_edge[j] = the hyperedge of incidence j (heads over a zero fill, then
-// an inclusive max-scan).
+// S.inc_edge[j] = the hyperedge of incidence j
 hnv_status incidence_edges(const int32_t *ptr, int64_t nE, int64_t nnz, Scratch &S, hipStream_t s)
 {
-    k_fill<<<grid_for(nnz), kThreads, 0, s>>>(S.heads, nnz, 0);
-    k_heads<<<grid_for(nE), kThreads, 0, s>>>(ptr, nE, nnz, S.heads);
-    size_t tb = S.temp_bytes;
-    if (prim_inclusive_max(S.temp, tb, S.heads, S.inc_edge, (int)nnz, s) != hipSuccess)
-        return fail(HNV_EDEVICE, "scan of hyperedge heads");
-    return HNV_OK;
+    k_fill<<<grid_for(nnz), kThreads, 0, s>>>(S.inc_edge, nnz, 0);
+    k_inc_edge<<<grid_for(nE), kThreads, 0, s>>>(ptr, nE, nnz, S.inc_edge);
+    return dev_check("incidence map");
 }
 
 // Checks of level l and (with a coarser level) of map l, launched without

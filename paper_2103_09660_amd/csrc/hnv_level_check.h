@@ -51,19 +51,35 @@ __global__ __launch_bounds__(kThreads) void k_check_edges(const int32_t *__restr
         atomicOr(flag, bad);
 }
 
-// inc_edge[j] = the hyperedge of incidence j: each nonempty hyperedge writes
-// its id at its first incidence (over a zero fill), and an inclusive
-// max-scan spreads it.  Offsets outside [0, nnz) are skipped here and
-// reported by k_check_edges.
-__global__ __launch_bounds__(kThreads) void k_heads(const int32_t *__restrict__ ptr, int64_t n_edges, int64_t nnz,
-                                                    int32_t *__restrict__ inc_edge)
+// inc_edge[j] = the hyperedge of incidence j, written by the hyperedges over
+// a zero fill (the caller's): a hyperedge of at most kIncSmall members by its
+// own thread, longer ones by the whole wavefront in turn, found with a ballot.
+// Offsets are clamped to [0, nnz] (bad ones are reported by k_check_edges), so
+// every write stays in the array and every value is a hyperedge id.
+constexpr int kIncSmall = 32;
+
+__global__ __launch_bounds__(kThreads) void k_inc_edge(const int32_t *__restrict__ ptr, int64_t n_edges,
+                                                       int64_t nnz, int32_t *__restrict__ inc_edge)
 {
     const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (e >= n_edges)
-        return;
-    const int32_t a = ptr[e];
-    if (a >= 0 && a < nnz && ptr[e + 1] > a)
-        inc_edge[a] = (int32_t)e;
+    int32_t a = 0, b = 0;
+    if (e < n_edges) {
+        a = (int32_t)max<int64_t>(ptr[e], 0);
+        b = (int32_t)min<int64_t>(ptr[e + 1], nnz);
+    }
+    const bool big = b - a > kIncSmall;
+    if (!big)
+        for (int32_t j = a; j < b; ++j)
+            inc_edge[j] = (int32_t)e;
+    uint64_t m = __ballot(big);   // every lane reaches this
+    const int lane = threadIdx.x % 64;
+    while (m) {
+        const int l = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const int32_t la = __shfl(a, l, 64), lb = __shfl(b, l, 64), le = __shfl((int32_t)e, l, 64);
+        for (int32_t j = la + lane; j < lb; j += 64)
+            inc_edge[j] = le;
+    }
 }
 
 // Member range per incidence; with `full` also strictly ascending members

@@ -18,13 +18,19 @@
 
 namespace hnv {
 
+// The radix sorts take the one-sweep (digit-at-a-time) path from 2^16 pairs
+// on: for the hundreds of thousands of hyperedges of a coarse level it is
+// fewer launches than the merge path rocPRIM picks by default below 2^20.
+using SortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                              rocprim::default_config, size_t(1) << 16>;
+
 // (key, value) pairs by key bits [begin_bit, end_bit), stable.
 template <typename K, typename V>
 inline hipError_t prim_sort_pairs(void *temp, size_t &bytes, const K *keys_in, K *keys_out, const V *vals_in,
                                   V *vals_out, int64_t n, int begin_bit, int end_bit, hipStream_t s = 0)
 {
-    return rocprim::radix_sort_pairs(temp, bytes, keys_in, keys_out, vals_in, vals_out, (size_t)n,
-                                     (unsigned)begin_bit, (unsigned)end_bit, s);
+    return rocprim::radix_sort_pairs<SortConfig>(temp, bytes, keys_in, keys_out, vals_in, vals_out, (size_t)n,
+                                                 (unsigned)begin_bit, (unsigned)end_bit, s);
 }
 
 // Keys of each segment [begin[i], end[i]) sorted independently, stable.
@@ -44,11 +50,12 @@ inline hipError_t prim_exclusive_sum(void *temp, size_t &bytes, const T *in, T *
     return rocprim::exclusive_scan(temp, bytes, in, out, T(0), (size_t)n, rocprim::plus<T>(), s);
 }
 
-// out[i] = max(in[0], .., in[i]).
-template <typename T>
-inline hipError_t prim_inclusive_max(void *temp, size_t &bytes, const T *in, T *out, int64_t n, hipStream_t s = 0)
+// out[i] = in[0] op .. op in[i-1], out[0] = init, for an associative op.
+template <typename T, typename Op>
+inline hipError_t prim_exclusive_scan(void *temp, size_t &bytes, const T *in, T *out, T init, int64_t n, Op op,
+                                      hipStream_t s = 0)
 {
-    return rocprim::inclusive_scan(temp, bytes, in, out, (size_t)n, rocprim::maximum<T>(), s);
+    return rocprim::exclusive_scan(temp, bytes, in, out, init, (size_t)n, op, s);
 }
 
 }  // namespace hnv

@@ -109,3 +109,6 @@ def test_trace_summary_table(tmp_path):
     assert lines[0].startswith("| `k_big` | 3 | 3.0 |") and lines[0].endswith("| 90.0 |")
     assert lines[1].startswith("| `k_small` | 10 | 0.1 |")
     assert "    cmd" in text and bench.kernel_source_digest() in text
+    ex = bench.trace_summary([str(d)], "t", ["cmd"], exclude="big")
+    rows = [l for l in ex.splitlines() if l.startswith("| `")]
+    assert len(rows) == 1 and rows[0].startswith("| `k_small` | 10 |") and rows[0].endswith("| 100.0 |")

@@ -39,10 +39,13 @@ def _compare(O, H, n_nodes, n_edges, eptr, eidx, w, n_coarsen, what):
 @pytest.mark.parametrize("seed,n_nodes,n_edges,hi,weights", [
     (0, 1, 1, 1, "float"), (1, 10, 4, 3, "int"), (2, 50, 30, 5, "none"), (3, 300, 200, 8, "int"),
     (4, 1000, 700, 12, "float"), (5, 3000, 2500, 4, "int"), (6, 64, 300, 16, "float"), (7, 5000, 200, 60, "none"),
-    (8, 20000, 15000, 30, "int"), (9, 257, 1000, 2, "none")])
+    (8, 20000, 15000, 30, "int"), (9, 257, 1000, 2, "none"),
+    (10, 200000, 150000, 14, "int"), (11, 100000, 150000, 14, "float")])
 def test_random_hypergraphs(oracle_mod, H, seed, n_nodes, n_edges, hi, weights):
     """Isolated nodes, singleton hyperedges, integer weights (many ties in
-    the weight key, so size and id decide) and unit weights."""
+    the weight key, so size and id decide) and unit weights.  The last two
+    have over 2^20 incidences, so the least rank per node is taken by
+    bucketed minima (1024 and 512 nodes per bucket) instead of atomics."""
     hg = random_hypergraph(seed, n_nodes, n_edges, 1, hi, weighted=weights != "none",
                            integer_weights=weights == "int")
     _compare(oracle_mod, H, hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, 3,
