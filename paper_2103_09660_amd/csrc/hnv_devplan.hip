@@ -836,6 +836,9 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
     }
     if ((st = dev_check("weights")) != HNV_OK)
         return st;
+    const int64_t *const n_small[2] = {M->counts, M->counts + 4};
+    if ((st = dev_fill_inline_ids(p, l, n_small, s)) != HNV_OK)
+        return st;
     return dev_recompute_reciprocals(p, l, s);
 }
 

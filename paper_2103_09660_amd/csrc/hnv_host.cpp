@@ -661,6 +661,8 @@ void carve(hnv_plan *p, const std::vector<LevelShape> &shape, char *base)
             S.n_chunks = h.n_chunks[s];
             S.n_splits = h.n_splits[s];
             S.small = c.take<Item>(S.n_small);
+            S.small_ids = c.take<InlineIds>(S.n_small);
+            S.small_cids = h.has_coarse ? c.take<InlineIds>(S.n_small) : nullptr;
             S.chunks = c.take<Item>(S.n_chunks);
             S.splits = c.take<Split>(S.n_splits);
             L.n_small[s] = S.n_small;
@@ -892,6 +894,10 @@ extern "C" hnv_status hnv_plan_create(const hnv_level *levels, const hnv_map *ma
             }
             if (st == HNV_OK)
                 st = dev_recompute_reciprocals(p, l, stream);
+            if (st == HNV_OK) {
+                const int64_t *const known[2] = {nullptr, nullptr};
+                st = dev_fill_inline_ids(p, l, known, s);
+            }
             if (st != HNV_OK) {
                 delete p;
                 return st;

@@ -30,6 +30,13 @@ constexpr int kRowsPerGroup = HNV_ROWS_PER_GROUP;   // lane-group tier rows a gr
 struct alignas(16) Item {
     int32_t row, start, len, aux;
 };
+// The first kInlineIds neighbour ids of a lane-group row (unused entries 0),
+// kept beside its work item so that a row of that many neighbours or fewer
+// needs no load of its own index list.
+constexpr int kInlineIds = 4;
+struct alignas(16) InlineIds {
+    int32_t id[kInlineIds];
+};
 // A row split over n_slots consecutive partial slots starting at first_slot.
 struct alignas(16) Split {
     int32_t row, first_slot, n_slots, deg;
@@ -47,6 +54,8 @@ struct DevSide {
     float *wn = nullptr;             // [nnz] weight of each star edge (side 1 only)
     float *sn = nullptr;             // [nnz] reverse-mode scale: reciprocal of the neighbour's row sum
     const Item *small = nullptr;
+    const InlineIds *small_ids = nullptr;    // [n_small] first ids of each small row, from idx
+    const InlineIds *small_cids = nullptr;   // [n_small] the same from cidx, or null
     int32_t n_small = 0;
     const Item *chunks = nullptr;
     int32_t n_chunks = 0;
@@ -177,6 +186,11 @@ constexpr int kScoreChunk = 512;     // members per wavefront work item of the s
 
 // Device-side pieces implemented in hnv_kernels.hip
 hnv_status dev_recompute_reciprocals(hnv_plan *p, int level, void *stream);
+// Fills both sides' small_ids / small_cids of a level from its work items and
+// neighbour arrays; n_small_dev (per side, may be null) holds the item counts
+// on the device when the host does not know them yet (the side's n_small is
+// then the bound the arrays were carved for).
+hnv_status dev_fill_inline_ids(hnv_plan *p, int level, const int64_t *const n_small_dev[2], hipStream_t s);
 hnv_status dev_check(const char *what);
 hnv_status dev_score(const ScorePlan &sp, const void *z, hnv_dtype dtype, int d, int op, float *out,
                      hipStream_t s);

@@ -230,9 +230,13 @@ HNV_DEV Mats mats_of(const GatherArgs &a)
 template <typename T, int EPL, int G, bool SCALE, bool SCALAR>
 HNV_DEV void gather_group(const int32_t *__restrict__ nb, const float *__restrict__ sc,
                           const float *__restrict__ cvec, int start, int deg, const T *__restrict__ src, int64_t ld,
-                          int col, bool col_ok, int gl, int gbase, float (&acc)[EPL], float &csum)
+                          int col, bool col_ok, int gl, int gbase, int my_id, float (&acc)[EPL], float &csum)
 {
     using S = Slice<T, EPL>;
+    // With at least kInlineIds lanes per group, lane gl < kInlineIds holds
+    // neighbour gl's id from the work item (my_id), so the first neighbours
+    // are gathered without waiting for the index list.
+    constexpr bool kInl = G >= kInlineIds;
     int ix[kIdxRegs];
     float sv[kIdxRegs];
 #pragma unroll
@@ -241,7 +245,7 @@ HNV_DEV void gather_group(const int32_t *__restrict__ nb, const float *__restric
         ix[r] = 0;
         sv[r] = 1.0f;
         if (p < deg) {
-            ix[r] = nb[start + p];
+            ix[r] = (kInl && p < kInlineIds) ? my_id : nb[start + p];
             if (SCALE)
                 sv[r] = sc[start + p];
         }
@@ -252,7 +256,26 @@ HNV_DEV void gather_group(const int32_t *__restrict__ nb, const float *__restric
             if (gl + r * G < deg)
                 csum += cvec[ix[r]];
     }
-    for (int j = 0; j < deg; j += kUnroll) {
+    int j0 = 0;
+    if (kInl) {   // neighbours 0 .. kInlineIds-1 (the first position of lanes 0 .. kInlineIds-1)
+        typename S::Raw raw[kInlineIds];
+        float s[kInlineIds];
+#pragma unroll
+        for (int k = 0; k < kInlineIds; ++k) {
+            const int v = __shfl(my_id, gbase + k, kWave);
+            s[k] = SCALE ? __shfl(sv[0], gbase + k, kWave) : 1.0f;
+            if (k < deg && col_ok)
+                raw[k] = S::load(src + (int64_t)v * ld + col);
+        }
+        if (col_ok) {
+#pragma unroll
+            for (int k = 0; k < kInlineIds; ++k)
+                if (k < deg)
+                    accumulate<SCALE, T, EPL>(acc, s[k], raw[k]);
+        }
+        j0 = kInlineIds;
+    }
+    for (int j = j0; j < deg; j += kUnroll) {
         typename S::Raw raw[kUnroll];
         float s[kUnroll];
         bool ok[kUnroll];
@@ -652,8 +675,12 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
             const int item = (b * kRowsPerGroup + rr) * (kBlock / G) + (int)(threadIdx.x / G);
             const bool valid = item < Sd.n_small;
             Item it{0, 0, 0, 0};
-            if (valid)
+            int my_id = 0;   // lane gl < kInlineIds: the row's neighbour gl, loaded with the item
+            if (valid) {
                 it = Sd.small[item];
+                if (gl < kInlineIds && G >= kInlineIds)
+                    my_id = (FUSED ? Sd.small_cids : Sd.small_ids)[item].id[gl];
+            }
             const int zrow = Sd.row_base + it.row;
             Own<T, EPL> self{};
             if (valid && col_ok) {
@@ -666,10 +693,10 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
             }
             if (use_scale)
                 gather_group<T, EPL, G, true, kScalar>(nb, sc, a.cvec, it.start, it.len, src, a.ld, col, col_ok, gl,
-                                                       g * G, acc, csum);
+                                                       g * G, my_id, acc, csum);
             else
                 gather_group<T, EPL, G, false, kScalar>(nb, sc, a.cvec, it.start, it.len, src, a.ld, col, col_ok, gl,
-                                                        g * G, acc, csum);
+                                                        g * G, my_id, acc, csum);
             if (MODE == kFwd) {
                 if (valid)
                     r2 += epilogue_fwd<T, EPL>(a, mats.dst, zrow, it.len, col, col_ok, acc, self);
@@ -1360,6 +1387,46 @@ hnv_status dev_recompute_reciprocals(hnv_plan *p, int level, void *stream)
         k_fill_weights<<<grid1d(L.nnz, kBlock), kBlock, 0, s>>>(L.side[1].idx, L.w, L.nnz, L.n_nodes, L.side[1].wn);
     L.scales_ready = false;   // the reverse sweep refills them from these reciprocals
     return dev_check("reciprocal kernels");
+}
+
+// small_ids[i] (and small_cids[i]) = the first kInlineIds neighbour ids of
+// lane-group item i from idx (cidx), 0 past the row's degree; n items, or
+// *n_dev of them when given.
+__global__ __launch_bounds__(kBlock) void k_inline_ids(const Item *__restrict__ small, int64_t n,
+                                                       const int64_t *__restrict__ n_dev,
+                                                       const int32_t *__restrict__ idx,
+                                                       const int32_t *__restrict__ cidx,
+                                                       InlineIds *__restrict__ ids, InlineIds *__restrict__ cids)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n || (n_dev && i >= *n_dev))
+        return;
+    const Item it = small[i];
+    InlineIds a{}, c{};
+#pragma unroll
+    for (int k = 0; k < kInlineIds; ++k) {
+        if (k < it.len) {
+            a.id[k] = idx[it.start + k];
+            if (cids)
+                c.id[k] = cidx[it.start + k];
+        }
+    }
+    ids[i] = a;
+    if (cids)
+        cids[i] = c;
+}
+
+hnv_status dev_fill_inline_ids(hnv_plan *p, int level, const int64_t *const n_small_dev[2], hipStream_t s)
+{
+    LevelPlan &L = p->lv[level];
+    for (int sd = 0; sd < 2; ++sd) {
+        const DevSide &D = L.side[sd];
+        if (D.n_small > 0)
+            k_inline_ids<<<grid1d(D.n_small, kBlock), kBlock, 0, s>>>(D.small, D.n_small, n_small_dev[sd], D.idx,
+                                                                    D.cidx, const_cast<InlineIds *>(D.small_ids),
+                                                                    const_cast<InlineIds *>(D.small_cids));
+    }
+    return dev_check("inline neighbour ids");
 }
 
 // The reverse sweep's per-star-edge scales of a level, filled from the

@@ -28,6 +28,10 @@ extern "C" const char *hipGetErrorString(hipError_t) { return "no device (saniti
 hnv_plan::~hnv_plan() {}
 namespace hnv {
 hnv_status dev_recompute_reciprocals(hnv_plan *, int, void *) { return fail(HNV_EDEVICE, "no device"); }
+hnv_status dev_fill_inline_ids(hnv_plan *, int, const int64_t *const[2], hipStream_t)
+{
+    return fail(HNV_EDEVICE, "no device");
+}
 hnv_status dev_score(const ScorePlan &, const void *, hnv_dtype, int, int, float *, hipStream_t)
 {
     return fail(HNV_EDEVICE, "no device");
