@@ -208,13 +208,14 @@ __global__ __launch_bounds__(kThreads) void k_map(const int32_t *__restrict__ id
 // Coarse member lists sorted per hyperedge.  A library segmented sort spends
 // most of its time on per-segment overhead when, as here, most segments hold
 // two to four keys.  So: lists of at most kSortThread members are sorted by
-// one thread in registers; lists of at most kSortWave members by one
-// wavefront (a bitonic network over 64 lanes x up to 16 registers); the few
-// longer ones go to the library's segmented sort.  Each list's result is the
-// same whatever order the lists are taken in.
+// one thread in registers (a network of 8, or of 16 above 8 members); lists
+// of at most kSortWave members by one wavefront (a bitonic network over 64
+// lanes x up to 16 registers); the few longer ones go to the library's
+// segmented sort.  Each list's result is the same whatever order the lists
+// are taken in.
 // ---------------------------------------------------------------------------
 
-constexpr int kSortThread = 8;
+constexpr int kSortThread = 16;
 constexpr int kSortWave = 1024;
 
 // Appends the lanes with `pred` to a list through one atomic per wavefront;
@@ -234,11 +235,35 @@ __device__ __forceinline__ int32_t wave_append(int32_t *counter, bool pred)
     return pred ? base + (int32_t)__popcll(m & ((1ull << lane) - 1ull)) : -1;
 }
 
-// One thread per hyperedge: a list of at most kSortThread members is sorted
-// here (Batcher's odd-even merge network of 19 comparators, INT_MAX
-// padding); one of more than kSortWave members is appended to the library
-// sort's segment list (a few per level, so one atomic per wavefront that
-// has any is cheap).  The lists in between are left to k_sort_wave.
+// Bitonic sorting network over the N registers of one thread (N a power of
+// two; every index is a compile-time constant).
+template <int N>
+__device__ __forceinline__ void thread_bitonic(int32_t (&v)[N])
+{
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const int32_t a = v[i], b = v[l];
+                    const bool up = (i & k) == 0;
+                    v[i] = up ? min(a, b) : max(a, b);
+                    v[l] = up ? max(a, b) : min(a, b);
+                }
+            }
+        }
+    }
+}
+
+// One thread per hyperedge: a list of at most 8 members is sorted here with
+// Batcher's odd-even merge network of 19 comparators, one of 9 to
+// kSortThread members with a bitonic network of 16 (INT_MAX padding); one of
+// more than kSortWave members is appended to the library sort's segment
+// list (a few per level, so one atomic per wavefront that has any is
+// cheap).  The lists in between are left to k_sort_wave.
 __global__ __launch_bounds__(kThreads) void k_sort_short(const int32_t *__restrict__ ptr,
                                                          const int32_t *__restrict__ mapped, int64_t n_edges,
                                                          int32_t *__restrict__ sorted, int32_t *__restrict__ big_begin,
@@ -250,10 +275,21 @@ __global__ __launch_bounds__(kThreads) void k_sort_short(const int32_t *__restri
         s = ptr[e];
         n = ptr[e + 1] - s;
     }
-    if (e < n_edges && n <= kSortThread) {
-        int32_t v[kSortThread];
+    if (e < n_edges && n > 8 && n <= kSortThread) {
+        int32_t v[16];
 #pragma unroll
-        for (int i = 0; i < kSortThread; ++i)
+        for (int i = 0; i < 16; ++i)
+            v[i] = (i < n) ? mapped[s + i] : INT_MAX;
+        thread_bitonic<16>(v);
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i < n)
+                sorted[s + i] = v[i];
+    }
+    if (e < n_edges && n <= 8) {
+        int32_t v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
             v[i] = (i < n) ? mapped[s + i] : INT_MAX;
         constexpr int net[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {1, 2}, {5, 6},
                                     {0, 4}, {3, 7}, {1, 5}, {2, 6}, {1, 4}, {3, 6}, {2, 4}, {3, 5}, {3, 4}};
@@ -264,7 +300,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_short(const int32_t *__restri
             v[net[c][1]] = max(a, b);
         }
 #pragma unroll
-        for (int i = 0; i < kSortThread; ++i)
+        for (int i = 0; i < 8; ++i)
             if (i < n)
                 sorted[s + i] = v[i];
     }

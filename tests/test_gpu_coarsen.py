@@ -179,13 +179,15 @@ def test_depth_rule_matches_host(H):
 
 
 def test_member_sort_boundaries(oracle_mod, H):
-    """Coarse member lists sorted by a thread (up to 8 members), a wavefront
-    (up to 1,024, in 64-lane registers x 1..16) or the library's segmented
-    sort (longer): hyperedges at every boundary, with members whose coarse
-    ids come out in every order, against the oracle bit for bit."""
+    """Coarse member lists sorted by a thread (up to 8 members by one network,
+    up to 16 by another), a wavefront (up to 1,024, in 64-lane registers x
+    1..16) or the library's segmented sort (longer): hyperedges at every
+    boundary, with members whose coarse ids come out in every order, against
+    the oracle bit for bit."""
     rng = np.random.default_rng(77)
     n_nodes = 6000
-    sizes = [1, 2, 7, 8, 9, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 3000]
+    sizes = [1, 2, 7, 8, 9, 12, 15, 16, 17, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024,
+             1025, 3000]
     sizes += list(rng.integers(2, 12, size=3000))      # small hyperedges that merge nodes into groups
     edges = [sorted(rng.choice(n_nodes, size=k, replace=False).tolist()) for k in sizes]
     ptr = np.concatenate([[0], np.cumsum([len(e) for e in edges])]).astype(np.int64)
