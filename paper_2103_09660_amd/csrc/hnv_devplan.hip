@@ -336,18 +336,42 @@ __global__ void k_tier_counts(const uint32_t *__restrict__ sorted_key, const Tie
 }
 
 // lane-group tier items in sorted order; aux = the coarse row the row's own
-// value is projected from (0 at the coarsest level)
+// value is projected from (0 at the coarsest level).  With `ids`, also each
+// item's first kInlineIds neighbour ids from idx (and from cidx into
+// `cids`), 0 past the row's degree, and all 0 when the level failed its
+// checks (its offsets may then point anywhere).
 __global__ __launch_bounds__(kThreads) void k_small_items(const int32_t *__restrict__ sorted_row,
                                                           const int32_t *__restrict__ ptr,
                                                           const int64_t *__restrict__ n_small,
                                                           const int32_t *__restrict__ rowmap, int32_t row_base,
-                                                          Item *__restrict__ items)
+                                                          const int *__restrict__ bad,
+                                                          const int32_t *__restrict__ idx,
+                                                          const int32_t *__restrict__ cidx,
+                                                          Item *__restrict__ items, InlineIds *__restrict__ ids,
+                                                          InlineIds *__restrict__ cids)
 {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= *n_small)
         return;
     const int32_t r = sorted_row[i];
-    items[i] = Item{r, ptr[r], ptr[r + 1] - ptr[r], rowmap ? rowmap[row_base + r] : 0};
+    const int32_t a = ptr[r], len = ptr[r + 1] - a;
+    items[i] = Item{r, a, len, rowmap ? rowmap[row_base + r] : 0};
+    if (!ids)
+        return;
+    InlineIds x{}, c{};
+    if (!level_failed(bad)) {
+#pragma unroll
+        for (int k = 0; k < kInlineIds; ++k) {
+            if (k < len) {
+                x.id[k] = idx[a + k];
+                if (cids)
+                    c.id[k] = cidx[a + k];
+            }
+        }
+    }
+    ids[i] = x;
+    if (cids)
+        cids[i] = c;
 }
 
 // wavefront tier items in row order (pieces of a row in order), with the
@@ -734,13 +758,15 @@ hnv_status tier_scan(const int32_t *ptr, int64_t n_rows, int small_max, int chun
 // wavefront-tier items) and the kernels stop at the counts.  slot_base (on
 // the device, or null for none) holds the partial slots of the side before.
 hnv_status tier_emit(const int32_t *ptr, int64_t n_rows, int chunk, const int32_t *rowmap, int32_t row_base,
-                     const int64_t *slot_base, const int64_t *cnt, int64_t max_chunks, const TierArrays &T,
-                     Scratch &S, DevSide &D, hipStream_t s)
+                     const int64_t *slot_base, const int64_t *cnt, int64_t max_chunks, const int *bad,
+                     const TierArrays &T, Scratch &S, DevSide &D, hipStream_t s)
 {
     if (n_rows == 0)
         return HNV_OK;
-    k_small_items<<<grid_for(n_rows), kThreads, 0, s>>>(T.rows_b, ptr, cnt, rowmap, row_base,
-                                                        const_cast<Item *>(D.small));
+    k_small_items<<<grid_for(n_rows), kThreads, 0, s>>>(T.rows_b, ptr, cnt, rowmap, row_base, bad, D.idx, D.cidx,
+                                                        const_cast<Item *>(D.small),
+                                                        const_cast<InlineIds *>(D.small_ids),
+                                                        const_cast<InlineIds *>(D.small_cids));
     if (max_chunks > 0) {
         k_chunk_items<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, chunk, T.tc, T.tpos, slot_base, S.items,
                                                             S.ckey_a, S.ids_a);
@@ -824,7 +850,7 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
         int64_t *cnt = M->counts + 4 * sd;
         if ((st = tier_scan(D.ptr, n_rows, sm, chunk, bad, T[sd], S, cnt, s)) != HNV_OK ||
             (st = tier_emit(D.ptr, n_rows, chunk, C ? L.rowmap : nullptr, D.row_base,
-                            sd == 0 ? nullptr : M->counts + 3, cnt, D.n_chunks, T[sd], S, D, s)) != HNV_OK)
+                            sd == 0 ? nullptr : M->counts + 3, cnt, D.n_chunks, bad, T[sd], S, D, s)) != HNV_OK)
             return st;
     }
     // weights and reciprocals
@@ -835,9 +861,6 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
         k_fill_f32<<<grid_for(nE), kThreads, 0, s>>>(L.w, nE, 1.0f);
     }
     if ((st = dev_check("weights")) != HNV_OK)
-        return st;
-    const int64_t *const n_small[2] = {M->counts, M->counts + 4};
-    if ((st = dev_fill_inline_ids(p, l, n_small, s)) != HNV_OK)
         return st;
     return dev_recompute_reciprocals(p, l, s);
 }
@@ -1098,7 +1121,8 @@ extern "C" hnv_status hnv_score_plan_create_device(const int32_t *cand_ptr, cons
     if (n_cand > 0) {
         const TierArrays T = side_arrays(S, 0);
         if ((st = tier_scan(cand_ptr, n_cand, L.small_max, kScoreChunk, nullptr, T, S, S.counts, s)) != HNV_OK ||
-            (st = tier_emit(cand_ptr, n_cand, kScoreChunk, nullptr, 0, nullptr, S.counts, L.n_chunks, T, S, D, s)) !=
+            (st = tier_emit(cand_ptr, n_cand, kScoreChunk, nullptr, 0, nullptr, S.counts, L.n_chunks, nullptr, T, S, D,
+                            s)) !=
                 HNV_OK ||
             (st = read_back(cnt, S.counts, sizeof(cnt), s)) != HNV_OK)
             return st;

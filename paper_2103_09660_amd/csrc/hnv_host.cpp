@@ -894,10 +894,8 @@ extern "C" hnv_status hnv_plan_create(const hnv_level *levels, const hnv_map *ma
             }
             if (st == HNV_OK)
                 st = dev_recompute_reciprocals(p, l, stream);
-            if (st == HNV_OK) {
-                const int64_t *const known[2] = {nullptr, nullptr};
-                st = dev_fill_inline_ids(p, l, known, s);
-            }
+            if (st == HNV_OK)
+                st = dev_fill_inline_ids(p, l, s);
             if (st != HNV_OK) {
                 delete p;
                 return st;

@@ -186,11 +186,10 @@ constexpr int kScoreChunk = 512;     // members per wavefront work item of the s
 
 // Device-side pieces implemented in hnv_kernels.hip
 hnv_status dev_recompute_reciprocals(hnv_plan *p, int level, void *stream);
-// Fills both sides' small_ids / small_cids of a level from its work items and
-// neighbour arrays; n_small_dev (per side, may be null) holds the item counts
-// on the device when the host does not know them yet (the side's n_small is
-// then the bound the arrays were carved for).
-hnv_status dev_fill_inline_ids(hnv_plan *p, int level, const int64_t *const n_small_dev[2], hipStream_t s);
+// Fills both sides' small_ids / small_cids of a level of a host-built plan
+// from its work items and neighbour arrays (the device-built plan fills them
+// as it writes its work items).
+hnv_status dev_fill_inline_ids(hnv_plan *p, int level, hipStream_t s);
 hnv_status dev_check(const char *what);
 hnv_status dev_score(const ScorePlan &sp, const void *z, hnv_dtype dtype, int d, int op, float *out,
                      hipStream_t s);

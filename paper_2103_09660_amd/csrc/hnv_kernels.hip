@@ -1390,16 +1390,14 @@ hnv_status dev_recompute_reciprocals(hnv_plan *p, int level, void *stream)
 }
 
 // small_ids[i] (and small_cids[i]) = the first kInlineIds neighbour ids of
-// lane-group item i from idx (cidx), 0 past the row's degree; n items, or
-// *n_dev of them when given.
+// lane-group item i from idx (cidx), 0 past the row's degree.
 __global__ __launch_bounds__(kBlock) void k_inline_ids(const Item *__restrict__ small, int64_t n,
-                                                       const int64_t *__restrict__ n_dev,
                                                        const int32_t *__restrict__ idx,
                                                        const int32_t *__restrict__ cidx,
                                                        InlineIds *__restrict__ ids, InlineIds *__restrict__ cids)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n || (n_dev && i >= *n_dev))
+    if (i >= n)
         return;
     const Item it = small[i];
     InlineIds a{}, c{};
@@ -1416,14 +1414,14 @@ __global__ __launch_bounds__(kBlock) void k_inline_ids(const Item *__restrict__ 
         cids[i] = c;
 }
 
-hnv_status dev_fill_inline_ids(hnv_plan *p, int level, const int64_t *const n_small_dev[2], hipStream_t s)
+hnv_status dev_fill_inline_ids(hnv_plan *p, int level, hipStream_t s)
 {
     LevelPlan &L = p->lv[level];
     for (int sd = 0; sd < 2; ++sd) {
         const DevSide &D = L.side[sd];
         if (D.n_small > 0)
-            k_inline_ids<<<grid1d(D.n_small, kBlock), kBlock, 0, s>>>(D.small, D.n_small, n_small_dev[sd], D.idx,
-                                                                    D.cidx, const_cast<InlineIds *>(D.small_ids),
+            k_inline_ids<<<grid1d(D.n_small, kBlock), kBlock, 0, s>>>(D.small, D.n_small, D.idx, D.cidx,
+                                                                    const_cast<InlineIds *>(D.small_ids),
                                                                     const_cast<InlineIds *>(D.small_cids));
     }
     return dev_check("inline neighbour ids");

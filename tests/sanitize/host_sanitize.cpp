@@ -28,7 +28,7 @@ extern "C" const char *hipGetErrorString(hipError_t) { return "no device (saniti
 hnv_plan::~hnv_plan() {}
 namespace hnv {
 hnv_status dev_recompute_reciprocals(hnv_plan *, int, void *) { return fail(HNV_EDEVICE, "no device"); }
-hnv_status dev_fill_inline_ids(hnv_plan *, int, const int64_t *const[2], hipStream_t)
+hnv_status dev_fill_inline_ids(hnv_plan *, int, hipStream_t)
 {
     return fail(HNV_EDEVICE, "no device");
 }

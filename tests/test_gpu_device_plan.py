@@ -163,6 +163,18 @@ def test_device_plan_checks(H):
     with pytest.raises(H.HnvError) as ei:
         H.Plan.from_device([lv], [], 16, "f32", validate=False)
     assert ei.value.status == L.HNV_ERANGE
+    # offsets out of range and decreasing: rejected with or without
+    # validation; the build, which runs before the plan's single read-back,
+    # writes placeholder arrays for such a level instead of following them
+    for vflag in (True, False):
+        ptr = levels[0].edge_ptr.clone()
+        ptr[2] = levels[0].nnz + 7
+        lv = H.DeviceLevel(levels[0].n_nodes, levels[0].n_edges, levels[0].nnz, ptr, levels[0].edge_idx,
+                           levels[0].edge_w)
+        with pytest.raises(H.HnvError) as ei:
+            H.Plan.from_device([lv, levels[1]], [maps[0]], 16, "f32", validate=vflag)
+        assert ei.value.status == L.HNV_EINVAL
+    torch.cuda.synchronize()
     # non-positive weight: rejected with validation
     w = levels[0].edge_w.clone()
     w[2] = 0.0
