@@ -228,14 +228,6 @@ __global__ __launch_bounds__(kThreads) void k_iota(int64_t n, int32_t *__restric
         out[i] = (int32_t)i;
 }
 
-__global__ __launch_bounds__(kThreads) void k_add_const(const int32_t *__restrict__ in, int64_t n, int32_t c,
-                                                        int32_t *__restrict__ out)
-{
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i < n)
-        out[i] = in[i] + c;
-}
-
 __global__ __launch_bounds__(kThreads) void k_fill_f32(float *__restrict__ p, int64_t n, float v)
 {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -267,13 +259,38 @@ __global__ __launch_bounds__(kThreads) void k_rowmap(const int32_t *__restrict__
     rowmap[u] = (r >= 0) ? (int32_t)(n_nodes_c + r) : node_rep[idx[ptr[e]]];
 }
 
-__global__ __launch_bounds__(kThreads) void k_compose(const int32_t *__restrict__ idx,
-                                                      const int32_t *__restrict__ map, int64_t n,
-                                                      const int *__restrict__ bad, int32_t *__restrict__ out)
+// Side 0's neighbour arrays: the member lists as given, and with a coarser
+// level each member's coarse row (a node's row maps to rep(v), so
+// cidx = node_rep[idx]; 0 when the level failed its checks).
+__global__ __launch_bounds__(kThreads) void k_side0_idx(const int32_t *__restrict__ edge_idx,
+                                                        const int32_t *__restrict__ node_rep, int64_t nnz,
+                                                        const int *__restrict__ bad, int32_t *__restrict__ idx,
+                                                        int32_t *__restrict__ cidx)
 {
     const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (j < n)
-        out[j] = level_failed(bad) ? 0 : map[idx[j]];
+    if (j >= nnz)
+        return;
+    const int32_t v = edge_idx[j];
+    idx[j] = v;
+    if (cidx)
+        cidx[j] = level_failed(bad) ? 0 : node_rep[v];
+}
+
+// Side 1's neighbour arrays from the hyperedge of each incidence in node
+// order: the hyperedge's Z row n_nodes + e, and with a coarser level its
+// coarse row rowmap[n_nodes + e] (0 when the level failed its checks).
+__global__ __launch_bounds__(kThreads) void k_side1_idx(const int32_t *__restrict__ csc_e, int64_t nnz,
+                                                        int32_t n_nodes, const int32_t *__restrict__ rowmap,
+                                                        const int *__restrict__ bad, int32_t *__restrict__ idx,
+                                                        int32_t *__restrict__ cidx)
+{
+    const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (j >= nnz)
+        return;
+    const int32_t u = csc_e[j] + n_nodes;
+    idx[j] = u;
+    if (cidx)
+        cidx[j] = level_failed(bad) ? 0 : rowmap[u];
 }
 
 // A row's wavefront-tier counts: its chunks, whether it is split, its
@@ -799,10 +816,17 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
     const int sm = p->small_max, chunk = p->opts.chunk;
     DevSide &S0 = L.side[0], &S1 = L.side[1];
     hnv_status st;
-    // side 0: the member lists as given
-    if ((st = copy_d2d((void *)S0.ptr, lv.edge_ptr, 4 * (nE + 1), s)) != HNV_OK ||
-        (st = copy_d2d((void *)S0.idx, lv.edge_idx, 4 * nnz, s)) != HNV_OK)
+    // projection row map (first: the composed indices below read it)
+    if (C)
+        k_rowmap<<<grid_for(nV + nE), kThreads, 0, s>>>(lv.edge_ptr, lv.edge_idx, m->node_rep, m->edge_rep, nV, nE,
+                                                        C->n_nodes, bad, L.rowmap);
+    // side 0: the member lists as given, and their coarse rows
+    if ((st = copy_d2d((void *)S0.ptr, lv.edge_ptr, 4 * (nE + 1), s)) != HNV_OK)
         return st;
+    if (nnz > 0)
+        k_side0_idx<<<grid_for(nnz), kThreads, 0, s>>>(lv.edge_idx, C ? m->node_rep : nullptr, nnz, bad,
+                                                       const_cast<int32_t *>(S0.idx),
+                                                       C ? const_cast<int32_t *>(S0.cidx) : nullptr);
     // side 1: node -> hyperedges in ascending id (stable sort of incidences
     // by node; the offsets come from the sorted node ids)
     size_t tb = S.temp_bytes;
@@ -813,18 +837,14 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
                                                reinterpret_cast<uint32_t *>(S.keys_out), S.inc_edge, S.csc_e,
                                                (int)nnz, 0, bits_for(nV), s) != hipSuccess)
             return fail(HNV_EDEVICE, "sort of incidences by node");
-        k_add_const<<<grid_for(nnz), kThreads, 0, s>>>(S.csc_e, nnz, (int32_t)nV, const_cast<int32_t *>(S1.idx));
+        k_side1_idx<<<grid_for(nnz), kThreads, 0, s>>>(S.csc_e, nnz, (int32_t)nV, C ? L.rowmap : nullptr, bad,
+                                                       const_cast<int32_t *>(S1.idx),
+                                                       C ? const_cast<int32_t *>(S1.cidx) : nullptr);
     }
     k_offsets_sorted<<<grid_for(nnz + 1), kThreads, 0, s>>>(reinterpret_cast<const uint32_t *>(S.keys_out), nnz, nV,
                                                             bad, const_cast<int32_t *>(S1.ptr));
-    // projection row map, composed indices, inverse map
+    // inverse map
     if (C) {
-        k_rowmap<<<grid_for(nV + nE), kThreads, 0, s>>>(lv.edge_ptr, lv.edge_idx, m->node_rep, m->edge_rep, nV, nE,
-                                                        C->n_nodes, bad, L.rowmap);
-        if (nnz > 0) {
-            k_compose<<<grid_for(nnz), kThreads, 0, s>>>(S0.idx, L.rowmap, nnz, bad, const_cast<int32_t *>(S0.cidx));
-            k_compose<<<grid_for(nnz), kThreads, 0, s>>>(S1.idx, L.rowmap, nnz, bad, const_cast<int32_t *>(S1.cidx));
-        }
         const int64_t rows = nV + nE, rows_c = L.rows_coarse;
         if (rows > 0) {
             k_iota<<<grid_for(rows), kThreads, 0, s>>>(rows, S.tier.rows_a);

@@ -21,8 +21,16 @@ namespace hnv {
 // The radix sorts take the one-sweep (digit-at-a-time) path from 2^16 pairs
 // on: for the hundreds of thousands of hyperedges of a coarse level it is
 // fewer launches than the merge path rocPRIM picks by default below 2^20.
-using SortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
-                                              rocprim::default_config, size_t(1) << 16>;
+// The one-sweep passes take 9-bit digits over workgroups of 1024 threads x 8
+// pairs: measured on MI355X against rocPRIM's default for this target (8-bit
+// digits, 1024 x 16), 22% faster on 13.1M pairs with 21-bit keys, 7% on 3.5M
+// with 22-bit keys, 21-31% on 0.4M-1.5M; the result does not depend on the
+// configuration (a stable sort).
+using SortConfig = rocprim::radix_sort_config<
+    rocprim::default_config, rocprim::default_config,
+    rocprim::radix_sort_onesweep_config<rocprim::kernel_config<1024, 16>, rocprim::kernel_config<1024, 8>, 9,
+                                        rocprim::block_radix_rank_algorithm::match>,
+    size_t(1) << 16>;
 
 // (key, value) pairs by key bits [begin_bit, end_bit), stable.
 template <typename K, typename V>
