@@ -89,12 +89,13 @@ __global__ void k_check_no_edges(const int32_t *__restrict__ ptr, int64_t nnz, i
 // (key >> shift) & mask, which is below n_bins <= kBinsMax: per-tile counts
 // of every digit, an exclusive scan of the counts laid out digit-major
 // (digit b of tile t at b * n_tiles + t), and a scatter in which each tile
-// places its elements in input order.  The degree tiers need one pass (at
-// most small_max + 2 <= 258 keys), the wavefront tier's chunk keys one pass
-// per 9 bits; the result equals a stable radix sort's.  The number of pairs
-// is n_max, or *n_dev when that is given (the grid is sized for n_max).
-constexpr int kBinsMax = 512;
-constexpr int kBinBits = 9;   // digit width of the multi-pass form
+// places its elements in input order.  The degree tiers of both sides need
+// one pass (2 (small_max + 3) keys), the wavefront tier's chunk keys one pass
+// while both sides' keys (2 chunk) fit in kBinsMax, else one per 10 bits;
+// the result equals a stable radix sort's.  The number of pairs is n_max, or
+// *n_dev when that is given (the grid is sized for n_max).
+constexpr int kBinsMax = 1024;
+constexpr int kBinBits = 10;   // digit width of the multi-pass form
 constexpr int kBinRounds = 16;
 constexpr int kBinTile = kThreads * kBinRounds;
 constexpr int kBinWaves = kThreads / kWave;
@@ -306,50 +307,113 @@ struct TierCountPlus {
     }
 };
 
-// per row of one side: the small-tier sort key (small_max - degree, or
-// small_max + 1 for longer rows), the row id and its tier counts
-__global__ __launch_bounds__(kThreads) void k_tier_keys(const int32_t *__restrict__ ptr, int64_t n_rows,
-                                                        int small_max, int chunk, const int *__restrict__ bad,
-                                                        uint32_t *__restrict__ key, int32_t *__restrict__ row,
-                                                        TierCount *__restrict__ tc)
+// The degree tiers of up to two sides are built together, over one array of
+// entries: side k's rows take entries [off, off + n_rows), side 1 starting
+// past side 0 on a 256-byte boundary, and the entries in between are
+// padding.  Each kernel below handles every entry of both sides in one
+// launch.  A stable sort of the entries on a key that puts side 0's keys
+// below side 1's leaves each side's rows in its own entries, so one counting
+// pass and one scan serve both sides; partial slots run on from side 0 into
+// side 1, chunk items and split rows restart per side.
+struct TierSide {
+    const int32_t *ptr;      // [n_rows + 1] the side's offsets
+    int32_t n_rows;
+    int32_t off;             // first entry of the side's rows
+    const int32_t *rowmap;   // projection row map (Z row row_base + r), or null
+    int32_t row_base;
+    const int32_t *idx, *cidx;   // the side's neighbour arrays (cidx may be null)
+    Item *small;
+    InlineIds *ids, *cids;   // may be null
+    Item *chunks;
+    Split *splits;
+};
+struct TierSides {
+    TierSide s[2];
+    int32_t n;       // sides (1 or 2)
+    int64_t total;   // entries: s[n - 1].off + s[n - 1].n_rows
+};
+
+// The side of entry p (its row there is p - off; a row >= n_rows is
+// padding), for p = blockIdx.x * kThreads + threadIdx.x.  Side 1 starts on a
+// multiple of kTierAlign = 64 entries and a wavefront covers 64 consecutive
+// entries from a multiple of 64, so every wavefront lies in one side: the
+// side is taken wave-uniform, and the side's pointers then come from scalar
+// loads.
+__device__ inline int side_of(const TierSides &T, int64_t p)
 {
-    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (r >= n_rows)
-        return;
-    const int32_t deg = level_failed(bad) ? 0 : ptr[r + 1] - ptr[r];
-    const bool small = deg <= small_max;
-    const int32_t pc = small ? 0 : (deg + chunk - 1) / chunk;
-    key[r] = small ? (uint32_t)(small_max - deg) : (uint32_t)(small_max + 1);
-    row[r] = (int32_t)r;
-    tc[r] = TierCount{pc, pc > 1 ? 1 : 0, pc > 1 ? pc : 0};
+    const int64_t p0 = p & ~(int64_t)(kWave - 1);
+    return __builtin_amdgcn_readfirstlane((T.n == 2 && p0 >= T.s[1].off) ? 1 : 0);
 }
 
-// counts[0..3] of one side: small rows, chunks, split rows, partial slots
-// (the exclusive scan plus its last term; the small rows from the sorted keys)
-__global__ void k_tier_counts(const uint32_t *__restrict__ sorted_key, const TierCount *__restrict__ tc,
-                              const TierCount *__restrict__ tpos, int64_t n_rows, int small_max,
-                              int64_t *__restrict__ counts)
+// Tier sort key of a side's row: small_max - degree for the lane-group tier,
+// small_max + 1 for longer rows, small_max + 2 for padding, plus the side
+// times small_max + 3.
+__device__ inline uint32_t tier_key_base(int sd, int small_max) { return (uint32_t)sd * (uint32_t)(small_max + 3); }
+
+__global__ __launch_bounds__(kThreads) void k_tier_keys(TierSides T, int small_max, int chunk,
+                                                        const int *__restrict__ bad, uint32_t *__restrict__ key,
+                                                        int32_t *__restrict__ row, TierCount *__restrict__ tc)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0)
+    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= T.total)
         return;
-    if (n_rows == 0) {
-        counts[0] = counts[1] = counts[2] = counts[3] = 0;
+    const int sd = side_of(T, p);
+    const TierSide &S = T.s[sd];
+    const int64_t r = p - S.off;
+    const uint32_t kb = tier_key_base(sd, small_max);
+    if (r >= S.n_rows) {
+        key[p] = kb + (uint32_t)(small_max + 2);
+        row[p] = -1;
+        tc[p] = TierCount{0, 0, 0};
         return;
     }
-    // sorted ascending: small rows first; binary search for the first long row
-    int64_t lo = 0, hi = n_rows;
+    const int32_t deg = level_failed(bad) ? 0 : S.ptr[r + 1] - S.ptr[r];
+    const bool small = deg <= small_max;
+    const int32_t pc = small ? 0 : (deg + chunk - 1) / chunk;
+    key[p] = kb + (small ? (uint32_t)(small_max - deg) : (uint32_t)(small_max + 1));
+    row[p] = (int32_t)r;
+    tc[p] = TierCount{pc, pc > 1 ? 1 : 0, pc > 1 ? pc : 0};
+}
+
+// the sums of the tier counts over entries [0, p) from the exclusive scan
+__device__ inline TierCount counts_before(const TierCount *tc, const TierCount *tpos, int64_t p)
+{
+    if (p == 0)
+        return TierCount{0, 0, 0};
+    const TierCount a = tpos[p - 1], b = tc[p - 1];
+    return TierCount{a.pieces + b.pieces, a.split + b.split, a.slots + b.slots};
+}
+
+// counts[4 * side + 0..3]: small rows, chunks, split rows, partial slots of
+// the side (small rows from the sorted keys, the rest from the scan); and
+// n_chunks: both sides' chunks.  Thread k handles side k.
+__global__ void k_tier_counts(const uint32_t *__restrict__ sorted_key, const TierCount *__restrict__ tc,
+                              const TierCount *__restrict__ tpos, TierSides T, int small_max,
+                              int64_t *__restrict__ counts, int64_t *__restrict__ n_chunks)
+{
+    const int sd = threadIdx.x;
+    if (blockIdx.x != 0 || sd >= T.n)
+        return;
+    const TierSide &S = T.s[sd];
+    // sorted ascending: the side's small rows first; binary search for its
+    // first longer row
+    const uint32_t last_small = tier_key_base(sd, small_max) + (uint32_t)small_max;
+    int64_t lo = S.off, hi = (int64_t)S.off + S.n_rows;
     while (lo < hi) {
         const int64_t mid = (lo + hi) / 2;
-        if (sorted_key[mid] <= (uint32_t)small_max)
+        if (sorted_key[mid] <= last_small)
             lo = mid + 1;
         else
             hi = mid;
     }
-    counts[0] = lo;
-    const TierCount c = tc[n_rows - 1], p = tpos[n_rows - 1];
-    counts[1] = (int64_t)p.pieces + c.pieces;
-    counts[2] = (int64_t)p.split + c.split;
-    counts[3] = (int64_t)p.slots + c.slots;
+    const TierCount a = counts_before(tc, tpos, S.off), b = counts_before(tc, tpos, (int64_t)S.off + S.n_rows);
+    int64_t *c = counts + 4 * sd;
+    c[0] = lo - S.off;
+    c[1] = (int64_t)b.pieces - a.pieces;
+    c[2] = (int64_t)b.split - a.split;
+    c[3] = (int64_t)b.slots - a.slots;
+    if (sd == T.n - 1)
+        *n_chunks = b.pieces;
 }
 
 // lane-group tier items in sorted order; aux = the coarse row the row's own
@@ -357,88 +421,96 @@ __global__ void k_tier_counts(const uint32_t *__restrict__ sorted_key, const Tie
 // item's first kInlineIds neighbour ids from idx (and from cidx into
 // `cids`), 0 past the row's degree, and all 0 when the level failed its
 // checks (its offsets may then point anywhere).
-__global__ __launch_bounds__(kThreads) void k_small_items(const int32_t *__restrict__ sorted_row,
-                                                          const int32_t *__restrict__ ptr,
-                                                          const int64_t *__restrict__ n_small,
-                                                          const int32_t *__restrict__ rowmap, int32_t row_base,
-                                                          const int *__restrict__ bad,
-                                                          const int32_t *__restrict__ idx,
-                                                          const int32_t *__restrict__ cidx,
-                                                          Item *__restrict__ items, InlineIds *__restrict__ ids,
-                                                          InlineIds *__restrict__ cids)
+__global__ __launch_bounds__(kThreads) void k_small_items(TierSides T, const int32_t *__restrict__ sorted_row,
+                                                          const int64_t *__restrict__ counts,
+                                                          const int *__restrict__ bad)
 {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= *n_small)
+    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= T.total)
         return;
-    const int32_t r = sorted_row[i];
-    const int32_t a = ptr[r], len = ptr[r + 1] - a;
-    items[i] = Item{r, a, len, rowmap ? rowmap[row_base + r] : 0};
-    if (!ids)
+    const int sd = side_of(T, p);
+    const TierSide &S = T.s[sd];
+    const int64_t i = p - S.off;
+    if (i >= counts[4 * sd])
+        return;
+    const int32_t r = sorted_row[p];
+    const int32_t a = S.ptr[r], len = S.ptr[r + 1] - a;
+    S.small[i] = Item{r, a, len, S.rowmap ? S.rowmap[S.row_base + r] : 0};
+    if (!S.ids)
         return;
     InlineIds x{}, c{};
     if (!level_failed(bad)) {
 #pragma unroll
         for (int k = 0; k < kInlineIds; ++k) {
             if (k < len) {
-                x.id[k] = idx[a + k];
-                if (cids)
-                    c.id[k] = cidx[a + k];
+                x.id[k] = S.idx[a + k];
+                if (S.cids)
+                    c.id[k] = S.cidx[a + k];
             }
         }
     }
-    ids[i] = x;
-    if (cids)
-        cids[i] = c;
+    S.ids[i] = x;
+    if (S.cids)
+        S.cids[i] = c;
 }
 
-// wavefront tier items in row order (pieces of a row in order), with the
-// sort key chunk - len (a stable ascending sort puts the longest first)
-__global__ __launch_bounds__(kThreads) void k_chunk_items(const int32_t *__restrict__ ptr, int64_t n_rows, int chunk,
-                                                          const TierCount *__restrict__ tc,
+// wavefront tier items of both sides in entry order (pieces of a row in
+// order), with the sort key side * chunk + chunk - len (a stable ascending
+// sort keeps the sides apart and puts each side's longest first)
+__global__ __launch_bounds__(kThreads) void k_chunk_items(TierSides T, int chunk, const TierCount *__restrict__ tc,
                                                           const TierCount *__restrict__ tpos,
-                                                          const int64_t *__restrict__ slot_base,
                                                           Item *__restrict__ items, uint32_t *__restrict__ key,
                                                           int32_t *__restrict__ id)
 {
-    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (r >= n_rows)
+    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= T.total)
         return;
-    const int32_t pc = tc[r].pieces;
+    const int32_t pc = tc[p].pieces;
     if (pc == 0)
         return;
-    const TierCount at = tpos[r];
-    const int32_t slot_offset = slot_base ? (int32_t)*slot_base : 0;
+    const int sd = side_of(T, p);
+    const TierSide &S = T.s[sd];
+    const int32_t r = (int32_t)(p - S.off);
+    const TierCount at = tpos[p];
     for (int32_t k = 0; k < pc; ++k) {
         const int32_t pos = at.pieces + k;
-        const int32_t s = ptr[r] + k * chunk;
-        const int32_t len = min(chunk, ptr[r + 1] - s);
-        items[pos] = Item{(int32_t)r, s, len, pc == 1 ? -1 : slot_offset + at.slots + k};
-        key[pos] = (uint32_t)(chunk - len);
+        const int32_t s = S.ptr[r] + k * chunk;
+        const int32_t len = min(chunk, S.ptr[r + 1] - s);
+        items[pos] = Item{r, s, len, pc == 1 ? -1 : at.slots + k};
+        key[pos] = (uint32_t)(sd * chunk + chunk - len);
         id[pos] = pos;
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_gather_items(const Item *__restrict__ in,
+// the sorted chunk items into each side's list (side 0's come first)
+__global__ __launch_bounds__(kThreads) void k_gather_items(TierSides T, const Item *__restrict__ in,
                                                            const int32_t *__restrict__ order,
-                                                           const int64_t *__restrict__ n, Item *__restrict__ out)
+                                                           const int64_t *__restrict__ counts,
+                                                           const int64_t *__restrict__ n)
 {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i < *n)
-        out[i] = in[order[i]];
+    if (i >= *n)
+        return;
+    const int64_t c0 = counts[1];
+    if (T.n == 2 && i >= c0)
+        T.s[1].chunks[i - c0] = in[order[i]];
+    else
+        T.s[0].chunks[i] = in[order[i]];
 }
 
-__global__ __launch_bounds__(kThreads) void k_split_items(const int32_t *__restrict__ ptr, int64_t n_rows,
-                                                          const TierCount *__restrict__ tc,
+__global__ __launch_bounds__(kThreads) void k_split_items(TierSides T, const TierCount *__restrict__ tc,
                                                           const TierCount *__restrict__ tpos,
-                                                          const int64_t *__restrict__ slot_base,
-                                                          Split *__restrict__ splits)
+                                                          const int64_t *__restrict__ counts)
 {
-    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (r >= n_rows || tc[r].pieces <= 1)
+    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= T.total || tc[p].pieces <= 1)
         return;
-    const int32_t slot_offset = slot_base ? (int32_t)*slot_base : 0;
-    const TierCount at = tpos[r];
-    splits[at.split] = Split{(int32_t)r, slot_offset + at.slots, tc[r].pieces, ptr[r + 1] - ptr[r]};
+    const int sd = side_of(T, p);
+    const TierSide &S = T.s[sd];
+    const int32_t r = (int32_t)(p - S.off);
+    const TierCount at = tpos[p];
+    const int64_t first = sd == 0 ? 0 : counts[2];   // side 1's entries follow side 0's split rows
+    S.splits[at.split - first] = Split{r, at.slots, tc[p].pieces, S.ptr[r + 1] - S.ptr[r]};
 }
 
 // ---------------------------------------------------------------------------
@@ -471,36 +543,33 @@ LevelShape bound_shape(const hnv_level_dev &lv, const hnv_level_dev *coarse, int
     return sh;
 }
 
-// The per-row arrays of one side's degree tiers.
+// The per-entry arrays of the degree tiers (both sides' entries).
 struct TierArrays {
     int32_t *rows_a, *rows_b;
-    TierCount *tc, *tpos;   // per-row tier counts and their exclusive scan
+    TierCount *tc, *tpos;   // per-entry tier counts and their exclusive scan
     uint32_t *key_a, *key_b;
+    int32_t *sorted_rows;   // rows_a or rows_b: the entries' rows in tier order
 };
 
 // Temporaries of one level's build, carved from `base` (nullptr: sizing).
-// The tier arrays hold rows + 2 + kTierAlign entries: side 0 uses them from
-// 0, side 1 from side1_offset(n_edges), so both sides' scans can run before
-// their counts are read.
+// The tier arrays hold tier_entries(rows) entries: side 0's rows from 0,
+// side 1's from side1_offset(n_edges).
 struct Scratch {
     int32_t *inc_edge, *csc_e, *keys_out, *ids_a, *ids_b, *bin_counts, *bin_offs;
     uint32_t *ckey_a, *ckey_b;
     TierArrays tier;
     Item *items;
     int *flag;
-    int64_t *counts;   // [side][small rows, chunks, split rows, partial slots]
+    int64_t *counts;     // [side][small rows, chunks, split rows, partial slots]
+    int64_t *n_chunks;   // both sides' chunk items
     void *temp;
     size_t temp_bytes, total;
 };
 
-constexpr int64_t kTierAlign = 64;   // side 1 starts on a 256-byte boundary
+constexpr int64_t kTierAlign = 64;   // side 1 starts on a 256-byte boundary and a wavefront boundary
+static_assert(kTierAlign % kWave == 0, "a wavefront of tier entries must lie in one side");
 int64_t side1_offset(int64_t n_edges) { return (n_edges + 1 + kTierAlign - 1) / kTierAlign * kTierAlign; }
-
-TierArrays side_arrays(const Scratch &S, int64_t off)
-{
-    const TierArrays &t = S.tier;
-    return TierArrays{t.rows_a + off, t.rows_b + off, t.tc + off, t.tpos + off, t.key_a + off, t.key_b + off};
-}
+int64_t tier_entries(int64_t rows) { return rows + 2 + kTierAlign; }
 
 // entries of the key-count arrays of a bin sort of up to `rows` pairs
 int64_t bin_cap(int64_t rows, int n_bins) { return (int64_t)n_bins * (rows / kBinTile + 1); }
@@ -521,7 +590,7 @@ hnv_status cub_sizes(int64_t nnz, int64_t rows, int64_t n_chunks, int64_t bins, 
         e = prim_exclusive_sum(nullptr, t[4], (int32_t *)nullptr, (int32_t *)nullptr, (int)bins);
     if (e == hipSuccess)
         e = prim_exclusive_scan(nullptr, t[5], (TierCount *)nullptr, (TierCount *)nullptr, TierCount{0, 0, 0},
-                                (int)std::max<int64_t>(rows + 1, 1), TierCountPlus());
+                                (int)tier_entries(rows), TierCountPlus());
     if (e != hipSuccess)
         return fail(HNV_EDEVICE, std::string("sort / scan storage query (needs a visible GPU): ") +
                                      hipGetErrorString(e));
@@ -529,7 +598,9 @@ hnv_status cub_sizes(int64_t nnz, int64_t rows, int64_t n_chunks, int64_t bins, 
     return HNV_OK;
 }
 
-hnv_status scratch_layout(int64_t nnz, int64_t rows, int64_t n_chunks, int n_bins, char *base, Scratch &S)
+// n_chunks: the chunk items of both sides together; tier_bins: the keys of
+// the degree-tier sort
+hnv_status scratch_layout(int64_t nnz, int64_t rows, int64_t n_chunks, int tier_bins, char *base, Scratch &S)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
@@ -542,14 +613,14 @@ hnv_status scratch_layout(int64_t nnz, int64_t rows, int64_t n_chunks, int n_bin
     S.inc_edge = (int32_t *)take(4 * nnz);
     S.csc_e = (int32_t *)take(n4);
     S.keys_out = (int32_t *)take(n4);
-    const size_t t4 = 4 * (size_t)(rows + 2 + kTierAlign);
+    const size_t t4 = 4 * (size_t)tier_entries(rows);
     S.tier.rows_a = (int32_t *)take(t4);
     S.tier.rows_b = (int32_t *)take(t4);
     S.tier.tc = (TierCount *)take(3 * t4);
     S.tier.tpos = (TierCount *)take(3 * t4);
     S.tier.key_a = (uint32_t *)take(t4);
     S.tier.key_b = (uint32_t *)take(t4);
-    const int64_t bins = std::max(bin_cap(rows, n_bins), bin_cap(n_chunks, kBinsMax));
+    const int64_t bins = std::max(bin_cap(tier_entries(rows), tier_bins), bin_cap(n_chunks, kBinsMax));
     S.bin_counts = (int32_t *)take(4 * bins);
     S.bin_offs = (int32_t *)take(4 * bins);
     S.ckey_a = (uint32_t *)take(4 * n_chunks);
@@ -559,6 +630,7 @@ hnv_status scratch_layout(int64_t nnz, int64_t rows, int64_t n_chunks, int n_bin
     S.items = (Item *)take(sizeof(Item) * n_chunks);
     S.flag = (int *)take(16);
     S.counts = (int64_t *)take(8 * 8);
+    S.n_chunks = (int64_t *)take(8);
     if (hnv_status st = cub_sizes(nnz, rows, n_chunks, bins, S.temp_bytes); st != HNV_OK)
         return st;
     S.temp = take(S.temp_bytes);
@@ -595,8 +667,8 @@ hnv_status device_layout(const hnv_level_dev *levels, int n_levels, int d, hnv_d
     for (int l = 0; l < n_levels; ++l) {
         bounds[l] = bound_shape(levels[l], l + 1 < n_levels ? &levels[l + 1] : nullptr, p->small_max, o.chunk);
         Scratch S{};
-        const int32_t nch = std::max(bounds[l].n_chunks[0], bounds[l].n_chunks[1]);
-        if (hnv_status st = scratch_layout(bounds[l].nnz, bounds[l].rows, nch, p->small_max + 2, nullptr, S);
+        const int64_t nch = (int64_t)bounds[l].n_chunks[0] + bounds[l].n_chunks[1];
+        if (hnv_status st = scratch_layout(bounds[l].nnz, bounds[l].rows, nch, 2 * (p->small_max + 3), nullptr, S);
             st != HNV_OK)
             return st;
         scratch_bytes = std::max(scratch_bytes, S.total);
@@ -743,61 +815,78 @@ hnv_status bin_sort(uint32_t *ka, int32_t *va, uint32_t *kb, int32_t *vb, int64_
     return dev_check("counting sort");
 }
 
-// The tier keys, sorts and scans of one side (arrays T); counts[0..3] on the
-// device.  `bad`: the level's check flags (null: checked already).
-hnv_status tier_scan(const int32_t *ptr, int64_t n_rows, int small_max, int chunk, const int *bad,
-                     const TierArrays &T, Scratch &S, int64_t *counts, hipStream_t s)
+// The tier keys, sort and scan of the sides T (one or two); counts[4 * side
+// + 0..3] and S.n_chunks on the device.  `bad`: the level's check flags
+// (null: checked already).
+hnv_status tier_scan(const TierSides &T, int small_max, int chunk, const int *bad, Scratch &S, int64_t *counts,
+                     hipStream_t s)
 {
-    if (n_rows == 0) {
-        k_fill<<<1, kThreads, 0, s>>>(reinterpret_cast<int32_t *>(counts), 8, 0);
+    if (T.total == 0) {
+        k_fill<<<1, kThreads, 0, s>>>(reinterpret_cast<int32_t *>(counts), 16, 0);
+        k_fill<<<1, kThreads, 0, s>>>(reinterpret_cast<int32_t *>(S.n_chunks), 2, 0);
         return dev_check("tier counts");
     }
-    if (small_max + 2 > kBinsMax)
+    const int64_t n_keys = (int64_t)T.n * (small_max + 3);
+    if (n_keys > kBinsMax)
         return fail(HNV_EUNSUPPORTED, "small_max above the tier sort's key range");
-    const int n = (int)n_rows;
-    k_tier_keys<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, small_max, chunk, bad, T.key_a, T.rows_a,
-                                                      T.tc);
-    // the lane-group tier order: one counting pass over the small_max + 2
-    // keys, which leaves the sorted rows in rows_b
+    TierArrays &A = S.tier;
+    k_tier_keys<<<grid_for(T.total), kThreads, 0, s>>>(T, small_max, chunk, bad, A.key_a, A.rows_a, A.tc);
+    // the lane-group tier order of both sides: one counting pass
     bool in_b = false;
-    if (hnv_status st = bin_sort(T.key_a, T.rows_a, T.key_b, T.rows_b, n_rows, nullptr, small_max + 2, S, s, in_b);
+    if (hnv_status st = bin_sort(A.key_a, A.rows_a, A.key_b, A.rows_b, T.total, nullptr, n_keys, S, s, in_b);
         st != HNV_OK)
         return st;
+    A.sorted_rows = in_b ? A.rows_b : A.rows_a;
     size_t tb = S.temp_bytes;
-    if (prim_exclusive_scan(S.temp, tb, T.tc, T.tpos, TierCount{0, 0, 0}, n, TierCountPlus(), s) != hipSuccess)
+    if (prim_exclusive_scan(S.temp, tb, A.tc, A.tpos, TierCount{0, 0, 0}, (int)T.total, TierCountPlus(), s) !=
+        hipSuccess)
         return fail(HNV_EDEVICE, "scan of the tier counts");
-    k_tier_counts<<<1, 64, 0, s>>>(T.key_b, T.tc, T.tpos, n_rows, small_max, counts);
+    k_tier_counts<<<1, 64, 0, s>>>(in_b ? A.key_b : A.key_a, A.tc, A.tpos, T, small_max, counts, S.n_chunks);
     return dev_check("tier keys");
 }
 
-// The work lists of one side after tier_scan, from its counts on the device
-// (cnt[0..3]) without reading them: grids cover the bounds (max_chunks
-// wavefront-tier items) and the kernels stop at the counts.  slot_base (on
-// the device, or null for none) holds the partial slots of the side before.
-hnv_status tier_emit(const int32_t *ptr, int64_t n_rows, int chunk, const int32_t *rowmap, int32_t row_base,
-                     const int64_t *slot_base, const int64_t *cnt, int64_t max_chunks, const int *bad,
-                     const TierArrays &T, Scratch &S, DevSide &D, hipStream_t s)
+// The work lists of the sides T after tier_scan, from the counts it left on
+// the device without reading them: grids cover the bounds (max_chunks
+// wavefront-tier items of both sides) and the kernels stop at the counts.
+hnv_status tier_emit(const TierSides &T, int chunk, int64_t max_chunks, const int *bad, Scratch &S,
+                     const int64_t *counts, hipStream_t s)
 {
-    if (n_rows == 0)
+    if (T.total == 0)
         return HNV_OK;
-    k_small_items<<<grid_for(n_rows), kThreads, 0, s>>>(T.rows_b, ptr, cnt, rowmap, row_base, bad, D.idx, D.cidx,
-                                                        const_cast<Item *>(D.small),
-                                                        const_cast<InlineIds *>(D.small_ids),
-                                                        const_cast<InlineIds *>(D.small_cids));
+    const TierArrays &A = S.tier;
+    k_small_items<<<grid_for(T.total), kThreads, 0, s>>>(T, A.sorted_rows, counts, bad);
     if (max_chunks > 0) {
-        k_chunk_items<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, chunk, T.tc, T.tpos, slot_base, S.items,
-                                                            S.ckey_a, S.ids_a);
-        // longest first: a stable sort on chunk - len, which is below chunk
+        k_chunk_items<<<grid_for(T.total), kThreads, 0, s>>>(T, chunk, A.tc, A.tpos, S.items, S.ckey_a, S.ids_a);
+        // each side's longest first: a stable sort on side * chunk + chunk - len
         bool in_b = false;
-        if (hnv_status st = bin_sort(S.ckey_a, S.ids_a, S.ckey_b, S.ids_b, max_chunks, cnt + 1, chunk, S, s, in_b);
+        if (hnv_status st = bin_sort(S.ckey_a, S.ids_a, S.ckey_b, S.ids_b, max_chunks, S.n_chunks,
+                                     (int64_t)T.n * chunk, S, s, in_b);
             st != HNV_OK)
             return st;
-        k_gather_items<<<grid_for(max_chunks), kThreads, 0, s>>>(S.items, in_b ? S.ids_b : S.ids_a, cnt + 1,
-                                                                 const_cast<Item *>(D.chunks));
+        k_gather_items<<<grid_for(max_chunks), kThreads, 0, s>>>(T, S.items, in_b ? S.ids_b : S.ids_a, counts,
+                                                                 S.n_chunks);
     }
-    k_split_items<<<grid_for(n_rows), kThreads, 0, s>>>(ptr, n_rows, T.tc, T.tpos, slot_base,
-                                                        const_cast<Split *>(D.splits));
+    k_split_items<<<grid_for(T.total), kThreads, 0, s>>>(T, A.tc, A.tpos, counts);
     return dev_check("work lists");
+}
+
+// One side's part of a tier build (its rows at entries from `off`).
+TierSide tier_side(const DevSide &D, int64_t n_rows, int64_t off, const int32_t *rowmap)
+{
+    TierSide t{};
+    t.ptr = D.ptr;
+    t.n_rows = (int32_t)n_rows;
+    t.off = (int32_t)off;
+    t.rowmap = rowmap;
+    t.row_base = D.row_base;
+    t.idx = D.idx;
+    t.cidx = D.cidx;
+    t.small = const_cast<Item *>(D.small);
+    t.ids = const_cast<InlineIds *>(D.small_ids);
+    t.cids = const_cast<InlineIds *>(D.small_cids);
+    t.chunks = const_cast<Item *>(D.chunks);
+    t.splits = const_cast<Split *>(D.splits);
+    return t;
 }
 
 // Level l of a plan, enqueued without waiting: its checks were launched
@@ -859,20 +948,18 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
     }
     if ((st = dev_check("plan arrays")) != HNV_OK)
         return st;
-    // degree tiers: each side's scans, then its work lists, side 0 then
-    // side 1 (partial slots continue across sides); the sizes of the work
-    // lists stay on the device until the build ends.  D.n_* still hold the
-    // bounds the workspace was carved for.
-    const TierArrays T[2] = {side_arrays(S, 0), side_arrays(S, side1_offset(nE))};
-    for (int sd = 0; sd < 2; ++sd) {
-        DevSide &D = L.side[sd];
-        const int64_t n_rows = sd == 0 ? nE : nV;
-        int64_t *cnt = M->counts + 4 * sd;
-        if ((st = tier_scan(D.ptr, n_rows, sm, chunk, bad, T[sd], S, cnt, s)) != HNV_OK ||
-            (st = tier_emit(D.ptr, n_rows, chunk, C ? L.rowmap : nullptr, D.row_base,
-                            sd == 0 ? nullptr : M->counts + 3, cnt, D.n_chunks, bad, T[sd], S, D, s)) != HNV_OK)
-            return st;
-    }
+    // degree tiers of both sides together (partial slots continue from side
+    // 0 into side 1); the sizes of the work lists stay on the device until
+    // the build ends.  D.n_* still hold the bounds the workspace was carved
+    // for.
+    TierSides TS{};
+    TS.n = 2;
+    TS.s[0] = tier_side(S0, nE, 0, C ? L.rowmap : nullptr);
+    TS.s[1] = tier_side(S1, nV, side1_offset(nE), C ? L.rowmap : nullptr);
+    TS.total = side1_offset(nE) + nV;
+    if ((st = tier_scan(TS, sm, chunk, bad, S, M->counts, s)) != HNV_OK ||
+        (st = tier_emit(TS, chunk, (int64_t)S0.n_chunks + S1.n_chunks, bad, S, M->counts, s)) != HNV_OK)
+        return st;
     // weights and reciprocals
     if (lv.edge_w) {
         if ((st = copy_d2d(L.w, lv.edge_w, 4 * nE, s)) != HNV_OK)
@@ -952,7 +1039,7 @@ hnv_status score_dev_layout(int64_t n_cand, int64_t n_members, int d, hnv_dtype 
     L.off_splits = take(sizeof(Split) * (size_t)L.n_splits);
     L.off_part = take(sizeof(float) * (size_t)L.n_slots * (2 * d + 8));
     Scratch S{};
-    if (hnv_status st = scratch_layout(n_members, n_cand, L.n_chunks, L.small_max + 2, nullptr, S); st != HNV_OK)
+    if (hnv_status st = scratch_layout(n_members, n_cand, L.n_chunks, L.small_max + 3, nullptr, S); st != HNV_OK)
         return st;
     L.scratch_bytes = S.total;
     L.off_scratch = take(L.scratch_bytes);
@@ -1040,9 +1127,9 @@ extern "C" hnv_status hnv_plan_create_device(const hnv_level_dev *levels, const 
         k_fill<<<grid_for(meta_words), kThreads, 0, s>>>(reinterpret_cast<int32_t *>(meta), meta_words, 0);
         for (int l = 0; l < n_levels && st == HNV_OK; ++l) {
             Scratch S{};
-            const int32_t nch = std::max(bounds[l].n_chunks[0], bounds[l].n_chunks[1]);
+            const int64_t nch = (int64_t)bounds[l].n_chunks[0] + bounds[l].n_chunks[1];
             const hnv_level_dev *C = l + 1 < n_levels ? &levels[l + 1] : nullptr;
-            if ((st = scratch_layout(bounds[l].nnz, bounds[l].rows, nch, p->small_max + 2, level_base, S)) ==
+            if ((st = scratch_layout(bounds[l].nnz, bounds[l].rows, nch, 2 * (p->small_max + 3), level_base, S)) ==
                     HNV_OK &&
                 (st = launch_checks(levels[l], C, C ? &maps[l] : nullptr, full, S, meta[l].flags, s)) == HNV_OK)
                 st = build_level(p, levels, maps, n_levels, l, &meta[l], S, s);
@@ -1104,7 +1191,7 @@ extern "C" hnv_status hnv_score_plan_create_device(const int32_t *cand_ptr, cons
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *base = static_cast<char *>(workspace);
     Scratch S{};
-    if ((st = scratch_layout(n_members, n_cand, L.n_chunks, L.small_max + 2, base + L.off_scratch, S)) != HNV_OK)
+    if ((st = scratch_layout(n_members, n_cand, L.n_chunks, L.small_max + 3, base + L.off_scratch, S)) != HNV_OK)
         return st;
     // checks: offsets (start 0, never decrease, end at n_members) and member
     // ids in [0, z_rows); empty candidates are allowed (their rows are NaN)
@@ -1139,11 +1226,13 @@ extern "C" hnv_status hnv_score_plan_create_device(const int32_t *cand_ptr, cons
     D.chunks = reinterpret_cast<const Item *>(base + L.off_chunks);
     D.splits = reinterpret_cast<const Split *>(base + L.off_splits);
     if (n_cand > 0) {
-        const TierArrays T = side_arrays(S, 0);
-        if ((st = tier_scan(cand_ptr, n_cand, L.small_max, kScoreChunk, nullptr, T, S, S.counts, s)) != HNV_OK ||
-            (st = tier_emit(cand_ptr, n_cand, kScoreChunk, nullptr, 0, nullptr, S.counts, L.n_chunks, nullptr, T, S, D,
-                            s)) !=
-                HNV_OK ||
+        D.ptr = cand_ptr;
+        TierSides TS{};
+        TS.n = 1;
+        TS.s[0] = tier_side(D, n_cand, 0, nullptr);
+        TS.total = n_cand;
+        if ((st = tier_scan(TS, L.small_max, kScoreChunk, nullptr, S, S.counts, s)) != HNV_OK ||
+            (st = tier_emit(TS, kScoreChunk, L.n_chunks, nullptr, S, S.counts, s)) != HNV_OK ||
             (st = read_back(cnt, S.counts, sizeof(cnt), s)) != HNV_OK)
             return st;
         if (cnt[0] > L.n_small || cnt[1] > L.n_chunks || cnt[2] > L.n_splits || cnt[3] > L.n_slots)
