@@ -151,9 +151,13 @@ hnv_status hnv_coarsen_level(const hnv_level *fine, int32_t *node_rep, int32_t *
  *   level and owned by the caller; only the first c_n_edges+1 / c_nnz /
  *   c_n_edges entries of the coarse arrays are written.
  * c_sizes: HOST int64[3] receiving coarse n_nodes, n_edges, nnz.  The call
- * checks the input on the device first (same statuses as
- * hnv_validate_level), then enqueues the kernels on `stream` and waits for
- * the sizes, so it returns with the outputs complete.  workspace: DEVICE,
+ * checks the input on the device (same statuses as hnv_validate_level),
+ * enqueues the step's kernels behind the checks on `stream` and waits once,
+ * for the checks' result and the sizes together, so it returns with the
+ * outputs complete.  The kernels that follow the input's offsets or member
+ * ids read the checks' result first and do nothing on invalid input, which
+ * therefore leaves every access inside the given arrays; the outputs are
+ * then unspecified.  workspace: DEVICE,
  * >= hnv_coarsen_workspace_bytes, 256-byte aligned; its contents need not
  * be initialised and are scratch afterwards.  Calls sharing a workspace on
  * different streams race.  The workspace size includes the temporary

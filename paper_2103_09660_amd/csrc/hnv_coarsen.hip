@@ -70,8 +70,10 @@ __global__ __launch_bounds__(kThreads) void k_rank(const int32_t *__restrict__ o
 __global__ __launch_bounds__(kThreads) void k_best(const int32_t *__restrict__ idx,
                                                    const int32_t *__restrict__ inc_edge,
                                                    const int32_t *__restrict__ rank, int64_t nnz,
-                                                   int32_t *__restrict__ best)
+                                                   int32_t *__restrict__ best, const int *__restrict__ bad)
 {
+    if (*bad)   // the step's input failed its checks
+        return;
     const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (j >= nnz)
         return;
@@ -129,8 +131,11 @@ __global__ __launch_bounds__(kThreads) void k_bucket_starts(const uint32_t *__re
 __global__ __launch_bounds__(kBucketThreads) void k_bucket_min(const uint32_t *__restrict__ keys,
                                                                const int32_t *__restrict__ vals,
                                                                const int64_t *__restrict__ start, int shift,
-                                                               int64_t n_nodes, int32_t *__restrict__ best)
+                                                               int64_t n_nodes, int32_t *__restrict__ best,
+                                                               const int *__restrict__ bad)
 {
+    if (*bad)   // the step's input failed its checks
+        return;
     __shared__ int32_t m[1 << kBucketShiftMax];
     const int span = 1 << shift;
     const int64_t base = (int64_t)blockIdx.x << shift;
@@ -177,8 +182,10 @@ __global__ __launch_bounds__(kThreads) void k_group_flags(const int32_t *__restr
 __global__ __launch_bounds__(kThreads) void k_node_rep(const int32_t *__restrict__ choice,
                                                        const int32_t *__restrict__ first,
                                                        const int32_t *__restrict__ gid, int64_t n_nodes,
-                                                       int32_t *__restrict__ node_rep)
+                                                       int32_t *__restrict__ node_rep, const int *__restrict__ bad)
 {
+    if (*bad)   // the step's input failed its checks
+        return;
     const int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (v >= n_nodes)
         return;
@@ -197,8 +204,10 @@ __global__ __launch_bounds__(kThreads) void k_kept_flags(const int32_t *__restri
 
 __global__ __launch_bounds__(kThreads) void k_map(const int32_t *__restrict__ idx,
                                                   const int32_t *__restrict__ node_rep, int64_t nnz,
-                                                  int32_t *__restrict__ mapped)
+                                                  int32_t *__restrict__ mapped, const int *__restrict__ bad)
 {
+    if (*bad)   // the step's input failed its checks
+        return;
     const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (j < nnz)
         mapped[j] = node_rep[idx[j]];
@@ -267,8 +276,11 @@ __device__ __forceinline__ void thread_bitonic(int32_t (&v)[N])
 __global__ __launch_bounds__(kThreads) void k_sort_short(const int32_t *__restrict__ ptr,
                                                          const int32_t *__restrict__ mapped, int64_t n_edges,
                                                          int32_t *__restrict__ sorted, int32_t *__restrict__ big_begin,
-                                                         int32_t *__restrict__ big_end, int32_t *__restrict__ n_big)
+                                                         int32_t *__restrict__ big_end, int32_t *__restrict__ n_big,
+                                                         const int *__restrict__ bad)
 {
+    if (*bad)   // the step's input failed its checks
+        return;
     const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     int32_t s = 0, n = 0;
     if (e < n_edges) {
@@ -375,8 +387,10 @@ __device__ __forceinline__ void wave_sort(const int32_t *__restrict__ in, int32_
 // all 64 lanes.  No list of work, no atomics.
 __global__ __launch_bounds__(kThreads) void k_sort_wave(const int32_t *__restrict__ ptr,
                                                         const int32_t *__restrict__ mapped, int64_t n_edges,
-                                                        int32_t *__restrict__ sorted)
+                                                        int32_t *__restrict__ sorted, const int *__restrict__ bad)
 {
+    if (*bad)   // the step's input failed its checks
+        return;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t window = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kWave;
     const int64_t e = window * kWave + lane;
@@ -409,8 +423,10 @@ __global__ __launch_bounds__(kThreads) void k_distinct(const int32_t *__restrict
                                                        const int32_t *__restrict__ sorted,
                                                        const int32_t *__restrict__ inc_edge,
                                                        const int32_t *__restrict__ kept, int64_t nnz,
-                                                       int32_t *__restrict__ dflag)
+                                                       int32_t *__restrict__ dflag, const int *__restrict__ bad)
 {
+    if (*bad)   // the step's input failed its checks
+        return;
     const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (j >= nnz)
         return;
@@ -422,8 +438,10 @@ __global__ __launch_bounds__(kThreads) void k_distinct(const int32_t *__restrict
 __global__ __launch_bounds__(kThreads) void k_emit_members(const int32_t *__restrict__ sorted,
                                                            const int32_t *__restrict__ dflag,
                                                            const int32_t *__restrict__ dpos, int64_t nnz,
-                                                           int32_t *__restrict__ c_idx)
+                                                           int32_t *__restrict__ c_idx, const int *__restrict__ bad)
 {
+    if (*bad)   // the step's input failed its checks
+        return;
     const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (j < nnz && dflag[j])
         c_idx[dpos[j]] = sorted[j];
@@ -437,8 +455,10 @@ __global__ __launch_bounds__(kThreads) void k_emit_edges(const int32_t *__restri
                                                          const int32_t *__restrict__ dpos,
                                                          const float *__restrict__ w, int64_t n_edges,
                                                          int32_t *__restrict__ edge_rep, int32_t *__restrict__ c_ptr,
-                                                         float *__restrict__ c_w)
+                                                         float *__restrict__ c_w, const int *__restrict__ bad)
 {
+    if (*bad)   // the step's input failed its checks
+        return;
     const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (e >= n_edges)
         return;
@@ -457,8 +477,10 @@ __global__ __launch_bounds__(kThreads) void k_emit_edges(const int32_t *__restri
 __global__ void k_sizes(const int32_t *__restrict__ gflag, const int32_t *__restrict__ gid, int64_t n_nodes,
                         const int32_t *__restrict__ kept, const int32_t *__restrict__ krank, int64_t n_edges,
                         const int32_t *__restrict__ dflag, const int32_t *__restrict__ dpos, int64_t nnz,
-                        int32_t *__restrict__ c_ptr, int64_t *__restrict__ sizes)
+                        int32_t *__restrict__ c_ptr, int64_t *__restrict__ sizes, const int *__restrict__ bad)
 {
+    if (*bad)   // the step's input failed its checks
+        return;
     if (threadIdx.x != 0 || blockIdx.x != 0)
         return;
     const int64_t nv = n_nodes ? (int64_t)gid[n_nodes - 1] + gflag[n_nodes - 1] : 0;
@@ -962,29 +984,38 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
     }
     if ((st = dev_check("coarsening input check")) != HNV_OK)
         return st;
+    // The checks' result: read here on the feature path; on the featureless
+    // path with the coarse sizes at the end (every kernel there that follows
+    // offsets or member ids, or writes an output, first reads the check
+    // word and does nothing when it is set).
     struct {
         int bad, pad;
         unsigned long long total;
     } chk{};
-    if ((st = sync_read(&chk, flag, sizeof(chk))) != HNV_OK)
-        return st;
-    if (nE == 0) {
-        int32_t p0 = 0;
-        if ((st = sync_read(&p0, edge_ptr, 4)) != HNV_OK)
+    auto report = [&]() -> hnv_status {
+        if (nE == 0) {
+            int32_t p0 = 0;
+            if (hnv_status r = sync_read(&p0, edge_ptr, 4); r != HNV_OK)
+                return r;
+            if (p0 != 0 || nz != 0)
+                chk.bad |= 1;
+        }
+        if (chk.bad & 1)
+            return fail(HNV_EINVAL, "edge_ptr: offsets must start at 0, increase, end at nnz, no empty hyperedge");
+        if (chk.bad & 2)
+            return fail(HNV_ERANGE, "a member id is outside [0, n_nodes)");
+        if (chk.bad & 4)
+            return fail(HNV_EUNSORTED, "member lists must be strictly ascending");
+        if (chk.bad & 8)
+            return fail(HNV_EINVAL, "weights must be finite and > 0");
+        if ((chk.bad & 16) || chk.total >= (1ull << 31))
+            return fail(HNV_EINVAL, "features must be counts >= 0 with a total below 2^31");
+        return HNV_OK;
+    };
+    if (feat) {
+        if ((st = sync_read(&chk, flag, sizeof(chk))) != HNV_OK || (st = report()) != HNV_OK)
             return st;
-        if (p0 != 0 || nz != 0)
-            chk.bad |= 1;
     }
-    if (chk.bad & 1)
-        return fail(HNV_EINVAL, "edge_ptr: offsets must start at 0, increase, end at nnz, no empty hyperedge");
-    if (chk.bad & 2)
-        return fail(HNV_ERANGE, "a member id is outside [0, n_nodes)");
-    if (chk.bad & 4)
-        return fail(HNV_EUNSORTED, "member lists must be strictly ascending");
-    if (chk.bad & 8)
-        return fail(HNV_EINVAL, "weights must be finite and > 0");
-    if ((chk.bad & 16) || chk.total >= (1ull << 31))
-        return fail(HNV_EINVAL, "features must be counts >= 0 with a total below 2^31");
 
     int32_t *order = at(L.order), *rank = at(L.rank), *best = at(L.best), *choice = at(L.choice);
     int32_t *first = at(L.first), *count = at(L.count), *gflag = at(L.gflag), *gid = at(L.gid);
@@ -1033,9 +1064,9 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
                     return fail(HNV_EDEVICE, "partition of incidences by node");
                 k_bucket_starts<<<grid_for(nb + 1), kThreads, 0, s>>>(nodes_sorted, nnz, shift, nb, bstart);
                 k_bucket_min<<<(unsigned)nb, kBucketThreads, 0, s>>>(nodes_sorted, pr_sorted, bstart, shift, n_nodes,
-                                                                     best);
+                                                                     best, flag);
             } else {
-                k_best<<<grid_for(nz), kThreads, 0, s>>>(edge_idx, inc_edge, rank, nnz, best);
+                k_best<<<grid_for(nz), kThreads, 0, s>>>(edge_idx, inc_edge, rank, nnz, best, flag);
             }
         }
         if (nE > 0 && feat) {
@@ -1061,7 +1092,7 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
         tb = L.temp_bytes;
         if (prim_exclusive_sum(temp, tb, gflag, gid, nV, s) != hipSuccess)
             return fail(HNV_EDEVICE, "scan of group flags");
-        k_node_rep<<<grid_for(nV), kThreads, 0, s>>>(choice, first, gid, n_nodes, node_rep);
+        k_node_rep<<<grid_for(nV), kThreads, 0, s>>>(choice, first, gid, n_nodes, node_rep, flag);
     }
     if (nE > 0) {
         // 4. removed hyperedges
@@ -1073,16 +1104,16 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
         // lists by a thread, medium ones by a wavefront, long ones by the
         // library's segmented sort over a list of them)
         if (nz > 0) {
-            k_map<<<grid_for(nz), kThreads, 0, s>>>(edge_idx, node_rep, nnz, mapped);
+            k_map<<<grid_for(nz), kThreads, 0, s>>>(edge_idx, node_rep, nnz, mapped, flag);
             int32_t *big_begin = at(L.big_begin), *big_end = at(L.big_end), *n_big_dev = at(L.sort_counts);
             const int64_t n_big = max_big_lists(nnz);
             k_fill<<<1, kThreads, 0, s>>>(n_big_dev, 1, 0);
             k_fill<<<grid_for(n_big), kThreads, 0, s>>>(big_begin, n_big, 0);
             k_fill<<<grid_for(n_big), kThreads, 0, s>>>(big_end, n_big, 0);
             k_sort_short<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, mapped, n_edges, sorted, big_begin, big_end,
-                                                            n_big_dev);
+                                                            n_big_dev, flag);
             if (nnz > kSortThread)
-                k_sort_wave<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, mapped, n_edges, sorted);
+                k_sort_wave<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, mapped, n_edges, sorted, flag);
             if (nnz > kSortWave) {
                 tb = L.temp_bytes;
                 // non-negative ids: sorted as unsigned so only the low bits count;
@@ -1093,15 +1124,15 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
                     return fail(HNV_EDEVICE, "segmented sort of long coarse member lists");
             }
         }
-        k_distinct<<<grid_for(nz), kThreads, 0, s>>>(edge_ptr, sorted, inc_edge, kept, nnz, dflag);
+        k_distinct<<<grid_for(nz), kThreads, 0, s>>>(edge_ptr, sorted, inc_edge, kept, nnz, dflag, flag);
         tb = L.temp_bytes;
         if (prim_exclusive_sum(temp, tb, dflag, dpos, nz, s) != hipSuccess)
             return fail(HNV_EDEVICE, "scan of coarse members");
-        k_emit_members<<<grid_for(nz), kThreads, 0, s>>>(sorted, dflag, dpos, nnz, c_edge_idx);
+        k_emit_members<<<grid_for(nz), kThreads, 0, s>>>(sorted, dflag, dpos, nnz, c_edge_idx, flag);
         k_emit_edges<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, kept, krank, dpos, edge_w, n_edges, edge_rep,
-                                                       c_edge_ptr, c_edge_w);
+                                                       c_edge_ptr, c_edge_w, flag);
     }
-    k_sizes<<<1, 64, 0, s>>>(gflag, gid, n_nodes, kept, krank, n_edges, dflag, dpos, nnz, c_edge_ptr, sizes);
+    k_sizes<<<1, 64, 0, s>>>(gflag, gid, n_nodes, kept, krank, n_edges, dflag, dpos, nnz, c_edge_ptr, sizes, flag);
     if (feat && nV > 0) {
         // 6. X': each coarse node's row is the sum of its fine nodes' rows
         int32_t *gcount = at(L.gcount), *gptr = at(L.gptr), *gcur = at(L.gcur), *gnodes = at(L.gnodes);
@@ -1123,7 +1154,20 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
     }
     if ((st = dev_check("coarsening kernels")) != HNV_OK)
         return st;
-    return sync_read(c_sizes, sizes, 3 * sizeof(int64_t));
+    if (feat)
+        return sync_read(c_sizes, sizes, 3 * sizeof(int64_t));
+    int64_t sz[3] = {0, 0, 0};
+    hipError_t e = hipMemcpyAsync(&chk, flag, sizeof(chk), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sz, sizes, sizeof(sz), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return fail(HNV_EDEVICE, std::string("read-back: ") + hipGetErrorString(e));
+    if ((st = report()) != HNV_OK)
+        return st;
+    std::memcpy(c_sizes, sz, sizeof(sz));
+    return HNV_OK;
 }
 
 }  // namespace

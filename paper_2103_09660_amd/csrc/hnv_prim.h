@@ -41,14 +41,23 @@ inline hipError_t prim_sort_pairs(void *temp, size_t &bytes, const K *keys_in, K
                                                  (unsigned)begin_bit, (unsigned)end_bit, s);
 }
 
+// The segmented sort takes one workgroup per segment and never splits the
+// segments by size: the split that rocPRIM's default configuration makes
+// from 64 segments on reads the split's counts back to the host, a wait in
+// the middle of the caller's work.  The callers pass only long segments
+// (and empty ones, which end at once).
+using SegSortConfig = rocprim::segmented_radix_sort_config<8, rocprim::kernel_config<256, 16>,
+                                                           rocprim::DisabledWarpSortConfig, false>;
+
 // Keys of each segment [begin[i], end[i]) sorted independently, stable.
 template <typename K, typename O>
 inline hipError_t prim_segmented_sort_keys(void *temp, size_t &bytes, const K *keys_in, K *keys_out, int64_t n,
                                            int64_t segments, O begin, O end, int begin_bit, int end_bit,
                                            hipStream_t s = 0)
 {
-    return rocprim::segmented_radix_sort_keys(temp, bytes, keys_in, keys_out, (unsigned)n, (unsigned)segments,
-                                              begin, end, (unsigned)begin_bit, (unsigned)end_bit, s);
+    return rocprim::segmented_radix_sort_keys<SegSortConfig>(temp, bytes, keys_in, keys_out, (unsigned)n,
+                                                             (unsigned)segments, begin, end, (unsigned)begin_bit,
+                                                             (unsigned)end_bit, s);
 }
 
 // out[i] = in[0] + .. + in[i-1], out[0] = 0.

@@ -141,6 +141,40 @@ def test_invalid_inputs_are_rejected(H):
     assert _bad(H, 4, [0, 2, 4], [0, 1, 2, 3], [float("inf"), 1.0]) == L.HNV_EINVAL
 
 
+def test_invalid_large_inputs_are_rejected(oracle_mod, H):
+    """At the size where the least ranks are taken in LDS buckets (over 2^20
+    incidences), malformed input reaches the step's later kernels, which read
+    the check word first: the status comes back, and the same workspace then
+    gives the oracle's maps for the valid level."""
+    import torch
+    from paper_2103_09660_amd import _lib as L
+    O = oracle_mod
+    hg = random_hypergraph(21, 300_000, 250_000, 1, 10, weighted=False)
+    assert hg.nnz >= (1 << 20)
+    ws = torch.empty(H.coarsen_workspace_bytes(hg.n_nodes, hg.n_edges, hg.nnz), dtype=torch.uint8, device="cuda")
+
+    def run(ptr, idx):
+        lv = H.DeviceLevel(hg.n_nodes, hg.n_edges, hg.nnz, torch.tensor(ptr, dtype=torch.int32, device="cuda"),
+                           torch.tensor(idx, dtype=torch.int32, device="cuda"))
+        return H.coarsen_level_device(lv, ws)
+
+    ptr = hg.edge_ptr.astype(np.int32)
+    e = int(np.argmax(np.diff(hg.edge_ptr) >= 2))
+    last = int(hg.edge_ptr[e + 1]) - 1
+    for k, (p2, i2, status) in enumerate([
+            (ptr, np.where(np.arange(hg.nnz) == last, hg.n_nodes, hg.edge_idx), L.HNV_ERANGE),
+            (ptr, np.where(np.arange(hg.nnz) == 7, -5, hg.edge_idx), L.HNV_ERANGE),
+            (np.where(np.arange(hg.n_edges + 1) == hg.n_edges // 2, hg.nnz + 100, ptr), hg.edge_idx,
+             L.HNV_EINVAL)]):
+        with pytest.raises(H.HnvError) as ei:
+            run(p2, i2.astype(np.int32))
+        assert ei.value.status == status, k
+    ref = O.coarsen_level(O.Level(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w))
+    nrep, erep, c = run(ptr, hg.edge_idx.astype(np.int32))
+    assert np.array_equal(nrep.cpu().numpy(), ref.node_rep) and np.array_equal(erep.cpu().numpy(), ref.edge_rep)
+    assert np.array_equal(c.edge_idx.cpu().numpy(), ref.coarse.eidx)
+
+
 def test_workspace_errors(H):
     import torch
     from paper_2103_09660_amd import _lib as L
