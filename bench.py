@@ -696,16 +696,9 @@ def run_coarsening(H, torch, hg, cfg, hier, host_ms, reps=3):
     finest level already in device memory to the coarsest, against the
     library's host coarsening; the maps must agree bit for bit."""
     lv0 = H.DeviceLevel.from_host(hier.levels[0], "cuda")
-    ws = torch.empty(H.coarsen_workspace_bytes(lv0.n_nodes, lv0.n_edges, lv0.nnz), dtype=torch.uint8,
-                     device="cuda")
 
     def build():
-        levels, maps = [lv0], []
-        for _ in range(cfg.levels):
-            nrep, erep, c = H.coarsen_level_device(levels[-1], ws)
-            maps.append((nrep, erep))
-            levels.append(c)
-        return levels, maps
+        return H.coarsen_hierarchy_device(lv0, cfg.levels)
 
     build()
     torch.cuda.synchronize()

@@ -149,11 +149,18 @@ def coarsen_level_device(level: DeviceLevel, workspace=None):
     The call waits for the coarse sizes; ``workspace`` (a uint8 tensor of at
     least :func:`coarsen_workspace_bytes`) may be reused between calls."""
     torch = _torch()
-    dev = level.edge_ptr.device
     level.check()
     need = coarsen_workspace_bytes(level.n_nodes, level.n_edges, level.nnz)
     if workspace is None or workspace.numel() < need:
-        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+        workspace = torch.empty(need, dtype=torch.uint8, device=level.edge_ptr.device)
+    return _coarsen_step(level, workspace)
+
+
+def _coarsen_step(level: DeviceLevel, workspace):
+    """coarsen_level_device with a workspace taken as is (the library
+    returns HNV_EWORKSPACE if it is too small)."""
+    torch = _torch()
+    dev = level.edge_ptr.device
     i32 = dict(dtype=torch.int32, device=dev)
     node_rep = torch.empty(max(level.n_nodes, 1), **i32)
     edge_rep = torch.empty(max(level.n_edges, 1), **i32)
@@ -237,6 +244,9 @@ def coarsen_hierarchy_device(level: DeviceLevel, n_coarsen: int, min_rows: int =
     min_rows > 0 stops them, see :func:`_stop`), one shared workspace:
     returns (device levels, [(node_rep, edge_rep)] per step)."""
     torch = _torch()
+    level.check()
+    # the finest level's workspace serves every step: no step's workspace is
+    # larger, since a coarse level is never larger than the fine one
     ws = torch.empty(coarsen_workspace_bytes(level.n_nodes, level.n_edges, level.nnz), dtype=torch.uint8,
                      device=level.edge_ptr.device)
     levels, maps = [level], []
@@ -244,7 +254,7 @@ def coarsen_hierarchy_device(level: DeviceLevel, n_coarsen: int, min_rows: int =
         fine = levels[-1]
         if _stop(fine.n_nodes + fine.n_edges, None, min_rows):
             break
-        nrep, erep, coarse = coarsen_level_device(fine, ws)
+        nrep, erep, coarse = _coarsen_step(fine, ws)
         if _stop(fine.n_nodes + fine.n_edges, coarse.n_nodes + coarse.n_edges, min_rows):
             break
         maps.append((nrep, erep))

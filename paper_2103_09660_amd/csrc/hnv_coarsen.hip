@@ -57,12 +57,33 @@ __global__ __launch_bounds__(kThreads) void k_keys(const int32_t *__restrict__ p
     ids[e] = (int32_t)e;
 }
 
+// rank[order[i]] = i, and the per-hyperedge and per-node accumulators of
+// the choice step set to their start values (first INT_MAX, count 0, best
+// INT_MAX)
 __global__ __launch_bounds__(kThreads) void k_rank(const int32_t *__restrict__ order, int64_t n_edges,
-                                                   int32_t *__restrict__ rank)
+                                                   int64_t n_nodes, int32_t *__restrict__ rank,
+                                                   int32_t *__restrict__ first, int32_t *__restrict__ count,
+                                                   int32_t *__restrict__ best)
 {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i < n_edges)
+    if (i < n_edges) {
         rank[order[i]] = (int32_t)i;
+        first[i] = INT_MAX;
+        count[i] = 0;
+    }
+    if (i < n_nodes)
+        best[i] = INT_MAX;
+}
+
+// no long member lists yet: the count and both bound arrays cleared
+__global__ __launch_bounds__(kThreads) void k_clear_big(int32_t *__restrict__ n_big, int32_t *__restrict__ begin,
+                                                        int32_t *__restrict__ end, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i == 0)
+        *n_big = 0;
+    if (i < n)
+        begin[i] = end[i] = 0;
 }
 
 // best[v] = least rank over the hyperedges containing v, one incidence per
@@ -877,8 +898,10 @@ hnv_status layout(int64_t nV, int64_t nE, int64_t nnz, int k, CoarsenLayout &L)
     L.inc_edge = take(4 * nnz);
     L.dflag = take(4 * nnz);
     L.dpos = take(4 * nnz);
-    L.sizes = take(8 * 4);
-    L.flag = take(16);
+    // the check word (int flags, pad, uint64 feature total) and the coarse
+    // sizes (3 x int64) side by side: one read-back takes both
+    L.flag = take(16 + 8 * 4);
+    L.sizes = L.flag + 16;
     L.big_begin = take(4 * max_big_lists(nnz));
     L.big_end = take(4 * max_big_lists(nnz));
     L.sort_counts = take(8);
@@ -1041,14 +1064,12 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
         k_keys<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, edge_w, n_edges, size_bits, kin, at(L.ids_in));
         if (prim_sort_pairs(temp, tb, kin, kout, at(L.ids_in), order, nE, 0, key_bits, s) != hipSuccess)
             return fail(HNV_EDEVICE, "radix sort of hyperedge keys");
-        k_rank<<<grid_for(nE), kThreads, 0, s>>>(order, n_edges, rank);
-        k_fill<<<grid_for(nE), kThreads, 0, s>>>(first, n_edges, INT_MAX);
-        k_fill<<<grid_for(nE), kThreads, 0, s>>>(count, n_edges, 0);
     }
+    if (nE > 0 || nV > 0)
+        k_rank<<<grid_for(std::max(nE, nV)), kThreads, 0, s>>>(order, n_edges, n_nodes, rank, first, count, best);
     if (nV > 0) {
         // 2. choices: the least rank, or (features) the least rank among the
         // hyperedges of best cosine score
-        k_fill<<<grid_for(nV), kThreads, 0, s>>>(best, n_nodes, INT_MAX);
         if (nE > 0 && !feat) {
             if (bucketed_best(n_nodes, nnz)) {
                 // (mapped, sorted and dflag are free until step 5)
@@ -1107,9 +1128,7 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
             k_map<<<grid_for(nz), kThreads, 0, s>>>(edge_idx, node_rep, nnz, mapped, flag);
             int32_t *big_begin = at(L.big_begin), *big_end = at(L.big_end), *n_big_dev = at(L.sort_counts);
             const int64_t n_big = max_big_lists(nnz);
-            k_fill<<<1, kThreads, 0, s>>>(n_big_dev, 1, 0);
-            k_fill<<<grid_for(n_big), kThreads, 0, s>>>(big_begin, n_big, 0);
-            k_fill<<<grid_for(n_big), kThreads, 0, s>>>(big_end, n_big, 0);
+            k_clear_big<<<grid_for(n_big), kThreads, 0, s>>>(n_big_dev, big_begin, big_end, n_big);
             k_sort_short<<<grid_for(nE), kThreads, 0, s>>>(edge_ptr, mapped, n_edges, sorted, big_begin, big_end,
                                                             n_big_dev, flag);
             if (nnz > kSortThread)
@@ -1156,17 +1175,19 @@ hnv_status coarsen_device(int64_t n_nodes, int64_t n_edges, int64_t nnz, const i
         return st;
     if (feat)
         return sync_read(c_sizes, sizes, 3 * sizeof(int64_t));
-    int64_t sz[3] = {0, 0, 0};
-    hipError_t e = hipMemcpyAsync(&chk, flag, sizeof(chk), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(sz, sizes, sizeof(sz), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(s);
-    if (e != hipSuccess)
-        return fail(HNV_EDEVICE, std::string("read-back: ") + hipGetErrorString(e));
+    struct {
+        int bad, pad;
+        unsigned long long total;
+        int64_t sizes[3];
+    } back{};
+    static_assert(sizeof(back) == 16 + 3 * sizeof(int64_t), "check word and sizes are read as one block");
+    if ((st = sync_read(&back, flag, sizeof(back))) != HNV_OK)
+        return st;
+    chk.bad = back.bad;
+    chk.total = back.total;
     if ((st = report()) != HNV_OK)
         return st;
-    std::memcpy(c_sizes, sz, sizeof(sz));
+    std::memcpy(c_sizes, back.sizes, sizeof(back.sizes));
     return HNV_OK;
 }
 
