@@ -60,6 +60,20 @@ def test_tiers_bit_identical(H, small_max, chunk, dtype, d, order):
     _assert_same_refine(host, dev, hier, d, [3, 2, 2], 11)
 
 
+@pytest.mark.parametrize("n_edges", [1, 63, 64, 65, 127, 128, 129, 191])
+def test_side_boundary_bit_identical(H, n_edges):
+    """Both sides' degree tiers are built over one array of entries in which
+    side 1 starts at the first multiple of 64 past side 0's rows: hyperedge
+    counts on either side of those multiples, with split rows on both sides
+    (small_max 4, chunk 8) and with the default tiers."""
+    n_nodes = max(64, 3 * n_edges + 5)
+    hg = random_hypergraph(100 + n_edges, n_nodes, n_edges, 1, 40)
+    hier = H.Hierarchy.build(hg.n_nodes, hg.n_edges, hg.edge_ptr, hg.edge_idx, hg.edge_w, 2)
+    for opts in ({"small_max": 4, "chunk": 8}, None):
+        host, dev = _both_plans(H, hier, 32, "f32", opts)
+        _assert_same_refine(host, dev, hier, 32, [2, 2, 2][:hier.n_levels], 5)
+
+
 @pytest.mark.parametrize("seed,n_nodes,n_edges,hi,weighted", [
     (0, 40, 20, 4, True), (1, 3000, 2000, 12, False), (2, 700, 900, 40, True), (3, 1, 1, 1, False)])
 def test_random_bit_identical(H, seed, n_nodes, n_edges, hi, weighted):
