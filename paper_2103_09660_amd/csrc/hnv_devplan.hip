@@ -93,7 +93,8 @@ __global__ void k_check_no_edges(const int32_t *__restrict__ ptr, int64_t nnz, i
 // one pass (2 (small_max + 3) keys), the wavefront tier's chunk keys one pass
 // while both sides' keys (2 chunk) fit in kBinsMax, else one per 10 bits;
 // the result equals a stable radix sort's.  The number of pairs is n_max, or
-// *n_dev when that is given (the grid is sized for n_max).
+// *n_dev when that is given (the grid is sized for n_max).  A one-pass sort
+// can also write each input element's sorted position (pos_out).
 constexpr int kBinsMax = 1024;
 constexpr int kBinBits = 10;   // digit width of the multi-pass form
 constexpr int kBinRounds = 16;
@@ -147,7 +148,8 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(const uint32_t *__rest
                                                           uint32_t mask, int n_bins, int bits, int64_t n_tiles,
                                                           const int32_t *__restrict__ offs,
                                                           uint32_t *__restrict__ key_out,
-                                                          int32_t *__restrict__ val_out)
+                                                          int32_t *__restrict__ val_out,
+                                                          int32_t *__restrict__ pos_out)
 {
     __shared__ int32_t next[kBinsMax];
     __shared__ int32_t wcount[kBinWaves][kBinsMax];
@@ -177,6 +179,8 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(const uint32_t *__rest
                 pos += wcount[w][dg];
             key_out[pos] = kv;
             val_out[pos] = val[i];
+            if (pos_out)
+                pos_out[i] = pos;
         }
         __syncthreads();
         for (int b = threadIdx.x; b < n_bins; b += kThreads) {
@@ -416,12 +420,15 @@ __global__ void k_tier_counts(const uint32_t *__restrict__ sorted_key, const Tie
         *n_chunks = b.pieces;
 }
 
-// lane-group tier items in sorted order; aux = the coarse row the row's own
+// lane-group tier items, one thread per row in row order (so that the
+// offsets and neighbour ids are read in order): the tier sort's position of
+// the row's entry, less its side's first entry, is the row's item when it is
+// below the side's count of small rows.  aux = the coarse row the row's own
 // value is projected from (0 at the coarsest level).  With `ids`, also each
 // item's first kInlineIds neighbour ids from idx (and from cidx into
 // `cids`), 0 past the row's degree, and all 0 when the level failed its
 // checks (its offsets may then point anywhere).
-__global__ __launch_bounds__(kThreads) void k_small_items(TierSides T, const int32_t *__restrict__ sorted_row,
+__global__ __launch_bounds__(kThreads) void k_small_items(TierSides T, const int32_t *__restrict__ pos,
                                                           const int64_t *__restrict__ counts,
                                                           const int *__restrict__ bad)
 {
@@ -430,10 +437,12 @@ __global__ __launch_bounds__(kThreads) void k_small_items(TierSides T, const int
         return;
     const int sd = side_of(T, p);
     const TierSide &S = T.s[sd];
-    const int64_t i = p - S.off;
+    const int32_t r = (int32_t)(p - S.off);
+    if (r >= S.n_rows)
+        return;
+    const int64_t i = (int64_t)pos[p] - S.off;
     if (i >= counts[4 * sd])
         return;
-    const int32_t r = sorted_row[p];
     const int32_t a = S.ptr[r], len = S.ptr[r + 1] - a;
     S.small[i] = Item{r, a, len, S.rowmap ? S.rowmap[S.row_base + r] : 0};
     if (!S.ids)
@@ -548,7 +557,7 @@ struct TierArrays {
     int32_t *rows_a, *rows_b;
     TierCount *tc, *tpos;   // per-entry tier counts and their exclusive scan
     uint32_t *key_a, *key_b;
-    int32_t *sorted_rows;   // rows_a or rows_b: the entries' rows in tier order
+    int32_t *pos;           // each entry's position in tier order
 };
 
 // Temporaries of one level's build, carved from `base` (nullptr: sizing).
@@ -620,6 +629,7 @@ hnv_status scratch_layout(int64_t nnz, int64_t rows, int64_t n_chunks, int tier_
     S.tier.tpos = (TierCount *)take(3 * t4);
     S.tier.key_a = (uint32_t *)take(t4);
     S.tier.key_b = (uint32_t *)take(t4);
+    S.tier.pos = (int32_t *)take(t4);
     const int64_t bins = std::max(bin_cap(tier_entries(rows), tier_bins), bin_cap(n_chunks, kBinsMax));
     S.bin_counts = (int32_t *)take(4 * bins);
     S.bin_offs = (int32_t *)take(4 * bins);
@@ -786,9 +796,10 @@ hnv_status report_checks(int l, const int *flags, bool full)
 // Stable sort of the pairs (ka, va) by key (every key below key_limit) with
 // the counting passes above: n_max pairs, or *n_dev of them.  The sorted
 // pairs end in (kb, vb) after an odd number of passes, else in (ka, va);
-// `in_b` tells which.
+// `in_b` tells which.  pos_out (one pass only): pos_out[i] = the sorted
+// position of input pair i.
 hnv_status bin_sort(uint32_t *ka, int32_t *va, uint32_t *kb, int32_t *vb, int64_t n_max, const int64_t *n_dev,
-                    int64_t key_limit, Scratch &S, hipStream_t s, bool &in_b)
+                    int64_t key_limit, Scratch &S, hipStream_t s, bool &in_b, int32_t *pos_out = nullptr)
 {
     in_b = false;
     if (n_max == 0)
@@ -797,6 +808,8 @@ hnv_status bin_sort(uint32_t *ka, int32_t *va, uint32_t *kb, int32_t *vb, int64_
     const bool one = key_limit <= kBinsMax;
     const int passes = one ? 1 : (bits_for(key_limit) + kBinBits - 1) / kBinBits;
     const int n_bins = one ? (int)key_limit : kBinsMax;
+    if (pos_out && !one)
+        return fail(HNV_EUNSUPPORTED, "sorted positions from a multi-pass counting sort");
     const uint32_t mask = one ? 0xffffffffu : (uint32_t)(kBinsMax - 1);
     uint32_t *kin = ka, *kout = kb;
     int32_t *vin = va, *vout = vb;
@@ -807,7 +820,7 @@ hnv_status bin_sort(uint32_t *ka, int32_t *va, uint32_t *kb, int32_t *vb, int64_
         if (prim_exclusive_sum(S.temp, tb, S.bin_counts, S.bin_offs, tiles * n_bins, s) != hipSuccess)
             return fail(HNV_EDEVICE, "scan of a counting sort's digit counts");
         k_bin_scatter<<<(unsigned)tiles, kThreads, 0, s>>>(kin, vin, n_max, n_dev, shift, mask, n_bins,
-                                                           bits_for(n_bins), tiles, S.bin_offs, kout, vout);
+                                                           bits_for(n_bins), tiles, S.bin_offs, kout, vout, pos_out);
         std::swap(kin, kout);
         std::swap(vin, vout);
         in_b = !in_b;
@@ -829,14 +842,13 @@ hnv_status tier_scan(const TierSides &T, int small_max, int chunk, const int *ba
     const int64_t n_keys = (int64_t)T.n * (small_max + 3);
     if (n_keys > kBinsMax)
         return fail(HNV_EUNSUPPORTED, "small_max above the tier sort's key range");
-    TierArrays &A = S.tier;
+    const TierArrays &A = S.tier;
     k_tier_keys<<<grid_for(T.total), kThreads, 0, s>>>(T, small_max, chunk, bad, A.key_a, A.rows_a, A.tc);
     // the lane-group tier order of both sides: one counting pass
     bool in_b = false;
-    if (hnv_status st = bin_sort(A.key_a, A.rows_a, A.key_b, A.rows_b, T.total, nullptr, n_keys, S, s, in_b);
+    if (hnv_status st = bin_sort(A.key_a, A.rows_a, A.key_b, A.rows_b, T.total, nullptr, n_keys, S, s, in_b, A.pos);
         st != HNV_OK)
         return st;
-    A.sorted_rows = in_b ? A.rows_b : A.rows_a;
     size_t tb = S.temp_bytes;
     if (prim_exclusive_scan(S.temp, tb, A.tc, A.tpos, TierCount{0, 0, 0}, (int)T.total, TierCountPlus(), s) !=
         hipSuccess)
@@ -854,7 +866,7 @@ hnv_status tier_emit(const TierSides &T, int chunk, int64_t max_chunks, const in
     if (T.total == 0)
         return HNV_OK;
     const TierArrays &A = S.tier;
-    k_small_items<<<grid_for(T.total), kThreads, 0, s>>>(T, A.sorted_rows, counts, bad);
+    k_small_items<<<grid_for(T.total), kThreads, 0, s>>>(T, A.pos, counts, bad);
     if (max_chunks > 0) {
         k_chunk_items<<<grid_for(T.total), kThreads, 0, s>>>(T, chunk, A.tc, A.tpos, S.items, S.ckey_a, S.ids_a);
         // each side's longest first: a stable sort on side * chunk + chunk - len
