@@ -93,8 +93,9 @@ __global__ void k_check_no_edges(const int32_t *__restrict__ ptr, int64_t nnz, i
 // one pass (2 (small_max + 3) keys), the wavefront tier's chunk keys one pass
 // while both sides' keys (2 chunk) fit in kBinsMax, else one per 10 bits;
 // the result equals a stable radix sort's.  The number of pairs is n_max, or
-// *n_dev when that is given (the grid is sized for n_max).  A one-pass sort
-// can also write each input element's sorted position (pos_out).
+// *n_dev when that is given (the grid is sized for n_max).  The values may
+// be absent (null); a one-pass sort can also write each input element's
+// sorted position (pos_out).
 constexpr int kBinsMax = 1024;
 constexpr int kBinBits = 10;   // digit width of the multi-pass form
 constexpr int kBinRounds = 16;
@@ -178,7 +179,8 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(const uint32_t *__rest
             for (int w = 0; w < wave; ++w)
                 pos += wcount[w][dg];
             key_out[pos] = kv;
-            val_out[pos] = val[i];
+            if (val_out)
+                val_out[pos] = val[i];
             if (pos_out)
                 pos_out[i] = pos;
         }
@@ -356,7 +358,7 @@ __device__ inline uint32_t tier_key_base(int sd, int small_max) { return (uint32
 
 __global__ __launch_bounds__(kThreads) void k_tier_keys(TierSides T, int small_max, int chunk,
                                                         const int *__restrict__ bad, uint32_t *__restrict__ key,
-                                                        int32_t *__restrict__ row, TierCount *__restrict__ tc)
+                                                        TierCount *__restrict__ tc)
 {
     const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (p >= T.total)
@@ -367,7 +369,6 @@ __global__ __launch_bounds__(kThreads) void k_tier_keys(TierSides T, int small_m
     const uint32_t kb = tier_key_base(sd, small_max);
     if (r >= S.n_rows) {
         key[p] = kb + (uint32_t)(small_max + 2);
-        row[p] = -1;
         tc[p] = TierCount{0, 0, 0};
         return;
     }
@@ -375,7 +376,6 @@ __global__ __launch_bounds__(kThreads) void k_tier_keys(TierSides T, int small_m
     const bool small = deg <= small_max;
     const int32_t pc = small ? 0 : (deg + chunk - 1) / chunk;
     key[p] = kb + (small ? (uint32_t)(small_max - deg) : (uint32_t)(small_max + 1));
-    row[p] = (int32_t)r;
     tc[p] = TierCount{pc, pc > 1 ? 1 : 0, pc > 1 ? pc : 0};
 }
 
@@ -554,7 +554,7 @@ LevelShape bound_shape(const hnv_level_dev &lv, const hnv_level_dev *coarse, int
 
 // The per-entry arrays of the degree tiers (both sides' entries).
 struct TierArrays {
-    int32_t *rows_a, *rows_b;
+    int32_t *row_ids;       // 0, 1, 2, ..: the values of the inverse map's sort
     TierCount *tc, *tpos;   // per-entry tier counts and their exclusive scan
     uint32_t *key_a, *key_b;
     int32_t *pos;           // each entry's position in tier order
@@ -623,8 +623,7 @@ hnv_status scratch_layout(int64_t nnz, int64_t rows, int64_t n_chunks, int tier_
     S.csc_e = (int32_t *)take(n4);
     S.keys_out = (int32_t *)take(n4);
     const size_t t4 = 4 * (size_t)tier_entries(rows);
-    S.tier.rows_a = (int32_t *)take(t4);
-    S.tier.rows_b = (int32_t *)take(t4);
+    S.tier.row_ids = (int32_t *)take(t4);
     S.tier.tc = (TierCount *)take(3 * t4);
     S.tier.tpos = (TierCount *)take(3 * t4);
     S.tier.key_a = (uint32_t *)take(t4);
@@ -796,8 +795,8 @@ hnv_status report_checks(int l, const int *flags, bool full)
 // Stable sort of the pairs (ka, va) by key (every key below key_limit) with
 // the counting passes above: n_max pairs, or *n_dev of them.  The sorted
 // pairs end in (kb, vb) after an odd number of passes, else in (ka, va);
-// `in_b` tells which.  pos_out (one pass only): pos_out[i] = the sorted
-// position of input pair i.
+// `in_b` tells which.  va and vb may both be null (keys only).  pos_out (one
+// pass only): pos_out[i] = the sorted position of input pair i.
 hnv_status bin_sort(uint32_t *ka, int32_t *va, uint32_t *kb, int32_t *vb, int64_t n_max, const int64_t *n_dev,
                     int64_t key_limit, Scratch &S, hipStream_t s, bool &in_b, int32_t *pos_out = nullptr)
 {
@@ -843,10 +842,11 @@ hnv_status tier_scan(const TierSides &T, int small_max, int chunk, const int *ba
     if (n_keys > kBinsMax)
         return fail(HNV_EUNSUPPORTED, "small_max above the tier sort's key range");
     const TierArrays &A = S.tier;
-    k_tier_keys<<<grid_for(T.total), kThreads, 0, s>>>(T, small_max, chunk, bad, A.key_a, A.rows_a, A.tc);
-    // the lane-group tier order of both sides: one counting pass
+    k_tier_keys<<<grid_for(T.total), kThreads, 0, s>>>(T, small_max, chunk, bad, A.key_a, A.tc);
+    // the lane-group tier order of both sides: one counting pass, which
+    // gives each entry's position in that order
     bool in_b = false;
-    if (hnv_status st = bin_sort(A.key_a, A.rows_a, A.key_b, A.rows_b, T.total, nullptr, n_keys, S, s, in_b, A.pos);
+    if (hnv_status st = bin_sort(A.key_a, nullptr, A.key_b, nullptr, T.total, nullptr, n_keys, S, s, in_b, A.pos);
         st != HNV_OK)
         return st;
     size_t tb = S.temp_bytes;
@@ -948,10 +948,10 @@ hnv_status build_level(hnv_plan *p, const hnv_level_dev *levels, const hnv_map *
     if (C) {
         const int64_t rows = nV + nE, rows_c = L.rows_coarse;
         if (rows > 0) {
-            k_iota<<<grid_for(rows), kThreads, 0, s>>>(rows, S.tier.rows_a);
+            k_iota<<<grid_for(rows), kThreads, 0, s>>>(rows, S.tier.row_ids);
             tb = S.temp_bytes;
             if (prim_sort_pairs(S.temp, tb, reinterpret_cast<const uint32_t *>(L.rowmap),
-                                                   reinterpret_cast<uint32_t *>(S.keys_out), S.tier.rows_a, L.inv_idx,
+                                                   reinterpret_cast<uint32_t *>(S.keys_out), S.tier.row_ids, L.inv_idx,
                                                    (int)rows, 0, bits_for(rows_c), s) != hipSuccess)
                 return fail(HNV_EDEVICE, "sort of the inverse map");
         }
