@@ -248,8 +248,11 @@ typedef struct {
  * visible GPU.  validate != 0 runs, on the device, the checks that
  * hnv_validate_level and hnv_plan_create(validate = 1) run; offsets, index
  * ranges and map ranges are always checked.  The level and map arrays are
- * read during the call only.  Synchronises `stream` several times (the
- * checks and the work-list sizes are read back) and before returning. */
+ * read during the call only.  Synchronises `stream` once, before returning:
+ * the checks' flags and the work-list sizes of every level are read back
+ * together once the whole build is enqueued (the kernels that follow a
+ * level's offsets, ids or map entries read its flags first and write empty
+ * but well-formed arrays when a check failed). */
 hnv_status hnv_plan_workspace_bytes_device(const hnv_level_dev *levels, const hnv_map *maps, int n_levels, int d,
                                            hnv_dtype dtype, const hnv_options *opts, size_t *bytes);
 hnv_status hnv_plan_create_device(const hnv_level_dev *levels, const hnv_map *maps, int n_levels, int d,
