@@ -175,7 +175,9 @@ hnv_status hnv_coarsen_level_device(int64_t n_nodes, int64_t n_edges, int64_t nn
  * of f(e) and f(v), and among equal scores the first in the featureless
  * order above (in place of the paper's random choice); the coarse feature
  * matrix X' gives each coarse node the sum of its fine nodes' rows (merged
- * bags of words).  Maps and coarse level as hnv_coarsen_level_device.
+ * bags of words).  Maps and coarse level as hnv_coarsen_level_device; this
+ * step reads the input checks' result back before its feature kernels run
+ * (two waits: the checks', then the sizes').
  *   x: DEVICE int32 [n_nodes x k], row-major, 16-byte aligned: counts >= 0
  *      whose total is below 2^31 (checked; HNV_EINVAL otherwise), k a
  *      multiple of 4 up to 65536 (pad with zero columns: they change no
