@@ -139,6 +139,20 @@ def test_invalid_inputs_are_rejected(H):
     assert _bad(H, 4, [0, 2, 4], [0, 1, 2, 3], [1.0, 0.0]) == L.HNV_EINVAL
     assert _bad(H, 4, [0, 2, 4], [0, 1, 2, 3], [1.0, float("nan")]) == L.HNV_EINVAL
     assert _bad(H, 4, [0, 2, 4], [0, 1, 2, 3], [float("inf"), 1.0]) == L.HNV_EINVAL
+    assert _bad(H, 4, [3], []) == L.HNV_EINVAL                              # no hyperedges, offset not 0
+
+
+def test_level_without_hyperedges(oracle_mod, H):
+    """A level of nodes only: every node stays a node of its own, nothing else
+    is written (the status of the same level with a bad offset is above)."""
+    import torch
+    O = oracle_mod
+    lv = H.DeviceLevel(5, 0, 0, torch.zeros(1, dtype=torch.int32, device="cuda"),
+                       torch.zeros(0, dtype=torch.int32, device="cuda"))
+    nrep, erep, c = H.coarsen_level_device(lv)
+    ref = O.coarsen_level(O.Level(5, 0, np.zeros(1, dtype=np.int64), np.zeros(0, dtype=np.int32), None))
+    assert np.array_equal(nrep.cpu().numpy(), ref.node_rep)
+    assert (c.n_nodes, c.n_edges, c.nnz) == (5, 0, 0)
 
 
 def test_invalid_large_inputs_are_rejected(oracle_mod, H):
