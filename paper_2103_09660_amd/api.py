@@ -161,11 +161,13 @@ def _coarsen_step(level: DeviceLevel, workspace):
     returns HNV_EWORKSPACE if it is too small)."""
     torch = _torch()
     dev = level.edge_ptr.device
-    i32 = dict(dtype=torch.int32, device=dev)
-    node_rep = torch.empty(max(level.n_nodes, 1), **i32)
-    edge_rep = torch.empty(max(level.n_edges, 1), **i32)
-    c_ptr = torch.empty(level.n_edges + 1, **i32)
-    c_idx = torch.empty(max(level.nnz, 1), **i32)
+    # the four int32 outputs carved from one allocation, each on a 256-byte boundary
+    lens = (max(level.n_nodes, 1), max(level.n_edges, 1), level.n_edges + 1, max(level.nnz, 1))
+    offs = [0]
+    for n in lens:
+        offs.append(offs[-1] + (n + 63) // 64 * 64)
+    block = torch.empty(offs[-1], dtype=torch.int32, device=dev)
+    node_rep, edge_rep, c_ptr, c_idx = (block[o:o + n] for o, n in zip(offs, lens))
     c_w = None if level.edge_w is None else torch.empty(max(level.n_edges, 1), dtype=torch.float32, device=dev)
     sizes = (ctypes.c_int64 * 3)()
     with torch.cuda.device(dev):
