@@ -685,9 +685,9 @@ void carve(hnv_plan *p, const std::vector<LevelShape> &shape, char *base)
     }
     p->zbuf = c.take<char>(p->lv[0].rows * p->d * (int64_t)elem);
     p->partials = c.take<float>(p->max_slots * p->pstride);
-    p->resid_part = c.take<double>(p->max_resid_blocks);
+    p->resid_part = c.take<double>(kResidBatch * p->max_resid_blocks);
     p->resid_stage_len = blocks_for(p->max_resid_blocks, kBlock * 8) + 1;
-    p->resid_stage = c.take<double>(2 * p->resid_stage_len);
+    p->resid_stage = c.take<double>(2 * kResidBatch * p->resid_stage_len);
     p->cscratch = c.take<float>(max_nodes);
     p->resid_tmp = c.take<double>(1);
     p->ctl = c.take<SweepCtl>(1);

@@ -100,6 +100,12 @@ struct LevelPlan {
 
 }  // namespace hnv
 
+namespace hnv {
+// Sweeps of one level whose residuals a fixed-count refinement reduces
+// together (their per-block partials wait in as many slots).
+constexpr int kResidBatch = 8;
+}  // namespace hnv
+
 struct hnv_plan {
     int n_levels = 0;
     int d = 0;
@@ -110,9 +116,9 @@ struct hnv_plan {
     float *partials = nullptr;       // [max_slots x pstride]
     int32_t pstride = 0;             // floats per partial slot (d + 8)
     int64_t max_slots = 0;
-    double *resid_part = nullptr;    // [max_resid_blocks]
+    double *resid_part = nullptr;    // [kResidBatch x max_resid_blocks] per-block partials, one slot per sweep
     int64_t max_resid_blocks = 0;
-    double *resid_stage = nullptr;   // [2 x resid_stage_len] partial sums of the residual stages
+    double *resid_stage = nullptr;   // [2 x kResidBatch x resid_stage_len] partial sums of the residual stages
     int64_t resid_stage_len = 0;
     float *cscratch = nullptr;       // [max n_nodes] per-node scalar of the reverse sweep
     double *resid_tmp = nullptr;     // [1]

@@ -803,14 +803,18 @@ __global__ __launch_bounds__(kBlock) void k_finalize(GatherArgs a)
 // (ctl != null) nothing runs once the level has stopped, and the last stage
 // instead stores the residual at the next packed position, counts the
 // sweep, raises the level's stop flag if the residual is <= tol, and makes
-// the sweep's output the latest iterate.
+// the sweep's output the latest iterate.  Several sweeps' reductions run
+// side by side along blockIdx.y, sweep y reading part + y * part_stride and
+// writing out + y * out_stride (each in the order one sweep alone takes).
 constexpr int kResidPer = kBlock * 8;
 __global__ __launch_bounds__(kBlock) void k_resid_stage(const double *__restrict__ part, int64_t n,
-                                                        double *__restrict__ out, int final_sqrt, SweepCtl *ctl,
-                                                        int level)
+                                                        int64_t part_stride, double *__restrict__ out,
+                                                        int64_t out_stride, int final_sqrt, SweepCtl *ctl, int level)
 {
     if (ctl && ctl->stop[level])
         return;
+    part += (int64_t)blockIdx.y * part_stride;
+    out += (int64_t)blockIdx.y * out_stride;
     __shared__ double s[kBlock];
     const int64_t base = (int64_t)blockIdx.x * kResidPer + threadIdx.x;
     double x[8];
@@ -1595,16 +1599,44 @@ static SweepScratch plan_scratch(const hnv_plan *p)
     return SweepScratch{p->partials, p->resid_part, p->resid_stage, p->resid_stage_len};
 }
 
+// The residuals of `batch` sweeps of one level (batch 1: a single sweep, the
+// only form with ctl) from their per-block partials: n partials per sweep,
+// sweep y's at part + y * part_stride; sweep y's residual goes to out[y].
+// The stage sums alternate between two halves of sc.resid_stage, each
+// batch x resid_stage_len long (a single sweep's scratch holds batch 1).
+static hnv_status reduce_resid(const double *part, int64_t n, int batch, int64_t part_stride, double *out,
+                               const SweepScratch &sc, SweepCtl *ctl, int level, hipStream_t s)
+{
+    const double *in = part;
+    int64_t stride = part_stride;
+    int which = 0;
+    while (n > kResidPer) {
+        const int64_t nb = blocks_for(n, kResidPer);
+        double *o = sc.resid_stage + (int64_t)which * batch * sc.resid_stage_len;
+        k_resid_stage<<<dim3((unsigned)nb, (unsigned)batch), kBlock, 0, s>>>(in, n, stride, o, sc.resid_stage_len, 0,
+                                                                            ctl, level);
+        in = o;
+        stride = sc.resid_stage_len;
+        n = nb;
+        which ^= 1;
+    }
+    k_resid_stage<<<dim3(1, (unsigned)batch), kBlock, 0, s>>>(in, n, stride, out, 1, 1, ctl, level);
+    return dev_check("residual kernels");
+}
+
 // One forward sweep of `level` (src -> dst); fused reads the coarser level.
 // Jacobi: both sides in one launch, every row reading src.  Edge-first:
 // hyperedge rows first (from src), then node rows, whose neighbours are the
 // new hyperedge rows in dst and whose own value still comes from src.  With
 // ctl (an early-stop refinement) src and dst come from the control block and
 // the residual stage decides on the device whether the level goes on.  The
-// scratch is the plan's workspace unless `scr` names other memory.
+// scratch is the plan's workspace unless `scr` names other memory.  With
+// resid_slot >= 0 (a fixed-count refinement) the sweep only leaves its
+// per-block partials in that slot of the plan's residual scratch, for
+// reduce_resid to reduce with the level's next sweeps.
 static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, float omega, bool fused,
                             double *resid_out, hipStream_t s, SweepCtl *ctl = nullptr,
-                            const SweepScratch *scr = nullptr)
+                            const SweepScratch *scr = nullptr, int resid_slot = -1)
 {
     LevelPlan &L = p->lv[level];
     const SweepScratch sc = scr ? *scr : plan_scratch(p);
@@ -1618,6 +1650,8 @@ static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, 
     a.ctl_level = level;
     a.ctl_src_next = 0;
     a.resid = (resid_out || ctl) ? sc.resid_part : nullptr;
+    if (resid_slot >= 0)
+        a.resid = sc.resid_part + (int64_t)resid_slot * p->max_resid_blocks;
     a.resid_offset = 0;
     const bool bf = p->dtype == HNV_BF16;
     hnv_status st;
@@ -1640,22 +1674,10 @@ static hnv_status run_sweep(hnv_plan *p, int level, const void *src, void *dst, 
     }
     if (st != HNV_OK)
         return st;
-    if (resid_out || ctl) {
+    if (resid_slot < 0 && (resid_out || ctl)) {
         int64_t mb = 0, fb = 0;
         forward_geometry(p, L, &mb, &fb);
-        const double *in = sc.resid_part;
-        int64_t n = mb + fb;
-        int which = 0;
-        while (n > kResidPer) {
-            const int64_t nb = blocks_for(n, kResidPer);
-            double *out = sc.resid_stage + which * sc.resid_stage_len;
-            k_resid_stage<<<(unsigned)nb, kBlock, 0, s>>>(in, n, out, 0, ctl, level);
-            in = out;
-            n = nb;
-            which ^= 1;
-        }
-        k_resid_stage<<<1, kBlock, 0, s>>>(in, n, resid_out, 1, ctl, level);
-        return dev_check("residual kernels");
+        return reduce_resid(sc.resid_part, mb + fb, 1, 0, resid_out, sc, ctl, level, s);
     }
     return HNV_OK;
 }
@@ -2001,14 +2023,25 @@ extern "C" hnv_status hnv_refine(hnv_plan *plan, const void *z_coarsest, void *z
                 return st;
             cur = out;
         }
+        // the level's residuals reduced kResidBatch sweeps at a time
+        int64_t mb = 0, fb = 0;
+        forward_geometry(plan, plan->lv[l], &mb, &fb);
+        int pending = 0;
         for (int k = 0; k < K; ++k) {
             void *out = target(op++);
             const bool fused = (k == 0 && l < Lc);
-            double *rd = residuals_dev ? residuals_dev + resid_k : nullptr;
-            if ((st = run_sweep(plan, l, cur, out, omega, fused, rd, s)) != HNV_OK)
+            if ((st = run_sweep(plan, l, cur, out, omega, fused, nullptr, s, nullptr, nullptr,
+                                residuals_dev ? pending : -1)) != HNV_OK)
                 return st;
             ++resid_k;
             cur = out;
+            if (residuals_dev && (++pending == kResidBatch || k + 1 == K)) {
+                if ((st = reduce_resid(plan->resid_part, mb + fb, pending, plan->max_resid_blocks,
+                                       residuals_dev + resid_k - pending, plan_scratch(plan), nullptr, l, s)) !=
+                    HNV_OK)
+                    return st;
+                pending = 0;
+            }
         }
         if (sweeps_done)
             sweeps_done[l] = K;
