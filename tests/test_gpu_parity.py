@@ -162,6 +162,19 @@ def test_refine_tiny2k_f32(oracle_mod, H):
     np.testing.assert_allclose(res[: len(ref_res)], ref_res, rtol=1e-5)
 
 
+@pytest.mark.parametrize("sweeps", [[8, 9, 0, 17], [16, 1, 3, 0]])
+def test_refine_residual_batches(oracle_mod, H, sweeps):
+    """A fixed-count refinement reduces its residuals 8 sweeps of a level at
+    a time: sweep counts that fill one or two batches exactly, leave a
+    partial batch, or are 0 (a bare projection); every residual against the
+    oracle's."""
+    got, ref, res, ref_res, done, K = _refine_case(oracle_mod, H, "tiny-2k", "f32", sweeps=sweeps)
+    _assert_close(got, ref, F32_TOL, f"tiny-2k refine {sweeps}")
+    assert list(done) == list(K)
+    assert len(ref_res) == sum(K)
+    np.testing.assert_allclose(res[: len(ref_res)], ref_res, rtol=1e-5)
+
+
 def test_refine_tiny2k_bf16(oracle_mod, H):
     got, ref, E, _, _, _ = _refine_case(oracle_mod, H, "tiny-2k", "bf16")
     assert_bf16(got, ref, E, "tiny-2k refine bf16")
