@@ -306,7 +306,10 @@ hnv_status hnv_set_edge_logweights(hnv_plan *plan, int level, const float *theta
  *   residuals_dev: DEVICE double [sum of sweeps_per_level] or NULL; entry k
  *        receives ||Z^i - Z^{i-1}||_F of the k-th sweep run (coarsest level
  *        first), reduced in FP64 in a fixed order.  Entries past the last
- *        sweep run (when tol stops levels early) are left untouched.
+ *        sweep run (when tol stops levels early) are left untouched.  With
+ *        tol <= 0 the residuals of up to 8 consecutive sweeps of a level are
+ *        reduced together after the last of them (same values); the entries
+ *        are all written once the call's work on `stream` has completed.
  *   sweeps_done: HOST int32 [n_levels] or NULL: sweeps actually run.  With
  *        tol > 0 the counts are known on the device only, and a non-NULL
  *        sweeps_done makes the call wait for the stream to read them. */
